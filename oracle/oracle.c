@@ -1,0 +1,294 @@
+/*
+ * FP64 CPU oracle for softened direct-summation gravity.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header or constant with the
+ * GPU path.
+ *
+ * Every function is the plain definition written out, in double precision,
+ * summing j in ascending index order with Neumaier-compensated sums so that
+ * the oracle's own rounding error stays near 1e-16 relative.  OpenMP only
+ * distributes independent rows i; each row's arithmetic is sequential, so the
+ * result does not depend on the thread count.
+ *
+ * Layout: vectors are SoA, x[c*n + i] for component c in {0,1,2}; masses m[i].
+ *
+ * Sources (the paper: "Assessing Performance and Porting Strategies for
+ * Gravitational N-Body Simulations on the RISC-V-Based Tenstorrent Wormhole"):
+ *   - acceleration: Eq. (1) of Sec. 2.1 divided by m_i, with the softening
+ *     parameter of App. A read as Plummer softening |d|^2 + eps^2;
+ *   - pair arithmetic order: App. A, Algorithm 3 (displacement, squared
+ *     distance, inverse root, cube, weight times cube, accumulate);
+ *   - integrator: kick-drift-kick leapfrog (the paper's Sec. 2.1 uses a Hermite
+ *     predictor-corrector; the workloads use KDK);
+ *   - diagnostics: kinetic + softened pair potential (self pair excluded),
+ *     linear and angular momentum (Sec. 4.1 compares particle energies);
+ *   - adjoint: the exact reverse-mode derivative of the KDK map above.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- Neumaier compensated sum ----------------------------------------- */
+typedef struct { double s, c; } nsum;
+
+static inline void nadd(nsum* a, double t) {
+    double s = a->s + t;
+    if (fabs(a->s) >= fabs(t)) a->c += (a->s - s) + t;
+    else a->c += (t - s) + a->s;
+    a->s = s;
+}
+static inline double nval(const nsum* a) { return a->s + a->c; }
+
+/* ---- O1: acceleration of one row i (Eq. 1 / m_i, softened) -------------- */
+static void accel_row(int64_t n, const double* x, const double* m, double G, double eps,
+                      int64_t i, double out[3]) {
+    const double* X = x;
+    const double* Y = x + n;
+    const double* Z = x + 2 * n;
+    const double e2 = eps * eps;
+    nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;                    /* the sum in Eq. (1) skips j = i */
+        double dx = X[j] - X[i];                 /* r_ij = r_j - r_i */
+        double dy = Y[j] - Y[i];
+        double dz = Z[j] - Z[i];
+        double r2 = dx * dx + dy * dy + dz * dz + e2;
+        double rinv = 1.0 / sqrt(r2);
+        double rinv3 = rinv * rinv * rinv;
+        double t = m[j] * rinv3;                 /* weight of j times r^-3 */
+        nadd(&ax, t * dx);
+        nadd(&ay, t * dy);
+        nadd(&az, t * dz);
+    }
+    out[0] = G * nval(&ax);
+    out[1] = G * nval(&ay);
+    out[2] = G * nval(&az);
+}
+
+void oracle_accel(int64_t n, const double* x, const double* m, double G, double eps, double* a) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double o[3];
+        accel_row(n, x, m, G, eps, i, o);
+        a[i] = o[0];
+        a[n + i] = o[1];
+        a[2 * n + i] = o[2];
+    }
+}
+
+/* Rows listed in `rows` only (each exact as in oracle_accel); out is [3][nrows]. */
+void oracle_accel_rows(int64_t n, const double* x, const double* m, double G, double eps,
+                       int64_t nrows, const int64_t* rows, double* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nrows; ++k) {
+        double o[3];
+        accel_row(n, x, m, G, eps, rows[k], o);
+        out[k] = o[0];
+        out[nrows + k] = o[1];
+        out[2 * nrows + k] = o[2];
+    }
+}
+
+/* Per-row scale of the terms: G * sum_{j != i} m_j / (|d|^2 + eps^2), used to
+ * normalise errors of rows whose acceleration nearly cancels. */
+void oracle_term_scale_rows(int64_t n, const double* x, const double* m, double G, double eps,
+                            int64_t nrows, const int64_t* rows, double* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows[k];
+        nsum s = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
+            nadd(&s, m[j] / (dx * dx + dy * dy + dz * dz + eps * eps));
+        }
+        out[k] = G * nval(&s);
+    }
+}
+
+/* ---- O2: kick-drift-kick leapfrog -------------------------------------- */
+/* Advances (x, v) in place by nsteps steps of size dt.  If traj != NULL it
+ * receives the positions x_0 .. x_nsteps, traj[s*3n + c*n + i]. */
+void oracle_kdk(int64_t n, double* x, double* v, const double* m, double G, double eps,
+                double dt, int64_t nsteps, double* traj) {
+    const int64_t n3 = 3 * n;
+    double* a = (double*)malloc(sizeof(double) * (size_t)(n3 > 0 ? n3 : 1));
+    oracle_accel(n, x, m, G, eps, a);
+    if (traj) memcpy(traj, x, sizeof(double) * (size_t)n3);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int64_t k = 0; k < n3; ++k) v[k] = v[k] + 0.5 * dt * a[k];   /* half kick */
+        for (int64_t k = 0; k < n3; ++k) x[k] = x[k] + dt * v[k];         /* drift */
+        oracle_accel(n, x, m, G, eps, a);                                  /* a(x_{s+1}) */
+        for (int64_t k = 0; k < n3; ++k) v[k] = v[k] + 0.5 * dt * a[k];   /* half kick */
+        if (traj) memcpy(traj + (size_t)(s + 1) * n3, x, sizeof(double) * (size_t)n3);
+    }
+    free(a);
+}
+
+/* ---- O3: diagnostics --------------------------------------------------- */
+/* out = {K, W, E, Px, Py, Pz, Lx, Ly, Lz}.  W sums the softened pair potential
+ * -G m_i m_j / sqrt(|d|^2 + eps^2) over unordered pairs i < j only. */
+void oracle_energy(int64_t n, const double* x, const double* v, const double* m, double G,
+                   double eps, double* out) {
+    const double *X = x, *Y = x + n, *Z = x + 2 * n;
+    const double *VX = v, *VY = v + n, *VZ = v + 2 * n;
+    double* wrow = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        nsum w = {0, 0};
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            double r = sqrt(dx * dx + dy * dy + dz * dz + eps * eps);
+            nadd(&w, m[i] * m[j] / r);
+        }
+        wrow[i] = nval(&w);
+    }
+    nsum W = {0, 0}, K = {0, 0};
+    nsum P[3] = {{0, 0}, {0, 0}, {0, 0}}, L[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t i = 0; i < n; ++i) {
+        nadd(&W, wrow[i]);
+        nadd(&K, 0.5 * m[i] * (VX[i] * VX[i] + VY[i] * VY[i] + VZ[i] * VZ[i]));
+        nadd(&P[0], m[i] * VX[i]);
+        nadd(&P[1], m[i] * VY[i]);
+        nadd(&P[2], m[i] * VZ[i]);
+        nadd(&L[0], m[i] * (Y[i] * VZ[i] - Z[i] * VY[i]));
+        nadd(&L[1], m[i] * (Z[i] * VX[i] - X[i] * VZ[i]));
+        nadd(&L[2], m[i] * (X[i] * VY[i] - Y[i] * VX[i]));
+    }
+    free(wrow);
+    out[0] = nval(&K);
+    out[1] = -G * nval(&W);
+    out[2] = out[0] + out[1];
+    for (int c = 0; c < 3; ++c) {
+        out[3 + c] = nval(&P[c]);
+        out[6 + c] = nval(&L[c]);
+    }
+}
+
+/* ---- O6: vector-Jacobian products of the acceleration ------------------ */
+/* With d_kj = x_j - x_k, s = |d|^2 + eps^2 and K(d) = s^-3/2 I - 3 s^-5/2 d d^T:
+ *   gx_k = G sum_{j != k} K(d_kj) (m_k w_j - m_j w_k)      (d a / d x)^T w
+ *   gm_k = -G sum_{j != k} s^-3/2 (d_kj . w_j)              (d a / d m)^T w
+ * Both follow from differentiating Eq. (1) / m_i term by term. */
+void oracle_accel_vjp(int64_t n, const double* x, const double* m, const double* w, double G,
+                      double eps, double* gx, double* gm) {
+    const double *X = x, *Y = x + n, *Z = x + 2 * n;
+    const double *WX = w, *WY = w + n, *WZ = w + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n; ++k) {
+        nsum gxs = {0, 0}, gys = {0, 0}, gzs = {0, 0}, gms = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == k) continue;
+            double d[3] = {X[j] - X[k], Y[j] - Y[k], Z[j] - Z[k]};
+            double u[3] = {m[k] * WX[j] - m[j] * WX[k], m[k] * WY[j] - m[j] * WY[k],
+                           m[k] * WZ[j] - m[j] * WZ[k]};
+            double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+            double s32 = 1.0 / (s * sqrt(s));
+            double s52 = s32 / s;
+            double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+            nadd(&gxs, s32 * u[0] - 3.0 * s52 * du * d[0]);
+            nadd(&gys, s32 * u[1] - 3.0 * s52 * du * d[1]);
+            nadd(&gzs, s32 * u[2] - 3.0 * s52 * du * d[2]);
+            double dw = d[0] * WX[j] + d[1] * WY[j] + d[2] * WZ[j];
+            nadd(&gms, -s32 * dw);
+        }
+        gx[k] = G * nval(&gxs);
+        gx[n + k] = G * nval(&gys);
+        gx[2 * n + k] = G * nval(&gzs);
+        gm[k] = G * nval(&gms);
+    }
+}
+
+/* Directional derivative of the acceleration: (da/dx) dx + (da/dm) dm, the
+ * forward-mode counterpart used by the dot-product test. */
+void oracle_accel_jvp(int64_t n, const double* x, const double* m, const double* tx,
+                      const double* tm, double G, double eps, double* out) {
+    const double *X = x, *Y = x + n, *Z = x + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        nsum o[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3] = {X[j] - X[i], Y[j] - Y[i], Z[j] - Z[i]};
+            double dd[3] = {tx[j] - tx[i], tx[n + j] - tx[n + i], tx[2 * n + j] - tx[2 * n + i]};
+            double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+            double s32 = 1.0 / (s * sqrt(s));
+            double s52 = s32 / s;
+            double ddot = d[0] * dd[0] + d[1] * dd[1] + d[2] * dd[2];
+            for (int c = 0; c < 3; ++c)
+                nadd(&o[c], m[j] * (s32 * dd[c] - 3.0 * s52 * ddot * d[c]) + tm[j] * s32 * d[c]);
+        }
+        for (int c = 0; c < 3; ++c) out[c * n + i] = G * nval(&o[c]);
+    }
+}
+
+/* ---- O6: reverse sweep of the KDK map ---------------------------------- */
+/* Given cotangents (gxT, gvT) of the final state after nsteps KDK steps from
+ * (x0, v0), returns the cotangents (gx0, gv0, gm) of the initial state and the
+ * masses.  The whole position trajectory is stored (no checkpointing), and the
+ * two Jacobian products at each interior position are taken separately. */
+void oracle_kdk_adjoint(int64_t n, const double* x0, const double* v0, const double* m, double G,
+                        double eps, double dt, int64_t nsteps, const double* gxT,
+                        const double* gvT, double* gx0, double* gv0, double* gm) {
+    const int64_t n3 = 3 * n;
+    const size_t nb = sizeof(double) * (size_t)(n3 > 0 ? n3 : 1);
+    double* traj = (double*)malloc(nb * (size_t)(nsteps + 1));
+    double* xw = (double*)malloc(nb);
+    double* vw = (double*)malloc(nb);
+    memcpy(xw, x0, sizeof(double) * (size_t)n3);
+    memcpy(vw, v0, sizeof(double) * (size_t)n3);
+    oracle_kdk(n, xw, vw, m, G, eps, dt, nsteps, traj);
+
+    double* lx = (double*)malloc(nb);
+    double* lv = (double*)malloc(nb);
+    double* w = (double*)malloc(nb);
+    double* jx = (double*)malloc(nb);
+    double* jm = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    memcpy(lx, gxT, sizeof(double) * (size_t)n3);
+    memcpy(lv, gvT, sizeof(double) * (size_t)n3);
+    for (int64_t i = 0; i < n; ++i) gm[i] = 0.0;
+    const double h = 0.5 * dt;
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        const double* xs1 = traj + (size_t)(s + 1) * n3;
+        const double* xs = traj + (size_t)s * n3;
+        /* v_{s+1} = vh + h a(x_{s+1}) */
+        for (int64_t k = 0; k < n3; ++k) w[k] = h * lv[k];
+        oracle_accel_vjp(n, xs1, m, w, G, eps, jx, jm);
+        for (int64_t k = 0; k < n3; ++k) lx[k] += jx[k];
+        for (int64_t i = 0; i < n; ++i) gm[i] += jm[i];
+        /* x_{s+1} = x_s + dt vh */
+        for (int64_t k = 0; k < n3; ++k) lv[k] += dt * lx[k];
+        /* vh = v_s + h a(x_s) */
+        for (int64_t k = 0; k < n3; ++k) w[k] = h * lv[k];
+        oracle_accel_vjp(n, xs, m, w, G, eps, jx, jm);
+        for (int64_t k = 0; k < n3; ++k) lx[k] += jx[k];
+        for (int64_t i = 0; i < n; ++i) gm[i] += jm[i];
+    }
+    memcpy(gx0, lx, sizeof(double) * (size_t)n3);
+    memcpy(gv0, lv, sizeof(double) * (size_t)n3);
+    free(traj); free(xw); free(vw); free(lx); free(lv); free(w); free(jx); free(jm);
+}
+
+/* Mean squared distance of positions to a target: (1/N) sum_i |x_i - t_i|^2. */
+double oracle_msd_loss(int64_t n, const double* x, const double* tgt) {
+    nsum s = {0, 0};
+    for (int64_t k = 0; k < 3 * n; ++k) {
+        double d = x[k] - tgt[k];
+        nadd(&s, d * d);
+    }
+    return n > 0 ? nval(&s) / (double)n : 0.0;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,346 @@
+"""Pins of the FP64 oracle against facts it does not define itself.
+
+Each test checks the oracle against something fixed by mathematics or physics
+rather than by retyping the oracle's own formula:
+
+* 50-digit mpmath brute force (tests/golden/tiny5_mp50.txt) for the
+  acceleration, the pair potential and the vector-Jacobian product;
+* the force as minus the gradient of the separately written potential W;
+* Newton's third law (sum m_i a_i = 0);
+* the analytic mean field of a Plummer sphere;
+* the two-body Kepler solution and second-order convergence of KDK;
+* conservation of momentum and angular momentum, time reversibility,
+  O(dt^2) energy error, the virial theorem and E = -1/4 in Henon units;
+* complex-step and central finite differences of an independent numpy
+  forward model for the adjoint, and a forward/reverse dot-product test.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import ics
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tiny5_mp50.txt")
+
+
+def _read_golden():
+    d = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *vals = line.split()
+            d[k] = np.array([float(v) for v in vals])
+    x = np.stack([d["x0"], d["x1"], d["x2"]])
+    w = np.stack([d["w0"], d["w1"], d["w2"]])
+    a = np.stack([d["a0"], d["a1"], d["a2"]])
+    gx = np.stack([d["gx0"], d["gx1"], d["gx2"]])
+    return dict(x=x, m=d["m"], w=w, a=a, W=float(d["W"][0]), gx=gx, gm=d["gm"],
+                G=float(d["G"][0]), eps=float(d["eps"][0]))
+
+
+def test_golden_accel_mp50(oracle_mod):
+    g = _read_golden()
+    a = oracle_mod.accel(g["x"], g["m"], G=g["G"], eps=g["eps"])
+    err = np.abs(a - g["a"]).max() / np.abs(g["a"]).max()
+    assert err < 2e-16 * 8, err
+
+
+def test_golden_potential_mp50(oracle_mod):
+    g = _read_golden()
+    e = oracle_mod.energy(g["x"], np.zeros_like(g["x"]), g["m"], G=g["G"], eps=g["eps"])
+    assert abs(e[1] - g["W"]) <= 4e-16 * abs(g["W"])
+    assert e[0] == 0.0 and e[2] == e[1]
+
+
+def test_golden_vjp_mp50(oracle_mod):
+    g = _read_golden()
+    gx, gm = oracle_mod.accel_vjp(g["x"], g["m"], g["w"], G=g["G"], eps=g["eps"])
+    assert np.abs(gx - g["gx"]).max() <= 1e-14 * np.abs(g["gx"]).max()
+    assert np.abs(gm - g["gm"]).max() <= 1e-14 * np.abs(g["gm"]).max()
+
+
+def test_mpmath_bruteforce_random(oracle_mod):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    x, _, m = ics.random_cloud(8, seed=11)
+    eps = 0.05
+    a = oracle_mod.accel(x, m, G=1.7, eps=eps)
+    for i in range(8):
+        acc = [mp.mpf(0)] * 3
+        for j in range(8):
+            if j == i:
+                continue
+            d = [mp.mpf(x[c, j]) - mp.mpf(x[c, i]) for c in range(3)]
+            s = d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + mp.mpf(eps) ** 2
+            for c in range(3):
+                acc[c] += mp.mpf(1.7) * mp.mpf(m[j]) * d[c] / s ** mp.mpf(1.5)
+        ref = np.array([float(v) for v in acc])
+        assert np.abs(a[:, i] - ref).max() <= 4e-16 * np.abs(ref).max()
+
+
+def test_accel_is_minus_grad_potential(oracle_mod):
+    """m_i a_i = -dW/dx_i with W computed by the separately written potential."""
+    x, v, m = ics.random_cloud(12, seed=3)
+    eps, G = 0.1, 1.3
+    a = oracle_mod.accel(x, m, G=G, eps=eps)
+    h = 1e-5
+    for c in range(3):
+        for i in range(12):
+            xp = x.copy(); xp[c, i] += h
+            xm = x.copy(); xm[c, i] -= h
+            dW = (oracle_mod.energy(xp, v, m, G, eps)[1] - oracle_mod.energy(xm, v, m, G, eps)[1]) / (2 * h)
+            assert abs(m[i] * a[c, i] + dW) <= 1e-7 * (abs(dW) + 1e-3 * np.abs(m * a).max())
+
+
+def test_newton_third_law(oracle_mod):
+    x, _, m = ics.two_component(3000, seed=5)
+    a = oracle_mod.accel(x, m, G=1.0, eps=0.001)
+    tot = (a * m).sum(axis=1)
+    scale = (np.abs(a) * m).sum()
+    assert np.abs(tot).max() <= 1e-14 * scale
+
+
+def test_two_body_closed_form(oracle_mod):
+    """N = 2: |a_1| = G m_2 r / (r^2 + eps^2)^(3/2), directed towards body 2."""
+    x = np.array([[0.3, -1.1], [0.2, 0.7], [-0.4, 0.1]])
+    m = np.array([2.5, 0.75])
+    eps, G = 0.3, 0.9
+    a = oracle_mod.accel(x, m, G=G, eps=eps)
+    d = x[:, 1] - x[:, 0]
+    r = math.sqrt(float(d @ d))
+    mag = G * m[1] * r / (r * r + eps * eps) ** 1.5
+    np.testing.assert_allclose(np.linalg.norm(a[:, 0]), mag, rtol=1e-15)
+    np.testing.assert_allclose(a[:, 0] / np.linalg.norm(a[:, 0]), d / r, rtol=1e-14)
+    np.testing.assert_allclose(m[0] * a[:, 0], -m[1] * a[:, 1], rtol=1e-15)
+
+
+def test_plummer_mean_field(oracle_mod):
+    """Radial acceleration of a Plummer sample matches -G M r / (r^2 + a^2)^(3/2)."""
+    n = 8192
+    x, _, m = ics.plummer(n, seed=21)
+    acc = oracle_mod.accel(x, m, G=1.0, eps=0.002)
+    r = np.linalg.norm(x, axis=0)
+    ar = (acc * x).sum(axis=0) / r
+    a = ics.HENON_A
+    model = -r / (r * r + a * a) ** 1.5
+    edges = np.quantile(r, np.linspace(0.05, 0.9, 9))
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (r >= lo) & (r < hi)
+        ratio = ar[sel].mean() / model[sel].mean()
+        assert abs(ratio - 1.0) < 0.05, (lo, hi, ratio)
+
+
+def _kepler_positions(m1, m2, a_sm, e, t, G=1.0):
+    """Relative orbit from Kepler's equation, pericentre on +x at t = 0."""
+    mu = G * (m1 + m2)
+    n_mean = math.sqrt(mu / a_sm ** 3)
+    M = n_mean * t
+    E = M if e < 0.8 else math.pi
+    for _ in range(60):
+        E -= (E - e * math.sin(E) - M) / (1 - e * math.cos(E))
+    rx = a_sm * (math.cos(E) - e)
+    ry = a_sm * math.sqrt(1 - e * e) * math.sin(E)
+    return np.array([rx, ry, 0.0])
+
+
+def _kepler_ics(m1, m2, a_sm, e, G=1.0):
+    mu = G * (m1 + m2)
+    rp = a_sm * (1 - e)
+    vp = math.sqrt(mu * (1 + e) / (a_sm * (1 - e)))
+    rel_x = np.array([rp, 0.0, 0.0])
+    rel_v = np.array([0.0, vp, 0.0])
+    mt = m1 + m2
+    x = np.stack([-m2 / mt * rel_x, m1 / mt * rel_x], axis=1)
+    v = np.stack([-m2 / mt * rel_v, m1 / mt * rel_v], axis=1)
+    return x, v, np.array([m1, m2])
+
+
+def test_kepler_orbit_second_order(oracle_mod):
+    m1, m2, a_sm, e = 0.7, 0.3, 1.0, 0.5
+    x0, v0, m = _kepler_ics(m1, m2, a_sm, e)
+    period = 2 * math.pi * math.sqrt(a_sm ** 3 / (m1 + m2))
+    t_end = 0.8 * period
+    errs = []
+    for steps in (2000, 4000, 8000):
+        dt = t_end / steps
+        x, _ = oracle_mod.kdk(x0, v0, m, dt, steps, G=1.0, eps=0.0)
+        rel = x[:, 1] - x[:, 0]
+        errs.append(np.linalg.norm(rel - _kepler_positions(m1, m2, a_sm, e, t_end)))
+    assert errs[-1] < 2e-4
+    for coarse, fine in zip(errs[:-1], errs[1:]):
+        assert 3.5 < coarse / fine < 4.5, errs
+
+
+def test_momentum_and_angular_momentum_conserved(oracle_mod):
+    x, v, m = ics.random_cloud(64, seed=8)
+    e0 = oracle_mod.energy(x, v, m, 1.0, 0.05)
+    x1, v1 = oracle_mod.kdk(x, v, m, 1e-3, 50, G=1.0, eps=0.05)
+    e1 = oracle_mod.energy(x1, v1, m, 1.0, 0.05)
+    pscale = (m * np.abs(v1).sum(axis=0)).sum()
+    lscale = (m * np.linalg.norm(x1, axis=0) * np.linalg.norm(v1, axis=0)).sum()
+    assert np.abs(e1[3:6] - e0[3:6]).max() <= 1e-14 * pscale
+    assert np.abs(e1[6:9] - e0[6:9]).max() <= 1e-13 * lscale
+
+
+def test_time_reversibility(oracle_mod):
+    x, v, m = ics.plummer(128, seed=9)
+    x1, v1 = oracle_mod.kdk(x, v, m, 1.0 / 256, 40, eps=0.05)
+    x2, v2 = oracle_mod.kdk(x1, -v1, m, 1.0 / 256, 40, eps=0.05)
+    assert np.abs(x2 - x).max() < 1e-12
+    assert np.abs(v2 + v).max() < 1e-12
+
+
+def test_energy_error_second_order(oracle_mod):
+    """Leapfrog's energy error oscillates but its amplitude scales as dt^2: the
+    largest error over common sample times drops about 4x when dt halves."""
+    x, v, m = ics.plummer(256, seed=10)
+    eps = 0.05
+    e0 = oracle_mod.energy(x, v, m, 1.0, eps)[2]
+    amps = []
+    for dt in (1.0 / 64, 1.0 / 128):
+        per = int(round((1.0 / 32) / dt))
+        xs, vs, worst = x, v, 0.0
+        for _ in range(16):
+            xs, vs = oracle_mod.kdk(xs, vs, m, dt, per, eps=eps)
+            worst = max(worst, abs(oracle_mod.energy(xs, vs, m, 1.0, eps)[2] - e0))
+        amps.append(worst)
+    assert 3.0 < amps[0] / amps[1] < 5.0, amps
+
+
+def test_plummer_virial_and_energy(oracle_mod):
+    x, v, m = ics.plummer(16384, seed=12)
+    e = oracle_mod.energy(x, v, m, 1.0, 1e-4)
+    assert abs(2 * e[0] / abs(e[1]) - 1.0) < 0.05
+    assert abs(e[2] + 0.25) < 0.015
+
+
+def test_accel_rows_match_full(oracle_mod):
+    x, _, m = ics.plummer(700, seed=13)
+    full = oracle_mod.accel(x, m, eps=0.01)
+    rows = np.array([0, 5, 699, 350, 5])
+    part = oracle_mod.accel_rows(x, m, rows, eps=0.01)
+    assert np.array_equal(part, full[:, rows])
+
+
+def test_exclude_self_eps_zero(oracle_mod):
+    x, _, m = ics.random_cloud(10, seed=14)
+    a = oracle_mod.accel(x, m, eps=0.0)
+    assert np.isfinite(a).all()
+
+
+def test_vjp_dot_product(oracle_mod):
+    x, _, m = ics.random_cloud(24, seed=15)
+    rng = np.random.default_rng(1)
+    tx, tm, w = rng.standard_normal((3, 24)), rng.standard_normal(24), rng.standard_normal((3, 24))
+    jv = oracle_mod.accel_jvp(x, m, tx, tm, G=1.1, eps=0.07)
+    gx, gm = oracle_mod.accel_vjp(x, m, w, G=1.1, eps=0.07)
+    lhs = float((jv * w).sum())
+    rhs = float((tx * gx).sum() + (tm * gm).sum())
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs))
+
+
+def test_jvp_matches_central_difference(oracle_mod):
+    x, _, m = ics.random_cloud(16, seed=16)
+    rng = np.random.default_rng(2)
+    tx, tm = rng.standard_normal((3, 16)), rng.standard_normal(16)
+    h = 1e-6
+    fd = (oracle_mod.accel(x + h * tx, m + h * tm, eps=0.1)
+          - oracle_mod.accel(x - h * tx, m - h * tm, eps=0.1)) / (2 * h)
+    jv = oracle_mod.accel_jvp(x, m, tx, tm, eps=0.1)
+    assert np.abs(fd - jv).max() <= 1e-7 * np.abs(jv).max()
+
+
+# ---- independent complex-capable numpy forward model for the adjoint pins ----
+
+def _np_accel(x, m, eps, G):
+    d = x[:, None, :] - x[:, :, None]              # d[c, i, j] = x_j - x_i
+    s = (d * d).sum(axis=0) + eps * eps
+    n = x.shape[1]
+    s = s + np.eye(n)                               # keep the diagonal finite
+    w = m[None, :] / (s * np.sqrt(s))
+    w = w * (1 - np.eye(n))
+    return G * (w[None] * d).sum(axis=2)
+
+
+def _np_kdk_loss(x, v, m, tgt, dt, steps, eps, G):
+    a = _np_accel(x, m, eps, G)
+    for _ in range(steps):
+        v = v + 0.5 * dt * a
+        x = x + dt * v
+        a = _np_accel(x, m, eps, G)
+        v = v + 0.5 * dt * a
+    d = x - tgt
+    return (d * d).sum() / x.shape[1]
+
+
+def test_kdk_adjoint_complex_step(oracle_mod):
+    """Every component of the oracle's gradient against a complex-step derivative
+    (Squire & Trapp 1998) of an independent numpy forward model."""
+    n, steps, dt, eps, G = 6, 12, 1.0 / 64, 0.08, 1.0
+    x, v, m = ics.random_cloud(n, seed=17)
+    tgt = x + 0.05 * np.random.default_rng(3).standard_normal(x.shape)
+    loss, (gx, gv, gm) = oracle_mod.loss_grad(x, v, m, tgt, dt, steps, G=G, eps=eps)
+    assert abs(loss - _np_kdk_loss(x, v, m, tgt, dt, steps, eps, G)) <= 1e-13 * loss
+    h = 1e-30
+    for c in range(3):
+        for i in range(n):
+            xc = x.astype(complex); xc[c, i] += 1j * h
+            vc = v.astype(complex); vc[c, i] += 1j * h
+            np.testing.assert_allclose(gx[c, i], _np_kdk_loss(xc, v, m, tgt, dt, steps, eps, G).imag / h,
+                                       rtol=1e-11, atol=1e-14)
+            np.testing.assert_allclose(gv[c, i], _np_kdk_loss(x, vc, m, tgt, dt, steps, eps, G).imag / h,
+                                       rtol=1e-11, atol=1e-14)
+    for i in range(n):
+        mc = m.astype(complex); mc[i] += 1j * h
+        np.testing.assert_allclose(gm[i], _np_kdk_loss(x, v, mc, tgt, dt, steps, eps, G).imag / h,
+                                   rtol=1e-11, atol=1e-14)
+
+
+def test_kdk_adjoint_final_velocity_cotangent(oracle_mod):
+    """A cotangent on the final velocities propagates like the complex step says."""
+    n, steps, dt, eps = 5, 7, 1.0 / 32, 0.1
+    x, v, m = ics.random_cloud(n, seed=18)
+    wv = np.random.default_rng(4).standard_normal((3, n))
+    _, gv0, gm = oracle_mod.kdk_adjoint(x, v, m, dt, steps, np.zeros((3, n)), wv, eps=eps)
+
+    def final_v_dot(xc, vc, mc):
+        a = _np_accel(xc, mc, eps, 1.0)
+        for _ in range(steps):
+            vc = vc + 0.5 * dt * a
+            xc = xc + dt * vc
+            a = _np_accel(xc, mc, eps, 1.0)
+            vc = vc + 0.5 * dt * a
+        return (vc * wv).sum()
+
+    h = 1e-30
+    for i in range(n):
+        vc = v.astype(complex); vc[1, i] += 1j * h
+        np.testing.assert_allclose(gv0[1, i], final_v_dot(x, vc, m).imag / h, rtol=1e-11, atol=1e-14)
+        mc = m.astype(complex); mc[i] += 1j * h
+        np.testing.assert_allclose(gm[i], final_v_dot(x, v, mc).imag / h, rtol=1e-11, atol=1e-14)
+
+
+def test_kdk_adjoint_central_difference(oracle_mod):
+    """A Plummer-sampled system, gradient against central differences h = 1e-6."""
+    n, steps, dt, eps = 64, 20, 1.0 / 256, 0.01
+    x, v, m = ics.plummer(n, seed=19)
+    tgt, _ = ics.perturb(x, v, 1e-3, seed=20)
+    _, (gx, gv, gm) = oracle_mod.loss_grad(x, v, m, tgt, dt, steps, eps=eps)
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for _ in range(6):
+        c, i = int(rng.integers(3)), int(rng.integers(n))
+        for arr, g in ((x, gx), (v, gv)):
+            p = arr.copy(); p[c, i] += h
+            q = arr.copy(); q[c, i] -= h
+            if arr is x:
+                lp = oracle_mod.msd_loss(oracle_mod.kdk(p, v, m, dt, steps, eps=eps)[0], tgt)
+                lq = oracle_mod.msd_loss(oracle_mod.kdk(q, v, m, dt, steps, eps=eps)[0], tgt)
+            else:
+                lp = oracle_mod.msd_loss(oracle_mod.kdk(x, p, m, dt, steps, eps=eps)[0], tgt)
+                lq = oracle_mod.msd_loss(oracle_mod.kdk(x, q, m, dt, steps, eps=eps)[0], tgt)
+            fd = (lp - lq) / (2 * h)
+            assert abs(fd - g[c, i]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max())
