@@ -1,0 +1,194 @@
+/*
+ * nbody.h -- C ABI of libnbody_accel.so: softened O(N^2) direct-summation
+ * gravity on one AMD Instinct MI355X (gfx950), with a kick-drift-kick
+ * integrator, energy/momentum diagnostics, a batched ensemble integrator and
+ * the adjoint (reverse-mode) of the integrated trajectory.
+ *
+ * What is computed (paper: "Assessing Performance and Porting Strategies for
+ * Gravitational N-Body Simulations on the RISC-V-Based Tenstorrent Wormhole"):
+ *   a_i = G * sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2)
+ * which is the force of Eq. (1) (Sec. 2.1) divided by m_i, with the softening
+ * parameter of App. A entering the squared distance.  The pair arithmetic
+ * follows App. A, Algorithm 3 (displacement, squared distance, inverse square
+ * root, its cube, weight times cube, accumulate); the weight p_w,j is G m_j.
+ * The accelerator computes only the pairwise evaluation and the rest stays in
+ * FP64 (Sec. 3.1); here that rest (state update, diagnostics) also stays on
+ * the GPU, in FP64.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (hipMalloc / torch CUDA tensors) on
+ *     the current HIP device, owned by the caller, contiguous, 8-byte aligned,
+ *     float64.  Vectors are SoA: v[c*n + i] for component c = 0 (x), 1 (y),
+ *     2 (z) of particle i; masses m[i].  Pointers marked "host" are ordinary
+ *     host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued on it and the call returns without waiting, unless a
+ *     function says otherwise.  Outputs are valid once the stream reaches the
+ *     enqueued work.
+ *   - Arguments are validated before anything is enqueued; on a negative
+ *     status nothing was launched and no output was touched (except where a
+ *     function says so).  nbody_last_error() then returns a message.
+ *   - The library keeps one scratch workspace per device.  It grows on demand
+ *     (hipMalloc, which may synchronise the device) and is released by
+ *     nbody_finalize().  Calls that share a device share that workspace, so
+ *     calls enqueued on different streams of one device must not overlap.
+ *   - Results are deterministic: the same inputs and configuration give
+ *     bitwise-identical outputs (no floating-point atomics anywhere).
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every entry point. */
+typedef enum {
+  NBODY_OK = 0,
+  NBODY_EINVAL = -1,       /* bad argument (null pointer, n < 0, eps < 0, ...) */
+  NBODY_EHIP = -2,         /* a HIP runtime call or kernel launch failed */
+  NBODY_ENOMEM = -3,       /* workspace allocation failed */
+  NBODY_ENONFINITE = -4,   /* NBODY_CHECK_FINITE found NaN/Inf in an output */
+  NBODY_EUNSUPPORTED = -5  /* valid request this build cannot serve */
+} nbody_status;
+
+/* Arithmetic of the pair evaluation.  The particle state, the integrator and
+ * the diagnostics are FP64 in every mode. */
+typedef enum {
+  NBODY_FP64 = 0,   /* all pair arithmetic in FP64 (the plain FP64 path) */
+  NBODY_FP32C = 1,  /* FP32 pairs on float-float (hi+lo) positions, so the
+                       displacement x_j - x_i keeps FP64-level accuracy;
+                       compensated (TwoSum) accumulation of the j-sum */
+  NBODY_FP32 = 2    /* FP32 pairs on positions rounded to FP32; same
+                       compensated accumulation (faster, less accurate for
+                       close pairs far from the origin) */
+} nbody_precision;
+
+/* Bits of nbody_params.flags. */
+enum {
+  NBODY_EXCLUDE_SELF = 1,  /* mask j == i explicitly; required when eps == 0
+                              (with eps > 0 the self term is exactly zero) */
+  NBODY_CHECK_FINITE = 2,  /* after the call, wait for the stream and return
+                              NBODY_ENONFINITE if an output holds NaN/Inf */
+  NBODY_ACC_VALID = 4      /* nbody_step / nbody_step_batched: `a` already
+                              holds a(x) on entry, skip the initial evaluation */
+};
+
+typedef struct nbody_params {
+  double G;           /* gravitational constant (Eq. (1)); any finite value */
+  double eps;         /* Plummer softening length, >= 0 (App. A) */
+  int32_t precision;  /* an nbody_precision value */
+  uint32_t flags;     /* OR of the flag bits above */
+} nbody_params;
+
+/* Accelerations a (3*n) of particles at x (3*n) with masses m (n).
+ * Eq. (1) of Sec. 2.1 divided by m_i, softened as in App. A.
+ * n == 0 is a no-op.  x, m, a must not alias.  Errors: NBODY_EINVAL for null
+ * pointers with n > 0, n < 0, n > 2^31 - 1024, eps < 0, eps == 0 without
+ * NBODY_EXCLUDE_SELF, non-finite G, unknown precision. */
+int nbody_accel(int64_t n, const double* x, const double* m, double* a,
+                const nbody_params* p, void* stream);
+
+/* nsteps kick-drift-kick leapfrog steps of size dt, in place on x, v, a:
+ *   v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a
+ * (the workloads' integrator; the paper's Sec. 2.1 predict-evaluate-correct
+ * loop has the same structure of one all-pairs evaluation per step).
+ * On entry a must hold a(x) if NBODY_ACC_VALID is set, otherwise it is
+ * computed first; on return a = a(x_final), so consecutive calls chain and
+ * S steps in one call equal S1 + S2 steps in two calls bitwise.
+ * nsteps == 0 only (re)computes a unless NBODY_ACC_VALID is set.
+ * Errors: as nbody_accel, plus non-finite dt or nsteps < 0. */
+int nbody_step(int64_t n, double* x, double* v, double* a, const double* m, double dt,
+               int64_t nsteps, const nbody_params* p, void* stream);
+
+/* Diagnostics of the state (x, v, m), always in FP64, written to the device
+ * array out9 = {K, W, E, Px, Py, Pz, Lx, Ly, Lz}:
+ *   K = 1/2 sum m_i |v_i|^2,  W = -G sum_{i<j} m_i m_j / sqrt(|d_ij|^2 + eps^2)
+ *   (the self pair is always excluded), E = K + W, P = sum m v, L = sum m x x v.
+ * These are the energies compared in Sec. 4.1 (Fig. 4) and the conserved
+ * quantities of the integrator.  p->precision is ignored.  eps == 0 is
+ * allowed (the self pair is excluded by index). */
+int nbody_energy(int64_t n, const double* x, const double* v, const double* m,
+                 const nbody_params* p, double* out9, void* stream);
+
+/* Vector-Jacobian products of the acceleration map at (x, m) with cotangent
+ * w (3*n), obtained by differentiating Eq. (1) / m_i term by term:
+ *   gx_k = G sum_{j != k} K(d_kj) (m_k w_j - m_j w_k),
+ *   gm_k = -G sum_{j != k} s_kj^(-3/2) (d_kj . w_j),
+ *   d_kj = x_j - x_k, s = |d|^2 + eps^2, K(d) = s^(-3/2) I - 3 s^(-5/2) d d^T.
+ * Outputs gx (3*n) and gm (n) are overwritten.  Pair arithmetic follows
+ * p->precision (FP32C/FP32 use FP32 pairs with compensated sums).
+ * Errors: as nbody_accel. */
+int nbody_accel_vjp(int64_t n, const double* x, const double* m, const double* w,
+                    double* gx, double* gm, const nbody_params* p, void* stream);
+
+/* Reverse-mode derivative of `nsteps` KDK steps from (x0, v0) (the map of
+ * nbody_step starting without NBODY_ACC_VALID), using checkpoints.
+ *   ckpt_x, ckpt_v: [nckpt][3][n] states at steps 0, every, 2*every, ...,
+ *                   nckpt = ceil(nsteps / every); checkpoint 0 is (x0, v0).
+ *   gxT, gvT:       cotangents of the final positions and velocities (3*n).
+ *   gx0, gv0, gm:   outputs, cotangents of x0, v0 (3*n) and m (n).
+ * Each segment is recomputed forward from its checkpoint with the same kernels
+ * as nbody_step (bitwise the same trajectory), then swept in reverse; the two
+ * Jacobian products at each interior position share one cotangent and are
+ * merged into one VJP evaluation per step.  Inputs are not modified.
+ * Errors: as nbody_step, plus every < 1. */
+int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64_t every,
+                    int64_t nsteps, const double* m, double dt, const double* gxT,
+                    const double* gvT, double* gx0, double* gv0, double* gm,
+                    const nbody_params* p, void* stream);
+
+/* Batched ensemble: ncl independent systems concatenated along the particle
+ * axis; system c owns columns [off[c], off[c+1]) of x, v, a (each 3*total,
+ * SoA over the whole concatenation, total = off[ncl]) and m (total), and has
+ * softening eps[c].  Each system advances nsteps KDK steps exactly as
+ * nbody_step would advance it alone (same pair arithmetic, FP64 state), all
+ * systems and all steps inside ONE persistent kernel launch.  off (ncl+1,
+ * int64, off[0] == 0, non-decreasing) and eps (ncl) are HOST arrays; the
+ * work plan built from them is cached, so a repeated call with the same
+ * layout enqueues only the launch (and may be captured into a HIP graph).
+ * Systems larger than the persistent kernel's LDS capacity return
+ * NBODY_EUNSUPPORTED.  p->eps is ignored; p->precision must be NBODY_FP32C,
+ * NBODY_FP32 or NBODY_FP64. */
+int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, double* x,
+                       double* v, double* a, const double* m, double dt, int64_t nsteps,
+                       const nbody_params* p, void* stream);
+
+/* Tile configuration of the all-pairs kernels (see nbody_set_config). */
+typedef struct nbody_config {
+  int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
+  int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
+  int32_t bcl;     /* batched kernel: threads per workgroup (256, 512 or 1024), 0 = auto */
+  int32_t reserved;
+} nbody_config;
+
+/* Force a tile configuration for subsequent calls on this thread (all zeros
+ * restores the automatic choice).  Errors: NBODY_EINVAL for values outside
+ * the lists above. */
+int nbody_set_config(const nbody_config* cfg);
+
+/* Autotuner: for a system of n particles and the given precision, time every
+ * supported tile configuration of the force kernel with HIP events on a
+ * synthetic input (synchronous; allocates and frees its own buffers) and
+ * record the fastest in the library's per-device table, which automatic
+ * selection then uses for that (n, precision).  If cache_path is non-NULL the
+ * table is also appended there as one JSON object per line.  best (host,
+ * may be NULL) receives the chosen configuration. */
+int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_config* best);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* nbody_last_error(void);
+
+/* Releases the per-device workspaces and plans. */
+int nbody_finalize(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int nbody_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

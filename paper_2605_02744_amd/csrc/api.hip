@@ -1,0 +1,450 @@
+// C ABI of libnbody_accel (declared in include/nbody.h): argument validation,
+// per-device workspace, tile-configuration choice and the autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace nb {
+
+int run_traj_grad(int64_t n, const double* ckx, const double* ckv, int64_t every, int64_t nsteps,
+                  const double* m, double dt, const double* gxT, const double* gvT, double* gx0, double* gv0,
+                  double* gm, double G, double eps, int precision, bool excl, const PairConfig& cfg,
+                  hipStream_t s);
+int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
+                bool acc_valid, hipStream_t s);
+void release_batched_plans();
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+int set_error(int status, const std::string& msg) {
+  g_err = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_error(NBODY_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// --------------------------------------------------------------- workspace
+namespace {
+constexpr int kMaxDev = 64;
+constexpr int kSlots = 4;
+struct Buf { void* p = nullptr; size_t bytes = 0; };
+std::mutex g_ws_mu;
+Buf g_ws[kMaxDev][kSlots];
+int g_cus[kMaxDev] = {0};
+}  // namespace
+
+int current_device() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return 0;
+  return d;
+}
+
+int cu_count(int device) {
+  if (device < 0 || device >= kMaxDev) return 256;
+  if (g_cus[device] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c <= 0) c = 256;
+    g_cus[device] = c;
+  }
+  return g_cus[device];
+}
+
+void* workspace(int device, int slot, size_t bytes, int* status) {
+  if (device < 0 || device >= kMaxDev || slot < 0 || slot >= kSlots) {
+    *status = set_error(NBODY_EINVAL, "workspace: bad device or slot");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  Buf& b = g_ws[device][slot];
+  if (b.bytes >= bytes && b.p) return b.p;
+  size_t want = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+  if (b.p) {
+    // the old buffer may still be read by enqueued work
+    if (hipDeviceSynchronize() != hipSuccess || hipFree(b.p) != hipSuccess) {
+      *status = set_error(NBODY_EHIP, "workspace: releasing the previous buffer failed");
+      return nullptr;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    *status = set_error(NBODY_ENOMEM, "workspace: hipMalloc of " + std::to_string(want) + " bytes failed");
+    return nullptr;
+  }
+  b.p = p;
+  b.bytes = want;
+  return p;
+}
+
+void release_workspaces() {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (int d = 0; d < kMaxDev; ++d)
+    for (int s = 0; s < kSlots; ++s)
+      if (g_ws[d][s].p) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(d);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g_ws[d][s].p);
+        (void)hipSetDevice(prev);
+        g_ws[d][s] = Buf{};
+      }
+}
+
+// ------------------------------------------------------------- configuration
+namespace {
+thread_local nbody_config t_cfg = {0, 0, 0, 0};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t>, PairConfig> g_tuned;  // (device, precision, n)
+}  // namespace
+
+void set_thread_config(const nbody_config& c) { t_cfg = c; }
+const nbody_config& thread_config() { return t_cfg; }
+
+void record_tuned(int device, int64_t n, int precision, const PairConfig& c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[std::make_tuple(device, precision, n)] = c;
+}
+
+// Default choice: 2 i per lane, and a j-split that gives every CU several
+// rounds of workgroups (so the last round's imbalance stays small) while
+// keeping at least 4 LDS tiles per workgroup.
+static int auto_split(int64_t n, int ipl, int device) {
+  const int64_t iblocks = (n + kBlock * ipl - 1) / (kBlock * ipl);
+  const int64_t target = 24LL * cu_count(device);
+  const int64_t smax = std::max<int64_t>(1, n / (4 * kTile));
+  int64_t s = (target + iblocks - 1) / iblocks;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(smax, 1024)));
+}
+
+PairConfig choose_config(int64_t n, int precision, int device) {
+  PairConfig c;
+  const nbody_config& t = t_cfg;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(device, precision, n));
+    if (it != g_tuned.end()) c = it->second;
+    else c.split = 0;
+  }
+  if (t.ipl) c.ipl = t.ipl;
+  if (t.split) c.split = t.split;
+  if (c.split <= 0) c.split = auto_split(n, c.ipl, device);
+  return c;
+}
+
+// ------------------------------------------------------------- validation
+namespace {
+
+int check_dev_range(const void* p, size_t bytes, const char* name) {
+  if (!p) return set_error(NBODY_EINVAL, std::string(name) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) % 8 != 0)
+    return set_error(NBODY_EINVAL, std::string(name) + " is not 8-byte aligned");
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(NBODY_EINVAL, std::string(name) + " is not a HIP device pointer");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return set_error(NBODY_EINVAL, std::string(name) + " is not device memory");
+  if (at.device != current_device())
+    return set_error(NBODY_EINVAL, std::string(name) + " belongs to another device");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+    const char* b = static_cast<const char*>(base);
+    const char* q = static_cast<const char*>(p);
+    if (q < b || q + bytes > b + size)
+      return set_error(NBODY_EINVAL, std::string(name) + " is smaller than the size implied by n");
+  } else {
+    (void)hipGetLastError();
+  }
+  return NBODY_OK;
+}
+
+constexpr int64_t kMaxN = int64_t(1) << 29;
+
+int check_common(int64_t n, const nbody_params* p, bool need_eps_rule) {
+  if (!p) return set_error(NBODY_EINVAL, "params is NULL");
+  if (n < 0) return set_error(NBODY_EINVAL, "n < 0");
+  if (n > kMaxN) return set_error(NBODY_EINVAL, "n exceeds 2^29");
+  if (!std::isfinite(p->G)) return set_error(NBODY_EINVAL, "G is not finite");
+  if (!std::isfinite(p->eps) || p->eps < 0) return set_error(NBODY_EINVAL, "eps must be finite and >= 0");
+  if (p->precision != NBODY_FP64 && p->precision != NBODY_FP32C && p->precision != NBODY_FP32)
+    return set_error(NBODY_EINVAL, "unknown precision");
+  if (p->flags & ~uint32_t(NBODY_EXCLUDE_SELF | NBODY_CHECK_FINITE | NBODY_ACC_VALID))
+    return set_error(NBODY_EINVAL, "unknown flag bits");
+  if (need_eps_rule && p->eps == 0.0 && !(p->flags & NBODY_EXCLUDE_SELF))
+    return set_error(NBODY_EINVAL, "eps == 0 requires NBODY_EXCLUDE_SELF");
+  return NBODY_OK;
+}
+
+#define NB_TRY(expr)          \
+  do {                        \
+    int nb_s_ = (expr);       \
+    if (nb_s_) return nb_s_;  \
+  } while (0)
+
+int finish(int st, hipStream_t s, const nbody_params* p, std::initializer_list<std::pair<const double*, int64_t>> outs) {
+  if (st) return st;
+  if (!(p->flags & NBODY_CHECK_FINITE)) return NBODY_OK;
+  for (auto& o : outs) {
+    bool ok = true;
+    NB_TRY(check_finite(o.first, o.second, s, &ok));
+    if (!ok) return set_error(NBODY_ENONFINITE, "output contains NaN or Inf");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace
+}  // namespace nb
+
+using namespace nb;
+
+extern "C" {
+
+int nbody_accel(int64_t n, const double* x, const double* m, double* a, const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  if ((const void*)a == (const void*)x || (const void*)a == (const void*)m)
+    return set_error(NBODY_EINVAL, "a aliases an input");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = launch_accel(n, x, m, a, p->G, p->eps, p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0, cfg, s);
+  return finish(st, s, p, {{a, 3 * n}});
+}
+
+int nbody_step(int64_t n, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
+               const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt is not finite");
+  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(v, b3, "v"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  if (x == v || x == a || v == a) return set_error(NBODY_EINVAL, "x, v and a must be distinct");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = run_kdk(n, x, v, a, m, dt, nsteps, p->G, p->eps, p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0,
+                   (p->flags & NBODY_ACC_VALID) != 0, cfg, s, nullptr);
+  return finish(st, s, p, {{x, 3 * n}, {v, 3 * n}, {a, 3 * n}});
+}
+
+int nbody_energy(int64_t n, const double* x, const double* v, const double* m, const nbody_params* p,
+                 double* out9, void* stream) {
+  NB_TRY(check_common(n, p, false));
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  if (n > 0) {
+    NB_TRY(check_dev_range(x, b3, "x"));
+    NB_TRY(check_dev_range(v, b3, "v"));
+    NB_TRY(check_dev_range(m, b1, "m"));
+  }
+  NB_TRY(check_dev_range(out9, 9 * sizeof(double), "out9"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = launch_energy(n, x, v, m, p->G, p->eps, out9, s);
+  return finish(st, s, p, {{out9, 9}});
+}
+
+int nbody_accel_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm,
+                    const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(w, b3, "w"));
+  NB_TRY(check_dev_range(gx, b3, "gx"));
+  NB_TRY(check_dev_range(gm, b1, "gm"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = launch_vjp(n, x, m, w, gx, gm, p->G, p->eps, p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0, cfg, s);
+  return finish(st, s, p, {{gx, 3 * n}, {gm, n}});
+}
+
+int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64_t every, int64_t nsteps,
+                    const double* m, double dt, const double* gxT, const double* gvT, double* gx0, double* gv0,
+                    double* gm, const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt is not finite");
+  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
+  if (every < 1) return set_error(NBODY_EINVAL, "every < 1");
+  if (n == 0) return NBODY_OK;
+  const int64_t nck = std::max<int64_t>(1, (nsteps + every - 1) / every);
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(ckpt_x, b3 * nck, "ckpt_x"));
+  NB_TRY(check_dev_range(ckpt_v, b3 * nck, "ckpt_v"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(gxT, b3, "gxT"));
+  NB_TRY(check_dev_range(gvT, b3, "gvT"));
+  NB_TRY(check_dev_range(gx0, b3, "gx0"));
+  NB_TRY(check_dev_range(gv0, b3, "gv0"));
+  NB_TRY(check_dev_range(gm, b1, "gm"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = run_traj_grad(n, ckpt_x, ckpt_v, every, nsteps, m, dt, gxT, gvT, gx0, gv0, gm, p->G, p->eps,
+                         p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0, cfg, s);
+  return finish(st, s, p, {{gx0, 3 * n}, {gv0, 3 * n}, {gm, n}});
+}
+
+int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                       const double* m, double dt, int64_t nsteps, const nbody_params* p, void* stream) {
+  if (!p) return set_error(NBODY_EINVAL, "params is NULL");
+  if (ncl < 0) return set_error(NBODY_EINVAL, "ncl < 0");
+  if (ncl == 0) return NBODY_OK;
+  if (!off || !eps) return set_error(NBODY_EINVAL, "off and eps must be host arrays");
+  if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt is not finite");
+  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
+  if (!std::isfinite(p->G)) return set_error(NBODY_EINVAL, "G is not finite");
+  if (p->precision != NBODY_FP64 && p->precision != NBODY_FP32C && p->precision != NBODY_FP32)
+    return set_error(NBODY_EINVAL, "unknown precision");
+  if (p->flags & ~uint32_t(NBODY_EXCLUDE_SELF | NBODY_CHECK_FINITE | NBODY_ACC_VALID))
+    return set_error(NBODY_EINVAL, "unknown flag bits");
+  if (off[0] != 0) return set_error(NBODY_EINVAL, "off[0] must be 0");
+  for (int32_t c = 0; c < ncl; ++c) {
+    if (off[c + 1] < off[c]) return set_error(NBODY_EINVAL, "off must be non-decreasing");
+    if (!std::isfinite(eps[c]) || eps[c] < 0) return set_error(NBODY_EINVAL, "eps[c] must be finite and >= 0");
+    if (eps[c] == 0.0 && !(p->flags & NBODY_EXCLUDE_SELF))
+      return set_error(NBODY_EINVAL, "eps[c] == 0 requires NBODY_EXCLUDE_SELF");
+  }
+  const int64_t total = off[ncl];
+  if (total > kMaxN) return set_error(NBODY_EINVAL, "total particle count exceeds 2^29");
+  if (total == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)total, b1 = sizeof(double) * (size_t)total;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(v, b3, "v"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  if (x == v || x == a || v == a) return set_error(NBODY_EINVAL, "x, v and a must be distinct");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = run_batched(ncl, off, eps, x, v, a, m, dt, nsteps, p->G, p->precision,
+                       (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, s);
+  return finish(st, s, p, {{x, 3 * total}, {v, 3 * total}, {a, 3 * total}});
+}
+
+int nbody_set_config(const nbody_config* cfg) {
+  if (!cfg) return set_error(NBODY_EINVAL, "cfg is NULL");
+  if (cfg->ipl != 0 && cfg->ipl != 1 && cfg->ipl != 2 && cfg->ipl != 4)
+    return set_error(NBODY_EINVAL, "ipl must be 0, 1, 2 or 4");
+  if (cfg->split < 0 || cfg->split > 1024) return set_error(NBODY_EINVAL, "split must be in 0..1024");
+  if (cfg->bcl != 0 && cfg->bcl != 256 && cfg->bcl != 512 && cfg->bcl != 1024)
+    return set_error(NBODY_EINVAL, "bcl must be 0, 256, 512 or 1024");
+  set_thread_config(*cfg);
+  return NBODY_OK;
+}
+
+int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_config* best) {
+  if (n <= 0 || n > kMaxN) return set_error(NBODY_EINVAL, "n must be in 1..2^29");
+  if (precision != NBODY_FP64 && precision != NBODY_FP32C && precision != NBODY_FP32)
+    return set_error(NBODY_EINVAL, "unknown precision");
+  const int dev = current_device();
+  // synthetic input: a deterministic pseudo-random cloud in the unit cube
+  std::vector<double> hx(3 * (size_t)n), hm((size_t)n);
+  uint64_t st64 = 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    st64 = st64 * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(st64 >> 11) * (1.0 / 9007199254740992.0);
+  };
+  for (auto& v : hx) v = 2.0 * next() - 1.0;
+  for (auto& v : hm) v = (0.5 + next()) / (double)n;
+  double *dx = nullptr, *dm = nullptr, *da = nullptr;
+  auto cleanup = [&]() {
+    if (dx) (void)hipFree(dx);
+    if (dm) (void)hipFree(dm);
+    if (da) (void)hipFree(da);
+  };
+  if (hipMalloc(&dx, hx.size() * 8) != hipSuccess || hipMalloc(&dm, hm.size() * 8) != hipSuccess ||
+      hipMalloc(&da, hx.size() * 8) != hipSuccess) {
+    cleanup();
+    return set_error(NBODY_ENOMEM, "tune: allocation failed");
+  }
+  if (hipMemcpy(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dm, hm.data(), hm.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    cleanup();
+    return set_error(NBODY_EHIP, "tune: copy failed");
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best_ms = 1e30f;
+  PairConfig bc;
+  const int ipls[3] = {1, 2, 4};
+  std::vector<std::pair<PairConfig, float>> log;
+  for (int ipl : ipls) {
+    const int base = auto_split(n, ipl, dev);
+    std::vector<int> splits = {base};
+    for (int f : {2, 4}) {
+      if (base / f >= 1) splits.push_back(base / f);
+      if ((int64_t)base * f <= std::max<int64_t>(1, std::min<int64_t>(1024, n / (4 * kTile)))) splits.push_back(base * f);
+    }
+    std::sort(splits.begin(), splits.end());
+    splits.erase(std::unique(splits.begin(), splits.end()), splits.end());
+    for (int sp : splits) {
+      PairConfig c;
+      c.ipl = ipl;
+      c.split = sp;
+      int st = launch_accel(n, dx, dm, da, 1.0, 0.01, precision, false, c, nullptr);
+      if (st) { cleanup(); return st; }
+      const int reps = 3;
+      (void)hipEventRecord(e0, nullptr);
+      for (int r = 0; r < reps; ++r) launch_accel(n, dx, dm, da, 1.0, 0.01, precision, false, c, nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      if (hipEventSynchronize(e1) != hipSuccess) { cleanup(); return set_error(NBODY_EHIP, "tune: sync failed"); }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      log.push_back({c, ms});
+      if (ms < best_ms) { best_ms = ms; bc = c; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cleanup();
+  record_tuned(dev, n, precision, bc);
+  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0};
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      hipDeviceProp_t prop;
+      (void)hipGetDeviceProperties(&prop, dev);
+      std::fprintf(f, "{\"arch\": \"%s\", \"n\": %lld, \"precision\": %d, \"ipl\": %d, \"split\": %d, \"ms\": %.6f, \"trials\": [",
+                   prop.gcnArchName, (long long)n, precision, bc.ipl, bc.split, best_ms);
+      for (size_t k = 0; k < log.size(); ++k)
+        std::fprintf(f, "%s[%d, %d, %.6f]", k ? ", " : "", log[k].first.ipl, log[k].first.split, log[k].second);
+      std::fprintf(f, "]}\n");
+      std::fclose(f);
+    }
+  }
+  return NBODY_OK;
+}
+
+const char* nbody_last_error(void) { return g_err.c_str(); }
+
+int nbody_finalize(void) {
+  release_batched_plans();
+  release_workspaces();
+  return NBODY_OK;
+}
+
+int nbody_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP sources of libnbody_accel.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+
+#include "nbody.h"
+
+namespace nb {
+
+// ---------------------------------------------------------------- errors
+// Thread-local message for nbody_last_error(); set_error returns the status.
+int set_error(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define NB_HIP(call)                                        \
+  do {                                                      \
+    hipError_t nb_e_ = (call);                              \
+    if (nb_e_ != hipSuccess) return ::nb::hip_fail(nb_e_, #call); \
+  } while (0)
+
+#define NB_LAUNCH_CHECK(what)                                \
+  do {                                                       \
+    hipError_t nb_e_ = hipGetLastError();                    \
+    if (nb_e_ != hipSuccess) return ::nb::hip_fail(nb_e_, what); \
+  } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Growable scratch allocations, one per (device, slot), never shrunk.  Slots
+// keep nested users apart: 0 = per-launch partial sums of the all-pairs
+// kernels, 1 = per-call buffers of a driver (energy, adjoint sweep),
+// 2 = batched plans, 3 = status flags.  Growing a slot synchronises the device.
+void* workspace(int device, int slot, size_t bytes, int* status);
+void release_workspaces();
+int current_device();
+int cu_count(int device);
+
+// ---------------------------------------------------------------- constants
+constexpr int kBlock = 256;        // threads per workgroup of the all-pairs kernels
+constexpr int kTile = 256;         // j-particles staged in LDS per tile
+constexpr int kFold = 64;          // j-terms summed in plain FP32/FP64 before a TwoSum fold
+constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
+
+// Per-call configuration of the all-pairs kernels.
+struct PairConfig {
+  int ipl = 2;    // i-particles per lane
+  int split = 1;  // j-range split across workgroups
+};
+
+PairConfig choose_config(int64_t n, int precision, int device);
+void set_thread_config(const nbody_config& c);
+const nbody_config& thread_config();
+void record_tuned(int device, int64_t n, int precision, const PairConfig& c);
+
+// ---------------------------------------------------------------- launchers
+// Accelerations a(x) into `a` (FP64 SoA).  Uses the workspace for j-split
+// partial sums.  Returns NBODY_OK or an error status.
+int launch_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps,
+                 int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
+
+// (da/dx)^T w into gx and (da/dm)^T w into gm.
+int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx,
+               double* gm, double G, double eps, int precision, bool exclude_self,
+               const PairConfig& cfg, hipStream_t s);
+
+// Elementwise KDK pieces over 3n entries.
+int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s);
+int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double h, double dt,
+                      int nkicks, hipStream_t s);
+
+// Energy/momentum diagnostics into out9 (device).
+int launch_energy(int64_t n, const double* x, const double* v, const double* m, double G,
+                  double eps, double* out9, hipStream_t s);
+
+// Returns true if any of the n doubles at p is NaN/Inf (synchronises s).
+int check_finite(const double* p, int64_t n, hipStream_t s, bool* all_finite);
+
+// The KDK integration loop shared by nbody_step and the adjoint's recompute.
+// If traj != nullptr, positions after every step are copied to traj[(k+1)*3n].
+int run_kdk(int64_t n, double* x, double* v, double* a, const double* m, double dt,
+            int64_t nsteps, double G, double eps, int precision, bool exclude_self,
+            bool acc_valid, const PairConfig& cfg, hipStream_t s, double* traj);
+
+}  // namespace nb

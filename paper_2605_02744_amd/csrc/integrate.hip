@@ -1,0 +1,290 @@
+// O(N) kernels and drivers of libnbody_accel: the kick-drift-kick integrator,
+// the energy/momentum diagnostics and the checkpointed adjoint sweep.  All of
+// this is FP64 and bound by HBM bandwidth; the all-pairs work lives in pairs.hip.
+#include "common.h"
+
+namespace nb {
+
+int launch_potential(int64_t n, const double* x, const double* m, double eps, double* phi, int split,
+                     hipStream_t s);
+
+namespace {
+
+constexpr int kEw = 256;  // threads per block of the elementwise kernels
+
+inline unsigned ew_blocks(int64_t cnt) { return (unsigned)((cnt + kEw - 1) / kEw); }
+
+// v += h a (nkicks times, each rounded separately) then x += dt v.
+// nkicks = 2 is the closing half-kick of one step followed by the opening
+// half-kick of the next, so one call of S steps equals two calls of S1 + S2.
+__global__ void kick_drift_kernel(int64_t n3, double* __restrict__ x, double* __restrict__ v,
+                                  const double* __restrict__ a, double h, double dt, int nkicks) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  double ae = a[e];
+  double ve = v[e];
+  for (int k = 0; k < nkicks; ++k) ve = fma(h, ae, ve);
+  v[e] = ve;
+  x[e] = fma(dt, ve, x[e]);
+}
+
+__global__ void kick_kernel(int64_t n3, double* __restrict__ v, const double* __restrict__ a, double h) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  v[e] = fma(h, a[e], v[e]);
+}
+
+__global__ void copy_kernel(int64_t cnt, const double* __restrict__ src, double* __restrict__ dst) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt) dst[e] = src[e];
+}
+
+__global__ void fill_kernel(int64_t cnt, double* __restrict__ dst, double val) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt) dst[e] = val;
+}
+
+// Adjoint bookkeeping after one merged VJP at position index p:
+//   lx += gxp;  gm += gmp;  if (drift) lv += dt * lx
+__global__ void adjoint_update_kernel(int64_t n, double* __restrict__ lx, double* __restrict__ lv,
+                                      double* __restrict__ gm, const double* __restrict__ gxp,
+                                      const double* __restrict__ gmp, double dt, int drift) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  double l = lx[e] + gxp[e];
+  lx[e] = l;
+  if (drift) lv[e] = fma(dt, l, lv[e]);
+  if (e < n) gm[e] += gmp[e];
+}
+
+// ---- deterministic reduction of the diagnostics -----------------------
+// Each thread accumulates fixed-stride elements into 9 (hi, lo) TwoSum pairs;
+// the block then combines lanes in a fixed tree order.
+struct DD { double h, l; };
+
+__device__ __forceinline__ void dd_add(DD& a, double x) {
+  double s = a.h + x;
+  double bp = s - a.h;
+  a.l += (a.h - (s - bp)) + (x - bp);
+  a.h = s;
+}
+__device__ __forceinline__ void dd_add(DD& a, const DD& b) {
+  dd_add(a, b.h);
+  a.l += b.l;
+}
+
+constexpr int kRedBlock = 256;
+constexpr int kRedBlocks = 256;
+constexpr int kQ = 9;  // K, W, (unused slot for E), Px, Py, Pz, Lx, Ly, Lz
+
+__device__ void block_reduce_store(DD (&acc)[kQ], DD* __restrict__ dst) {
+  __shared__ DD sh[kQ][kRedBlock];
+  const int t = threadIdx.x;
+  for (int q = 0; q < kQ; ++q) sh[q][t] = acc[q];
+  __syncthreads();
+  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (t < w)
+      for (int q = 0; q < kQ; ++q) dd_add(sh[q][t], sh[q][t + w]);
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int q = 0; q < kQ; ++q) dst[q] = sh[q][0];
+}
+
+__global__ __launch_bounds__(kRedBlock) void energy_partial_kernel(int64_t n, const double* __restrict__ x,
+                                                                   const double* __restrict__ v,
+                                                                   const double* __restrict__ m,
+                                                                   const double* __restrict__ phi, double G,
+                                                                   DD* __restrict__ part) {
+  DD acc[kQ];
+  for (int q = 0; q < kQ; ++q) acc[q] = DD{0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double mi = m[i];
+    const double px = x[i], py = x[n + i], pz = x[2 * n + i];
+    const double vx = v[i], vy = v[n + i], vz = v[2 * n + i];
+    dd_add(acc[0], 0.5 * mi * (vx * vx + vy * vy + vz * vz));
+    dd_add(acc[1], -0.5 * G * mi * phi[i]);
+    dd_add(acc[3], mi * vx);
+    dd_add(acc[4], mi * vy);
+    dd_add(acc[5], mi * vz);
+    dd_add(acc[6], mi * (py * vz - pz * vy));
+    dd_add(acc[7], mi * (pz * vx - px * vz));
+    dd_add(acc[8], mi * (px * vy - py * vx));
+  }
+  block_reduce_store(acc, part + (size_t)blockIdx.x * kQ);
+}
+
+__global__ __launch_bounds__(kRedBlock) void energy_final_kernel(int nparts, const DD* __restrict__ part,
+                                                                 double* __restrict__ out9) {
+  DD acc[kQ];
+  for (int q = 0; q < kQ; ++q) acc[q] = DD{0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+    for (int q = 0; q < kQ; ++q) dd_add(acc[q], part[(size_t)b * kQ + q]);
+  __shared__ DD res[kQ];
+  block_reduce_store(acc, res);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double K = res[0].h + res[0].l;
+    const double W = res[1].h + res[1].l;
+    out9[0] = K;
+    out9[1] = W;
+    out9[2] = K + W;
+    for (int q = 3; q < kQ; ++q) out9[q] = res[q].h + res[q].l;
+  }
+}
+
+__global__ void nonfinite_kernel(int64_t cnt, const double* __restrict__ p, int* __restrict__ flag) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt && !isfinite(p[e])) *flag = 1;  // benign race: every writer stores 1
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+}  // namespace
+
+int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s) {
+  if (n3 == 0) return NBODY_OK;
+  kick_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, v, a, h);
+  NB_LAUNCH_CHECK("kick_kernel");
+  return NBODY_OK;
+}
+
+int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double h, double dt, int nkicks,
+                      hipStream_t s) {
+  if (n3 == 0) return NBODY_OK;
+  kick_drift_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, x, v, a, h, dt, nkicks);
+  NB_LAUNCH_CHECK("kick_drift_kernel");
+  return NBODY_OK;
+}
+
+int launch_copy(int64_t cnt, const double* src, double* dst, hipStream_t s) {
+  if (cnt == 0) return NBODY_OK;
+  copy_kernel<<<ew_blocks(cnt), kEw, 0, s>>>(cnt, src, dst);
+  NB_LAUNCH_CHECK("copy_kernel");
+  return NBODY_OK;
+}
+
+int launch_fill(int64_t cnt, double* dst, double val, hipStream_t s) {
+  if (cnt == 0) return NBODY_OK;
+  fill_kernel<<<ew_blocks(cnt), kEw, 0, s>>>(cnt, dst, val);
+  NB_LAUNCH_CHECK("fill_kernel");
+  return NBODY_OK;
+}
+
+int launch_energy(int64_t n, const double* x, const double* v, const double* m, double G, double eps,
+                  double* out9, hipStream_t s) {
+  int st = NBODY_OK;
+  const size_t part_bytes = sizeof(DD) * kQ * kRedBlocks;
+  char* ws = static_cast<char*>(workspace(current_device(), 1, part_bytes + sizeof(double) * (size_t)(n > 0 ? n : 1), &st));
+  if (!ws) return st;
+  DD* part = reinterpret_cast<DD*>(ws);
+  double* phi = reinterpret_cast<double*>(ws + part_bytes);
+  if (n > 0) {
+    const int64_t iblocks = (n + kBlock - 1) / kBlock;
+    const int64_t want = 4LL * cu_count(current_device());
+    int split = (int)std::min<int64_t>(64, std::max<int64_t>(1, (want + iblocks - 1) / iblocks));
+    st = launch_potential(n, x, m, eps, phi, split, s);
+    if (st) return st;
+  }
+  energy_partial_kernel<<<kRedBlocks, kRedBlock, 0, s>>>(n, x, v, m, phi, G, part);
+  NB_LAUNCH_CHECK("energy_partial_kernel");
+  energy_final_kernel<<<1, kRedBlock, 0, s>>>(kRedBlocks, part, out9);
+  NB_LAUNCH_CHECK("energy_final_kernel");
+  return NBODY_OK;
+}
+
+int check_finite(const double* p, int64_t cnt, hipStream_t s, bool* all_finite) {
+  int st = NBODY_OK;
+  int* flag = static_cast<int*>(workspace(current_device(), 3, sizeof(int), &st));
+  if (!flag) return st;
+  zero_int_kernel<<<1, 1, 0, s>>>(flag);
+  NB_LAUNCH_CHECK("zero_int_kernel");
+  if (cnt > 0) {
+    nonfinite_kernel<<<ew_blocks(cnt), kEw, 0, s>>>(cnt, p, flag);
+    NB_LAUNCH_CHECK("nonfinite_kernel");
+  }
+  int h = 0;
+  NB_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  NB_HIP(hipStreamSynchronize(s));
+  *all_finite = (h == 0);
+  return NBODY_OK;
+}
+
+int run_kdk(int64_t n, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
+            double G, double eps, int precision, bool excl, bool acc_valid, const PairConfig& cfg,
+            hipStream_t s, double* traj) {
+  const int64_t n3 = 3 * n;
+  const double h = 0.5 * dt;
+  int st;
+  if (!acc_valid) {
+    st = launch_accel(n, x, m, a, G, eps, precision, excl, cfg, s);
+    if (st) return st;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    st = launch_kick_drift(n3, x, v, a, h, dt, k == 0 ? 1 : 2, s);
+    if (st) return st;
+    st = launch_accel(n, x, m, a, G, eps, precision, excl, cfg, s);
+    if (st) return st;
+    if (traj) {
+      st = launch_copy(n3, x, traj + (size_t)(k + 1) * n3, s);
+      if (st) return st;
+    }
+  }
+  if (nsteps > 0) return launch_kick(n3, v, a, h, s);
+  return NBODY_OK;
+}
+
+// Reverse sweep over checkpointed segments; see nbody_traj_grad in nbody.h.
+int run_traj_grad(int64_t n, const double* ckx, const double* ckv, int64_t every, int64_t nsteps,
+                  const double* m, double dt, const double* gxT, const double* gvT, double* gx0, double* gv0,
+                  double* gm, double G, double eps, int precision, bool excl, const PairConfig& cfg,
+                  hipStream_t s) {
+  const int64_t n3 = 3 * n;
+  const int64_t seglen = std::min<int64_t>(every, std::max<int64_t>(nsteps, 1));
+  const size_t need = sizeof(double) * ((size_t)(seglen + 1) * n3 + 4 * (size_t)n3 + (size_t)n);
+  int st = NBODY_OK;
+  double* ws = static_cast<double*>(workspace(current_device(), 1, need, &st));
+  if (!ws) return st;
+  double* traj = ws;                                 // (seglen + 1) * 3n
+  double* xs = traj + (size_t)(seglen + 1) * n3;      // 3n
+  double* vs = xs + n3;                               // 3n
+  double* acc = vs + n3;                              // 3n
+  double* gxp = acc + n3;                             // 3n
+  double* gmp = gxp + n3;                             // n
+  // lambda_x and lambda_v live in the caller's outputs gx0 / gv0.
+  double* lx = gx0;
+  double* lv = gv0;
+  if ((st = launch_copy(n3, gxT, lx, s))) return st;
+  if ((st = launch_copy(n3, gvT, lv, s))) return st;
+  if ((st = launch_fill(n, gm, 0.0, s))) return st;
+  const double h = 0.5 * dt;
+  const int64_t nseg = (nsteps + every - 1) / every;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t k0 = seg * every;
+    const int64_t k1 = std::min<int64_t>(nsteps, k0 + every);
+    const int64_t L = k1 - k0;
+    if ((st = launch_copy(n3, ckx + (size_t)seg * n3, xs, s))) return st;
+    if ((st = launch_copy(n3, ckv + (size_t)seg * n3, vs, s))) return st;
+    if ((st = launch_copy(n3, xs, traj, s))) return st;
+    if ((st = run_kdk(n, xs, vs, acc, m, dt, L, G, eps, precision, excl, false, cfg, s, traj))) return st;
+    for (int64_t p = k1; p > k0; --p) {
+      // the kicks at x_p: one closing half-kick at the final position, two
+      // (closing + opening) at interior positions, merged into one VJP
+      const double c = (p == nsteps) ? h : dt;
+      const double* xp = traj + (size_t)(p - k0) * n3;
+      if ((st = launch_vjp(n, xp, m, lv, gxp, gmp, G * c, eps, precision, excl, cfg, s))) return st;
+      adjoint_update_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n, lx, lv, gm, gxp, gmp, dt, 1);
+      NB_LAUNCH_CHECK("adjoint_update_kernel");
+    }
+  }
+  // opening half-kick of step 0 at x_0
+  if (nsteps > 0) {
+    if ((st = launch_vjp(n, ckx, m, lv, gxp, gmp, G * h, eps, precision, excl, cfg, s))) return st;
+    adjoint_update_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n, lx, lv, gm, gxp, gmp, dt, 0);
+    NB_LAUNCH_CHECK("adjoint_update_kernel");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace nb

@@ -1,0 +1,106 @@
+// Device-side pair arithmetic shared by the all-pairs kernels (pairs.hip) and
+// the persistent ensemble kernel (ensemble.hip).
+#pragma once
+
+#include <type_traits>
+
+#include "common.h"
+
+namespace nb {
+
+enum Mode { kFP64 = NBODY_FP64, kFP32C = NBODY_FP32C, kFP32 = NBODY_FP32 };
+
+// Knuth's TwoSum: (hi, lo) += x with the rounding error of hi + x kept in lo.
+template <typename T>
+__device__ __forceinline__ void fold(T& hi, T& lo, T x) {
+  T s = hi + x;
+  T bp = s - hi;
+  T e = (hi - (s - bp)) + (x - bp);
+  hi = s;
+  lo += e;
+}
+
+// 1/sqrt(r2) in FP64: hardware estimate (about 5e-8 relative) refined by two
+// Newton-Raphson steps for r^(-1/2) in residual form, y += y/2 * (1 - r2 y^2),
+// which brings the error to the FP64 rounding level.
+__device__ __forceinline__ double rsqrt64(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  double h = fma(-r2 * y, y, 1.0);
+  y = fma(0.5 * y, h, y);
+  h = fma(-r2 * y, y, 1.0);
+  return fma(0.5 * y, h, y);
+}
+
+__device__ __forceinline__ float rsqrt32(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
+// Per-mode LDS record of one j-particle and its conversion from FP64.
+template <int MODE> struct JRec;
+
+template <> struct JRec<kFP64> {
+  double4 p;  // x, y, z, m
+  __device__ static JRec make(double x, double y, double z, double m) {
+    JRec r; r.p = make_double4(x, y, z, m); return r;
+  }
+};
+template <> struct JRec<kFP32C> {
+  float4 h;   // hi parts, mass
+  float4 l;   // lo parts
+  __device__ static JRec make(double x, double y, double z, double m) {
+    JRec r;
+    float hx = (float)x, hy = (float)y, hz = (float)z;
+    r.h = make_float4(hx, hy, hz, (float)m);
+    r.l = make_float4((float)(x - (double)hx), (float)(y - (double)hy), (float)(z - (double)hz), 0.f);
+    return r;
+  }
+};
+template <> struct JRec<kFP32> {
+  float4 h;
+  __device__ static JRec make(double x, double y, double z, double m) {
+    JRec r; r.h = make_float4((float)x, (float)y, (float)z, (float)m); return r;
+  }
+};
+
+// Per-mode i-particle state held in registers.
+template <int MODE> struct IPos;
+template <> struct IPos<kFP64> {
+  double x, y, z;
+  __device__ void set(double a, double b, double c) { x = a; y = b; z = c; }
+  __device__ void from(const JRec<kFP64>& r) { x = r.p.x; y = r.p.y; z = r.p.z; }
+};
+template <> struct IPos<kFP32C> {
+  float hx, hy, hz, lx, ly, lz;
+  __device__ void set(double a, double b, double c) {
+    hx = (float)a; hy = (float)b; hz = (float)c;
+    lx = (float)(a - (double)hx); ly = (float)(b - (double)hy); lz = (float)(c - (double)hz);
+  }
+  __device__ void from(const JRec<kFP32C>& r) {
+    hx = r.h.x; hy = r.h.y; hz = r.h.z; lx = r.l.x; ly = r.l.y; lz = r.l.z;
+  }
+};
+template <> struct IPos<kFP32> {
+  float hx, hy, hz;
+  __device__ void set(double a, double b, double c) { hx = (float)a; hy = (float)b; hz = (float)c; }
+  __device__ void from(const JRec<kFP32>& r) { hx = r.h.x; hy = r.h.y; hz = r.h.z; }
+};
+
+template <int MODE> using Real = typename std::conditional<MODE == kFP64, double, float>::type;
+
+// Displacement d = x_j - x_i per mode.
+__device__ __forceinline__ void disp(const JRec<kFP64>& r, const IPos<kFP64>& p, double& dx, double& dy, double& dz) {
+  dx = r.p.x - p.x; dy = r.p.y - p.y; dz = r.p.z - p.z;
+}
+__device__ __forceinline__ void disp(const JRec<kFP32C>& r, const IPos<kFP32C>& p, float& dx, float& dy, float& dz) {
+  dx = (r.h.x - p.hx) + (r.l.x - p.lx);
+  dy = (r.h.y - p.hy) + (r.l.y - p.ly);
+  dz = (r.h.z - p.hz) + (r.l.z - p.lz);
+}
+__device__ __forceinline__ void disp(const JRec<kFP32>& r, const IPos<kFP32>& p, float& dx, float& dy, float& dz) {
+  dx = r.h.x - p.hx; dy = r.h.y - p.hy; dz = r.h.z - p.hz;
+}
+__device__ __forceinline__ double jmass(const JRec<kFP64>& r) { return r.p.w; }
+__device__ __forceinline__ float jmass(const JRec<kFP32C>& r) { return r.h.w; }
+__device__ __forceinline__ float jmass(const JRec<kFP32>& r) { return r.h.w; }
+__device__ __forceinline__ double rsq(double r2) { return rsqrt64(r2); }
+__device__ __forceinline__ float rsq(float r2) { return rsqrt32(r2); }
+
+}  // namespace nb

@@ -1,0 +1,458 @@
+// All-pairs kernels of libnbody_accel: acceleration, its vector-Jacobian
+// product, and the pair potential used by the diagnostics.
+//
+// Shape of every kernel (the MI355X counterpart of the paper's read / compute /
+// write pipeline, Sec. 3.1 and Algorithms 1-2):
+//   * one i-particle per lane (IPL of them per lane, strided by the block size
+//     so loads and stores stay coalesced); a workgroup of 256 lanes owns
+//     256 * IPL consecutive i's and a contiguous j-range (the grid's y index
+//     splits the j-range when there are too few i-blocks to fill 256 CUs);
+//   * the j-range is streamed through LDS in tiles of 256 records, double
+//     buffered: while the tile in LDS is consumed, the next tile's FP64 values
+//     are already in flight from global memory to registers, and are converted
+//     and written to the other LDS buffer before the single barrier per tile;
+//   * every lane reads the same LDS record (a broadcast, no bank conflicts) and
+//     applies it to its IPL i-particles with the pair arithmetic of App. A,
+//     Algorithm 3: displacement, squared distance (+ eps^2), inverse square
+//     root, cube, weight times cube, accumulate;
+//   * partial sums of kFold terms are kept in plain arithmetic and folded into
+//     a (hi, lo) pair with Knuth's TwoSum, so the j-sum is compensated at a
+//     cost of a few operations per 64 pairs;
+//   * the tile loader converts the caller's FP64 SoA positions on the fly, so
+//     no staging pass or staging buffer exists: FP32C keeps each coordinate as
+//     hi = fl32(x), lo = fl32(x - hi) and forms x_j - x_i = (hi_j - hi_i) +
+//     (lo_j - lo_i), where the first difference is exact for nearby pairs
+//     (Sterbenz) -- the only place where FP32 positions lose accuracy.
+// Padding j-records (past the j-range) sit at kFarAway with zero mass, so they
+// contribute exactly zero without a bounds test in the inner loop.
+#include "pair_math.h"
+
+namespace nb {
+namespace {
+
+// Loads the record of j (or padding if j >= je) from the caller's FP64 arrays.
+template <int MODE>
+__device__ __forceinline__ JRec<MODE> load_rec(const double* __restrict__ x, const double* __restrict__ m,
+                                               int n, int j, int je) {
+  if (j < je) return JRec<MODE>::make(x[j], x[n + j], x[2 * n + j], m[j]);
+  return JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+}
+
+// ============================================================== acceleration
+// Grid: (ceil(n / (256*IPL)), split).  Block y handles j in [y*chunk, min(n, (y+1)*chunk)).
+// split == 1: writes G*(hi+lo) to a[c*n+i].  split > 1: writes hi+lo to
+// part[(y*3+c)*n+i] and a second kernel sums the slices in order.
+template <int MODE, int IPL, bool EXCL>
+__global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __restrict__ x,
+                                                       const double* __restrict__ m, double eps, double G,
+                                                       int chunk, double* __restrict__ out) {
+  using R = Real<MODE>;
+  __shared__ JRec<MODE> tile[2][kTile];
+  const int t = threadIdx.x;
+  const int ibase = blockIdx.x * (kBlock * IPL) + t;
+  const int js = blockIdx.y * chunk;
+  const int je = min(n, js + chunk);
+  const R e2 = (R)(eps * eps);
+
+  IPos<MODE> pi[IPL];
+  int iidx[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    int i = ibase + k * kBlock;
+    iidx[k] = i;
+    int ic = i < n ? i : n - 1;
+    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+  }
+  R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = R(0);
+
+  const int ntiles = (je - js + kTile - 1) / kTile;
+  if (ntiles > 0) tile[0][t] = load_rec<MODE>(x, m, n, js + t, je);
+  __syncthreads();
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int jt = js + tt * kTile;
+    const bool more = tt + 1 < ntiles;
+    // prefetch the next tile's FP64 values while this tile is consumed
+    double nx = 0, ny = 0, nz = 0, nm = 0;
+    const int jn = jt + kTile + t;
+    if (more && jn < je) { nx = x[jn]; ny = x[n + jn]; nz = x[2 * n + jn]; nm = m[jn]; }
+    const JRec<MODE>* cur = tile[tt & 1];
+#pragma unroll 1
+    for (int f = 0; f < kTile; f += kFold) {
+      R px[IPL], py[IPL], pz[IPL];
+#pragma unroll
+      for (int k = 0; k < IPL; ++k) px[k] = py[k] = pz[k] = R(0);
+#pragma unroll 16
+      for (int jj = f; jj < f + kFold; ++jj) {
+        const JRec<MODE> r = cur[jj];
+        const R mj = jmass(r);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          R dx, dy, dz;
+          disp(r, pi[k], dx, dy, dz);
+          R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          R ri = rsq(r2);
+          R s = (mj * ri) * (ri * ri);
+          if (EXCL) s = (jt + jj == iidx[k]) ? R(0) : s;
+          px[k] = fma(s, dx, px[k]);
+          py[k] = fma(s, dy, py[k]);
+          pz[k] = fma(s, dz, pz[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < IPL; ++k) {
+        fold(hx[k], lx[k], px[k]);
+        fold(hy[k], ly[k], py[k]);
+        fold(hz[k], lz[k], pz[k]);
+      }
+    }
+    if (more) {
+      tile[(tt + 1) & 1][t] = (jn < je) ? JRec<MODE>::make(nx, ny, nz, nm)
+                                        : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+    }
+    __syncthreads();
+  }
+
+  const bool direct = gridDim.y == 1;
+  double* o = direct ? out : out + (size_t)blockIdx.y * 3 * n;
+  const double scale = direct ? G : 1.0;
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    const int i = iidx[k];
+    if (i < n) {
+      o[i] = scale * ((double)hx[k] + (double)lx[k]);
+      o[n + i] = scale * ((double)hy[k] + (double)ly[k]);
+      o[2 * n + i] = scale * ((double)hz[k] + (double)lz[k]);
+    }
+  }
+}
+
+// Sums `split` slices of `cnt` partials in slice order (TwoSum across slices)
+// and scales by G; entries e < n0 go to out0[e], the rest to out1[e - n0].
+__global__ void sum_slices_kernel(int64_t cnt, int split, const double* __restrict__ part, double G,
+                                  int64_t n0, double* __restrict__ out0, double* __restrict__ out1) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  double s = 0.0, c = 0.0;
+  for (int y = 0; y < split; ++y) {
+    double v = part[(size_t)y * cnt + e];
+    double t = s + v;
+    double bp = t - s;
+    c += (s - (t - bp)) + (v - bp);
+    s = t;
+  }
+  if (e < n0) out0[e] = G * (s + c);
+  else out1[e - n0] = G * (s + c);
+}
+
+// ============================================================== VJP
+// j-record for the VJP: the acceleration record plus the cotangent w_j.
+template <int MODE> struct WRec {
+  JRec<MODE> r;
+  typename std::conditional<MODE == kFP64, double4, float4>::type w;
+};
+
+template <int MODE>
+__device__ __forceinline__ WRec<MODE> load_wrec(const double* __restrict__ x, const double* __restrict__ m,
+                                                const double* __restrict__ w, int n, int j, int je) {
+  using R = Real<MODE>;
+  WRec<MODE> o;
+  if (j < je) {
+    o.r = JRec<MODE>::make(x[j], x[n + j], x[2 * n + j], m[j]);
+    o.w.x = (R)w[j]; o.w.y = (R)w[n + j]; o.w.z = (R)w[2 * n + j]; o.w.w = R(0);
+  } else {
+    o.r = JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+    o.w.x = o.w.y = o.w.z = o.w.w = R(0);
+  }
+  return o;
+}
+
+// u = m_k w_j - m_j w_k without contraction, so that u is exactly zero for j == k.
+template <typename R>
+__device__ __forceinline__ R cross_weight(R mk, R wj, R mj, R wk) {
+#pragma clang fp contract(off)
+  R a = mk * wj;
+  R b = mj * wk;
+  return a - b;
+}
+
+// gx_k = G sum_j [ r^-3 u - 3 r^-5 (d.u) d ],  gm_k = -G sum_j r^-3 (d . w_j),
+// d = x_j - x_k, u = m_k w_j - m_j w_k, r^2 = |d|^2 + eps^2.
+// split == 1: writes G * sums to gx (3n) and gm (n).
+// split > 1: writes slice y's unscaled 4n partials (gx then gm) at part + y*4n.
+template <int MODE, int IPL, bool EXCL>
+__global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __restrict__ x,
+                                                     const double* __restrict__ m,
+                                                     const double* __restrict__ w, double eps, double G,
+                                                     int chunk, double* __restrict__ gx,
+                                                     double* __restrict__ gm, double* __restrict__ part) {
+  using R = Real<MODE>;
+  __shared__ WRec<MODE> tile[2][kTile];
+  const int t = threadIdx.x;
+  const int ibase = blockIdx.x * (kBlock * IPL) + t;
+  const int js = blockIdx.y * chunk;
+  const int je = min(n, js + chunk);
+  const R e2 = (R)(eps * eps);
+
+  IPos<MODE> pi[IPL];
+  R mk[IPL], wkx[IPL], wky[IPL], wkz[IPL];
+  int iidx[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    int i = ibase + k * kBlock;
+    iidx[k] = i;
+    int ic = i < n ? i : n - 1;
+    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+    mk[k] = (R)m[ic];
+    wkx[k] = (R)w[ic]; wky[k] = (R)w[n + ic]; wkz[k] = (R)w[2 * n + ic];
+  }
+  R hx[IPL], hy[IPL], hz[IPL], hm[IPL], lx[IPL], ly[IPL], lz[IPL], lm[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) hx[k] = hy[k] = hz[k] = hm[k] = lx[k] = ly[k] = lz[k] = lm[k] = R(0);
+
+  const int ntiles = (je - js + kTile - 1) / kTile;
+  if (ntiles > 0) tile[0][t] = load_wrec<MODE>(x, m, w, n, js + t, je);
+  __syncthreads();
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int jt = js + tt * kTile;
+    const bool more = tt + 1 < ntiles;
+    WRec<MODE> nxt;
+    if (more) nxt = load_wrec<MODE>(x, m, w, n, jt + kTile + t, je);
+    const WRec<MODE>* cur = tile[tt & 1];
+#pragma unroll 1
+    for (int f = 0; f < kTile; f += kFold) {
+      R px[IPL], py[IPL], pz[IPL], pm[IPL];
+#pragma unroll
+      for (int k = 0; k < IPL; ++k) px[k] = py[k] = pz[k] = pm[k] = R(0);
+#pragma unroll 8
+      for (int jj = f; jj < f + kFold; ++jj) {
+        const WRec<MODE> q = cur[jj];
+        const R mj = jmass(q.r);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          R dx, dy, dz;
+          disp(q.r, pi[k], dx, dy, dz);
+          R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          R ri = rsq(r2);
+          R ri2 = ri * ri;
+          R r3 = ri2 * ri;
+          R r5 = r3 * ri2;
+          if (EXCL) {
+            const bool self = (jt + jj == iidx[k]);
+            r3 = self ? R(0) : r3;
+            r5 = self ? R(0) : r5;
+          }
+          R ux = cross_weight(mk[k], q.w.x, mj, wkx[k]);
+          R uy = cross_weight(mk[k], q.w.y, mj, wky[k]);
+          R uz = cross_weight(mk[k], q.w.z, mj, wkz[k]);
+          R du = fma(dz, uz, fma(dy, uy, dx * ux));
+          R c = R(3) * r5 * du;
+          px[k] = fma(-c, dx, fma(r3, ux, px[k]));
+          py[k] = fma(-c, dy, fma(r3, uy, py[k]));
+          pz[k] = fma(-c, dz, fma(r3, uz, pz[k]));
+          R dw = fma(dz, q.w.z, fma(dy, q.w.y, dx * q.w.x));
+          pm[k] = fma(-r3, dw, pm[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < IPL; ++k) {
+        fold(hx[k], lx[k], px[k]);
+        fold(hy[k], ly[k], py[k]);
+        fold(hz[k], lz[k], pz[k]);
+        fold(hm[k], lm[k], pm[k]);
+      }
+    }
+    if (more) tile[(tt + 1) & 1][t] = nxt;
+    __syncthreads();
+  }
+
+  const bool direct = gridDim.y == 1;
+  double* o = direct ? gx : part + (size_t)blockIdx.y * 4 * n;
+  double* om = direct ? gm : o + 3 * (size_t)n;
+  const double scale = direct ? G : 1.0;
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    const int i = iidx[k];
+    if (i < n) {
+      o[i] = scale * ((double)hx[k] + (double)lx[k]);
+      o[n + i] = scale * ((double)hy[k] + (double)ly[k]);
+      o[2 * n + i] = scale * ((double)hz[k] + (double)lz[k]);
+      om[i] = scale * ((double)hm[k] + (double)lm[k]);
+    }
+  }
+}
+
+// ============================================================== potential
+// phi_i = sum_{j != i} m_j / sqrt(|d|^2 + eps^2) in FP64, self pair excluded by
+// index.  split == 1: writes phi at out; split > 1: slice y at out + y*n.
+__global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* __restrict__ x,
+                                                           const double* __restrict__ m, double eps,
+                                                           int chunk, double* __restrict__ out) {
+  __shared__ double4 tile[2][kTile];
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * kBlock + t;
+  const int ic = i < n ? i : n - 1;
+  const int js = blockIdx.y * chunk;
+  const int je = min(n, js + chunk);
+  const double e2 = eps * eps;
+  const double xi = x[ic], yi = x[n + ic], zi = x[2 * n + ic];
+  double hp = 0, lp = 0;
+  const int ntiles = (je - js + kTile - 1) / kTile;
+  auto ld = [&](int j) {
+    return j < je ? make_double4(x[j], x[n + j], x[2 * n + j], m[j])
+                  : make_double4(kFarAway, kFarAway, kFarAway, 0.0);
+  };
+  if (ntiles > 0) tile[0][t] = ld(js + t);
+  __syncthreads();
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int jt = js + tt * kTile;
+    const bool more = tt + 1 < ntiles;
+    double4 nxt = make_double4(0, 0, 0, 0);
+    if (more) nxt = ld(jt + kTile + t);
+    const double4* cur = tile[tt & 1];
+#pragma unroll 1
+    for (int f = 0; f < kTile; f += kFold) {
+      double p = 0;
+#pragma unroll 8
+      for (int jj = f; jj < f + kFold; ++jj) {
+        const double4 r = cur[jj];
+        double dx = r.x - xi, dy = r.y - yi, dz = r.z - zi;
+        double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+        double v = r.w * rsqrt64(r2);
+        p += (jt + jj == i) ? 0.0 : v;
+      }
+      fold(hp, lp, p);
+    }
+    if (more) tile[(tt + 1) & 1][t] = nxt;
+    __syncthreads();
+  }
+  if (i < n) out[(size_t)blockIdx.y * n + i] = hp + lp;
+}
+
+// ============================================================== launch helpers
+inline int split_chunk(int64_t n, int split) {
+  int64_t c = (n + split - 1) / split;
+  c = (c + kTile - 1) / kTile * kTile;
+  return (int)(c > 0 ? c : kTile);
+}
+inline int effective_split(int64_t n, int split) {
+  int chunk = split_chunk(n, split);
+  return (int)((n + chunk - 1) / chunk);
+}
+
+template <int MODE, int IPL>
+int accel_dispatch(int64_t n, const double* x, const double* m, double* a, double G, double eps,
+                   bool excl, int split, hipStream_t s) {
+  const int chunk = split_chunk(n, split);
+  const int sp = effective_split(n, split);
+  dim3 grid((unsigned)((n + kBlock * IPL - 1) / (kBlock * IPL)), (unsigned)sp);
+  double* out = a;
+  int st = NBODY_OK;
+  if (sp > 1) {
+    out = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 3 * (size_t)n * sp, &st));
+    if (!out) return st;
+  }
+  if (excl)
+    accel_kernel<MODE, IPL, true><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
+  else
+    accel_kernel<MODE, IPL, false><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
+  NB_LAUNCH_CHECK("accel_kernel");
+  if (sp > 1) {
+    const int64_t cnt = 3 * n;
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, out, G, cnt, a, nullptr);
+    NB_LAUNCH_CHECK("sum_slices_kernel");
+  }
+  return NBODY_OK;
+}
+
+template <int MODE, int IPL>
+int vjp_dispatch(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm,
+                 double G, double eps, bool excl, int split, hipStream_t s) {
+  const int chunk = split_chunk(n, split);
+  const int sp = effective_split(n, split);
+  dim3 grid((unsigned)((n + kBlock * IPL - 1) / (kBlock * IPL)), (unsigned)sp);
+  int st = NBODY_OK;
+  double* part = nullptr;
+  if (sp > 1) {
+    part = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 4 * (size_t)n * sp, &st));
+    if (!part) return st;
+  }
+  if (excl)
+    vjp_kernel<MODE, IPL, true><<<grid, kBlock, 0, s>>>((int)n, x, m, w, eps, G, chunk, gx, gm, part);
+  else
+    vjp_kernel<MODE, IPL, false><<<grid, kBlock, 0, s>>>((int)n, x, m, w, eps, G, chunk, gx, gm, part);
+  NB_LAUNCH_CHECK("vjp_kernel");
+  if (sp > 1) {
+    const int64_t cnt = 4 * n;
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, gx, gm);
+    NB_LAUNCH_CHECK("sum_slices_kernel");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace
+
+int launch_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps,
+                 int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  const int split = cfg.split < 1 ? 1 : cfg.split;
+#define NB_ACC(MODE, IPL) return accel_dispatch<MODE, IPL>(n, x, m, a, G, eps, excl, split, s)
+  switch (precision) {
+    case kFP64:
+      if (cfg.ipl == 1) NB_ACC(kFP64, 1);
+      if (cfg.ipl == 2) NB_ACC(kFP64, 2);
+      NB_ACC(kFP64, 4);
+    case kFP32C:
+      if (cfg.ipl == 1) NB_ACC(kFP32C, 1);
+      if (cfg.ipl == 2) NB_ACC(kFP32C, 2);
+      NB_ACC(kFP32C, 4);
+    case kFP32:
+      if (cfg.ipl == 1) NB_ACC(kFP32, 1);
+      if (cfg.ipl == 2) NB_ACC(kFP32, 2);
+      NB_ACC(kFP32, 4);
+  }
+#undef NB_ACC
+  return set_error(NBODY_EINVAL, "unknown precision");
+}
+
+int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm,
+               double G, double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  const int split = cfg.split < 1 ? 1 : cfg.split;
+  // The VJP keeps twice the accumulators of the force, so it runs at most 2 i per lane.
+  const bool one = cfg.ipl <= 1;
+#define NB_VJP(MODE) return one ? vjp_dispatch<MODE, 1>(n, x, m, w, gx, gm, G, eps, excl, split, s) \
+                               : vjp_dispatch<MODE, 2>(n, x, m, w, gx, gm, G, eps, excl, split, s)
+  switch (precision) {
+    case kFP64: NB_VJP(kFP64);
+    case kFP32C: NB_VJP(kFP32C);
+    case kFP32: NB_VJP(kFP32);
+  }
+#undef NB_VJP
+  return set_error(NBODY_EINVAL, "unknown precision");
+}
+
+// Potential phi_i (FP64) into phi[n]; used by the energy diagnostics.
+int launch_potential(int64_t n, const double* x, const double* m, double eps, double* phi, int split,
+                     hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  const int chunk = split_chunk(n, split);
+  const int sp = effective_split(n, split);
+  dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)sp);
+  int st = NBODY_OK;
+  double* part = phi;
+  if (sp > 1) {
+    part = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * (size_t)n * sp, &st));
+    if (!part) return st;
+  }
+  potential_kernel<<<grid, kBlock, 0, s>>>((int)n, x, m, eps, chunk, part);
+  NB_LAUNCH_CHECK("potential_kernel");
+  if (sp > 1) {
+    sum_slices_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, sp, part, 1.0, n, phi, nullptr);
+    NB_LAUNCH_CHECK("sum_slices_kernel");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace nb

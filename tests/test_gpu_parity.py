@@ -1,0 +1,314 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Error statistic for accelerations: per particle e_i = |a_i - a_i^ref| / |a_i^ref|,
+gated on the maximum over particles.  Tolerances: 1e-12 for the FP64 path and
+1e-5 for FP32C (FP32 pair arithmetic on float-float positions with compensated
+sums); FP32 (rounded positions) is held to 1e-4 on these well-separated inputs.
+"""
+import numpy as np
+import pytest
+
+import ics
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_02744_amd as nbm
+    nbm.load()
+    return nbm
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def rel_err(a, ref):
+    num = np.linalg.norm(a - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    return (num / np.where(den > 0, den, 1.0)).max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 255, 256, 257, 511, 1000, 1025, 3001])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_accel_ragged_sizes(nb, oracle_mod, n, prec):
+    x, _, m = ics.plummer(n, seed=100 + n)
+    eps = 0.01
+    ref = oracle_mod.accel(x, m, G=1.0, eps=eps)
+    a = nb.nbody_accel(dev(x), dev(m), eps=eps, precision=prec).cpu().numpy()
+    if n == 1:
+        assert np.all(a == 0.0)
+        return
+    print("accel n=%d %s max rel err %.3e" % (n, prec, rel_err(a, ref)))
+    assert rel_err(a, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("ipl,split", [(1, 1), (2, 1), (4, 1), (1, 3), (2, 7), (4, 16), (2, 0), (1, 64)])
+def test_accel_tile_configs(nb, oracle_mod, prec, ipl, split):
+    n = 4099
+    x, _, m = ics.two_component(n, seed=7)
+    G, eps = 1.3, 0.02
+    ref = oracle_mod.accel(x, m, G=G, eps=eps)
+    nb.nbody_set_config(ipl=ipl, split=split)
+    try:
+        a1 = nb.nbody_accel(dev(x), dev(m), G=G, eps=eps, precision=prec)
+        a2 = nb.nbody_accel(dev(x), dev(m), G=G, eps=eps, precision=prec)
+    finally:
+        nb.nbody_set_config()
+    assert torch.equal(a1, a2), "not deterministic"
+    assert rel_err(a1.cpu().numpy(), ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_accel_exclude_self_eps_zero(nb, oracle_mod, prec):
+    x, _, m = ics.random_cloud(700, seed=3)
+    ref = oracle_mod.accel(x, m, eps=0.0)
+    a = nb.nbody_accel(dev(x), dev(m), eps=0.0, precision=prec, exclude_self=True).cpu().numpy()
+    assert np.isfinite(a).all()
+    assert rel_err(a, ref) <= 10 * TOL[prec]
+
+
+def test_accel_plummer1k_fp64(nb, oracle_mod):
+    w = ics.WORKLOADS["plummer1k_fp64"]
+    x, _, m = ics.plummer(w["n"], seed=w["seed"])
+    ref = oracle_mod.accel(x, m, eps=w["eps"])
+    a = nb.nbody_accel(dev(x), dev(m), eps=w["eps"], precision="fp64").cpu().numpy()
+    assert rel_err(a, ref) <= 1e-12
+
+
+def test_kdk_plummer1k_fp64_trajectory(nb, oracle_mod):
+    """Ten KDK steps of the 1024-body Plummer sphere, FP64 path vs oracle."""
+    w = ics.WORKLOADS["plummer1k_fp64"]
+    x, v, m = ics.plummer(w["n"], seed=w["seed"])
+    rx, rv = oracle_mod.kdk(x, v, m, w["dt"], w["steps"], eps=w["eps"])
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    nb.nbody_step(tx, tv, ta, tm, w["dt"], w["steps"], eps=w["eps"], precision="fp64")
+    assert np.abs(tx.cpu().numpy() - rx).max() <= 1e-10
+    assert np.abs(tv.cpu().numpy() - rv).max() <= 1e-10
+    ra = oracle_mod.accel(rx, m, eps=w["eps"])
+    assert rel_err(ta.cpu().numpy(), ra) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_step_resumable_bitwise(nb, prec):
+    x, v, m = ics.plummer(2000, seed=4)
+    out = []
+    for chunks in ((10,), (4, 6), (1, 1, 8)):
+        tx, tv, tm = dev(x), dev(v), dev(m)
+        ta = torch.empty_like(tx)
+        valid = False
+        for c in chunks:
+            nb.nbody_step(tx, tv, ta, tm, 1.0 / 128, c, eps=0.01, precision=prec, acc_valid=valid)
+            valid = True
+        out.append((tx.cpu(), tv.cpu(), ta.cpu()))
+    for o in out[1:]:
+        for p, q in zip(out[0], o):
+            assert torch.equal(p, q)
+
+
+def test_step_zero_steps_computes_acc(nb, oracle_mod):
+    x, v, m = ics.plummer(300, seed=5)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.zeros_like(tx)
+    nb.nbody_step(tx, tv, ta, tm, 0.01, 0, eps=0.01, precision="fp64")
+    assert torch.equal(tx.cpu(), torch.tensor(x)) and torch.equal(tv.cpu(), torch.tensor(v))
+    assert rel_err(ta.cpu().numpy(), oracle_mod.accel(x, m, eps=0.01)) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 77, 1024, 5000])
+def test_energy_matches_oracle(nb, oracle_mod, n):
+    x, v, m = ics.plummer(n, seed=6 + n)
+    ref = oracle_mod.energy(x, v, m, G=1.2, eps=0.01)
+    e = nb.nbody_energy(dev(x), dev(v), dev(m), G=1.2, eps=0.01).cpu().numpy()
+    for k in range(3):
+        assert abs(e[k] - ref[k]) <= 1e-12 * max(abs(ref[k]), 1e-300), (k, e[k], ref[k])
+    scale_p = (m * np.abs(v).sum(axis=0)).sum()
+    scale_l = (m * np.linalg.norm(x, axis=0) * np.linalg.norm(v, axis=0)).sum()
+    assert np.abs(e[3:6] - ref[3:6]).max() <= 1e-14 * scale_p + 1e-300
+    assert np.abs(e[6:9] - ref[6:9]).max() <= 1e-14 * scale_l + 1e-300
+
+
+def test_energy_eps_zero_excludes_self(nb, oracle_mod):
+    x, v, m = ics.random_cloud(257, seed=9)
+    ref = oracle_mod.energy(x, v, m, eps=0.0)
+    e = nb.nbody_energy(dev(x), dev(v), dev(m), eps=0.0).cpu().numpy()
+    assert np.isfinite(e).all()
+    assert abs(e[1] - ref[1]) <= 1e-12 * abs(ref[1])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32c", 2e-5), ("fp32", 2e-4)])
+@pytest.mark.parametrize("n", [2, 65, 1000, 2049])
+def test_vjp_matches_oracle(nb, oracle_mod, prec, tol, n):
+    x, _, m = ics.two_component(n, seed=11)
+    w = np.random.default_rng(n).standard_normal((3, n))
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, G=0.7, eps=0.02)
+    gx, gm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), G=0.7, eps=0.02, precision=prec)
+    gx, gm = gx.cpu().numpy(), gm.cpu().numpy()
+    assert np.linalg.norm(gx - rgx) <= tol * np.linalg.norm(rgx)
+    assert np.linalg.norm(gm - rgm) <= tol * np.linalg.norm(rgm)
+
+
+def test_vjp_split_configs_agree(nb, oracle_mod):
+    n = 3000
+    x, _, m = ics.plummer(n, seed=12)
+    w = np.random.default_rng(1).standard_normal((3, n))
+    rgx, _ = oracle_mod.accel_vjp(x, m, w, eps=0.01)
+    for ipl, split in ((1, 1), (2, 5), (1, 11)):
+        nb.nbody_set_config(ipl=ipl, split=split)
+        try:
+            gx, _ = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp64")
+        finally:
+            nb.nbody_set_config()
+        assert np.linalg.norm(gx.cpu().numpy() - rgx) <= 1e-11 * np.linalg.norm(rgx)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32c", 1e-4)])
+def test_traj_grad_matches_oracle(nb, oracle_mod, prec, tol):
+    n, steps, every, dt, eps = 512, 23, 5, 1.0 / 256, 0.01
+    x, v, m = ics.plummer(n, seed=13)
+    tgt, _ = ics.perturb(x, v, 1e-3, seed=14)
+    loss, (rgx, rgv, rgm) = oracle_mod.loss_grad(x, v, m, tgt, dt, steps, eps=eps)
+    tx, tv, tm = dev(x).requires_grad_(), dev(v).requires_grad_(), dev(m).requires_grad_()
+    xT, _ = nb.NBodyTrajectory.apply(tx, tv, tm, dt, steps, every, 1.0, eps, prec)
+    L = ((xT - dev(tgt)) ** 2).sum() / n
+    L.backward()
+    assert abs(L.item() - loss) <= (1e-12 if prec == "fp64" else 1e-5) * loss
+    for g, r in ((tx.grad, rgx), (tv.grad, rgv), (tm.grad, rgm)):
+        g = g.cpu().numpy()
+        assert np.linalg.norm(g - r) <= tol * np.linalg.norm(r), (prec, np.linalg.norm(g - r) / np.linalg.norm(r))
+
+
+def test_traj_grad_recompute_matches_forward(nb):
+    """The forward with checkpoints and one uninterrupted nbody_step agree bitwise."""
+    n, steps = 700, 13
+    x, v, m = ics.plummer(n, seed=15)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    xT, vT = nb.trajectory(tx, tv, tm, 1.0 / 128, steps, 4, 1.0, 0.01, "fp32c")
+    ax, av = dev(x), dev(v)
+    aa = torch.empty_like(ax)
+    nb.nbody_step(ax, av, aa, tm, 1.0 / 128, steps, eps=0.01, precision="fp32c")
+    assert torch.equal(xT, ax) and torch.equal(vT, av)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-9), ("fp32", 1e-7)])
+def test_batched_matches_single_system(nb, prec, tol):
+    sizes = [1, 64, 100, 300, 513, 1024, 1500, 2500, 4096, 65]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=16, sizes=sizes)
+    dt, steps = 1.0 / 512, 7
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, dt, steps, precision=prec)
+    bx, bv = tx.cpu().numpy(), tv.cpu().numpy()
+    for c in range(len(sizes)):
+        s, e = off[c], off[c + 1]
+        cx, cv, cm = dev(x[:, s:e]), dev(v[:, s:e]), dev(m[s:e])
+        ca = torch.empty_like(cx)
+        nb.nbody_step(cx, cv, ca, cm, dt, steps, eps=float(epsv[c]), precision=prec)
+        dx = np.abs(bx[:, s:e] - cx.cpu().numpy()).max()
+        dv = np.abs(bv[:, s:e] - cv.cpu().numpy()).max()
+        assert dx <= tol and dv <= tol * 100, (c, sizes[c], dx, dv)
+
+
+def test_batched_matches_oracle_fp64(nb, oracle_mod):
+    sizes = [5, 80, 700]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=17, sizes=sizes)
+    dt, steps = 1.0 / 512, 5
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, dt, steps, precision="fp64")
+    for c in range(len(sizes)):
+        s, e = off[c], off[c + 1]
+        rx, rv = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], dt, steps, eps=float(epsv[c]))
+        assert np.abs(tx.cpu().numpy()[:, s:e] - rx).max() <= 1e-12
+        assert np.abs(tv.cpu().numpy()[:, s:e] - rv).max() <= 1e-12
+
+
+def test_batched_repeat_and_graph_capture(nb):
+    sizes = [64, 257, 1000]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=18, sizes=sizes)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    # eager reference: 3 calls of 2 steps
+    ex, ev, ea = tx.clone(), tv.clone(), ta.clone()
+    nb.nbody_step_batched(off, epsv, ex, ev, ea, tm, 1.0 / 512, 2, precision="fp32c")
+    ref = []
+    for _ in range(3):
+        nb.nbody_step_batched(off, epsv, ex, ev, ea, tm, 1.0 / 512, 2, precision="fp32c", acc_valid=True)
+        ref.append((ex.clone(), ev.clone()))
+    # graph: the first call (plan build, a(x)) runs eagerly, then replays
+    gx, gv, ga = tx.clone(), tv.clone(), ta.clone()
+    nb.nbody_step_batched(off, epsv, gx, gv, ga, tm, 1.0 / 512, 2, precision="fp32c")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        nb.nbody_step_batched(off, epsv, gx, gv, ga, tm, 1.0 / 512, 2, precision="fp32c", acc_valid=True)
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (gx.sum() + 1.0).item()  # eager work between replays
+        assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
+
+
+def test_abi_rejects_bad_pointers(nb):
+    from paper_2605_02744_amd._binding import nbody_params
+    import ctypes
+    L = nb.load()
+    p = nbody_params(1.0, 0.01, nb.NBODY_FP32C, 0)
+    x = torch.zeros((3, 100), dtype=torch.float64, device="cuda:0")
+    m = torch.ones(100, dtype=torch.float64, device="cuda:0")
+    a = torch.empty_like(x)
+    host = np.zeros(300)
+    # host pointer where device memory is required
+    st = L.nbody_accel(100, ctypes.c_void_p(host.ctypes.data), ctypes.c_void_p(m.data_ptr()),
+                       ctypes.c_void_p(a.data_ptr()), ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL
+    # misaligned pointer
+    st = L.nbody_accel(100, ctypes.c_void_p(x.data_ptr() + 4), ctypes.c_void_p(m.data_ptr()),
+                       ctypes.c_void_p(a.data_ptr()), ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL and b"aligned" in L.nbody_last_error()
+    # null output
+    st = L.nbody_accel(100, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(m.data_ptr()), None,
+                       ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL
+    # aliasing output
+    st = L.nbody_accel(100, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                       ctypes.c_void_p(x.data_ptr()), ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL
+    # the binding refuses wrong dtype and CPU tensors before the C call
+    with pytest.raises(TypeError):
+        nb.nbody_accel(x.float(), m, eps=0.01)
+    with pytest.raises(ValueError):
+        nb.nbody_accel(x.cpu(), m, eps=0.01)
+
+
+def test_check_finite_flag(nb):
+    x, _, m = ics.plummer(200, seed=19)
+    x[0, 5] = np.nan
+    with pytest.raises(nb.NBodyError) as ei:
+        nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp64", check_finite=True)
+    assert ei.value.status == nb.NBODY_ENONFINITE
+    x[0, 5] = 0.1
+    a = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp64", check_finite=True)
+    assert torch.isfinite(a).all()
+
+
+def test_tune_records_a_choice(nb, tmp_path, oracle_mod):
+    n = 5000
+    path = str(tmp_path / "tune.jsonl")
+    best = nb.nbody_tune(n, "fp32c", path)
+    assert best["ipl"] in (1, 2, 4) and best["split"] >= 1
+    import json
+    rec = json.loads(open(path).read().splitlines()[-1])
+    assert rec["n"] == n and rec["arch"].startswith("gfx950") and rec["trials"]
+    x, _, m = ics.plummer(n, seed=20)
+    a = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp32c").cpu().numpy()
+    assert rel_err(a, oracle_mod.accel(x, m, eps=0.01)) <= 1e-5
