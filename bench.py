@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct-summation hot path on one MI355X.
+
+Default workload (twocomp1m_force): one softened force evaluation of a
+two-component Plummer model with N = 2^20 particles (90 % of the mass in an
+a = 0.5 core, 10 % in an a = 3 halo, log-uniform masses in [0.1, 10]),
+eps = 0.001.  A step is one FP32C force evaluation through the C ABI
+(nbody_accel), inputs resident in HBM.  Reported beside it in the same run:
+the plain FP64 GPU path and the forward + adjoint (force + VJP) rate, errors
+against the FP64 path (all rows) and the CPU oracle (sampled rows), the
+roofline of the force kernel and the oracle's own throughput on the host.
+
+Throughput is in ordered pair interactions, N (N - 1) per evaluation; the
+fraction of peak uses 20 flops per interaction against the 157.3 TFLOP/s FP32
+vector peak of the MI355X.
+
+Other workloads (--workload): plummer64k_fp32c (100 KDK steps, N = 65536),
+ensemble512 (512 clusters, 1000 steps in one persistent launch),
+grad16k (forward + adjoint of 200 steps, N = 16384), plummer1k_fp64.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G pair-interactions/s + % FP32 peak, fwd and fwd+adjoint, vs FP64 GPU path"
+UNIT = "G pair-interactions/s"
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (packed) peak
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
+FLOPS_PER_PAIR = 20          # acceleration-only softened interaction convention
+VJP_FLOPS_PER_PAIR = 45      # convention for the VJP pair
+KERNEL_SOURCES = ("paper_2605_02744_amd/csrc/pairs.hip", "paper_2605_02744_amd/csrc/pair_math.h")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def timed(fn, steps, warmup, torch):
+    """Runs fn warmup times, then times exactly `steps` calls with HIP events on
+    the current stream, bracketed by device synchronisation. Returns (ms/step,
+    list of per-call ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record()
+    for k in range(steps):
+        fn()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+    return sum(per) / steps, per, wall
+
+
+def rel_err_rows(a, ref):
+    num = np.linalg.norm(a - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    return num / np.where(den > 0, den, 1.0)
+
+
+def cpu_baseline_rows(oracle, x, m, eps, budget_s, rng_seed=0):
+    """Oracle acceleration rows on a bounded sample of the workload: calibrate on
+    a few rows, then time a sample sized to ~budget_s seconds."""
+    n = m.shape[0]
+    rng = np.random.default_rng(rng_seed)
+    cal = rng.choice(n, size=min(n, 32), replace=False)
+    t0 = time.perf_counter()
+    oracle.accel_rows(x, m, cal, eps=eps)
+    dt_cal = max(time.perf_counter() - t0, 1e-6)
+    rows_n = int(min(n, max(64, len(cal) * budget_s / dt_cal)))
+    rows = np.sort(rng.choice(n, size=rows_n, replace=False))
+    t0 = time.perf_counter()
+    ref_rows = oracle.accel_rows(x, m, rows, eps=eps)
+    el = time.perf_counter() - t0
+    return rows, ref_rows, el
+
+
+def bench_force(args, torch, nb):
+    import ics
+    w = ics.WORKLOADS["twocomp1m_force"]
+    n, eps = args.n or w["n"], w["eps"]
+    x, _, m = ics.two_component(n, seed=w["seed"])
+    dev = torch.device("cuda:0")
+    tx = torch.tensor(x, device=dev)
+    tm = torch.tensor(m, device=dev)
+    a32 = torch.empty_like(tx)
+    a64 = torch.empty_like(tx)
+    pairs = float(n) * (n - 1)
+
+    if args.tune:
+        nb.nbody_tune(n, "fp32c")
+        nb.nbody_tune(n, "fp64")
+
+    f32 = lambda: nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
+    ms, per, wall = timed(f32, args.steps, args.warmup, torch)
+    value = pairs / (ms * 1e-3) / 1e9
+    c20_tflops = pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12
+
+    res = {"metric": METRIC, "value": round(value, 3), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "twocomp1m_force", "n": n, "eps": eps, "precision": args.precision,
+                      "interactions_per_step": pairs, "state": "f64",
+                      "flop_convention": "20 flops per ordered interaction"},
+           "pct_fp32_peak": round(100 * c20_tflops / FP32_PEAK_TFLOPS, 2),
+           "wall_ms_timed_region": round(wall, 2)}
+
+    if not args.quick:
+        # plain FP64 GPU path
+        f64 = lambda: nb.nbody_accel(tx, tm, eps=eps, precision="fp64", out=a64)
+        ms64, _, _ = timed(f64, max(1, args.steps // 2), 1, torch)
+        # forward + adjoint: force then VJP with a fixed cotangent
+        wv = torch.tensor(np.random.default_rng(1).standard_normal((3, n)), device=dev)
+
+        def fa():
+            nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
+            nb.nbody_accel_vjp(tx, tm, wv, eps=eps, precision=args.precision)
+        msfa, _, _ = timed(fa, max(1, args.steps // 2), 1, torch)
+        res["fp64_path"] = {"value": round(pairs / (ms64 * 1e-3) / 1e9, 3), "unit": UNIT,
+                            "ms_per_eval": round(ms64, 4),
+                            "pct_fp64_peak": round(100 * pairs * FLOPS_PER_PAIR / (ms64 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 2),
+                            "fp32c_speedup": round(ms64 / ms, 3)}
+        res["fwd_adjoint"] = {"value": round(2 * pairs / (msfa * 1e-3) / 1e9, 3), "unit": UNIT,
+                              "ms_per_fwd_plus_vjp": round(msfa, 4),
+                              "vjp_ms": round(msfa - ms, 4),
+                              "note": "force + VJP pair evaluations per second (2 N(N-1) per pass)"}
+        # accuracy of this run's result
+        nb.nbody_accel(tx, tm, eps=eps, precision="fp64", out=a64)
+        nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
+        A32, A64 = a32.cpu().numpy(), a64.cpu().numpy()
+        e_all = rel_err_rows(A32, A64)
+        res["accuracy"] = {"fp32c_vs_fp64gpu_max_rel": float(e_all.max()),
+                           "fp32c_vs_fp64gpu_p99": float(np.quantile(e_all, 0.99)),
+                           "fp32c_vs_fp64gpu_median": float(np.median(e_all)),
+                           "fp32c_vs_fp64gpu_rows_over_1e-5": int((e_all > 1e-5).sum())}
+
+    # roofline of the force kernel: C20 flops / measured duration per launch
+    res["roofline"] = {"bound": "alu", "achieved": round(c20_tflops, 3), "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(c20_tflops / FP32_PEAK_TFLOPS, 4),
+                       "traffic": load_traffic("twocomp1m_force"),
+                       "kernel": "accel_kernel<FP32C>", "flops_per_launch": pairs * FLOPS_PER_PAIR}
+
+    if not args.no_cpu:
+        import oracle
+        rows, ref_rows, el = cpu_baseline_rows(oracle, x, m, eps, args.cpu_budget)
+        rate = len(rows) * (n - 1) / el / 1e9
+        res["cpu_baseline"] = {"value": round(rate, 4), "unit": UNIT, "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": "%d sampled rows x %d j (%.1f s), FP64 Neumaier C oracle" % (len(rows), n - 1, el)}
+        if "accuracy" in res:
+            e32 = rel_err_rows(A32[:, rows], ref_rows)
+            e64 = rel_err_rows(A64[:, rows], ref_rows)
+            res["accuracy"]["fp32c_vs_oracle_sampled_max_rel"] = float(e32.max())
+            res["accuracy"]["fp64gpu_vs_oracle_sampled_max_rel"] = float(e64.max())
+            res["accuracy"]["sampled_rows"] = int(len(rows))
+    return res
+
+
+def bench_kdk64k(args, torch, nb):
+    import ics
+    w = ics.WORKLOADS["plummer64k_fp32c"]
+    n, eps, dt = w["n"], w["eps"], w["dt"]
+    x, v, m = ics.plummer(n, seed=w["seed"])
+    dev = torch.device("cuda:0")
+    tm = torch.tensor(m, device=dev)
+    out = {}
+    for prec in (args.precision, "fp64"):
+        tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+        ta = torch.empty_like(tx)
+        e0 = nb.nbody_energy(tx, tv, tm, eps=eps).cpu().numpy()
+        nb.nbody_step(tx, tv, ta, tm, dt, 0, eps=eps, precision=prec)
+        ms, _, wall = timed(lambda: nb.nbody_step(tx, tv, ta, tm, dt, 1, eps=eps, precision=prec, acc_valid=True),
+                            args.steps, 0, torch)
+        e1 = nb.nbody_energy(tx, tv, tm, eps=eps).cpu().numpy()
+        out[prec] = dict(ms=ms, dE=abs((e1[2] - e0[2]) / e0[2]), x=tx.cpu().numpy())
+    pairs = float(n) * (n - 1)
+    ms = out[args.precision]["ms"]
+    return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
+            "steps": args.steps, "warmup": 0, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "plummer64k_fp32c", "n": n, "eps": eps, "dt": dt, "precision": args.precision},
+            "pct_fp32_peak": round(100 * pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
+            "energy_drift": {p: out[p]["dE"] for p in out},
+            "fp64_path": {"value": round(pairs / (out["fp64"]["ms"] * 1e-3) / 1e9, 3),
+                          "ms_per_step": round(out["fp64"]["ms"], 4)},
+            "final_position_maxdiff_vs_fp64": float(np.abs(out[args.precision]["x"] - out["fp64"]["x"]).max())}
+
+
+def bench_ensemble(args, torch, nb):
+    import ics
+    w = ics.WORKLOADS["ensemble512"]
+    off, epsv, x, v, m = ics.ensemble(w["ncl"], seed=w["seed"], nmin=w["nmin"], nmax=w["nmax"])
+    dev = torch.device("cuda:0")
+    tm = torch.tensor(m, device=dev)
+    sizes = np.diff(off)
+    pairs = float((sizes * (sizes - 1)).sum())
+    res = {}
+    for prec in (args.precision, "fp64"):
+        tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+        ta = torch.empty_like(tx)
+        nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=prec)  # plan + a(x)
+        steps = args.steps
+        ms, _, _ = timed(lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], steps, precision=prec,
+                                                       acc_valid=True), 1, 0, torch)
+        res[prec] = ms
+    ms = res[args.precision]
+    return {"metric": METRIC, "value": round(pairs * args.steps / (ms * 1e-3) / 1e9, 3), "unit": UNIT,
+            "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": round(ms / args.steps, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
+                       "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
+                       "launches": 1},
+            "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
+            "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),
+                          "ms_per_step": round(res["fp64"] / args.steps, 5)}}
+
+
+def bench_grad(args, torch, nb):
+    import ics
+    w = ics.WORKLOADS["grad16k"]
+    n, eps, dt, steps, every = w["n"], w["eps"], w["dt"], w["steps"], w["every"]
+    x, v, m = ics.plummer(n, seed=w["seed"])
+    xp, vp = ics.perturb(x, v, w["sigma"], seed=w["target_seed"])
+    dev = torch.device("cuda:0")
+    out = {}
+    for prec in (args.precision, "fp64"):
+        tgt_x = torch.tensor(xp, device=dev)
+        tgt_v = torch.tensor(vp, device=dev)
+        tm = torch.tensor(m, device=dev)
+        tg = torch.empty_like(tgt_x)
+        nb.nbody_step(tgt_x, tgt_v, tg, tm, dt, steps, eps=eps, precision="fp64")
+        tx = torch.tensor(x, device=dev, requires_grad=True)
+        tv = torch.tensor(v, device=dev, requires_grad=True)
+        tmg = torch.tensor(m, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xT, _ = nb.NBodyTrajectory.apply(tx, tv, tmg, dt, steps, every, 1.0, eps, prec)
+        loss = ((xT - tgt_x) ** 2).sum() / n
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[prec] = dict(fwd=t1 - t0, bwd=t2 - t1, loss=loss.item())
+    pairs = float(n) * (n - 1)
+    p = out[args.precision]
+    # forward: steps + 1 evaluations; backward: recompute (steps + nseg) + steps + 1 VJPs
+    nseg = -(-steps // every)
+    work = pairs * ((steps + 1) + (steps + nseg) + (steps + 1))
+    return {"metric": METRIC, "value": round(work / (p["fwd"] + p["bwd"]) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
+            "steps": steps, "warmup": 0, "ms_per_step": round(1e3 * (p["fwd"] + p["bwd"]) / steps, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "grad16k", "n": n, "eps": eps, "dt": dt, "every": every, "precision": args.precision},
+            "fwd_s": p["fwd"], "bwd_s": p["bwd"], "bwd_over_fwd": p["bwd"] / p["fwd"], "loss": p["loss"],
+            "fp64_path": {"fwd_s": out["fp64"]["fwd"], "bwd_s": out["fp64"]["bwd"], "loss": out["fp64"]["loss"]}}
+
+
+def bench_copy(args, torch, nb):
+    """A plain device copy of known size, used to calibrate the HBM byte
+    counters (FETCH_SIZE / WRITE_SIZE) that price the force kernel's traffic."""
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    ms, _, _ = timed(lambda: dst.copy_(src), args.steps, args.warmup, torch)
+    return {"metric": "copy bandwidth", "value": round(2 * nbytes / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "copy256m", "bytes_read": nbytes, "bytes_written": nbytes}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="twocomp1m_force",
+                    choices=["twocomp1m_force", "plummer64k_fp32c", "ensemble512", "grad16k", "copy256m"])
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
+    ap.add_argument("--n", type=int, default=None, help="override N of the force workload")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--quick", action="store_true", help="force workload: skip FP64, adjoint and accuracy legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work in the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps is None:
+        args.steps = {"twocomp1m_force": 10, "plummer64k_fp32c": 100, "ensemble512": 1000, "grad16k": 200,
+                      "copy256m": 20}[args.workload]
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_2605_02744_amd as nb
+    nb.load()
+    fn = {"twocomp1m_force": bench_force, "plummer64k_fp32c": bench_kdk64k, "ensemble512": bench_ensemble,
+          "grad16k": bench_grad, "copy256m": bench_copy}[args.workload]
+    res = fn(args, torch, nb)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
