@@ -149,9 +149,13 @@ int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64
  * int64, off[0] == 0, non-decreasing) and eps (ncl) are HOST arrays; the
  * work plan built from them is cached, so a repeated call with the same
  * layout enqueues only the launch (and may be captured into a HIP graph).
- * Systems larger than the persistent kernel's LDS capacity return
- * NBODY_EUNSUPPORTED.  p->eps is ignored; p->precision must be NBODY_FP32C,
- * NBODY_FP32 or NBODY_FP64. */
+ * Systems of more than 4096 particles return NBODY_EUNSUPPORTED.  The
+ * largest systems may be split over up to 4 workgroups that exchange their
+ * positions through global memory every step (see nbody_config.bsplit); if
+ * such an exchange ever waits more than about a second (the GPU shared with
+ * other work), that system's x, v and a are set to NaN rather than hanging,
+ * which NBODY_CHECK_FINITE reports.  p->eps is ignored; p->precision must be
+ * NBODY_FP32C, NBODY_FP32 or NBODY_FP64. */
 int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, double* x,
                        double* v, double* a, const double* m, double dt, int64_t nsteps,
                        const nbody_params* p, void* stream);
@@ -160,13 +164,16 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
   int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
-  int32_t bcl;     /* batched kernel: threads per workgroup (256, 512 or 1024), 0 = auto */
+  int32_t bsplit;  /* batched kernel: 0 = split systems costlier than the per-CU average
+                      across up to 4 workgroups (they exchange positions every step),
+                      1 = one workgroup per system */
   int32_t reserved;
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros
- * restores the automatic choice).  Errors: NBODY_EINVAL for values outside
- * the lists above. */
+ * restores the automatic choice).  A batched plan is built with the bsplit
+ * value in force when its layout is first seen.  Errors: NBODY_EINVAL for
+ * values outside the lists above. */
 int nbody_set_config(const nbody_config* cfg);
 
 /* Autotuner: for a system of n particles and the given precision, time every

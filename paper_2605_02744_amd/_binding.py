@@ -47,7 +47,7 @@ class nbody_params(ctypes.Structure):
 
 class nbody_config(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("bcl", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bsplit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -217,9 +217,10 @@ def nbody_step_batched(off, eps, x, v, a, m, dt, nsteps, *, G=1.0, precision="fp
     return x, v, a
 
 
-def nbody_set_config(ipl=0, split=0, bcl=0):
-    """Forces a tile configuration on this thread (all zeros = automatic)."""
-    c = nbody_config(int(ipl), int(split), int(bcl), 0)
+def nbody_set_config(ipl=0, split=0, bsplit=0):
+    """Forces a tile configuration on this thread (all zeros = automatic);
+    bsplit=1 keeps every ensemble system on a single workgroup."""
+    c = nbody_config(int(ipl), int(split), int(bsplit), 0)
     _check(load().nbody_set_config(ctypes.byref(c)))
 
 

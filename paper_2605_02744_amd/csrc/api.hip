@@ -346,8 +346,7 @@ int nbody_set_config(const nbody_config* cfg) {
   if (cfg->ipl != 0 && cfg->ipl != 1 && cfg->ipl != 2 && cfg->ipl != 4)
     return set_error(NBODY_EINVAL, "ipl must be 0, 1, 2 or 4");
   if (cfg->split < 0 || cfg->split > 1024) return set_error(NBODY_EINVAL, "split must be in 0..1024");
-  if (cfg->bcl != 0 && cfg->bcl != 256 && cfg->bcl != 512 && cfg->bcl != 1024)
-    return set_error(NBODY_EINVAL, "bcl must be 0, 256, 512 or 1024");
+  if (cfg->bsplit != 0 && cfg->bsplit != 1) return set_error(NBODY_EINVAL, "bsplit must be 0 or 1");
   set_thread_config(*cfg);
   return NBODY_OK;
 }

@@ -1,22 +1,26 @@
 // Persistent ensemble integrator: many independent softened systems of uneven
 // size advanced for all KDK steps inside ONE kernel launch.
 //
-// Each 512-lane workgroup (8 waves, one workgroup per CU) owns whole systems
-// from a host-built longest-processing-time plan and integrates each of them
-// for every step before taking the next, so no communication between
-// workgroups is ever needed.  Per step and system:
-//   1. kick-drift of the FP64 state (closing half-kick of the previous step and
-//      opening half-kick of this one, rounded separately as in nbody_step), and
-//      the new positions written straight into LDS as pair records;
-//   2. barrier; every lane evaluates its i-particles against the system's
-//      records in LDS with the same pair arithmetic and compensated folds as
-//      the single-system kernel;
-//   3. small systems, which cannot fill 512 lanes with i-particles, split
-//      their j-range over lane groups, and the partial (hi, lo) sums of the
-//      groups are combined through LDS in group order;
-// then a final closing half-kick.  The mapping of a system onto the lanes
-// (i-particles per lane `ipl`, j-groups `js`) is chosen per system on the
-// host to minimise its per-lane pair count.
+// Work is a list of items per workgroup (one workgroup per CU; 1024 lanes for
+// the FP32 pair modes, 512 for FP64).  An item is a whole system, or one of P
+// equal i-ranges of a system too costly for one CU (the plan splits the
+// largest systems so that no CU carries much more than the average load).
+// For every item and step:
+//   1. kick-drift of the owned FP64 state (closing half-kick of the previous
+//      step and opening half-kick of this one, rounded separately as in
+//      nbody_step); the new positions go straight into LDS as pair records;
+//   2. a split item also publishes its records in a global exchange buffer,
+//      signals its step with an agent-scope release, waits (bounded) for the
+//      other parts' signals and copies their records into LDS;
+//   3. every lane evaluates its i-particles against all records of the system
+//      in LDS with the same pair arithmetic and compensated folds as the
+//      single-system kernel; small systems, which cannot fill the lanes,
+//      split their j-range over lane groups and combine the groups' (hi, lo)
+//      sums through LDS in group order;
+// then a final closing half-kick.  Deadlock freedom: every workgroup holds at
+// most one split item and processes it first, all workgroups are resident
+// (grid <= CUs, one workgroup per CU), and every wait is bounded; on a timeout
+// the item's state is set to NaN and the workgroup moves on.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -28,38 +32,42 @@
 namespace nb {
 namespace {
 
-constexpr int kEnsBlock = 512;
-constexpr int kMaxIpl = 8;   // i-particles per lane
-constexpr int kPass = 4;     // i-particles evaluated together in one pass over j
+template <int MODE> constexpr int ens_block() { return MODE == kFP64 ? 512 : 1024; }
+template <int MODE> constexpr int ens_max_ipl() { return MODE == kFP64 ? 8 : 4; }
+constexpr int kMaxSys = 4096;            // particles per system
+constexpr int kPass = 4;                 // i-particles evaluated together in one pass over j
 constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kSpinLimit = 1 << 21;      // polls of a partner flag before giving up (~1 s)
 
 template <int MODE> struct Part { Real<MODE> hx, lx, hy, ly, hz, lz; };
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
-// Per-system lane mapping, packed as ipl | js << 8.
+// Lane mapping of an item: ni i-particles of a system of nc particles.
 struct Map { int ipl, js; };
 
+__host__ __device__ inline int map_gsz(int ni, int ipl) { return ((ni + ipl - 1) / ipl + 63) / 64 * 64; }
+
 template <int MODE>
-size_t lds_bytes(int nc, Map mp) {
-  const int gsz = ((nc + mp.ipl - 1) / mp.ipl + 63) / 64 * 64;
+size_t lds_bytes(int nc, int ni, Map mp) {
   size_t b = align16((size_t)nc * sizeof(JRec<MODE>));
-  if (mp.js > 1) b += (size_t)(mp.js - 1) * mp.ipl * gsz * sizeof(Part<MODE>);
+  if (mp.js > 1) b += (size_t)(mp.js - 1) * mp.ipl * map_gsz(ni, mp.ipl) * sizeof(Part<MODE>);
   return b;
 }
 
+// Chooses (ipl, js) minimising the per-lane pair count; returns the cost in
+// pair-iterations per lane per step (plus a fixed per-step overhead).
 template <int MODE>
-bool choose_map(int nc, Map* out, double* cost) {
+bool choose_map(int nc, int ni, Map* out, double* cost) {
+  constexpr int block = ens_block<MODE>();
   bool found = false;
   double best = 0;
-  for (int ipl = 1; ipl <= kMaxIpl; ++ipl) {
-    const int gsz = ((nc + ipl - 1) / ipl + 63) / 64 * 64;
-    if (gsz > kEnsBlock) continue;
-    for (int js = 1; js * gsz <= kEnsBlock && js <= 16 && (js == 1 || ipl <= kPass); js *= 2) {
+  for (int ipl = 1; ipl <= ens_max_ipl<MODE>(); ++ipl) {
+    const int gsz = map_gsz(ni, ipl);
+    if (gsz > block) continue;
+    for (int js = 1; js * gsz <= block && js <= 16 && (js == 1 || ipl <= kPass); js *= 2) {
       Map mp{ipl, js};
-      if (lds_bytes<MODE>(nc, mp) > kLdsLimit) continue;
-      // per-lane pair iterations plus a per-step overhead for the kick,
-      // staging and barriers, in the same units
+      if (lds_bytes<MODE>(nc, ni, mp) > kLdsLimit) continue;
       const double c = (double)ipl * ((nc + js - 1) / js) + 48.0 + (js > 1 ? 16.0 * js : 0.0);
       if (!found || c < best) { best = c; *out = mp; found = true; }
     }
@@ -68,16 +76,21 @@ bool choose_map(int nc, Map* out, double* cost) {
   return found;
 }
 
-// Per-system view of the lane mapping, shared by the phases of one step.
+// Device description of one work item.
+struct Item {
+  int sys;      // system index
+  int part;     // part index within the system
+  int nparts;   // 1 = whole system
+  int map;      // ipl | js << 8
+};
+
 struct SysView {
-  int nc, ipl, js, gsz, g, l, j0, j1;
+  int nc, ni, i0, ipl, js, gsz, g, l, j0, j1;
   int64_t T;
 };
 
-// Accelerations of one system from the records in LDS, for the lane's
-// i-particles k = kb .. kb+IPL-1 (i = l + k*gsz).  Lanes of group 0 write a_i;
-// other groups (only when js > 1, which implies kb == 0) hand their partial
-// sums to group 0 through LDS.
+// Accelerations of the item's i-particles (i0 + l + k*gsz, k = kb .. kb+IPL-1)
+// from all records of the system in LDS.
 template <int MODE, int IPL>
 __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __restrict__ rec,
                              Part<MODE>* __restrict__ part, Real<MODE> e2, double G, int excl,
@@ -88,9 +101,10 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
   R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
-    const int i = sv.l + (kb + k) * sv.gsz;
-    ii[k] = i;
-    pi[k].from(rec[i < sv.nc ? i : sv.nc - 1]);
+    const int il = sv.l + (kb + k) * sv.gsz;
+    const int i = sv.i0 + (il < sv.ni ? il : sv.ni - 1);
+    ii[k] = il < sv.ni ? i : -1;
+    pi[k].from(rec[i]);
     hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = R(0);
   }
   for (int f = sv.j0; f < sv.j1; f += kFold) {
@@ -145,7 +159,7 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       const int i = ii[k];
-      if (i < sv.nc) {
+      if (i >= 0) {
         A[i] = G * ((double)hx[k] + (double)lx[k]);
         A[sv.T + i] = G * ((double)hy[k] + (double)ly[k]);
         A[2 * sv.T + i] = G * ((double)hz[k] + (double)lz[k]);
@@ -165,68 +179,117 @@ __device__ __forceinline__ void system_force_pass(const SysView& sv, int kb, int
   }
 }
 
-// All of a lane's i-particles, in passes of at most kPass.
 template <int MODE>
-__device__ __forceinline__ void system_force_dispatch(const SysView& sv, const JRec<MODE>* rec, Part<MODE>* part,
-                                                      Real<MODE> e2, double G, int excl, double* A) {
+__device__ __forceinline__ void system_force_all(const SysView& sv, const JRec<MODE>* rec, Part<MODE>* part,
+                                                 Real<MODE> e2, double G, int excl, double* A) {
   for (int kb = 0; kb < sv.ipl; kb += kPass) system_force_pass<MODE>(sv, kb, min(kPass, sv.ipl - kb), rec, part, e2, G, excl, A);
 }
 
-// One launch integrates every system of the plan for nsteps KDK steps.
-// Particle i of a system is read and written in global memory only by the
-// lane that owns it (group 0, lane i % gsz), so the lanes of a workgroup
-// exchange positions only through the LDS records.
+// Publishes this part's records (already in LDS), signals round r, waits for
+// the other parts' round r and copies their records into LDS.  Returns false
+// (for the whole workgroup) if a partner did not arrive in time.
 template <int MODE>
-__global__ __launch_bounds__(kEnsBlock) void ensemble_kernel(
-    const int64_t* __restrict__ off, const double* __restrict__ epsv, const int* __restrict__ maps,
-    const int* __restrict__ wg_off, const int* __restrict__ wg_list, double* __restrict__ x,
-    double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m, int64_t total, double dt,
-    int64_t nsteps, double G, int acc_valid, int excl) {
+__device__ bool exchange(const SysView& sv, const Item& it, int64_t o, JRec<MODE>* rec,
+                         JRec<MODE>* __restrict__ xrec, int* __restrict__ flags, int flag_base, int r,
+                         int* lds_ok) {
+  const int t = threadIdx.x;
+  JRec<MODE>* xb = xrec + (size_t)(r & 1) * sv.T + o;
+  for (int i = sv.i0 + t; i < sv.i0 + sv.ni; i += blockDim.x) xb[i] = rec[i];
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    __hip_atomic_store(flags + flag_base + it.part, r + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    for (int p = 0; p < it.nparts && ok; ++p) {
+      if (p == it.part) continue;
+      int polls = 0;
+      while (__hip_atomic_load(flags + flag_base + p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < r + 1) {
+        if (++polls > kSpinLimit) { ok = 0; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    *lds_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = *lds_ok != 0;
+  if (ok) {
+    __threadfence();
+    for (int j = t; j < sv.nc; j += blockDim.x)
+      if (j < sv.i0 || j >= sv.i0 + sv.ni) rec[j] = xb[j];
+  }
+  __syncthreads();
+  return ok;
+}
+
+// One launch integrates every item of the plan for nsteps KDK steps.  The FP64
+// state of particle i is read and written in global memory only by the lane
+// that owns it (group 0, lane (i - i0) % gsz of the item holding i).
+template <int MODE>
+__global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
+    const int64_t* __restrict__ off, const double* __restrict__ epsv, const Item* __restrict__ items,
+    const int* __restrict__ flag_base, const int* __restrict__ wg_off, const int* __restrict__ wg_list,
+    double* __restrict__ x, double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m,
+    JRec<MODE>* __restrict__ xrec, int* __restrict__ flags, int64_t total, double dt, int64_t nsteps, double G,
+    int acc_valid, int excl) {
   using R = Real<MODE>;
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int lds_ok;
   JRec<MODE>* rec = reinterpret_cast<JRec<MODE>*>(smem);
   const int t = threadIdx.x;
   const double h = 0.5 * dt;
 
   for (int q = wg_off[blockIdx.x]; q < wg_off[blockIdx.x + 1]; ++q) {
-    const int c = wg_list[q];
-    const int64_t o = off[c];
+    const Item it = items[wg_list[q]];
+    const int64_t o = off[it.sys];
     SysView sv;
-    sv.nc = (int)(off[c + 1] - o);
+    sv.nc = (int)(off[it.sys + 1] - o);
     if (sv.nc <= 0) continue;
+    const int np = (sv.nc + it.nparts - 1) / it.nparts;
+    sv.i0 = min(sv.nc, it.part * np);
+    sv.ni = min(sv.nc, sv.i0 + np) - sv.i0;
+    if (sv.ni <= 0) continue;
     sv.T = total;
-    sv.ipl = maps[c] & 0xff;
-    sv.js = maps[c] >> 8;
-    sv.gsz = ((sv.nc + sv.ipl - 1) / sv.ipl + 63) / 64 * 64;
+    sv.ipl = it.map & 0xff;
+    sv.js = it.map >> 8;
+    sv.gsz = map_gsz(sv.ni, sv.ipl);
     sv.g = t / sv.gsz;
     sv.l = t - sv.g * sv.gsz;
     const int jc = (sv.nc + sv.js - 1) / sv.js;
     sv.j0 = sv.g < sv.js ? min(sv.nc, sv.g * jc) : sv.nc;
     sv.j1 = sv.g < sv.js ? min(sv.nc, sv.j0 + jc) : sv.nc;
-    const R e2 = (R)(epsv[c] * epsv[c]);
+    const R e2 = (R)(epsv[it.sys] * epsv[it.sys]);
     Part<MODE>* part = reinterpret_cast<Part<MODE>*>(smem + align16((size_t)sv.nc * sizeof(JRec<MODE>)));
     double* X = x + o;
     double* V = v + o;
     double* A = a + o;
     const double* M = m + o;
     const bool owner = sv.g == 0;
+    const bool split = it.nparts > 1;
+    const int fb = split ? flag_base[it.sys] : 0;
+    int round = 0;
+    bool ok = true;
 
     if (!acc_valid) {
       if (owner)
         for (int k = 0; k < sv.ipl; ++k) {
-          const int i = sv.l + k * sv.gsz;
-          if (i < sv.nc) rec[i] = JRec<MODE>::make(X[i], X[total + i], X[2 * total + i], M[i]);
+          const int il = sv.l + k * sv.gsz;
+          if (il < sv.ni) {
+            const int i = sv.i0 + il;
+            rec[i] = JRec<MODE>::make(X[i], X[total + i], X[2 * total + i], M[i]);
+          }
         }
       __syncthreads();
-      system_force_dispatch<MODE>(sv, rec, part, e2, G, excl, A);
+      if (split) ok = exchange<MODE>(sv, it, o, rec, xrec, flags, fb, round++, &lds_ok);
+      if (ok) system_force_all<MODE>(sv, rec, part, e2, G, excl, A);
       __syncthreads();
     }
-    for (int64_t s = 0; s < nsteps; ++s) {
+    for (int64_t s = 0; s < nsteps && ok; ++s) {
       const int nk = s == 0 ? 1 : 2;
       if (owner)
         for (int k = 0; k < sv.ipl; ++k) {
-          const int i = sv.l + k * sv.gsz;
-          if (i < sv.nc) {
+          const int il = sv.l + k * sv.gsz;
+          if (il < sv.ni) {
+            const int i = sv.i0 + il;
             double xn[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -242,101 +305,168 @@ __global__ __launch_bounds__(kEnsBlock) void ensemble_kernel(
           }
         }
       __syncthreads();
-      system_force_dispatch<MODE>(sv, rec, part, e2, G, excl, A);
+      if (split) ok = exchange<MODE>(sv, it, o, rec, xrec, flags, fb, round++, &lds_ok);
+      if (ok) system_force_all<MODE>(sv, rec, part, e2, G, excl, A);
       __syncthreads();
     }
-    if (nsteps > 0 && owner)
+    if (owner)
       for (int k = 0; k < sv.ipl; ++k) {
-        const int i = sv.l + k * sv.gsz;
-        if (i < sv.nc)
+        const int il = sv.l + k * sv.gsz;
+        if (il < sv.ni) {
+          const int i = sv.i0 + il;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) V[d * total + i] = fma(h, A[d * total + i], V[d * total + i]);
+          for (int d = 0; d < 3; ++d) {
+            const int64_t e = d * total + i;
+            if (!ok) {
+              X[e] = NAN;
+              V[e] = NAN;
+              A[e] = NAN;
+            } else if (nsteps > 0) {
+              V[e] = fma(h, A[e], V[e]);
+            }
+          }
+        }
       }
+    __syncthreads();
   }
+}
+
+__global__ void zero_flags_kernel(int* flags, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) flags[i] = 0;
 }
 
 // ------------------------------------------------------------------ plans
 struct Plan {
   std::vector<int64_t> off;
   std::vector<double> eps;
+  bool allow_split = true;
   int precision = 0;
   int device = 0;
   int nwg = 0;
+  int nflags = 0;
   size_t lds = 0;
+  int64_t total = 0;
   int64_t* d_off = nullptr;
   double* d_eps = nullptr;
-  int* d_maps = nullptr;
+  Item* d_items = nullptr;
+  int* d_flag_base = nullptr;
   int* d_wg_off = nullptr;
   int* d_wg_list = nullptr;
+  void* d_xrec = nullptr;
+  int* d_flags = nullptr;
 };
 
 std::mutex g_plan_mu;
 std::vector<Plan*> g_plans;
 
 void free_plan(Plan* p) {
-  if (p->d_off) (void)hipFree(p->d_off);
-  if (p->d_eps) (void)hipFree(p->d_eps);
-  if (p->d_maps) (void)hipFree(p->d_maps);
-  if (p->d_wg_off) (void)hipFree(p->d_wg_off);
-  if (p->d_wg_list) (void)hipFree(p->d_wg_list);
+  for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_items, (void*)p->d_flag_base, (void*)p->d_wg_off,
+                  (void*)p->d_wg_list, p->d_xrec, (void*)p->d_flags})
+    if (q) (void)hipFree(q);
   delete p;
 }
 
+template <typename T>
+bool upload(T** dst, const std::vector<T>& src) {
+  const size_t bytes = sizeof(T) * std::max<size_t>(1, src.size());
+  if (hipMalloc(dst, bytes) != hipSuccess) return false;
+  return src.empty() || hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// Builds the work plan: systems whose cost exceeds 3/4 of the per-CU average
+// are split into P <= 4 parts (at most one split item per workgroup, placed
+// first in its list); everything else is assigned longest-processing-time first.
 template <int MODE>
-int build_plan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, Plan** out) {
+int build_plan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, bool allow_split,
+               Plan** out) {
   Plan* p = new Plan();
   p->off.assign(off, off + ncl + 1);
   p->eps.assign(eps, eps + ncl);
   p->precision = precision;
   p->device = device;
-  std::vector<int> maps(ncl);
-  std::vector<double> cost(ncl);
+  p->allow_split = allow_split;
+  p->total = off[ncl];
+  std::vector<double> cost(ncl, 0.0);
+  std::vector<Map> whole(ncl);
   size_t lds = 16;
+  double sum = 0;
   for (int c = 0; c < ncl; ++c) {
     const int64_t nc = off[c + 1] - off[c];
-    if (nc == 0) { maps[c] = 1 | (1 << 8); cost[c] = 0; continue; }
-    Map mp;
-    if (nc > kEnsBlock * kMaxIpl || !choose_map<MODE>((int)nc, &mp, &cost[c])) {
+    if (nc == 0) { whole[c] = Map{1, 1}; continue; }
+    if (nc > kMaxSys || !choose_map<MODE>((int)nc, (int)nc, &whole[c], &cost[c])) {
       delete p;
       return set_error(NBODY_EUNSUPPORTED, "batched: system " + std::to_string(c) + " of " + std::to_string(nc) +
-                                               " particles exceeds the persistent kernel's LDS capacity");
+                                               " particles exceeds the persistent kernel's capacity (" +
+                                               std::to_string(kMaxSys) + ")");
     }
-    maps[c] = mp.ipl | (mp.js << 8);
-    lds = std::max(lds, lds_bytes<MODE>((int)nc, mp));
+    sum += cost[c];
+    lds = std::max(lds, lds_bytes<MODE>((int)nc, (int)nc, whole[c]));
   }
-  // longest-processing-time assignment of systems to workgroups (one per CU)
   const int nwg = std::max(1, std::min<int>(ncl, cu_count(device)));
+  const double avg = sum / nwg;
   std::vector<int> order(ncl);
   for (int c = 0; c < ncl; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(), [&](int u, int w) { return cost[u] > cost[w]; });
+
+  std::vector<Item> items;
+  std::vector<double> icost;
+  std::vector<int> flag_base(ncl, 0);
+  int nflags = 0;
+  std::vector<int> unsplit;
+  for (int c : order) {
+    const int nc = (int)(off[c + 1] - off[c]);
+    int P = 1;
+    if (allow_split && nwg > 1 && nc >= 512 && cost[c] > 0.75 * avg)
+      P = std::min(4, (int)std::ceil(cost[c] / (0.75 * avg)));
+    if (P > 1 && nflags + P > nwg) P = 1;
+    Map mp{1, 1};
+    double pc = 0;
+    if (P > 1 && !choose_map<MODE>(nc, (nc + P - 1) / P, &mp, &pc)) P = 1;
+    if (P == 1) { unsplit.push_back(c); continue; }
+    flag_base[c] = nflags;
+    nflags += P;
+    for (int q = 0; q < P; ++q) {
+      items.push_back(Item{c, q, P, mp.ipl | (mp.js << 8)});
+      icost.push_back(pc + 32.0);  // the exchange adds a little per step
+    }
+    lds = std::max(lds, lds_bytes<MODE>(nc, (nc + P - 1) / P, mp));
+  }
+  const int nsplit = (int)items.size();
+  for (int c : unsplit) {
+    items.push_back(Item{c, 0, 1, whole[c].ipl | (whole[c].js << 8)});
+    icost.push_back(cost[c]);
+  }
+  // split items first, one per workgroup; then LPT over the rest
+  std::vector<std::vector<int>> lists(nwg);
+  std::vector<double> load(nwg, 0.0);
+  for (int k = 0; k < nsplit; ++k) {
+    lists[k].push_back(k);
+    load[k] = icost[k];
+  }
   using Slot = std::pair<double, int>;
   std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
-  for (int w = 0; w < nwg; ++w) heap.push({0.0, w});
-  std::vector<std::vector<int>> lists(nwg);
-  for (int c : order) {
+  for (int w = 0; w < nwg; ++w) heap.push({load[w], w});
+  for (int k = nsplit; k < (int)items.size(); ++k) {
     Slot s = heap.top();
     heap.pop();
-    lists[s.second].push_back(c);
-    heap.push({s.first + cost[c], s.second});
+    lists[s.second].push_back(k);
+    heap.push({s.first + icost[k], s.second});
   }
   std::vector<int> wg_off(nwg + 1, 0), wg_list;
-  wg_list.reserve(ncl);
   for (int w = 0; w < nwg; ++w) {
     wg_list.insert(wg_list.end(), lists[w].begin(), lists[w].end());
     wg_off[w + 1] = (int)wg_list.size();
   }
   p->nwg = nwg;
   p->lds = lds;
-  bool ok = hipMalloc(&p->d_off, sizeof(int64_t) * (ncl + 1)) == hipSuccess &&
-            hipMalloc(&p->d_eps, sizeof(double) * ncl) == hipSuccess &&
-            hipMalloc(&p->d_maps, sizeof(int) * ncl) == hipSuccess &&
-            hipMalloc(&p->d_wg_off, sizeof(int) * (nwg + 1)) == hipSuccess &&
-            hipMalloc(&p->d_wg_list, sizeof(int) * std::max(1, ncl)) == hipSuccess;
-  ok = ok && hipMemcpy(p->d_off, off, sizeof(int64_t) * (ncl + 1), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_eps, eps, sizeof(double) * ncl, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_maps, maps.data(), sizeof(int) * ncl, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_wg_off, wg_off.data(), sizeof(int) * (nwg + 1), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_wg_list, wg_list.data(), sizeof(int) * ncl, hipMemcpyHostToDevice) == hipSuccess;
+  p->nflags = nflags;
+  std::vector<double> epsv(eps, eps + ncl);
+  bool ok = upload(&p->d_off, p->off) && upload(&p->d_eps, epsv) && upload(&p->d_items, items) &&
+            upload(&p->d_flag_base, flag_base) && upload(&p->d_wg_off, wg_off) && upload(&p->d_wg_list, wg_list);
+  if (ok && nflags > 0) {
+    ok = hipMalloc(&p->d_xrec, 2 * (size_t)p->total * sizeof(JRec<MODE>)) == hipSuccess &&
+         hipMalloc(&p->d_flags, sizeof(int) * nflags) == hipSuccess;
+  }
   if (!ok) {
     (void)hipGetLastError();
     free_plan(p);
@@ -346,22 +476,28 @@ int build_plan(int32_t ncl, const int64_t* off, const double* eps, int precision
   return NBODY_OK;
 }
 
-Plan* find_plan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
+Plan* find_plan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, bool allow_split) {
   for (Plan* p : g_plans) {
-    if (p->device != device || p->precision != precision || (int)p->eps.size() != ncl) continue;
+    if (p->device != device || p->precision != precision || (int)p->eps.size() != ncl ||
+        p->allow_split != allow_split)
+      continue;
     if (std::equal(p->off.begin(), p->off.end(), off) && std::equal(p->eps.begin(), p->eps.end(), eps)) return p;
   }
   return nullptr;
 }
 
 template <int MODE>
-int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m, int64_t total, double dt,
-                int64_t nsteps, double G, bool acc_valid, bool excl, hipStream_t s) {
+int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
+                double G, bool acc_valid, bool excl, hipStream_t s) {
   NB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel<MODE>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds));
-  ensemble_kernel<MODE><<<p->nwg, kEnsBlock, p->lds, s>>>(p->d_off, p->d_eps, p->d_maps, p->d_wg_off,
-                                                          p->d_wg_list, x, v, a, m, total, dt, nsteps, G,
-                                                          acc_valid ? 1 : 0, excl ? 1 : 0);
+  if (p->nflags > 0) {
+    zero_flags_kernel<<<1, 256, 0, s>>>(p->d_flags, p->nflags);
+    NB_LAUNCH_CHECK("zero_flags_kernel");
+  }
+  ensemble_kernel<MODE><<<p->nwg, ens_block<MODE>(), p->lds, s>>>(
+      p->d_off, p->d_eps, p->d_items, p->d_flag_base, p->d_wg_off, p->d_wg_list, x, v, a, m,
+      static_cast<JRec<MODE>*>(p->d_xrec), p->d_flags, p->total, dt, nsteps, G, acc_valid ? 1 : 0, excl ? 1 : 0);
   NB_LAUNCH_CHECK("ensemble_kernel");
   return NBODY_OK;
 }
@@ -372,25 +508,23 @@ int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, d
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
                 hipStream_t s) {
   const int device = current_device();
+  const bool allow_split = thread_config().bsplit == 0;
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  Plan* p = find_plan(ncl, off, eps, precision, device);
+  Plan* p = find_plan(ncl, off, eps, precision, device, allow_split);
   if (!p) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
       return set_error(NBODY_EINVAL, "batched: the plan for this layout must be built by one call outside stream capture");
     int st;
-    if (precision == NBODY_FP64) st = build_plan<NBODY_FP64>(ncl, off, eps, precision, device, &p);
-    else if (precision == NBODY_FP32C) st = build_plan<NBODY_FP32C>(ncl, off, eps, precision, device, &p);
-    else st = build_plan<NBODY_FP32>(ncl, off, eps, precision, device, &p);
+    if (precision == NBODY_FP64) st = build_plan<NBODY_FP64>(ncl, off, eps, precision, device, allow_split, &p);
+    else if (precision == NBODY_FP32C) st = build_plan<NBODY_FP32C>(ncl, off, eps, precision, device, allow_split, &p);
+    else st = build_plan<NBODY_FP32>(ncl, off, eps, precision, device, allow_split, &p);
     if (st) return st;
     g_plans.push_back(p);
   }
-  const int64_t total = off[ncl];
-  if (precision == NBODY_FP64)
-    return launch_plan<NBODY_FP64>(p, x, v, a, m, total, dt, nsteps, G, acc_valid, excl, s);
-  if (precision == NBODY_FP32C)
-    return launch_plan<NBODY_FP32C>(p, x, v, a, m, total, dt, nsteps, G, acc_valid, excl, s);
-  return launch_plan<NBODY_FP32>(p, x, v, a, m, total, dt, nsteps, G, acc_valid, excl, s);
+  if (precision == NBODY_FP64) return launch_plan<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  if (precision == NBODY_FP32C) return launch_plan<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  return launch_plan<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
 }
 
 void release_batched_plans() {

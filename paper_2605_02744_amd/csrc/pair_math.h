@@ -94,6 +94,10 @@ __device__ __forceinline__ void disp(const JRec<kFP32C>& r, const IPos<kFP32C>& 
   dy = (r.h.y - p.hy) + (r.l.y - p.ly);
   dz = (r.h.z - p.hz) + (r.l.z - p.lz);
 }
+// Displacement from the hi parts only (positions rounded to FP32).
+__device__ __forceinline__ void disp_hi(const JRec<kFP32C>& r, const IPos<kFP32C>& p, float& dx, float& dy, float& dz) {
+  dx = r.h.x - p.hx; dy = r.h.y - p.hy; dz = r.h.z - p.hz;
+}
 __device__ __forceinline__ void disp(const JRec<kFP32>& r, const IPos<kFP32>& p, float& dx, float& dy, float& dz) {
   dx = r.h.x - p.hx; dy = r.h.y - p.hy; dz = r.h.z - p.hz;
 }

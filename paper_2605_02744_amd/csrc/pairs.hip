@@ -39,14 +39,29 @@ __device__ __forceinline__ JRec<MODE> load_rec(const double* __restrict__ x, con
 }
 
 // ============================================================== acceleration
+// Near-field repair of the FP32C force: pairs are evaluated from positions
+// rounded to FP32 (12 VALU operations per pair instead of 18 with float-float
+// displacements), and every lane tracks the smallest squared distance it met
+// in each block of kFold j-particles.  Rounding a coordinate to FP32 moves it
+// by up to 2^-24 |x|, which only matters for pairs much closer than |x|; when
+// a block holds a pair closer than d_c(i) = max(kNearX |x_i|, kNearEps eps),
+// that lane recomputes the block's partial sum with float-float displacements
+// for those pairs.  Such blocks are rare (a pair closer than a few eps), so the
+// force costs one extra min per pair and keeps float-float accuracy.
+constexpr float kNearX = 2.0e-2f;
+constexpr float kNearEps = 2.0f;
+
 // Grid: (ceil(n / (256*IPL)), split).  Block y handles j in [y*chunk, min(n, (y+1)*chunk)).
 // split == 1: writes G*(hi+lo) to a[c*n+i].  split > 1: writes hi+lo to
 // part[(y*3+c)*n+i] and a second kernel sums the slices in order.
-template <int MODE, int IPL, bool EXCL>
+// NEAR (FP32C only): rounded-position pairs with the near-field repair above;
+// otherwise FP32C uses float-float displacements for every pair.
+template <int MODE, int IPL, bool EXCL, bool NEAR>
 __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __restrict__ x,
                                                        const double* __restrict__ m, double eps, double G,
                                                        int chunk, double* __restrict__ out) {
   using R = Real<MODE>;
+  static_assert(!NEAR || MODE == kFP32C, "the near-field repair needs float-float records");
   __shared__ JRec<MODE> tile[2][kTile];
   const int t = threadIdx.x;
   const int ibase = blockIdx.x * (kBlock * IPL) + t;
@@ -56,12 +71,16 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
 
   IPos<MODE> pi[IPL];
   int iidx[IPL];
+  R rc2[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     int i = ibase + k * kBlock;
     iidx[k] = i;
     int ic = i < n ? i : n - 1;
-    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+    const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
+    pi[k].set(xa, ya, za);
+    const float dc = fmaxf(kNearX * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
+    rc2[k] = (R)(dc * dc) + e2;
   }
   R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
 #pragma unroll
@@ -80,9 +99,12 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
     const JRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
     for (int f = 0; f < kTile; f += kFold) {
-      R px[IPL], py[IPL], pz[IPL];
+      R px[IPL], py[IPL], pz[IPL], r2min[IPL];
 #pragma unroll
-      for (int k = 0; k < IPL; ++k) px[k] = py[k] = pz[k] = R(0);
+      for (int k = 0; k < IPL; ++k) {
+        px[k] = py[k] = pz[k] = R(0);
+        r2min[k] = R(3.0e38f);
+      }
 #pragma unroll 16
       for (int jj = f; jj < f + kFold; ++jj) {
         const JRec<MODE> r = cur[jj];
@@ -90,7 +112,8 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
           R dx, dy, dz;
-          disp(r, pi[k], dx, dy, dz);
+          if constexpr (NEAR) disp_hi(r, pi[k], dx, dy, dz);
+          else disp(r, pi[k], dx, dy, dz);
           R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
           R ri = rsq(r2);
           R s = (mj * ri) * (ri * ri);
@@ -98,6 +121,35 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
           px[k] = fma(s, dx, px[k]);
           py[k] = fma(s, dy, py[k]);
           pz[k] = fma(s, dz, pz[k]);
+          if constexpr (NEAR) r2min[k] = fminf(r2min[k], r2);
+        }
+      }
+      if constexpr (NEAR) {
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          if (r2min[k] < rc2[k]) {
+            // rare: redo this block for lane k with float-float displacements for the close pairs
+            R qx = 0, qy = 0, qz = 0;
+            for (int jj = f; jj < f + kFold; ++jj) {
+              const JRec<MODE> r = cur[jj];
+              R dx, dy, dz;
+              disp_hi(r, pi[k], dx, dy, dz);
+              R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 < rc2[k]) {
+                disp(r, pi[k], dx, dy, dz);
+                r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              }
+              R ri = rsq(r2);
+              R s = (jmass(r) * ri) * (ri * ri);
+              if (EXCL) s = (jt + jj == iidx[k]) ? R(0) : s;
+              qx = fma(s, dx, qx);
+              qy = fma(s, dy, qy);
+              qz = fma(s, dz, qz);
+            }
+            px[k] = qx;
+            py[k] = qy;
+            pz[k] = qz;
+          }
         }
       }
 #pragma unroll
@@ -177,17 +229,45 @@ __device__ __forceinline__ R cross_weight(R mk, R wj, R mj, R wk) {
   return a - b;
 }
 
+// One VJP pair term for lane particle k and record j, displacement d = x_j - x_k:
+//   g += r^-3 u - 3 r^-5 (d.u) d,  gm -= r^-3 (d . w_j),  u = m_k w_j - m_j w_k.
+template <typename R>
+__device__ __forceinline__ R vjp_pair(R dx, R dy, R dz, R e2, R mj, R wjx, R wjy, R wjz, R mk, R wkx, R wky,
+                                      R wkz, bool self, R& px, R& py, R& pz, R& pm) {
+  R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+  R ri = rsq(r2);
+  R ri2 = ri * ri;
+  R r3 = ri2 * ri;
+  R r5 = r3 * ri2;
+  r3 = self ? R(0) : r3;
+  r5 = self ? R(0) : r5;
+  R ux = cross_weight(mk, wjx, mj, wkx);
+  R uy = cross_weight(mk, wjy, mj, wky);
+  R uz = cross_weight(mk, wjz, mj, wkz);
+  R du = fma(dz, uz, fma(dy, uy, dx * ux));
+  R c = R(3) * r5 * du;
+  px = fma(-c, dx, fma(r3, ux, px));
+  py = fma(-c, dy, fma(r3, uy, py));
+  pz = fma(-c, dz, fma(r3, uz, pz));
+  R dw = fma(dz, wjz, fma(dy, wjy, dx * wjx));
+  pm = fma(-r3, dw, pm);
+  return r2;
+}
+
 // gx_k = G sum_j [ r^-3 u - 3 r^-5 (d.u) d ],  gm_k = -G sum_j r^-3 (d . w_j),
 // d = x_j - x_k, u = m_k w_j - m_j w_k, r^2 = |d|^2 + eps^2.
 // split == 1: writes G * sums to gx (3n) and gm (n).
 // split > 1: writes slice y's unscaled 4n partials (gx then gm) at part + y*4n.
-template <int MODE, int IPL, bool EXCL>
+// NEAR (FP32C only): rounded-position pairs with the near-field repair of the
+// force kernel; otherwise FP32C uses float-float displacements for every pair.
+template <int MODE, int IPL, bool EXCL, bool NEAR>
 __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __restrict__ x,
                                                      const double* __restrict__ m,
                                                      const double* __restrict__ w, double eps, double G,
                                                      int chunk, double* __restrict__ gx,
                                                      double* __restrict__ gm, double* __restrict__ part) {
   using R = Real<MODE>;
+  static_assert(!NEAR || MODE == kFP32C, "the near-field repair needs float-float records");
   __shared__ WRec<MODE> tile[2][kTile];
   const int t = threadIdx.x;
   const int ibase = blockIdx.x * (kBlock * IPL) + t;
@@ -196,16 +276,19 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
   const R e2 = (R)(eps * eps);
 
   IPos<MODE> pi[IPL];
-  R mk[IPL], wkx[IPL], wky[IPL], wkz[IPL];
+  R mk[IPL], wkx[IPL], wky[IPL], wkz[IPL], rc2[IPL];
   int iidx[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     int i = ibase + k * kBlock;
     iidx[k] = i;
     int ic = i < n ? i : n - 1;
-    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+    const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
+    pi[k].set(xa, ya, za);
     mk[k] = (R)m[ic];
     wkx[k] = (R)w[ic]; wky[k] = (R)w[n + ic]; wkz[k] = (R)w[2 * n + ic];
+    const float dc = fmaxf(kNearX * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
+    rc2[k] = (R)(dc * dc) + e2;
   }
   R hx[IPL], hy[IPL], hz[IPL], hm[IPL], lx[IPL], ly[IPL], lz[IPL], lm[IPL];
 #pragma unroll
@@ -222,9 +305,12 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
     const WRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
     for (int f = 0; f < kTile; f += kFold) {
-      R px[IPL], py[IPL], pz[IPL], pm[IPL];
+      R px[IPL], py[IPL], pz[IPL], pm[IPL], r2min[IPL];
 #pragma unroll
-      for (int k = 0; k < IPL; ++k) px[k] = py[k] = pz[k] = pm[k] = R(0);
+      for (int k = 0; k < IPL; ++k) {
+        px[k] = py[k] = pz[k] = pm[k] = R(0);
+        r2min[k] = R(3.0e38f);
+      }
 #pragma unroll 8
       for (int jj = f; jj < f + kFold; ++jj) {
         const WRec<MODE> q = cur[jj];
@@ -232,27 +318,33 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
           R dx, dy, dz;
-          disp(q.r, pi[k], dx, dy, dz);
-          R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-          R ri = rsq(r2);
-          R ri2 = ri * ri;
-          R r3 = ri2 * ri;
-          R r5 = r3 * ri2;
-          if (EXCL) {
-            const bool self = (jt + jj == iidx[k]);
-            r3 = self ? R(0) : r3;
-            r5 = self ? R(0) : r5;
+          if constexpr (NEAR) disp_hi(q.r, pi[k], dx, dy, dz);
+          else disp(q.r, pi[k], dx, dy, dz);
+          const R r2 = vjp_pair<R>(dx, dy, dz, e2, mj, q.w.x, q.w.y, q.w.z, mk[k], wkx[k], wky[k], wkz[k],
+                                   EXCL && (jt + jj == iidx[k]), px[k], py[k], pz[k], pm[k]);
+          if constexpr (NEAR) r2min[k] = fminf(r2min[k], r2);
+        }
+      }
+      if constexpr (NEAR) {
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          if (r2min[k] < rc2[k]) {
+            // rare: redo this block for lane k with float-float displacements for the close pairs
+            R qx = 0, qy = 0, qz = 0, qm = 0;
+            for (int jj = f; jj < f + kFold; ++jj) {
+              const WRec<MODE> q = cur[jj];
+              R dx, dy, dz;
+              disp_hi(q.r, pi[k], dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 < rc2[k]) disp(q.r, pi[k], dx, dy, dz);
+              vjp_pair<R>(dx, dy, dz, e2, jmass(q.r), q.w.x, q.w.y, q.w.z, mk[k], wkx[k], wky[k], wkz[k],
+                          EXCL && (jt + jj == iidx[k]), qx, qy, qz, qm);
+            }
+            px[k] = qx;
+            py[k] = qy;
+            pz[k] = qz;
+            pm[k] = qm;
           }
-          R ux = cross_weight(mk[k], q.w.x, mj, wkx[k]);
-          R uy = cross_weight(mk[k], q.w.y, mj, wky[k]);
-          R uz = cross_weight(mk[k], q.w.z, mj, wkz[k]);
-          R du = fma(dz, uz, fma(dy, uy, dx * ux));
-          R c = R(3) * r5 * du;
-          px[k] = fma(-c, dx, fma(r3, ux, px[k]));
-          py[k] = fma(-c, dy, fma(r3, uy, py[k]));
-          pz[k] = fma(-c, dz, fma(r3, uz, pz[k]));
-          R dw = fma(dz, q.w.z, fma(dy, q.w.y, dx * q.w.x));
-          pm[k] = fma(-r3, dw, pm[k]);
         }
       }
 #pragma unroll
@@ -353,10 +445,11 @@ int accel_dispatch(int64_t n, const double* x, const double* m, double* a, doubl
     out = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 3 * (size_t)n * sp, &st));
     if (!out) return st;
   }
+  constexpr bool kNear = MODE == kFP32C;
   if (excl)
-    accel_kernel<MODE, IPL, true><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
+    accel_kernel<MODE, IPL, true, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
   else
-    accel_kernel<MODE, IPL, false><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
+    accel_kernel<MODE, IPL, false, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
   NB_LAUNCH_CHECK("accel_kernel");
   if (sp > 1) {
     const int64_t cnt = 3 * n;
@@ -378,10 +471,11 @@ int vjp_dispatch(int64_t n, const double* x, const double* m, const double* w, d
     part = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 4 * (size_t)n * sp, &st));
     if (!part) return st;
   }
+  constexpr bool kNear = MODE == kFP32C;
   if (excl)
-    vjp_kernel<MODE, IPL, true><<<grid, kBlock, 0, s>>>((int)n, x, m, w, eps, G, chunk, gx, gm, part);
+    vjp_kernel<MODE, IPL, true, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, w, eps, G, chunk, gx, gm, part);
   else
-    vjp_kernel<MODE, IPL, false><<<grid, kBlock, 0, s>>>((int)n, x, m, w, eps, G, chunk, gx, gm, part);
+    vjp_kernel<MODE, IPL, false, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, w, eps, G, chunk, gx, gm, part);
   NB_LAUNCH_CHECK("vjp_kernel");
   if (sp > 1) {
     const int64_t cnt = 4 * n;

@@ -75,6 +75,43 @@ def test_accel_exclude_self_eps_zero(nb, oracle_mod, prec):
     assert rel_err(a, ref) <= 10 * TOL[prec]
 
 
+def _tight_pairs_far_away(n=3000, seed=30):
+    """A Plummer cloud shifted to (3, -2, 5) with 200 particles given a partner
+    at 1e-5 .. 1e-3 (well inside eps = 0.01): FP32-rounded positions resolve
+    those separations to only a few per cent."""
+    x, _, m = ics.plummer(n, seed=seed)
+    x = x + np.array([[3.0], [-2.0], [5.0]])
+    rng = np.random.default_rng(seed)
+    a = rng.choice(n // 2, 200, replace=False)
+    b = n // 2 + np.arange(200)
+    off = rng.standard_normal((3, 200))
+    off *= 10 ** rng.uniform(-5, -3, 200) / np.linalg.norm(off, axis=0)
+    x[:, b] = x[:, a] + off
+    return x, m
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_accel_tight_pairs_near_field(nb, oracle_mod, prec, tol):
+    x, m = _tight_pairs_far_away()
+    ref = oracle_mod.accel(x, m, eps=0.01)
+    a = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision=prec).cpu().numpy()
+    e = rel_err(a, ref)
+    print("tight pairs %s max rel err %.3e" % (prec, e))
+    assert e <= tol
+    # rounded positions without the repair are far off for these pairs
+    a32 = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp32").cpu().numpy()
+    assert rel_err(a32, ref) > 10 * tol
+
+
+def test_vjp_tight_pairs_near_field(nb, oracle_mod):
+    x, m = _tight_pairs_far_away(2000, seed=31)
+    w = np.random.default_rng(2).standard_normal(x.shape)
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
+    gx, gm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp32c")
+    assert np.linalg.norm(gx.cpu().numpy() - rgx) <= 2e-5 * np.linalg.norm(rgx)
+    assert np.linalg.norm(gm.cpu().numpy() - rgm) <= 2e-5 * np.linalg.norm(rgm)
+
+
 def test_accel_plummer1k_fp64(nb, oracle_mod):
     w = ics.WORKLOADS["plummer1k_fp64"]
     x, _, m = ics.plummer(w["n"], seed=w["seed"])
@@ -215,6 +252,26 @@ def test_batched_matches_single_system(nb, prec, tol):
         dx = np.abs(bx[:, s:e] - cx.cpu().numpy()).max()
         dv = np.abs(bv[:, s:e] - cv.cpu().numpy()).max()
         assert dx <= tol and dv <= tol * 100, (c, sizes[c], dx, dv)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_batched_split_and_unsplit_agree(nb, prec):
+    """Large systems split over workgroups give the same trajectories (to
+    rounding) as one workgroup per system."""
+    sizes = [4096, 3000, 2048, 700, 64, 1]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=21, sizes=sizes)
+    out = []
+    for bsplit in (0, 1):
+        nb.nbody_set_config(bsplit=bsplit)
+        try:
+            tx, tv, tm = dev(x), dev(v), dev(m)
+            ta = torch.empty_like(tx)
+            nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 6, precision=prec, check_finite=True)
+        finally:
+            nb.nbody_set_config()
+        out.append((tx.cpu().numpy(), tv.cpu().numpy()))
+    assert np.abs(out[0][0] - out[1][0]).max() <= 1e-10
+    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-8
 
 
 def test_batched_matches_oracle_fp64(nb, oracle_mod):
