@@ -50,6 +50,8 @@ def _load():
         lib.oracle_accel_jvp.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D]
         lib.oracle_kdk_adjoint.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, _I64, _D, _D, _D, _D, _D]
+        lib.oracle_accel_jerk.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D, _D]
+        lib.oracle_hermite4.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I64]
         lib.oracle_msd_loss.argtypes = [_I64, _D, _D]
         lib.oracle_msd_loss.restype = ctypes.c_double
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -172,6 +174,28 @@ def kdk_adjoint(x0, v0, m, dt, nsteps, gxT, gvT, G=1.0, eps=0.0):
     _load().oracle_kdk_adjoint(n, _p(x0), _p(v0), _p(m), float(G), float(eps), float(dt),
                                int(nsteps), _p(gxT), _p(gvT), _p(gx0), _p(gv0), _p(gm))
     return gx0, gv0, gm
+
+
+def accel_jerk(x, v, m, G=1.0, eps=0.0):
+    """(a, jerk), each (3, N): App. A Algorithm 3 with softened r^2."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n))
+    v = _c(v, (3, n))
+    a = np.empty((3, n))
+    jk = np.empty((3, n))
+    _load().oracle_accel_jerk(n, _p(x), _p(v), _p(m), float(G), float(eps), _p(a), _p(jk))
+    return a, jk
+
+
+def hermite4(x, v, m, dt, nsteps, G=1.0, eps=0.0):
+    """Fourth-order Hermite predictor-evaluator-corrector; returns (x, v)."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n)).copy()
+    v = _c(v, (3, n)).copy()
+    _load().oracle_hermite4(n, _p(x), _p(v), _p(m), float(G), float(eps), float(dt), int(nsteps))
+    return x, v
 
 
 def msd_loss(x, tgt):

@@ -24,7 +24,14 @@
  *     predictor-corrector; the workloads use KDK);
  *   - diagnostics: kinetic + softened pair potential (self pair excluded),
  *     linear and angular momentum (Sec. 4.1 compares particle energies);
- *   - adjoint: the exact reverse-mode derivative of the KDK map above.
+ *   - adjoint: the exact reverse-mode derivative of the KDK map above;
+ *   - jerk: App. A, Algorithm 3 (t_j = p_w r^-3, A = -3 r^-2, v_r = r . v,
+ *     q = A v_r, a += t_j r_ij, jerk += t_j (v_ij + q r_ij)), with the
+ *     softened r^2 = |d|^2 + eps^2, i.e. the time derivative of the softened
+ *     acceleration along the motion;
+ *   - Hermite: the fourth-order predictor-evaluator-corrector with a shared
+ *     time step (Sec. 2.1 describes the sixth-order member of this family:
+ *     predict, evaluate acceleration and jerk, correct).
  */
 #include <math.h>
 #include <stdint.h>
@@ -273,6 +280,78 @@ void oracle_kdk_adjoint(int64_t n, const double* x0, const double* v0, const dou
     memcpy(gx0, lx, sizeof(double) * (size_t)n3);
     memcpy(gv0, lv, sizeof(double) * (size_t)n3);
     free(traj); free(xw); free(vw); free(lx); free(lv); free(w); free(jx); free(jm);
+}
+
+/* ---- acceleration and jerk (App. A, Algorithm 3) ----------------------- */
+static void accel_jerk_row(int64_t n, const double* x, const double* v, const double* m, double G,
+                           double eps, int64_t i, double a[3], double jk[3]) {
+    nsum sa[3] = {{0, 0}, {0, 0}, {0, 0}}, sj[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double r[3], w[3];
+        for (int c = 0; c < 3; ++c) {
+            r[c] = x[c * n + j] - x[c * n + i];       /* r_ij = r_j - r_i */
+            w[c] = v[c * n + j] - v[c * n + i];       /* v_ij = v_j - v_i */
+        }
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps * eps;
+        double rinv = 1.0 / sqrt(r2);
+        double rinv2 = rinv * rinv;
+        double t = m[j] * rinv2 * rinv;               /* t_j = p_w,j r^-3 */
+        double A = -3.0 * rinv2;                      /* A = -3 r^-2 */
+        double vr = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+        double q = A * vr;                            /* q = A v_r */
+        for (int c = 0; c < 3; ++c) {
+            nadd(&sa[c], t * r[c]);
+            nadd(&sj[c], t * (w[c] + q * r[c]));
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        a[c] = G * nval(&sa[c]);
+        jk[c] = G * nval(&sj[c]);
+    }
+}
+
+void oracle_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double G, double eps,
+                       double* a, double* jk) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double ai[3], ji[3];
+        accel_jerk_row(n, x, v, m, G, eps, i, ai, ji);
+        for (int c = 0; c < 3; ++c) {
+            a[c * n + i] = ai[c];
+            jk[c * n + i] = ji[c];
+        }
+    }
+}
+
+/* Fourth-order Hermite predictor-evaluator-corrector, shared step dt:
+ *   predict  xp = x + v dt + a dt^2/2 + j dt^3/6,  vp = v + a dt + j dt^2/2
+ *   evaluate a1, j1 at (xp, vp)
+ *   correct  v1 = v + (a0 + a1) dt/2 + (j0 - j1) dt^2/12
+ *            x1 = x + (v + v1) dt/2 + (a0 - a1) dt^2/12
+ * (x, v) advance in place by nsteps steps. */
+void oracle_hermite4(int64_t n, double* x, double* v, const double* m, double G, double eps, double dt,
+                     int64_t nsteps) {
+    const int64_t n3 = 3 * n;
+    const size_t nb = sizeof(double) * (size_t)(n3 > 0 ? n3 : 1);
+    double *a0 = (double*)malloc(nb), *j0 = (double*)malloc(nb), *a1 = (double*)malloc(nb),
+           *j1 = (double*)malloc(nb), *xp = (double*)malloc(nb), *vp = (double*)malloc(nb);
+    oracle_accel_jerk(n, x, v, m, G, eps, a0, j0);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int64_t k = 0; k < n3; ++k) {
+            xp[k] = x[k] + v[k] * dt + a0[k] * (dt * dt / 2.0) + j0[k] * (dt * dt * dt / 6.0);
+            vp[k] = v[k] + a0[k] * dt + j0[k] * (dt * dt / 2.0);
+        }
+        oracle_accel_jerk(n, xp, vp, m, G, eps, a1, j1);
+        for (int64_t k = 0; k < n3; ++k) {
+            double v1 = v[k] + (a0[k] + a1[k]) * (dt / 2.0) + (j0[k] - j1[k]) * (dt * dt / 12.0);
+            x[k] = x[k] + (v[k] + v1) * (dt / 2.0) + (a0[k] - a1[k]) * (dt * dt / 12.0);
+            v[k] = v1;
+            a0[k] = a1[k];
+            j0[k] = j1[k];
+        }
+    }
+    free(a0); free(j0); free(a1); free(j1); free(xp); free(vp);
 }
 
 /* Mean squared distance of positions to a target: (1/N) sum_i |x_i - t_i|^2. */

@@ -11,6 +11,8 @@ Definitions (Eq. (1) of Sec. 2.1 divided by m_i, Plummer softening of App. A):
   W    = -G sum_{i < j} m_i m_j / (|d_ij|^2 + eps^2)^(1/2)
   VJP  : gx_k = sum_i (d a_i / d x_k)^T w_i,  gm_k = sum_i (d a_i / d m_k)^T w_i,
          obtained here by mpmath differentiation of the mpmath acceleration.
+  jerk : d/dt a_i(x + V t) at t = 0 for velocities V (mpmath differentiation),
+         the quantity App. A, Algorithm 3 accumulates beside the acceleration.
 Run:  python tests/golden/make_tiny_mp50.py
 """
 import os
@@ -26,6 +28,9 @@ X = [[0.5, -0.25, 0.125, 0.75, -0.625],
 M = [0.25, 0.125, 0.375, 0.0625, 0.1875]
 G = 1.0
 EPS = 0.0625
+VEL = [[0.25, -0.5, 0.0, 0.125, -0.375],
+       [0.5, 0.0, -0.25, 0.75, 0.0625],
+       [-0.125, 0.375, 0.5, 0.0, -0.25]]
 W_COT = [[0.5, -1.0, 0.25, 0.0, 0.75],
          [-0.5, 0.125, 1.0, -0.25, 0.0],
          [0.25, 0.5, -0.75, 1.0, -0.125]]
@@ -82,6 +87,19 @@ def vjp(x, m, w, eps, G):
     return gx, gm
 
 
+def jerk(x, vel, m, eps, G):
+    """d/dt of the mpmath acceleration along straight-line motion x + vel t."""
+    n = len(m)
+    out = [[mp.mpf(0)] * n for _ in range(3)]
+    for c in range(3):
+        for i in range(n):
+            def f(t, c=c, i=i):
+                xs = [[x[d][k] + vel[d][k] * t for k in range(n)] for d in range(3)]
+                return accel(xs, m, eps, G)[c][i]
+            out[c][i] = mp.diff(f, 0)
+    return out
+
+
 def main():
     x = [[mp.mpf(v) for v in row] for row in X]
     m = [mp.mpf(v) for v in M]
@@ -90,6 +108,8 @@ def main():
     a = accel(x, m, eps, g)
     pot = potential(x, m, eps, g)
     gx, gm = vjp(x, m, w, eps, g)
+    vel = [[mp.mpf(v) for v in row] for row in VEL]
+    jk = jerk(x, vel, m, eps, g)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny5_mp50.txt")
     with open(path, "w") as f:
         f.write("# 5-body softened gravity evaluated with mpmath at 50 digits\n")
@@ -107,6 +127,10 @@ def main():
         for c in range(3):
             f.write("gx%d %s\n" % (c, " ".join(mp.nstr(v, 40) for v in gx[c])))
         f.write("gm %s\n" % " ".join(mp.nstr(v, 40) for v in gm))
+        for c in range(3):
+            f.write("v%d %s\n" % (c, " ".join(repr(v) for v in VEL[c])))
+        for c in range(3):
+            f.write("j%d %s\n" % (c, " ".join(mp.nstr(v, 40) for v in jk[c])))
     print("wrote", path)
 
 

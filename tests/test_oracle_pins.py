@@ -37,7 +37,9 @@ def _read_golden():
     w = np.stack([d["w0"], d["w1"], d["w2"]])
     a = np.stack([d["a0"], d["a1"], d["a2"]])
     gx = np.stack([d["gx0"], d["gx1"], d["gx2"]])
-    return dict(x=x, m=d["m"], w=w, a=a, W=float(d["W"][0]), gx=gx, gm=d["gm"],
+    vel = np.stack([d["v0"], d["v1"], d["v2"]])
+    jk = np.stack([d["j0"], d["j1"], d["j2"]])
+    return dict(x=x, m=d["m"], w=w, a=a, W=float(d["W"][0]), gx=gx, gm=d["gm"], v=vel, j=jk,
                 G=float(d["G"][0]), eps=float(d["eps"][0]))
 
 
@@ -344,3 +346,55 @@ def test_kdk_adjoint_central_difference(oracle_mod):
                 lq = oracle_mod.msd_loss(oracle_mod.kdk(x, q, m, dt, steps, eps=eps)[0], tgt)
             fd = (lp - lq) / (2 * h)
             assert abs(fd - g[c, i]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max())
+
+
+# ---- acceleration + jerk (App. A, Algorithm 3) and the Hermite integrator ----
+
+def test_golden_jerk_mp50(oracle_mod):
+    g = _read_golden()
+    a, jk = oracle_mod.accel_jerk(g["x"], g["v"], g["m"], G=g["G"], eps=g["eps"])
+    assert np.abs(a - g["a"]).max() <= 2e-15 * np.abs(g["a"]).max()
+    assert np.abs(jk - g["j"]).max() <= 2e-15 * np.abs(g["j"]).max()
+
+
+def test_jerk_is_time_derivative_of_accel(oracle_mod):
+    """jerk_i = d/dt a_i(x + v t) at t = 0, by central differences of the
+    separately written acceleration routine."""
+    x, v, m = ics.plummer(200, seed=40)
+    eps = 0.02
+    _, jk = oracle_mod.accel_jerk(x, v, m, G=1.3, eps=eps)
+    h = 1e-6
+    fd = (oracle_mod.accel(x + h * v, m, G=1.3, eps=eps) - oracle_mod.accel(x - h * v, m, G=1.3, eps=eps)) / (2 * h)
+    assert np.abs(fd - jk).max() <= 2e-8 * np.abs(jk).max()
+
+
+def test_jerk_total_is_zero_momentum_rate(oracle_mod):
+    """sum_i m_i jerk_i = d/dt sum_i m_i a_i = 0 (pairwise antisymmetry)."""
+    x, v, m = ics.random_cloud(300, seed=41)
+    _, jk = oracle_mod.accel_jerk(x, v, m, eps=0.05)
+    assert np.abs((jk * m).sum(axis=1)).max() <= 1e-14 * (np.abs(jk) * m).sum()
+
+
+def test_hermite4_kepler_fourth_order(oracle_mod):
+    m1, m2, a_sm, e = 0.7, 0.3, 1.0, 0.5
+    x0, v0, m = _kepler_ics(m1, m2, a_sm, e)
+    period = 2 * math.pi * math.sqrt(a_sm ** 3 / (m1 + m2))
+    t_end = 0.8 * period
+    errs = []
+    for steps in (400, 800, 1600):
+        x, _ = oracle_mod.hermite4(x0, v0, m, t_end / steps, steps, eps=0.0)
+        errs.append(np.linalg.norm(x[:, 1] - x[:, 0] - _kepler_positions(m1, m2, a_sm, e, t_end)))
+    assert errs[-1] < 1e-6
+    for coarse, fine in zip(errs[:-1], errs[1:]):
+        assert 12.0 < coarse / fine < 20.0, errs
+
+
+def test_hermite4_conserves_momentum_and_energy(oracle_mod):
+    x, v, m = ics.plummer(128, seed=42)
+    eps = 0.05
+    e0 = oracle_mod.energy(x, v, m, 1.0, eps)
+    x1, v1 = oracle_mod.hermite4(x, v, m, 1.0 / 256, 64, eps=eps)
+    e1 = oracle_mod.energy(x1, v1, m, 1.0, eps)
+    pscale = (m * np.abs(v1).sum(axis=0)).sum()
+    assert np.abs(e1[3:6] - e0[3:6]).max() <= 1e-13 * pscale
+    assert abs(e1[2] - e0[2]) <= 1e-7 * abs(e0[2])
