@@ -160,6 +160,30 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
                        double* v, double* a, const double* m, double dt, int64_t nsteps,
                        const nbody_params* p, void* stream);
 
+/* Accelerations a (3*n) and jerks jk (3*n) of particles at x (3*n) with
+ * velocities v (3*n) and masses m (n): App. A, Algorithm 3 in full,
+ *   a_i  = G sum_{j != i} m_j r_ij / r^3,
+ *   jk_i = G sum_{j != i} m_j [ v_ij - 3 (r_ij . v_ij) r_ij / r^2 ] / r^3,
+ * r_ij = x_j - x_i, v_ij = v_j - v_i, r^2 = |r_ij|^2 + eps^2 (the time
+ * derivative of the softened acceleration along the motion).  FP32C keeps
+ * float-float positions and FP32 velocities for every pair.  Errors: as
+ * nbody_accel; a and jk must be distinct from each other and the inputs. */
+int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk,
+                     const nbody_params* p, void* stream);
+
+/* nsteps fourth-order Hermite predictor-evaluator-corrector steps with a
+ * shared step dt (the integrator family of Sec. 2.1: predict positions and
+ * velocities from a and its derivative, evaluate acceleration and jerk,
+ * correct), in place on x, v, a, jk:
+ *   predict  xp = x + v dt + a dt^2/2 + jk dt^3/6,  vp = v + a dt + jk dt^2/2
+ *   evaluate (a1, jk1) at (xp, vp)
+ *   correct  v' = v + (a + a1) dt/2 + (jk - jk1) dt^2/12,
+ *            x' = x + (v + v') dt/2 + (a - a1) dt^2/12.
+ * NBODY_ACC_VALID means a and jk already hold the evaluation at (x, v).
+ * Errors: as nbody_step. */
+int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt,
+                       int64_t nsteps, const nbody_params* p, void* stream);
+
 /* Tile configuration of the all-pairs kernels (see nbody_set_config). */
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */

@@ -73,6 +73,8 @@ def load():
     lib.nbody_traj_grad.argtypes = [_I64, _P, _P, _I64, _I64, _P, _D, _P, _P, _P, _P, _P, PP, _P]
     lib.nbody_step_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double), _P, _P, _P, _P, _D, _I64, PP, _P]
+    lib.nbody_accel_jerk.argtypes = [_I64, _P, _P, _P, _P, _P, PP, _P]
+    lib.nbody_step_hermite.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_set_config.argtypes = [ctypes.POINTER(nbody_config)]
     lib.nbody_tune.argtypes = [_I64, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(nbody_config)]
     lib.nbody_last_error.restype = ctypes.c_char_p
@@ -80,7 +82,8 @@ def load():
     lib.nbody_finalize.argtypes = []
     lib.nbody_version.argtypes = []
     for f in ("nbody_accel", "nbody_step", "nbody_energy", "nbody_accel_vjp", "nbody_traj_grad",
-              "nbody_step_batched", "nbody_set_config", "nbody_tune", "nbody_finalize", "nbody_version"):
+              "nbody_step_batched", "nbody_set_config", "nbody_tune", "nbody_finalize", "nbody_version",
+              "nbody_accel_jerk", "nbody_step_hermite"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -215,6 +218,32 @@ def nbody_step_batched(off, eps, x, v, a, m, dt, nsteps, *, G=1.0, precision="fp
                                       _ptr(m, "m", (total,)), float(dt), int(nsteps), ctypes.byref(p),
                                       _stream(x.device)))
     return x, v, a
+
+
+def nbody_accel_jerk(x, v, m, *, G=1.0, eps, precision="fp32c", exclude_self=False, check_finite=False):
+    """(a, jerk), each (3, N), of particles x, v (3, N) with masses m (N,)."""
+    lib = load()
+    n = m.shape[0]
+    a = torch.empty((3, n), dtype=torch.float64, device=x.device)
+    jk = torch.empty((3, n), dtype=torch.float64, device=x.device)
+    p = _params(G, eps, precision, _flags(exclude_self, check_finite))
+    with torch.cuda.device(x.device):
+        _check(lib.nbody_accel_jerk(n, _ptr(x, "x", (3, n)), _ptr(v, "v", (3, n)), _ptr(m, "m", (n,)),
+                                    _ptr(a, "a", (3, n)), _ptr(jk, "jk", (3, n)), ctypes.byref(p), _stream(x.device)))
+    return a, jk
+
+
+def nbody_step_hermite(x, v, a, jk, m, dt, nsteps, *, G=1.0, eps, precision="fp32c", acc_valid=False,
+                       exclude_self=False, check_finite=False):
+    """nsteps fourth-order Hermite steps in place on x, v, a, jk (each (3, N))."""
+    lib = load()
+    n = m.shape[0]
+    p = _params(G, eps, precision, _flags(exclude_self, check_finite, acc_valid))
+    with torch.cuda.device(x.device):
+        _check(lib.nbody_step_hermite(n, _ptr(x, "x", (3, n)), _ptr(v, "v", (3, n)), _ptr(a, "a", (3, n)),
+                                      _ptr(jk, "jk", (3, n)), _ptr(m, "m", (n,)), float(dt), int(nsteps),
+                                      ctypes.byref(p), _stream(x.device)))
+    return x, v, a, jk
 
 
 def nbody_set_config(ipl=0, split=0, bsplit=0):

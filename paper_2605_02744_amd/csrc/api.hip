@@ -341,6 +341,46 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
   return finish(st, s, p, {{x, 3 * total}, {v, 3 * total}, {a, 3 * total}});
 }
 
+int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk,
+                     const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(v, b3, "v"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  NB_TRY(check_dev_range(jk, b3, "jk"));
+  if (a == jk || (const double*)a == x || (const double*)a == v || (const double*)jk == x || (const double*)jk == v)
+    return set_error(NBODY_EINVAL, "a and jk must be distinct from each other and the inputs");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = launch_accel_jerk(n, x, v, m, a, jk, p->G, p->eps, p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0,
+                             cfg, s);
+  return finish(st, s, p, {{a, 3 * n}, {jk, 3 * n}});
+}
+
+int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt,
+                       int64_t nsteps, const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt is not finite");
+  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(v, b3, "v"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  NB_TRY(check_dev_range(jk, b3, "jk"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  if (x == v || x == a || x == jk || v == a || v == jk || a == jk)
+    return set_error(NBODY_EINVAL, "x, v, a and jk must be distinct");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = run_hermite(n, x, v, a, jk, m, dt, nsteps, p->G, p->eps, p->precision,
+                       (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, cfg, s);
+  return finish(st, s, p, {{x, 3 * n}, {v, 3 * n}, {a, 3 * n}, {jk, 3 * n}});
+}
+
 int nbody_set_config(const nbody_config* cfg) {
   if (!cfg) return set_error(NBODY_EINVAL, "cfg is NULL");
   if (cfg->ipl != 0 && cfg->ipl != 1 && cfg->ipl != 2 && cfg->ipl != 4)

@@ -66,6 +66,15 @@ int launch_vjp(int64_t n, const double* x, const double* m, const double* w, dou
                double* gm, double G, double eps, int precision, bool exclude_self,
                const PairConfig& cfg, hipStream_t s);
 
+// Acceleration and jerk (App. A, Algorithm 3) into a and jk (FP64 SoA).
+int launch_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
+                      double eps, int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
+
+// The fourth-order Hermite loop of nbody_step_hermite.
+int run_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt, int64_t nsteps,
+                double G, double eps, int precision, bool exclude_self, bool acc_valid, const PairConfig& cfg,
+                hipStream_t s);
+
 // Elementwise KDK pieces over 3n entries.
 int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s);
 int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double h, double dt,

@@ -57,6 +57,34 @@ __global__ void adjoint_update_kernel(int64_t n, double* __restrict__ lx, double
   if (e < n) gm[e] += gmp[e];
 }
 
+// Hermite predictor: xp = x + v dt + a dt^2/2 + j dt^3/6, vp = v + a dt + j dt^2/2.
+__global__ void hermite_predict_kernel(int64_t n3, const double* __restrict__ x, const double* __restrict__ v,
+                                       const double* __restrict__ a, const double* __restrict__ jk, double dt,
+                                       double* __restrict__ xp, double* __restrict__ vp) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double h2 = 0.5 * dt * dt, h3 = dt * dt * dt / 6.0;
+  xp[e] = fma(jk[e], h3, fma(a[e], h2, fma(v[e], dt, x[e])));
+  vp[e] = fma(jk[e], h2, fma(a[e], dt, v[e]));
+}
+
+// Hermite corrector, in place on (x, v, a, jk) from the evaluation (a1, j1):
+//   v1 = v + (a0 + a1) dt/2 + (j0 - j1) dt^2/12
+//   x1 = x + (v + v1) dt/2 + (a0 - a1) dt^2/12
+__global__ void hermite_correct_kernel(int64_t n3, double* __restrict__ x, double* __restrict__ v,
+                                       double* __restrict__ a, double* __restrict__ jk,
+                                       const double* __restrict__ a1, const double* __restrict__ j1, double dt) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double h = 0.5 * dt, h12 = dt * dt / 12.0;
+  const double a0 = a[e], j0 = jk[e], an = a1[e], jn = j1[e], v0 = v[e];
+  const double v1 = fma(j0 - jn, h12, fma(a0 + an, h, v0));
+  x[e] = fma(a0 - an, h12, fma(v0 + v1, h, x[e]));
+  v[e] = v1;
+  a[e] = an;
+  jk[e] = jn;
+}
+
 // ---- deterministic reduction of the diagnostics -----------------------
 // Each thread accumulates fixed-stride elements into 9 (hi, lo) TwoSum pairs;
 // the block then combines lanes in a fixed tree order.
@@ -232,6 +260,29 @@ int run_kdk(int64_t n, double* x, double* v, double* a, const double* m, double 
     }
   }
   if (nsteps > 0) return launch_kick(n3, v, a, h, s);
+  return NBODY_OK;
+}
+
+int run_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt, int64_t nsteps,
+                double G, double eps, int precision, bool excl, bool acc_valid, const PairConfig& cfg,
+                hipStream_t s) {
+  const int64_t n3 = 3 * n;
+  int st = NBODY_OK;
+  if (!acc_valid && (st = launch_accel_jerk(n, x, v, m, a, jk, G, eps, precision, excl, cfg, s))) return st;
+  if (nsteps == 0) return NBODY_OK;
+  double* ws = static_cast<double*>(workspace(current_device(), 1, sizeof(double) * 4 * (size_t)n3, &st));
+  if (!ws) return st;
+  double* xp = ws;
+  double* vp = xp + n3;
+  double* a1 = vp + n3;
+  double* j1 = a1 + n3;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hermite_predict_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, x, v, a, jk, dt, xp, vp);
+    NB_LAUNCH_CHECK("hermite_predict_kernel");
+    if ((st = launch_accel_jerk(n, xp, vp, m, a1, j1, G, eps, precision, excl, cfg, s))) return st;
+    hermite_correct_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, x, v, a, jk, a1, j1, dt);
+    NB_LAUNCH_CHECK("hermite_correct_kernel");
+  }
   return NBODY_OK;
 }
 

@@ -375,6 +375,117 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
   }
 }
 
+// ============================================================== acceleration + jerk
+// App. A, Algorithm 3 in full: per pair r_ij, v_ij, t_j = m_j r^-3,
+// A = -3 r^-2, v_r = r_ij . v_ij, q = A v_r; a += t_j r_ij and
+// jerk += t_j (v_ij + q r_ij), with r^2 = |r_ij|^2 + eps^2.  Records carry the
+// position record plus the velocity (FP32C: float-float positions, FP32
+// velocities).  split == 1 writes G*sums to a and jk; split > 1 writes slice
+// y's unscaled 6n partials (a then jerk) at part + y*6n.
+template <int MODE, int IPL, bool EXCL>
+__global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __restrict__ x,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ m, double eps, double G,
+                                                      int chunk, double* __restrict__ a, double* __restrict__ jk,
+                                                      double* __restrict__ part) {
+  using R = Real<MODE>;
+  __shared__ WRec<MODE> tile[2][kTile];
+  const int t = threadIdx.x;
+  const int ibase = blockIdx.x * (kBlock * IPL) + t;
+  const int js = blockIdx.y * chunk;
+  const int je = min(n, js + chunk);
+  const R e2 = (R)(eps * eps);
+
+  IPos<MODE> pi[IPL];
+  R vx[IPL], vy[IPL], vz[IPL];
+  int iidx[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    int i = ibase + k * kBlock;
+    iidx[k] = i;
+    int ic = i < n ? i : n - 1;
+    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+    vx[k] = (R)v[ic]; vy[k] = (R)v[n + ic]; vz[k] = (R)v[2 * n + ic];
+  }
+  R ah[3][IPL], al[3][IPL], jh[3][IPL], jl[3][IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ah[c][k] = al[c][k] = jh[c][k] = jl[c][k] = R(0);
+
+  const int ntiles = (je - js + kTile - 1) / kTile;
+  if (ntiles > 0) tile[0][t] = load_wrec<MODE>(x, m, v, n, js + t, je);
+  __syncthreads();
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int jt = js + tt * kTile;
+    const bool more = tt + 1 < ntiles;
+    WRec<MODE> nxt;
+    if (more) nxt = load_wrec<MODE>(x, m, v, n, jt + kTile + t, je);
+    const WRec<MODE>* cur = tile[tt & 1];
+#pragma unroll 1
+    for (int f = 0; f < kTile; f += kFold) {
+      R pa[3][IPL], pj[3][IPL];
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pa[c][k] = pj[c][k] = R(0);
+#pragma unroll 8
+      for (int jj = f; jj < f + kFold; ++jj) {
+        const WRec<MODE> q = cur[jj];
+        const R mj = jmass(q.r);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          R dx, dy, dz;
+          disp(q.r, pi[k], dx, dy, dz);                     // r_ij
+          const R wx = q.w.x - vx[k], wy = q.w.y - vy[k], wz = q.w.z - vz[k];  // v_ij
+          const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          const R ri = rsq(r2);
+          R ri2 = ri * ri;
+          R tj = (mj * ri) * ri2;                            // t_j = p_w,j r^-3
+          if (EXCL) {
+            const bool self = (jt + jj == iidx[k]);
+            tj = self ? R(0) : tj;
+            ri2 = self ? R(0) : ri2;
+          }
+          const R vr = fma(dz, wz, fma(dy, wy, dx * wx));    // v_r = r . v
+          const R qq = R(-3) * ri2 * vr;                     // q = A v_r, A = -3 r^-2
+          pa[0][k] = fma(tj, dx, pa[0][k]);
+          pa[1][k] = fma(tj, dy, pa[1][k]);
+          pa[2][k] = fma(tj, dz, pa[2][k]);
+          pj[0][k] = fma(tj, fma(qq, dx, wx), pj[0][k]);
+          pj[1][k] = fma(tj, fma(qq, dy, wy), pj[1][k]);
+          pj[2][k] = fma(tj, fma(qq, dz, wz), pj[2][k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          fold(ah[c][k], al[c][k], pa[c][k]);
+          fold(jh[c][k], jl[c][k], pj[c][k]);
+        }
+    }
+    if (more) tile[(tt + 1) & 1][t] = nxt;
+    __syncthreads();
+  }
+
+  const bool direct = gridDim.y == 1;
+  double* oa = direct ? a : part + (size_t)blockIdx.y * 6 * n;
+  double* oj = direct ? jk : oa + 3 * (size_t)n;
+  const double scale = direct ? G : 1.0;
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    const int i = iidx[k];
+    if (i < n) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        oa[c * (size_t)n + i] = scale * ((double)ah[c][k] + (double)al[c][k]);
+        oj[c * (size_t)n + i] = scale * ((double)jh[c][k] + (double)jl[c][k]);
+      }
+    }
+  }
+}
+
 // ============================================================== potential
 // phi_i = sum_{j != i} m_j / sqrt(|d|^2 + eps^2) in FP64, self pair excluded by
 // index.  split == 1: writes phi at out; split > 1: slice y at out + y*n.
@@ -485,7 +596,48 @@ int vjp_dispatch(int64_t n, const double* x, const double* m, const double* w, d
   return NBODY_OK;
 }
 
+template <int MODE, int IPL>
+int jerk_dispatch(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
+                  double eps, bool excl, int split, hipStream_t s) {
+  const int chunk = split_chunk(n, split);
+  const int sp = effective_split(n, split);
+  dim3 grid((unsigned)((n + kBlock * IPL - 1) / (kBlock * IPL)), (unsigned)sp);
+  int st = NBODY_OK;
+  double* part = nullptr;
+  if (sp > 1) {
+    part = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 6 * (size_t)n * sp, &st));
+    if (!part) return st;
+  }
+  if (excl)
+    jerk_kernel<MODE, IPL, true><<<grid, kBlock, 0, s>>>((int)n, x, v, m, eps, G, chunk, a, jk, part);
+  else
+    jerk_kernel<MODE, IPL, false><<<grid, kBlock, 0, s>>>((int)n, x, v, m, eps, G, chunk, a, jk, part);
+  NB_LAUNCH_CHECK("jerk_kernel");
+  if (sp > 1) {
+    const int64_t cnt = 6 * n;
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, a, jk);
+    NB_LAUNCH_CHECK("sum_slices_kernel");
+  }
+  return NBODY_OK;
+}
+
 }  // namespace
+
+int launch_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
+                      double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  const int split = cfg.split < 1 ? 1 : cfg.split;
+  const bool one = cfg.ipl <= 1;
+  switch (precision) {
+    case kFP64: return one ? jerk_dispatch<kFP64, 1>(n, x, v, m, a, jk, G, eps, excl, split, s)
+                           : jerk_dispatch<kFP64, 2>(n, x, v, m, a, jk, G, eps, excl, split, s);
+    case kFP32C: return one ? jerk_dispatch<kFP32C, 1>(n, x, v, m, a, jk, G, eps, excl, split, s)
+                            : jerk_dispatch<kFP32C, 2>(n, x, v, m, a, jk, G, eps, excl, split, s);
+    case kFP32: return one ? jerk_dispatch<kFP32, 1>(n, x, v, m, a, jk, G, eps, excl, split, s)
+                           : jerk_dispatch<kFP32, 2>(n, x, v, m, a, jk, G, eps, excl, split, s);
+  }
+  return set_error(NBODY_EINVAL, "unknown precision");
+}
 
 int launch_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps,
                  int precision, bool excl, const PairConfig& cfg, hipStream_t s) {

@@ -369,3 +369,56 @@ def test_tune_records_a_choice(nb, tmp_path, oracle_mod):
     x, _, m = ics.plummer(n, seed=20)
     a = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp32c").cpu().numpy()
     assert rel_err(a, oracle_mod.accel(x, m, eps=0.01)) <= 1e-5
+
+
+# ---- acceleration + jerk (Algorithm 3) and fourth-order Hermite -------------
+
+@pytest.mark.parametrize("n", [2, 65, 1000, 2049])
+@pytest.mark.parametrize("prec,tola,tolj", [("fp64", 1e-12, 1e-11), ("fp32c", 1e-5, 1e-4)])
+def test_accel_jerk_matches_oracle(nb, oracle_mod, n, prec, tola, tolj):
+    x, v, m = ics.plummer(n, seed=50 + n)
+    ra, rj = oracle_mod.accel_jerk(x, v, m, G=1.1, eps=0.01)
+    a, jk = nb.nbody_accel_jerk(dev(x), dev(v), dev(m), G=1.1, eps=0.01, precision=prec)
+    assert rel_err(a.cpu().numpy(), ra) <= tola
+    assert rel_err(jk.cpu().numpy(), rj) <= tolj
+    # the paper's per-component criterion (0.05 % acceleration, 0.2 % jerk)
+    assert np.all(np.abs(jk.cpu().numpy() - rj) <= 2e-3 * np.abs(rj) + 1e-6 * np.abs(rj).max())
+
+
+def test_accel_jerk_split_configs(nb, oracle_mod):
+    x, v, m = ics.plummer(3001, seed=60)
+    ra, rj = oracle_mod.accel_jerk(x, v, m, eps=0.01)
+    for ipl, split in ((1, 1), (2, 5), (1, 13)):
+        nb.nbody_set_config(ipl=ipl, split=split)
+        try:
+            a, jk = nb.nbody_accel_jerk(dev(x), dev(v), dev(m), eps=0.01, precision="fp64")
+        finally:
+            nb.nbody_set_config()
+        assert rel_err(a.cpu().numpy(), ra) <= 1e-12
+        assert rel_err(jk.cpu().numpy(), rj) <= 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32c", 1e-6)])
+def test_hermite_matches_oracle(nb, oracle_mod, prec, tol):
+    x, v, m = ics.plummer(1024, seed=61)
+    dt, steps, eps = 1.0 / 256, 8, 0.01
+    rx, rv = oracle_mod.hermite4(x, v, m, dt, steps, eps=eps)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta, tj = torch.empty_like(tx), torch.empty_like(tx)
+    nb.nbody_step_hermite(tx, tv, ta, tj, tm, dt, steps, eps=eps, precision=prec)
+    assert np.abs(tx.cpu().numpy() - rx).max() <= tol
+    assert np.abs(tv.cpu().numpy() - rv).max() <= 10 * tol
+
+
+def test_hermite_resumable_bitwise(nb):
+    x, v, m = ics.plummer(700, seed=62)
+    out = []
+    for chunks in ((6,), (2, 4)):
+        tx, tv, tm = dev(x), dev(v), dev(m)
+        ta, tj = torch.empty_like(tx), torch.empty_like(tx)
+        valid = False
+        for c in chunks:
+            nb.nbody_step_hermite(tx, tv, ta, tj, tm, 1.0 / 128, c, eps=0.01, precision="fp32c", acc_valid=valid)
+            valid = True
+        out.append((tx.cpu(), tv.cpu()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
