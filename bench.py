@@ -117,9 +117,10 @@ def bench_force(args, torch, nb):
     a64 = torch.empty_like(tx)
     pairs = float(n) * (n - 1)
 
+    tuned = None
     if args.tune:
-        nb.nbody_tune(n, "fp32c")
-        nb.nbody_tune(n, "fp64")
+        tuned = {p: nb.nbody_tune(n, p, os.path.join(ROOT, "gpurun_out", "tune.jsonl") if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else None) for p in (args.precision, "fp64")}
 
     f32 = lambda: nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
     ms, per, wall = timed(f32, args.steps, args.warmup, torch)
@@ -134,6 +135,8 @@ def bench_force(args, torch, nb):
                       "flop_convention": "20 flops per ordered interaction"},
            "pct_fp32_peak": round(100 * c20_tflops / FP32_PEAK_TFLOPS, 2),
            "wall_ms_timed_region": round(wall, 2)}
+    if tuned:
+        res["tuned"] = tuned
 
     if not args.quick:
         # plain FP64 GPU path
@@ -224,7 +227,7 @@ def bench_ensemble(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     sizes = np.diff(off)
     pairs = float((sizes * (sizes - 1)).sum())
-    nb.nbody_set_config(bsplit=1 if args.no_split else 0)
+    nb.nbody_set_config(bsplit=1 if args.split else 0)
     res = {}
     for prec in (args.precision, "fp64"):
         tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
@@ -240,7 +243,7 @@ def bench_ensemble(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": 1, "split_large_systems": not args.no_split},
+                       "launches": 1, "split_large_systems": bool(args.split)},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),
                           "ms_per_step": round(res["fp64"] / args.steps, 5)}}
@@ -320,7 +323,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="force workload: skip FP64, adjoint and accuracy legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work in the CPU baseline")
-    ap.add_argument("--no-split", action="store_true", help="ensemble: one workgroup per system")
+    ap.add_argument("--split", action="store_true", help="ensemble: split the largest systems over workgroups")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)

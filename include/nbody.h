@@ -150,8 +150,9 @@ int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64
  * work plan built from them is cached, so a repeated call with the same
  * layout enqueues only the launch (and may be captured into a HIP graph).
  * Systems of more than 4096 particles return NBODY_EUNSUPPORTED.  The
- * largest systems may be split over up to 4 workgroups that exchange their
- * positions through global memory every step (see nbody_config.bsplit); if
+ * largest systems may optionally be split over up to 4 workgroups that
+ * exchange their positions through global memory every step
+ * (nbody_config.bsplit = 1); if
  * such an exchange ever waits more than about a second (the GPU shared with
  * other work), that system's x, v and a are set to NaN rather than hanging,
  * which NBODY_CHECK_FINITE reports.  p->eps is ignored; p->precision must be
@@ -188,9 +189,9 @@ int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, c
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
   int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
-  int32_t bsplit;  /* batched kernel: 0 = split systems costlier than the per-CU average
-                      across up to 4 workgroups (they exchange positions every step),
-                      1 = one workgroup per system */
+  int32_t bsplit;  /* batched kernel: 0 = one workgroup per system (default),
+                      1 = split systems costlier than 3/4 of the per-CU average across
+                      up to 4 workgroups that exchange positions every step */
   int32_t reserved;
 } nbody_config;
 

@@ -248,7 +248,8 @@ def nbody_step_hermite(x, v, a, jk, m, dt, nsteps, *, G=1.0, eps, precision="fp3
 
 def nbody_set_config(ipl=0, split=0, bsplit=0):
     """Forces a tile configuration on this thread (all zeros = automatic);
-    bsplit=1 keeps every ensemble system on a single workgroup."""
+    bsplit=1 lets the ensemble kernel split its largest systems over up to 4
+    workgroups (default 0: one workgroup per system)."""
     c = nbody_config(int(ipl), int(split), int(bsplit), 0)
     _check(load().nbody_set_config(ctypes.byref(c)))
 

@@ -120,19 +120,23 @@ void record_tuned(int device, int64_t n, int precision, const PairConfig& c) {
   g_tuned[std::make_tuple(device, precision, n)] = c;
 }
 
-// Default choice: 2 i per lane, and a j-split that gives every CU several
-// rounds of workgroups (so the last round's imbalance stays small) while
-// keeping at least 4 LDS tiles per workgroup.
+// Default j-split: enough workgroups for about 32 rounds of 4 per CU, so the
+// last round's imbalance stays small (the autotuner's choice at N = 2^20 was
+// 32768 workgroups of one i per lane), while keeping at least 2 LDS tiles per
+// workgroup.
 static int auto_split(int64_t n, int ipl, int device) {
   const int64_t iblocks = (n + kBlock * ipl - 1) / (kBlock * ipl);
-  const int64_t target = 24LL * cu_count(device);
-  const int64_t smax = std::max<int64_t>(1, n / (4 * kTile));
+  const int64_t target = 128LL * cu_count(device);
+  const int64_t smax = std::max<int64_t>(1, n / (2 * kTile));
   int64_t s = (target + iblocks - 1) / iblocks;
   return (int)std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(smax, 1024)));
 }
 
 PairConfig choose_config(int64_t n, int precision, int device) {
   PairConfig c;
+  // measured at N = 2^20: one i per lane is fastest for the FP32 pair loops,
+  // four for FP64 (whose rsqrt refinement leaves more latency to hide)
+  c.ipl = precision != NBODY_FP64 ? 1 : (n >= (int64_t(1) << 18) ? 4 : 2);
   const nbody_config& t = t_cfg;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -433,7 +437,7 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
     std::vector<int> splits = {base};
     for (int f : {2, 4}) {
       if (base / f >= 1) splits.push_back(base / f);
-      if ((int64_t)base * f <= std::max<int64_t>(1, std::min<int64_t>(1024, n / (4 * kTile)))) splits.push_back(base * f);
+      if ((int64_t)base * f <= std::max<int64_t>(1, std::min<int64_t>(1024, n / (2 * kTile)))) splits.push_back(base * f);
     }
     std::sort(splits.begin(), splits.end());
     splits.erase(std::unique(splits.begin(), splits.end()), splits.end());

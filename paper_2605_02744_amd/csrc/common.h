@@ -46,7 +46,7 @@ constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
 
 // Per-call configuration of the all-pairs kernels.
 struct PairConfig {
-  int ipl = 2;    // i-particles per lane
+  int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups
 };
 

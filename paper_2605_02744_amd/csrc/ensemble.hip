@@ -5,7 +5,8 @@
 // the FP32 pair modes, 512 for FP64).  An item is a whole system, or one of P
 // equal i-ranges of a system too costly for one CU (the plan splits the
 // largest systems so that no CU carries much more than the average load).
-// For every item and step:
+// Pair arithmetic is that of the single-system kernel (FP32C: rounded-position
+// pairs with the float-float near-field repair).  For every item and step:
 //   1. kick-drift of the owned FP64 state (closing half-kick of the previous
 //      step and opening half-kick of this one, rounded separately as in
 //      nbody_step); the new positions go straight into LDS as pair records;
@@ -90,14 +91,20 @@ struct SysView {
 };
 
 // Accelerations of the item's i-particles (i0 + l + k*gsz, k = kb .. kb+IPL-1)
-// from all records of the system in LDS.
+// from all records of the system in LDS.  FP32C uses the near-field repair of
+// the single-system kernel: pairs from FP32-rounded positions, and a block of
+// kFold j's holding a pair closer than the lane's repair radius is redone with
+// float-float displacements for those pairs.
 template <int MODE, int IPL>
 __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __restrict__ rec,
-                             Part<MODE>* __restrict__ part, Real<MODE> e2, double G, int excl,
+                             Part<MODE>* __restrict__ part, double eps, double G, int excl,
                              double* __restrict__ A) {
   using R = Real<MODE>;
+  constexpr bool kNear = MODE == kFP32C;
+  const R e2 = (R)(eps * eps);
   IPos<MODE> pi[IPL];
   int ii[IPL];
+  R rc2[IPL];
   R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
@@ -105,13 +112,17 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
     const int i = sv.i0 + (il < sv.ni ? il : sv.ni - 1);
     ii[k] = il < sv.ni ? i : -1;
     pi[k].from(rec[i]);
+    if constexpr (kNear) rc2[k] = near_rc2(pi[k].hx, pi[k].hy, pi[k].hz, eps);
     hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = R(0);
   }
   for (int f = sv.j0; f < sv.j1; f += kFold) {
     const int fe = min(sv.j1, f + kFold);
-    R px[IPL], py[IPL], pz[IPL];
+    R px[IPL], py[IPL], pz[IPL], r2min[IPL];
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) px[k] = py[k] = pz[k] = R(0);
+    for (int k = 0; k < IPL; ++k) {
+      px[k] = py[k] = pz[k] = R(0);
+      r2min[k] = R(3.0e38f);
+    }
 #pragma unroll 2
     for (int j = f; j < fe; ++j) {
       const JRec<MODE> r = rec[j];
@@ -119,7 +130,8 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
 #pragma unroll
       for (int k = 0; k < IPL; ++k) {
         R dx, dy, dz;
-        disp(r, pi[k], dx, dy, dz);
+        if constexpr (kNear) disp_hi(r, pi[k], dx, dy, dz);
+        else disp(r, pi[k], dx, dy, dz);
         R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
         R ri = rsq(r2);
         R s = (mj * ri) * (ri * ri);
@@ -127,6 +139,34 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
         px[k] = fma(s, dx, px[k]);
         py[k] = fma(s, dy, py[k]);
         pz[k] = fma(s, dz, pz[k]);
+        if constexpr (kNear) r2min[k] = fminf(r2min[k], r2);
+      }
+    }
+    if constexpr (kNear) {
+#pragma unroll
+      for (int k = 0; k < IPL; ++k) {
+        if (r2min[k] < rc2[k]) {
+          R qx = 0, qy = 0, qz = 0;
+          for (int j = f; j < fe; ++j) {
+            const JRec<MODE> r = rec[j];
+            R dx, dy, dz;
+            disp_hi(r, pi[k], dx, dy, dz);
+            R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+            if (r2 < rc2[k]) {
+              disp(r, pi[k], dx, dy, dz);
+              r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+            }
+            R ri = rsq(r2);
+            R s = (jmass(r) * ri) * (ri * ri);
+            if (excl) s = (j == ii[k]) ? R(0) : s;
+            qx = fma(s, dx, qx);
+            qy = fma(s, dy, qy);
+            qz = fma(s, dz, qz);
+          }
+          px[k] = qx;
+          py[k] = qy;
+          pz[k] = qz;
+        }
       }
     }
 #pragma unroll
@@ -170,19 +210,19 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
 
 template <int MODE>
 __device__ __forceinline__ void system_force_pass(const SysView& sv, int kb, int cnt, const JRec<MODE>* rec,
-                                                  Part<MODE>* part, Real<MODE> e2, double G, int excl, double* A) {
+                                                  Part<MODE>* part, double eps, double G, int excl, double* A) {
   switch (cnt) {
-    case 1: system_force<MODE, 1>(sv, kb, rec, part, e2, G, excl, A); break;
-    case 2: system_force<MODE, 2>(sv, kb, rec, part, e2, G, excl, A); break;
-    case 3: system_force<MODE, 3>(sv, kb, rec, part, e2, G, excl, A); break;
-    default: system_force<MODE, 4>(sv, kb, rec, part, e2, G, excl, A); break;
+    case 1: system_force<MODE, 1>(sv, kb, rec, part, eps, G, excl, A); break;
+    case 2: system_force<MODE, 2>(sv, kb, rec, part, eps, G, excl, A); break;
+    case 3: system_force<MODE, 3>(sv, kb, rec, part, eps, G, excl, A); break;
+    default: system_force<MODE, 4>(sv, kb, rec, part, eps, G, excl, A); break;
   }
 }
 
 template <int MODE>
 __device__ __forceinline__ void system_force_all(const SysView& sv, const JRec<MODE>* rec, Part<MODE>* part,
-                                                 Real<MODE> e2, double G, int excl, double* A) {
-  for (int kb = 0; kb < sv.ipl; kb += kPass) system_force_pass<MODE>(sv, kb, min(kPass, sv.ipl - kb), rec, part, e2, G, excl, A);
+                                                 double eps, double G, int excl, double* A) {
+  for (int kb = 0; kb < sv.ipl; kb += kPass) system_force_pass<MODE>(sv, kb, min(kPass, sv.ipl - kb), rec, part, eps, G, excl, A);
 }
 
 // Publishes this part's records (already in LDS), signals round r, waits for
@@ -231,7 +271,6 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
     double* __restrict__ x, double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m,
     JRec<MODE>* __restrict__ xrec, int* __restrict__ flags, int64_t total, double dt, int64_t nsteps, double G,
     int acc_valid, int excl) {
-  using R = Real<MODE>;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int lds_ok;
   JRec<MODE>* rec = reinterpret_cast<JRec<MODE>*>(smem);
@@ -257,7 +296,7 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
     const int jc = (sv.nc + sv.js - 1) / sv.js;
     sv.j0 = sv.g < sv.js ? min(sv.nc, sv.g * jc) : sv.nc;
     sv.j1 = sv.g < sv.js ? min(sv.nc, sv.j0 + jc) : sv.nc;
-    const R e2 = (R)(epsv[it.sys] * epsv[it.sys]);
+    const double eps = epsv[it.sys];
     Part<MODE>* part = reinterpret_cast<Part<MODE>*>(smem + align16((size_t)sv.nc * sizeof(JRec<MODE>)));
     double* X = x + o;
     double* V = v + o;
@@ -280,7 +319,7 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
         }
       __syncthreads();
       if (split) ok = exchange<MODE>(sv, it, o, rec, xrec, flags, fb, round++, &lds_ok);
-      if (ok) system_force_all<MODE>(sv, rec, part, e2, G, excl, A);
+      if (ok) system_force_all<MODE>(sv, rec, part, eps, G, excl, A);
       __syncthreads();
     }
     for (int64_t s = 0; s < nsteps && ok; ++s) {
@@ -306,7 +345,7 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
         }
       __syncthreads();
       if (split) ok = exchange<MODE>(sv, it, o, rec, xrec, flags, fb, round++, &lds_ok);
-      if (ok) system_force_all<MODE>(sv, rec, part, e2, G, excl, A);
+      if (ok) system_force_all<MODE>(sv, rec, part, eps, G, excl, A);
       __syncthreads();
     }
     if (owner)
@@ -508,7 +547,7 @@ int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, d
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
                 hipStream_t s) {
   const int device = current_device();
-  const bool allow_split = thread_config().bsplit == 0;
+  const bool allow_split = thread_config().bsplit == 1;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   Plan* p = find_plan(ncl, off, eps, precision, device, allow_split);
   if (!p) {

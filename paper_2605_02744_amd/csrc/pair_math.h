@@ -107,4 +107,15 @@ __device__ __forceinline__ float jmass(const JRec<kFP32>& r) { return r.h.w; }
 __device__ __forceinline__ double rsq(double r2) { return rsqrt64(r2); }
 __device__ __forceinline__ float rsq(float r2) { return rsqrt32(r2); }
 
+// Near-field repair of FP32C pairs (see accel_kernel): a pair closer than
+// d_c(i) = max(kNearX |x_i|_inf, kNearEps eps) gets a float-float displacement.
+constexpr float kNearX = 2.0e-2f;
+constexpr float kNearEps = 2.0f;
+
+// Squared repair radius of lane particle i (positions given in double).
+__device__ __forceinline__ float near_rc2(double xa, double ya, double za, double eps) {
+  const float dc = fmaxf(kNearX * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
+  return dc * dc + (float)(eps * eps);
+}
+
 }  // namespace nb

@@ -48,8 +48,6 @@ __device__ __forceinline__ JRec<MODE> load_rec(const double* __restrict__ x, con
 // that lane recomputes the block's partial sum with float-float displacements
 // for those pairs.  Such blocks are rare (a pair closer than a few eps), so the
 // force costs one extra min per pair and keeps float-float accuracy.
-constexpr float kNearX = 2.0e-2f;
-constexpr float kNearEps = 2.0f;
 
 // Grid: (ceil(n / (256*IPL)), split).  Block y handles j in [y*chunk, min(n, (y+1)*chunk)).
 // split == 1: writes G*(hi+lo) to a[c*n+i].  split > 1: writes hi+lo to
@@ -79,8 +77,7 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
     int ic = i < n ? i : n - 1;
     const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
     pi[k].set(xa, ya, za);
-    const float dc = fmaxf(kNearX * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
-    rc2[k] = (R)(dc * dc) + e2;
+    rc2[k] = (R)near_rc2(xa, ya, za, eps);
   }
   R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
 #pragma unroll
@@ -287,8 +284,7 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
     pi[k].set(xa, ya, za);
     mk[k] = (R)m[ic];
     wkx[k] = (R)w[ic]; wky[k] = (R)w[n + ic]; wkz[k] = (R)w[2 * n + ic];
-    const float dc = fmaxf(kNearX * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
-    rc2[k] = (R)(dc * dc) + e2;
+    rc2[k] = (R)near_rc2(xa, ya, za, eps);
   }
   R hx[IPL], hy[IPL], hz[IPL], hm[IPL], lx[IPL], ly[IPL], lz[IPL], lm[IPL];
 #pragma unroll

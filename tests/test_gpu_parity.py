@@ -235,8 +235,12 @@ def test_traj_grad_recompute_matches_forward(nb):
     assert torch.equal(xT, ax) and torch.equal(vT, av)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-9), ("fp32", 1e-7)])
-def test_batched_matches_single_system(nb, prec, tol):
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_batched_matches_single_system(nb, prec):
+    """Every system of a batched run against nbody_step on that system alone:
+    FP64 to 1e-12; the FP32 modes (same pair arithmetic, different summation
+    blocking) against the FP64 single-system run, to FP32 accuracy of the
+    motion over the run."""
     sizes = [1, 64, 100, 300, 513, 1024, 1500, 2500, 4096, 65]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=16, sizes=sizes)
     dt, steps = 1.0 / 512, 7
@@ -248,10 +252,16 @@ def test_batched_matches_single_system(nb, prec, tol):
         s, e = off[c], off[c + 1]
         cx, cv, cm = dev(x[:, s:e]), dev(v[:, s:e]), dev(m[s:e])
         ca = torch.empty_like(cx)
-        nb.nbody_step(cx, cv, ca, cm, dt, steps, eps=float(epsv[c]), precision=prec)
-        dx = np.abs(bx[:, s:e] - cx.cpu().numpy()).max()
-        dv = np.abs(bv[:, s:e] - cv.cpu().numpy()).max()
-        assert dx <= tol and dv <= tol * 100, (c, sizes[c], dx, dv)
+        nb.nbody_step(cx, cv, ca, cm, dt, steps, eps=float(epsv[c]), precision="fp64")
+        rx, rv, ra = cx.cpu().numpy(), cv.cpu().numpy(), ca.cpu().numpy()
+        dx = np.abs(bx[:, s:e] - rx).max()
+        dv = np.abs(bv[:, s:e] - rv).max()
+        if prec == "fp64":
+            assert dx <= 1e-12 and dv <= 1e-12, (c, sizes[c], dx, dv)
+        else:
+            # relative accuracy of the velocity change dt*steps*a and the displacement
+            tol_v = (1e-5 if prec == "fp32c" else 1e-3) * dt * steps * max(np.abs(ra).max(), 1e-30)
+            assert dv <= tol_v and dx <= tol_v * dt * steps, (c, sizes[c], dx, dv, tol_v)
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
@@ -261,7 +271,7 @@ def test_batched_split_and_unsplit_agree(nb, prec):
     sizes = [4096, 3000, 2048, 700, 64, 1]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=21, sizes=sizes)
     out = []
-    for bsplit in (0, 1):
+    for bsplit in (1, 0):
         nb.nbody_set_config(bsplit=bsplit)
         try:
             tx, tv, tm = dev(x), dev(v), dev(m)
