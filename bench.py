@@ -16,7 +16,9 @@ vector peak of the MI355X.
 
 Other workloads (--workload): plummer64k_fp32c (100 KDK steps, N = 65536),
 ensemble512 (512 clusters, 1000 steps in one persistent launch),
-grad16k (forward + adjoint of 200 steps, N = 16384), plummer1k_fp64.
+grad16k (forward + adjoint of 200 steps, N = 16384), plummer1k_fp64 (10 FP64
+steps of N = 1024 with the oracle timed beside it), jerk1m (acceleration + jerk
+at N = 2^20 and Hermite steps at N = 65536).
 """
 from __future__ import annotations
 
@@ -227,7 +229,7 @@ def bench_ensemble(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     sizes = np.diff(off)
     pairs = float((sizes * (sizes - 1)).sum())
-    nb.nbody_set_config(bsplit=1 if args.split else 0)
+    nb.nbody_set_config(bsplit=1 if args.split else 0, bpass=args.bpass)
     res = {}
     for prec in (args.precision, "fp64"):
         tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
@@ -243,7 +245,7 @@ def bench_ensemble(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": 1, "split_large_systems": bool(args.split)},
+                       "launches": 1, "split_large_systems": bool(args.split), "bpass": args.bpass},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),
                           "ms_per_step": round(res["fp64"] / args.steps, 5)}}
@@ -297,6 +299,79 @@ def bench_grad(args, torch, nb):
             "fp64_path": {"fwd_s": out["fp64"]["fwd"], "bwd_s": out["fp64"]["bwd"], "loss": out["fp64"]["loss"]}}
 
 
+def bench_kdk1k(args, torch, nb):
+    """1024-body Plummer sphere, 10 FP64 KDK steps (dt = 1/128): launch-latency
+    bound; reported with the oracle's time for the same run."""
+    import ics
+    import oracle
+    w = ics.WORKLOADS["plummer1k_fp64"]
+    n, eps, dt, steps = w["n"], w["eps"], w["dt"], w["steps"]
+    x, v, m = ics.plummer(n, seed=w["seed"])
+    dev = torch.device("cuda:0")
+    tm = torch.tensor(m, device=dev)
+    tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+    ta = torch.empty_like(tx)
+
+    def run():
+        tx.copy_(torch.tensor(x, device=dev))
+        tv.copy_(torch.tensor(v, device=dev))
+        nb.nbody_step(tx, tv, ta, tm, dt, steps, eps=eps, precision="fp64")
+    ms, _, _ = timed(run, args.steps, args.warmup, torch)
+    t0 = time.perf_counter()
+    rx, rv = oracle.kdk(x, v, m, dt, steps, eps=eps)
+    cpu = time.perf_counter() - t0
+    pairs = float(n) * (n - 1) * (steps + 1)
+    return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "plummer1k_fp64", "n": n, "eps": eps, "dt": dt, "kdk_steps_per_run": steps,
+                       "precision": "fp64"},
+            "max_abs_dx_vs_oracle": float(np.abs(tx.cpu().numpy() - rx).max()),
+            "max_abs_dv_vs_oracle": float(np.abs(tv.cpu().numpy() - rv).max()),
+            "cpu_baseline": {"value": round(pairs / cpu / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(),
+                             "kind": "oracle", "sample": "the whole 10-step run (%.3f s)" % cpu}}
+
+
+def bench_jerk(args, torch, nb):
+    """Acceleration + jerk (App. A, Algorithm 3) of an N = 2^20 Plummer sphere
+    with velocities, FP32C and FP64, and 20 fourth-order Hermite steps of the
+    N = 65536 sphere; each pair evaluation counted once."""
+    import ics
+    n = args.n or (1 << 20)
+    x, v, m = ics.plummer(n, seed=6)
+    dev = torch.device("cuda:0")
+    tx, tv, tm = (torch.tensor(q, device=dev) for q in (x, v, m))
+    pairs = float(n) * (n - 1)
+    out = {}
+    for prec in (args.precision, "fp64"):
+        ms, _, _ = timed(lambda: nb.nbody_accel_jerk(tx, tv, tm, eps=0.001, precision=prec), max(2, args.steps // 3),
+                         1, torch)
+        out[prec] = ms
+    a32, j32 = nb.nbody_accel_jerk(tx, tv, tm, eps=0.001, precision=args.precision)
+    a64, j64 = nb.nbody_accel_jerk(tx, tv, tm, eps=0.001, precision="fp64")
+    ej = rel_err_rows(j32.cpu().numpy(), j64.cpu().numpy())
+    ea = rel_err_rows(a32.cpu().numpy(), a64.cpu().numpy())
+    nh = 65536
+    xh, vh, mh = ics.plummer(nh, seed=2)
+    hx, hv, hm = (torch.tensor(q, device=dev) for q in (xh, vh, mh))
+    ha, hj = torch.empty_like(hx), torch.empty_like(hx)
+    nb.nbody_step_hermite(hx, hv, ha, hj, hm, 1.0 / 256, 0, eps=0.005, precision=args.precision)
+    e0 = nb.nbody_energy(hx, hv, hm, eps=0.005).cpu().numpy()[2]
+    hms, _, _ = timed(lambda: nb.nbody_step_hermite(hx, hv, ha, hj, hm, 1.0 / 256, 1, eps=0.005,
+                                                     precision=args.precision, acc_valid=True), 20, 0, torch)
+    e1 = nb.nbody_energy(hx, hv, hm, eps=0.005).cpu().numpy()[2]
+    ms = out[args.precision]
+    return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
+            "steps": max(2, args.steps // 3), "warmup": 1, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "jerk1m", "n": n, "eps": 0.001, "precision": args.precision},
+            "fp64_path": {"value": round(pairs / (out["fp64"] * 1e-3) / 1e9, 3), "ms_per_eval": round(out["fp64"], 4)},
+            "accuracy": {"accel_max_rel_vs_fp64": float(ea.max()), "jerk_max_rel_vs_fp64": float(ej.max()),
+                         "jerk_p99_rel_vs_fp64": float(np.quantile(ej, 0.99))},
+            "hermite64k": {"ms_per_step": round(hms, 4), "energy_drift_20_steps": float(abs((e1 - e0) / e0)),
+                           "pairs_per_s_g": round(float(nh) * (nh - 1) / (hms * 1e-3) / 1e9, 3)}}
+
+
 def bench_copy(args, torch, nb):
     """A plain device copy of known size, used to calibrate the HBM byte
     counters (FETCH_SIZE / WRITE_SIZE) that price the force kernel's traffic."""
@@ -316,7 +391,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twocomp1m_force",
-                    choices=["twocomp1m_force", "plummer64k_fp32c", "ensemble512", "grad16k", "copy256m"])
+                    choices=["twocomp1m_force", "plummer64k_fp32c", "ensemble512", "grad16k", "copy256m",
+                             "plummer1k_fp64", "jerk1m"])
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="override N of the force workload")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
@@ -324,13 +400,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work in the CPU baseline")
     ap.add_argument("--split", action="store_true", help="ensemble: split the largest systems over workgroups")
+    ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
         args.steps = {"twocomp1m_force": 10, "plummer64k_fp32c": 100, "ensemble512": 1000, "grad16k": 200,
-                      "copy256m": 20}[args.workload]
+                      "copy256m": 20, "plummer1k_fp64": 20, "jerk1m": 6}[args.workload]
 
     import torch
     if not torch.cuda.is_available():
@@ -339,7 +416,8 @@ def main():
     import paper_2605_02744_amd as nb
     nb.load()
     fn = {"twocomp1m_force": bench_force, "plummer64k_fp32c": bench_kdk64k, "ensemble512": bench_ensemble,
-          "grad16k": bench_grad, "copy256m": bench_copy}[args.workload]
+          "grad16k": bench_grad, "copy256m": bench_copy, "plummer1k_fp64": bench_kdk1k,
+          "jerk1m": bench_jerk}[args.workload]
     res = fn(args, torch, nb)
     print(json.dumps(res), flush=True)
 

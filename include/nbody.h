@@ -192,7 +192,8 @@ typedef struct nbody_config {
   int32_t bsplit;  /* batched kernel: 0 = one workgroup per system (default),
                       1 = split systems costlier than 3/4 of the per-CU average across
                       up to 4 workgroups that exchange positions every step */
-  int32_t reserved;
+  int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
+                      pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros

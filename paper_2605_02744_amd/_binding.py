@@ -47,7 +47,7 @@ class nbody_params(ctypes.Structure):
 
 class nbody_config(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("bsplit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32)]
 
 
 _lib = None
@@ -246,11 +246,12 @@ def nbody_step_hermite(x, v, a, jk, m, dt, nsteps, *, G=1.0, eps, precision="fp3
     return x, v, a, jk
 
 
-def nbody_set_config(ipl=0, split=0, bsplit=0):
+def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0):
     """Forces a tile configuration on this thread (all zeros = automatic);
     bsplit=1 lets the ensemble kernel split its largest systems over up to 4
-    workgroups (default 0: one workgroup per system)."""
-    c = nbody_config(int(ipl), int(split), int(bsplit), 0)
+    workgroups (default 0: one workgroup per system); bpass sets how many of
+    a lane's i-particles the ensemble kernel evaluates per pass (1, 2, 4)."""
+    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass))
     _check(load().nbody_set_config(ctypes.byref(c)))
 
 

@@ -391,6 +391,8 @@ int nbody_set_config(const nbody_config* cfg) {
     return set_error(NBODY_EINVAL, "ipl must be 0, 1, 2 or 4");
   if (cfg->split < 0 || cfg->split > 1024) return set_error(NBODY_EINVAL, "split must be in 0..1024");
   if (cfg->bsplit != 0 && cfg->bsplit != 1) return set_error(NBODY_EINVAL, "bsplit must be 0 or 1");
+  if (cfg->bpass != 0 && cfg->bpass != 1 && cfg->bpass != 2 && cfg->bpass != 4)
+    return set_error(NBODY_EINVAL, "bpass must be 0, 1, 2 or 4");
   set_thread_config(*cfg);
   return NBODY_OK;
 }

@@ -36,7 +36,7 @@ namespace {
 template <int MODE> constexpr int ens_block() { return MODE == kFP64 ? 512 : 1024; }
 template <int MODE> constexpr int ens_max_ipl() { return MODE == kFP64 ? 8 : 4; }
 constexpr int kMaxSys = 4096;            // particles per system
-constexpr int kPass = 4;                 // i-particles evaluated together in one pass over j
+constexpr int kPass = 4;                 // most i-particles evaluated together in one pass over j
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kSpinLimit = 1 << 21;      // polls of a partner flag before giving up (~1 s)
 
@@ -220,9 +220,12 @@ __device__ __forceinline__ void system_force_pass(const SysView& sv, int kb, int
 }
 
 template <int MODE>
-__device__ __forceinline__ void system_force_all(const SysView& sv, const JRec<MODE>* rec, Part<MODE>* part,
-                                                 double eps, double G, int excl, double* A) {
-  for (int kb = 0; kb < sv.ipl; kb += kPass) system_force_pass<MODE>(sv, kb, min(kPass, sv.ipl - kb), rec, part, eps, G, excl, A);
+__device__ __forceinline__ void system_force_all(const SysView& sv, int pass, const JRec<MODE>* rec,
+                                                 Part<MODE>* part, double eps, double G, int excl, double* A) {
+  // with a j-split (js > 1) all of the lane's i-particles go in one pass, as
+  // the LDS reduction of the groups' partial sums expects
+  const int w = sv.js > 1 ? kPass : pass;
+  for (int kb = 0; kb < sv.ipl; kb += w) system_force_pass<MODE>(sv, kb, min(w, sv.ipl - kb), rec, part, eps, G, excl, A);
 }
 
 // Publishes this part's records (already in LDS), signals round r, waits for
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
     const int* __restrict__ flag_base, const int* __restrict__ wg_off, const int* __restrict__ wg_list,
     double* __restrict__ x, double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m,
     JRec<MODE>* __restrict__ xrec, int* __restrict__ flags, int64_t total, double dt, int64_t nsteps, double G,
-    int acc_valid, int excl) {
+    int acc_valid, int excl, int pass) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int lds_ok;
   JRec<MODE>* rec = reinterpret_cast<JRec<MODE>*>(smem);
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
         }
       __syncthreads();
       if (split) ok = exchange<MODE>(sv, it, o, rec, xrec, flags, fb, round++, &lds_ok);
-      if (ok) system_force_all<MODE>(sv, rec, part, eps, G, excl, A);
+      if (ok) system_force_all<MODE>(sv, pass, rec, part, eps, G, excl, A);
       __syncthreads();
     }
     for (int64_t s = 0; s < nsteps && ok; ++s) {
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(ens_block<MODE>()) void ensemble_kernel(
         }
       __syncthreads();
       if (split) ok = exchange<MODE>(sv, it, o, rec, xrec, flags, fb, round++, &lds_ok);
-      if (ok) system_force_all<MODE>(sv, rec, part, eps, G, excl, A);
+      if (ok) system_force_all<MODE>(sv, pass, rec, part, eps, G, excl, A);
       __syncthreads();
     }
     if (owner)
@@ -528,6 +531,7 @@ Plan* find_plan(int32_t ncl, const int64_t* off, const double* eps, int precisio
 template <int MODE>
 int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
                 double G, bool acc_valid, bool excl, hipStream_t s) {
+  const int pass = thread_config().bpass > 0 ? thread_config().bpass : kPass;
   NB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel<MODE>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds));
   if (p->nflags > 0) {
@@ -536,7 +540,8 @@ int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m,
   }
   ensemble_kernel<MODE><<<p->nwg, ens_block<MODE>(), p->lds, s>>>(
       p->d_off, p->d_eps, p->d_items, p->d_flag_base, p->d_wg_off, p->d_wg_list, x, v, a, m,
-      static_cast<JRec<MODE>*>(p->d_xrec), p->d_flags, p->total, dt, nsteps, G, acc_valid ? 1 : 0, excl ? 1 : 0);
+      static_cast<JRec<MODE>*>(p->d_xrec), p->d_flags, p->total, dt, nsteps, G, acc_valid ? 1 : 0, excl ? 1 : 0,
+      pass);
   NB_LAUNCH_CHECK("ensemble_kernel");
   return NBODY_OK;
 }

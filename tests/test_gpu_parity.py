@@ -284,6 +284,30 @@ def test_batched_split_and_unsplit_agree(nb, prec):
     assert np.abs(out[0][1] - out[1][1]).max() <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_batched_pass_widths_agree(nb, prec):
+    """Evaluating 1, 2 or 4 of a lane's i-particles per pass over the records
+    changes only which j-blocks the near-field repair revisits."""
+    sizes = [4096, 1500, 333, 64]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=22, sizes=sizes)
+    out = []
+    for bpass in (0, 1, 2):
+        nb.nbody_set_config(bpass=bpass)
+        try:
+            tx, tv, tm = dev(x), dev(v), dev(m)
+            ta = torch.empty_like(tx)
+            nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 4, precision=prec, check_finite=True)
+        finally:
+            nb.nbody_set_config()
+        out.append((tx.cpu().numpy(), tv.cpu().numpy()))
+    for k in (1, 2):
+        if prec == "fp64":
+            assert np.array_equal(out[0][0], out[k][0]) and np.array_equal(out[0][1], out[k][1])
+        else:
+            assert np.abs(out[0][0] - out[k][0]).max() <= 1e-10
+            assert np.abs(out[0][1] - out[k][1]).max() <= 1e-8
+
+
 def test_batched_matches_oracle_fp64(nb, oracle_mod):
     sizes = [5, 80, 700]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=17, sizes=sizes)
