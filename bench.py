@@ -230,15 +230,28 @@ def bench_ensemble(args, torch, nb):
     sizes = np.diff(off)
     pairs = float((sizes * (sizes - 1)).sum())
     nb.nbody_set_config(bsplit=1 if args.split else 0, bpass=args.bpass)
-    res = {}
+    res, drift = {}, {}
+
+    def energies(tx, tv):
+        # per-cluster total energy E_c (FP64 diagnostics on the GPU), untimed
+        out = []
+        for c in range(len(sizes)):
+            s, e = int(off[c]), int(off[c + 1])
+            out.append(nb.nbody_energy(tx[:, s:e].contiguous(), tv[:, s:e].contiguous(), tm[s:e],
+                                       eps=float(epsv[c]))[2])
+        return torch.stack(out).cpu().numpy()
+
     for prec in (args.precision, "fp64"):
         tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
         ta = torch.empty_like(tx)
+        e0 = energies(tx, tv)
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=prec)  # plan + a(x)
         steps = args.steps
         ms, _, _ = timed(lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], steps, precision=prec,
                                                        acc_valid=True), 1, 0, torch)
         res[prec] = ms
+        rel = np.abs((energies(tx, tv) - e0) / e0)
+        drift[prec] = {"max": float(rel.max()), "median": float(np.median(rel))}
     ms = res[args.precision]
     return {"metric": METRIC, "value": round(pairs * args.steps / (ms * 1e-3) / 1e9, 3), "unit": UNIT,
             "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": round(ms / args.steps, 5),
@@ -247,6 +260,7 @@ def bench_ensemble(args, torch, nb):
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
                        "launches": 1, "split_large_systems": bool(args.split), "bpass": args.bpass},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
+            "energy_drift_per_cluster": drift,
             "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),
                           "ms_per_step": round(res["fp64"] / args.steps, 5)}}
 

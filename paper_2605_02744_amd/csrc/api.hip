@@ -127,7 +127,9 @@ void record_tuned(int device, int64_t n, int precision, const PairConfig& c) {
 static int auto_split(int64_t n, int ipl, int device) {
   const int64_t iblocks = (n + kBlock * ipl - 1) / (kBlock * ipl);
   const int64_t target = 128LL * cu_count(device);
-  const int64_t smax = std::max<int64_t>(1, n / (2 * kTile));
+  // slices of at least two tiles, or of one fold block for small systems whose
+  // i-blocks alone cannot fill the chip
+  const int64_t smax = std::max<int64_t>(1, n / (n < (int64_t(1) << 14) ? kFold : 2 * kTile));
   int64_t s = (target + iblocks - 1) / iblocks;
   return (int)std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(smax, 1024)));
 }
@@ -135,8 +137,9 @@ static int auto_split(int64_t n, int ipl, int device) {
 PairConfig choose_config(int64_t n, int precision, int device) {
   PairConfig c;
   // measured at N = 2^20: one i per lane is fastest for the FP32 pair loops,
-  // four for FP64 (whose rsqrt refinement leaves more latency to hide)
-  c.ipl = precision != NBODY_FP64 ? 1 : (n >= (int64_t(1) << 18) ? 4 : 2);
+  // four for FP64 (whose rsqrt refinement leaves more latency to hide); fewer
+  // for smaller FP64 systems so that they still spread over many workgroups
+  c.ipl = precision != NBODY_FP64 ? 1 : (n >= (int64_t(1) << 18) ? 4 : (n >= (int64_t(1) << 14) ? 2 : 1));
   const nbody_config& t = t_cfg;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

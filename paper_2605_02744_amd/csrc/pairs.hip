@@ -88,6 +88,8 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
   __syncthreads();
   for (int tt = 0; tt < ntiles; ++tt) {
     const int jt = js + tt * kTile;
+    // records past je are zero-mass padding: skip whole fold blocks of them
+    const int fend = min(kTile, (je - jt + kFold - 1) / kFold * kFold);
     const bool more = tt + 1 < ntiles;
     // prefetch the next tile's FP64 values while this tile is consumed
     double nx = 0, ny = 0, nz = 0, nm = 0;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
     if (more && jn < je) { nx = x[jn]; ny = x[n + jn]; nz = x[2 * n + jn]; nm = m[jn]; }
     const JRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
-    for (int f = 0; f < kTile; f += kFold) {
+    for (int f = 0; f < fend; f += kFold) {
       R px[IPL], py[IPL], pz[IPL], r2min[IPL];
 #pragma unroll
       for (int k = 0; k < IPL; ++k) {
@@ -295,12 +297,14 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
   __syncthreads();
   for (int tt = 0; tt < ntiles; ++tt) {
     const int jt = js + tt * kTile;
+    // records past je are zero-mass padding: skip whole fold blocks of them
+    const int fend = min(kTile, (je - jt + kFold - 1) / kFold * kFold);
     const bool more = tt + 1 < ntiles;
     WRec<MODE> nxt;
     if (more) nxt = load_wrec<MODE>(x, m, w, n, jt + kTile + t, je);
     const WRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
-    for (int f = 0; f < kTile; f += kFold) {
+    for (int f = 0; f < fend; f += kFold) {
       R px[IPL], py[IPL], pz[IPL], pm[IPL], r2min[IPL];
 #pragma unroll
       for (int k = 0; k < IPL; ++k) {
@@ -414,12 +418,14 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
   __syncthreads();
   for (int tt = 0; tt < ntiles; ++tt) {
     const int jt = js + tt * kTile;
+    // records past je are zero-mass padding: skip whole fold blocks of them
+    const int fend = min(kTile, (je - jt + kFold - 1) / kFold * kFold);
     const bool more = tt + 1 < ntiles;
     WRec<MODE> nxt;
     if (more) nxt = load_wrec<MODE>(x, m, v, n, jt + kTile + t, je);
     const WRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
-    for (int f = 0; f < kTile; f += kFold) {
+    for (int f = 0; f < fend; f += kFold) {
       R pa[3][IPL], pj[3][IPL];
 #pragma unroll
       for (int k = 0; k < IPL; ++k)
@@ -506,12 +512,14 @@ __global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* 
   __syncthreads();
   for (int tt = 0; tt < ntiles; ++tt) {
     const int jt = js + tt * kTile;
+    // records past je are zero-mass padding: skip whole fold blocks of them
+    const int fend = min(kTile, (je - jt + kFold - 1) / kFold * kFold);
     const bool more = tt + 1 < ntiles;
     double4 nxt = make_double4(0, 0, 0, 0);
     if (more) nxt = ld(jt + kTile + t);
     const double4* cur = tile[tt & 1];
 #pragma unroll 1
-    for (int f = 0; f < kTile; f += kFold) {
+    for (int f = 0; f < fend; f += kFold) {
       double p = 0;
 #pragma unroll 8
       for (int jj = f; jj < f + kFold; ++jj) {
@@ -530,10 +538,12 @@ __global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* 
 }
 
 // ============================================================== launch helpers
+// j-slices are whole fold blocks (64 records), so that small systems can be
+// spread over more workgroups than they have 256-record tiles
 inline int split_chunk(int64_t n, int split) {
   int64_t c = (n + split - 1) / split;
-  c = (c + kTile - 1) / kTile * kTile;
-  return (int)(c > 0 ? c : kTile);
+  c = (c + kFold - 1) / kFold * kFold;
+  return (int)(c > 0 ? c : kFold);
 }
 inline int effective_split(int64_t n, int split) {
   int chunk = split_chunk(n, split);
