@@ -52,6 +52,11 @@ def _load():
                                            ctypes.c_double, _I64, _D, _D, _D, _D, _D]
         lib.oracle_accel_jerk.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D, _D]
         lib.oracle_hermite4.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I64]
+        lib.oracle_accel_jerk_snap.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D, _D, _D]
+        lib.oracle_accel_jerk_snap_rows.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _I64,
+                                                    ctypes.POINTER(ctypes.c_int64), _D, _D, _D]
+        lib.oracle_hermite6_crackle.argtypes = [_I64, ctypes.c_double, _D, _D, _D, _D, _D, _D, _D]
+        lib.oracle_hermite6.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I64]
         lib.oracle_msd_loss.argtypes = [_I64, _D, _D]
         lib.oracle_msd_loss.restype = ctypes.c_double
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -195,6 +200,48 @@ def hermite4(x, v, m, dt, nsteps, G=1.0, eps=0.0):
     x = _c(x, (3, n)).copy()
     v = _c(v, (3, n)).copy()
     _load().oracle_hermite4(n, _p(x), _p(v), _p(m), float(G), float(eps), float(dt), int(nsteps))
+    return x, v
+
+
+def accel_jerk_snap(x, v, acc, m, G=1.0, eps=0.0):
+    """(a, jerk, snap), each (3, N), along paths of constant acceleration acc."""
+    m = _c(m)
+    n = m.shape[0]
+    x, v, acc = _c(x, (3, n)), _c(v, (3, n)), _c(acc, (3, n))
+    a, jk, sn = np.empty((3, n)), np.empty((3, n)), np.empty((3, n))
+    _load().oracle_accel_jerk_snap(n, _p(x), _p(v), _p(acc), _p(m), float(G), float(eps), _p(a), _p(jk), _p(sn))
+    return a, jk, sn
+
+
+def accel_jerk_snap_rows(x, v, acc, m, rows, G=1.0, eps=0.0):
+    """The listed rows of ``accel_jerk_snap``, each (3, len(rows))."""
+    m = _c(m)
+    n = m.shape[0]
+    x, v, acc = _c(x, (3, n)), _c(v, (3, n)), _c(acc, (3, n))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if rows.size and (rows.min() < 0 or rows.max() >= n):
+        raise ValueError("row index out of range")
+    a, jk, sn = (np.empty((3, rows.size)) for _ in range(3))
+    _load().oracle_accel_jerk_snap_rows(n, _p(x), _p(v), _p(acc), _p(m), float(G), float(eps), rows.size,
+                                        rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(a), _p(jk), _p(sn))
+    return a, jk, sn
+
+
+def hermite6_crackle(h, a0, j0, s0, a1, j1, s1):
+    """Third derivative at t = h of the quintic through (a, jerk, snap) at 0 and h."""
+    arrs = [_c(q) for q in (a0, j0, s0, a1, j1, s1)]
+    out = np.empty_like(arrs[0])
+    _load().oracle_hermite6_crackle(out.size, float(h), *[_p(q) for q in arrs], _p(out))
+    return out
+
+
+def hermite6(x, v, m, dt, nsteps, G=1.0, eps=0.0):
+    """Sixth-order Hermite predictor-evaluator-corrector; returns (x, v)."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n)).copy()
+    v = _c(v, (3, n)).copy()
+    _load().oracle_hermite6(n, _p(x), _p(v), _p(m), float(G), float(eps), float(dt), int(nsteps))
     return x, v
 
 

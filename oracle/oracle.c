@@ -31,7 +31,13 @@
  *     acceleration along the motion;
  *   - Hermite: the fourth-order predictor-evaluator-corrector with a shared
  *     time step (Sec. 2.1 describes the sixth-order member of this family:
- *     predict, evaluate acceleration and jerk, correct).
+ *     predict, evaluate acceleration and jerk, correct);
+ *   - sixth-order Hermite (Sec. 2.1, after the scheme of Nitadori & Makino
+ *     2008 that the paper cites): the evaluation also returns the snap, the
+ *     second time derivative of the softened acceleration along paths of
+ *     constant acceleration, and the predictor uses the crackle of the
+ *     quintic that interpolates a, jerk and snap at both ends of the
+ *     previous step (zero before the first step).
  */
 #include <math.h>
 #include <stdint.h>
@@ -352,6 +358,144 @@ void oracle_hermite4(int64_t n, double* x, double* v, const double* m, double G,
         }
     }
     free(a0); free(j0); free(a1); free(j1); free(xp); free(vp);
+}
+
+/* ---- acceleration, jerk and snap (sixth-order Hermite, Sec. 2.1) --------
+ * Each particle moves on x_k(t) = x_k + v_k t + acc_k t^2 / 2.  The pair term
+ * P(t) = m_j d / s^(3/2), d = x_j - x_i, s = |d|^2 + eps^2, has at t = 0, with
+ * w = v_j - v_i and u = acc_j - acc_i,
+ *   t_j   = m_j s^(-3/2)
+ *   alpha = (d . w) / s
+ *   beta  = (w . w + d . u) / s + alpha^2
+ *   P     = t_j d
+ *   P'    = t_j w - 3 alpha P                 (the jerk term of Algorithm 3)
+ *   P''   = t_j u - 6 alpha P' - 3 beta P
+ * (differentiate t_j' = -3 alpha t_j and alpha' = (w.w + d.u)/s - 2 alpha^2).
+ * a, jerk and snap are G times the sums of P, P' and P'' over j != i. */
+static void accel_jerk_snap_row(int64_t n, const double* x, const double* v, const double* acc,
+                                const double* m, double G, double eps, int64_t i, double* a, double* jk,
+                                double* sn) {
+    nsum sa[3] = {{0, 0}, {0, 0}, {0, 0}}, sj[3] = {{0, 0}, {0, 0}, {0, 0}}, ss[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double d[3], w[3], u[3];
+        for (int c = 0; c < 3; ++c) {
+            d[c] = x[c * n + j] - x[c * n + i];
+            w[c] = v[c * n + j] - v[c * n + i];
+            u[c] = acc[c * n + j] - acc[c * n + i];
+        }
+        double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+        double sinv = 1.0 / s2;
+        double t = m[j] * sinv / sqrt(s2);
+        double alpha = (d[0] * w[0] + d[1] * w[1] + d[2] * w[2]) * sinv;
+        double beta = (w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + d[0] * u[0] + d[1] * u[1] + d[2] * u[2]) * sinv +
+                      alpha * alpha;
+        for (int c = 0; c < 3; ++c) {
+            double P0 = t * d[c];
+            double P1 = t * w[c] - 3.0 * alpha * P0;
+            double P2 = t * u[c] - 6.0 * alpha * P1 - 3.0 * beta * P0;
+            nadd(&sa[c], P0);
+            nadd(&sj[c], P1);
+            nadd(&ss[c], P2);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        a[c] = G * nval(&sa[c]);
+        jk[c] = G * nval(&sj[c]);
+        sn[c] = G * nval(&ss[c]);
+    }
+}
+
+void oracle_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
+                            double G, double eps, double* a, double* jk, double* sn) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double ai[3], ji[3], si[3];
+        accel_jerk_snap_row(n, x, v, acc, m, G, eps, i, ai, ji, si);
+        for (int c = 0; c < 3; ++c) {
+            a[c * n + i] = ai[c];
+            jk[c * n + i] = ji[c];
+            sn[c * n + i] = si[c];
+        }
+    }
+}
+
+/* The listed rows of oracle_accel_jerk_snap, out arrays of shape (3, nrows). */
+void oracle_accel_jerk_snap_rows(int64_t n, const double* x, const double* v, const double* acc, const double* m,
+                                 double G, double eps, int64_t nrows, const int64_t* rows, double* a, double* jk,
+                                 double* sn) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nrows; ++r) {
+        double ai[3], ji[3], si[3];
+        accel_jerk_snap_row(n, x, v, acc, m, G, eps, rows[r], ai, ji, si);
+        for (int c = 0; c < 3; ++c) {
+            a[c * nrows + r] = ai[c];
+            jk[c * nrows + r] = ji[c];
+            sn[c * nrows + r] = si[c];
+        }
+    }
+}
+
+/* Third derivative at the end t = h of the quintic q(t) with q(0) = a0,
+ * q'(0) = j0, q''(0) = s0, q(h) = a1, q'(h) = j1, q''(h) = s1.  Writing
+ * q = a0 + j0 t + s0 t^2/2 + k3 t^3 + k4 t^4 + k5 t^5 and
+ *   A = (a1 - a0 - j0 h - s0 h^2/2) / h^3 = k3 + k4 h + k5 h^2
+ *   B = (j1 - j0 - s0 h) / h^2             = 3 k3 + 4 k4 h + 5 k5 h^2
+ *   C = (s1 - s0) / h                      = 6 k3 + 12 k4 h + 20 k5 h^2,
+ * the solution k3 = 10A - 4B + C/2, k4 h = 7B - 15A - C, k5 h^2 = (C + 12A - 6B)/2
+ * gives q'''(h) = 6 k3 + 24 k4 h + 60 k5 h^2 = 60 A - 36 B + 9 C. */
+void oracle_hermite6_crackle(int64_t cnt, double h, const double* a0, const double* j0, const double* s0,
+                             const double* a1, const double* j1, const double* s1, double* c1) {
+    for (int64_t k = 0; k < cnt; ++k) {
+        double A = (a1[k] - a0[k] - j0[k] * h - s0[k] * (h * h / 2.0)) / (h * h * h);
+        double B = (j1[k] - j0[k] - s0[k] * h) / (h * h);
+        double C = (s1[k] - s0[k]) / h;
+        c1[k] = 60.0 * A - 36.0 * B + 9.0 * C;
+    }
+}
+
+/* Sixth-order Hermite predictor-evaluator-corrector, shared step h = dt:
+ *   predict  xp = x + v h + a h^2/2 + j h^3/6 + s h^4/24 + c h^5/120
+ *            vp = v + a h + j h^2/2 + s h^3/6 + c h^4/24
+ *            ap = a + j h + s h^2/2 + c h^3/6
+ *   evaluate a1, j1, s1 at (xp, vp, ap)
+ *   correct  v1 = v + (a + a1) h/2 - (j1 - j) h^2/10 + (s + s1) h^3/120
+ *            x1 = x + (v + v1) h/2 - (a1 - a) h^2/10 + (j + j1) h^3/120
+ *   crackle  c1 from oracle_hermite6_crackle
+ * Start: a, j at (x, v) (Algorithm 3), then a, j, s at (x, v, a); c = 0.
+ * (x, v) advance in place by nsteps steps. */
+void oracle_hermite6(int64_t n, double* x, double* v, const double* m, double G, double eps, double dt,
+                     int64_t nsteps) {
+    const int64_t n3 = 3 * n;
+    const size_t nb = sizeof(double) * (size_t)(n3 > 0 ? n3 : 1);
+    double *a = (double*)malloc(nb), *j = (double*)malloc(nb), *s = (double*)malloc(nb), *c = (double*)malloc(nb);
+    double *a1 = (double*)malloc(nb), *j1 = (double*)malloc(nb), *s1 = (double*)malloc(nb);
+    double *xp = (double*)malloc(nb), *vp = (double*)malloc(nb), *ap = (double*)malloc(nb);
+    const double h = dt;
+    oracle_accel_jerk(n, x, v, m, G, eps, a1, j1);
+    oracle_accel_jerk_snap(n, x, v, a1, m, G, eps, a, j, s);
+    for (int64_t k = 0; k < n3; ++k) c[k] = 0.0;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        for (int64_t k = 0; k < n3; ++k) {
+            xp[k] = x[k] + v[k] * h + a[k] * (h * h / 2.0) + j[k] * (h * h * h / 6.0) +
+                    s[k] * (h * h * h * h / 24.0) + c[k] * (h * h * h * h * h / 120.0);
+            vp[k] = v[k] + a[k] * h + j[k] * (h * h / 2.0) + s[k] * (h * h * h / 6.0) + c[k] * (h * h * h * h / 24.0);
+            ap[k] = a[k] + j[k] * h + s[k] * (h * h / 2.0) + c[k] * (h * h * h / 6.0);
+        }
+        oracle_accel_jerk_snap(n, xp, vp, ap, m, G, eps, a1, j1, s1);
+        oracle_hermite6_crackle(n3, h, a, j, s, a1, j1, s1, c);
+        for (int64_t k = 0; k < n3; ++k) {
+            double v1 = v[k] + (a[k] + a1[k]) * (h / 2.0) - (j1[k] - j[k]) * (h * h / 10.0) +
+                        (s[k] + s1[k]) * (h * h * h / 120.0);
+            x[k] = x[k] + (v[k] + v1) * (h / 2.0) - (a1[k] - a[k]) * (h * h / 10.0) +
+                   (j[k] + j1[k]) * (h * h * h / 120.0);
+            v[k] = v1;
+            a[k] = a1[k];
+            j[k] = j1[k];
+            s[k] = s1[k];
+        }
+    }
+    free(a); free(j); free(s); free(c); free(a1); free(j1); free(s1); free(xp); free(vp); free(ap);
 }
 
 /* Mean squared distance of positions to a target: (1/N) sum_i |x_i - t_i|^2. */

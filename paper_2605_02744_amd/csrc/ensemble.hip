@@ -95,9 +95,9 @@ struct SysView {
 // the single-system kernel: pairs from FP32-rounded positions, and a block of
 // kFold j's holding a pair closer than the lane's repair radius is redone with
 // float-float displacements for those pairs.
-template <int MODE, int IPL>
+template <int MODE, int IPL, bool EXCL>
 __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __restrict__ rec,
-                             Part<MODE>* __restrict__ part, double eps, double G, int excl,
+                             Part<MODE>* __restrict__ part, double eps, double G,
                              double* __restrict__ A) {
   using R = Real<MODE>;
   constexpr bool kNear = MODE == kFP32C;
@@ -135,7 +135,7 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
         R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
         R ri = rsq(r2);
         R s = (mj * ri) * (ri * ri);
-        if (excl) s = (j == ii[k]) ? R(0) : s;
+        if constexpr (EXCL) s = (j == ii[k]) ? R(0) : s;
         px[k] = fma(s, dx, px[k]);
         py[k] = fma(s, dy, py[k]);
         pz[k] = fma(s, dz, pz[k]);
@@ -145,7 +145,19 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
     if constexpr (kNear) {
 #pragma unroll
       for (int k = 0; k < IPL; ++k) {
-        if (r2min[k] < rc2[k]) {
+        // the lane's own pair (zero displacement) always sets r2min = eps^2:
+        // in the block holding it, rescan for a close pair other than that one
+        bool close = r2min[k] < rc2[k];
+        if (close && ii[k] >= f && ii[k] < fe) {
+          close = false;
+          for (int j = f; j < fe; ++j) {
+            R dx, dy, dz;
+            disp_hi(rec[j], pi[k], dx, dy, dz);
+            const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+            close = close || (r2 < rc2[k] && j != ii[k]);
+          }
+        }
+        if (close) {
           R qx = 0, qy = 0, qz = 0;
           for (int j = f; j < fe; ++j) {
             const JRec<MODE> r = rec[j];
@@ -158,7 +170,7 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
             }
             R ri = rsq(r2);
             R s = (jmass(r) * ri) * (ri * ri);
-            if (excl) s = (j == ii[k]) ? R(0) : s;
+            if constexpr (EXCL) s = (j == ii[k]) ? R(0) : s;
             qx = fma(s, dx, qx);
             qy = fma(s, dy, qy);
             qz = fma(s, dz, qz);
@@ -211,11 +223,22 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
 template <int MODE>
 __device__ __forceinline__ void system_force_pass(const SysView& sv, int kb, int cnt, const JRec<MODE>* rec,
                                                   Part<MODE>* part, double eps, double G, int excl, double* A) {
-  switch (cnt) {
-    case 1: system_force<MODE, 1>(sv, kb, rec, part, eps, G, excl, A); break;
-    case 2: system_force<MODE, 2>(sv, kb, rec, part, eps, G, excl, A); break;
-    case 3: system_force<MODE, 3>(sv, kb, rec, part, eps, G, excl, A); break;
-    default: system_force<MODE, 4>(sv, kb, rec, part, eps, G, excl, A); break;
+  // the self-pair mask costs two instructions per pair: compiled in only for
+  // eps = 0, where the zero-displacement self pair would give 0 * inf
+  if (excl) {
+    switch (cnt) {
+      case 1: system_force<MODE, 1, true>(sv, kb, rec, part, eps, G, A); break;
+      case 2: system_force<MODE, 2, true>(sv, kb, rec, part, eps, G, A); break;
+      case 3: system_force<MODE, 3, true>(sv, kb, rec, part, eps, G, A); break;
+      default: system_force<MODE, 4, true>(sv, kb, rec, part, eps, G, A); break;
+    }
+  } else {
+    switch (cnt) {
+      case 1: system_force<MODE, 1, false>(sv, kb, rec, part, eps, G, A); break;
+      case 2: system_force<MODE, 2, false>(sv, kb, rec, part, eps, G, A); break;
+      case 3: system_force<MODE, 3, false>(sv, kb, rec, part, eps, G, A); break;
+      default: system_force<MODE, 4, false>(sv, kb, rec, part, eps, G, A); break;
+    }
   }
 }
 
@@ -415,9 +438,11 @@ bool upload(T** dst, const std::vector<T>& src) {
   return src.empty() || hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) == hipSuccess;
 }
 
-// Builds the work plan: systems whose cost exceeds 3/4 of the per-CU average
-// are split into P <= 4 parts (at most one split item per workgroup, placed
-// first in its list); everything else is assigned longest-processing-time first.
+// Builds the work plan.  With splitting allowed, a system whose cost exceeds
+// the per-CU average T is split into P = ceil(cost / T) <= 4 parts; the items
+// are then assigned longest-processing-time first, each to the least loaded
+// workgroup, except that a workgroup takes at most one split item, which goes
+// first in its list (so that every part of a system runs concurrently).
 template <int MODE>
 int build_plan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, bool allow_split,
                Plan** out) {
@@ -454,17 +479,19 @@ int build_plan(int32_t ncl, const int64_t* off, const double* eps, int precision
   std::vector<double> icost;
   std::vector<int> flag_base(ncl, 0);
   int nflags = 0;
-  std::vector<int> unsplit;
   for (int c : order) {
     const int nc = (int)(off[c + 1] - off[c]);
     int P = 1;
-    if (allow_split && nwg > 1 && nc >= 512 && cost[c] > 0.75 * avg)
-      P = std::min(4, (int)std::ceil(cost[c] / (0.75 * avg)));
+    if (allow_split && nwg > 1 && nc >= 512 && cost[c] > avg) P = std::min(4, (int)std::ceil(cost[c] / avg));
     if (P > 1 && nflags + P > nwg) P = 1;
     Map mp{1, 1};
     double pc = 0;
     if (P > 1 && !choose_map<MODE>(nc, (nc + P - 1) / P, &mp, &pc)) P = 1;
-    if (P == 1) { unsplit.push_back(c); continue; }
+    if (P == 1) {
+      items.push_back(Item{c, 0, 1, whole[c].ipl | (whole[c].js << 8)});
+      icost.push_back(cost[c]);
+      continue;
+    }
     flag_base[c] = nflags;
     nflags += P;
     for (int q = 0; q < P; ++q) {
@@ -473,26 +500,26 @@ int build_plan(int32_t ncl, const int64_t* off, const double* eps, int precision
     }
     lds = std::max(lds, lds_bytes<MODE>(nc, (nc + P - 1) / P, mp));
   }
-  const int nsplit = (int)items.size();
-  for (int c : unsplit) {
-    items.push_back(Item{c, 0, 1, whole[c].ipl | (whole[c].js << 8)});
-    icost.push_back(cost[c]);
-  }
-  // split items first, one per workgroup; then LPT over the rest
+  std::vector<int> korder(items.size());
+  for (size_t k = 0; k < items.size(); ++k) korder[k] = (int)k;
+  std::stable_sort(korder.begin(), korder.end(), [&](int u, int w) { return icost[u] > icost[w]; });
   std::vector<std::vector<int>> lists(nwg);
   std::vector<double> load(nwg, 0.0);
-  for (int k = 0; k < nsplit; ++k) {
-    lists[k].push_back(k);
-    load[k] = icost[k];
-  }
-  using Slot = std::pair<double, int>;
-  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
-  for (int w = 0; w < nwg; ++w) heap.push({load[w], w});
-  for (int k = nsplit; k < (int)items.size(); ++k) {
-    Slot s = heap.top();
-    heap.pop();
-    lists[s.second].push_back(k);
-    heap.push({s.first + icost[k], s.second});
+  std::vector<char> has_split(nwg, 0);
+  for (int k : korder) {
+    const bool sp = items[k].nparts > 1;
+    int best = -1;
+    for (int w = 0; w < nwg; ++w) {
+      if (sp && has_split[w]) continue;
+      if (best < 0 || load[w] < load[best]) best = w;
+    }
+    if (sp) {
+      has_split[best] = 1;
+      lists[best].insert(lists[best].begin(), k);
+    } else {
+      lists[best].push_back(k);
+    }
+    load[best] += icost[k];
   }
   std::vector<int> wg_off(nwg + 1, 0), wg_list;
   for (int w = 0; w < nwg; ++w) {

@@ -126,7 +126,19 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
       if constexpr (NEAR) {
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
-          if (r2min[k] < rc2[k]) {
+          // the lane's own pair (zero displacement) always sets r2min = eps^2:
+          // in the block holding it, rescan for a close pair other than that one
+          bool close = r2min[k] < rc2[k];
+          if (close && (unsigned)(iidx[k] - (jt + f)) < (unsigned)kFold) {
+            close = false;
+            for (int jj = f; jj < f + kFold; ++jj) {
+              R dx, dy, dz;
+              disp_hi(cur[jj], pi[k], dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              close = close || (r2 < rc2[k] && jt + jj != iidx[k]);
+            }
+          }
+          if (close) {
             // rare: redo this block for lane k with float-float displacements for the close pairs
             R qx = 0, qy = 0, qz = 0;
             for (int jj = f; jj < f + kFold; ++jj) {
@@ -328,7 +340,17 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
       if constexpr (NEAR) {
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
-          if (r2min[k] < rc2[k]) {
+          bool close = r2min[k] < rc2[k];  // a close pair other than the lane's own, as in accel_kernel
+          if (close && (unsigned)(iidx[k] - (jt + f)) < (unsigned)kFold) {
+            close = false;
+            for (int jj = f; jj < f + kFold; ++jj) {
+              R dx, dy, dz;
+              disp_hi(cur[jj].r, pi[k], dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              close = close || (r2 < rc2[k] && jt + jj != iidx[k]);
+            }
+          }
+          if (close) {
             // rare: redo this block for lane k with float-float displacements for the close pairs
             R qx = 0, qy = 0, qz = 0, qm = 0;
             for (int jj = f; jj < f + kFold; ++jj) {

@@ -13,6 +13,9 @@ Definitions (Eq. (1) of Sec. 2.1 divided by m_i, Plummer softening of App. A):
          obtained here by mpmath differentiation of the mpmath acceleration.
   jerk : d/dt a_i(x + V t) at t = 0 for velocities V (mpmath differentiation),
          the quantity App. A, Algorithm 3 accumulates beside the acceleration.
+  snap : d^2/dt^2 a_i(x + V t + ACC t^2 / 2) at t = 0 for accelerations ACC
+         (mpmath differentiation), the extra quantity a sixth-order Hermite
+         step (Sec. 2.1) evaluates.
 Run:  python tests/golden/make_tiny_mp50.py
 """
 import os
@@ -31,6 +34,9 @@ EPS = 0.0625
 VEL = [[0.25, -0.5, 0.0, 0.125, -0.375],
        [0.5, 0.0, -0.25, 0.75, 0.0625],
        [-0.125, 0.375, 0.5, 0.0, -0.25]]
+ACC = [[-0.5, 0.25, 0.125, -0.75, 0.375],
+       [0.0625, -0.25, 0.5, 0.125, -0.5],
+       [0.25, 0.0, -0.375, 0.5, 0.125]]
 W_COT = [[0.5, -1.0, 0.25, 0.0, 0.75],
          [-0.5, 0.125, 1.0, -0.25, 0.0],
          [0.25, 0.5, -0.75, 1.0, -0.125]]
@@ -100,6 +106,19 @@ def jerk(x, vel, m, eps, G):
     return out
 
 
+def snap(x, vel, acc, m, eps, G):
+    """d^2/dt^2 of the mpmath acceleration along x + vel t + acc t^2 / 2."""
+    n = len(m)
+    out = [[mp.mpf(0)] * n for _ in range(3)]
+    for c in range(3):
+        for i in range(n):
+            def f(t, c=c, i=i):
+                xs = [[x[d][k] + vel[d][k] * t + acc[d][k] * t * t / 2 for k in range(n)] for d in range(3)]
+                return accel(xs, m, eps, G)[c][i]
+            out[c][i] = mp.diff(f, 0, 2)
+    return out
+
+
 def main():
     x = [[mp.mpf(v) for v in row] for row in X]
     m = [mp.mpf(v) for v in M]
@@ -110,6 +129,8 @@ def main():
     gx, gm = vjp(x, m, w, eps, g)
     vel = [[mp.mpf(v) for v in row] for row in VEL]
     jk = jerk(x, vel, m, eps, g)
+    acc = [[mp.mpf(v) for v in row] for row in ACC]
+    sn = snap(x, vel, acc, m, eps, g)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny5_mp50.txt")
     with open(path, "w") as f:
         f.write("# 5-body softened gravity evaluated with mpmath at 50 digits\n")
@@ -131,6 +152,10 @@ def main():
             f.write("v%d %s\n" % (c, " ".join(repr(v) for v in VEL[c])))
         for c in range(3):
             f.write("j%d %s\n" % (c, " ".join(mp.nstr(v, 40) for v in jk[c])))
+        for c in range(3):
+            f.write("acc%d %s\n" % (c, " ".join(repr(v) for v in ACC[c])))
+        for c in range(3):
+            f.write("s%d %s\n" % (c, " ".join(mp.nstr(v, 40) for v in sn[c])))
     print("wrote", path)
 
 

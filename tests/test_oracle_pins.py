@@ -12,7 +12,10 @@ rather than by retyping the oracle's own formula:
 * conservation of momentum and angular momentum, time reversibility,
   O(dt^2) energy error, the virial theorem and E = -1/4 in Henon units;
 * complex-step and central finite differences of an independent numpy
-  forward model for the adjoint, and a forward/reverse dot-product test.
+  forward model for the adjoint, and a forward/reverse dot-product test;
+* for the sixth-order Hermite step: the 50-digit snap, central differences of
+  the separately written jerk along the path, the crackle formula on exact
+  quintics, sixth-order convergence on the Kepler problem and conservation.
 """
 import math
 import os
@@ -39,7 +42,9 @@ def _read_golden():
     gx = np.stack([d["gx0"], d["gx1"], d["gx2"]])
     vel = np.stack([d["v0"], d["v1"], d["v2"]])
     jk = np.stack([d["j0"], d["j1"], d["j2"]])
-    return dict(x=x, m=d["m"], w=w, a=a, W=float(d["W"][0]), gx=gx, gm=d["gm"], v=vel, j=jk,
+    acc = np.stack([d["acc0"], d["acc1"], d["acc2"]])
+    sn = np.stack([d["s0"], d["s1"], d["s2"]])
+    return dict(x=x, m=d["m"], w=w, a=a, W=float(d["W"][0]), gx=gx, gm=d["gm"], v=vel, j=jk, acc=acc, s=sn,
                 G=float(d["G"][0]), eps=float(d["eps"][0]))
 
 
@@ -398,3 +403,81 @@ def test_hermite4_conserves_momentum_and_energy(oracle_mod):
     pscale = (m * np.abs(v1).sum(axis=0)).sum()
     assert np.abs(e1[3:6] - e0[3:6]).max() <= 1e-13 * pscale
     assert abs(e1[2] - e0[2]) <= 1e-7 * abs(e0[2])
+
+
+def test_golden_snap_mp50(oracle_mod):
+    g = _read_golden()
+    a, jk, sn = oracle_mod.accel_jerk_snap(g["x"], g["v"], g["acc"], g["m"], G=g["G"], eps=g["eps"])
+    assert np.abs(a - g["a"]).max() <= 2e-15 * np.abs(g["a"]).max()
+    assert np.abs(jk - g["j"]).max() <= 1e-14 * np.abs(g["j"]).max()
+    assert np.abs(sn - g["s"]).max() <= 1e-14 * np.abs(g["s"]).max()
+
+
+def test_snap_is_time_derivative_of_jerk(oracle_mod):
+    """snap_i = d/dt jerk_i along x + v t + acc t^2/2 (velocity v + acc t), by
+    central differences of the separately written Algorithm-3 routine, for an
+    arbitrary acceleration field acc."""
+    x, v, m = ics.plummer(200, seed=43)
+    eps = 0.02
+    acc = np.random.default_rng(44).standard_normal((3, 200))
+    _, _, sn = oracle_mod.accel_jerk_snap(x, v, acc, m, G=1.3, eps=eps)
+    h = 2e-6
+
+    def jerk_at(t):
+        return oracle_mod.accel_jerk(x + v * t + acc * (t * t / 2), v + acc * t, m, G=1.3, eps=eps)[1]
+    fd = (jerk_at(h) - jerk_at(-h)) / (2 * h)
+    assert np.abs(fd - sn).max() <= 5e-8 * np.abs(sn).max()
+
+
+def test_snap_total_is_zero(oracle_mod):
+    """sum_i m_i snap_i = d^2/dt^2 sum_i m_i a_i = 0 (pairwise antisymmetry)."""
+    x, v, m = ics.random_cloud(300, seed=45)
+    acc = np.random.default_rng(46).standard_normal((3, 300))
+    _, _, sn = oracle_mod.accel_jerk_snap(x, v, acc, m, eps=0.05)
+    assert np.abs((sn * m).sum(axis=1)).max() <= 1e-14 * (np.abs(sn) * m).sum()
+
+
+def test_hermite6_crackle_exact_on_quintics(oracle_mod):
+    """The crackle estimate is the third derivative at t = h of the quintic
+    matching value, first and second derivative at both ends: exact when the
+    acceleration history is itself a quintic."""
+    rng = np.random.default_rng(47)
+    h = 0.37
+    k = rng.standard_normal((6, 50))           # q(t) = sum_p k_p t^p, 50 independent series
+
+    def der(t, order):
+        out = np.zeros(50)
+        for p in range(order, 6):
+            out += k[p] * math.factorial(p) / math.factorial(p - order) * t ** (p - order)
+        return out
+    c1 = oracle_mod.hermite6_crackle(h, der(0, 0), der(0, 1), der(0, 2), der(h, 0), der(h, 1), der(h, 2))
+    assert np.abs(c1 - der(h, 3)).max() <= 1e-11 * np.abs(der(h, 3)).max()
+
+
+def test_hermite6_kepler_sixth_order(oracle_mod):
+    m1, m2, a_sm, e = 0.7, 0.3, 1.0, 0.5
+    x0, v0, m = _kepler_ics(m1, m2, a_sm, e)
+    period = 2 * math.pi * math.sqrt(a_sm ** 3 / (m1 + m2))
+    t_end = 0.8 * period
+    errs = []
+    for steps in (100, 200, 400):
+        x, _ = oracle_mod.hermite6(x0, v0, m, t_end / steps, steps, eps=0.0)
+        errs.append(np.linalg.norm(x[:, 1] - x[:, 0] - _kepler_positions(m1, m2, a_sm, e, t_end)))
+    assert errs[-1] < 1e-8
+    for coarse, fine in zip(errs[:-1], errs[1:]):
+        assert 50.0 < coarse / fine < 80.0, errs
+
+
+def test_hermite6_conserves_momentum_and_energy(oracle_mod):
+    x, v, m = ics.plummer(128, seed=42)
+    eps = 0.05
+    e0 = oracle_mod.energy(x, v, m, 1.0, eps)
+    x1, v1 = oracle_mod.hermite6(x, v, m, 1.0 / 256, 64, eps=eps)
+    e1 = oracle_mod.energy(x1, v1, m, 1.0, eps)
+    pscale = (m * np.abs(v1).sum(axis=0)).sum()
+    assert np.abs(e1[3:6] - e0[3:6]).max() <= 1e-13 * pscale
+    assert abs(e1[2] - e0[2]) <= 1e-9 * abs(e0[2])
+    # the fourth-order scheme lands within its own (larger) error of the same point
+    x4, _ = oracle_mod.hermite4(x, v, m, 1.0 / 256, 64, eps=eps)
+    x4f, _ = oracle_mod.hermite4(x, v, m, 1.0 / 512, 128, eps=eps)
+    assert np.abs(x1 - x4f).max() < np.abs(x4 - x4f).max()
