@@ -18,7 +18,8 @@ Other workloads (--workload): plummer64k_fp32c (100 KDK steps, N = 65536),
 ensemble512 (512 clusters, 1000 steps in one persistent launch),
 grad16k (forward + adjoint of 200 steps, N = 16384), plummer1k_fp64 (10 FP64
 steps of N = 1024 with the oracle timed beside it), jerk1m (acceleration + jerk
-at N = 2^20 and Hermite steps at N = 65536).
+at N = 2^20 and Hermite steps at N = 65536), hermite6_409600 (the paper's
+N = 409600 sixth-order Hermite run: time-to-solution of three steps).
 """
 from __future__ import annotations
 
@@ -386,6 +387,43 @@ def bench_jerk(args, torch, nb):
                            "pairs_per_s_g": round(float(nh) * (nh - 1) / (hms * 1e-3) / 1e9, 3)}}
 
 
+def bench_hermite6(args, torch, nb):
+    """The paper's end-to-end setting: N = 409600 Plummer sphere, three
+    sixth-order Hermite steps (start-up evaluations included in the
+    time-to-solution), FP32C pairs with FP64 state, and the FP64 path."""
+    import ics
+    w = ics.WORKLOADS["hermite6_409600"]
+    n, eps, dt, steps = args.n or w["n"], w["eps"], w["dt"], w["steps"]
+    x, v, m = ics.plummer(n, seed=w["seed"])
+    dev = torch.device("cuda:0")
+    tm = torch.tensor(m, device=dev)
+    pairs = float(n) * (n - 1)
+    res = {}
+    for prec in (args.precision, "fp64"):
+        tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+        st = [torch.empty_like(tx) for _ in range(4)]
+        e0 = nb.nbody_energy(tx, tv, tm, eps=eps).cpu().numpy()[2]
+        # time-to-solution: start-up (two evaluations) and `steps` steps
+        ms_tts, _, _ = timed(lambda: nb.nbody_step_hermite6(tx, tv, *st, tm, dt, steps, eps=eps, precision=prec),
+                             1, 0, torch)
+        e1 = nb.nbody_energy(tx, tv, tm, eps=eps).cpu().numpy()[2]
+        # per-step time, resuming from the state just reached
+        ms_step, _, _ = timed(lambda: nb.nbody_step_hermite6(tx, tv, *st, tm, dt, 1, eps=eps, precision=prec,
+                                                              acc_valid=True), args.steps, 0, torch)
+        res[prec] = {"time_to_solution_ms": round(ms_tts, 3), "ms_per_step": round(ms_step, 3),
+                     "pairs_per_s_g": round(pairs / (ms_step * 1e-3) / 1e9, 3),
+                     "energy_error_after_steps": float(abs((e1 - e0) / e0))}
+    r = res[args.precision]
+    return {"metric": METRIC, "value": r["pairs_per_s_g"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+            "warmup": 0, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "hermite6_409600", "n": n, "eps": eps, "dt": dt, "steps_to_solution": steps,
+                       "precision": args.precision, "evaluation": "acceleration + jerk + snap per step"},
+            "paths": res,
+            "paper_context": {"time_to_solution_s": {"1 Wormhole n300 chip": 1459.46, "CPU 32 threads": 2875.39},
+                              "note": "paper's hardware; its time step and initial conditions are not stated"}}
+
+
 def bench_copy(args, torch, nb):
     """A plain device copy of known size, used to calibrate the HBM byte
     counters (FETCH_SIZE / WRITE_SIZE) that price the force kernel's traffic."""
@@ -406,7 +444,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twocomp1m_force",
                     choices=["twocomp1m_force", "plummer64k_fp32c", "ensemble512", "grad16k", "copy256m",
-                             "plummer1k_fp64", "jerk1m"])
+                             "plummer1k_fp64", "jerk1m", "hermite6_409600"])
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--n", type=int, default=None, help="override N of the force workload")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
@@ -421,7 +459,7 @@ def main():
         sys.exit(2)
     if args.steps is None:
         args.steps = {"twocomp1m_force": 10, "plummer64k_fp32c": 100, "ensemble512": 1000, "grad16k": 200,
-                      "copy256m": 20, "plummer1k_fp64": 20, "jerk1m": 6}[args.workload]
+                      "copy256m": 20, "plummer1k_fp64": 20, "jerk1m": 6, "hermite6_409600": 3}[args.workload]
 
     import torch
     if not torch.cuda.is_available():
@@ -431,7 +469,7 @@ def main():
     nb.load()
     fn = {"twocomp1m_force": bench_force, "plummer64k_fp32c": bench_kdk64k, "ensemble512": bench_ensemble,
           "grad16k": bench_grad, "copy256m": bench_copy, "plummer1k_fp64": bench_kdk1k,
-          "jerk1m": bench_jerk}[args.workload]
+          "jerk1m": bench_jerk, "hermite6_409600": bench_hermite6}[args.workload]
     res = fn(args, torch, nb)
     print(json.dumps(res), flush=True)
 

@@ -180,4 +180,14 @@ WORKLOADS = {
     "ensemble512": dict(ncl=512, nmin=64, nmax=4096, steps=1000, dt=1.0 / 512, seed=4),
     "grad16k": dict(n=16384, eps=0.01, steps=200, dt=1.0 / 256, seed=5, target_seed=55,
                     sigma=1e-3, every=20),
+    # the paper's end-to-end run: N = 409600, three sixth-order Hermite steps,
+    # softening 1e-7 (App. A); its initial conditions and step are not stated
+    "hermite6_409600": dict(n=409600, eps=1e-7, steps=3, dt=1.0 / 1024, seed=7),
 }
+
+
+def plummer_mean_field(x, b=3.0 * np.pi / 16.0):
+    """Acceleration of the smooth unit-mass Plummer potential, -x / (|x|^2 + b^2)^(3/2):
+    a physically scaled acceleration field for snap evaluations."""
+    r2 = (np.asarray(x) ** 2).sum(axis=0)
+    return -np.asarray(x) / (r2 + b * b) ** 1.5

@@ -185,13 +185,51 @@ int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* 
 int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt,
                        int64_t nsteps, const nbody_params* p, void* stream);
 
+/* Acceleration, jerk and snap of n particles at positions x, velocities v and
+ * accelerations acc (all [3][n] SoA), the evaluation of a sixth-order Hermite
+ * step (Sec. 2.1; the scheme of Nitadori & Makino 2008 that the paper cites):
+ * along paths x_k(t) = x_k + v_k t + acc_k t^2/2, with d = x_j - x_i,
+ * w = v_j - v_i, u = acc_j - acc_i, s = |d|^2 + eps^2, t_j = m_j s^-3/2,
+ * alpha = (d.w)/s and beta = (w.w + d.u)/s + alpha^2,
+ *   a_i  = G sum_j t_j d
+ *   jk_i = G sum_j (t_j w - 3 alpha t_j d)            (as Algorithm 3)
+ *   sn_i = G sum_j (t_j u - 6 alpha P' - 3 beta t_j d), P' the jerk term.
+ * acc is an input: the snap takes the accelerations the particles move with
+ * (in a Hermite step, the predicted ones).  Outputs a, jk, sn: [3][n] FP64,
+ * caller-owned, distinct from each other and the inputs.  FP32C evaluates
+ * pairs with float-float positions and FP32 velocity and acceleration
+ * differences.  Errors: as nbody_accel_jerk. */
+int nbody_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
+                          double* a, double* jk, double* sn, const nbody_params* p, void* stream);
+
+/* nsteps sixth-order Hermite predictor-evaluator-corrector steps with a
+ * shared step h = dt (Sec. 2.1), in place on x, v and the state a, jk, sn, cr
+ * (acceleration, jerk, snap and crackle, each [3][n] FP64):
+ *   predict  xp = x + v h + a h^2/2 + jk h^3/6 + sn h^4/24 + cr h^5/120
+ *            vp = v + a h + jk h^2/2 + sn h^3/6 + cr h^4/24
+ *            ap = a + jk h + sn h^2/2 + cr h^3/6
+ *   evaluate (a1, jk1, sn1) at (xp, vp, ap) with nbody_accel_jerk_snap
+ *   correct  v' = v + (a + a1) h/2 - (jk1 - jk) h^2/10 + (sn + sn1) h^3/120
+ *            x' = x + (v + v') h/2 - (a1 - a) h^2/10 + (jk + jk1) h^3/120
+ *   crackle  cr' = 60 A - 36 B + 9 C, the third derivative at the step's end of
+ *            the quintic through (a, jk, sn) at both ends, with
+ *            A = (a1 - a - jk h - sn h^2/2)/h^3, B = (jk1 - jk - sn h)/h^2,
+ *            C = (sn1 - sn)/h.
+ * Without NBODY_ACC_VALID the call first evaluates a, jk at (x, v), then
+ * a, jk, sn at (x, v, a), and sets cr = 0; with it, a, jk, sn, cr hold the
+ * state a previous call left (so that calls resume bitwise).
+ * Errors: as nbody_step, and NBODY_EINVAL for dt = 0 (the crackle divides
+ * by the step); the six arrays must be distinct. */
+int nbody_step_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double* sn, double* cr,
+                        const double* m, double dt, int64_t nsteps, const nbody_params* p, void* stream);
+
 /* Tile configuration of the all-pairs kernels (see nbody_set_config). */
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
   int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
   int32_t bsplit;  /* batched kernel: 0 = one workgroup per system (default),
-                      1 = split systems costlier than 3/4 of the per-CU average across
-                      up to 4 workgroups that exchange positions every step */
+                      1 = split systems costlier than the per-CU average across up
+                      to 4 workgroups that exchange positions every step */
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
 } nbody_config;

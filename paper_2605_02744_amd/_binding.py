@@ -75,6 +75,8 @@ def load():
                                        ctypes.POINTER(ctypes.c_double), _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_accel_jerk.argtypes = [_I64, _P, _P, _P, _P, _P, PP, _P]
     lib.nbody_step_hermite.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, PP, _P]
+    lib.nbody_accel_jerk_snap.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, PP, _P]
+    lib.nbody_step_hermite6.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_set_config.argtypes = [ctypes.POINTER(nbody_config)]
     lib.nbody_tune.argtypes = [_I64, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(nbody_config)]
     lib.nbody_last_error.restype = ctypes.c_char_p
@@ -83,7 +85,7 @@ def load():
     lib.nbody_version.argtypes = []
     for f in ("nbody_accel", "nbody_step", "nbody_energy", "nbody_accel_vjp", "nbody_traj_grad",
               "nbody_step_batched", "nbody_set_config", "nbody_tune", "nbody_finalize", "nbody_version",
-              "nbody_accel_jerk", "nbody_step_hermite"):
+              "nbody_accel_jerk", "nbody_step_hermite", "nbody_accel_jerk_snap", "nbody_step_hermite6"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -244,6 +246,32 @@ def nbody_step_hermite(x, v, a, jk, m, dt, nsteps, *, G=1.0, eps, precision="fp3
                                       _ptr(jk, "jk", (3, n)), _ptr(m, "m", (n,)), float(dt), int(nsteps),
                                       ctypes.byref(p), _stream(x.device)))
     return x, v, a, jk
+
+
+def nbody_accel_jerk_snap(x, v, acc, m, *, G=1.0, eps, precision="fp32c", exclude_self=False, check_finite=False):
+    """(a, jerk, snap), each (3, N), of particles x, v moving with accelerations acc."""
+    lib = load()
+    n = m.shape[0]
+    a, jk, sn = (torch.empty((3, n), dtype=torch.float64, device=x.device) for _ in range(3))
+    p = _params(G, eps, precision, _flags(exclude_self, check_finite))
+    with torch.cuda.device(x.device):
+        _check(lib.nbody_accel_jerk_snap(n, _ptr(x, "x", (3, n)), _ptr(v, "v", (3, n)), _ptr(acc, "acc", (3, n)),
+                                         _ptr(m, "m", (n,)), _ptr(a, "a", (3, n)), _ptr(jk, "jk", (3, n)),
+                                         _ptr(sn, "sn", (3, n)), ctypes.byref(p), _stream(x.device)))
+    return a, jk, sn
+
+
+def nbody_step_hermite6(x, v, a, jk, sn, cr, m, dt, nsteps, *, G=1.0, eps, precision="fp32c", acc_valid=False,
+                        exclude_self=False, check_finite=False):
+    """nsteps sixth-order Hermite steps in place on x, v and the state a, jk, sn, cr (each (3, N))."""
+    lib = load()
+    n = m.shape[0]
+    p = _params(G, eps, precision, _flags(exclude_self, check_finite, acc_valid))
+    with torch.cuda.device(x.device):
+        _check(lib.nbody_step_hermite6(n, _ptr(x, "x", (3, n)), _ptr(v, "v", (3, n)), _ptr(a, "a", (3, n)),
+                                       _ptr(jk, "jk", (3, n)), _ptr(sn, "sn", (3, n)), _ptr(cr, "cr", (3, n)),
+                                       _ptr(m, "m", (n,)), float(dt), int(nsteps), ctypes.byref(p),
+                                       _stream(x.device)))
 
 
 def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0):

@@ -367,6 +367,50 @@ int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* 
   return finish(st, s, p, {{a, 3 * n}, {jk, 3 * n}});
 }
 
+int nbody_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
+                          double* a, double* jk, double* sn, const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(v, b3, "v"));
+  NB_TRY(check_dev_range(acc, b3, "acc"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  NB_TRY(check_dev_range(jk, b3, "jk"));
+  NB_TRY(check_dev_range(sn, b3, "sn"));
+  for (const double* o : {(const double*)a, (const double*)jk, (const double*)sn})
+    for (const double* q : {x, v, acc, m})
+      if (o == q) return set_error(NBODY_EINVAL, "a, jk and sn must be distinct from the inputs");
+  if (a == jk || a == sn || jk == sn) return set_error(NBODY_EINVAL, "a, jk and sn must be distinct");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = launch_accel_jerk_snap(n, x, v, acc, m, a, jk, sn, p->G, p->eps, p->precision,
+                                  (p->flags & NBODY_EXCLUDE_SELF) != 0, cfg, s);
+  return finish(st, s, p, {{a, 3 * n}, {jk, 3 * n}, {sn, 3 * n}});
+}
+
+int nbody_step_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double* sn, double* cr,
+                        const double* m, double dt, int64_t nsteps, const nbody_params* p, void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (!std::isfinite(dt) || dt == 0.0) return set_error(NBODY_EINVAL, "dt must be finite and non-zero");
+  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  double* arr[6] = {x, v, a, jk, sn, cr};
+  const char* names[6] = {"x", "v", "a", "jk", "sn", "cr"};
+  for (int k = 0; k < 6; ++k) NB_TRY(check_dev_range(arr[k], b3, names[k]));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  for (int k = 0; k < 6; ++k)
+    for (int l = k + 1; l < 6; ++l)
+      if (arr[k] == arr[l]) return set_error(NBODY_EINVAL, "x, v, a, jk, sn and cr must be distinct");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PairConfig cfg = choose_config(n, p->precision, current_device());
+  int st = run_hermite6(n, x, v, a, jk, sn, cr, m, dt, nsteps, p->G, p->eps, p->precision,
+                        (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, cfg, s);
+  return finish(st, s, p, {{x, 3 * n}, {v, 3 * n}, {a, 3 * n}, {jk, 3 * n}, {sn, 3 * n}, {cr, 3 * n}});
+}
+
 int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt,
                        int64_t nsteps, const nbody_params* p, void* stream) {
   NB_TRY(check_common(n, p, true));

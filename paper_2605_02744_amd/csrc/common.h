@@ -66,6 +66,12 @@ int launch_vjp(int64_t n, const double* x, const double* m, const double* w, dou
                double* gm, double G, double eps, int precision, bool exclude_self,
                const PairConfig& cfg, hipStream_t s);
 
+// Acceleration, jerk and snap along paths of constant acceleration acc (the
+// evaluation of a sixth-order Hermite step) into a, jk and sn (FP64 SoA).
+int launch_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
+                           double* a, double* jk, double* sn, double G, double eps, int precision, bool excl,
+                           const PairConfig& cfg, hipStream_t s);
+
 // Acceleration and jerk (App. A, Algorithm 3) into a and jk (FP64 SoA).
 int launch_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
                       double eps, int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
@@ -74,6 +80,11 @@ int launch_accel_jerk(int64_t n, const double* x, const double* v, const double*
 int run_hermite(int64_t n, double* x, double* v, double* a, double* jk, const double* m, double dt, int64_t nsteps,
                 double G, double eps, int precision, bool exclude_self, bool acc_valid, const PairConfig& cfg,
                 hipStream_t s);
+
+// The sixth-order Hermite loop of nbody_step_hermite6.
+int run_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double* sn, double* cr, const double* m,
+                 double dt, int64_t nsteps, double G, double eps, int precision, bool exclude_self, bool acc_valid,
+                 const PairConfig& cfg, hipStream_t s);
 
 // Elementwise KDK pieces over 3n entries.
 int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s);

@@ -85,6 +85,50 @@ __global__ void hermite_correct_kernel(int64_t n3, double* __restrict__ x, doubl
   jk[e] = jn;
 }
 
+// Sixth-order Hermite predictor (shared step h, crackle c from the previous step):
+//   xp = x + v h + a h^2/2 + j h^3/6 + s h^4/24 + c h^5/120
+//   vp = v + a h + j h^2/2 + s h^3/6 + c h^4/24
+//   ap = a + j h + s h^2/2 + c h^3/6
+__global__ void hermite6_predict_kernel(int64_t n3, const double* __restrict__ x, const double* __restrict__ v,
+                                        const double* __restrict__ a, const double* __restrict__ jk,
+                                        const double* __restrict__ sn, const double* __restrict__ cr, double h,
+                                        double* __restrict__ xp, double* __restrict__ vp, double* __restrict__ ap) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double c2 = h * h / 2.0, c3 = h * h * h / 6.0, c4 = h * h * h * h / 24.0, c5 = h * h * h * h * h / 120.0;
+  const double ae = a[e], je = jk[e], se = sn[e], ce = cr[e];
+  xp[e] = fma(ce, c5, fma(se, c4, fma(je, c3, fma(ae, c2, fma(v[e], h, x[e])))));
+  vp[e] = fma(ce, c4, fma(se, c3, fma(je, c2, fma(ae, h, v[e]))));
+  ap[e] = fma(ce, c3, fma(se, c2, fma(je, h, ae)));
+}
+
+// Sixth-order Hermite corrector, in place on (x, v, a, jk, sn, cr) from the
+// evaluation (a1, j1, s1) at the predicted state:
+//   v1 = v + (a + a1) h/2 - (j1 - j) h^2/10 + (s + s1) h^3/120
+//   x1 = x + (v + v1) h/2 - (a1 - a) h^2/10 + (j + j1) h^3/120
+// and the crackle for the next predictor, the third derivative at t = h of the
+// quintic through (a, j, s) at both ends: 60 A - 36 B + 9 C with
+//   A = (a1 - a - j h - s h^2/2) / h^3,  B = (j1 - j - s h) / h^2,  C = (s1 - s) / h.
+__global__ void hermite6_correct_kernel(int64_t n3, double* __restrict__ x, double* __restrict__ v,
+                                        double* __restrict__ a, double* __restrict__ jk, double* __restrict__ sn,
+                                        double* __restrict__ cr, const double* __restrict__ a1,
+                                        const double* __restrict__ j1, const double* __restrict__ s1, double h) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double hh = h / 2.0, h10 = h * h / 10.0, h120 = h * h * h / 120.0;
+  const double a0 = a[e], j0 = jk[e], s0 = sn[e], an = a1[e], jn = j1[e], snn = s1[e], v0 = v[e];
+  const double v1 = fma(s0 + snn, h120, fma(-(jn - j0), h10, fma(a0 + an, hh, v0)));
+  x[e] = fma(j0 + jn, h120, fma(-(an - a0), h10, fma(v0 + v1, hh, x[e])));
+  v[e] = v1;
+  const double A = (an - a0 - j0 * h - s0 * (h * h / 2.0)) / (h * h * h);
+  const double B = (jn - j0 - s0 * h) / (h * h);
+  const double C = (snn - s0) / h;
+  cr[e] = 60.0 * A - 36.0 * B + 9.0 * C;
+  a[e] = an;
+  jk[e] = jn;
+  sn[e] = snn;
+}
+
 // ---- deterministic reduction of the diagnostics -----------------------
 // Each thread accumulates fixed-stride elements into 9 (hi, lo) TwoSum pairs;
 // the block then combines lanes in a fixed tree order.
@@ -282,6 +326,35 @@ int run_hermite(int64_t n, double* x, double* v, double* a, double* jk, const do
     if ((st = launch_accel_jerk(n, xp, vp, m, a1, j1, G, eps, precision, excl, cfg, s))) return st;
     hermite_correct_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, x, v, a, jk, a1, j1, dt);
     NB_LAUNCH_CHECK("hermite_correct_kernel");
+  }
+  return NBODY_OK;
+}
+
+// Start: a, j at (x, v) by Algorithm 3, then a, j, s at (x, v, a) and c = 0.
+int run_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double* sn, double* cr, const double* m,
+                 double dt, int64_t nsteps, double G, double eps, int precision, bool excl, bool acc_valid,
+                 const PairConfig& cfg, hipStream_t s) {
+  const int64_t n3 = 3 * n;
+  int st = NBODY_OK;
+  double* ws = static_cast<double*>(workspace(current_device(), 1, sizeof(double) * 6 * (size_t)n3, &st));
+  if (!ws) return st;
+  double* xp = ws;
+  double* vp = xp + n3;
+  double* ap = vp + n3;
+  double* a1 = ap + n3;
+  double* j1 = a1 + n3;
+  double* s1 = j1 + n3;
+  if (!acc_valid) {
+    if ((st = launch_accel_jerk(n, x, v, m, a1, j1, G, eps, precision, excl, cfg, s))) return st;
+    if ((st = launch_accel_jerk_snap(n, x, v, a1, m, a, jk, sn, G, eps, precision, excl, cfg, s))) return st;
+    if ((st = launch_fill(n3, cr, 0.0, s))) return st;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hermite6_predict_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, x, v, a, jk, sn, cr, dt, xp, vp, ap);
+    NB_LAUNCH_CHECK("hermite6_predict_kernel");
+    if ((st = launch_accel_jerk_snap(n, xp, vp, ap, m, a1, j1, s1, G, eps, precision, excl, cfg, s))) return st;
+    hermite6_correct_kernel<<<ew_blocks(n3), kEw, 0, s>>>(n3, x, v, a, jk, sn, cr, a1, j1, s1, dt);
+    NB_LAUNCH_CHECK("hermite6_correct_kernel");
   }
   return NBODY_OK;
 }

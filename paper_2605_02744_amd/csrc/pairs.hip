@@ -192,9 +192,11 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
 }
 
 // Sums `split` slices of `cnt` partials in slice order (TwoSum across slices)
-// and scales by G; entries e < n0 go to out0[e], the rest to out1[e - n0].
+// and scales by G; entries e < n0 go to out0[e], e < n1 to out1[e - n0] and
+// the rest to out2[e - n1].
 __global__ void sum_slices_kernel(int64_t cnt, int split, const double* __restrict__ part, double G,
-                                  int64_t n0, double* __restrict__ out0, double* __restrict__ out1) {
+                                  int64_t n0, double* __restrict__ out0, int64_t n1, double* __restrict__ out1,
+                                  double* __restrict__ out2) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= cnt) return;
   double s = 0.0, c = 0.0;
@@ -206,7 +208,8 @@ __global__ void sum_slices_kernel(int64_t cnt, int split, const double* __restri
     s = t;
   }
   if (e < n0) out0[e] = G * (s + c);
-  else out1[e - n0] = G * (s + c);
+  else if (e < n1) out1[e - n0] = G * (s + c);
+  else out2[e - n1] = G * (s + c);
 }
 
 // ============================================================== VJP
@@ -559,6 +562,164 @@ __global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* 
   if (i < n) out[(size_t)blockIdx.y * n + i] = hp + lp;
 }
 
+// ============================================================== acceleration + jerk + snap
+// The evaluation of a sixth-order Hermite step (Sec. 2.1): along paths of
+// constant acceleration, the pair term P = t_j d (d = x_j - x_i,
+// t_j = m_j s^-3/2, s = |d|^2 + eps^2) has the derivatives
+//   P'  = t_j w - 3 alpha P,                  alpha = (d . w) / s
+//   P'' = t_j u - 6 alpha P' - 3 beta P,      beta  = (w . w + d . u) / s + alpha^2
+// with w = v_j - v_i and u = acc_j - acc_i; a, jerk and snap are G times their
+// sums.  Records carry the position record plus velocity and acceleration
+// (FP32C: float-float positions, FP32 velocity and acceleration differences).
+// split == 1 writes G*sums to a, jk and sn; split > 1 writes slice y's
+// unscaled 9n partials (a, jerk, snap) at part + y*9n.
+template <int MODE> struct SRec {
+  using V4 = typename std::conditional<MODE == kFP64, double4, float4>::type;
+  JRec<MODE> r;
+  V4 v;
+  V4 u;
+};
+
+template <int MODE>
+__device__ __forceinline__ SRec<MODE> load_srec(const double* __restrict__ x, const double* __restrict__ m,
+                                                const double* __restrict__ v, const double* __restrict__ acc,
+                                                int n, int j, int je) {
+  using R = Real<MODE>;
+  SRec<MODE> o;
+  if (j < je) {
+    o.r = JRec<MODE>::make(x[j], x[n + j], x[2 * n + j], m[j]);
+    o.v.x = (R)v[j]; o.v.y = (R)v[n + j]; o.v.z = (R)v[2 * n + j]; o.v.w = R(0);
+    o.u.x = (R)acc[j]; o.u.y = (R)acc[n + j]; o.u.z = (R)acc[2 * n + j]; o.u.w = R(0);
+  } else {
+    o.r = JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+    o.v.x = o.v.y = o.v.z = o.v.w = R(0);
+    o.u.x = o.u.y = o.u.z = o.u.w = R(0);
+  }
+  return o;
+}
+
+template <int MODE, int IPL, bool EXCL>
+__global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __restrict__ x,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ acc,
+                                                      const double* __restrict__ m, double eps, double G,
+                                                      int chunk, double* __restrict__ a, double* __restrict__ jk,
+                                                      double* __restrict__ sn, double* __restrict__ part) {
+  using R = Real<MODE>;
+  __shared__ SRec<MODE> tile[2][kTile];
+  const int t = threadIdx.x;
+  const int ibase = blockIdx.x * (kBlock * IPL) + t;
+  const int js = blockIdx.y * chunk;
+  const int je = min(n, js + chunk);
+  const R e2 = (R)(eps * eps);
+
+  IPos<MODE> pi[IPL];
+  R vi[3][IPL], ui[3][IPL];
+  int iidx[IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    int i = ibase + k * kBlock;
+    iidx[k] = i;
+    int ic = i < n ? i : n - 1;
+    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vi[c][k] = (R)v[c * n + ic];
+      ui[c][k] = (R)acc[c * n + ic];
+    }
+  }
+  R ah[3][IPL], al[3][IPL], jh[3][IPL], jl[3][IPL], sh[3][IPL], sl[3][IPL];
+#pragma unroll
+  for (int k = 0; k < IPL; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ah[c][k] = al[c][k] = jh[c][k] = jl[c][k] = sh[c][k] = sl[c][k] = R(0);
+
+  const int ntiles = (je - js + kTile - 1) / kTile;
+  if (ntiles > 0) tile[0][t] = load_srec<MODE>(x, m, v, acc, n, js + t, je);
+  __syncthreads();
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int jt = js + tt * kTile;
+    // records past je are zero-mass padding: skip whole fold blocks of them
+    const int fend = min(kTile, (je - jt + kFold - 1) / kFold * kFold);
+    const bool more = tt + 1 < ntiles;
+    SRec<MODE> nxt;
+    if (more) nxt = load_srec<MODE>(x, m, v, acc, n, jt + kTile + t, je);
+    const SRec<MODE>* cur = tile[tt & 1];
+#pragma unroll 1
+    for (int f = 0; f < fend; f += kFold) {
+      R pa[3][IPL], pj[3][IPL], ps[3][IPL];
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pa[c][k] = pj[c][k] = ps[c][k] = R(0);
+#pragma unroll 4
+      for (int jj = f; jj < f + kFold; ++jj) {
+        const SRec<MODE> q = cur[jj];
+        const R mj = jmass(q.r);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          R d[3];
+          disp(q.r, pi[k], d[0], d[1], d[2]);
+          const R w[3] = {q.v.x - vi[0][k], q.v.y - vi[1][k], q.v.z - vi[2][k]};
+          const R u[3] = {q.u.x - ui[0][k], q.u.y - ui[1][k], q.u.z - ui[2][k]};
+          const R r2 = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], e2)));
+          const R ri = rsq(r2);
+          R sinv = ri * ri;
+          R tj = (mj * ri) * sinv;
+          if (EXCL) {
+            const bool self = (jt + jj == iidx[k]);
+            tj = self ? R(0) : tj;
+            sinv = self ? R(0) : sinv;
+          }
+          const R alpha = fma(d[2], w[2], fma(d[1], w[1], d[0] * w[0])) * sinv;
+          const R wwdu = fma(d[2], u[2], fma(d[1], u[1], fma(d[0], u[0],
+                             fma(w[2], w[2], fma(w[1], w[1], w[0] * w[0])))));
+          const R beta = fma(wwdu, sinv, alpha * alpha);
+          const R a3 = R(-3) * alpha;
+          const R b3 = R(-3) * beta;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const R P0 = tj * d[c];
+            const R P1 = fma(a3, P0, tj * w[c]);
+            const R P2 = fma(R(2) * a3, P1, fma(b3, P0, tj * u[c]));
+            pa[c][k] += P0;
+            pj[c][k] += P1;
+            ps[c][k] += P2;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < IPL; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          fold(ah[c][k], al[c][k], pa[c][k]);
+          fold(jh[c][k], jl[c][k], pj[c][k]);
+          fold(sh[c][k], sl[c][k], ps[c][k]);
+        }
+    }
+    if (more) tile[(tt + 1) & 1][t] = nxt;
+    __syncthreads();
+  }
+
+  const bool direct = gridDim.y == 1;
+  double* oa = direct ? a : part + (size_t)blockIdx.y * 9 * n;
+  double* oj = direct ? jk : oa + 3 * (size_t)n;
+  double* os = direct ? sn : oa + 6 * (size_t)n;
+  const double scale = direct ? G : 1.0;
+#pragma unroll
+  for (int k = 0; k < IPL; ++k) {
+    const int i = iidx[k];
+    if (i < n) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        oa[c * n + i] = scale * ((double)ah[c][k] + (double)al[c][k]);
+        oj[c * n + i] = scale * ((double)jh[c][k] + (double)jl[c][k]);
+        os[c * n + i] = scale * ((double)sh[c][k] + (double)sl[c][k]);
+      }
+    }
+  }
+}
+
 // ============================================================== launch helpers
 // j-slices are whole fold blocks (64 records), so that small systems can be
 // spread over more workgroups than they have 256-record tiles
@@ -592,7 +753,7 @@ int accel_dispatch(int64_t n, const double* x, const double* m, double* a, doubl
   NB_LAUNCH_CHECK("accel_kernel");
   if (sp > 1) {
     const int64_t cnt = 3 * n;
-    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, out, G, cnt, a, nullptr);
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, out, G, cnt, a, cnt, nullptr, nullptr);
     NB_LAUNCH_CHECK("sum_slices_kernel");
   }
   return NBODY_OK;
@@ -618,7 +779,7 @@ int vjp_dispatch(int64_t n, const double* x, const double* m, const double* w, d
   NB_LAUNCH_CHECK("vjp_kernel");
   if (sp > 1) {
     const int64_t cnt = 4 * n;
-    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, gx, gm);
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, gx, cnt, gm, nullptr);
     NB_LAUNCH_CHECK("sum_slices_kernel");
   }
   return NBODY_OK;
@@ -643,13 +804,51 @@ int jerk_dispatch(int64_t n, const double* x, const double* v, const double* m, 
   NB_LAUNCH_CHECK("jerk_kernel");
   if (sp > 1) {
     const int64_t cnt = 6 * n;
-    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, a, jk);
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, a, cnt, jk, nullptr);
+    NB_LAUNCH_CHECK("sum_slices_kernel");
+  }
+  return NBODY_OK;
+}
+
+template <int MODE, int IPL>
+int snap_dispatch(int64_t n, const double* x, const double* v, const double* acc, const double* m, double* a,
+                  double* jk, double* sn, double G, double eps, bool excl, int split, hipStream_t s) {
+  const int chunk = split_chunk(n, split);
+  const int sp = effective_split(n, split);
+  dim3 grid((unsigned)((n + kBlock * IPL - 1) / (kBlock * IPL)), (unsigned)sp);
+  int st = NBODY_OK;
+  double* part = nullptr;
+  if (sp > 1) {
+    part = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 9 * (size_t)n * sp, &st));
+    if (!part) return st;
+  }
+  if (excl)
+    snap_kernel<MODE, IPL, true><<<grid, kBlock, 0, s>>>((int)n, x, v, acc, m, eps, G, chunk, a, jk, sn, part);
+  else
+    snap_kernel<MODE, IPL, false><<<grid, kBlock, 0, s>>>((int)n, x, v, acc, m, eps, G, chunk, a, jk, sn, part);
+  NB_LAUNCH_CHECK("snap_kernel");
+  if (sp > 1) {
+    const int64_t cnt = 9 * n;
+    sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, part, G, 3 * n, a, 6 * n, jk, sn);
     NB_LAUNCH_CHECK("sum_slices_kernel");
   }
   return NBODY_OK;
 }
 
 }  // namespace
+
+int launch_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
+                           double* a, double* jk, double* sn, double G, double eps, int precision, bool excl,
+                           const PairConfig& cfg, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  const int split = cfg.split < 1 ? 1 : cfg.split;
+  switch (precision) {
+    case kFP64: return snap_dispatch<kFP64, 1>(n, x, v, acc, m, a, jk, sn, G, eps, excl, split, s);
+    case kFP32C: return snap_dispatch<kFP32C, 1>(n, x, v, acc, m, a, jk, sn, G, eps, excl, split, s);
+    case kFP32: return snap_dispatch<kFP32, 1>(n, x, v, acc, m, a, jk, sn, G, eps, excl, split, s);
+  }
+  return set_error(NBODY_EINVAL, "unknown precision");
+}
 
 int launch_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
                       double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
@@ -723,7 +922,7 @@ int launch_potential(int64_t n, const double* x, const double* m, double eps, do
   potential_kernel<<<grid, kBlock, 0, s>>>((int)n, x, m, eps, chunk, part);
   NB_LAUNCH_CHECK("potential_kernel");
   if (sp > 1) {
-    sum_slices_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, sp, part, 1.0, n, phi, nullptr);
+    sum_slices_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, sp, part, 1.0, n, phi, n, nullptr, nullptr);
     NB_LAUNCH_CHECK("sum_slices_kernel");
   }
   return NBODY_OK;

@@ -7,7 +7,10 @@ benchmark uses, on outputs the oracle can compute one by one:
 * 512-cluster ensemble: sampled clusters against the oracle's own KDK;
 * N = 16384 adjoint: the 200-step FP64 gradient against central finite
   differences (h = 1e-6) of the FP64 GPU forward on 64 random coordinates,
-  and a shorter run against the oracle's full adjoint.
+  and a shorter run against the oracle's full adjoint;
+* N = 409600 sixth-order Hermite (eps = 1e-7): acceleration, jerk and snap on
+  sampled rows against the oracle, and three FP32C steps against three FP64
+  steps of the GPU path.
 """
 import numpy as np
 import pytest
@@ -171,3 +174,32 @@ def test_grad16k_against_oracle_short(nb, oracle_mod, prec, tol):
         rel = np.linalg.norm(g.cpu().numpy() - r) / np.linalg.norm(r)
         print("grad16k short %s rel err %.3e" % (prec, rel))
         assert rel <= tol
+
+
+def test_hermite6_409600_sampled_rows_and_steps(nb, oracle_mod):
+    w = ics.WORKLOADS["hermite6_409600"]
+    n, eps, dt, steps = w["n"], w["eps"], w["dt"], w["steps"]
+    x, v, m = ics.plummer(n, seed=w["seed"])
+    acc = ics.plummer_mean_field(x)
+    rows = np.sort(np.random.default_rng(1).choice(n, 48, replace=False))
+    ra, rj, rs = oracle_mod.accel_jerk_snap_rows(x, v, acc, m, rows, eps=eps)
+    tx, tv, tacc, tm = dev(x), dev(v), dev(acc), dev(m)
+    for prec, tols in (("fp64", (1e-12, 1e-11, 1e-10)), ("fp32c", (1e-5, 2e-3, 2e-3))):
+        a, jk, sn = (q.cpu().numpy()[:, rows] for q in
+                     nb.nbody_accel_jerk_snap(tx, tv, tacc, tm, eps=eps, precision=prec))
+        errs = (row_err(a, ra).max(), row_err(jk, rj).max(), row_err(sn, rs).max())
+        print("N=409600 %s sampled rows: a %.2e jerk %.2e snap %.2e" % ((prec,) + errs))
+        assert all(e <= t for e, t in zip(errs, tols))
+    out = {}
+    for prec in ("fp64", "fp32c"):
+        sx, sv = dev(x), dev(v)
+        st = [torch.empty_like(sx) for _ in range(4)]
+        nb.nbody_step_hermite6(sx, sv, *st, tm, dt, steps, eps=eps, precision=prec, check_finite=True)
+        out[prec] = (sx.cpu().numpy(), sv.cpu().numpy())
+    dx = np.abs(out["fp32c"][0] - out["fp64"][0]).max()
+    # positions move by about dt^2 a per step, so a relative force error of
+    # 1e-5 allows steps * dt^2 * 1e-5 * max|a|
+    amax = np.abs(nb.nbody_accel(tx, tm, eps=eps, precision="fp64").cpu().numpy()).max()
+    tol = steps * dt * dt * 1e-5 * amax + 1e-12
+    print("N=409600 three steps: fp32c vs fp64 max |dx| %.2e (bound %.2e)" % (dx, tol))
+    assert dx <= tol
