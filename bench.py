@@ -413,6 +413,9 @@ def bench_hermite6(args, torch, nb):
         res[prec] = {"time_to_solution_ms": round(ms_tts, 3), "ms_per_step": round(ms_step, 3),
                      "pairs_per_s_g": round(pairs / (ms_step * 1e-3) / 1e9, 3),
                      "energy_error_after_steps": float(abs((e1 - e0) / e0))}
+    # per-particle potential (FP64) of the final state: the energy-distribution diagnostic
+    ms_phi, _, _ = timed(lambda: nb.nbody_potential(tx, tm, eps=eps), 3, 1, torch)
+    res["potential_fp64"] = {"ms": round(ms_phi, 3), "pairs_per_s_g": round(pairs / (ms_phi * 1e-3) / 1e9, 3)}
     r = res[args.precision]
     return {"metric": METRIC, "value": r["pairs_per_s_g"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": 0, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",

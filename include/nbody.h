@@ -113,6 +113,18 @@ int nbody_step(int64_t n, double* x, double* v, double* a, const double* m, doub
 int nbody_energy(int64_t n, const double* x, const double* v, const double* m,
                  const nbody_params* p, double* out9, void* stream);
 
+/* Per-particle softened potential, always in FP64 (p->precision is not used):
+ *   phi_i = -G sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^(1/2),
+ * the self pair excluded by index (so eps = 0 needs no flag).  With it the
+ * specific energy of particle i is |v_i|^2/2 + phi_i: the per-particle energy
+ * distribution that Sec. 4.1 (Fig. 4) compares between the accelerated run
+ * and the double-precision reference; sum_i m_i phi_i = 2 W of nbody_energy.
+ * x: [3][n], m: [n], phi: [n] FP64 device memory, caller-owned; phi must not
+ * alias x or m.  Errors: as nbody_accel (NBODY_ENONFINITE with
+ * NBODY_CHECK_FINITE). */
+int nbody_potential(int64_t n, const double* x, const double* m, double* phi, const nbody_params* p,
+                    void* stream);
+
 /* Vector-Jacobian products of the acceleration map at (x, m) with cotangent
  * w (3*n), obtained by differentiating Eq. (1) / m_i term by term:
  *   gx_k = G sum_{j != k} K(d_kj) (m_k w_j - m_j w_k),

@@ -57,6 +57,7 @@ def _load():
                                                     ctypes.POINTER(ctypes.c_int64), _D, _D, _D]
         lib.oracle_hermite6_crackle.argtypes = [_I64, ctypes.c_double, _D, _D, _D, _D, _D, _D, _D]
         lib.oracle_hermite6.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I64]
+        lib.oracle_potential.argtypes = [_I64, _D, _D, ctypes.c_double, ctypes.c_double, _D]
         lib.oracle_msd_loss.argtypes = [_I64, _D, _D]
         lib.oracle_msd_loss.restype = ctypes.c_double
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -201,6 +202,16 @@ def hermite4(x, v, m, dt, nsteps, G=1.0, eps=0.0):
     v = _c(v, (3, n)).copy()
     _load().oracle_hermite4(n, _p(x), _p(v), _p(m), float(G), float(eps), float(dt), int(nsteps))
     return x, v
+
+
+def potential(x, m, G=1.0, eps=0.0):
+    """phi_i = -G sum_{j != i} m_j / (|d_ij|^2 + eps^2)^(1/2), shape (N,)."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n))
+    phi = np.empty(n)
+    _load().oracle_potential(n, _p(x), _p(m), float(G), float(eps), _p(phi))
+    return phi
 
 
 def accel_jerk_snap(x, v, acc, m, G=1.0, eps=0.0):

@@ -360,6 +360,23 @@ void oracle_hermite4(int64_t n, double* x, double* v, const double* m, double G,
     free(a0); free(j0); free(a1); free(j1); free(xp); free(vp);
 }
 
+/* Per-particle potential phi_i = -G sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^(1/2)
+ * (the softened pair potential of the diagnostics, per particle): the specific
+ * energy of particle i is |v_i|^2 / 2 + phi_i, whose distribution Sec. 4.1
+ * (Fig. 4) compares against the double-precision reference. */
+void oracle_potential(int64_t n, const double* x, const double* m, double G, double eps, double* phi) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        nsum sp = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
+            nadd(&sp, m[j] / sqrt(dx * dx + dy * dy + dz * dz + eps * eps));
+        }
+        phi[i] = -G * nval(&sp);
+    }
+}
+
 /* ---- acceleration, jerk and snap (sixth-order Hermite, Sec. 2.1) --------
  * Each particle moves on x_k(t) = x_k + v_k t + acc_k t^2 / 2.  The pair term
  * P(t) = m_j d / s^(3/2), d = x_j - x_i, s = |d|^2 + eps^2, has at t = 0, with

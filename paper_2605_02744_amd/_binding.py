@@ -75,6 +75,7 @@ def load():
                                        ctypes.POINTER(ctypes.c_double), _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_accel_jerk.argtypes = [_I64, _P, _P, _P, _P, _P, PP, _P]
     lib.nbody_step_hermite.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, PP, _P]
+    lib.nbody_potential.argtypes = [_I64, _P, _P, _P, PP, _P]
     lib.nbody_accel_jerk_snap.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, PP, _P]
     lib.nbody_step_hermite6.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_set_config.argtypes = [ctypes.POINTER(nbody_config)]
@@ -85,7 +86,8 @@ def load():
     lib.nbody_version.argtypes = []
     for f in ("nbody_accel", "nbody_step", "nbody_energy", "nbody_accel_vjp", "nbody_traj_grad",
               "nbody_step_batched", "nbody_set_config", "nbody_tune", "nbody_finalize", "nbody_version",
-              "nbody_accel_jerk", "nbody_step_hermite", "nbody_accel_jerk_snap", "nbody_step_hermite6"):
+              "nbody_accel_jerk", "nbody_step_hermite", "nbody_accel_jerk_snap", "nbody_step_hermite6",
+              "nbody_potential"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -246,6 +248,19 @@ def nbody_step_hermite(x, v, a, jk, m, dt, nsteps, *, G=1.0, eps, precision="fp3
                                       _ptr(jk, "jk", (3, n)), _ptr(m, "m", (n,)), float(dt), int(nsteps),
                                       ctypes.byref(p), _stream(x.device)))
     return x, v, a, jk
+
+
+def nbody_potential(x, m, *, G=1.0, eps, check_finite=False, out=None):
+    """Device tensor (N,): phi_i = -G sum_{j != i} m_j / (|d_ij|^2 + eps^2)^(1/2), FP64."""
+    lib = load()
+    n = m.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=x.device)
+    p = _params(G, eps, NBODY_FP64, _flags(False, check_finite))
+    with torch.cuda.device(x.device):
+        _check(lib.nbody_potential(n, _ptr(x, "x", (3, n)), _ptr(m, "m", (n,)), _ptr(out, "phi", (n,)),
+                                   ctypes.byref(p), _stream(x.device)))
+    return out
 
 
 def nbody_accel_jerk_snap(x, v, acc, m, *, G=1.0, eps, precision="fp32c", exclude_self=False, check_finite=False):

@@ -367,6 +367,21 @@ int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* 
   return finish(st, s, p, {{a, 3 * n}, {jk, 3 * n}});
 }
 
+int nbody_potential(int64_t n, const double* x, const double* m, double* phi, const nbody_params* p,
+                    void* stream) {
+  NB_TRY(check_common(n, p, false));
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(phi, b1, "phi"));
+  if ((const double*)phi == x || (const double*)phi == m) return set_error(NBODY_EINVAL, "phi must not alias x or m");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int split = t_cfg.split ? t_cfg.split : auto_split(n, 1, current_device());
+  int st = launch_potential(n, x, m, p->eps, -p->G, phi, split, s);
+  return finish(st, s, p, {{phi, n}});
+}
+
 int nbody_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
                           double* a, double* jk, double* sn, const nbody_params* p, void* stream) {
   NB_TRY(check_common(n, p, true));

@@ -91,6 +91,10 @@ int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s)
 int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double h, double dt,
                       int nkicks, hipStream_t s);
 
+// scale * phi_i, phi_i = sum_{j != i} m_j (|d|^2 + eps^2)^-1/2 in FP64, into phi[n].
+int launch_potential(int64_t n, const double* x, const double* m, double eps, double scale, double* phi,
+                     int split, hipStream_t s);
+
 // Energy/momentum diagnostics into out9 (device).
 int launch_energy(int64_t n, const double* x, const double* v, const double* m, double G,
                   double eps, double* out9, hipStream_t s);

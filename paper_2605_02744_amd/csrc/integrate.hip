@@ -5,9 +5,6 @@
 
 namespace nb {
 
-int launch_potential(int64_t n, const double* x, const double* m, double eps, double* phi, int split,
-                     hipStream_t s);
-
 namespace {
 
 constexpr int kEw = 256;  // threads per block of the elementwise kernels
@@ -256,7 +253,7 @@ int launch_energy(int64_t n, const double* x, const double* v, const double* m, 
     const int64_t iblocks = (n + kBlock - 1) / kBlock;
     const int64_t want = 4LL * cu_count(current_device());
     int split = (int)std::min<int64_t>(64, std::max<int64_t>(1, (want + iblocks - 1) / iblocks));
-    st = launch_potential(n, x, m, eps, phi, split, s);
+    st = launch_potential(n, x, m, eps, 1.0, phi, split, s);
     if (st) return st;
   }
   energy_partial_kernel<<<kRedBlocks, kRedBlock, 0, s>>>(n, x, v, m, phi, G, part);

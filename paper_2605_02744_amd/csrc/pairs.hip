@@ -515,10 +515,11 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
 
 // ============================================================== potential
 // phi_i = sum_{j != i} m_j / sqrt(|d|^2 + eps^2) in FP64, self pair excluded by
-// index.  split == 1: writes phi at out; split > 1: slice y at out + y*n.
+// index.  split == 1: writes scale * phi at out; split > 1: the unscaled slice
+// y at out + y*n.
 __global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* __restrict__ x,
                                                            const double* __restrict__ m, double eps,
-                                                           int chunk, double* __restrict__ out) {
+                                                           double scale, int chunk, double* __restrict__ out) {
   __shared__ double4 tile[2][kTile];
   const int t = threadIdx.x;
   const int i = blockIdx.x * kBlock + t;
@@ -559,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* 
     if (more) tile[(tt + 1) & 1][t] = nxt;
     __syncthreads();
   }
-  if (i < n) out[(size_t)blockIdx.y * n + i] = hp + lp;
+  if (i < n) out[(size_t)blockIdx.y * n + i] = gridDim.y == 1 ? scale * (hp + lp) : hp + lp;
 }
 
 // ============================================================== acceleration + jerk + snap
@@ -906,9 +907,10 @@ int launch_vjp(int64_t n, const double* x, const double* m, const double* w, dou
   return set_error(NBODY_EINVAL, "unknown precision");
 }
 
-// Potential phi_i (FP64) into phi[n]; used by the energy diagnostics.
-int launch_potential(int64_t n, const double* x, const double* m, double eps, double* phi, int split,
-                     hipStream_t s) {
+// scale * phi_i (FP64) into phi[n]; the energy diagnostics use scale = 1,
+// nbody_potential scale = -G.
+int launch_potential(int64_t n, const double* x, const double* m, double eps, double scale, double* phi,
+                     int split, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   const int chunk = split_chunk(n, split);
   const int sp = effective_split(n, split);
@@ -919,10 +921,10 @@ int launch_potential(int64_t n, const double* x, const double* m, double eps, do
     part = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * (size_t)n * sp, &st));
     if (!part) return st;
   }
-  potential_kernel<<<grid, kBlock, 0, s>>>((int)n, x, m, eps, chunk, part);
+  potential_kernel<<<grid, kBlock, 0, s>>>((int)n, x, m, eps, scale, chunk, part);
   NB_LAUNCH_CHECK("potential_kernel");
   if (sp > 1) {
-    sum_slices_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, sp, part, 1.0, n, phi, n, nullptr, nullptr);
+    sum_slices_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, sp, part, scale, n, phi, n, nullptr, nullptr);
     NB_LAUNCH_CHECK("sum_slices_kernel");
   }
   return NBODY_OK;

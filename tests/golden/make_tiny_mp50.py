@@ -9,6 +9,7 @@ arbitrary precision, and does not call the oracle or the GPU library.
 Definitions (Eq. (1) of Sec. 2.1 divided by m_i, Plummer softening of App. A):
   a_i  = G sum_{j != i} m_j d_ij / (|d_ij|^2 + eps^2)^(3/2),   d_ij = x_j - x_i
   W    = -G sum_{i < j} m_i m_j / (|d_ij|^2 + eps^2)^(1/2)
+  phi  : phi_i = -G sum_{j != i} m_j / (|d_ij|^2 + eps^2)^(1/2), per particle
   VJP  : gx_k = sum_i (d a_i / d x_k)^T w_i,  gm_k = sum_i (d a_i / d m_k)^T w_i,
          obtained here by mpmath differentiation of the mpmath acceleration.
   jerk : d/dt a_i(x + V t) at t = 0 for velocities V (mpmath differentiation),
@@ -65,6 +66,19 @@ def potential(x, m, eps, G):
             d = [x[c][j] - x[c][i] for c in range(3)]
             w -= G * m[i] * m[j] / mp.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + eps ** 2)
     return w
+
+
+def phi(x, m, eps, G):
+    n = len(m)
+    out = []
+    for i in range(n):
+        acc = mp.mpf(0)
+        for j in range(n):
+            if j != i:
+                d = [x[c][j] - x[c][i] for c in range(3)]
+                acc -= G * m[j] / mp.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + eps ** 2)
+        out.append(acc)
+    return out
 
 
 def vjp(x, m, w, eps, G):
@@ -126,6 +140,7 @@ def main():
     eps, g = mp.mpf(EPS), mp.mpf(G)
     a = accel(x, m, eps, g)
     pot = potential(x, m, eps, g)
+    ph = phi(x, m, eps, g)
     gx, gm = vjp(x, m, w, eps, g)
     vel = [[mp.mpf(v) for v in row] for row in VEL]
     jk = jerk(x, vel, m, eps, g)
@@ -156,6 +171,7 @@ def main():
             f.write("acc%d %s\n" % (c, " ".join(repr(v) for v in ACC[c])))
         for c in range(3):
             f.write("s%d %s\n" % (c, " ".join(mp.nstr(v, 40) for v in sn[c])))
+        f.write("phi %s\n" % " ".join(mp.nstr(v, 40) for v in ph))
     print("wrote", path)
 
 

@@ -45,7 +45,7 @@ def _read_golden():
     acc = np.stack([d["acc0"], d["acc1"], d["acc2"]])
     sn = np.stack([d["s0"], d["s1"], d["s2"]])
     return dict(x=x, m=d["m"], w=w, a=a, W=float(d["W"][0]), gx=gx, gm=d["gm"], v=vel, j=jk, acc=acc, s=sn,
-                G=float(d["G"][0]), eps=float(d["eps"][0]))
+                phi=d["phi"], G=float(d["G"][0]), eps=float(d["eps"][0]))
 
 
 def test_golden_accel_mp50(oracle_mod):
@@ -481,3 +481,43 @@ def test_hermite6_conserves_momentum_and_energy(oracle_mod):
     x4, _ = oracle_mod.hermite4(x, v, m, 1.0 / 256, 64, eps=eps)
     x4f, _ = oracle_mod.hermite4(x, v, m, 1.0 / 512, 128, eps=eps)
     assert np.abs(x1 - x4f).max() < np.abs(x4 - x4f).max()
+
+
+def test_golden_potential_per_particle_mp50(oracle_mod):
+    g = _read_golden()
+    phi = oracle_mod.potential(g["x"], g["m"], G=g["G"], eps=g["eps"])
+    assert np.abs(phi - g["phi"]).max() <= 4e-16 * np.abs(g["phi"]).max()
+
+
+def test_potential_sums_to_twice_the_pair_energy(oracle_mod):
+    """sum_i m_i phi_i counts every pair twice: 2 W of the separately written
+    pair sum over i < j."""
+    x, v, m = ics.random_cloud(400, seed=81)
+    phi = oracle_mod.potential(x, m, G=1.2, eps=0.03)
+    W = oracle_mod.energy(x, v, m, 1.2, 0.03)[1]
+    assert abs((m * phi).sum() - 2 * W) <= 1e-13 * abs(W)
+
+
+def test_potential_plummer_mean_field(oracle_mod):
+    """For a Plummer sample, phi_i follows the smooth potential -1/(r^2 + b^2)^(1/2)
+    (b = 3 pi / 16, unit mass) up to sampling noise."""
+    x, _, m = ics.plummer(8192, seed=82)
+    phi = oracle_mod.potential(x, m, eps=0.01)
+    r2 = (x ** 2).sum(axis=0)
+    ref = -1.0 / np.sqrt(r2 + (3 * np.pi / 16) ** 2)
+    rel = np.abs(phi - ref) / np.abs(ref)
+    assert np.median(rel) < 0.01 and np.quantile(rel, 0.99) < 0.05
+
+
+def test_potential_gradient_is_minus_acceleration(oracle_mod):
+    """grad_i phi_i with the other particles held fixed is -a_i (central differences)."""
+    x, _, m = ics.random_cloud(50, seed=83)
+    a = oracle_mod.accel(x, m, eps=0.05)
+    h = 1e-6
+    for i in (0, 17, 49):
+        for c in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[c, i] += h
+            xm[c, i] -= h
+            d = (oracle_mod.potential(xp, m, eps=0.05)[i] - oracle_mod.potential(xm, m, eps=0.05)[i]) / (2 * h)
+            assert abs(d + a[c, i]) <= 1e-7 * np.abs(a[:, i]).max()
