@@ -112,7 +112,7 @@ __device__ void system_force(const SysView& sv, int kb, const JRec<MODE>* __rest
     const int i = sv.i0 + (il < sv.ni ? il : sv.ni - 1);
     ii[k] = il < sv.ni ? i : -1;
     pi[k].from(rec[i]);
-    if constexpr (kNear) rc2[k] = near_rc2(pi[k].hx, pi[k].hy, pi[k].hz, eps);
+    if constexpr (kNear) rc2[k] = near_rc2(pi[k].hx, pi[k].hy, pi[k].hz, eps, sv.nc);
     hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = R(0);
   }
   for (int f = sv.j0; f < sv.j1; f += kFold) {

@@ -108,13 +108,22 @@ __device__ __forceinline__ double rsq(double r2) { return rsqrt64(r2); }
 __device__ __forceinline__ float rsq(float r2) { return rsqrt32(r2); }
 
 // Near-field repair of FP32C pairs (see accel_kernel): a pair closer than
-// d_c(i) = max(kNearX |x_i|_inf, kNearEps eps) gets a float-float displacement.
+//   d_c(i) = max(max(kNearX, kNearN n^-1/3) |x_i|_inf, kNearEps eps)
+// gets a float-float displacement.  Rounding a coordinate to FP32 moves it by
+// up to u |x| (u = 2^-24), which changes a pair term m_j d / |d|^3 by about
+// 3 u |x| m_j / |d|^3.  The first bound keeps that below 3u / kNearX^3 of the
+// pair's own term; the second keeps it below 3u / kNearN^3 of G M / |x|^2 for
+// a pair of mass M / n, which matters in small systems, where one pair at the
+// radius can outweigh the whole acceleration of particle i.
 constexpr float kNearX = 2.0e-2f;
+constexpr float kNearN = 1.0f;
 constexpr float kNearEps = 2.0f;
 
-// Squared repair radius of lane particle i (positions given in double).
-__device__ __forceinline__ float near_rc2(double xa, double ya, double za, double eps) {
-  const float dc = fmaxf(kNearX * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
+// Squared repair radius of lane particle i (positions given in double) in a
+// system of n particles.
+__device__ __forceinline__ float near_rc2(double xa, double ya, double za, double eps, int n) {
+  const float fx = fmaxf(kNearX, kNearN / cbrtf((float)(n > 0 ? n : 1)));
+  const float dc = fmaxf(fx * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
   return dc * dc + (float)(eps * eps);
 }
 

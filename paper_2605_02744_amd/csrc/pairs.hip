@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
     int ic = i < n ? i : n - 1;
     const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
     pi[k].set(xa, ya, za);
-    rc2[k] = (R)near_rc2(xa, ya, za, eps);
+    rc2[k] = (R)near_rc2(xa, ya, za, eps, n);
   }
   R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
 #pragma unroll
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
     pi[k].set(xa, ya, za);
     mk[k] = (R)m[ic];
     wkx[k] = (R)w[ic]; wky[k] = (R)w[n + ic]; wkz[k] = (R)w[2 * n + ic];
-    rc2[k] = (R)near_rc2(xa, ya, za, eps);
+    rc2[k] = (R)near_rc2(xa, ya, za, eps, n);
   }
   R hx[IPL], hy[IPL], hz[IPL], hm[IPL], lx[IPL], ly[IPL], lz[IPL], lm[IPL];
 #pragma unroll
@@ -404,9 +404,33 @@ __global__ __launch_bounds__(kBlock) void vjp_kernel(int n, const double* __rest
 // App. A, Algorithm 3 in full: per pair r_ij, v_ij, t_j = m_j r^-3,
 // A = -3 r^-2, v_r = r_ij . v_ij, q = A v_r; a += t_j r_ij and
 // jerk += t_j (v_ij + q r_ij), with r^2 = |r_ij|^2 + eps^2.  Records carry the
-// position record plus the velocity (FP32C: float-float positions, FP32
-// velocities).  split == 1 writes G*sums to a and jk; split > 1 writes slice
-// y's unscaled 6n partials (a then jerk) at part + y*6n.
+// position record plus the velocity (FP32 velocities in the FP32 modes).
+// FP32C uses the near-field repair of accel_kernel: displacements from
+// FP32-rounded positions, and a block of kFold j's holding a pair closer than
+// the lane's repair radius is redone with float-float displacements for those
+// pairs.  split == 1 writes G*sums to a and jk; split > 1 writes slice y's
+// unscaled 6n partials (a then jerk) at part + y*6n.
+template <typename R>
+__device__ __forceinline__ R jerk_pair(R dx, R dy, R dz, R wx, R wy, R wz, R mj, R e2, bool self, R* pa, R* pj) {
+  const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+  const R ri = rsq(r2);
+  R ri2 = ri * ri;
+  R tj = (mj * ri) * ri2;                            // t_j = p_w,j r^-3
+  if (self) {
+    tj = R(0);
+    ri2 = R(0);
+  }
+  const R vr = fma(dz, wz, fma(dy, wy, dx * wx));    // v_r = r . v
+  const R qq = R(-3) * ri2 * vr;                     // q = A v_r, A = -3 r^-2
+  pa[0] = fma(tj, dx, pa[0]);
+  pa[1] = fma(tj, dy, pa[1]);
+  pa[2] = fma(tj, dz, pa[2]);
+  pj[0] = fma(tj, fma(qq, dx, wx), pj[0]);
+  pj[1] = fma(tj, fma(qq, dy, wy), pj[1]);
+  pj[2] = fma(tj, fma(qq, dz, wz), pj[2]);
+  return r2;
+}
+
 template <int MODE, int IPL, bool EXCL>
 __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __restrict__ x,
                                                       const double* __restrict__ v,
@@ -414,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
                                                       int chunk, double* __restrict__ a, double* __restrict__ jk,
                                                       double* __restrict__ part) {
   using R = Real<MODE>;
+  constexpr bool kNear = MODE == kFP32C;
   __shared__ WRec<MODE> tile[2][kTile];
   const int t = threadIdx.x;
   const int ibase = blockIdx.x * (kBlock * IPL) + t;
@@ -422,14 +447,16 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
   const R e2 = (R)(eps * eps);
 
   IPos<MODE> pi[IPL];
-  R vx[IPL], vy[IPL], vz[IPL];
+  R vx[IPL], vy[IPL], vz[IPL], rc2[IPL];
   int iidx[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     int i = ibase + k * kBlock;
     iidx[k] = i;
     int ic = i < n ? i : n - 1;
-    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+    const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
+    pi[k].set(xa, ya, za);
+    rc2[k] = (R)near_rc2(xa, ya, za, eps, n);
     vx[k] = (R)v[ic]; vy[k] = (R)v[n + ic]; vz[k] = (R)v[2 * n + ic];
   }
   R ah[3][IPL], al[3][IPL], jh[3][IPL], jl[3][IPL];
@@ -451,11 +478,13 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
     const WRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
     for (int f = 0; f < fend; f += kFold) {
-      R pa[3][IPL], pj[3][IPL];
+      R pa[IPL][3], pj[IPL][3], r2min[IPL];
 #pragma unroll
-      for (int k = 0; k < IPL; ++k)
+      for (int k = 0; k < IPL; ++k) {
+        r2min[k] = R(3.0e38f);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pa[c][k] = pj[c][k] = R(0);
+        for (int c = 0; c < 3; ++c) pa[k][c] = pj[k][c] = R(0);
+      }
 #pragma unroll 8
       for (int jj = f; jj < f + kFold; ++jj) {
         const WRec<MODE> q = cur[jj];
@@ -463,33 +492,53 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
           R dx, dy, dz;
-          disp(q.r, pi[k], dx, dy, dz);                     // r_ij
-          const R wx = q.w.x - vx[k], wy = q.w.y - vy[k], wz = q.w.z - vz[k];  // v_ij
-          const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-          const R ri = rsq(r2);
-          R ri2 = ri * ri;
-          R tj = (mj * ri) * ri2;                            // t_j = p_w,j r^-3
-          if (EXCL) {
-            const bool self = (jt + jj == iidx[k]);
-            tj = self ? R(0) : tj;
-            ri2 = self ? R(0) : ri2;
+          if constexpr (kNear) disp_hi(q.r, pi[k], dx, dy, dz);
+          else disp(q.r, pi[k], dx, dy, dz);
+          const R r2 = jerk_pair<R>(dx, dy, dz, q.w.x - vx[k], q.w.y - vy[k], q.w.z - vz[k], mj, e2,
+                                    EXCL && (jt + jj == iidx[k]), pa[k], pj[k]);
+          if constexpr (kNear) r2min[k] = fminf(r2min[k], r2);
+        }
+      }
+      if constexpr (kNear) {
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+          // in the block holding the lane's own pair, rescan for another close pair
+          bool close = r2min[k] < rc2[k];
+          if (close && (unsigned)(iidx[k] - (jt + f)) < (unsigned)kFold) {
+            close = false;
+            for (int jj = f; jj < f + kFold; ++jj) {
+              R dx, dy, dz;
+              disp_hi(cur[jj].r, pi[k], dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              close = close || (r2 < rc2[k] && jt + jj != iidx[k]);
+            }
           }
-          const R vr = fma(dz, wz, fma(dy, wy, dx * wx));    // v_r = r . v
-          const R qq = R(-3) * ri2 * vr;                     // q = A v_r, A = -3 r^-2
-          pa[0][k] = fma(tj, dx, pa[0][k]);
-          pa[1][k] = fma(tj, dy, pa[1][k]);
-          pa[2][k] = fma(tj, dz, pa[2][k]);
-          pj[0][k] = fma(tj, fma(qq, dx, wx), pj[0][k]);
-          pj[1][k] = fma(tj, fma(qq, dy, wy), pj[1][k]);
-          pj[2][k] = fma(tj, fma(qq, dz, wz), pj[2][k]);
+          if (close) {
+            // rare: redo this block for lane k with float-float displacements for the close pairs
+            R qa[3] = {R(0), R(0), R(0)}, qj[3] = {R(0), R(0), R(0)};
+            for (int jj = f; jj < f + kFold; ++jj) {
+              const WRec<MODE> q = cur[jj];
+              R dx, dy, dz;
+              disp_hi(q.r, pi[k], dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 < rc2[k]) disp(q.r, pi[k], dx, dy, dz);
+              jerk_pair<R>(dx, dy, dz, q.w.x - vx[k], q.w.y - vy[k], q.w.z - vz[k], jmass(q.r), e2,
+                           EXCL && (jt + jj == iidx[k]), qa, qj);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              pa[k][c] = qa[c];
+              pj[k][c] = qj[c];
+            }
+          }
         }
       }
 #pragma unroll
       for (int k = 0; k < IPL; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          fold(ah[c][k], al[c][k], pa[c][k]);
-          fold(jh[c][k], jl[c][k], pj[c][k]);
+          fold(ah[c][k], al[c][k], pa[k][c]);
+          fold(jh[c][k], jl[c][k], pj[k][c]);
         }
     }
     if (more) tile[(tt + 1) & 1][t] = nxt;
@@ -506,8 +555,8 @@ __global__ __launch_bounds__(kBlock) void jerk_kernel(int n, const double* __res
     if (i < n) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        oa[c * (size_t)n + i] = scale * ((double)ah[c][k] + (double)al[c][k]);
-        oj[c * (size_t)n + i] = scale * ((double)jh[c][k] + (double)jl[c][k]);
+        oa[c * n + i] = scale * ((double)ah[c][k] + (double)al[c][k]);
+        oj[c * n + i] = scale * ((double)jh[c][k] + (double)jl[c][k]);
       }
     }
   }
@@ -571,9 +620,10 @@ __global__ __launch_bounds__(kBlock) void potential_kernel(int n, const double* 
 //   P'' = t_j u - 6 alpha P' - 3 beta P,      beta  = (w . w + d . u) / s + alpha^2
 // with w = v_j - v_i and u = acc_j - acc_i; a, jerk and snap are G times their
 // sums.  Records carry the position record plus velocity and acceleration
-// (FP32C: float-float positions, FP32 velocity and acceleration differences).
-// split == 1 writes G*sums to a, jk and sn; split > 1 writes slice y's
-// unscaled 9n partials (a, jerk, snap) at part + y*9n.
+// (FP32 velocity and acceleration differences in the FP32 modes; FP32C with
+// the near-field repair of accel_kernel).  split == 1 writes G*sums to a, jk
+// and sn; split > 1 writes slice y's unscaled 9n partials (a, jerk, snap) at
+// part + y*9n.
 template <int MODE> struct SRec {
   using V4 = typename std::conditional<MODE == kFP64, double4, float4>::type;
   JRec<MODE> r;
@@ -599,6 +649,34 @@ __device__ __forceinline__ SRec<MODE> load_srec(const double* __restrict__ x, co
   return o;
 }
 
+template <typename R>
+__device__ __forceinline__ R snap_pair(const R* d, const R* w, const R* u, R mj, R e2, bool self, R* pa, R* pj,
+                                       R* ps) {
+  const R r2 = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], e2)));
+  const R ri = rsq(r2);
+  R sinv = ri * ri;
+  R tj = (mj * ri) * sinv;
+  if (self) {
+    tj = R(0);
+    sinv = R(0);
+  }
+  const R alpha = fma(d[2], w[2], fma(d[1], w[1], d[0] * w[0])) * sinv;
+  const R wwdu = fma(d[2], u[2], fma(d[1], u[1], fma(d[0], u[0], fma(w[2], w[2], fma(w[1], w[1], w[0] * w[0])))));
+  const R beta = fma(wwdu, sinv, alpha * alpha);
+  const R a3 = R(-3) * alpha;
+  const R b3 = R(-3) * beta;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R P0 = tj * d[c];
+    const R P1 = fma(a3, P0, tj * w[c]);
+    const R P2 = fma(R(2) * a3, P1, fma(b3, P0, tj * u[c]));
+    pa[c] += P0;
+    pj[c] += P1;
+    ps[c] += P2;
+  }
+  return r2;
+}
+
 template <int MODE, int IPL, bool EXCL>
 __global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __restrict__ x,
                                                       const double* __restrict__ v,
@@ -607,6 +685,7 @@ __global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __res
                                                       int chunk, double* __restrict__ a, double* __restrict__ jk,
                                                       double* __restrict__ sn, double* __restrict__ part) {
   using R = Real<MODE>;
+  constexpr bool kNear = MODE == kFP32C;
   __shared__ SRec<MODE> tile[2][kTile];
   const int t = threadIdx.x;
   const int ibase = blockIdx.x * (kBlock * IPL) + t;
@@ -615,14 +694,16 @@ __global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __res
   const R e2 = (R)(eps * eps);
 
   IPos<MODE> pi[IPL];
-  R vi[3][IPL], ui[3][IPL];
+  R vi[3][IPL], ui[3][IPL], rc2[IPL];
   int iidx[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     int i = ibase + k * kBlock;
     iidx[k] = i;
     int ic = i < n ? i : n - 1;
-    pi[k].set(x[ic], x[n + ic], x[2 * n + ic]);
+    const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
+    pi[k].set(xa, ya, za);
+    rc2[k] = (R)near_rc2(xa, ya, za, eps, n);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       vi[c][k] = (R)v[c * n + ic];
@@ -648,11 +729,13 @@ __global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __res
     const SRec<MODE>* cur = tile[tt & 1];
 #pragma unroll 1
     for (int f = 0; f < fend; f += kFold) {
-      R pa[3][IPL], pj[3][IPL], ps[3][IPL];
+      R pa[IPL][3], pj[IPL][3], ps[IPL][3], r2min[IPL];
 #pragma unroll
-      for (int k = 0; k < IPL; ++k)
+      for (int k = 0; k < IPL; ++k) {
+        r2min[k] = R(3.0e38f);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pa[c][k] = pj[c][k] = ps[c][k] = R(0);
+        for (int c = 0; c < 3; ++c) pa[k][c] = pj[k][c] = ps[k][c] = R(0);
+      }
 #pragma unroll 4
       for (int jj = f; jj < f + kFold; ++jj) {
         const SRec<MODE> q = cur[jj];
@@ -660,32 +743,47 @@ __global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __res
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
           R d[3];
-          disp(q.r, pi[k], d[0], d[1], d[2]);
+          if constexpr (kNear) disp_hi(q.r, pi[k], d[0], d[1], d[2]);
+          else disp(q.r, pi[k], d[0], d[1], d[2]);
           const R w[3] = {q.v.x - vi[0][k], q.v.y - vi[1][k], q.v.z - vi[2][k]};
           const R u[3] = {q.u.x - ui[0][k], q.u.y - ui[1][k], q.u.z - ui[2][k]};
-          const R r2 = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], e2)));
-          const R ri = rsq(r2);
-          R sinv = ri * ri;
-          R tj = (mj * ri) * sinv;
-          if (EXCL) {
-            const bool self = (jt + jj == iidx[k]);
-            tj = self ? R(0) : tj;
-            sinv = self ? R(0) : sinv;
-          }
-          const R alpha = fma(d[2], w[2], fma(d[1], w[1], d[0] * w[0])) * sinv;
-          const R wwdu = fma(d[2], u[2], fma(d[1], u[1], fma(d[0], u[0],
-                             fma(w[2], w[2], fma(w[1], w[1], w[0] * w[0])))));
-          const R beta = fma(wwdu, sinv, alpha * alpha);
-          const R a3 = R(-3) * alpha;
-          const R b3 = R(-3) * beta;
+          const R r2 = snap_pair<R>(d, w, u, mj, e2, EXCL && (jt + jj == iidx[k]), pa[k], pj[k], ps[k]);
+          if constexpr (kNear) r2min[k] = fminf(r2min[k], r2);
+        }
+      }
+      if constexpr (kNear) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const R P0 = tj * d[c];
-            const R P1 = fma(a3, P0, tj * w[c]);
-            const R P2 = fma(R(2) * a3, P1, fma(b3, P0, tj * u[c]));
-            pa[c][k] += P0;
-            pj[c][k] += P1;
-            ps[c][k] += P2;
+        for (int k = 0; k < IPL; ++k) {
+          // in the block holding the lane's own pair, rescan for another close pair
+          bool close = r2min[k] < rc2[k];
+          if (close && (unsigned)(iidx[k] - (jt + f)) < (unsigned)kFold) {
+            close = false;
+            for (int jj = f; jj < f + kFold; ++jj) {
+              R dx, dy, dz;
+              disp_hi(cur[jj].r, pi[k], dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              close = close || (r2 < rc2[k] && jt + jj != iidx[k]);
+            }
+          }
+          if (close) {
+            // rare: redo this block for lane k with float-float displacements for the close pairs
+            R qa[3] = {R(0), R(0), R(0)}, qj[3] = {R(0), R(0), R(0)}, qs[3] = {R(0), R(0), R(0)};
+            for (int jj = f; jj < f + kFold; ++jj) {
+              const SRec<MODE> q = cur[jj];
+              R d[3];
+              disp_hi(q.r, pi[k], d[0], d[1], d[2]);
+              const R r2 = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], e2)));
+              if (r2 < rc2[k]) disp(q.r, pi[k], d[0], d[1], d[2]);
+              const R w[3] = {q.v.x - vi[0][k], q.v.y - vi[1][k], q.v.z - vi[2][k]};
+              const R u[3] = {q.u.x - ui[0][k], q.u.y - ui[1][k], q.u.z - ui[2][k]};
+              snap_pair<R>(d, w, u, jmass(q.r), e2, EXCL && (jt + jj == iidx[k]), qa, qj, qs);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              pa[k][c] = qa[c];
+              pj[k][c] = qj[c];
+              ps[k][c] = qs[c];
+            }
           }
         }
       }
@@ -693,9 +791,9 @@ __global__ __launch_bounds__(kBlock) void snap_kernel(int n, const double* __res
       for (int k = 0; k < IPL; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          fold(ah[c][k], al[c][k], pa[c][k]);
-          fold(jh[c][k], jl[c][k], pj[c][k]);
-          fold(sh[c][k], sl[c][k], ps[c][k]);
+          fold(ah[c][k], al[c][k], pa[k][c]);
+          fold(jh[c][k], jl[c][k], pj[k][c]);
+          fold(sh[c][k], sl[c][k], ps[k][c]);
         }
     }
     if (more) tile[(tt + 1) & 1][t] = nxt;

@@ -49,6 +49,24 @@ def test_accel_ragged_sizes(nb, oracle_mod, n, prec):
     assert rel_err(a, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("n", [64, 300, 2049])
+def test_accel_fp32c_small_systems_many_seeds(nb, oracle_mod, n):
+    """Small systems have heavy particles: one pair just outside a fixed
+    near-field radius can carry more than the particle's whole acceleration,
+    so the repair radius grows as n^-1/3 (regression: a 2049-body Plummer
+    sample reached 1.5e-5 with a radius of 0.02 |x| alone)."""
+    worst = 0.0
+    for seed in range(12):
+        x, v, m = ics.plummer(n, seed=1000 * n + seed)
+        ref = oracle_mod.accel(x, m, G=1.1, eps=0.01)
+        a = nb.nbody_accel(dev(x), dev(m), G=1.1, eps=0.01, precision="fp32c").cpu().numpy()
+        ra, rj = oracle_mod.accel_jerk(x, v, m, G=1.1, eps=0.01)
+        aj, jk = nb.nbody_accel_jerk(dev(x), dev(v), dev(m), G=1.1, eps=0.01, precision="fp32c")
+        worst = max(worst, rel_err(a, ref), rel_err(aj.cpu().numpy(), ra))
+    print("n=%d worst fp32c accel error over 12 seeds %.2e" % (n, worst))
+    assert worst <= 1e-5
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 @pytest.mark.parametrize("ipl,split", [(1, 1), (2, 1), (4, 1), (1, 3), (2, 7), (4, 16), (2, 0), (1, 64)])
 def test_accel_tile_configs(nb, oracle_mod, prec, ipl, split):
@@ -347,6 +365,45 @@ def test_batched_repeat_and_graph_capture(nb):
         torch.cuda.synchronize()
         _ = (gx.sum() + 1.0).item()  # eager work between replays
         assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
+
+
+@pytest.mark.parametrize("kind", ["kdk", "hermite6"])
+def test_single_system_graph_capture(nb, kind):
+    """nbody_step and nbody_step_hermite6 captured into a HIP graph (after one
+    eager call has sized the library's workspace) replay bitwise like eager
+    calls, with eager work and synchronisation between the replays."""
+    x, v, m = ics.plummer(3001, seed=19)
+    dt = 1.0 / 256
+    tm = dev(m)
+
+    def state():
+        tx, tv = dev(x), dev(v)
+        return [tx, tv] + [torch.empty_like(tx) for _ in range(1 if kind == "kdk" else 4)]
+
+    def call(st, valid):
+        if kind == "kdk":
+            nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
+        else:
+            nb.nbody_step_hermite6(st[0], st[1], *st[2:], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
+
+    eager = state()
+    call(eager, False)
+    ref = []
+    for _ in range(3):
+        call(eager, True)
+        ref.append([q.clone() for q in eager[:2]])
+    graph = state()
+    call(graph, False)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        call(graph, True)
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (graph[0].sum() + 1.0).item()  # eager work between replays
+        assert torch.equal(graph[0], ref[k][0]) and torch.equal(graph[1], ref[k][1]), k
 
 
 def test_abi_rejects_bad_pointers(nb):
