@@ -116,7 +116,7 @@ __device__ __forceinline__ float rsq(float r2) { return rsqrt32(r2); }
 // a pair of mass M / n, which matters in small systems, where one pair at the
 // radius can outweigh the whole acceleration of particle i.
 constexpr float kNearX = 2.0e-2f;
-constexpr float kNearN = 1.0f;
+constexpr float kNearN = 0.5f;
 constexpr float kNearEps = 2.0f;
 
 // Squared repair radius of lane particle i (positions given in double) in a
