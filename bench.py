@@ -230,7 +230,8 @@ def bench_ensemble(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     sizes = np.diff(off)
     pairs = float((sizes * (sizes - 1)).sum())
-    nb.nbody_set_config(bsplit=1 if args.split else 0, bpass=args.bpass)
+    mode = args.bsplit if args.bsplit is not None else (1 if args.split else 0)
+    nb.nbody_set_config(bsplit=mode, bpass=args.bpass)
     res, drift = {}, {}
 
     def energies(tx, tv):
@@ -259,7 +260,7 @@ def bench_ensemble(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": 1, "split_large_systems": bool(args.split), "bpass": args.bpass},
+                       "launches": 1, "kernel_mode": mode, "bpass": args.bpass},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift_per_cluster": drift,
             "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),
@@ -455,6 +456,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work in the CPU baseline")
     ap.add_argument("--split", action="store_true", help="ensemble: split the largest systems over workgroups")
+    ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2],
+                    help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items")
     ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:

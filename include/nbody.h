@@ -239,9 +239,16 @@ int nbody_step_hermite6(int64_t n, double* x, double* v, double* a, double* jk, 
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
   int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
-  int32_t bsplit;  /* batched kernel: 0 = one workgroup per system (default),
-                      1 = split systems costlier than the per-CU average across up
-                      to 4 workgroups that exchange positions every step */
+  int32_t bsplit;  /* batched kernel: 0 = one workgroup per system, its records
+                      resident in LDS (default); 1 = as 0, but systems costlier than
+                      the per-CU average split across up to 4 workgroups that
+                      exchange positions every step; 2 = streamed: every system cut
+                      into items of <= 128 particles spread over up to 8 resident
+                      256-lane workgroups per CU, records streamed through LDS tiles,
+                      items of a system synchronised every step.  Modes 1 and 2
+                      need every workgroup of the launch resident at once: with
+                      another kernel occupying the GPU a bounded wait can expire,
+                      and the affected systems then end NaN. */
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
 } nbody_config;

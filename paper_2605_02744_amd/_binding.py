@@ -292,8 +292,10 @@ def nbody_step_hermite6(x, v, a, jk, sn, cr, m, dt, nsteps, *, G=1.0, eps, preci
 def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0):
     """Forces a tile configuration on this thread (all zeros = automatic);
     bsplit=1 lets the ensemble kernel split its largest systems over up to 4
-    workgroups (default 0: one workgroup per system); bpass sets how many of
-    a lane's i-particles the ensemble kernel evaluates per pass (1, 2, 4)."""
+    workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
+    items of <= 128 particles), default 0: one workgroup per system; bpass sets
+    how many of a lane's i-particles the ensemble kernel evaluates per pass
+    (1, 2, 4)."""
     c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass))
     _check(load().nbody_set_config(ctypes.byref(c)))
 

@@ -22,6 +22,7 @@ int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, d
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
                 bool acc_valid, hipStream_t s);
 void release_batched_plans();
+void release_stream_plans();
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -452,7 +453,7 @@ int nbody_set_config(const nbody_config* cfg) {
   if (cfg->ipl != 0 && cfg->ipl != 1 && cfg->ipl != 2 && cfg->ipl != 4)
     return set_error(NBODY_EINVAL, "ipl must be 0, 1, 2 or 4");
   if (cfg->split < 0 || cfg->split > 1024) return set_error(NBODY_EINVAL, "split must be in 0..1024");
-  if (cfg->bsplit != 0 && cfg->bsplit != 1) return set_error(NBODY_EINVAL, "bsplit must be 0 or 1");
+  if (cfg->bsplit < 0 || cfg->bsplit > 2) return set_error(NBODY_EINVAL, "bsplit must be 0, 1 or 2");
   if (cfg->bpass != 0 && cfg->bpass != 1 && cfg->bpass != 2 && cfg->bpass != 4)
     return set_error(NBODY_EINVAL, "bpass must be 0, 1, 2 or 4");
   set_thread_config(*cfg);
@@ -548,6 +549,7 @@ const char* nbody_last_error(void) { return g_err.c_str(); }
 
 int nbody_finalize(void) {
   release_batched_plans();
+  release_stream_plans();
   release_workspaces();
   return NBODY_OK;
 }

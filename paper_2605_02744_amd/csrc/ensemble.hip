@@ -575,9 +575,15 @@ int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m,
 
 }  // namespace
 
+int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                       const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
+                       bool acc_valid, hipStream_t s);
+
 int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
                 hipStream_t s) {
+  if (thread_config().bsplit == 2)
+    return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, s);
   const int device = current_device();
   const bool allow_split = thread_config().bsplit == 1;
   std::lock_guard<std::mutex> lk(g_plan_mu);

@@ -1,0 +1,446 @@
+// Streamed persistent ensemble integrator (nbody_config.bsplit = 2).
+//
+// Many independent softened systems advanced for all KDK steps in ONE launch,
+// with the work cut finer than whole systems so that no CU waits on one large
+// system.  Every system is split into items of at most 512 i-particles; a
+// 1024-lane workgroup evaluates one item at a time with its lanes in j-groups
+// (2 groups of 512 lanes for large systems, up to 16 groups of 64 for small
+// ones), streaming the system's pair records through a double-buffered LDS
+// tile as the single-system force kernel does, and combining the groups'
+// (hi, lo) sums through LDS in group order.  Items are assigned
+// longest-processing-time first over the workgroups that can be resident at
+// once (two per CU at <= 64 VGPRs: 8 waves per SIMD, the occupancy of the
+// single-system kernel).
+//
+// The loop is step-major.  In every round each workgroup
+//   A. kick-drifts the particles it owns (one lane per particle, FP64 state in
+//      global memory), writes their pair records to the round's half of a
+//      double-buffered record array, and publishes: every wave waits for its
+//      stores, then after a barrier one lane issues an agent-scope release
+//      fence and increments its items' system counters;
+//   B. one lane polls (bounded) until every system it holds items of has all
+//      its items published for this round, then issues one agent-scope
+//      acquire fence, and after a barrier the workgroup evaluates its items.
+// Agent-scope fences write back or invalidate a whole XCD's L2, and the L2
+// serialises them (about 0.3 us each, measured): one release and one acquire
+// per workgroup per round, and few large workgroups, keep their cost small.
+// Phase A never waits, so all publications of a round happen once every
+// workgroup has finished the previous round's phase B; with every workgroup
+// resident this cannot deadlock.  Record buffers alternate by round: a
+// workgroup rewrites a buffer only after all readers of that system have
+// published the next round, i.e. finished reading it.  A wait that exceeds
+// its bound (a workgroup that never became resident) makes the workgroup
+// publish NaN records from then on, so every system coupled to it ends NaN
+// instead of silently wrong, and the kernel still terminates.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <queue>
+#include <vector>
+
+#include "pair_math.h"
+
+namespace nb {
+namespace {
+
+constexpr int kSBlock = 1024;           // lanes per workgroup
+constexpr int kSMaxPerCu = 2;           // resident workgroups per CU at most
+constexpr int kSWaves = 8;              // waves per SIMD the kernel is built for (<= 64 VGPRs)
+constexpr int kSSpin = 1 << 22;         // polls of a counter before giving up
+
+struct SItem {
+  int sys;  // system
+  int i0;   // first particle of the item (system-local)
+  int ni;   // particles in the item, <= kSBlock / js
+  int js;   // j-groups: 2, 4, 8 or 16
+};
+
+template <int MODE> struct SPart { Real<MODE> hx, lx, hy, ly, hz, lz; };
+
+template <int MODE, bool EXCL>
+__global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
+    const int64_t* __restrict__ off, const double* __restrict__ epsv, const int* __restrict__ nparts,
+    const SItem* __restrict__ items, const int* __restrict__ wg_off, const int* __restrict__ wg_list,
+    double* __restrict__ x, double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m,
+    JRec<MODE>* __restrict__ xrec, int* __restrict__ cnt, int64_t total, double dt, int64_t nsteps, double G,
+    int acc_valid) {
+  using R = Real<MODE>;
+  constexpr bool kNear = MODE == kFP32C;
+  static_assert(sizeof(SPart<MODE>) * kSBlock <= sizeof(JRec<MODE>) * 2 * kSBlock, "group partials alias the tiles");
+  __shared__ JRec<MODE> tile[2][kSBlock];
+  __shared__ int lds_bad;
+  SPart<MODE>* gpart = reinterpret_cast<SPart<MODE>*>(&tile[0][0]);
+  const int t = threadIdx.x;
+  const double h = 0.5 * dt;
+  const int q0 = wg_off[blockIdx.x], q1 = wg_off[blockIdx.x + 1];
+  bool bad = false;  // a wait of this workgroup timed out (uniform)
+
+  const int64_t rounds = nsteps + (acc_valid ? 0 : 1);
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t s = acc_valid ? r : r - 1;  // step of this round; -1: the initial evaluation
+    JRec<MODE>* xb = xrec + (size_t)(r & 1) * total;
+    // ---- phase A: kick-drift the owned particles and publish their records
+    for (int q = q0; q < q1; ++q) {
+      const SItem it = items[wg_list[q]];
+      const int64_t o = off[it.sys];
+      if (t < it.ni) {
+        const int64_t i = o + it.i0 + t;
+        double xn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int64_t e = d * total + i;
+          if (s >= 0) {
+            double ve = v[e];
+            const double ae = a[e];
+            ve = fma(h, ae, ve);
+            if (s > 0) ve = fma(h, ae, ve);  // closing half-kick of the previous step, rounded separately
+            v[e] = ve;
+            xn[d] = fma(dt, ve, x[e]);
+            x[e] = xn[d];
+          } else {
+            xn[d] = x[e];
+          }
+        }
+        xb[i] = bad ? JRec<MODE>::make(NAN, NAN, NAN, NAN) : JRec<MODE>::make(xn[0], xn[1], xn[2], m[i]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+    __syncthreads();
+    if (t == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int q = q0; q < q1; ++q)
+        __hip_atomic_fetch_add(cnt + items[wg_list[q]].sys, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // ---- wait until every item of every system held here has published this round.
+      // Counters wrap modulo 2^32 and are never more than one round ahead of `want`;
+      // after one expired wait the workgroup stops waiting (its results are NaN anyway).
+      int ok = bad ? 0 : 1;
+      for (int q = q0; q < q1 && ok; ++q) {
+        const int sys = items[wg_list[q]].sys;
+        const unsigned want = (unsigned)nparts[sys] * (unsigned)(r + 1);
+        int polls = 0;
+        while (ok && (int)((unsigned)__hip_atomic_load(cnt + sys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                           want) < 0) {
+          if (++polls > kSSpin) ok = 0;
+          else __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      lds_bad = ok ? 0 : 1;
+    }
+    __syncthreads();
+    bad = bad || lds_bad != 0;
+
+    // ---- phase B: evaluate the items
+    for (int q = q0; q < q1; ++q) {
+      const SItem it = items[wg_list[q]];
+      const int64_t o = off[it.sys];
+      const int nc = (int)(off[it.sys + 1] - o);
+      const JRec<MODE>* src = xb + o;
+      const int gsz = kSBlock / it.js;
+      const int g = t / gsz, l = t - g * gsz;
+      const int il = l < it.ni ? l : it.ni - 1;
+      const int ii = it.i0 + il;  // system-local index of the lane's particle
+      const int iself = l < it.ni ? ii : -1;
+      const double eps = epsv[it.sys];
+      const R e2 = (R)(eps * eps);
+      IPos<MODE> pi;
+      pi.from(src[ii]);
+      R rc2 = R(0);
+      if constexpr (kNear) rc2 = near_rc2(pi.hx, pi.hy, pi.hz, eps, nc);
+      R hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
+      const int ntiles = (nc + kSBlock - 1) / kSBlock;
+      tile[0][t] = t < nc ? src[t] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+      __syncthreads();
+      for (int tt = 0; tt < ntiles; ++tt) {
+        const int jt = tt * kSBlock;
+        const bool more = tt + 1 < ntiles;
+        JRec<MODE> nxt;
+        if (more) {
+          const int jn = jt + kSBlock + t;
+          nxt = jn < nc ? src[jn] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+        }
+        const JRec<MODE>* cur = tile[tt & 1];
+        // this group's slice of the tile: records [g*gsz, (g+1)*gsz), padding skipped by fold blocks
+        const int jg = jt + g * gsz;
+        const int cntg = min(gsz, max(0, nc - jg));
+        const int fend = g * gsz + (cntg + kFold - 1) / kFold * kFold;
+#pragma unroll 1
+        for (int f = g * gsz; f < fend; f += kFold) {
+          R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
+#pragma unroll 16
+          for (int jj = f; jj < f + kFold; ++jj) {
+            const JRec<MODE> rj = cur[jj];
+            R dx, dy, dz;
+            if constexpr (kNear) disp_hi(rj, pi, dx, dy, dz);
+            else disp(rj, pi, dx, dy, dz);
+            const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+            const R ri = rsq(r2);
+            R sc = (jmass(rj) * ri) * (ri * ri);
+            if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+            px = fma(sc, dx, px);
+            py = fma(sc, dy, py);
+            pz = fma(sc, dz, pz);
+            if constexpr (kNear) r2min = fminf(r2min, r2);
+          }
+          if constexpr (kNear) {
+            // the lane's own pair always has r2 = eps^2: in its block, rescan for another close pair
+            bool close = r2min < rc2;
+            if (close && (unsigned)(iself - (jt + f)) < (unsigned)kFold) {
+              close = false;
+              for (int jj = f; jj < f + kFold; ++jj) {
+                R dx, dy, dz;
+                disp_hi(cur[jj], pi, dx, dy, dz);
+                const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+                close = close || (r2 < rc2 && jt + jj != iself);
+              }
+            }
+            if (close) {
+              // rare: redo this block with float-float displacements for the close pairs
+              R qx = 0, qy = 0, qz = 0;
+              for (int jj = f; jj < f + kFold; ++jj) {
+                const JRec<MODE> rj = cur[jj];
+                R dx, dy, dz;
+                disp_hi(rj, pi, dx, dy, dz);
+                R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+                if (r2 < rc2) {
+                  disp(rj, pi, dx, dy, dz);
+                  r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+                }
+                const R ri = rsq(r2);
+                R sc = (jmass(rj) * ri) * (ri * ri);
+                if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+                qx = fma(sc, dx, qx);
+                qy = fma(sc, dy, qy);
+                qz = fma(sc, dz, qz);
+              }
+              px = qx;
+              py = qy;
+              pz = qz;
+            }
+          }
+          fold(hx, lx, px);
+          fold(hy, ly, py);
+          fold(hz, lz, pz);
+        }
+        if (more) tile[(tt + 1) & 1][t] = nxt;
+        __syncthreads();
+      }
+      // combine the j-groups in group order (the tiles are free: gpart aliases them)
+      if (g > 0) gpart[(g - 1) * gsz + l] = SPart<MODE>{hx, lx, hy, ly, hz, lz};
+      __syncthreads();
+      if (g == 0) {
+        for (int gg = 1; gg < it.js; ++gg) {
+          const SPart<MODE> p = gpart[(gg - 1) * gsz + l];
+          fold(hx, lx, p.hx); lx += p.lx;
+          fold(hy, ly, p.hy); ly += p.ly;
+          fold(hz, lz, p.hz); lz += p.lz;
+        }
+        if (l < it.ni) {
+          const int64_t i = o + ii;
+          a[i] = G * ((double)hx + (double)lx);
+          a[total + i] = G * ((double)hy + (double)ly);
+          a[2 * total + i] = G * ((double)hz + (double)lz);
+        }
+      }
+      __syncthreads();  // before the next item's tile reuses the LDS
+    }
+  }
+  // closing half-kick of the last step; a workgroup whose wait timed out marks its particles NaN
+  for (int q = q0; q < q1; ++q) {
+    const SItem it = items[wg_list[q]];
+    if (t < it.ni) {
+      const int64_t i = off[it.sys] + it.i0 + t;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int64_t e = d * total + i;
+        if (bad) {
+          x[e] = NAN;
+          v[e] = NAN;
+          a[e] = NAN;
+        } else if (nsteps > 0) {
+          v[e] = fma(h, a[e], v[e]);
+        }
+      }
+    }
+  }
+}
+
+__global__ void zero_counters_kernel(int* c, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0;
+}
+
+// ------------------------------------------------------------------ plans
+struct SPlan {
+  std::vector<int64_t> off;
+  std::vector<double> eps;
+  int precision = 0, device = 0, nwg = 0, ncl = 0;
+  int64_t total = 0;
+  int64_t* d_off = nullptr;
+  double* d_eps = nullptr;
+  int* d_nparts = nullptr;
+  SItem* d_items = nullptr;
+  int* d_wg_off = nullptr;
+  int* d_wg_list = nullptr;
+  void* d_xrec = nullptr;
+  int* d_cnt = nullptr;
+};
+
+std::mutex g_splan_mu;
+std::vector<SPlan*> g_splans;
+
+void free_splan(SPlan* p) {
+  for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_nparts, (void*)p->d_items, (void*)p->d_wg_off,
+                  (void*)p->d_wg_list, p->d_xrec, (void*)p->d_cnt})
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+template <typename T>
+bool supload(T** dst, const std::vector<T>& src) {
+  const size_t bytes = sizeof(T) * std::max<size_t>(1, src.size());
+  if (hipMalloc(dst, bytes) != hipSuccess) return false;
+  return src.empty() || hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+template <int MODE>
+int resident_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&ens_stream_kernel<MODE, false>),
+                                                    kSBlock, 0) != hipSuccess)
+    nb = 1;
+  int nb2 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, reinterpret_cast<const void*>(&ens_stream_kernel<MODE, true>),
+                                                    kSBlock, 0) != hipSuccess)
+    nb2 = 1;
+  (void)hipGetLastError();
+  return std::max(1, std::min(kSMaxPerCu, std::min(nb, nb2)));
+}
+
+// Items: a system of nc <= 512 particles is one item whose lanes split j into
+// js = 16, 8, 4 or 2 groups (nc <= 64, 128, 256, 512); larger systems are cut
+// into ceil(nc / 512) near-equal items with 2 j-groups.  Cost of an item per
+// step: j-iterations per lane plus a fixed overhead.
+template <int MODE>
+int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, SPlan** out) {
+  SPlan* p = new SPlan();
+  p->off.assign(off, off + ncl + 1);
+  p->eps.assign(eps, eps + ncl);
+  p->precision = precision;
+  p->device = device;
+  p->ncl = ncl;
+  p->total = off[ncl];
+  std::vector<SItem> items;
+  std::vector<double> cost;
+  std::vector<int> nparts(ncl, 0);
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nc = off[c + 1] - off[c];
+    if (nc <= 0) continue;
+    if (nc > (int64_t(1) << 24)) {
+      delete p;
+      return set_error(NBODY_EUNSUPPORTED, "batched: a system of more than 2^24 particles");
+    }
+    const int js = nc <= 64 ? 16 : nc <= 128 ? 8 : nc <= 256 ? 4 : 2;
+    const int cap = kSBlock / js;
+    const int P = (int)((nc + cap - 1) / cap);
+    const int per = (int)((nc + P - 1) / P);
+    for (int k = 0; k < P; ++k) {
+      const int i0 = k * per;
+      const int ni = (int)std::min<int64_t>(per, nc - i0);
+      if (ni <= 0) continue;
+      items.push_back(SItem{c, i0, ni, js});
+      cost.push_back((double)((nc + js - 1) / js) + 96.0);
+      ++nparts[c];
+    }
+  }
+  const int cap_wg = std::max(1, resident_per_cu<MODE>() * cu_count(device));
+  const int nwg = std::max(1, std::min<int>((int)items.size(), cap_wg));
+  std::vector<int> order(items.size());
+  for (size_t k = 0; k < items.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int w) { return cost[u] > cost[w]; });
+  std::vector<std::vector<int>> lists(nwg);
+  using Slot = std::pair<double, int>;
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+  for (int w = 0; w < nwg; ++w) heap.push({0.0, w});
+  for (int k : order) {
+    Slot sl = heap.top();
+    heap.pop();
+    lists[sl.second].push_back(k);
+    heap.push({sl.first + cost[k], sl.second});
+  }
+  std::vector<int> wg_off(nwg + 1, 0), wg_list;
+  for (int w = 0; w < nwg; ++w) {
+    wg_list.insert(wg_list.end(), lists[w].begin(), lists[w].end());
+    wg_off[w + 1] = (int)wg_list.size();
+  }
+  p->nwg = nwg;
+  bool ok = supload(&p->d_off, p->off) && supload(&p->d_eps, p->eps) && supload(&p->d_nparts, nparts) &&
+            supload(&p->d_items, items) && supload(&p->d_wg_off, wg_off) && supload(&p->d_wg_list, wg_list) &&
+            hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
+            hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_splan(p);
+    return set_error(NBODY_ENOMEM, "batched: plan upload failed");
+  }
+  *out = p;
+  return NBODY_OK;
+}
+
+SPlan* find_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
+  for (SPlan* p : g_splans) {
+    if (p->device != device || p->precision != precision || p->ncl != ncl) continue;
+    if (std::equal(p->off.begin(), p->off.end(), off) && std::equal(p->eps.begin(), p->eps.end(), eps)) return p;
+  }
+  return nullptr;
+}
+
+template <int MODE>
+int launch_splan(const SPlan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
+                 double G, bool acc_valid, bool excl, hipStream_t s) {
+  if (p->total == 0 || (nsteps == 0 && acc_valid)) return NBODY_OK;
+  zero_counters_kernel<<<1, 256, 0, s>>>(p->d_cnt, std::max(1, p->ncl));
+  NB_LAUNCH_CHECK("zero_counters_kernel");
+  auto* rec = static_cast<JRec<MODE>*>(p->d_xrec);
+  if (excl)
+    ens_stream_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items,
+                                                               p->d_wg_off, p->d_wg_list, x, v, a, m, rec, p->d_cnt,
+                                                               p->total, dt, nsteps, G, acc_valid ? 1 : 0);
+  else
+    ens_stream_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items,
+                                                                p->d_wg_off, p->d_wg_list, x, v, a, m, rec, p->d_cnt,
+                                                                p->total, dt, nsteps, G, acc_valid ? 1 : 0);
+  NB_LAUNCH_CHECK("ens_stream_kernel");
+  return NBODY_OK;
+}
+
+}  // namespace
+
+int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                       const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
+                       bool acc_valid, hipStream_t s) {
+  const int device = current_device();
+  std::lock_guard<std::mutex> lk(g_splan_mu);
+  SPlan* p = find_splan(ncl, off, eps, precision, device);
+  if (!p) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return set_error(NBODY_EINVAL, "batched: the plan for this layout must be built by one call outside stream capture");
+    int st;
+    if (precision == NBODY_FP64) st = build_splan<NBODY_FP64>(ncl, off, eps, precision, device, &p);
+    else if (precision == NBODY_FP32C) st = build_splan<NBODY_FP32C>(ncl, off, eps, precision, device, &p);
+    else st = build_splan<NBODY_FP32>(ncl, off, eps, precision, device, &p);
+    if (st) return st;
+    g_splans.push_back(p);
+  }
+  if (precision == NBODY_FP64) return launch_splan<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  if (precision == NBODY_FP32C) return launch_splan<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  return launch_splan<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+}
+
+void release_stream_plans() {
+  std::lock_guard<std::mutex> lk(g_splan_mu);
+  for (SPlan* p : g_splans) free_splan(p);
+  g_splans.clear();
+}
+
+}  // namespace nb

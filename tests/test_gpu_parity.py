@@ -326,6 +326,112 @@ def test_batched_pass_widths_agree(nb, prec):
             assert np.abs(out[0][1] - out[k][1]).max() <= 1e-8
 
 
+def _stream(nb, fn):
+    nb.nbody_set_config(bsplit=2)
+    try:
+        return fn()
+    finally:
+        nb.nbody_set_config()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_stream_batched_matches_oracle(nb, oracle_mod, prec):
+    """Streamed ensemble kernel: systems cut into items of <= 128 particles
+    (several items per system above 128) against the oracle's KDK."""
+    sizes = [5, 64, 65, 80, 129, 700, 1300]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=23, sizes=sizes)
+    dt, steps = 1.0 / 512, 5
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    _stream(nb, lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, dt, steps, precision=prec,
+                                              check_finite=True))
+    for c in range(len(sizes)):
+        s, e = off[c], off[c + 1]
+        rx, rv = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], dt, steps, eps=float(epsv[c]))
+        dx = np.abs(tx.cpu().numpy()[:, s:e] - rx).max()
+        dv = np.abs(tv.cpu().numpy()[:, s:e] - rv).max()
+        if prec == "fp64":
+            assert dx <= 1e-12 and dv <= 1e-12, (c, dx, dv)
+        else:
+            ra = oracle_mod.accel(x[:, s:e], m[s:e], eps=float(epsv[c]))
+            tol_v = 1e-5 * dt * steps * max(np.abs(ra).max(), 1e-30)
+            assert dv <= tol_v and dx <= tol_v * dt * steps, (c, dx, dv, tol_v)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_stream_batched_agrees_with_resident_kernel(nb, prec):
+    sizes = [4096, 3000, 2048, 700, 257, 64, 1]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=24, sizes=sizes)
+    out = []
+    for mode in (0, 2):
+        nb.nbody_set_config(bsplit=mode)
+        try:
+            tx, tv, tm = dev(x), dev(v), dev(m)
+            ta = torch.empty_like(tx)
+            nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 6, precision=prec, check_finite=True)
+        finally:
+            nb.nbody_set_config()
+        out.append((tx.cpu().numpy(), tv.cpu().numpy()))
+    assert np.abs(out[0][0] - out[1][0]).max() <= 1e-10
+    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-8
+
+
+def test_stream_batched_resumable_and_eps0(nb, oracle_mod):
+    sizes = [300, 77, 1025]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=25, sizes=sizes)
+    res = []
+    for chunks in ((6,), (2, 4), (0, 3, 3)):
+        tx, tv, tm = dev(x), dev(v), dev(m)
+        ta = torch.empty_like(tx)
+        valid = False
+        for c in chunks:
+            _stream(nb, lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 256, c, precision="fp32c",
+                                                      acc_valid=valid))
+            valid = True
+        res.append((tx.cpu(), tv.cpu()))
+    for r in res[1:]:
+        assert torch.equal(res[0][0], r[0]) and torch.equal(res[0][1], r[1])
+    # eps = 0 with the self pair masked by index
+    eps0 = np.zeros(len(sizes))
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    _stream(nb, lambda: nb.nbody_step_batched(off, eps0, tx, tv, ta, tm, 1.0 / 1024, 2, precision="fp64",
+                                              exclude_self=True, check_finite=True))
+    for c in range(len(sizes)):
+        s, e = off[c], off[c + 1]
+        rx, _ = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], 1.0 / 1024, 2, eps=0.0)
+        assert np.abs(tx.cpu().numpy()[:, s:e] - rx).max() <= 1e-11
+
+
+def test_stream_batched_graph_capture(nb):
+    sizes = [64, 257, 1000]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=26, sizes=sizes)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    nb.nbody_set_config(bsplit=2)
+    try:
+        ex, ev, ea = tx.clone(), tv.clone(), ta.clone()
+        nb.nbody_step_batched(off, epsv, ex, ev, ea, tm, 1.0 / 512, 2, precision="fp32c")
+        ref = []
+        for _ in range(3):
+            nb.nbody_step_batched(off, epsv, ex, ev, ea, tm, 1.0 / 512, 2, precision="fp32c", acc_valid=True)
+            ref.append((ex.clone(), ev.clone()))
+        gx, gv, ga = tx.clone(), tv.clone(), ta.clone()
+        nb.nbody_step_batched(off, epsv, gx, gv, ga, tm, 1.0 / 512, 2, precision="fp32c")
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+            nb.nbody_step_batched(off, epsv, gx, gv, ga, tm, 1.0 / 512, 2, precision="fp32c", acc_valid=True)
+    finally:
+        nb.nbody_set_config()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (gx.sum() + 1.0).item()
+        assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
+
+
 def test_batched_matches_oracle_fp64(nb, oracle_mod):
     sizes = [5, 80, 700]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=17, sizes=sizes)
