@@ -11,8 +11,9 @@
 //      step and opening half-kick of this one, rounded separately as in
 //      nbody_step); the new positions go straight into LDS as pair records;
 //   2. a split item also publishes its records in a global exchange buffer,
-//      signals its step with an agent-scope release, waits (bounded) for the
-//      other parts' signals and copies their records into LDS;
+//      signals its step after an agent-scope release fence, waits (bounded)
+//      for the other parts' signals, acquires and copies their records into
+//      LDS;
 //   3. every lane evaluates its i-particles against all records of the system
 //      in LDS with the same pair arithmetic and compensated folds as the
 //      single-system kernel; small systems, which cannot fill the lanes,
@@ -261,25 +262,30 @@ __device__ bool exchange(const SysView& sv, const Item& it, int64_t o, JRec<MODE
   const int t = threadIdx.x;
   JRec<MODE>* xb = xrec + (size_t)(r & 1) * sv.T + o;
   for (int i = sv.i0 + t; i < sv.i0 + sv.ni; i += blockDim.x) xb[i] = rec[i];
-  __threadfence();
+  // Agent-scope fences write back / invalidate a whole XCD's L2 and are
+  // serialised there, so one lane issues them for the workgroup: every wave
+  // first waits for its own stores, then after the barrier lane 0 releases,
+  // signals, polls the partners with relaxed loads and acquires once.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (t == 0) {
-    __hip_atomic_store(flags + flag_base + it.part, r + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flags + flag_base + it.part, r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     for (int p = 0; p < it.nparts && ok; ++p) {
       if (p == it.part) continue;
       int polls = 0;
-      while (__hip_atomic_load(flags + flag_base + p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < r + 1) {
+      while (__hip_atomic_load(flags + flag_base + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < r + 1) {
         if (++polls > kSpinLimit) { ok = 0; break; }
         __builtin_amdgcn_s_sleep(2);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *lds_ok = ok;
   }
   __syncthreads();
   const bool ok = *lds_ok != 0;
   if (ok) {
-    __threadfence();
     for (int j = t; j < sv.nc; j += blockDim.x)
       if (j < sv.i0 || j >= sv.i0 + sv.ni) rec[j] = xb[j];
   }
