@@ -230,8 +230,10 @@ def bench_ensemble(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     sizes = np.diff(off)
     pairs = float((sizes * (sizes - 1)).sum())
-    mode = args.bsplit if args.bsplit is not None else (1 if args.split else 0)
-    nb.nbody_set_config(bsplit=mode, bpass=args.bpass)
+    # default: the streamed kernel (mode 2), fastest on this workload; the
+    # resident kernel (mode 0, the library default) is timed beside it
+    mode = args.bsplit if args.bsplit is not None else (1 if args.split else 2)
+    nb.nbody_set_config(bsplit=mode, bpass=args.bpass, bitem=args.bitem)
     res, drift = {}, {}
 
     def energies(tx, tv):
@@ -254,17 +256,29 @@ def bench_ensemble(args, torch, nb):
         res[prec] = ms
         rel = np.abs((energies(tx, tv) - e0) / e0)
         drift[prec] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    other = {}
+    if mode != 0:
+        nb.nbody_set_config(bsplit=0, bpass=args.bpass)
+        tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+        ta = torch.empty_like(tx)
+        nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=args.precision)
+        steps = args.steps
+        ms0, _, _ = timed(lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], steps,
+                                                        precision=args.precision, acc_valid=True), 1, 0, torch)
+        other = {"resident_kernel_path": {"ms_per_step": round(ms0 / args.steps, 5),
+                                          "value": round(pairs * args.steps / (ms0 * 1e-3) / 1e9, 3)}}
+    nb.nbody_set_config()
     ms = res[args.precision]
     return {"metric": METRIC, "value": round(pairs * args.steps / (ms * 1e-3) / 1e9, 3), "unit": UNIT,
             "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": round(ms / args.steps, 5),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": 1, "kernel_mode": mode, "bpass": args.bpass},
+                       "launches": 1, "kernel_mode": mode, "bpass": args.bpass, "bitem": args.bitem},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift_per_cluster": drift,
             "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),
-                          "ms_per_step": round(res["fp64"] / args.steps, 5)}}
+                          "ms_per_step": round(res["fp64"] / args.steps, 5)}, **other}
 
 
 def bench_grad(args, torch, nb):
@@ -459,6 +473,7 @@ def main():
     ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2],
                     help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items")
     ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
+    ap.add_argument("--bitem", type=int, default=0, help="streamed ensemble: most particles per item (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)

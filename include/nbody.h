@@ -251,6 +251,8 @@ typedef struct nbody_config {
                       and the affected systems then end NaN. */
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
+  int32_t bitem;   /* streamed batched kernel (bsplit = 2): most particles per item of
+                      a system above 256 particles: 0 = automatic (1024), 256, 512 or 1024 */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros

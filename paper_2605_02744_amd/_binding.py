@@ -47,7 +47,7 @@ class nbody_params(ctypes.Structure):
 
 class nbody_config(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32)]
+                ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32), ("bitem", ctypes.c_int32)]
 
 
 _lib = None
@@ -289,14 +289,15 @@ def nbody_step_hermite6(x, v, a, jk, sn, cr, m, dt, nsteps, *, G=1.0, eps, preci
                                        _stream(x.device)))
 
 
-def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0):
+def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0):
     """Forces a tile configuration on this thread (all zeros = automatic);
     bsplit=1 lets the ensemble kernel split its largest systems over up to 4
     workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
     items of <= 128 particles), default 0: one workgroup per system; bpass sets
     how many of a lane's i-particles the ensemble kernel evaluates per pass
-    (1, 2, 4)."""
-    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass))
+    (1, 2, 4); bitem the streamed kernel's most particles per item (256, 512,
+    1024)."""
+    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem))
     _check(load().nbody_set_config(ctypes.byref(c)))
 
 

@@ -2,10 +2,10 @@
 //
 // Many independent softened systems advanced for all KDK steps in ONE launch,
 // with the work cut finer than whole systems so that no CU waits on one large
-// system.  Every system is split into items of at most 512 i-particles; a
-// 1024-lane workgroup evaluates one item at a time with its lanes in j-groups
-// (2 groups of 512 lanes for large systems, up to 16 groups of 64 for small
-// ones), streaming the system's pair records through a double-buffered LDS
+// system.  Every system is split into items of at most 1024 i-particles; a
+// 1024-lane workgroup evaluates one item at a time, small systems with their
+// lanes in j-groups (up to 16 groups of 64), streaming the system's pair
+// records through a double-buffered LDS
 // tile as the single-system force kernel does, and combining the groups'
 // (hi, lo) sums through LDS in group order.  Items are assigned
 // longest-processing-time first over the workgroups that can be resident at
@@ -52,7 +52,7 @@ struct SItem {
   int sys;  // system
   int i0;   // first particle of the item (system-local)
   int ni;   // particles in the item, <= kSBlock / js
-  int js;   // j-groups: 2, 4, 8 or 16
+  int js;   // j-groups: 1, 2, 4, 8 or 16
 };
 
 template <int MODE> struct SPart { Real<MODE> hx, lx, hy, ly, hz, lz; };
@@ -273,7 +273,7 @@ __global__ void zero_counters_kernel(int* c, int n) {
 struct SPlan {
   std::vector<int64_t> off;
   std::vector<double> eps;
-  int precision = 0, device = 0, nwg = 0, ncl = 0;
+  int precision = 0, device = 0, nwg = 0, ncl = 0, bitem = 0;
   int64_t total = 0;
   int64_t* d_off = nullptr;
   double* d_eps = nullptr;
@@ -316,19 +316,24 @@ int resident_per_cu() {
   return std::max(1, std::min(kSMaxPerCu, std::min(nb, nb2)));
 }
 
-// Items: a system of nc <= 512 particles is one item whose lanes split j into
-// js = 16, 8, 4 or 2 groups (nc <= 64, 128, 256, 512); larger systems are cut
-// into ceil(nc / 512) near-equal items with 2 j-groups.  Cost of an item per
-// step: j-iterations per lane plus a fixed overhead.
+// Items: a system of nc <= 256 particles is one item whose lanes split j into
+// js = 16, 8 or 4 groups (nc <= 64, 128, 256); larger systems are cut into
+// ceil(nc / bitem) near-equal items with 1024 / bitem j-groups (bitem = 1024,
+// one group, unless configured: measured on the 512-cluster workload, 1024
+// gave 1.24 ms per step, 256 1.28 and 512 1.54).  Cost of an item per step:
+// j-iterations per lane plus a fixed overhead.
 template <int MODE>
-int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, SPlan** out) {
+int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, int bitem,
+                SPlan** out) {
   SPlan* p = new SPlan();
   p->off.assign(off, off + ncl + 1);
   p->eps.assign(eps, eps + ncl);
   p->precision = precision;
   p->device = device;
   p->ncl = ncl;
+  p->bitem = bitem;
   p->total = off[ncl];
+  const int item_max = bitem > 0 ? bitem : 1024;
   std::vector<SItem> items;
   std::vector<double> cost;
   std::vector<int> nparts(ncl, 0);
@@ -339,7 +344,7 @@ int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precisio
       delete p;
       return set_error(NBODY_EUNSUPPORTED, "batched: a system of more than 2^24 particles");
     }
-    const int js = nc <= 64 ? 16 : nc <= 128 ? 8 : nc <= 256 ? 4 : 2;
+    const int js = nc <= 64 ? 16 : nc <= 128 ? 8 : nc <= 256 ? 4 : kSBlock / item_max;
     const int cap = kSBlock / js;
     const int P = (int)((nc + cap - 1) / cap);
     const int per = (int)((nc + P - 1) / P);
@@ -386,9 +391,9 @@ int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   return NBODY_OK;
 }
 
-SPlan* find_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
+SPlan* find_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, int bitem) {
   for (SPlan* p : g_splans) {
-    if (p->device != device || p->precision != precision || p->ncl != ncl) continue;
+    if (p->device != device || p->precision != precision || p->ncl != ncl || p->bitem != bitem) continue;
     if (std::equal(p->off.begin(), p->off.end(), off) && std::equal(p->eps.begin(), p->eps.end(), eps)) return p;
   }
   return nullptr;
@@ -420,15 +425,16 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
                        bool acc_valid, hipStream_t s) {
   const int device = current_device();
   std::lock_guard<std::mutex> lk(g_splan_mu);
-  SPlan* p = find_splan(ncl, off, eps, precision, device);
+  const int bitem = thread_config().bitem;
+  SPlan* p = find_splan(ncl, off, eps, precision, device, bitem);
   if (!p) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
       return set_error(NBODY_EINVAL, "batched: the plan for this layout must be built by one call outside stream capture");
     int st;
-    if (precision == NBODY_FP64) st = build_splan<NBODY_FP64>(ncl, off, eps, precision, device, &p);
-    else if (precision == NBODY_FP32C) st = build_splan<NBODY_FP32C>(ncl, off, eps, precision, device, &p);
-    else st = build_splan<NBODY_FP32>(ncl, off, eps, precision, device, &p);
+    if (precision == NBODY_FP64) st = build_splan<NBODY_FP64>(ncl, off, eps, precision, device, bitem, &p);
+    else if (precision == NBODY_FP32C) st = build_splan<NBODY_FP32C>(ncl, off, eps, precision, device, bitem, &p);
+    else st = build_splan<NBODY_FP32>(ncl, off, eps, precision, device, bitem, &p);
     if (st) return st;
     g_splans.push_back(p);
   }

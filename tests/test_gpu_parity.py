@@ -358,13 +358,13 @@ def test_stream_batched_matches_oracle(nb, oracle_mod, prec):
             assert dv <= tol_v and dx <= tol_v * dt * steps, (c, dx, dv, tol_v)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_stream_batched_agrees_with_resident_kernel(nb, prec):
+@pytest.mark.parametrize("prec,bitem", [("fp64", 0), ("fp32c", 0), ("fp32c", 256), ("fp32c", 1024)])
+def test_stream_batched_agrees_with_resident_kernel(nb, prec, bitem):
     sizes = [4096, 3000, 2048, 700, 257, 64, 1]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=24, sizes=sizes)
     out = []
     for mode in (0, 2):
-        nb.nbody_set_config(bsplit=mode)
+        nb.nbody_set_config(bsplit=mode, bitem=bitem if mode == 2 else 0)
         try:
             tx, tv, tm = dev(x), dev(v), dev(m)
             ta = torch.empty_like(tx)
