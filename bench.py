@@ -92,20 +92,27 @@ def rel_err_rows(a, ref):
 
 
 def cpu_baseline_rows(oracle, x, m, eps, budget_s, rng_seed=0):
-    """Oracle acceleration rows on a bounded sample of the workload: calibrate on
-    a few rows, then time a sample sized to ~budget_s seconds."""
+    """Oracle acceleration rows on a bounded sample of the workload: rows in a
+    seeded random order, evaluated in chunks until about budget_s seconds of
+    oracle time have been spent."""
     n = m.shape[0]
-    rng = np.random.default_rng(rng_seed)
-    cal = rng.choice(n, size=min(n, 32), replace=False)
-    t0 = time.perf_counter()
-    oracle.accel_rows(x, m, cal, eps=eps)
-    dt_cal = max(time.perf_counter() - t0, 1e-6)
-    rows_n = int(min(n, max(64, len(cal) * budget_s / dt_cal)))
-    rows = np.sort(rng.choice(n, size=rows_n, replace=False))
-    t0 = time.perf_counter()
-    ref_rows = oracle.accel_rows(x, m, rows, eps=eps)
-    el = time.perf_counter() - t0
-    return rows, ref_rows, el
+    order = np.random.default_rng(rng_seed).permutation(n)
+    oracle.accel_rows(x, m, order[:8], eps=eps)  # thread pool start-up, untimed
+    done, el, refs = 0, 0.0, []
+    chunk = 256
+    while done < n and el < budget_s:
+        rows = order[done:done + chunk]
+        t0 = time.perf_counter()
+        refs.append(oracle.accel_rows(x, m, rows, eps=eps))
+        dt = time.perf_counter() - t0
+        el += dt
+        done += rows.size
+        # aim at chunks of about a tenth of the budget
+        chunk = int(max(64, min(8192, rows.size * (0.1 * budget_s) / max(dt, 1e-3))))
+    rows = order[:done]
+    ref_rows = np.concatenate(refs, axis=1)
+    srt = np.argsort(rows)
+    return rows[srt], ref_rows[:, srt], el
 
 
 def bench_force(args, torch, nb):
@@ -468,7 +475,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--quick", action="store_true", help="force workload: skip FP64, adjoint and accuracy legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work in the CPU baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU baseline")
     ap.add_argument("--split", action="store_true", help="ensemble: split the largest systems over workgroups")
     ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2],
                     help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items")
