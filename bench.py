@@ -237,10 +237,19 @@ def bench_ensemble(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     sizes = np.diff(off)
     pairs = float((sizes * (sizes - 1)).sum())
-    # default: the streamed kernel (mode 2), fastest on this workload; the
-    # resident kernel (mode 0, the library default) is timed beside it
-    mode = args.bsplit if args.bsplit is not None else (1 if args.split else 2)
-    nb.nbody_set_config(bsplit=mode, bpass=args.bpass, bitem=args.bitem)
+    # default: the batched autotuner picks the kernel configuration for this
+    # layout (all modes); --bsplit/--split force one instead.  The resident
+    # kernel (mode 0, the library default without tuning) is timed beside it.
+    tuned = {}
+    if args.bsplit is None and not args.split:
+        nb.nbody_set_config()
+        tx0, tv0 = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+        for prec in (args.precision, "fp64"):
+            tuned[prec] = nb.nbody_tune_batched(off, epsv, tx0, tv0, tm, w["dt"], 20, precision=prec)
+        mode = tuned[args.precision]["bsplit"]
+    else:
+        mode = args.bsplit if args.bsplit is not None else 1
+        nb.nbody_set_config(bsplit=mode, bpass=args.bpass, bitem=args.bitem)
     res, drift = {}, {}
 
     def energies(tx, tv):
@@ -258,14 +267,19 @@ def bench_ensemble(args, torch, nb):
         e0 = energies(tx, tv)
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=prec)  # plan + a(x)
         steps = args.steps
-        ms, _, _ = timed(lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], steps, precision=prec,
-                                                       acc_valid=True), 1, 0, torch)
+        # all clusters, all steps: one persistent launch, captured in a HIP graph and replayed once
+        gs = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs, capture_error_mode="relaxed"):
+            nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], steps, precision=prec, acc_valid=True)
+        ms, _, _ = timed(graph.replay, 1, 0, torch)
         res[prec] = ms
         rel = np.abs((energies(tx, tv) - e0) / e0)
         drift[prec] = {"max": float(rel.max()), "median": float(np.median(rel))}
     other = {}
     if mode != 0:
-        nb.nbody_set_config(bsplit=0, bpass=args.bpass)
+        nb.nbody_set_config(bsplit=0, bpass=args.bpass or 4)  # forced, so no tuned choice applies
         tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
         ta = torch.empty_like(tx)
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=args.precision)
@@ -281,7 +295,8 @@ def bench_ensemble(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": 1, "kernel_mode": mode, "bpass": args.bpass, "bitem": args.bitem},
+                       "launches": 1, "hip_graph": True, "kernel_mode": mode,
+                       "autotuned": tuned or None, "bpass": args.bpass, "bitem": args.bitem},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift_per_cluster": drift,
             "fp64_path": {"value": round(pairs * args.steps / (res["fp64"] * 1e-3) / 1e9, 3),

@@ -270,6 +270,24 @@ int nbody_set_config(const nbody_config* cfg);
  * may be NULL) receives the chosen configuration. */
 int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_config* best);
 
+/* Autotuner of the batched kernels for one ensemble layout (off, eps as in
+ * nbody_step_batched, precision and flags from p): times every candidate
+ * configuration for nsteps (>= 1) KDK steps from the state (x, v, m), on the
+ * library's own copies (the caller's arrays are only read), and keeps the
+ * fastest whose state stays finite.  Candidates: the resident kernel with 1, 2
+ * or 4 i-particles per lane per pass; with allow_cooperative != 0 also the
+ * split mode and the streamed kernel with items of 256, 512 or 1024 particles
+ * (the modes that need every workgroup of a launch resident at once).  The
+ * choice is recorded for this (device, precision, layout): later
+ * nbody_step_batched calls on the same layout use it whenever the thread has
+ * not forced a batched configuration with nbody_set_config.  best (may be
+ * NULL) receives it as bsplit/bpass/bitem.  Synchronous; allocates and frees
+ * its own buffers and builds (and caches) one plan per candidate.  Errors: as
+ * nbody_step_batched; NBODY_ENONFINITE if no candidate stayed finite. */
+int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const double* x, const double* v,
+                       const double* m, double dt, int64_t nsteps, int32_t allow_cooperative,
+                       const nbody_params* p, nbody_config* best);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* nbody_last_error(void);
 

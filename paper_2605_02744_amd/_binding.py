@@ -80,6 +80,8 @@ def load():
     lib.nbody_step_hermite6.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_set_config.argtypes = [ctypes.POINTER(nbody_config)]
     lib.nbody_tune.argtypes = [_I64, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(nbody_config)]
+    lib.nbody_tune_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                       _P, _P, _P, _D, _I64, ctypes.c_int32, PP, ctypes.POINTER(nbody_config)]
     lib.nbody_last_error.restype = ctypes.c_char_p
     lib.nbody_last_error.argtypes = []
     lib.nbody_finalize.argtypes = []
@@ -87,7 +89,7 @@ def load():
     for f in ("nbody_accel", "nbody_step", "nbody_energy", "nbody_accel_vjp", "nbody_traj_grad",
               "nbody_step_batched", "nbody_set_config", "nbody_tune", "nbody_finalize", "nbody_version",
               "nbody_accel_jerk", "nbody_step_hermite", "nbody_accel_jerk_snap", "nbody_step_hermite6",
-              "nbody_potential"):
+              "nbody_potential", "nbody_tune_batched"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -222,6 +224,31 @@ def nbody_step_batched(off, eps, x, v, a, m, dt, nsteps, *, G=1.0, precision="fp
                                       _ptr(m, "m", (total,)), float(dt), int(nsteps), ctypes.byref(p),
                                       _stream(x.device)))
     return x, v, a
+
+
+def nbody_tune_batched(off, eps, x, v, m, dt, nsteps, *, G=1.0, precision="fp32c", exclude_self=False,
+                       allow_cooperative=True):
+    """Times the batched kernels' configurations on copies of (x, v) for this
+    layout, records the fastest for later nbody_step_batched calls, and
+    returns it as {"bsplit", "bpass", "bitem"}."""
+    import numpy as np
+    lib = load()
+    off_h = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    eps_h = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+    ncl = eps_h.shape[0]
+    if off_h.shape[0] != ncl + 1:
+        raise ValueError("off must have ncl + 1 entries")
+    total = int(off_h[-1])
+    p = _params(G, 0.0, precision, _flags(exclude_self, False))
+    best = nbody_config()
+    with torch.cuda.device(x.device):
+        torch.cuda.current_stream(x.device).synchronize()
+        _check(lib.nbody_tune_batched(ncl, off_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      eps_h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _ptr(x, "x", (3, total)), _ptr(v, "v", (3, total)), _ptr(m, "m", (total,)),
+                                      float(dt), int(nsteps), 1 if allow_cooperative else 0, ctypes.byref(p),
+                                      ctypes.byref(best)))
+    return {"bsplit": best.bsplit, "bpass": best.bpass, "bitem": best.bitem}
 
 
 def nbody_accel_jerk(x, v, m, *, G=1.0, eps, precision="fp32c", exclude_self=False, check_finite=False):

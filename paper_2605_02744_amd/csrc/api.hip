@@ -18,9 +18,6 @@ int run_traj_grad(int64_t n, const double* ckx, const double* ckv, int64_t every
                   const double* m, double dt, const double* gxT, const double* gvT, double* gx0, double* gv0,
                   double* gm, double G, double eps, int precision, bool excl, const PairConfig& cfg,
                   hipStream_t s);
-int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
-                const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                bool acc_valid, hipStream_t s);
 void release_batched_plans();
 void release_stream_plans();
 
@@ -222,6 +219,66 @@ int finish(int st, hipStream_t s, const nbody_params* p, std::initializer_list<s
 
 using namespace nb;
 
+namespace {
+
+// Host-side checks shared by the batched calls; total receives off[ncl].
+int check_batched_host(int32_t ncl, const int64_t* off, const double* eps, double dt, int64_t nsteps,
+                       const nbody_params* p, int64_t* total) {
+  if (!p) return set_error(NBODY_EINVAL, "params is NULL");
+  if (ncl < 0) return set_error(NBODY_EINVAL, "ncl < 0");
+  *total = 0;
+  if (ncl == 0) return NBODY_OK;
+  if (!off || !eps) return set_error(NBODY_EINVAL, "off and eps must be host arrays");
+  if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt is not finite");
+  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
+  if (!std::isfinite(p->G)) return set_error(NBODY_EINVAL, "G is not finite");
+  if (p->precision != NBODY_FP64 && p->precision != NBODY_FP32C && p->precision != NBODY_FP32)
+    return set_error(NBODY_EINVAL, "unknown precision");
+  if (p->flags & ~uint32_t(NBODY_EXCLUDE_SELF | NBODY_CHECK_FINITE | NBODY_ACC_VALID))
+    return set_error(NBODY_EINVAL, "unknown flag bits");
+  if (off[0] != 0) return set_error(NBODY_EINVAL, "off[0] must be 0");
+  for (int32_t c = 0; c < ncl; ++c) {
+    if (off[c + 1] < off[c]) return set_error(NBODY_EINVAL, "off must be non-decreasing");
+    if (!std::isfinite(eps[c]) || eps[c] < 0) return set_error(NBODY_EINVAL, "eps[c] must be finite and >= 0");
+    if (eps[c] == 0.0 && !(p->flags & NBODY_EXCLUDE_SELF))
+      return set_error(NBODY_EINVAL, "eps[c] == 0 requires NBODY_EXCLUDE_SELF");
+  }
+  *total = off[ncl];
+  if (*total > kMaxN) return set_error(NBODY_EINVAL, "total particle count exceeds 2^29");
+  return NBODY_OK;
+}
+
+// Batched configurations chosen by nbody_tune_batched, per (device, precision, layout).
+struct TunedBatch {
+  int device, precision;
+  std::vector<int64_t> off;
+  std::vector<double> eps;
+  BatchConfig bc;
+};
+std::mutex g_tb_mu;
+std::vector<TunedBatch> g_tuned_batch;
+
+// The thread's forced configuration if it sets any batched field, else the
+// tuned one for this layout, else the resident kernel with its defaults.
+BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
+  const nbody_config& t = t_cfg;
+  BatchConfig bc;
+  if (t.bsplit || t.bpass || t.bitem) {
+    bc.mode = t.bsplit;
+    bc.pass = t.bpass;
+    bc.item = t.bitem;
+    return bc;
+  }
+  std::lock_guard<std::mutex> lk(g_tb_mu);
+  for (const TunedBatch& e : g_tuned_batch)
+    if (e.device == device && e.precision == precision && (int)e.eps.size() == ncl &&
+        std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps))
+      return e.bc;
+  return bc;
+}
+
+}  // namespace
+
 extern "C" {
 
 int nbody_accel(int64_t n, const double* x, const double* m, double* a, const nbody_params* p, void* stream) {
@@ -314,28 +371,11 @@ int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64
   return finish(st, s, p, {{gx0, 3 * n}, {gv0, 3 * n}, {gm, n}});
 }
 
+
 int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, const nbody_params* p, void* stream) {
-  if (!p) return set_error(NBODY_EINVAL, "params is NULL");
-  if (ncl < 0) return set_error(NBODY_EINVAL, "ncl < 0");
-  if (ncl == 0) return NBODY_OK;
-  if (!off || !eps) return set_error(NBODY_EINVAL, "off and eps must be host arrays");
-  if (!std::isfinite(dt)) return set_error(NBODY_EINVAL, "dt is not finite");
-  if (nsteps < 0) return set_error(NBODY_EINVAL, "nsteps < 0");
-  if (!std::isfinite(p->G)) return set_error(NBODY_EINVAL, "G is not finite");
-  if (p->precision != NBODY_FP64 && p->precision != NBODY_FP32C && p->precision != NBODY_FP32)
-    return set_error(NBODY_EINVAL, "unknown precision");
-  if (p->flags & ~uint32_t(NBODY_EXCLUDE_SELF | NBODY_CHECK_FINITE | NBODY_ACC_VALID))
-    return set_error(NBODY_EINVAL, "unknown flag bits");
-  if (off[0] != 0) return set_error(NBODY_EINVAL, "off[0] must be 0");
-  for (int32_t c = 0; c < ncl; ++c) {
-    if (off[c + 1] < off[c]) return set_error(NBODY_EINVAL, "off must be non-decreasing");
-    if (!std::isfinite(eps[c]) || eps[c] < 0) return set_error(NBODY_EINVAL, "eps[c] must be finite and >= 0");
-    if (eps[c] == 0.0 && !(p->flags & NBODY_EXCLUDE_SELF))
-      return set_error(NBODY_EINVAL, "eps[c] == 0 requires NBODY_EXCLUDE_SELF");
-  }
-  const int64_t total = off[ncl];
-  if (total > kMaxN) return set_error(NBODY_EINVAL, "total particle count exceeds 2^29");
+  int64_t total = 0;
+  NB_TRY(check_batched_host(ncl, off, eps, dt, nsteps, p, &total));
   if (total == 0) return NBODY_OK;
   const size_t b3 = sizeof(double) * 3 * (size_t)total, b1 = sizeof(double) * (size_t)total;
   NB_TRY(check_dev_range(x, b3, "x"));
@@ -344,9 +384,87 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
   NB_TRY(check_dev_range(m, b1, "m"));
   if (x == v || x == a || v == a) return set_error(NBODY_EINVAL, "x, v and a must be distinct");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const BatchConfig bc = batch_config_for(ncl, off, eps, p->precision, current_device());
   int st = run_batched(ncl, off, eps, x, v, a, m, dt, nsteps, p->G, p->precision,
-                       (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, s);
+                       (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, bc, s);
   return finish(st, s, p, {{x, 3 * total}, {v, 3 * total}, {a, 3 * total}});
+}
+
+int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const double* x, const double* v,
+                       const double* m, double dt, int64_t nsteps, int32_t allow_cooperative,
+                       const nbody_params* p, nbody_config* best) {
+  int64_t total = 0;
+  NB_TRY(check_batched_host(ncl, off, eps, dt, nsteps, p, &total));
+  if (nsteps < 1) return set_error(NBODY_EINVAL, "tune_batched: nsteps must be >= 1");
+  if (total == 0) return set_error(NBODY_EINVAL, "tune_batched: the ensemble is empty");
+  const size_t b3 = sizeof(double) * 3 * (size_t)total, b1 = sizeof(double) * (size_t)total;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(v, b3, "v"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  const int dev = current_device();
+  std::vector<BatchConfig> cand;
+  for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0});
+  if (allow_cooperative) {
+    cand.push_back(BatchConfig{1, 0, 0});
+    for (int item : {256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});
+  }
+  double *sx = nullptr, *sv = nullptr, *sa = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    for (double* q : {sx, sv, sa})
+      if (q) (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&sx, b3) != hipSuccess || hipMalloc(&sv, b3) != hipSuccess || hipMalloc(&sa, b3) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return set_error(NBODY_ENOMEM, "tune_batched: allocation failed");
+  }
+  const bool excl = (p->flags & NBODY_EXCLUDE_SELF) != 0;
+  float best_ms = 0.0f;
+  int best_k = -1;
+  for (size_t k = 0; k < cand.size(); ++k) {
+    if (hipMemcpy(sx, x, b3, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(sv, v, b3, hipMemcpyDeviceToDevice) != hipSuccess) {
+      cleanup();
+      return set_error(NBODY_EHIP, "tune_batched: copy failed");
+    }
+    int st = run_batched(ncl, off, eps, sx, sv, sa, m, dt, 0, p->G, p->precision, excl, false, cand[k], nullptr);
+    if (st) { cleanup(); return st; }
+    (void)hipEventRecord(e0, nullptr);
+    st = run_batched(ncl, off, eps, sx, sv, sa, m, dt, nsteps, p->G, p->precision, excl, true, cand[k], nullptr);
+    if (st) { cleanup(); return st; }
+    (void)hipEventRecord(e1, nullptr);
+    if (hipEventSynchronize(e1) != hipSuccess) { cleanup(); return set_error(NBODY_EHIP, "tune_batched: sync failed"); }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    bool finite_ok = true;
+    if ((st = check_finite(sx, 3 * total, nullptr, &finite_ok))) { cleanup(); return st; }
+    if (finite_ok && (best_k < 0 || ms < best_ms)) {
+      best_ms = ms;
+      best_k = (int)k;
+    }
+  }
+  cleanup();
+  if (best_k < 0) return set_error(NBODY_ENONFINITE, "tune_batched: every configuration produced non-finite state");
+  const BatchConfig bc = cand[best_k];
+  {
+    std::lock_guard<std::mutex> lk(g_tb_mu);
+    bool found = false;
+    for (TunedBatch& e : g_tuned_batch)
+      if (e.device == dev && e.precision == p->precision && (int)e.eps.size() == ncl &&
+          std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps)) {
+        e.bc = bc;
+        found = true;
+      }
+    if (!found)
+      g_tuned_batch.push_back(TunedBatch{dev, p->precision, std::vector<int64_t>(off, off + ncl + 1),
+                                         std::vector<double>(eps, eps + ncl), bc});
+  }
+  if (best) *best = nbody_config{0, 0, bc.mode, bc.pass, bc.item};
+  return NBODY_OK;
 }
 
 int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk,
@@ -552,6 +670,10 @@ const char* nbody_last_error(void) { return g_err.c_str(); }
 int nbody_finalize(void) {
   release_batched_plans();
   release_stream_plans();
+  {
+    std::lock_guard<std::mutex> lk(g_tb_mu);
+    g_tuned_batch.clear();
+  }
   release_workspaces();
   return NBODY_OK;
 }

@@ -95,6 +95,21 @@ int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double 
 int launch_potential(int64_t n, const double* x, const double* m, double eps, double scale, double* phi,
                      int split, hipStream_t s);
 
+// Configuration of the batched (ensemble) kernels: mode 0 resident systems,
+// 1 resident with split systems, 2 streamed items; pass = i-particles per lane
+// per pass of mode 0/1 (0 = automatic); item = most particles per item of
+// mode 2 (0 = automatic).
+struct BatchConfig {
+  int mode = 0;
+  int pass = 0;
+  int item = 0;
+};
+
+// nsteps KDK steps of every system of the ensemble with the given kernel configuration.
+int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
+                bool acc_valid, const BatchConfig& bc, hipStream_t s);
+
 // Energy/momentum diagnostics into out9 (device).
 int launch_energy(int64_t n, const double* x, const double* v, const double* m, double G,
                   double eps, double* out9, hipStream_t s);

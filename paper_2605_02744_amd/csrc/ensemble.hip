@@ -563,8 +563,8 @@ Plan* find_plan(int32_t ncl, const int64_t* off, const double* eps, int precisio
 
 template <int MODE>
 int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
-                double G, bool acc_valid, bool excl, hipStream_t s) {
-  const int pass = thread_config().bpass > 0 ? thread_config().bpass : kPass;
+                double G, bool acc_valid, bool excl, int bpass, hipStream_t s) {
+  const int pass = bpass > 0 ? bpass : kPass;
   NB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel<MODE>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds));
   if (p->nflags > 0) {
@@ -583,15 +583,15 @@ int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m,
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                       bool acc_valid, hipStream_t s);
+                       bool acc_valid, int item, hipStream_t s);
 
 int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
-                hipStream_t s) {
-  if (thread_config().bsplit == 2)
-    return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, s);
+                const BatchConfig& bc, hipStream_t s) {
+  if (bc.mode == 2)
+    return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, bc.item, s);
   const int device = current_device();
-  const bool allow_split = thread_config().bsplit == 1;
+  const bool allow_split = bc.mode == 1;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   Plan* p = find_plan(ncl, off, eps, precision, device, allow_split);
   if (!p) {
@@ -605,9 +605,11 @@ int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, d
     if (st) return st;
     g_plans.push_back(p);
   }
-  if (precision == NBODY_FP64) return launch_plan<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
-  if (precision == NBODY_FP32C) return launch_plan<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
-  return launch_plan<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  if (precision == NBODY_FP64)
+    return launch_plan<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, bc.pass, s);
+  if (precision == NBODY_FP32C)
+    return launch_plan<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, bc.pass, s);
+  return launch_plan<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, bc.pass, s);
 }
 
 void release_batched_plans() {

@@ -422,10 +422,9 @@ int launch_splan(const SPlan* p, double* x, double* v, double* a, const double* 
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                       bool acc_valid, hipStream_t s) {
+                       bool acc_valid, int bitem, hipStream_t s) {
   const int device = current_device();
   std::lock_guard<std::mutex> lk(g_splan_mu);
-  const int bitem = thread_config().bitem;
   SPlan* p = find_splan(ncl, off, eps, precision, device, bitem);
   if (!p) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;

@@ -114,6 +114,25 @@ def test_batched_host_validation(lib):
     assert st == nb.NBODY_EINVAL
 
 
+def test_tune_batched_host_validation(lib):
+    import numpy as np
+    import paper_2605_02744_amd as nb
+    from paper_2605_02744_amd._binding import nbody_params
+    L = nb.load()
+    p = nbody_params(1.0, 0.0, nb.NBODY_FP32C, 0)
+    PI = ctypes.POINTER(ctypes.c_int64)
+    PD = ctypes.POINTER(ctypes.c_double)
+    off = np.array([0, 0], dtype=np.int64)
+    eps = np.array([0.1])
+    st = L.nbody_tune_batched(1, off.ctypes.data_as(PI), eps.ctypes.data_as(PD), None, None, None, 0.1, 4, 1,
+                              ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL and b"empty" in L.nbody_last_error()
+    off = np.array([0, 10], dtype=np.int64)
+    st = L.nbody_tune_batched(1, off.ctypes.data_as(PI), eps.ctypes.data_as(PD), None, None, None, 0.1, 0, 1,
+                              ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL and b"nsteps" in L.nbody_last_error()
+
+
 def test_set_config_validation(lib):
     import paper_2605_02744_amd as nb
     with pytest.raises(nb.NBodyError):

@@ -432,6 +432,33 @@ def test_stream_batched_graph_capture(nb):
         assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
 
 
+def test_tune_batched_records_and_applies_choice(nb):
+    """The batched autotuner returns one of its candidates, leaves the caller's
+    arrays untouched, and later calls on the same layout (no forced
+    configuration) run exactly the chosen configuration."""
+    sizes = [1500, 333, 2700, 64, 901]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=27, sizes=sizes)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    best = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 4, precision="fp32c")
+    assert best["bsplit"] in (0, 1, 2) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 256, 512, 1024)
+    assert torch.equal(tx, dev(x)) and torch.equal(tv, dev(v))
+    out = []
+    for forced in (False, True):
+        if forced:
+            nb.nbody_set_config(bsplit=best["bsplit"], bpass=best["bpass"], bitem=best["bitem"])
+        try:
+            gx, gv = dev(x), dev(v)
+            ga = torch.empty_like(gx)
+            nb.nbody_step_batched(off, epsv, gx, gv, ga, tm, 1.0 / 512, 5, precision="fp32c", check_finite=True)
+        finally:
+            nb.nbody_set_config()
+        out.append((gx.cpu(), gv.cpu()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    # the resident-only search returns a resident configuration
+    best0 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp64", allow_cooperative=False)
+    assert best0["bsplit"] == 0
+
+
 def test_batched_matches_oracle_fp64(nb, oracle_mod):
     sizes = [5, 80, 700]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=17, sizes=sizes)
