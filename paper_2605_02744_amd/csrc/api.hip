@@ -595,10 +595,13 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
   for (auto& v : hx) v = 2.0 * next() - 1.0;
   for (auto& v : hm) v = (0.5 + next()) / (double)n;
   double *dx = nullptr, *dm = nullptr, *da = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&]() {
     if (dx) (void)hipFree(dx);
     if (dm) (void)hipFree(dm);
     if (da) (void)hipFree(da);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   };
   if (hipMalloc(&dx, hx.size() * 8) != hipSuccess || hipMalloc(&dm, hm.size() * 8) != hipSuccess ||
       hipMalloc(&da, hx.size() * 8) != hipSuccess) {
@@ -610,9 +613,10 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
     cleanup();
     return set_error(NBODY_EHIP, "tune: copy failed");
   }
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return set_error(NBODY_EHIP, "tune: event creation failed");
+  }
   float best_ms = 1e30f;
   PairConfig bc;
   const int ipls[3] = {1, 2, 4};
@@ -644,11 +648,9 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
       if (ms < best_ms) { best_ms = ms; bc = c; }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   cleanup();
   record_tuned(dev, n, precision, bc);
-  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0};
+  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0, 0};
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
