@@ -1,6 +1,7 @@
 // C ABI of libnbody_accel (declared in include/nbody.h): argument validation,
 // per-device workspace, tile-configuration choice and the autotuner.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -40,7 +41,7 @@ constexpr int kSlots = 4;
 struct Buf { void* p = nullptr; size_t bytes = 0; };
 std::mutex g_ws_mu;
 Buf g_ws[kMaxDev][kSlots];
-int g_cus[kMaxDev] = {0};
+std::atomic<int> g_cus[kMaxDev];  // zero-initialised (static storage)
 }  // namespace
 
 int current_device() {
@@ -51,12 +52,12 @@ int current_device() {
 
 int cu_count(int device) {
   if (device < 0 || device >= kMaxDev) return 256;
-  if (g_cus[device] == 0) {
-    int c = 0;
+  int c = g_cus[device].load(std::memory_order_relaxed);
+  if (c == 0) {
     if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c <= 0) c = 256;
-    g_cus[device] = c;
+    g_cus[device].store(c, std::memory_order_relaxed);
   }
-  return g_cus[device];
+  return c;
 }
 
 void* workspace(int device, int slot, size_t bytes, int* status) {

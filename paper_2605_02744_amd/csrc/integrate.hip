@@ -1,6 +1,7 @@
 // O(N) kernels and drivers of libnbody_accel: the kick-drift-kick integrator,
-// the energy/momentum diagnostics and the checkpointed adjoint sweep.  All of
-// this is FP64 and bound by HBM bandwidth; the all-pairs work lives in pairs.hip.
+// the fourth- and sixth-order Hermite predictors and correctors, the
+// energy/momentum diagnostics and the checkpointed adjoint sweep.  All of this
+// is FP64 and bound by HBM bandwidth; the all-pairs work lives in pairs.hip.
 #include "common.h"
 
 namespace nb {
