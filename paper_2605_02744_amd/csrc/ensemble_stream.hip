@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
       const int il = l < it.ni ? l : it.ni - 1;
       const int ii = it.i0 + il;  // system-local index of the lane's particle
       const int iself = l < it.ni ? ii : -1;
+      const bool wave_live = (l & ~63) < it.ni;  // gsz is a multiple of 64: uniform per wave
       const double eps = epsv[it.sys];
       const R e2 = (R)(eps * eps);
       IPos<MODE> pi;
@@ -161,8 +162,10 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
         }
         const JRec<MODE>* cur = tile[tt & 1];
         // this group's slice of the tile: records [g*gsz, (g+1)*gsz), padding skipped by fold blocks
+        // a wave none of whose lanes owns a particle of the item skips the pairs
+        // (it still stages tiles and meets the barriers), leaving the SIMD to the others
         const int jg = jt + g * gsz;
-        const int cntg = min(gsz, max(0, nc - jg));
+        const int cntg = wave_live ? min(gsz, max(0, nc - jg)) : 0;
         const int fend = g * gsz + (cntg + kFold - 1) / kFold * kFold;
 #pragma unroll 1
         for (int f = g * gsz; f < fend; f += kFold) {
