@@ -66,10 +66,70 @@ def load_traffic(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+class GpuEnergy:
+    """Reads the energy accumulator of the GPU behind cuda:0 through amdsmi
+    (read-only); every method returns None where that is not available."""
+
+    def __init__(self):
+        self.h = None
+        try:
+            import ctypes
+            import amdsmi
+            hip = ctypes.CDLL("libamdhip64.so")
+            buf = ctypes.create_string_buffer(64)
+            if hip.hipDeviceGetPCIBusId(buf, 64, 0) != 0:
+                return
+            bdf = buf.value.decode().lower()
+            amdsmi.amdsmi_init(amdsmi.AmdSmiInitFlags.INIT_AMD_GPUS)
+            for h in amdsmi.amdsmi_get_processor_handles():
+                if str(amdsmi.amdsmi_get_gpu_device_bdf(h)).lower() == bdf:
+                    self.h, self.m = h, amdsmi
+            if self.h is not None:
+                self.joules()
+        except Exception:
+            self.h = None
+
+    def joules(self):
+        if self.h is None:
+            return None
+        try:
+            e = self.m.amdsmi_get_energy_count(self.h)
+            return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+        except Exception:
+            return None
+
+
+def energy_per_call(fn, reps, torch, meter, settle=0.5):
+    """GPU board energy (J) of one call of fn, from the amdsmi energy counter
+    over `reps` back-to-back calls.  The counter is refreshed with some delay,
+    so every read follows a settling pause, and the idle energy of the pauses
+    (idle power from a separate one-second window) is subtracted.  Returns
+    (joules per call, busy seconds per call, idle watts) or None."""
+    if meter is None or meter.joules() is None:
+        return None
+    torch.cuda.synchronize()
+    time.sleep(settle)
+    ja = meter.joules()
+    time.sleep(1.0)
+    jb = meter.joules()
+    tb = time.perf_counter()
+    idle_w = (jb - ja) / 1.0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    busy = time.perf_counter() - t0
+    time.sleep(settle)
+    jc = meter.joules()
+    window = time.perf_counter() - tb
+    e_busy = (jc - jb) - idle_w * (window - busy)
+    return e_busy / reps, busy / reps, idle_w
+
+
 def timed(fn, steps, warmup, torch):
     """Runs fn warmup times, then times exactly `steps` calls with HIP events on
     the current stream, bracketed by device synchronisation. Returns (ms/step,
-    list of per-call ms)."""
+    list of per-call ms, wall ms)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -145,6 +205,11 @@ def bench_force(args, torch, nb):
                       "flop_convention": "20 flops per ordered interaction"},
            "pct_fp32_peak": round(100 * c20_tflops / FP32_PEAK_TFLOPS, 2),
            "wall_ms_timed_region": round(wall, 2)}
+    en = energy_per_call(f32, args.steps, torch, GpuEnergy())
+    if en:
+        # GPU board energy of one evaluation (amdsmi energy counter, untimed repeat), for context
+        res["gpu_energy"] = {"joules_per_eval": round(en[0], 2), "avg_power_w": round(en[0] / en[1], 1),
+                             "idle_power_w": round(en[2], 1), "interactions_per_joule": round(pairs / en[0], 1)}
     if tuned:
         res["tuned"] = tuned
 
@@ -436,6 +501,7 @@ def bench_hermite6(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     pairs = float(n) * (n - 1)
     res = {}
+    meter = GpuEnergy()
     for prec in (args.precision, "fp64"):
         tx, tv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
         st = [torch.empty_like(tx) for _ in range(4)]
@@ -450,6 +516,16 @@ def bench_hermite6(args, torch, nb):
         res[prec] = {"time_to_solution_ms": round(ms_tts, 3), "ms_per_step": round(ms_step, 3),
                      "pairs_per_s_g": round(pairs / (ms_step * 1e-3) / 1e9, 3),
                      "energy_error_after_steps": float(abs((e1 - e0) / e0))}
+        # energy to solution: the same run repeated from the initial state (untimed)
+        def solve():
+            sx, sv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+            nb.nbody_step_hermite6(sx, sv, *[torch.empty_like(sx) for _ in range(4)], tm, dt, steps, eps=eps,
+                                   precision=prec)
+        en = energy_per_call(solve, max(3, int(3000.0 / ms_tts) + 1), torch, meter)
+        if en:
+            res[prec]["gpu_energy_to_solution_j"] = round(en[0], 1)
+            res[prec]["gpu_edp_j_s"] = round(en[0] * ms_tts * 1e-3, 2)
+            res[prec]["avg_power_w"] = round(en[0] / en[1], 1)
     # per-particle potential (FP64) of the final state: the energy-distribution diagnostic
     ms_phi, _, _ = timed(lambda: nb.nbody_potential(tx, tm, eps=eps), 3, 1, torch)
     res["potential_fp64"] = {"ms": round(ms_phi, 3), "pairs_per_s_g": round(pairs / (ms_phi * 1e-3) / 1e9, 3)}
@@ -461,7 +537,10 @@ def bench_hermite6(args, torch, nb):
                        "precision": args.precision, "evaluation": "acceleration + jerk + snap per step"},
             "paths": res,
             "paper_context": {"time_to_solution_s": {"1 Wormhole n300 chip": 1459.46, "CPU 32 threads": 2875.39},
-                              "note": "paper's hardware; its time step and initial conditions are not stated"}}
+                              "energy_to_solution_kj": {"1 Wormhole n300 chip": 385.8, "CPU 32 threads": 670.4},
+                              "note": "paper's hardware (host CPU and accelerators measured together, energy "
+                                      "derived from its EDP column); its time step and initial conditions are "
+                                      "not stated; the MI355X figures here are GPU board energy only"}}
 
 
 def bench_copy(args, torch, nb):
