@@ -39,7 +39,9 @@ template <int MODE> constexpr int ens_max_ipl() { return MODE == kFP64 ? 8 : 4; 
 constexpr int kMaxSys = 4096;            // particles per system
 constexpr int kPass = 4;                 // most i-particles evaluated together in one pass over j
 constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kSpinLimit = 1 << 21;      // polls of a partner flag before giving up (~1 s)
+// wall-clock bound of one wait for a partner flag, in ticks of the 100 MHz
+// real-time counter (10 s; a round of LDS-resident systems takes milliseconds)
+constexpr uint64_t kWaitTicks = 1000000000ull;
 
 template <int MODE> struct Part { Real<MODE> hx, lx, hy, ly, hz, lz; };
 
@@ -274,9 +276,9 @@ __device__ bool exchange(const SysView& sv, const Item& it, int64_t o, JRec<MODE
     int ok = 1;
     for (int p = 0; p < it.nparts && ok; ++p) {
       if (p == it.part) continue;
-      int polls = 0;
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
       while (__hip_atomic_load(flags + flag_base + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < r + 1) {
-        if (++polls > kSpinLimit) { ok = 0; break; }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) { ok = 0; break; }
         __builtin_amdgcn_s_sleep(2);
       }
     }

@@ -31,7 +31,11 @@
 // published the next round, i.e. finished reading it.  A wait that exceeds
 // its bound (a workgroup that never became resident) makes the workgroup
 // publish NaN records from then on, so every system coupled to it ends NaN
-// instead of silently wrong, and the kernel still terminates.
+// instead of silently wrong, and the kernel still terminates.  The bound is
+// wall-clock time (the 100 MHz real-time counter), set per plan from its
+// largest per-workgroup pair count at a pessimistic 10^8 pairs/s plus 2 s, so
+// that a legitimately long round (systems of millions of particles) never
+// trips it.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -46,7 +50,6 @@ namespace {
 constexpr int kSBlock = 1024;           // lanes per workgroup
 constexpr int kSMaxPerCu = 2;           // resident workgroups per CU at most
 constexpr int kSWaves = 8;              // waves per SIMD the kernel is built for (<= 64 VGPRs)
-constexpr int kSSpin = 1 << 22;         // polls of a counter before giving up
 
 struct SItem {
   int sys;  // system
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
     const SItem* __restrict__ items, const int* __restrict__ wg_off, const int* __restrict__ wg_list,
     double* __restrict__ x, double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m,
     JRec<MODE>* __restrict__ xrec, int* __restrict__ cnt, int64_t total, double dt, int64_t nsteps, double G,
-    int acc_valid) {
+    int acc_valid, uint64_t wait_ticks) {
   using R = Real<MODE>;
   constexpr bool kNear = MODE == kFP32C;
   static_assert(sizeof(SPart<MODE>) * kSBlock <= sizeof(JRec<MODE>) * 2 * kSBlock, "group partials alias the tiles");
@@ -117,10 +120,10 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
       for (int q = q0; q < q1 && ok; ++q) {
         const int sys = items[wg_list[q]].sys;
         const unsigned want = (unsigned)nparts[sys] * (unsigned)(r + 1);
-        int polls = 0;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
         while (ok && (int)((unsigned)__hip_atomic_load(cnt + sys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
                            want) < 0) {
-          if (++polls > kSSpin) ok = 0;
+          if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) ok = 0;
           else __builtin_amdgcn_s_sleep(1);
         }
       }
@@ -161,14 +164,20 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
           nxt = jn < nc ? src[jn] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
         }
         const JRec<MODE>* cur = tile[tt & 1];
-        // this group's slice of the tile: records [g*gsz, (g+1)*gsz), padding skipped by fold blocks
-        // a wave none of whose lanes owns a particle of the item skips the pairs
-        // (it still stages tiles and meets the barriers), leaving the SIMD to the others
-        const int jg = jt + g * gsz;
-        const int cntg = wave_live ? min(gsz, max(0, nc - jg)) : 0;
-        const int fend = g * gsz + (cntg + kFold - 1) / kFold * kFold;
+        // this group's slice of the tile's valid records: the records are dealt
+        // to the groups in equal runs of whole fold blocks, [g*cs, (g+1)*cs), so
+        // a partly filled tile still spreads over the groups; a run never
+        // reaches past the tile's last fold block (cs and g*cs are multiples of
+        // kFold), and records past nc are zero-mass padding.
+        // A wave none of whose lanes owns a particle of the item skips the pairs
+        // (it still stages tiles and meets the barriers), leaving the SIMD to the others.
+        const int cntt = min(kSBlock, nc - jt);
+        const int cs = ((cntt + it.js - 1) / it.js + kFold - 1) / kFold * kFold;
+        const int j0 = g * cs;
+        const int cntg = wave_live ? max(0, min(cs, cntt - j0)) : 0;
+        const int fend = j0 + (cntg + kFold - 1) / kFold * kFold;
 #pragma unroll 1
-        for (int f = g * gsz; f < fend; f += kFold) {
+        for (int f = j0; f < fend; f += kFold) {
           R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
 #pragma unroll 16
           for (int jj = f; jj < f + kFold; ++jj) {
@@ -278,6 +287,7 @@ struct SPlan {
   std::vector<double> eps;
   int precision = 0, device = 0, nwg = 0, ncl = 0, bitem = 0;
   int64_t total = 0;
+  uint64_t wait_ticks = 0;  // bound of one counter wait, 100 MHz ticks
   int64_t* d_off = nullptr;
   double* d_eps = nullptr;
   int* d_nparts = nullptr;
@@ -319,12 +329,27 @@ int resident_per_cu() {
   return std::max(1, std::min(kSMaxPerCu, std::min(nb, nb2)));
 }
 
+// j-records one lane applies per round for an item of a system of nc
+// particles with js j-groups: each tile's valid records are dealt to the
+// groups in equal runs of whole fold blocks (as in ens_stream_kernel).
+double item_rounds(int64_t nc, int js) {
+  double w = 0.0;
+  for (int64_t jt = 0; jt < nc; jt += kSBlock) {
+    const int64_t cnt = std::min<int64_t>(kSBlock, nc - jt);
+    w += (double)(((cnt + js - 1) / js + kFold - 1) / kFold * kFold);
+  }
+  return w;
+}
+
 // Items: a system of nc <= 256 particles is one item whose lanes split j into
 // js = 16, 8 or 4 groups (nc <= 64, 128, 256); larger systems are cut into
 // ceil(nc / bitem) near-equal items with 1024 / bitem j-groups (bitem = 1024,
 // one group, unless configured: measured on the 512-cluster workload, 1024
-// gave 1.24 ms per step, 256 1.28 and 512 1.54).  Cost of an item per step:
-// j-iterations per lane plus a fixed overhead.
+// gave 1.18 ms per step, 512 1.21 and 256 1.25).  Cost of an item per round:
+// its j-iterations per lane plus a fixed overhead, i.e. its duration, since a
+// workgroup runs its items one after the other (weighting by the item's live
+// waves instead, a measure of its share of SIMD throughput, was measured
+// 46 % slower on the 512-cluster workload).
 template <int MODE>
 int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, int bitem,
                 SPlan** out) {
@@ -356,7 +381,7 @@ int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precisio
       const int ni = (int)std::min<int64_t>(per, nc - i0);
       if (ni <= 0) continue;
       items.push_back(SItem{c, i0, ni, js});
-      cost.push_back((double)((nc + js - 1) / js) + 96.0);
+      cost.push_back(item_rounds(nc, js) + 96.0);
       ++nparts[c];
     }
   }
@@ -376,11 +401,17 @@ int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precisio
     heap.push({sl.first + cost[k], sl.second});
   }
   std::vector<int> wg_off(nwg + 1, 0), wg_list;
+  double maxpairs = 0.0;
   for (int w = 0; w < nwg; ++w) {
     wg_list.insert(wg_list.end(), lists[w].begin(), lists[w].end());
     wg_off[w + 1] = (int)wg_list.size();
+    double pairs = 0.0;
+    for (int k : lists[w]) pairs += (double)items[k].ni * (double)(off[items[k].sys + 1] - off[items[k].sys]);
+    maxpairs = std::max(maxpairs, pairs);
   }
   p->nwg = nwg;
+  // a counter wait lasts at most about one round of the busiest workgroup
+  p->wait_ticks = (uint64_t)(1.0e8 * (2.0 + maxpairs / 1.0e8));
   bool ok = supload(&p->d_off, p->off) && supload(&p->d_eps, p->eps) && supload(&p->d_nparts, nparts) &&
             supload(&p->d_items, items) && supload(&p->d_wg_off, wg_off) && supload(&p->d_wg_list, wg_list) &&
             hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
@@ -412,11 +443,11 @@ int launch_splan(const SPlan* p, double* x, double* v, double* a, const double* 
   if (excl)
     ens_stream_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items,
                                                                p->d_wg_off, p->d_wg_list, x, v, a, m, rec, p->d_cnt,
-                                                               p->total, dt, nsteps, G, acc_valid ? 1 : 0);
+                                                               p->total, dt, nsteps, G, acc_valid ? 1 : 0, p->wait_ticks);
   else
     ens_stream_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items,
                                                                 p->d_wg_off, p->d_wg_list, x, v, a, m, rec, p->d_cnt,
-                                                                p->total, dt, nsteps, G, acc_valid ? 1 : 0);
+                                                                p->total, dt, nsteps, G, acc_valid ? 1 : 0, p->wait_ticks);
   NB_LAUNCH_CHECK("ens_stream_kernel");
   return NBODY_OK;
 }
