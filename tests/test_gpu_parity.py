@@ -169,6 +169,33 @@ def test_step_resumable_bitwise(nb, prec):
             assert torch.equal(p, q)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_pair_kernels_repeat_bitwise(nb, prec):
+    """Repeated calls on the same inputs give bitwise-identical outputs: every
+    j-sum (in-kernel folds, slice sums, group combines) has a fixed order, which
+    the checkpointed adjoint relies on when it recomputes the forward pass."""
+    x, v, m = ics.plummer(3001, seed=12)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    w = dev(np.random.default_rng(3).standard_normal((3, 3001)))
+    acc = dev(ics.plummer_mean_field(x))
+    nb.nbody_set_config(ipl=1, split=8)  # several j-slices, so the slice sum is exercised
+    try:
+        runs = []
+        for _ in range(3):
+            outs = [nb.nbody_accel(tx, tm, eps=0.01, precision=prec)]
+            outs += list(nb.nbody_accel_vjp(tx, tm, w, eps=0.01, precision=prec))
+            outs += list(nb.nbody_accel_jerk(tx, tv, tm, eps=0.01, precision=prec))
+            outs += list(nb.nbody_accel_jerk_snap(tx, tv, acc, tm, eps=0.01, precision=prec))
+            if prec == "fp64":
+                outs.append(nb.nbody_potential(tx, tm, eps=0.01))
+            runs.append([o.cpu() for o in outs])
+    finally:
+        nb.nbody_set_config()
+    for r in runs[1:]:
+        for p_, q_ in zip(runs[0], r):
+            assert torch.equal(p_, q_)
+
+
 def test_step_zero_steps_computes_acc(nb, oracle_mod):
     x, v, m = ics.plummer(300, seed=5)
     tx, tv, tm = dev(x), dev(v), dev(m)
