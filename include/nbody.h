@@ -252,7 +252,9 @@ typedef struct nbody_config {
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
   int32_t bitem;   /* streamed batched kernel (bsplit = 2): most particles per item of
-                      a system above 256 particles: 0 = automatic (1024), 256, 512 or 1024 */
+                      a system above 256 particles: 0 = automatic (1024), 256, 512 or
+                      1024; or 64: items of 64 particles of any system, each
+                      evaluated by one wave against the system's whole j-range */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros
@@ -276,7 +278,7 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * library's own copies (the caller's arrays are only read), and keeps the
  * fastest whose state stays finite.  Candidates: the resident kernel with 1, 2
  * or 4 i-particles per lane per pass; with allow_cooperative != 0 also the
- * split mode and the streamed kernel with items of 256, 512 or 1024 particles
+ * split mode and the streamed kernel with items of 64, 256, 512 or 1024 particles
  * (the modes that need every workgroup of a launch resident at once).  The
  * choice is recorded for this (device, precision, layout): later
  * nbody_step_batched calls on the same layout use it whenever the thread has

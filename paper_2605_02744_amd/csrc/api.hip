@@ -575,8 +575,8 @@ int nbody_set_config(const nbody_config* cfg) {
   if (cfg->bsplit < 0 || cfg->bsplit > 2) return set_error(NBODY_EINVAL, "bsplit must be 0, 1 or 2");
   if (cfg->bpass != 0 && cfg->bpass != 1 && cfg->bpass != 2 && cfg->bpass != 4)
     return set_error(NBODY_EINVAL, "bpass must be 0, 1, 2 or 4");
-  if (cfg->bitem != 0 && cfg->bitem != 256 && cfg->bitem != 512 && cfg->bitem != 1024)
-    return set_error(NBODY_EINVAL, "bitem must be 0, 256, 512 or 1024");
+  if (cfg->bitem != 0 && cfg->bitem != 64 && cfg->bitem != 256 && cfg->bitem != 512 && cfg->bitem != 1024)
+    return set_error(NBODY_EINVAL, "bitem must be 0, 64, 256, 512 or 1024");
   set_thread_config(*cfg);
   return NBODY_OK;
 }

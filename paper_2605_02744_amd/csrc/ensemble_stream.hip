@@ -277,6 +277,209 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
   }
 }
 
+// ------------------------------------------------------------- wave items
+// Items of at most 64 particles (bitem = 64), each evaluated by ONE wave
+// against its system's whole j-range.  The wave streams the system's pair
+// records through its own 64-record LDS slot (records written and read by
+// the same wave, so no workgroup barrier inside phase B): every wave of a
+// workgroup runs its own list of items, and a wave that finishes a short
+// item goes on to its next one instead of idling until a 1024-particle item
+// is done.  Items are placed longest first over all resident waves.  The
+// round protocol is the one above, per workgroup (one release, one acquire):
+// wave 0 publishes for every system the workgroup holds items of, one lane
+// per system, and waits for all of them the same way.
+constexpr int kWWaves = kSBlock / 64;  // waves per workgroup
+
+// Orders this wave's LDS accesses around a rewrite of its slot (LDS
+// instructions of one wave execute in order; this keeps the compiler from
+// moving reads and writes across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int MODE, bool EXCL>
+__global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
+    const int64_t* __restrict__ off, const double* __restrict__ epsv, const int* __restrict__ nparts,
+    const SItem* __restrict__ items, const int* __restrict__ wv_off, const int* __restrict__ wv_list,
+    const int* __restrict__ ws_off, const int2* __restrict__ ws_sys, double* __restrict__ x,
+    double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m, JRec<MODE>* __restrict__ xrec,
+    int* __restrict__ cnt, int64_t total, double dt, int64_t nsteps, double G, int acc_valid, uint64_t wait_ticks) {
+  using R = Real<MODE>;
+  constexpr bool kNear = MODE == kFP32C;
+  __shared__ JRec<MODE> slot[kWWaves][64];
+  __shared__ int lds_bad;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, lane = t & 63;
+  const int gw = blockIdx.x * kWWaves + wv;
+  const int q0 = wv_off[gw], q1 = wv_off[gw + 1];
+  const int s0 = ws_off[blockIdx.x], s1 = ws_off[blockIdx.x + 1];
+  JRec<MODE>* buf = slot[wv];
+  const double h = 0.5 * dt;
+  bool bad = false;  // a wait of this workgroup timed out (uniform)
+
+  const int64_t rounds = nsteps + (acc_valid ? 0 : 1);
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t s = acc_valid ? r : r - 1;  // step of this round; -1: the initial evaluation
+    JRec<MODE>* xb = xrec + (size_t)(r & 1) * total;
+    // ---- phase A: kick-drift this wave's particles and publish their records
+    for (int q = q0; q < q1; ++q) {
+      const SItem it = items[wv_list[q]];
+      if (lane < it.ni) {
+        const int64_t i = off[it.sys] + it.i0 + lane;
+        double xn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int64_t e = d * total + i;
+          if (s >= 0) {
+            double ve = v[e];
+            const double ae = a[e];
+            ve = fma(h, ae, ve);
+            if (s > 0) ve = fma(h, ae, ve);  // closing half-kick of the previous step, rounded separately
+            v[e] = ve;
+            xn[d] = fma(dt, ve, x[e]);
+            x[e] = xn[d];
+          } else {
+            xn[d] = x[e];
+          }
+        }
+        xb[i] = bad ? JRec<MODE>::make(NAN, NAN, NAN, NAN) : JRec<MODE>::make(xn[0], xn[1], xn[2], m[i]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+    __syncthreads();
+    if (wv == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int k = s0 + lane; k < s1; k += 64)
+        __hip_atomic_fetch_add(cnt + ws_sys[k].x, ws_sys[k].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // ---- wait, one lane per held system, until every item of it has published this round
+      int ok = bad ? 0 : 1;
+      for (int k = s0 + lane; k < s1 && ok; k += 64) {
+        const int sys = ws_sys[k].x;
+        const unsigned want = (unsigned)nparts[sys] * (unsigned)(r + 1);
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while ((int)((unsigned)__hip_atomic_load(cnt + sys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - want) < 0) {
+          if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) { ok = 0; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      const bool all_ok = __ballot(!ok) == 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (lane == 0) lds_bad = all_ok ? 0 : 1;
+    }
+    __syncthreads();
+    bad = bad || lds_bad != 0;
+
+    // ---- phase B: this wave's items, each against its system's whole j-range
+    for (int q = q0; q < q1; ++q) {
+      const SItem it = items[wv_list[q]];
+      const int64_t o = off[it.sys];
+      const int nc = (int)(off[it.sys + 1] - o);
+      const JRec<MODE>* src = xb + o;
+      const int ii = it.i0 + (lane < it.ni ? lane : it.ni - 1);  // system-local index of the lane's particle
+      const int iself = lane < it.ni ? ii : -1;
+      const double eps = epsv[it.sys];
+      const R e2 = (R)(eps * eps);
+      IPos<MODE> pi;
+      pi.from(src[ii]);
+      R rc2 = R(0);
+      if constexpr (kNear) rc2 = near_rc2(pi.hx, pi.hy, pi.hz, eps, nc);
+      R hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
+      JRec<MODE> nxt = lane < nc ? src[lane] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+#pragma unroll 1
+      for (int jt = 0; jt < nc; jt += 64) {
+        wave_lds_sync();  // the previous block's reads are done
+        buf[lane] = nxt;
+        wave_lds_sync();  // the block is in the slot
+        if (jt + 64 < nc) {
+          const int jn = jt + 64 + lane;
+          nxt = jn < nc ? src[jn] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+        }
+        R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
+#pragma unroll 16
+        for (int jj = 0; jj < 64; ++jj) {
+          const JRec<MODE> rj = buf[jj];
+          R dx, dy, dz;
+          if constexpr (kNear) disp_hi(rj, pi, dx, dy, dz);
+          else disp(rj, pi, dx, dy, dz);
+          const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          const R ri = rsq(r2);
+          R sc = (jmass(rj) * ri) * (ri * ri);
+          if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+          px = fma(sc, dx, px);
+          py = fma(sc, dy, py);
+          pz = fma(sc, dz, pz);
+          if constexpr (kNear) r2min = fminf(r2min, r2);
+        }
+        if constexpr (kNear) {
+          // the lane's own pair always has r2 = eps^2: in its block, rescan for another close pair
+          bool close = r2min < rc2;
+          if (close && (unsigned)(iself - jt) < 64u) {
+            close = false;
+            for (int jj = 0; jj < 64; ++jj) {
+              R dx, dy, dz;
+              disp_hi(buf[jj], pi, dx, dy, dz);
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              close = close || (r2 < rc2 && jt + jj != iself);
+            }
+          }
+          if (close) {
+            // rare: redo this block with float-float displacements for the close pairs
+            R qx = 0, qy = 0, qz = 0;
+            for (int jj = 0; jj < 64; ++jj) {
+              const JRec<MODE> rj = buf[jj];
+              R dx, dy, dz;
+              disp_hi(rj, pi, dx, dy, dz);
+              R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 < rc2) {
+                disp(rj, pi, dx, dy, dz);
+                r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              }
+              const R ri = rsq(r2);
+              R sc = (jmass(rj) * ri) * (ri * ri);
+              if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+              qx = fma(sc, dx, qx);
+              qy = fma(sc, dy, qy);
+              qz = fma(sc, dz, qz);
+            }
+            px = qx;
+            py = qy;
+            pz = qz;
+          }
+        }
+        fold(hx, lx, px);
+        fold(hy, ly, py);
+        fold(hz, lz, pz);
+      }
+      if (lane < it.ni) {
+        const int64_t i = o + ii;
+        a[i] = G * ((double)hx + (double)lx);
+        a[total + i] = G * ((double)hy + (double)ly);
+        a[2 * total + i] = G * ((double)hz + (double)lz);
+      }
+    }
+  }
+  // closing half-kick of the last step; a workgroup whose wait timed out marks its particles NaN
+  for (int q = q0; q < q1; ++q) {
+    const SItem it = items[wv_list[q]];
+    if (lane < it.ni) {
+      const int64_t i = off[it.sys] + it.i0 + lane;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int64_t e = d * total + i;
+        if (bad) {
+          x[e] = NAN;
+          v[e] = NAN;
+          a[e] = NAN;
+        } else if (nsteps > 0) {
+          v[e] = fma(h, a[e], v[e]);
+        }
+      }
+    }
+  }
+}
+
 __global__ void zero_counters_kernel(int* c, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0;
 }
@@ -292,8 +495,10 @@ struct SPlan {
   double* d_eps = nullptr;
   int* d_nparts = nullptr;
   SItem* d_items = nullptr;
-  int* d_wg_off = nullptr;
+  int* d_wg_off = nullptr;   // per workgroup (per wave for wave items): offsets into d_wg_list
   int* d_wg_list = nullptr;
+  int* d_ws_off = nullptr;   // wave items: per workgroup, offsets into d_ws_sys
+  int2* d_ws_sys = nullptr;  // wave items: (system, items of it held by the workgroup)
   void* d_xrec = nullptr;
   int* d_cnt = nullptr;
 };
@@ -303,7 +508,7 @@ std::vector<SPlan*> g_splans;
 
 void free_splan(SPlan* p) {
   for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_nparts, (void*)p->d_items, (void*)p->d_wg_off,
-                  (void*)p->d_wg_list, p->d_xrec, (void*)p->d_cnt})
+                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt})
     if (q) (void)hipFree(q);
   delete p;
 }
@@ -315,18 +520,22 @@ bool supload(T** dst, const std::vector<T>& src) {
   return src.empty() || hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) == hipSuccess;
 }
 
-template <int MODE>
-int resident_per_cu() {
+// Workgroups of the kernel that fit on one CU at once (both EXCL variants), at most kSMaxPerCu.
+template <typename K>
+int resident_per_cu(K k0, K k1) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&ens_stream_kernel<MODE, false>),
-                                                    kSBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k0), kSBlock, 0) != hipSuccess)
     nb = 1;
   int nb2 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, reinterpret_cast<const void*>(&ens_stream_kernel<MODE, true>),
-                                                    kSBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, reinterpret_cast<const void*>(k1), kSBlock, 0) != hipSuccess)
     nb2 = 1;
   (void)hipGetLastError();
   return std::max(1, std::min(kSMaxPerCu, std::min(nb, nb2)));
+}
+
+template <int MODE>
+int resident_per_cu() {
+  return resident_per_cu(&ens_stream_kernel<MODE, false>, &ens_stream_kernel<MODE, true>);
 }
 
 // j-records one lane applies per round for an item of a system of nc
@@ -425,6 +634,100 @@ int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   return NBODY_OK;
 }
 
+// Plan of wave items (bitem = 64): every system is cut into items of 64
+// consecutive particles (the last one shorter); an item's cost per round is
+// its system's j-range padded to blocks of 64 plus a fixed per-item overhead
+// (the own-block rescan and the item set-up); items are placed longest first
+// on the least loaded of all resident waves, and workgroup b runs waves
+// [16 b, 16 b + 16).
+template <int MODE>
+int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, SPlan** out) {
+  SPlan* p = new SPlan();
+  p->off.assign(off, off + ncl + 1);
+  p->eps.assign(eps, eps + ncl);
+  p->precision = precision;
+  p->device = device;
+  p->ncl = ncl;
+  p->bitem = 64;
+  p->total = off[ncl];
+  std::vector<SItem> items;
+  std::vector<double> cost;
+  std::vector<int> nparts(ncl, 0);
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nc = off[c + 1] - off[c];
+    if (nc <= 0) continue;
+    if (nc > (int64_t(1) << 24)) {
+      delete p;
+      return set_error(NBODY_EUNSUPPORTED, "batched: a system of more than 2^24 particles");
+    }
+    for (int64_t i0 = 0; i0 < nc; i0 += 64) {
+      items.push_back(SItem{c, (int)i0, (int)std::min<int64_t>(64, nc - i0), 1});
+      cost.push_back((double)((nc + 63) / 64 * 64) + 48.0);
+      ++nparts[c];
+    }
+  }
+  const int cap_wg = std::max(1, resident_per_cu(&ens_wave_kernel<MODE, false>, &ens_wave_kernel<MODE, true>) *
+                                     cu_count(device));
+  const int nwg = std::max(1, std::min<int>((int)((items.size() + kWWaves - 1) / kWWaves), cap_wg));
+  const int nw = nwg * kWWaves;
+  std::vector<int> order(items.size());
+  for (size_t k = 0; k < items.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int w) { return cost[u] > cost[w]; });
+  std::vector<std::vector<int>> lists(nw);
+  std::vector<double> load(nw, 0.0);
+  using Slot = std::pair<double, int>;
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+  for (int w = 0; w < nw; ++w) heap.push({0.0, w});
+  for (int k : order) {
+    Slot sl = heap.top();
+    heap.pop();
+    lists[sl.second].push_back(k);
+    load[sl.second] = sl.first + cost[k];
+    heap.push({load[sl.second], sl.second});
+  }
+  std::vector<int> wv_off(nw + 1, 0), wv_list;
+  for (int w = 0; w < nw; ++w) {
+    wv_list.insert(wv_list.end(), lists[w].begin(), lists[w].end());
+    wv_off[w + 1] = (int)wv_list.size();
+  }
+  // per workgroup: the systems it holds items of, with the number of such items
+  std::vector<int> ws_off(nwg + 1, 0);
+  std::vector<int2> ws_sys;
+  double maxpairs = 0.0;
+  for (int b = 0; b < nwg; ++b) {
+    std::vector<std::pair<int, int>> held;
+    for (int w = b * kWWaves; w < (b + 1) * kWWaves; ++w)
+      for (int k : lists[w]) held.push_back({items[k].sys, 1});
+    std::sort(held.begin(), held.end());
+    for (size_t k = 0; k < held.size();) {
+      size_t e = k;
+      while (e < held.size() && held[e].first == held[k].first) ++e;
+      ws_sys.push_back(make_int2(held[k].first, (int)(e - k)));
+      k = e;
+    }
+    ws_off[b + 1] = (int)ws_sys.size();
+  }
+  for (int w = 0; w < nw; ++w) {
+    double pairs = 0.0;
+    for (int k : lists[w]) pairs += 64.0 * (double)(off[items[k].sys + 1] - off[items[k].sys]);
+    maxpairs = std::max(maxpairs, pairs * kWWaves);
+  }
+  p->nwg = nwg;
+  p->wait_ticks = (uint64_t)(1.0e8 * (2.0 + maxpairs / 1.0e8));
+  bool ok = supload(&p->d_off, p->off) && supload(&p->d_eps, p->eps) && supload(&p->d_nparts, nparts) &&
+            supload(&p->d_items, items) && supload(&p->d_wg_off, wv_off) && supload(&p->d_wg_list, wv_list) &&
+            supload(&p->d_ws_off, ws_off) && supload(&p->d_ws_sys, ws_sys) &&
+            hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
+            hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_splan(p);
+    return set_error(NBODY_ENOMEM, "batched: plan upload failed");
+  }
+  *out = p;
+  return NBODY_OK;
+}
+
 SPlan* find_splan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, int bitem) {
   for (SPlan* p : g_splans) {
     if (p->device != device || p->precision != precision || p->ncl != ncl || p->bitem != bitem) continue;
@@ -440,6 +743,20 @@ int launch_splan(const SPlan* p, double* x, double* v, double* a, const double* 
   zero_counters_kernel<<<1, 256, 0, s>>>(p->d_cnt, std::max(1, p->ncl));
   NB_LAUNCH_CHECK("zero_counters_kernel");
   auto* rec = static_cast<JRec<MODE>*>(p->d_xrec);
+  if (p->bitem == 64) {
+    if (excl)
+      ens_wave_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items, p->d_wg_off,
+                                                             p->d_wg_list, p->d_ws_off, p->d_ws_sys, x, v, a, m, rec,
+                                                             p->d_cnt, p->total, dt, nsteps, G, acc_valid ? 1 : 0,
+                                                             p->wait_ticks);
+    else
+      ens_wave_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items, p->d_wg_off,
+                                                              p->d_wg_list, p->d_ws_off, p->d_ws_sys, x, v, a, m, rec,
+                                                              p->d_cnt, p->total, dt, nsteps, G, acc_valid ? 1 : 0,
+                                                              p->wait_ticks);
+    NB_LAUNCH_CHECK("ens_wave_kernel");
+    return NBODY_OK;
+  }
   if (excl)
     ens_stream_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_nparts, p->d_items,
                                                                p->d_wg_off, p->d_wg_list, x, v, a, m, rec, p->d_cnt,
@@ -465,9 +782,17 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
       return set_error(NBODY_EINVAL, "batched: the plan for this layout must be built by one call outside stream capture");
     int st;
-    if (precision == NBODY_FP64) st = build_splan<NBODY_FP64>(ncl, off, eps, precision, device, bitem, &p);
-    else if (precision == NBODY_FP32C) st = build_splan<NBODY_FP32C>(ncl, off, eps, precision, device, bitem, &p);
-    else st = build_splan<NBODY_FP32>(ncl, off, eps, precision, device, bitem, &p);
+    if (bitem == 64) {
+      if (precision == NBODY_FP64) st = build_wplan<NBODY_FP64>(ncl, off, eps, precision, device, &p);
+      else if (precision == NBODY_FP32C) st = build_wplan<NBODY_FP32C>(ncl, off, eps, precision, device, &p);
+      else st = build_wplan<NBODY_FP32>(ncl, off, eps, precision, device, &p);
+    } else if (precision == NBODY_FP64) {
+      st = build_splan<NBODY_FP64>(ncl, off, eps, precision, device, bitem, &p);
+    } else if (precision == NBODY_FP32C) {
+      st = build_splan<NBODY_FP32C>(ncl, off, eps, precision, device, bitem, &p);
+    } else {
+      st = build_splan<NBODY_FP32>(ncl, off, eps, precision, device, bitem, &p);
+    }
     if (st) return st;
     g_splans.push_back(p);
   }

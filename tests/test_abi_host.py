@@ -145,5 +145,8 @@ def test_set_config_validation(lib):
         nb.nbody_set_config(bpass=3)
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(bitem=300)
+    with pytest.raises(nb.NBodyError):
+        nb.nbody_set_config(bitem=32)
+    nb.nbody_set_config(bsplit=2, bitem=64)
     nb.nbody_set_config(ipl=2, split=4)
     nb.nbody_set_config()

@@ -353,25 +353,27 @@ def test_batched_pass_widths_agree(nb, prec):
             assert np.abs(out[0][1] - out[k][1]).max() <= 1e-8
 
 
-def _stream(nb, fn):
-    nb.nbody_set_config(bsplit=2)
+def _stream(nb, fn, bitem=0):
+    nb.nbody_set_config(bsplit=2, bitem=bitem)
     try:
         return fn()
     finally:
         nb.nbody_set_config()
 
 
+@pytest.mark.parametrize("bitem", [0, 64])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_stream_batched_matches_oracle(nb, oracle_mod, prec):
-    """Streamed ensemble kernel: systems cut into items of <= 128 particles
-    (several items per system above 128) against the oracle's KDK."""
+def test_stream_batched_matches_oracle(nb, oracle_mod, prec, bitem):
+    """Streamed ensemble kernel against the oracle's KDK: items of <= 1024
+    particles (one item per system here), or of 64 particles evaluated by one
+    wave each (several items per system above 64)."""
     sizes = [5, 64, 65, 80, 129, 700, 1300]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=23, sizes=sizes)
     dt, steps = 1.0 / 512, 5
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
     _stream(nb, lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, dt, steps, precision=prec,
-                                              check_finite=True))
+                                              check_finite=True), bitem)
     for c in range(len(sizes)):
         s, e = off[c], off[c + 1]
         rx, rv = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], dt, steps, eps=float(epsv[c]))
@@ -385,7 +387,8 @@ def test_stream_batched_matches_oracle(nb, oracle_mod, prec):
             assert dv <= tol_v and dx <= tol_v * dt * steps, (c, dx, dv, tol_v)
 
 
-@pytest.mark.parametrize("prec,bitem", [("fp64", 0), ("fp32c", 0), ("fp32c", 256), ("fp32c", 1024)])
+@pytest.mark.parametrize("prec,bitem", [("fp64", 0), ("fp32c", 0), ("fp32c", 256), ("fp32c", 1024), ("fp64", 64),
+                                        ("fp32c", 64)])
 def test_stream_batched_agrees_with_resident_kernel(nb, prec, bitem):
     sizes = [4096, 3000, 2048, 700, 257, 64, 1]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=24, sizes=sizes)
@@ -403,7 +406,8 @@ def test_stream_batched_agrees_with_resident_kernel(nb, prec, bitem):
     assert np.abs(out[0][1] - out[1][1]).max() <= 1e-8
 
 
-def test_stream_batched_resumable_and_eps0(nb, oracle_mod):
+@pytest.mark.parametrize("bitem", [0, 64])
+def test_stream_batched_resumable_and_eps0(nb, oracle_mod, bitem):
     sizes = [300, 77, 1025]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=25, sizes=sizes)
     res = []
@@ -413,7 +417,7 @@ def test_stream_batched_resumable_and_eps0(nb, oracle_mod):
         valid = False
         for c in chunks:
             _stream(nb, lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 256, c, precision="fp32c",
-                                                      acc_valid=valid))
+                                                      acc_valid=valid), bitem)
             valid = True
         res.append((tx.cpu(), tv.cpu()))
     for r in res[1:]:
@@ -423,19 +427,20 @@ def test_stream_batched_resumable_and_eps0(nb, oracle_mod):
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
     _stream(nb, lambda: nb.nbody_step_batched(off, eps0, tx, tv, ta, tm, 1.0 / 1024, 2, precision="fp64",
-                                              exclude_self=True, check_finite=True))
+                                              exclude_self=True, check_finite=True), bitem)
     for c in range(len(sizes)):
         s, e = off[c], off[c + 1]
         rx, _ = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], 1.0 / 1024, 2, eps=0.0)
         assert np.abs(tx.cpu().numpy()[:, s:e] - rx).max() <= 1e-11
 
 
-def test_stream_batched_graph_capture(nb):
+@pytest.mark.parametrize("bitem", [0, 64])
+def test_stream_batched_graph_capture(nb, bitem):
     sizes = [64, 257, 1000]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=26, sizes=sizes)
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
-    nb.nbody_set_config(bsplit=2)
+    nb.nbody_set_config(bsplit=2, bitem=bitem)
     try:
         ex, ev, ea = tx.clone(), tv.clone(), ta.clone()
         nb.nbody_step_batched(off, epsv, ex, ev, ea, tm, 1.0 / 512, 2, precision="fp32c")
@@ -467,7 +472,7 @@ def test_tune_batched_records_and_applies_choice(nb):
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=27, sizes=sizes)
     tx, tv, tm = dev(x), dev(v), dev(m)
     best = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 4, precision="fp32c")
-    assert best["bsplit"] in (0, 1, 2) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 256, 512, 1024)
+    assert best["bsplit"] in (0, 1, 2) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 64, 256, 512, 1024)
     assert torch.equal(tx, dev(x)) and torch.equal(tv, dev(v))
     out = []
     for forced in (False, True):
