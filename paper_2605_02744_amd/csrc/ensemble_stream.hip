@@ -281,13 +281,17 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_stream_kernel(
 // Items of at most 64 particles (bitem = 64), each evaluated by ONE wave
 // against its system's whole j-range.  The wave streams the system's pair
 // records through its own 64-record LDS slot (records written and read by
-// the same wave, so no workgroup barrier inside phase B): every wave of a
-// workgroup runs its own list of items, and a wave that finishes a short
-// item goes on to its next one instead of idling until a 1024-particle item
-// is done.  Items are placed longest first over all resident waves.  The
-// round protocol is the one above, per workgroup (one release, one acquire):
-// wave 0 publishes for every system the workgroup holds items of, one lane
-// per system, and waits for all of them the same way.
+// the same wave, so no workgroup barrier inside an item).  Items are placed
+// longest first over the workgroups; inside a workgroup the waves take the
+// next item of its list (longest first) from an LDS counter as they become
+// free, so the SIMD arbiter's preference for older waves, which makes
+// statically assigned waves of equal cost finish up to 1.7x apart, costs
+// nothing, and the workgroup ends a round with its shortest items.  Phase A
+// and the closing half-kick deal the workgroup's items to its waves
+// statically.  The round protocol is the one above, per workgroup (one
+// release, one acquire): wave 0 publishes for every system the workgroup
+// holds items of, one lane per system, and waits for all of them the same
+// way.
 constexpr int kWWaves = kSBlock / 64;  // waves per workgroup
 
 // Orders this wave's LDS accesses around a rewrite of its slot (LDS
@@ -302,7 +306,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <int MODE, bool EXCL>
 __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
     const int64_t* __restrict__ off, const double* __restrict__ epsv, const int* __restrict__ nparts,
-    const SItem* __restrict__ items, const int* __restrict__ wv_off, const int* __restrict__ wv_list,
+    const SItem* __restrict__ items, const int* __restrict__ wg_off, const int* __restrict__ wg_list,
     const int* __restrict__ ws_off, const int2* __restrict__ ws_sys, double* __restrict__ x,
     double* __restrict__ v, double* __restrict__ a, const double* __restrict__ m, JRec<MODE>* __restrict__ xrec,
     int* __restrict__ cnt, int64_t total, double dt, int64_t nsteps, double G, int acc_valid, uint64_t wait_ticks) {
@@ -310,10 +314,10 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
   constexpr bool kNear = MODE == kFP32C;
   __shared__ JRec<MODE> slot[kWWaves][64];
   __shared__ int lds_bad;
+  __shared__ int next_item;
   const int t = threadIdx.x;
   const int wv = t >> 6, lane = t & 63;
-  const int gw = blockIdx.x * kWWaves + wv;
-  const int q0 = wv_off[gw], q1 = wv_off[gw + 1];
+  const int q0 = wg_off[blockIdx.x], q1 = wg_off[blockIdx.x + 1];
   const int s0 = ws_off[blockIdx.x], s1 = ws_off[blockIdx.x + 1];
   JRec<MODE>* buf = slot[wv];
   const double h = 0.5 * dt;
@@ -323,9 +327,9 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
   for (int64_t r = 0; r < rounds; ++r) {
     const int64_t s = acc_valid ? r : r - 1;  // step of this round; -1: the initial evaluation
     JRec<MODE>* xb = xrec + (size_t)(r & 1) * total;
-    // ---- phase A: kick-drift this wave's particles and publish their records
-    for (int q = q0; q < q1; ++q) {
-      const SItem it = items[wv_list[q]];
+    // ---- phase A: kick-drift the workgroup's particles (items dealt to the waves) and publish their records
+    for (int q = q0 + wv; q < q1; q += kWWaves) {
+      const SItem it = items[wg_list[q]];
       if (lane < it.ni) {
         const int64_t i = off[it.sys] + it.i0 + lane;
         double xn[3];
@@ -366,14 +370,22 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
       }
       const bool all_ok = __ballot(!ok) == 0;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (lane == 0) lds_bad = all_ok ? 0 : 1;
+      if (lane == 0) {
+        lds_bad = all_ok ? 0 : 1;
+        next_item = 0;
+      }
     }
     __syncthreads();
     bad = bad || lds_bad != 0;
 
-    // ---- phase B: this wave's items, each against its system's whole j-range
-    for (int q = q0; q < q1; ++q) {
-      const SItem it = items[wv_list[q]];
+    // ---- phase B: each wave takes the workgroup's next item and evaluates it
+    // against its system's whole j-range
+    for (;;) {
+      int k = 0;
+      if (lane == 0) k = atomicAdd(&next_item, 1);
+      k = __builtin_amdgcn_readfirstlane(k);
+      if (k >= q1 - q0) break;
+      const SItem it = items[wg_list[q0 + k]];
       const int64_t o = off[it.sys];
       const int nc = (int)(off[it.sys + 1] - o);
       const JRec<MODE>* src = xb + o;
@@ -459,10 +471,11 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
         a[2 * total + i] = G * ((double)hz + (double)lz);
       }
     }
+    __syncthreads();  // the accelerations are visible to the waves that kick these particles next
   }
   // closing half-kick of the last step; a workgroup whose wait timed out marks its particles NaN
-  for (int q = q0; q < q1; ++q) {
-    const SItem it = items[wv_list[q]];
+  for (int q = q0 + wv; q < q1; q += kWWaves) {
+    const SItem it = items[wg_list[q]];
     if (lane < it.ni) {
       const int64_t i = off[it.sys] + it.i0 + lane;
 #pragma unroll
@@ -495,7 +508,7 @@ struct SPlan {
   double* d_eps = nullptr;
   int* d_nparts = nullptr;
   SItem* d_items = nullptr;
-  int* d_wg_off = nullptr;   // per workgroup (per wave for wave items): offsets into d_wg_list
+  int* d_wg_off = nullptr;   // per workgroup: offsets into d_wg_list
   int* d_wg_list = nullptr;
   int* d_ws_off = nullptr;   // wave items: per workgroup, offsets into d_ws_sys
   int2* d_ws_sys = nullptr;  // wave items: (system, items of it held by the workgroup)
@@ -638,8 +651,7 @@ int build_splan(int32_t ncl, const int64_t* off, const double* eps, int precisio
 // consecutive particles (the last one shorter); an item's cost per round is
 // its system's j-range padded to blocks of 64 plus a fixed per-item overhead
 // (the own-block rescan and the item set-up); items are placed longest first
-// on the least loaded of all resident waves, and workgroup b runs waves
-// [16 b, 16 b + 16).
+// on the least loaded workgroup.
 template <int MODE>
 int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, SPlan** out) {
   SPlan* p = new SPlan();
@@ -669,26 +681,25 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   const int cap_wg = std::max(1, resident_per_cu(&ens_wave_kernel<MODE, false>, &ens_wave_kernel<MODE, true>) *
                                      cu_count(device));
   const int nwg = std::max(1, std::min<int>((int)((items.size() + kWWaves - 1) / kWWaves), cap_wg));
-  const int nw = nwg * kWWaves;
   std::vector<int> order(items.size());
   for (size_t k = 0; k < items.size(); ++k) order[k] = (int)k;
   std::stable_sort(order.begin(), order.end(), [&](int u, int w) { return cost[u] > cost[w]; });
-  std::vector<std::vector<int>> lists(nw);
-  std::vector<double> load(nw, 0.0);
+  // longest first over the workgroups; each list stays in decreasing cost,
+  // the order in which the workgroup's waves take its items
+  std::vector<std::vector<int>> lists(nwg);
   using Slot = std::pair<double, int>;
   std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
-  for (int w = 0; w < nw; ++w) heap.push({0.0, w});
+  for (int w = 0; w < nwg; ++w) heap.push({0.0, w});
   for (int k : order) {
     Slot sl = heap.top();
     heap.pop();
     lists[sl.second].push_back(k);
-    load[sl.second] = sl.first + cost[k];
-    heap.push({load[sl.second], sl.second});
+    heap.push({sl.first + cost[k], sl.second});
   }
-  std::vector<int> wv_off(nw + 1, 0), wv_list;
-  for (int w = 0; w < nw; ++w) {
-    wv_list.insert(wv_list.end(), lists[w].begin(), lists[w].end());
-    wv_off[w + 1] = (int)wv_list.size();
+  std::vector<int> wg_off(nwg + 1, 0), wg_list;
+  for (int w = 0; w < nwg; ++w) {
+    wg_list.insert(wg_list.end(), lists[w].begin(), lists[w].end());
+    wg_off[w + 1] = (int)wg_list.size();
   }
   // per workgroup: the systems it holds items of, with the number of such items
   std::vector<int> ws_off(nwg + 1, 0);
@@ -696,8 +707,7 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   double maxpairs = 0.0;
   for (int b = 0; b < nwg; ++b) {
     std::vector<std::pair<int, int>> held;
-    for (int w = b * kWWaves; w < (b + 1) * kWWaves; ++w)
-      for (int k : lists[w]) held.push_back({items[k].sys, 1});
+    for (int k : lists[b]) held.push_back({items[k].sys, 1});
     std::sort(held.begin(), held.end());
     for (size_t k = 0; k < held.size();) {
       size_t e = k;
@@ -707,15 +717,15 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
     }
     ws_off[b + 1] = (int)ws_sys.size();
   }
-  for (int w = 0; w < nw; ++w) {
+  for (int b = 0; b < nwg; ++b) {
     double pairs = 0.0;
-    for (int k : lists[w]) pairs += 64.0 * (double)(off[items[k].sys + 1] - off[items[k].sys]);
-    maxpairs = std::max(maxpairs, pairs * kWWaves);
+    for (int k : lists[b]) pairs += 64.0 * (double)(off[items[k].sys + 1] - off[items[k].sys]);
+    maxpairs = std::max(maxpairs, pairs);
   }
   p->nwg = nwg;
   p->wait_ticks = (uint64_t)(1.0e8 * (2.0 + maxpairs / 1.0e8));
   bool ok = supload(&p->d_off, p->off) && supload(&p->d_eps, p->eps) && supload(&p->d_nparts, nparts) &&
-            supload(&p->d_items, items) && supload(&p->d_wg_off, wv_off) && supload(&p->d_wg_list, wv_list) &&
+            supload(&p->d_items, items) && supload(&p->d_wg_off, wg_off) && supload(&p->d_wg_list, wg_list) &&
             supload(&p->d_ws_off, ws_off) && supload(&p->d_ws_sys, ws_sys) &&
             hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
             hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
