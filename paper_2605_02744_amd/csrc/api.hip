@@ -407,7 +407,7 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0});
   if (allow_cooperative) {
     cand.push_back(BatchConfig{1, 0, 0});
-    for (int item : {256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});
+    for (int item : {64, 256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});
   }
   double *sx = nullptr, *sv = nullptr, *sa = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
