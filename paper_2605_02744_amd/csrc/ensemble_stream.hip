@@ -408,61 +408,58 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
           const int jn = jt + 64 + lane;
           nxt = jn < nc ? src[jn] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
         }
-        R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
+        // OWN: the block holding the lanes' own particles (the item's 64
+        // particles are one aligned block of its system): there the own pair,
+        // whose r2 is eps^2, is left out of the near-field minimum
+        auto block = [&](auto own_tag) {
+          constexpr bool kOwn = decltype(own_tag)::value;
+          R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
 #pragma unroll 16
-        for (int jj = 0; jj < 64; ++jj) {
-          const JRec<MODE> rj = buf[jj];
-          R dx, dy, dz;
-          if constexpr (kNear) disp_hi(rj, pi, dx, dy, dz);
-          else disp(rj, pi, dx, dy, dz);
-          const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-          const R ri = rsq(r2);
-          R sc = (jmass(rj) * ri) * (ri * ri);
-          if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
-          px = fma(sc, dx, px);
-          py = fma(sc, dy, py);
-          pz = fma(sc, dz, pz);
-          if constexpr (kNear) r2min = fminf(r2min, r2);
-        }
-        if constexpr (kNear) {
-          // the lane's own pair always has r2 = eps^2: in its block, rescan for another close pair
-          bool close = r2min < rc2;
-          if (close && (unsigned)(iself - jt) < 64u) {
-            close = false;
-            for (int jj = 0; jj < 64; ++jj) {
-              R dx, dy, dz;
-              disp_hi(buf[jj], pi, dx, dy, dz);
-              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-              close = close || (r2 < rc2 && jt + jj != iself);
-            }
+          for (int jj = 0; jj < 64; ++jj) {
+            const JRec<MODE> rj = buf[jj];
+            R dx, dy, dz;
+            if constexpr (kNear) disp_hi(rj, pi, dx, dy, dz);
+            else disp(rj, pi, dx, dy, dz);
+            const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+            const R ri = rsq(r2);
+            R sc = (jmass(rj) * ri) * (ri * ri);
+            if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+            px = fma(sc, dx, px);
+            py = fma(sc, dy, py);
+            pz = fma(sc, dz, pz);
+            if constexpr (kNear) r2min = fminf(r2min, (kOwn && jt + jj == ii) ? R(3.0e38f) : r2);
           }
-          if (close) {
-            // rare: redo this block with float-float displacements for the close pairs
-            R qx = 0, qy = 0, qz = 0;
-            for (int jj = 0; jj < 64; ++jj) {
-              const JRec<MODE> rj = buf[jj];
-              R dx, dy, dz;
-              disp_hi(rj, pi, dx, dy, dz);
-              R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-              if (r2 < rc2) {
-                disp(rj, pi, dx, dy, dz);
-                r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          if constexpr (kNear) {
+            if (r2min < rc2) {
+              // rare: redo this block with float-float displacements for the close pairs
+              R qx = 0, qy = 0, qz = 0;
+              for (int jj = 0; jj < 64; ++jj) {
+                const JRec<MODE> rj = buf[jj];
+                R dx, dy, dz;
+                disp_hi(rj, pi, dx, dy, dz);
+                R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+                if (r2 < rc2) {
+                  disp(rj, pi, dx, dy, dz);
+                  r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+                }
+                const R ri = rsq(r2);
+                R sc = (jmass(rj) * ri) * (ri * ri);
+                if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+                qx = fma(sc, dx, qx);
+                qy = fma(sc, dy, qy);
+                qz = fma(sc, dz, qz);
               }
-              const R ri = rsq(r2);
-              R sc = (jmass(rj) * ri) * (ri * ri);
-              if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
-              qx = fma(sc, dx, qx);
-              qy = fma(sc, dy, qy);
-              qz = fma(sc, dz, qz);
+              px = qx;
+              py = qy;
+              pz = qz;
             }
-            px = qx;
-            py = qy;
-            pz = qz;
           }
-        }
-        fold(hx, lx, px);
-        fold(hy, ly, py);
-        fold(hz, lz, pz);
+          fold(hx, lx, px);
+          fold(hy, ly, py);
+          fold(hz, lz, pz);
+        };
+        if (jt == it.i0) block(std::true_type{});
+        else block(std::false_type{});
       }
       if (lane < it.ni) {
         const int64_t i = o + ii;
