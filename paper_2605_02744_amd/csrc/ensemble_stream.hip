@@ -411,11 +411,15 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
         // OWN: the block holding the lanes' own particles (the item's 64
         // particles are one aligned block of its system): there the own pair,
         // whose r2 is eps^2, is left out of the near-field minimum
-        auto block = [&](auto own_tag) {
+        // FULL: 64 records; otherwise the system's last, partly filled block,
+        // of which only the cnt valid records are applied
+        auto block = [&](auto own_tag, auto full_tag, int cnt) {
           constexpr bool kOwn = decltype(own_tag)::value;
+          constexpr bool kFull = decltype(full_tag)::value;
+          const int jend = kFull ? 64 : cnt;
           R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
 #pragma unroll 16
-          for (int jj = 0; jj < 64; ++jj) {
+          for (int jj = 0; jj < jend; ++jj) {
             const JRec<MODE> rj = buf[jj];
             R dx, dy, dz;
             if constexpr (kNear) disp_hi(rj, pi, dx, dy, dz);
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
             if (r2min < rc2) {
               // rare: redo this block with float-float displacements for the close pairs
               R qx = 0, qy = 0, qz = 0;
-              for (int jj = 0; jj < 64; ++jj) {
+              for (int jj = 0; jj < jend; ++jj) {
                 const JRec<MODE> rj = buf[jj];
                 R dx, dy, dz;
                 disp_hi(rj, pi, dx, dy, dz);
@@ -458,8 +462,14 @@ __global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
           fold(hy, ly, py);
           fold(hz, lz, pz);
         };
-        if (jt == it.i0) block(std::true_type{});
-        else block(std::false_type{});
+        const int cnt = nc - jt;
+        if (cnt >= 64) {
+          if (jt == it.i0) block(std::true_type{}, std::true_type{}, 64);
+          else block(std::false_type{}, std::true_type{}, 64);
+        } else {
+          if (jt == it.i0) block(std::true_type{}, std::false_type{}, cnt);
+          else block(std::false_type{}, std::false_type{}, cnt);
+        }
       }
       if (lane < it.ni) {
         const int64_t i = o + ii;
