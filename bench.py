@@ -41,7 +41,6 @@ UNIT = "G pair-interactions/s"
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (packed) peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
 FLOPS_PER_PAIR = 20          # acceleration-only softened interaction convention
-VJP_FLOPS_PER_PAIR = 45      # convention for the VJP pair
 KERNEL_SOURCES = ("paper_2605_02744_amd/csrc/pairs.hip", "paper_2605_02744_amd/csrc/pair_math.h")
 
 
@@ -189,8 +188,7 @@ def bench_force(args, torch, nb):
 
     tuned = None
     if args.tune:
-        tuned = {p: nb.nbody_tune(n, p, os.path.join(ROOT, "gpurun_out", "tune.jsonl") if os.path.isdir(
-            os.path.join(ROOT, "gpurun_out")) else None) for p in (args.precision, "fp64")}
+        tuned = {p: nb.nbody_tune(n, p, args.tune_cache) for p in (args.precision, "fp64")}
 
     f32 = lambda: nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
     ms, per, wall = timed(f32, args.steps, args.warmup, torch)
@@ -589,6 +587,7 @@ def main():
     ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2],
                     help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items")
     ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
+    ap.add_argument("--tune-cache", default=None, help="with --tune: JSON-lines file the tuner appends its choice to")
     ap.add_argument("--bitem", type=int, default=0, help="streamed ensemble: most particles per item (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
