@@ -45,9 +45,10 @@ __device__ __forceinline__ JRec<MODE> load_rec(const double* __restrict__ x, con
 // in each block of kFold j-particles.  Rounding a coordinate to FP32 moves it
 // by up to 2^-24 |x|, which only matters for pairs much closer than |x|; when
 // a block holds a pair closer than d_c(i) = max(kNearX |x_i|, kNearEps eps),
-// that lane recomputes the block's partial sum with float-float displacements
-// for those pairs.  Such blocks are rare (a pair closer than a few eps), so the
-// force costs one extra min per pair and keeps float-float accuracy.
+// that lane rescans the block and replaces the term of each such pair by its
+// term from float-float displacements.  Such blocks are rare (a pair closer
+// than a few eps, or the block of the lane's own pair), so the force costs one
+// extra min per pair and keeps float-float accuracy.
 
 // Grid: (ceil(n / (256*IPL)), split).  Block y handles j in [y*chunk, min(n, (y+1)*chunk)).
 // split == 1: writes G*(hi+lo) to a[c*n+i].  split > 1: writes hi+lo to
@@ -126,40 +127,29 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
       if constexpr (NEAR) {
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
-          // the lane's own pair (zero displacement) always sets r2min = eps^2:
-          // in the block holding it, rescan for a close pair other than that one
-          bool close = r2min[k] < rc2[k];
-          if (close && (unsigned)(iidx[k] - (jt + f)) < (unsigned)kFold) {
-            close = false;
-            for (int jj = f; jj < f + kFold; ++jj) {
-              R dx, dy, dz;
-              disp_hi(cur[jj], pi[k], dx, dy, dz);
-              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-              close = close || (r2 < rc2[k] && jt + jj != iidx[k]);
-            }
-          }
-          if (close) {
-            // rare: redo this block for lane k with float-float displacements for the close pairs
-            R qx = 0, qy = 0, qz = 0;
+          // rare: the block holds a pair closer than the repair radius (the
+          // lane's own pair, r2 = eps^2, always is one): for every such pair
+          // other than the own pair, replace its term from rounded positions
+          // by its term from float-float displacements
+          if (r2min[k] < rc2[k]) {
             for (int jj = f; jj < f + kFold; ++jj) {
               const JRec<MODE> r = cur[jj];
               R dx, dy, dz;
               disp_hi(r, pi[k], dx, dy, dz);
-              R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-              if (r2 < rc2[k]) {
-                disp(r, pi[k], dx, dy, dz);
-                r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 < rc2[k] && jt + jj != iidx[k]) {
+                const R ri = rsq(r2);
+                const R s = (jmass(r) * ri) * (ri * ri);
+                R ex, ey, ez;
+                disp(r, pi[k], ex, ey, ez);
+                const R q2 = fma(ez, ez, fma(ey, ey, fma(ex, ex, e2)));
+                const R qi = rsq(q2);
+                const R t = (jmass(r) * qi) * (qi * qi);
+                px[k] = fma(t, ex, fma(-s, dx, px[k]));
+                py[k] = fma(t, ey, fma(-s, dy, py[k]));
+                pz[k] = fma(t, ez, fma(-s, dz, pz[k]));
               }
-              R ri = rsq(r2);
-              R s = (jmass(r) * ri) * (ri * ri);
-              if (EXCL) s = (jt + jj == iidx[k]) ? R(0) : s;
-              qx = fma(s, dx, qx);
-              qy = fma(s, dy, qy);
-              qz = fma(s, dz, qz);
             }
-            px[k] = qx;
-            py[k] = qy;
-            pz[k] = qz;
           }
         }
       }
