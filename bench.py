@@ -250,9 +250,18 @@ def bench_force(args, torch, nb):
         import oracle
         rows, ref_rows, el = cpu_baseline_rows(oracle, x, m, eps, args.cpu_budget)
         rate = len(rows) * (n - 1) / el / 1e9
-        res["cpu_baseline"] = {"value": round(rate, 4), "unit": UNIT, "cores": oracle.num_threads(),
+        cores = oracle.num_threads()
+        # the same oracle on one thread, on a smaller sample of the same rows
+        oracle.set_num_threads(1)
+        try:
+            rows1, _, el1 = cpu_baseline_rows(oracle, x, m, eps, max(1.0, args.cpu_budget / 5))
+        finally:
+            oracle.set_num_threads(cores)
+        res["cpu_baseline"] = {"value": round(rate, 4), "unit": UNIT, "cores": cores,
                                "kind": "oracle",
-                               "sample": "%d sampled rows x %d j (%.1f s), FP64 Neumaier C oracle" % (len(rows), n - 1, el)}
+                               "sample": "%d sampled rows x %d j (%.1f s), FP64 Neumaier C oracle" % (len(rows), n - 1, el),
+                               "value_1thread": round(len(rows1) * (n - 1) / el1 / 1e9, 4),
+                               "sample_1thread": "%d sampled rows x %d j (%.1f s) on one thread" % (len(rows1), n - 1, el1)}
         if "accuracy" in res:
             e32 = rel_err_rows(A32[:, rows], ref_rows)
             e64 = rel_err_rows(A64[:, rows], ref_rows)
@@ -352,6 +361,24 @@ def bench_ensemble(args, torch, nb):
         other = {"resident_kernel_path": {"ms_per_step": round(ms0 / args.steps, 5),
                                           "value": round(pairs * args.steps / (ms0 * 1e-3) / 1e9, 3)}}
     nb.nbody_set_config()
+    # the naive alternative: one nbody_step call per cluster (every cluster its own launches), FP64,
+    # on contiguous per-cluster copies made beforehand; a few steps, reported per step
+    naive_steps = 5
+    cl = []
+    for c in range(len(sizes)):
+        s, e = int(off[c]), int(off[c + 1])
+        cl.append((torch.tensor(x[:, s:e], device=dev), torch.tensor(v[:, s:e], device=dev),
+                   torch.empty((3, e - s), dtype=torch.float64, device=dev), tm[s:e].contiguous(), float(epsv[c])))
+    for cx, cv, ca, cm, ce in cl:
+        nb.nbody_step(cx, cv, ca, cm, w["dt"], 0, eps=ce, precision="fp64")
+
+    def naive():
+        for cx, cv, ca, cm, ce in cl:
+            nb.nbody_step(cx, cv, ca, cm, w["dt"], naive_steps, eps=ce, precision="fp64", acc_valid=True)
+    msn, _, _ = timed(naive, 1, 1, torch)
+    other["naive_per_cluster_fp64"] = {"ms_per_step": round(msn / naive_steps, 4),
+                                       "value": round(pairs * naive_steps / (msn * 1e-3) / 1e9, 3),
+                                       "note": "one nbody_step call per cluster, %d steps each" % naive_steps}
     ms = res[args.precision]
     return {"metric": METRIC, "value": round(pairs * args.steps / (ms * 1e-3) / 1e9, 3), "unit": UNIT,
             "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": round(ms / args.steps, 5),
@@ -446,6 +473,14 @@ def bench_kdk1k(args, torch, nb):
     t0 = time.perf_counter()
     rx, rv = oracle.kdk(x, v, m, dt, steps, eps=eps)
     cpu = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.kdk(x, v, m, dt, steps, eps=eps)
+        cpu1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
     pairs = float(n) * (n - 1) * (steps + 1)
     return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
@@ -454,8 +489,9 @@ def bench_kdk1k(args, torch, nb):
                        "precision": "fp64"},
             "max_abs_dx_vs_oracle": float(np.abs(gx - rx).max()),
             "max_abs_dv_vs_oracle": float(np.abs(gv - rv).max()),
-            "cpu_baseline": {"value": round(pairs / cpu / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(),
-                             "kind": "oracle", "sample": "the whole 10-step run (%.3f s)" % cpu}}
+            "cpu_baseline": {"value": round(pairs / cpu / 1e9, 4), "unit": UNIT, "cores": cores,
+                             "kind": "oracle", "sample": "the whole 10-step run (%.3f s)" % cpu,
+                             "value_1thread": round(pairs / cpu1 / 1e9, 4)}}
 
 
 def bench_jerk(args, torch, nb):

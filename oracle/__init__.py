@@ -61,6 +61,8 @@ def _load():
         lib.oracle_msd_loss.argtypes = [_I64, _D, _D]
         lib.oracle_msd_loss.restype = ctypes.c_double
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -78,6 +80,11 @@ def _p(a):
 
 def num_threads():
     return _load().oracle_num_threads()
+
+
+def set_num_threads(k):
+    """Threads of the following oracle calls (OpenMP); for timing only."""
+    _load().oracle_set_num_threads(int(k))
 
 
 def accel(x, m, G=1.0, eps=0.0):

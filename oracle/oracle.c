@@ -532,3 +532,12 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads used by the following oracle calls (timing of the single-thread baseline). */
+void oracle_set_num_threads(int k) {
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
