@@ -202,6 +202,7 @@ def bench_force(args, torch, nb):
                       "interactions_per_step": pairs, "state": "f64",
                       "flop_convention": "20 flops per ordered interaction"},
            "pct_fp32_peak": round(100 * c20_tflops / FP32_PEAK_TFLOPS, 2),
+           "ms_per_step_std": round(float(np.std(per)), 4),
            "wall_ms_timed_region": round(wall, 2)}
     en = energy_per_call(f32, args.steps, torch, GpuEnergy())
     if en:
