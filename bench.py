@@ -291,10 +291,29 @@ def bench_kdk64k(args, torch, nb):
         out[prec] = dict(ms=ms, dE=abs((e1[2] - e0[2]) / e0[2]), x=tx.cpu().numpy())
     pairs = float(n) * (n - 1)
     ms = out[args.precision]["ms"]
+
+    # force error of the pair arithmetic at t = 0 and at the final state of its own run (untimed):
+    # every row against the FP64 GPU path, sampled rows against the oracle
+    def force_error(xs):
+        txs = torch.tensor(xs, device=dev)
+        a = nb.nbody_accel(txs, tm, eps=eps, precision=args.precision).cpu().numpy()
+        a64 = nb.nbody_accel(txs, tm, eps=eps, precision="fp64").cpu().numpy()
+        e = rel_err_rows(a, a64)
+        r = {"vs_fp64_gpu_max": float(e.max()), "vs_fp64_gpu_p99": float(np.quantile(e, 0.99))}
+        if not args.no_cpu:
+            import oracle
+            rows = np.random.default_rng(11).choice(n, 512, replace=False)
+            ref = oracle.accel_rows(xs, m, rows, eps=eps)
+            r["vs_oracle_sampled_max"] = float(rel_err_rows(a[:, rows], ref).max())
+            r["sampled_rows"] = 512
+        return r
+
+    ferr = {"t0": force_error(x), "final": force_error(out[args.precision]["x"])}
     return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
             "steps": args.steps, "warmup": 0, "ms_per_step": round(ms, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "plummer64k_fp32c", "n": n, "eps": eps, "dt": dt, "precision": args.precision},
+            "force_error": ferr,
             "pct_fp32_peak": round(100 * pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift": {p: out[p]["dE"] for p in out},
             "fp64_path": {"value": round(pairs / (out["fp64"]["ms"] * 1e-3) / 1e9, 3),
@@ -436,7 +455,38 @@ def bench_grad(args, torch, nb):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         t2 -= t1b - t1  # the loss itself is neither forward nor adjoint
-        out[prec] = dict(fwd=t1 - t0, bwd=t2 - t1, loss=loss.item())
+        out[prec] = dict(fwd=t1 - t0, bwd=t2 - t1, loss=loss.item(),
+                         g={"x": tx.grad.cpu().numpy(), "v": tv.grad.cpu().numpy(), "m": tmg.grad.cpu().numpy()})
+
+    # gradient check (untimed): central differences of the FP64 GPU forward, h = 1e-6, on 64 seeded
+    # coordinates (24 position, 24 velocity, 16 mass), error |g - fd| / max(|fd|, 1e-3 max|g|)
+    tm = torch.tensor(m, device=dev)
+    tg_x, tg_v = torch.tensor(xp, device=dev), torch.tensor(vp, device=dev)
+    nb.nbody_step(tg_x, tg_v, torch.empty_like(tg_x), tm, dt, steps, eps=eps, precision="fp64")
+
+    def loss_at(xx, vv, mm):
+        px, pv, pm = (torch.tensor(q, device=dev) for q in (xx, vv, mm))
+        nb.nbody_step(px, pv, torch.empty_like(px), pm, dt, steps, eps=eps, precision="fp64")
+        return float((((px - tg_x) ** 2).sum() / n).item())
+
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    coords = [("x", int(rng.integers(3)), int(rng.integers(n))) for _ in range(24)]
+    coords += [("v", int(rng.integers(3)), int(rng.integers(n))) for _ in range(24)]
+    coords += [("m", 0, int(rng.integers(n))) for _ in range(16)]
+    worst = {prec: 0.0 for prec in out}
+    for kind, c, i in coords:
+        xx, vv, mm = x.copy(), v.copy(), m.copy()
+        arr = {"x": xx, "v": vv, "m": mm}[kind]
+        idx = i if kind == "m" else (c, i)
+        arr[idx] += h
+        lp = loss_at(xx, vv, mm)
+        arr[idx] -= 2 * h
+        lq = loss_at(xx, vv, mm)
+        fd = (lp - lq) / (2 * h)
+        for prec in out:
+            g = out[prec]["g"][kind]
+            worst[prec] = max(worst[prec], abs(g[idx] - fd) / max(abs(fd), 1e-3 * np.abs(g).max()))
     pairs = float(n) * (n - 1)
     p = out[args.precision]
     # forward: steps + 1 evaluations; backward: recompute (steps + nseg) + steps + 1 VJPs
@@ -447,6 +497,8 @@ def bench_grad(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "grad16k", "n": n, "eps": eps, "dt": dt, "every": every, "precision": args.precision},
             "fwd_s": p["fwd"], "bwd_s": p["bwd"], "bwd_over_fwd": p["bwd"] / p["fwd"], "loss": p["loss"],
+            "gradient_vs_central_differences": {"coords": len(coords), "h": h, "worst_rel": worst[args.precision],
+                                                "fp64_worst_rel": worst["fp64"], "tolerance": 1e-4},
             "fp64_path": {"fwd_s": out["fp64"]["fwd"], "bwd_s": out["fp64"]["bwd"], "loss": out["fp64"]["loss"]}}
 
 
