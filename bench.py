@@ -425,16 +425,20 @@ def bench_grad(args, torch, nb):
     # fresh device has been seen to run the first 100 ms several times slower) stay outside
     # the timing: one full forward + backward per precision, twice
     # (the loss's own torch kernels are loaded here too: their first use costs tens of ms)
+    # runs: (label, forward precision, adjoint precision); the third is the mixed form, an FP64
+    # trajectory differentiated by the FP32C adjoint sweep
+    runs = [(args.precision, args.precision, args.precision), ("fp64", "fp64", "fp64"),
+            ("fp64_fwd_%s_adjoint" % args.precision, "fp64", args.precision)]
     wtgt = torch.tensor(xp, device=dev)
     for _ in range(2):
-        for prec in (args.precision, "fp64"):
+        for _, prec, aprec in runs:
             wx = torch.tensor(x, device=dev, requires_grad=True)
             wv = torch.tensor(v, device=dev, requires_grad=True)
             wm = torch.tensor(m, device=dev, requires_grad=True)
-            wT, _ = nb.NBodyTrajectory.apply(wx, wv, wm, dt, steps, every, 1.0, eps, prec)
+            wT, _ = nb.NBodyTrajectory.apply(wx, wv, wm, dt, steps, every, 1.0, eps, prec, aprec)
             (((wT - wtgt) ** 2).sum() / n).backward()
     torch.cuda.synchronize()
-    for prec in (args.precision, "fp64"):
+    for label, prec, aprec in runs:
         tgt_x = torch.tensor(xp, device=dev)
         tgt_v = torch.tensor(vp, device=dev)
         tm = torch.tensor(m, device=dev)
@@ -445,7 +449,7 @@ def bench_grad(args, torch, nb):
         tmg = torch.tensor(m, device=dev, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xT, _ = nb.NBodyTrajectory.apply(tx, tv, tmg, dt, steps, every, 1.0, eps, prec)
+        xT, _ = nb.NBodyTrajectory.apply(tx, tv, tmg, dt, steps, every, 1.0, eps, prec, aprec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss = ((xT - tgt_x) ** 2).sum() / n
@@ -455,7 +459,7 @@ def bench_grad(args, torch, nb):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         t2 -= t1b - t1  # the loss itself is neither forward nor adjoint
-        out[prec] = dict(fwd=t1 - t0, bwd=t2 - t1, loss=loss.item(),
+        out[label] = dict(fwd=t1 - t0, bwd=t2 - t1, loss=loss.item(),
                          g={"x": tx.grad.cpu().numpy(), "v": tv.grad.cpu().numpy(), "m": tmg.grad.cpu().numpy()})
 
     # gradient check (untimed): central differences of the FP64 GPU forward, h = 1e-6, on 64 seeded
@@ -498,8 +502,11 @@ def bench_grad(args, torch, nb):
             "config": {"workload": "grad16k", "n": n, "eps": eps, "dt": dt, "every": every, "precision": args.precision},
             "fwd_s": p["fwd"], "bwd_s": p["bwd"], "bwd_over_fwd": p["bwd"] / p["fwd"], "loss": p["loss"],
             "gradient_vs_central_differences": {"coords": len(coords), "h": h, "worst_rel": worst[args.precision],
-                                                "fp64_worst_rel": worst["fp64"], "tolerance": 1e-4},
-            "fp64_path": {"fwd_s": out["fp64"]["fwd"], "bwd_s": out["fp64"]["bwd"], "loss": out["fp64"]["loss"]}}
+                                                "fp64_worst_rel": worst["fp64"], "mixed_worst_rel": worst[runs[2][0]],
+                                                "tolerance": 1e-4},
+            "fp64_path": {"fwd_s": out["fp64"]["fwd"], "bwd_s": out["fp64"]["bwd"], "loss": out["fp64"]["loss"]},
+            "mixed_path": {"forward": "fp64", "adjoint": args.precision, "fwd_s": out[runs[2][0]]["fwd"],
+                           "bwd_s": out[runs[2][0]]["bwd"], "loss": out[runs[2][0]]["loss"]}}
 
 
 def bench_kdk1k(args, torch, nb):

@@ -4,6 +4,12 @@ backward through the library's hand-written adjoint sweep (nbody_traj_grad).
 Only (x, v) every `every` steps are kept on the device; the backward pass
 recomputes each segment from its checkpoint with the same kernels as the
 forward (bitwise the same trajectory) and sweeps it in reverse.
+
+The sweep may run in another precision than the forward pass
+(`adjoint_precision`): with an FP64 forward and an FP32C sweep the gradient is
+that of the FP64 trajectory (each segment restarts from an FP64 checkpoint, so
+the FP32C recompute stays within its 20-odd steps of it), at the cost of the
+FP32C adjoint.
 """
 from __future__ import annotations
 
@@ -15,12 +21,13 @@ from . import _binding as B
 class NBodyTrajectory(torch.autograd.Function):
     """(x0, v0, m) -> (x_T, v_T) after `nsteps` KDK steps of size dt.
 
-    Usage: xT, vT = NBodyTrajectory.apply(x0, v0, m, dt, nsteps, every, G, eps, precision)
+    Usage: xT, vT = NBodyTrajectory.apply(x0, v0, m, dt, nsteps, every, G, eps, precision[, adjoint_precision])
     x0, v0: (3, N) float64 CUDA tensors; m: (N,).  Gradients flow to all three.
+    adjoint_precision (default: precision) is the pair arithmetic of the reverse sweep.
     """
 
     @staticmethod
-    def forward(ctx, x0, v0, m, dt, nsteps, every=20, G=1.0, eps=0.01, precision="fp32c"):
+    def forward(ctx, x0, v0, m, dt, nsteps, every=20, G=1.0, eps=0.01, precision="fp32c", adjoint_precision=None):
         nsteps, every = int(nsteps), int(every)
         if every < 1:
             raise ValueError("every must be >= 1")
@@ -40,7 +47,7 @@ class NBodyTrajectory(torch.autograd.Function):
             B.nbody_step(x, v, a, md, dt, steps, G=G, eps=eps, precision=precision, acc_valid=seg > 0)
             done += steps
         ctx.save_for_backward(ckx, ckv, md)
-        ctx.cfg = (float(dt), nsteps, every, float(G), float(eps), precision)
+        ctx.cfg = (float(dt), nsteps, every, float(G), float(eps), adjoint_precision or precision)
         return x, v
 
     @staticmethod
@@ -53,9 +60,9 @@ class NBodyTrajectory(torch.autograd.Function):
             gvT = torch.zeros_like(ckx[0])
         gx0, gv0, gm = B.nbody_traj_grad(ckx, ckv, every, nsteps, m, dt, gxT.contiguous(), gvT.contiguous(),
                                          G=G, eps=eps, precision=precision)
-        return gx0, gv0, gm, None, None, None, None, None, None
+        return gx0, gv0, gm, None, None, None, None, None, None, None
 
 
-def trajectory(x0, v0, m, dt, nsteps, every=20, G=1.0, eps=0.01, precision="fp32c"):
+def trajectory(x0, v0, m, dt, nsteps, every=20, G=1.0, eps=0.01, precision="fp32c", adjoint_precision=None):
     """Functional form of NBodyTrajectory.apply."""
-    return NBodyTrajectory.apply(x0, v0, m, dt, nsteps, every, G, eps, precision)
+    return NBodyTrajectory.apply(x0, v0, m, dt, nsteps, every, G, eps, precision, adjoint_precision)

@@ -165,6 +165,27 @@ def test_grad16k_against_finite_differences(nb):
     assert worst <= 1e-4
 
 
+def test_grad16k_mixed_precision_adjoint(nb):
+    """FP64 forward, FP32C reverse sweep: the gradient of the FP64 trajectory.
+    Each segment of the sweep restarts from an FP64 checkpoint, so it must
+    agree with the all-FP64 gradient to FP32C arithmetic (1e-5 of each
+    gradient's largest component), unlike the all-FP32C gradient, which
+    differentiates its own trajectory."""
+    w, x, v, m, xp, vp = _grad_setup()
+    n, eps, dt, steps, every = w["n"], w["eps"], w["dt"], w["steps"], w["every"]
+    tm = dev(m)
+    tg_x, tg_v = dev(xp), dev(vp)
+    nb.nbody_step(tg_x, tg_v, torch.empty_like(tg_x), tm, dt, steps, eps=eps, precision="fp64")
+    grads = {}
+    for aprec in ("fp64", "fp32c"):
+        tx, tv, tmg = dev(x).requires_grad_(), dev(v).requires_grad_(), dev(m).requires_grad_()
+        xT, _ = nb.NBodyTrajectory.apply(tx, tv, tmg, dt, steps, every, 1.0, eps, "fp64", aprec)
+        (((xT - tg_x) ** 2).sum() / n).backward()
+        grads[aprec] = [tx.grad.cpu().numpy(), tv.grad.cpu().numpy(), tmg.grad.cpu().numpy()]
+    for g64, gmix in zip(grads["fp64"], grads["fp32c"]):
+        assert np.abs(gmix - g64).max() <= 1e-5 * np.abs(g64).max()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32c", 1e-4)])
 def test_grad16k_against_oracle_short(nb, oracle_mod, prec, tol):
     """Full N = 16384 system, 10 steps with checkpoints every 4, against the
