@@ -146,6 +146,10 @@ int nbody_accel_vjp(int64_t n, const double* x, const double* m, const double* w
  * as nbody_step (bitwise the same trajectory), then swept in reverse; the two
  * Jacobian products at each interior position share one cotangent and are
  * merged into one VJP evaluation per step.  Inputs are not modified.
+ * The checkpoints may come from a forward pass in another precision than
+ * p->precision: with FP64 checkpoints and an FP32C sweep, each segment's
+ * FP32C recompute restarts from an FP64 state, and the result is the
+ * gradient of the FP64 trajectory to FP32C accuracy.
  * Errors: as nbody_step, plus every < 1. */
 int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64_t every,
                     int64_t nsteps, const double* m, double dt, const double* gxT,
