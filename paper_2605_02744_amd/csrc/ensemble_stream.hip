@@ -303,8 +303,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// FP64 pairs need more than the 64 VGPRs of 8 waves per SIMD; they run at 4
+// (one workgroup per CU) without spilling.
+template <int MODE> constexpr int wave_kernel_waves() { return MODE == kFP64 ? 4 : kSWaves; }
+
 template <int MODE, bool EXCL>
-__global__ __launch_bounds__(kSBlock, kSWaves) void ens_wave_kernel(
+__global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wave_kernel(
     const int64_t* __restrict__ off, const double* __restrict__ epsv, const int* __restrict__ nparts,
     const SItem* __restrict__ items, const int* __restrict__ wg_off, const int* __restrict__ wg_list,
     const int* __restrict__ ws_off, const int2* __restrict__ ws_sys, double* __restrict__ x,
