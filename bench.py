@@ -337,7 +337,7 @@ def bench_ensemble(args, torch, nb):
         nb.nbody_set_config()
         tx0, tv0 = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
         for prec in (args.precision, "fp64"):
-            tuned[prec] = nb.nbody_tune_batched(off, epsv, tx0, tv0, tm, w["dt"], 20, precision=prec)
+            tuned[prec] = nb.nbody_tune_batched(off, epsv, tx0, tv0, tm, w["dt"], 50, precision=prec)
         mode = tuned[args.precision]["bsplit"]
     else:
         mode = args.bsplit if args.bsplit is not None else 1

@@ -255,10 +255,11 @@ typedef struct nbody_config {
                       and the affected systems then end NaN. */
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
-  int32_t bitem;   /* streamed batched kernel (bsplit = 2): most particles per item of
-                      a system above 256 particles: 0 = automatic (1024), 256, 512 or
-                      1024; or 64: items of 64 particles of any system, each
-                      evaluated by one wave against the system's whole j-range */
+  int32_t bitem;   /* streamed batched kernel (bsplit = 2): 64 (or 0 = automatic):
+                      items of 64 particles of any system, each evaluated by one
+                      wave against the system's whole j-range; or 256, 512, 1024:
+                      most particles per item of a system above 256 particles,
+                      evaluated by a whole workgroup */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros
@@ -278,7 +279,8 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
 
 /* Autotuner of the batched kernels for one ensemble layout (off, eps as in
  * nbody_step_batched, precision and flags from p): times every candidate
- * configuration for nsteps (>= 1) KDK steps from the state (x, v, m), on the
+ * configuration for nsteps (>= 1) KDK steps, after an untimed run of nsteps
+ * steps, from the state (x, v, m), on the
  * library's own copies (the caller's arrays are only read), and keeps the
  * fastest whose state stays finite.  Candidates: the resident kernel with 1, 2
  * or 4 i-particles per lane per pass; with allow_cooperative != 0 also the

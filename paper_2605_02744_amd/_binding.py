@@ -322,8 +322,8 @@ def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0):
     workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
     items of <= 1024 particles), default 0: one workgroup per system; bpass sets
     how many of a lane's i-particles the ensemble kernel evaluates per pass
-    (1, 2, 4); bitem the streamed kernel's most particles per item (256, 512,
-    1024, or 64: one wave per item)."""
+    (1, 2, 4); bitem the streamed kernel's item size (64, the automatic
+    choice: one wave per item; or 256, 512, 1024: one workgroup per item)."""
     c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem))
     _check(load().nbody_set_config(ctypes.byref(c)))
 

@@ -434,6 +434,10 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
     }
     int st = run_batched(ncl, off, eps, sx, sv, sa, m, dt, 0, p->G, p->precision, excl, false, cand[k], nullptr);
     if (st) { cleanup(); return st; }
+    // an untimed run of the same length first: a short timed run straight after the copies
+    // above mostly measures the GPU coming back to its clock, not the configuration
+    st = run_batched(ncl, off, eps, sx, sv, sa, m, dt, nsteps, p->G, p->precision, excl, true, cand[k], nullptr);
+    if (st) { cleanup(); return st; }
     (void)hipEventRecord(e0, nullptr);
     st = run_batched(ncl, off, eps, sx, sv, sa, m, dt, nsteps, p->G, p->precision, excl, true, cand[k], nullptr);
     if (st) { cleanup(); return st; }

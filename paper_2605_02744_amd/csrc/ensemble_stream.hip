@@ -796,6 +796,9 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
                        bool acc_valid, int bitem, hipStream_t s) {
   const int device = current_device();
+  // automatic item size: items of 64 particles evaluated by one wave each (faster than
+  // items of 1024 on every measured layout but one, 64 x 4096, where it is 2 % slower)
+  if (bitem == 0) bitem = 64;
   std::lock_guard<std::mutex> lk(g_splan_mu);
   SPlan* p = find_splan(ncl, off, eps, precision, device, bitem);
   if (!p) {

@@ -88,7 +88,7 @@ def test_plummer64k_force_and_drift(nb, oracle_mod):
     assert np.quantile(row_err(b32, a64), 0.999) <= 1e-5
 
 
-@pytest.mark.parametrize("mode,bitem", [(0, 0), (2, 0), (2, 64)])
+@pytest.mark.parametrize("mode,bitem", [(0, 0), (2, 1024), (2, 64)])
 def test_ensemble512_sampled_clusters(nb, oracle_mod, mode, bitem):
     """The batched kernels (mode 0: systems resident in LDS; mode 2: streamed
     items of up to 1024 particles, or of 64 evaluated by one wave each)
