@@ -341,7 +341,8 @@ def bench_ensemble(args, torch, nb):
         mode = tuned[args.precision]["bsplit"]
     else:
         mode = args.bsplit if args.bsplit is not None else 1
-        nb.nbody_set_config(bsplit=mode, bpass=args.bpass, bitem=args.bitem)
+        # bsplit 0 alone would read as "automatic": a pass width forces the resident kernel
+        nb.nbody_set_config(bsplit=mode, bpass=args.bpass or (4 if mode == 0 else 0), bitem=args.bitem)
     res, drift = {}, {}
 
     def energies(tx, tv):
@@ -680,7 +681,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU baseline")
     ap.add_argument("--split", action="store_true", help="ensemble: split the largest systems over workgroups")
-    ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2],
+    ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2, 3],
                     help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items")
     ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
     ap.add_argument("--tune-cache", default=None, help="with --tune: JSON-lines file the tuner appends its choice to")

@@ -243,16 +243,21 @@ int nbody_step_hermite6(int64_t n, double* x, double* v, double* a, double* jk, 
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
   int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
-  int32_t bsplit;  /* batched kernel: 0 = one workgroup per system, its records
-                      resident in LDS (default); 1 = as 0, but systems costlier than
+  int32_t bsplit;  /* batched kernel, used when any of bsplit, bpass, bitem is
+                      non-zero (all zero: the tuned choice for the layout, else
+                      mode 3): 0 = one workgroup per system, its records
+                      resident in LDS (force it with bpass); 1 = as 0, but systems costlier than
                       the per-CU average split across up to 4 workgroups that
                       exchange positions every step; 2 = streamed: every system cut
-                      into items of <= 128 particles spread over up to 8 resident
-                      256-lane workgroups per CU, records streamed through LDS tiles,
-                      items of a system synchronised every step.  Modes 1 and 2
-                      need every workgroup of the launch resident at once: with
-                      another kernel occupying the GPU a bounded wait can expire,
-                      and the affected systems then end NaN. */
+                      into items (see bitem) evaluated by 1024-lane workgroups
+                      resident for all steps, records streamed through LDS, the
+                      items of a system synchronised every step; 3 = the items of
+                      64 particles of mode 2, with two launches per step (kicks and
+                      drift, then the forces) instead of one persistent launch.
+                      Modes 1 and 2 need every workgroup of the launch resident at
+                      once: with another kernel occupying the GPU a bounded wait can
+                      expire, and the affected systems then end NaN.  Modes 0 and 3
+                      have no such requirement. */
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
   int32_t bitem;   /* streamed batched kernel (bsplit = 2): 64 (or 0 = automatic):
@@ -283,7 +288,8 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * steps, from the state (x, v, m), on the
  * library's own copies (the caller's arrays are only read), and keeps the
  * fastest whose state stays finite.  Candidates: the resident kernel with 1, 2
- * or 4 i-particles per lane per pass; with allow_cooperative != 0 also the
+ * or 4 i-particles per lane per pass and the per-step items of 64 (mode 3);
+ * with allow_cooperative != 0 also the
  * split mode and the streamed kernel with items of 64, 256, 512 or 1024 particles
  * (the modes that need every workgroup of a launch resident at once).  The
  * choice is recorded for this (device, precision, layout): later

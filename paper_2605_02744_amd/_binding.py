@@ -320,7 +320,8 @@ def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0):
     """Forces a tile configuration on this thread (all zeros = automatic);
     bsplit=1 lets the ensemble kernel split its largest systems over up to 4
     workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
-    items of <= 1024 particles), default 0: one workgroup per system; bpass sets
+    items, one persistent launch), bsplit=3 its items of 64 particles with two
+    launches per step, default 0: one workgroup per system; bpass sets
     how many of a lane's i-particles the ensemble kernel evaluates per pass
     (1, 2, 4); bitem the streamed kernel's item size (64, the automatic
     choice: one wave per item; or 256, 512, 1024: one workgroup per item)."""

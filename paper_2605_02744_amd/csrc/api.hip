@@ -260,7 +260,8 @@ std::mutex g_tb_mu;
 std::vector<TunedBatch> g_tuned_batch;
 
 // The thread's forced configuration if it sets any batched field, else the
-// tuned one for this layout, else the resident kernel with its defaults.
+// tuned one for this layout, else the per-step wave items (mode 3: the fastest
+// of the modes that need no co-resident workgroups on every measured layout).
 BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
   const nbody_config& t = t_cfg;
   BatchConfig bc;
@@ -275,6 +276,7 @@ BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps,
     if (e.device == device && e.precision == precision && (int)e.eps.size() == ncl &&
         std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps))
       return e.bc;
+  bc.mode = 3;
   return bc;
 }
 
@@ -405,6 +407,7 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   const int dev = current_device();
   std::vector<BatchConfig> cand;
   for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0});
+  cand.push_back(BatchConfig{3, 0, 64});
   if (allow_cooperative) {
     cand.push_back(BatchConfig{1, 0, 0});
     for (int item : {64, 256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});
@@ -576,7 +579,7 @@ int nbody_set_config(const nbody_config* cfg) {
   if (cfg->ipl != 0 && cfg->ipl != 1 && cfg->ipl != 2 && cfg->ipl != 4)
     return set_error(NBODY_EINVAL, "ipl must be 0, 1, 2 or 4");
   if (cfg->split < 0 || cfg->split > 1024) return set_error(NBODY_EINVAL, "split must be in 0..1024");
-  if (cfg->bsplit < 0 || cfg->bsplit > 2) return set_error(NBODY_EINVAL, "bsplit must be 0, 1 or 2");
+  if (cfg->bsplit < 0 || cfg->bsplit > 3) return set_error(NBODY_EINVAL, "bsplit must be 0, 1, 2 or 3");
   if (cfg->bpass != 0 && cfg->bpass != 1 && cfg->bpass != 2 && cfg->bpass != 4)
     return set_error(NBODY_EINVAL, "bpass must be 0, 1, 2 or 4");
   if (cfg->bitem != 0 && cfg->bitem != 64 && cfg->bitem != 256 && cfg->bitem != 512 && cfg->bitem != 1024)

@@ -504,6 +504,156 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wave_k
   }
 }
 
+// ----------------------------------------------------- wave items, per step
+// The same items without the persistent loop: every step is two launches,
+// ens_publish_kernel (the kicks and the drift of every particle, and its pair
+// record) and ens_waveforce_kernel (each workgroup's waves take its items from
+// an LDS counter and write the accelerations).  The kernel boundary is the
+// step's synchronisation, so no workgroup waits for another and nothing needs
+// every workgroup resident at once; the price is two launches per step.
+
+// kicks = 0: publish only; 1: v += h a, x += dt v; 2: v += h a twice (closing
+// half-kick of the previous step, opening half-kick of this one, rounded
+// separately), x += dt v.  Then the pair record of the new position.
+template <int MODE>
+__global__ void ens_publish_kernel(int64_t total, double* __restrict__ x, double* __restrict__ v,
+                                   const double* __restrict__ a, const double* __restrict__ m,
+                                   JRec<MODE>* __restrict__ xrec, double h, double dt, int kicks) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    double xn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t e = d * total + i;
+      if (kicks > 0) {
+        const double ae = a[e];
+        double ve = fma(h, ae, v[e]);
+        if (kicks > 1) ve = fma(h, ae, ve);
+        v[e] = ve;
+        xn[d] = fma(dt, ve, x[e]);
+        x[e] = xn[d];
+      } else {
+        xn[d] = x[e];
+      }
+    }
+    xrec[i] = JRec<MODE>::make(xn[0], xn[1], xn[2], m[i]);
+  }
+}
+
+__global__ void ens_kick_kernel(int64_t total, double* __restrict__ v, const double* __restrict__ a, double h) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * total; e += (int64_t)gridDim.x * blockDim.x)
+    v[e] = fma(h, a[e], v[e]);
+}
+
+template <int MODE, bool EXCL>
+__global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_waveforce_kernel(
+    const int64_t* __restrict__ off, const double* __restrict__ epsv, const SItem* __restrict__ items,
+    const int* __restrict__ wg_off, const int* __restrict__ wg_list, const JRec<MODE>* __restrict__ xrec,
+    double* __restrict__ a, int64_t total, double G) {
+  using R = Real<MODE>;
+  constexpr bool kNear = MODE == kFP32C;
+  __shared__ JRec<MODE> slot[kWWaves][64];
+  __shared__ int next_item;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, lane = t & 63;
+  const int q0 = wg_off[blockIdx.x], q1 = wg_off[blockIdx.x + 1];
+  JRec<MODE>* buf = slot[wv];
+  if (t == 0) next_item = 0;
+  __syncthreads();
+  for (;;) {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(&next_item, 1);
+    k = __builtin_amdgcn_readfirstlane(k);
+    if (k >= q1 - q0) break;
+    const SItem it = items[wg_list[q0 + k]];
+    const int64_t o = off[it.sys];
+    const int nc = (int)(off[it.sys + 1] - o);
+    const JRec<MODE>* src = xrec + o;
+    const int ii = it.i0 + (lane < it.ni ? lane : it.ni - 1);
+    const int iself = lane < it.ni ? ii : -1;
+    const double eps = epsv[it.sys];
+    const R e2 = (R)(eps * eps);
+    IPos<MODE> pi;
+    pi.from(src[ii]);
+    R rc2 = R(0);
+    if constexpr (kNear) rc2 = near_rc2(pi.hx, pi.hy, pi.hz, eps, nc);
+    R hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
+    JRec<MODE> nxt = lane < nc ? src[lane] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+#pragma unroll 1
+    for (int jt = 0; jt < nc; jt += 64) {
+      wave_lds_sync();
+      buf[lane] = nxt;
+      wave_lds_sync();
+      if (jt + 64 < nc) {
+        const int jn = jt + 64 + lane;
+        nxt = jn < nc ? src[jn] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
+      }
+      auto block = [&](auto own_tag, auto full_tag, int cnt) {
+        constexpr bool kOwn = decltype(own_tag)::value;
+        constexpr bool kFull = decltype(full_tag)::value;
+        const int jend = kFull ? 64 : cnt;
+        R px = 0, py = 0, pz = 0, r2min = R(3.0e38f);
+#pragma unroll 16
+        for (int jj = 0; jj < jend; ++jj) {
+          const JRec<MODE> rj = buf[jj];
+          R dx, dy, dz;
+          if constexpr (kNear) disp_hi(rj, pi, dx, dy, dz);
+          else disp(rj, pi, dx, dy, dz);
+          const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          const R ri = rsq(r2);
+          R sc = (jmass(rj) * ri) * (ri * ri);
+          if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+          px = fma(sc, dx, px);
+          py = fma(sc, dy, py);
+          pz = fma(sc, dz, pz);
+          if constexpr (kNear) r2min = fminf(r2min, (kOwn && jt + jj == ii) ? R(3.0e38f) : r2);
+        }
+        if constexpr (kNear) {
+          if (r2min < rc2) {
+            // rare: redo this block with float-float displacements for the close pairs
+            R qx = 0, qy = 0, qz = 0;
+            for (int jj = 0; jj < jend; ++jj) {
+              const JRec<MODE> rj = buf[jj];
+              R dx, dy, dz;
+              disp_hi(rj, pi, dx, dy, dz);
+              R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 < rc2) {
+                disp(rj, pi, dx, dy, dz);
+                r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              }
+              const R ri = rsq(r2);
+              R sc = (jmass(rj) * ri) * (ri * ri);
+              if constexpr (EXCL) sc = (jt + jj == iself) ? R(0) : sc;
+              qx = fma(sc, dx, qx);
+              qy = fma(sc, dy, qy);
+              qz = fma(sc, dz, qz);
+            }
+            px = qx;
+            py = qy;
+            pz = qz;
+          }
+        }
+        fold(hx, lx, px);
+        fold(hy, ly, py);
+        fold(hz, lz, pz);
+      };
+      const int cnt = nc - jt;
+      if (cnt >= 64) {
+        if (jt == it.i0) block(std::true_type{}, std::true_type{}, 64);
+        else block(std::false_type{}, std::true_type{}, 64);
+      } else {
+        if (jt == it.i0) block(std::true_type{}, std::false_type{}, cnt);
+        else block(std::false_type{}, std::false_type{}, cnt);
+      }
+    }
+    if (lane < it.ni) {
+      const int64_t i = o + ii;
+      a[i] = G * ((double)hx + (double)lx);
+      a[total + i] = G * ((double)hy + (double)ly);
+      a[2 * total + i] = G * ((double)hz + (double)lz);
+    }
+  }
+}
+
 __global__ void zero_counters_kernel(int* c, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0;
 }
@@ -790,15 +940,50 @@ int launch_splan(const SPlan* p, double* x, double* v, double* a, const double* 
   return NBODY_OK;
 }
 
+template <int MODE>
+int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
+                  double G, bool acc_valid, bool excl, hipStream_t s) {
+  if (p->total == 0 || (nsteps == 0 && acc_valid)) return NBODY_OK;
+  auto* rec = static_cast<JRec<MODE>*>(p->d_xrec);
+  const double h = 0.5 * dt;
+  const unsigned ew = (unsigned)std::min<int64_t>((p->total + 255) / 256, 4096);
+  auto force = [&]() -> int {
+    if (excl)
+      ens_waveforce_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
+                                                                  p->d_wg_list, rec, a, p->total, G);
+    else
+      ens_waveforce_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
+                                                                   p->d_wg_list, rec, a, p->total, G);
+    NB_LAUNCH_CHECK("ens_waveforce_kernel");
+    return NBODY_OK;
+  };
+  int st;
+  if (!acc_valid) {
+    ens_publish_kernel<MODE><<<ew, 256, 0, s>>>(p->total, x, v, a, m, rec, h, dt, 0);
+    NB_LAUNCH_CHECK("ens_publish_kernel");
+    if ((st = force())) return st;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    ens_publish_kernel<MODE><<<ew, 256, 0, s>>>(p->total, x, v, a, m, rec, h, dt, k == 0 ? 1 : 2);
+    NB_LAUNCH_CHECK("ens_publish_kernel");
+    if ((st = force())) return st;
+  }
+  if (nsteps > 0) {
+    ens_kick_kernel<<<ew, 256, 0, s>>>(p->total, v, a, h);
+    NB_LAUNCH_CHECK("ens_kick_kernel");
+  }
+  return NBODY_OK;
+}
+
 }  // namespace
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                       bool acc_valid, int bitem, hipStream_t s) {
+                       bool acc_valid, int bitem, bool per_step, hipStream_t s) {
   const int device = current_device();
   // automatic item size: items of 64 particles evaluated by one wave each (faster than
   // items of 1024 on every measured layout but one, 64 x 4096, where it is 2 % slower)
-  if (bitem == 0) bitem = 64;
+  if (bitem == 0 || per_step) bitem = 64;
   std::lock_guard<std::mutex> lk(g_splan_mu);
   SPlan* p = find_splan(ncl, off, eps, precision, device, bitem);
   if (!p) {
@@ -819,6 +1004,11 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
     }
     if (st) return st;
     g_splans.push_back(p);
+  }
+  if (per_step) {
+    if (precision == NBODY_FP64) return launch_wsteps<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+    if (precision == NBODY_FP32C) return launch_wsteps<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+    return launch_wsteps<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
   }
   if (precision == NBODY_FP64) return launch_splan<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
   if (precision == NBODY_FP32C) return launch_splan<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);

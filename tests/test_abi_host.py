@@ -140,7 +140,7 @@ def test_set_config_validation(lib):
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(split=5000)
     with pytest.raises(nb.NBodyError):
-        nb.nbody_set_config(bsplit=3)
+        nb.nbody_set_config(bsplit=4)
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(bpass=3)
     with pytest.raises(nb.NBodyError):

@@ -88,17 +88,18 @@ def test_plummer64k_force_and_drift(nb, oracle_mod):
     assert np.quantile(row_err(b32, a64), 0.999) <= 1e-5
 
 
-@pytest.mark.parametrize("mode,bitem", [(0, 0), (2, 1024), (2, 64)])
+@pytest.mark.parametrize("mode,bitem", [(0, 0), (2, 1024), (2, 64), (3, 0)])
 def test_ensemble512_sampled_clusters(nb, oracle_mod, mode, bitem):
     """The batched kernels (mode 0: systems resident in LDS; mode 2: streamed
-    items of up to 1024 particles, or of 64 evaluated by one wave each)
-    against the oracle's own KDK on sampled clusters."""
+    items of up to 1024 particles, or of 64 evaluated by one wave each; mode 3:
+    the items of 64 with two launches per step, the default) against the
+    oracle's own KDK on sampled clusters."""
     w = ics.WORKLOADS["ensemble512"]
     off, epsv, x, v, m = ics.ensemble(w["ncl"], seed=w["seed"], nmin=w["nmin"], nmax=w["nmax"])
     steps, dt = 8, w["dt"]
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
-    nb.nbody_set_config(bsplit=mode, bitem=bitem)
+    nb.nbody_set_config(bsplit=mode, bitem=bitem, bpass=4 if mode == 0 else 0)  # bpass forces the resident kernel
     try:
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, dt, steps, precision="fp32c", check_finite=True)
     finally:

@@ -317,7 +317,7 @@ def test_batched_split_and_unsplit_agree(nb, prec):
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=21, sizes=sizes)
     out = []
     for bsplit in (1, 0):
-        nb.nbody_set_config(bsplit=bsplit)
+        nb.nbody_set_config(bsplit=bsplit, bpass=4 if bsplit == 0 else 0)  # bpass forces the resident kernel
         try:
             tx, tv, tm = dev(x), dev(v), dev(m)
             ta = torch.empty_like(tx)
@@ -336,7 +336,7 @@ def test_batched_pass_widths_agree(nb, prec):
     sizes = [4096, 1500, 333, 64]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=22, sizes=sizes)
     out = []
-    for bpass in (0, 1, 2):
+    for bpass in (4, 1, 2):
         nb.nbody_set_config(bpass=bpass)
         try:
             tx, tv, tm = dev(x), dev(v), dev(m)
@@ -353,17 +353,17 @@ def test_batched_pass_widths_agree(nb, prec):
             assert np.abs(out[0][1] - out[k][1]).max() <= 1e-8
 
 
-def _stream(nb, fn, bitem=0):
-    nb.nbody_set_config(bsplit=2, bitem=bitem)
+def _stream(nb, fn, bitem=0, mode=2):
+    nb.nbody_set_config(bsplit=mode, bitem=bitem)
     try:
         return fn()
     finally:
         nb.nbody_set_config()
 
 
-@pytest.mark.parametrize("bitem", [1024, 64])
+@pytest.mark.parametrize("mode,bitem", [(2, 1024), (2, 64), (3, 0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_stream_batched_matches_oracle(nb, oracle_mod, prec, bitem):
+def test_stream_batched_matches_oracle(nb, oracle_mod, prec, mode, bitem):
     """Streamed ensemble kernels against the oracle's KDK: items of <= 1024
     particles (one item per system here), or of 64 particles evaluated by one
     wave each (several items per system above 64; the automatic choice)."""
@@ -373,7 +373,7 @@ def test_stream_batched_matches_oracle(nb, oracle_mod, prec, bitem):
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
     _stream(nb, lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, dt, steps, precision=prec,
-                                              check_finite=True), bitem)
+                                              check_finite=True), bitem, mode)
     for c in range(len(sizes)):
         s, e = off[c], off[c + 1]
         rx, rv = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], dt, steps, eps=float(epsv[c]))
@@ -394,7 +394,7 @@ def test_stream_batched_agrees_with_resident_kernel(nb, prec, bitem):
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=24, sizes=sizes)
     out = []
     for mode in (0, 2):
-        nb.nbody_set_config(bsplit=mode, bitem=bitem if mode == 2 else 0)
+        nb.nbody_set_config(bsplit=mode, bitem=bitem if mode == 2 else 0, bpass=4 if mode == 0 else 0)
         try:
             tx, tv, tm = dev(x), dev(v), dev(m)
             ta = torch.empty_like(tx)
@@ -406,8 +406,28 @@ def test_stream_batched_agrees_with_resident_kernel(nb, prec, bitem):
     assert np.abs(out[0][1] - out[1][1]).max() <= 1e-8
 
 
-@pytest.mark.parametrize("bitem", [1024, 64])
-def test_stream_batched_resumable_and_eps0(nb, oracle_mod, bitem):
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_per_step_wave_items_equal_persistent(nb, prec):
+    """Mode 3 (two launches per step) runs the same items and arithmetic as
+    mode 2 with items of 64 (one persistent launch): bitwise the same state."""
+    sizes = [4096, 3000, 2048, 700, 257, 64, 1]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=28, sizes=sizes)
+    out = []
+    for mode, bitem in ((2, 64), (3, 0)):
+        nb.nbody_set_config(bsplit=mode, bitem=bitem)
+        try:
+            tx, tv, tm = dev(x), dev(v), dev(m)
+            ta = torch.empty_like(tx)
+            nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 5, precision=prec)
+        finally:
+            nb.nbody_set_config()
+        out.append((tx.cpu(), tv.cpu(), ta.cpu()))
+    for p_, q_ in zip(out[0], out[1]):
+        assert torch.equal(p_, q_)
+
+
+@pytest.mark.parametrize("mode,bitem", [(2, 1024), (2, 64), (3, 0)])
+def test_stream_batched_resumable_and_eps0(nb, oracle_mod, mode, bitem):
     sizes = [300, 77, 1025]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=25, sizes=sizes)
     res = []
@@ -417,7 +437,7 @@ def test_stream_batched_resumable_and_eps0(nb, oracle_mod, bitem):
         valid = False
         for c in chunks:
             _stream(nb, lambda: nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 256, c, precision="fp32c",
-                                                      acc_valid=valid), bitem)
+                                                      acc_valid=valid), bitem, mode)
             valid = True
         res.append((tx.cpu(), tv.cpu()))
     for r in res[1:]:
@@ -427,20 +447,20 @@ def test_stream_batched_resumable_and_eps0(nb, oracle_mod, bitem):
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
     _stream(nb, lambda: nb.nbody_step_batched(off, eps0, tx, tv, ta, tm, 1.0 / 1024, 2, precision="fp64",
-                                              exclude_self=True, check_finite=True), bitem)
+                                              exclude_self=True, check_finite=True), bitem, mode)
     for c in range(len(sizes)):
         s, e = off[c], off[c + 1]
         rx, _ = oracle_mod.kdk(x[:, s:e], v[:, s:e], m[s:e], 1.0 / 1024, 2, eps=0.0)
         assert np.abs(tx.cpu().numpy()[:, s:e] - rx).max() <= 1e-11
 
 
-@pytest.mark.parametrize("bitem", [1024, 64])
-def test_stream_batched_graph_capture(nb, bitem):
+@pytest.mark.parametrize("mode,bitem", [(2, 1024), (2, 64), (3, 0)])
+def test_stream_batched_graph_capture(nb, mode, bitem):
     sizes = [64, 257, 1000]
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=26, sizes=sizes)
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
-    nb.nbody_set_config(bsplit=2, bitem=bitem)
+    nb.nbody_set_config(bsplit=mode, bitem=bitem)
     try:
         ex, ev, ea = tx.clone(), tv.clone(), ta.clone()
         nb.nbody_step_batched(off, epsv, ex, ev, ea, tm, 1.0 / 512, 2, precision="fp32c")
@@ -472,7 +492,7 @@ def test_tune_batched_records_and_applies_choice(nb):
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=27, sizes=sizes)
     tx, tv, tm = dev(x), dev(v), dev(m)
     best = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 4, precision="fp32c")
-    assert best["bsplit"] in (0, 1, 2) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 64, 256, 512, 1024)
+    assert best["bsplit"] in (0, 1, 2, 3) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 64, 256, 512, 1024)
     assert torch.equal(tx, dev(x)) and torch.equal(tv, dev(v))
     out = []
     for forced in (False, True):
@@ -486,9 +506,9 @@ def test_tune_batched_records_and_applies_choice(nb):
             nb.nbody_set_config()
         out.append((gx.cpu(), gv.cpu()))
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
-    # the resident-only search returns a resident configuration
+    # the search without co-residency returns a configuration that needs none (resident kernel or per-step items)
     best0 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp64", allow_cooperative=False)
-    assert best0["bsplit"] == 0
+    assert best0["bsplit"] in (0, 3)
 
 
 def test_batched_matches_oracle_fp64(nb, oracle_mod):
