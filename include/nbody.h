@@ -291,13 +291,15 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * or 4 i-particles per lane per pass and the per-step items of 64 (mode 3);
  * with allow_cooperative != 0 also the
  * split mode and the streamed kernel with items of 64, 256, 512 or 1024 particles
- * (the modes that need every workgroup of a launch resident at once).  The
+ * (the modes that need every workgroup of a launch resident at once). allow_cooperative = 2 keeps
+ * to the single-launch modes 0, 1 and 2 (all steps in one persistent launch).  The
  * choice is recorded for this (device, precision, layout): later
  * nbody_step_batched calls on the same layout use it whenever the thread has
  * not forced a batched configuration with nbody_set_config.  best (may be
  * NULL) receives it as bsplit/bpass/bitem.  Synchronous; allocates and frees
  * its own buffers and builds (and caches) one plan per candidate.  Errors: as
- * nbody_step_batched; NBODY_ENONFINITE if no candidate stayed finite. */
+ * nbody_step_batched; NBODY_EINVAL for allow_cooperative outside 0..2;
+ * NBODY_ENONFINITE if no candidate stayed finite. */
 int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const double* x, const double* v,
                        const double* m, double dt, int64_t nsteps, int32_t allow_cooperative,
                        const nbody_params* p, nbody_config* best);

@@ -230,7 +230,9 @@ def nbody_tune_batched(off, eps, x, v, m, dt, nsteps, *, G=1.0, precision="fp32c
                        allow_cooperative=True):
     """Times the batched kernels' configurations on copies of (x, v) for this
     layout, records the fastest for later nbody_step_batched calls, and
-    returns it as {"bsplit", "bpass", "bitem"}."""
+    returns it as {"bsplit", "bpass", "bitem"}.  allow_cooperative: False keeps
+    to the modes that need no co-resident workgroups (0, 3), True allows all,
+    "persistent" keeps to the single-launch modes (0, 1, 2)."""
     import numpy as np
     lib = load()
     off_h = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
@@ -246,7 +248,9 @@ def nbody_tune_batched(off, eps, x, v, m, dt, nsteps, *, G=1.0, precision="fp32c
         _check(lib.nbody_tune_batched(ncl, off_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                       eps_h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       _ptr(x, "x", (3, total)), _ptr(v, "v", (3, total)), _ptr(m, "m", (total,)),
-                                      float(dt), int(nsteps), 1 if allow_cooperative else 0, ctypes.byref(p),
+                                      float(dt), int(nsteps),
+                                      2 if allow_cooperative == "persistent" else (1 if allow_cooperative else 0),
+                                      ctypes.byref(p),
                                       ctypes.byref(best)))
     return {"bsplit": best.bsplit, "bpass": best.bpass, "bitem": best.bitem}
 

@@ -399,6 +399,8 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   int64_t total = 0;
   NB_TRY(check_batched_host(ncl, off, eps, dt, nsteps, p, &total));
   if (nsteps < 1) return set_error(NBODY_EINVAL, "tune_batched: nsteps must be >= 1");
+  if (allow_cooperative < 0 || allow_cooperative > 2)
+    return set_error(NBODY_EINVAL, "tune_batched: allow_cooperative must be 0, 1 or 2");
   if (total == 0) return set_error(NBODY_EINVAL, "tune_batched: the ensemble is empty");
   const size_t b3 = sizeof(double) * 3 * (size_t)total, b1 = sizeof(double) * (size_t)total;
   NB_TRY(check_dev_range(x, b3, "x"));
@@ -407,7 +409,7 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   const int dev = current_device();
   std::vector<BatchConfig> cand;
   for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0});
-  cand.push_back(BatchConfig{3, 0, 64});
+  if (allow_cooperative != 2) cand.push_back(BatchConfig{3, 0, 64});
   if (allow_cooperative) {
     cand.push_back(BatchConfig{1, 0, 0});
     for (int item : {64, 256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});

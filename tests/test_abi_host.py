@@ -131,6 +131,9 @@ def test_tune_batched_host_validation(lib):
     st = L.nbody_tune_batched(1, off.ctypes.data_as(PI), eps.ctypes.data_as(PD), None, None, None, 0.1, 0, 1,
                               ctypes.byref(p), None)
     assert st == nb.NBODY_EINVAL and b"nsteps" in L.nbody_last_error()
+    st = L.nbody_tune_batched(1, off.ctypes.data_as(PI), eps.ctypes.data_as(PD), None, None, None, 0.1, 4, 3,
+                              ctypes.byref(p), None)
+    assert st == nb.NBODY_EINVAL and b"allow_cooperative" in L.nbody_last_error()
 
 
 def test_set_config_validation(lib):

@@ -509,6 +509,10 @@ def test_tune_batched_records_and_applies_choice(nb):
     # the search without co-residency returns a configuration that needs none (resident kernel or per-step items)
     best0 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp64", allow_cooperative=False)
     assert best0["bsplit"] in (0, 3)
+    # the single-launch search returns a configuration that runs all steps in one launch
+    best1 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp32c",
+                                  allow_cooperative="persistent")
+    assert best1["bsplit"] in (0, 1, 2)
 
 
 def test_batched_matches_oracle_fp64(nb, oracle_mod):
