@@ -242,7 +242,9 @@ int nbody_step_hermite6(int64_t n, double* x, double* v, double* a, double* jk, 
 /* Tile configuration of the all-pairs kernels (see nbody_set_config). */
 typedef struct nbody_config {
   int32_t ipl;     /* i-particles per lane: 1, 2 or 4 */
-  int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024 */
+  int32_t split;   /* j-range split across workgroups: 0 = automatic, else 1..1024;
+                      with the symmetric force kernel (pairs), the least number of
+                      launches its half ring of block pairs is cut into */
   int32_t bsplit;  /* batched kernel, used when any of bsplit, bpass, bitem is
                       non-zero (all zero: the tuned choice for the layout, else
                       mode 3): 0 = one workgroup per system, its records
@@ -265,6 +267,16 @@ typedef struct nbody_config {
                       wave against the system's whole j-range; or 256, 512, 1024:
                       most particles per item of a system above 256 particles,
                       evaluated by a whole workgroup */
+  int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
+                      steps (FP32C and FP32; FP64 is always ordered):
+                      0 = automatic (the tuned choice for (n, precision), else
+                      symmetric from 32768 particles on), 1 = ordered: every
+                      ordered pair evaluated for its i; 2 = symmetric: every
+                      unordered pair evaluated once and applied to both particles
+                      (a_j gets the opposite of i's term scaled by m_i / m_j),
+                      results summed in a fixed order (reproducible), at the cost
+                      of a workspace of about 1 GiB for large n and an FP32 sum
+                      of up to 512 terms per j before the FP64 sums */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros

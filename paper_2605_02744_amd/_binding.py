@@ -47,7 +47,8 @@ class nbody_params(ctypes.Structure):
 
 class nbody_config(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32), ("bitem", ctypes.c_int32)]
+                ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32), ("bitem", ctypes.c_int32),
+                ("pairs", ctypes.c_int32)]
 
 
 _lib = None
@@ -320,7 +321,7 @@ def nbody_step_hermite6(x, v, a, jk, sn, cr, m, dt, nsteps, *, G=1.0, eps, preci
                                        _stream(x.device)))
 
 
-def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0):
+def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0):
     """Forces a tile configuration on this thread (all zeros = automatic);
     bsplit=1 lets the ensemble kernel split its largest systems over up to 4
     workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
@@ -328,8 +329,10 @@ def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0):
     launches per step, default 0: one workgroup per system; bpass sets
     how many of a lane's i-particles the ensemble kernel evaluates per pass
     (1, 2, 4); bitem the streamed kernel's item size (64, the automatic
-    choice: one wave per item; or 256, 512, 1024: one workgroup per item)."""
-    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem))
+    choice: one wave per item; or 256, 512, 1024: one workgroup per item);
+    pairs the form of the FP32C/FP32 force kernel (1 ordered, 2 symmetric:
+    each unordered pair once; 0 automatic)."""
+    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem), int(pairs))
     _check(load().nbody_set_config(ctypes.byref(c)))
 
 
@@ -340,7 +343,7 @@ def nbody_tune(n, precision="fp32c", cache_path=None):
     best = nbody_config()
     path = cache_path.encode() if cache_path else None
     _check(load().nbody_tune(int(n), int(precision), path, ctypes.byref(best)))
-    return {"ipl": best.ipl, "split": best.split}
+    return {"ipl": best.ipl, "split": best.split, "pairs": best.pairs}
 
 
 def nbody_last_error():

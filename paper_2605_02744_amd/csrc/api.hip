@@ -144,10 +144,19 @@ PairConfig choose_config(int64_t n, int precision, int device) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(std::make_tuple(device, precision, n));
     if (it != g_tuned.end()) c = it->second;
-    else c.split = 0;
+    else {
+      c.split = 0;
+      c.sym = (precision != NBODY_FP64 && n >= kSymMinN) ? 1 : 0;
+    }
   }
   if (t.ipl) c.ipl = t.ipl;
   if (t.split) c.split = t.split;
+  if (t.pairs) c.sym = t.pairs == 2 ? 1 : 0;
+  // the symmetric kernel reads split as a least number of launches (0 = automatic)
+  if (c.sym && precision != NBODY_FP64) {
+    c.split = t.split;
+    return c;
+  }
   if (c.split <= 0) c.split = auto_split(n, c.ipl, device);
   return c;
 }
@@ -586,6 +595,7 @@ int nbody_set_config(const nbody_config* cfg) {
     return set_error(NBODY_EINVAL, "bpass must be 0, 1, 2 or 4");
   if (cfg->bitem != 0 && cfg->bitem != 64 && cfg->bitem != 256 && cfg->bitem != 512 && cfg->bitem != 1024)
     return set_error(NBODY_EINVAL, "bitem must be 0, 64, 256, 512 or 1024");
+  if (cfg->pairs < 0 || cfg->pairs > 2) return set_error(NBODY_EINVAL, "pairs must be 0, 1 or 2");
   set_thread_config(*cfg);
   return NBODY_OK;
 }
@@ -658,18 +668,38 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
       if (ms < best_ms) { best_ms = ms; bc = c; }
     }
   }
+  if (precision != NBODY_FP64) {
+    // the symmetric kernel (its tiling is fixed)
+    PairConfig c;
+    c.ipl = 2;
+    c.split = 0;
+    c.sym = 1;
+    int st = launch_accel(n, dx, dm, da, 1.0, 0.01, precision, false, c, nullptr);
+    if (st) { cleanup(); return st; }
+    const int reps = 3;
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps; ++r) launch_accel(n, dx, dm, da, 1.0, 0.01, precision, false, c, nullptr);
+    (void)hipEventRecord(e1, nullptr);
+    if (hipEventSynchronize(e1) != hipSuccess) { cleanup(); return set_error(NBODY_EHIP, "tune: sync failed"); }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    log.push_back({c, ms});
+    if (ms < best_ms) { best_ms = ms; bc = c; }
+  }
   cleanup();
   record_tuned(dev, n, precision, bc);
-  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0, 0};
+  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0, 0, bc.sym ? 2 : 1};
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
       hipDeviceProp_t prop;
       (void)hipGetDeviceProperties(&prop, dev);
-      std::fprintf(f, "{\"arch\": \"%s\", \"n\": %lld, \"precision\": %d, \"ipl\": %d, \"split\": %d, \"ms\": %.6f, \"trials\": [",
-                   prop.gcnArchName, (long long)n, precision, bc.ipl, bc.split, best_ms);
+      std::fprintf(f, "{\"arch\": \"%s\", \"n\": %lld, \"precision\": %d, \"ipl\": %d, \"split\": %d, \"pairs\": %d, \"ms\": %.6f, \"trials\": [",
+                   prop.gcnArchName, (long long)n, precision, bc.ipl, bc.split, bc.sym ? 2 : 1, best_ms);
       for (size_t k = 0; k < log.size(); ++k)
-        std::fprintf(f, "%s[%d, %d, %.6f]", k ? ", " : "", log[k].first.ipl, log[k].first.split, log[k].second);
+        std::fprintf(f, "%s[%d, %d, %d, %.6f]", k ? ", " : "", log[k].first.ipl, log[k].first.split,
+                     log[k].first.sym ? 2 : 1, log[k].second);
       std::fprintf(f, "]}\n");
       std::fclose(f);
     }

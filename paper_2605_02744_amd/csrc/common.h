@@ -43,11 +43,13 @@ constexpr int kBlock = 256;        // threads per workgroup of the all-pairs ker
 constexpr int kTile = 256;         // j-particles staged in LDS per tile
 constexpr int kFold = 64;          // j-terms summed in plain FP32/FP64 before a TwoSum fold
 constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
+constexpr int64_t kSymMinN = 32768;  // FP32C/FP32 systems from this size use the symmetric kernel by default
 
 // Per-call configuration of the all-pairs kernels.
 struct PairConfig {
   int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups
+  int sym = 0;    // 1: the symmetric kernel (each unordered pair once; FP32C/FP32)
 };
 
 PairConfig choose_config(int64_t n, int precision, int device);
@@ -60,6 +62,13 @@ void record_tuned(int device, int64_t n, int precision, const PairConfig& c);
 // partial sums.  Returns NBODY_OK or an error status.
 int launch_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps,
                  int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
+
+// The same accelerations from the symmetric kernel (FP32C or FP32): every
+// unordered pair once, applied to both particles; slot sums in the workspace.
+// launches > 0: at least that many kernel launches over the half ring
+// (0 = as few as the workspace bound allows).
+int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
+                     bool exclude_self, int launches, hipStream_t s);
 
 // (da/dx)^T w into gx and (da/dm)^T w into gm.
 int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx,

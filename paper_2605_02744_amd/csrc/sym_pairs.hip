@@ -1,0 +1,486 @@
+// Symmetric all-pairs acceleration: every unordered pair {i, j} is evaluated
+// once and its term is applied to both particles (a_i gets m_j d r^-3, a_j gets
+// -m_i d r^-3, the pairwise antisymmetry of Eq. 1), which halves the inverse
+// square roots, displacements and squared distances of the ordered kernel.
+//
+// Layout on the chip:
+//   * a workgroup of 256 lanes holds an I-block of 512 particles, two per lane
+//     (lane t owns i = 512 g + t and 512 g + 256 + t), and streams J-blocks of
+//     512 particles through LDS in tiles of 64;
+//   * the lanes form 16 rows of 16.  A tile is 4 sub-blocks of 16 records, each
+//     stored twice in a row in LDS, so that at step K (0..15) lane r of a row
+//     reads record (r + K) of the sub-block at an immediate offset: over 16
+//     steps every lane meets all 16 records, and at each step the 16 lanes of a
+//     row meet 16 different j;
+//   * the i-side terms stay in the lane; the j-side terms of a step (both i of
+//     the lane summed first) belong to the lane that met that j at step 0 and
+//     move there through a row rotation (DPP row_ror) fused into the add;
+//   * after a sub-block each lane stores its 16-step j-side sum per row in LDS;
+//     after the tile the 16 row sums of each j are added in row order and the
+//     tile's sum is written to a per-distance slot in HBM; a reduction kernel
+//     adds the slots in a fixed order in FP64, so results are reproducible;
+//   * block pairs are visited once on a half ring: I-block g meets the J-blocks
+//     g + d (mod nb) for d = 1 .. nb/2 (d = nb/2 only for g < nb/2 when nb is
+//     even); d = 0 is the block with itself, evaluated in the ordered form (the
+//     i-side only, over all 512 j, the own pair masked when asked);
+//   * the half ring is cut into chunks of D distances, one launch and one
+//     reduction each, so the slot buffers stay bounded whatever N is.
+// FP32C (positions rounded to FP32 plus the near-field repair of the ordered
+// kernel: pairs closer than the larger repair radius of their two particles get
+// float-float displacements, for both sides) and FP32 (no repair) are built.
+#include "pair_math.h"
+
+namespace nb {
+namespace {
+
+constexpr int kSL = 256;            // lanes per workgroup
+constexpr int kSI = 2 * kSL;        // particles per I-block / J-block
+constexpr int kST = 64;             // j-particles per LDS tile
+constexpr int kSR = 16;             // lanes per row = records per sub-block
+constexpr int kSRows = kSL / kSR;   // rows per workgroup
+constexpr int kSTiles = kSI / kST;  // tiles per J-block
+
+// v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
+template <int K>
+__device__ __forceinline__ float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xF, 0xF, true));
+}
+
+struct SymArgs {
+  const double* x;  // [3][n]
+  const double* m;  // [n]
+  int n;
+  int nb;           // blocks of kSI particles
+  int npad;         // nb * kSI
+  int dmax;         // largest ring distance
+  int half;         // nb even: distance dmax only for g < nb / 2
+  int d_lo;         // first distance of this chunk
+  int L;            // distances per workgroup
+  int nparts;       // workgroups per I-block in this chunk
+  double eps;
+  float fx;         // repair-radius factor max(kNearX, kNearN n^-1/3)
+  float* pj;        // [D][3][npad] j-side tile sums of the chunk's distances
+  double* pi;       // [nparts][3][npad] i-side sums of the chunk's workgroups
+};
+
+// Largest valid distance + 1 for I-block g.
+__device__ __forceinline__ int ring_end(const SymArgs& A, int g) {
+  return (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1;
+}
+
+// Squared repair radius (the near-field rule of the ordered kernel, with its
+// n-dependent factor f given): a pair closer than max(f |x|_inf, kNearEps eps)
+// to the particle at (xa, ya, za) gets float-float displacements.
+__device__ __forceinline__ float sym_rc2(double xa, double ya, double za, double eps, float f) {
+  const float dc = fmaxf(f * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
+  return dc * dc + (float)(eps * eps);
+}
+
+struct ISet {
+  float x[2], y[2], z[2], mneg[2];
+};
+
+// One step of a sub-block: both i of the lane against record (r + K).
+template <int K, bool NEAR>
+__device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
+                                         float (&py)[2], float (&pz)[2], float& r2min, float& ajx, float& ajy,
+                                         float& ajz) {
+  const float4 r = rowp[K];
+  float tx = 0.f, ty = 0.f, tz = 0.f;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const float dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+    const float ri = rsqrt32(r2);
+    const float ri3 = (ri * ri) * ri;
+    const float si = r.w * ri3;
+    px[u] = fmaf(si, dx, px[u]);
+    py[u] = fmaf(si, dy, py[u]);
+    pz[u] = fmaf(si, dz, pz[u]);
+    if constexpr (NEAR) r2min = fminf(r2min, r2);
+    const float sj = s.mneg[u] * ri3;
+    if (u == 0) { tx = sj * dx; ty = sj * dy; tz = sj * dz; }
+    else { tx = fmaf(sj, dx, tx); ty = fmaf(sj, dy, ty); tz = fmaf(sj, dz, tz); }
+  }
+  // the j met here sits at row position (r + K): its owner, the lane that met it
+  // at step 0, is K lanes further on
+  if constexpr (K == 0) { ajx += tx; ajy += ty; ajz += tz; }
+  else {
+    ajx += row_ror<K>(tx);
+    ajy += row_ror<K>(ty);
+    ajz += row_ror<K>(tz);
+  }
+}
+
+template <bool NEAR, int... K>
+__device__ __forceinline__ void sym_sub(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
+                                        float (&py)[2], float (&pz)[2], float& r2min, float& ajx, float& ajy,
+                                        float& ajz, std::integer_sequence<int, K...>) {
+  (sym_step<K, NEAR>(s, rowp, e2, px, py, pz, r2min, ajx, ajy, ajz), ...);
+}
+
+// Loads the two i of lane t of I-block g (padding i: far away and massless, so
+// they add nothing to any j); thr = the larger of the two radii^2 that flag a
+// tile for the repair, -1 for padding.  PAIR: radii that also hold every pair
+// inside the j's own repair radius, since the pair serves both particles:
+// |d| < f |x_j| with |x_j| <= |x_i| + |d| gives |d| < f / (1 - f) |x_i| (f is at
+// most 1/2; the eps term is the same for both particles).
+template <bool PAIR>
+__device__ __forceinline__ void load_iset(const SymArgs& A, int g, int t, ISet& s, float& thr) {
+  thr = -1.f;
+  const int n = A.n;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = g * kSI + u * kSL + t;
+    if (i < n) {
+      const double xa = A.x[i], ya = A.x[n + i], za = A.x[2 * n + i];
+      s.x[u] = (float)xa; s.y[u] = (float)ya; s.z[u] = (float)za;
+      s.mneg[u] = -(float)A.m[i];
+      thr = fmaxf(thr, sym_rc2(xa, ya, za, A.eps, PAIR ? A.fx / (1.0f - A.fx) * 1.0001f : A.fx));
+    } else {
+      s.x[u] = s.y[u] = s.z[u] = (float)kFarAway;
+      s.mneg[u] = 0.f;
+    }
+  }
+}
+
+// j-record of particle j (padding past n: far away, massless, never repaired).
+template <bool NEAR>
+__device__ __forceinline__ void load_jrec(const SymArgs& A, int j, float4& hi, float4& lo) {
+  const int n = A.n;
+  if (j < n) {
+    const double xa = A.x[j], ya = A.x[n + j], za = A.x[2 * n + j];
+    hi = make_float4((float)xa, (float)ya, (float)za, (float)A.m[j]);
+    lo = make_float4((float)(xa - (double)hi.x), (float)(ya - (double)hi.y), (float)(za - (double)hi.z),
+                     NEAR ? sym_rc2(xa, ya, za, A.eps, A.fx) : -1.f);
+  } else {
+    hi = make_float4((float)kFarAway, (float)kFarAway, (float)kFarAway, 0.f);
+    lo = make_float4(0.f, 0.f, 0.f, -1.f);
+  }
+}
+
+// Float-float term minus rounded-position term of the pair (i, j), times m:
+// the near-field correction (FP32C), for i with m = m_j and for j with m = -m_i.
+__device__ __forceinline__ void near_delta(float dx, float dy, float dz, float r2, float ex, float ey, float ez,
+                                           float e2, float& fx, float& fy, float& fz) {
+  const float ri = rsqrt32(r2);
+  const float ri3 = (ri * ri) * ri;
+  const float q2 = fmaf(ez, ez, fmaf(ey, ey, fmaf(ex, ex, e2)));
+  const float qi = rsqrt32(q2);
+  const float qi3 = (qi * qi) * qi;
+  fx = fmaf(qi3, ex, -(ri3 * dx));
+  fy = fmaf(qi3, ey, -(ri3 * dy));
+  fz = fmaf(qi3, ez, -(ri3 * dz));
+}
+
+// Grid: nb * nparts workgroups; workgroup (g, part) takes the distances
+// [d_lo + part L, d_lo + (part + 1) L) of I-block g's half ring (d >= 1).
+template <bool NEAR>
+__global__ __launch_bounds__(kSL, 8) void sym_accel_kernel(SymArgs A) {
+  __shared__ float4 s_hi[2][4][2 * kSR];  // (x, y, z, m) hi parts, each sub-block twice
+  __shared__ float4 s_lo[2][kST];         // (x, y, z) lo parts and the repair radius^2 of j
+  __shared__ float s_part[3][kSRows][kST];
+
+  const int t = threadIdx.x;
+  const int rl = t & (kSR - 1);
+  const int row = t / kSR;
+  const int g = blockIdx.x % A.nb;
+  const int part = blockIdx.x / A.nb;
+  const int dbeg = A.d_lo + part * A.L;
+  const int dend = min(dbeg + A.L, ring_end(A, g));
+  const int ntiles = dend > dbeg ? (dend - dbeg) * kSTiles : 0;
+  const int n = A.n;
+  const float e2 = (float)(A.eps * A.eps);
+
+  ISet s;
+  float thr;
+  load_iset<true>(A, g, t, s, thr);
+  float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
+  float lx[2] = {0.f, 0.f}, ly[2] = {0.f, 0.f}, lz[2] = {0.f, 0.f};
+
+  // the last wave stages tile k of the workgroup into LDS buffer b
+  auto stage = [&](int k, int b) {
+    const int jl = t - 3 * 64;
+    const int J = (g + dbeg + k / kSTiles) % A.nb;
+    float4 hi, lo;
+    load_jrec<NEAR>(A, J * kSI + (k % kSTiles) * kST + jl, hi, lo);
+    s_hi[b][jl / kSR][jl % kSR] = hi;
+    s_hi[b][jl / kSR][kSR + jl % kSR] = hi;
+    s_lo[b][jl] = lo;
+  };
+
+  if (ntiles > 0 && t >= 3 * 64) stage(0, 0);
+  __syncthreads();
+
+  for (int k = 0; k < ntiles; ++k) {
+    const int b = k & 1;
+    const int d = dbeg + k / kSTiles;
+    const int tt = k % kSTiles;
+    float px[2] = {0.f, 0.f}, py[2] = {0.f, 0.f}, pz[2] = {0.f, 0.f};
+    float r2min = 3.0e38f;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      float ajx = 0.f, ajy = 0.f, ajz = 0.f;
+      sym_sub<NEAR>(s, &s_hi[b][q][rl], e2, px, py, pz, r2min, ajx, ajy, ajz, std::make_integer_sequence<int, kSR>{});
+      s_part[0][row][q * kSR + rl] = ajx;
+      s_part[1][row][q * kSR + rl] = ajy;
+      s_part[2][row][q * kSR + rl] = ajz;
+    }
+    if constexpr (NEAR) {
+      // rare: a pair of this tile may be closer than the larger repair radius
+      // of its two particles: replace the rounded-position term of every such
+      // pair by the float-float one, for i here and for j in the tile's row sums
+      if (r2min < thr) {
+        float rc[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int i = g * kSI + u * kSL + t;
+          rc[u] = i < n ? sym_rc2(A.x[i], A.x[n + i], A.x[2 * n + i], A.eps, A.fx) : -1.f;
+        }
+#pragma unroll 1
+        for (int jj = 0; jj < kST; ++jj) {
+          // in the rotated order of the main loop: at each step the lanes of a
+          // row touch distinct j, so the row-sum updates below never collide
+          const int q = jj / kSR;
+          const int jl = q * kSR + ((rl + jj) & (kSR - 1));
+          const float4 rh = s_hi[b][q][jl % kSR];
+          const float4 lo = s_lo[b][jl];
+          float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const float dx = rh.x - s.x[u], dy = rh.y - s.y[u], dz = rh.z - s.z[u];
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            if (rc[u] >= 0.f && r2 < fmaxf(rc[u], lo.w)) {
+              const int i = g * kSI + u * kSL + t;
+              const double xa = A.x[i], ya = A.x[n + i], za = A.x[2 * n + i];
+              const float ex = dx + (lo.x - (float)(xa - (double)s.x[u]));
+              const float ey = dy + (lo.y - (float)(ya - (double)s.y[u]));
+              const float ez = dz + (lo.z - (float)(za - (double)s.z[u]));
+              float fx, fy, fz;
+              near_delta(dx, dy, dz, r2, ex, ey, ez, e2, fx, fy, fz);
+              px[u] = fmaf(rh.w, fx, px[u]);
+              py[u] = fmaf(rh.w, fy, py[u]);
+              pz[u] = fmaf(rh.w, fz, pz[u]);
+              cx = fmaf(s.mneg[u], fx, cx);
+              cy = fmaf(s.mneg[u], fy, cy);
+              cz = fmaf(s.mneg[u], fz, cz);
+            }
+          }
+          if (cx != 0.f || cy != 0.f || cz != 0.f) {
+            s_part[0][row][jl] += cx;
+            s_part[1][row][jl] += cy;
+            s_part[2][row][jl] += cz;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      fold(hx[u], lx[u], px[u]);
+      fold(hy[u], ly[u], py[u]);
+      fold(hz[u], lz[u], pz[u]);
+    }
+    __syncthreads();
+    if (t < 3 * 64) {
+      // the tile's j-side sums: the 16 row sums of each j, in row order
+      const int c = t / kST, jl = t % kST;
+      float v = 0.f;
+#pragma unroll
+      for (int r = 0; r < kSRows; ++r) v += s_part[c][r][jl];
+      const int J = (g + d) % A.nb;
+      A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + (size_t)J * kSI + tt * kST + jl] = v;
+    } else if (k + 1 < ntiles) {
+      stage(k + 1, b ^ 1);
+    }
+    __syncthreads();
+  }
+
+  // the i-side sums of this workgroup
+  double* o = A.pi + (size_t)part * 3 * A.npad;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const size_t i = (size_t)g * kSI + u * kSL + t;
+    o[i] = (double)hx[u] + (double)lx[u];
+    o[A.npad + i] = (double)hy[u] + (double)ly[u];
+    o[2 * (size_t)A.npad + i] = (double)hz[u] + (double)lz[u];
+  }
+}
+
+// The block with itself (distance 0): the i-side of all ordered pairs inside
+// I-block g, in the ordered form (the LDS record broadcast to every lane), with
+// the own pair masked when asked and the near-field repair of the force kernel.
+// Writes hi + lo into pd[3][npad].
+template <bool NEAR, bool EXCL>
+__global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __restrict__ pd) {
+  __shared__ float4 s_hi[kSI];
+  __shared__ float4 s_lo[kSI];
+  const int t = threadIdx.x;
+  const int g = blockIdx.x;
+  const float e2 = (float)(A.eps * A.eps);
+  ISet s;
+  float thr;
+  load_iset<false>(A, g, t, s, thr);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) load_jrec<NEAR>(A, g * kSI + u * kSL + t, s_hi[u * kSL + t], s_lo[u * kSL + t]);
+  __syncthreads();
+  float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
+  float lx[2] = {0.f, 0.f}, ly[2] = {0.f, 0.f}, lz[2] = {0.f, 0.f};
+  float rc[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) rc[u] = s_lo[u * kSL + t].w;
+#pragma unroll 1
+  for (int f = 0; f < kSI; f += kFold) {
+    float px[2] = {0.f, 0.f}, py[2] = {0.f, 0.f}, pz[2] = {0.f, 0.f};
+    float r2min = 3.0e38f;
+#pragma unroll 16
+    for (int j = f; j < f + kFold; ++j) {
+      const float4 r = s_hi[j];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const float dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+        const float ri = rsqrt32(r2);
+        float si = (r.w * ri) * (ri * ri);
+        if (EXCL) si = (j == u * kSL + t) ? 0.f : si;
+        px[u] = fmaf(si, dx, px[u]);
+        py[u] = fmaf(si, dy, py[u]);
+        pz[u] = fmaf(si, dz, pz[u]);
+        if constexpr (NEAR) r2min = fminf(r2min, r2);
+      }
+    }
+    if constexpr (NEAR) {
+      if (r2min < thr) {
+        for (int j = f; j < f + kFold; ++j) {
+          const float4 rh = s_hi[j];
+          const float4 lo = s_lo[j];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const float dx = rh.x - s.x[u], dy = rh.y - s.y[u], dz = rh.z - s.z[u];
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            if (rc[u] >= 0.f && r2 < rc[u] && j != u * kSL + t) {
+              const float4 li = s_lo[u * kSL + t];
+              float fx, fy, fz;
+              near_delta(dx, dy, dz, r2, dx + (lo.x - li.x), dy + (lo.y - li.y), dz + (lo.z - li.z), e2, fx, fy, fz);
+              px[u] = fmaf(rh.w, fx, px[u]);
+              py[u] = fmaf(rh.w, fy, py[u]);
+              pz[u] = fmaf(rh.w, fz, pz[u]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      fold(hx[u], lx[u], px[u]);
+      fold(hy[u], ly[u], py[u]);
+      fold(hz[u], lz[u], pz[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const size_t i = (size_t)g * kSI + u * kSL + t;
+    pd[i] = (double)hx[u] + (double)lx[u];
+    pd[A.npad + i] = (double)hy[u] + (double)ly[u];
+    pd[2 * (size_t)A.npad + i] = (double)hz[u] + (double)lz[u];
+  }
+}
+
+// Adds the chunk's slots into a: the j-side tile sums of distances
+// d_lo .. d_lo + D - 1 that were evaluated, then the i-side sums of the
+// chunk's workgroups; the first chunk starts from the distance-0 sums pd, the
+// last applies G.  One thread per (particle, component), fixed order.
+__global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
+                                  const float* __restrict__ pj, const double* __restrict__ pi,
+                                  const double* __restrict__ pd, double* __restrict__ a, double G, int first,
+                                  int last) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (p >= n) return;
+  const int J = p / kSI;
+  double acc = first ? pd[(size_t)c * npad + p] : a[(size_t)c * n + p];
+  for (int s = 0; s < D; ++s) {
+    const int d = d_lo + s;
+    if (d > dmax) break;
+    const int g = ((J - d) % nb + nb) % nb;
+    if (half && d == dmax && g >= nb / 2) continue;
+    acc += (double)pj[((size_t)s * 3 + c) * npad + p];
+  }
+  for (int k = 0; k < nparts; ++k) acc += pi[((size_t)k * 3 + c) * npad + p];
+  a[(size_t)c * n + p] = last ? G * acc : acc;
+}
+
+}  // namespace
+
+// Chunking of the half ring for n particles: distances per workgroup (L) and
+// per launch (D), bounded by the slot memory; launches > 0 asks for at least
+// that many launches.
+void sym_plan(int64_t n, int launches, int* nb_out, int* L_out, int* D_out) {
+  const int nb = (int)((n + kSI - 1) / kSI);
+  const int dmax = nb / 2;
+  const int64_t npad = (int64_t)nb * kSI;
+  // j-side slots: 12 B per particle per distance; keep a chunk's slots near 1 GiB
+  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (12 * npad));
+  if (launches > 0) dcap = std::min<int64_t>(dcap, std::max(1, (dmax + launches - 1) / launches));
+  const int d0 = (int)std::max<int64_t>(1, std::min<int64_t>(dmax, dcap));
+  // at least ~4096 workgroups per launch (several rounds of 8 per CU), at most 16 distances each
+  const int L = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(16, d0), (int64_t)nb * d0 / 4096));
+  *nb_out = nb;
+  *L_out = L;
+  *D_out = (d0 + L - 1) / L * L;
+}
+
+int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
+                     bool excl, int launches, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  if (precision != kFP32C && precision != kFP32)
+    return set_error(NBODY_EUNSUPPORTED, "symmetric pair kernel: FP32C and FP32 only");
+  if (n > (int64_t(1) << 30)) return set_error(NBODY_EINVAL, "symmetric pair kernel: n too large");
+  int nb, L, D;
+  sym_plan(n, launches, &nb, &L, &D);
+  const int dmax = nb / 2;
+  const int half = (nb % 2 == 0) ? 1 : 0;
+  const int64_t npad = (int64_t)nb * kSI;
+  const int nparts = D / L;
+  int st = NBODY_OK;
+  const size_t pj_bytes = sizeof(float) * 3 * (size_t)npad * D;
+  const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
+  const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
+  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes, &st));
+  if (!ws) return st;
+  SymArgs A;
+  A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
+  A.L = L; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  A.fx = std::max(kNearX, kNearN / std::cbrt((float)n));
+  A.pj = reinterpret_cast<float*>(ws);
+  A.pi = reinterpret_cast<double*>(ws + pj_bytes);
+  double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);
+  const bool near = precision == kFP32C;
+  if (near) {
+    if (excl) sym_diag_kernel<true, true><<<nb, kSL, 0, s>>>(A, pd);
+    else sym_diag_kernel<true, false><<<nb, kSL, 0, s>>>(A, pd);
+  } else {
+    if (excl) sym_diag_kernel<false, true><<<nb, kSL, 0, s>>>(A, pd);
+    else sym_diag_kernel<false, false><<<nb, kSL, 0, s>>>(A, pd);
+  }
+  NB_LAUNCH_CHECK("sym_diag_kernel");
+  const dim3 rg((unsigned)((n + 255) / 256), 3);
+  if (dmax == 0) {
+    sym_reduce_kernel<<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, G, 1, 1);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+    return NBODY_OK;
+  }
+  const int nchunks = (dmax + D - 1) / D;
+  for (int c = 0; c < nchunks; ++c) {
+    A.d_lo = 1 + c * D;
+    const unsigned grid = (unsigned)nb * (unsigned)nparts;
+    if (near) sym_accel_kernel<true><<<grid, kSL, 0, s>>>(A);
+    else sym_accel_kernel<false><<<grid, kSL, 0, s>>>(A);
+    NB_LAUNCH_CHECK("sym_accel_kernel");
+    sym_reduce_kernel<<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd, a, G,
+                                         c == 0, c == nchunks - 1);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace nb

@@ -1,0 +1,166 @@
+"""GPU parity of the symmetric FP32C/FP32 force kernel (each unordered pair
+evaluated once and applied to both particles) against the FP64 CPU oracle,
+through the C ABI.  Same error statistic and tolerances as the ordered kernel:
+max over particles of |a_i - a_i^ref| / |a_i^ref|, 1e-5 for FP32C, 1e-4 for
+FP32 (rounded positions, no repair) on inputs without tight pairs.
+
+Sizes cover the block structure of the kernel: blocks of 512 particles, an odd
+and an even number of blocks (the half ring of block pairs visits the opposite
+block once when the count is even), ragged last blocks, a single block (only
+the block with itself), and half rings cut into several launches.
+"""
+import numpy as np
+import pytest
+
+import ics
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32c": 1e-5, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_02744_amd as nbm
+    nbm.load()
+    return nbm
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def rel_err(a, ref):
+    num = np.linalg.norm(a - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    return (num / np.where(den > 0, den, 1.0)).max()
+
+
+def sym_accel(nb, x, m, launches=0, **kw):
+    nb.nbody_set_config(pairs=2, split=launches)
+    try:
+        return nb.nbody_accel(dev(x), dev(m), **kw).cpu().numpy()
+    finally:
+        nb.nbody_set_config()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 511, 512, 513, 1024, 1025, 1536, 2048, 2500, 4097, 6000])
+@pytest.mark.parametrize("prec", ["fp32c", "fp32"])
+def test_sym_accel_ragged_sizes(nb, oracle_mod, n, prec):
+    x, _, m = ics.plummer(n, seed=300 + n)
+    G, eps = 1.2, 0.01
+    ref = oracle_mod.accel(x, m, G=G, eps=eps)
+    print("sym accel n=%d %s" % (n, prec), flush=True)
+    a = sym_accel(nb, x, m, G=G, eps=eps, precision=prec)
+    if n == 1:
+        assert np.all(a == 0.0)
+        return
+    e = rel_err(a, ref)
+    print("  max rel err %.3e" % e)
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("n,launches", [(5000, 1), (5000, 2), (5000, 5), (9000, 3), (9000, 9), (20000, 4)])
+def test_sym_accel_launch_splits(nb, oracle_mod, n, launches):
+    """The half ring cut into several launches (each with its own slot sums)
+    gives the oracle's accelerations, and the same bits whatever the cut is
+    not promised, but the same values to rounding."""
+    x, _, m = ics.two_component(n, seed=41)
+    G, eps = 1.0, 0.02
+    ref = oracle_mod.accel(x, m, G=G, eps=eps)
+    print("sym accel n=%d launches=%d" % (n, launches), flush=True)
+    a = sym_accel(nb, x, m, launches=launches, G=G, eps=eps, precision="fp32c")
+    e = rel_err(a, ref)
+    print("  max rel err %.3e" % e)
+    assert e <= TOL["fp32c"]
+
+
+def test_sym_accel_tight_pairs_near_field(nb, oracle_mod):
+    """Tight pairs far from the origin (separations 1e-5 .. 1e-3 at |x| ~ 6):
+    the repair must fix the term for both particles of the pair, whichever of
+    them is the lane's i and whichever the streamed j."""
+    x, _, m = ics.plummer(3000, seed=30)
+    x = x + np.array([[3.0], [-2.0], [5.0]])
+    rng = np.random.default_rng(30)
+    a_idx = rng.choice(1500, 200, replace=False)
+    b_idx = 1500 + np.arange(200)
+    off = rng.standard_normal((3, 200))
+    off *= 10 ** rng.uniform(-5, -3, 200) / np.linalg.norm(off, axis=0)
+    x[:, b_idx] = x[:, a_idx] + off
+    ref = oracle_mod.accel(x, m, eps=0.01)
+    a = sym_accel(nb, x, m, eps=0.01, precision="fp32c")
+    e = rel_err(a, ref)
+    print("sym tight pairs max rel err %.3e" % e)
+    assert e <= TOL["fp32c"]
+    a32 = sym_accel(nb, x, m, eps=0.01, precision="fp32")
+    assert rel_err(a32, ref) > 10 * TOL["fp32c"]
+
+
+@pytest.mark.parametrize("n", [700, 1500])
+def test_sym_accel_exclude_self_eps_zero(nb, oracle_mod, n):
+    x, _, m = ics.random_cloud(n, seed=3)
+    ref = oracle_mod.accel(x, m, eps=0.0)
+    a = sym_accel(nb, x, m, eps=0.0, precision="fp32c", exclude_self=True)
+    assert np.isfinite(a).all()
+    assert rel_err(a, ref) <= 10 * TOL["fp32c"]
+
+
+def test_sym_accel_unequal_masses(nb, oracle_mod):
+    """The j-side term uses m_i: masses spread over four decades."""
+    x, _, m = ics.plummer(3001, seed=77)
+    m = m * 10 ** np.random.default_rng(77).uniform(-2, 2, m.shape)
+    ref = oracle_mod.accel(x, m, G=0.7, eps=0.02)
+    a = sym_accel(nb, x, m, G=0.7, eps=0.02, precision="fp32c")
+    assert rel_err(a, ref) <= TOL["fp32c"]
+
+
+def test_sym_accel_repeat_bitwise(nb):
+    x, _, m = ics.two_component(7000, seed=5)
+    runs = [sym_accel(nb, x, m, launches=2, eps=0.01, precision="fp32c") for _ in range(3)]
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+
+
+def test_sym_and_ordered_agree(nb, oracle_mod):
+    x, _, m = ics.plummer(40000, seed=8)
+    rows = np.random.default_rng(8).choice(40000, 400, replace=False)
+    ref = oracle_mod.accel_rows(x, m, rows, eps=0.01)
+    nb.nbody_set_config(pairs=1)
+    try:
+        ao = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp32c").cpu().numpy()
+    finally:
+        nb.nbody_set_config()
+    asym = sym_accel(nb, x, m, eps=0.01, precision="fp32c")
+    # the automatic choice at this size is the symmetric kernel
+    aauto = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp32c").cpu().numpy()
+    assert np.array_equal(aauto, asym)
+    a64 = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp64").cpu().numpy()
+    assert rel_err(asym, a64) <= TOL["fp32c"]
+    assert rel_err(ao, a64) <= TOL["fp32c"]
+    assert rel_err(asym[:, rows], ref) <= TOL["fp32c"]
+
+
+def test_sym_kdk_steps_match_ordered(nb):
+    """nbody_step with the symmetric force: the trajectory stays within the
+    FP32C force error of the ordered kernel's trajectory."""
+    x, v, m = ics.plummer(6000, seed=9)
+    out = {}
+    for pairs in (1, 2):
+        tx, tv = dev(x), dev(v)
+        ta = torch.empty_like(tx)
+        nb.nbody_set_config(pairs=pairs)
+        try:
+            nb.nbody_step(tx, tv, ta, dev(m), 1.0 / 256, 8, eps=0.01, precision="fp32c")
+        finally:
+            nb.nbody_set_config()
+        out[pairs] = (tx.cpu().numpy(), tv.cpu().numpy())
+    assert np.abs(out[1][0] - out[2][0]).max() <= 1e-9
+    assert np.abs(out[1][1] - out[2][1]).max() <= 1e-7
+
+
+def test_sym_tune_candidate(nb):
+    best = nb.nbody_tune(40000, "fp32c")
+    assert best["pairs"] in (1, 2)
