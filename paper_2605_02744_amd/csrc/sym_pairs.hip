@@ -15,10 +15,12 @@
 //   * the i-side terms stay in the lane; the j-side terms of a step (both i of
 //     the lane summed first) belong to the lane that met that j at step 0 and
 //     move there through a row rotation (DPP row_ror) fused into the add;
-//   * after a sub-block each lane stores its 16-step j-side sum per row in LDS;
-//     after the tile the 16 row sums of each j are added in row order and the
-//     tile's sum is written to a per-distance slot in HBM; a reduction kernel
-//     adds the slots in a fixed order in FP64, so results are reproducible;
+//   * after a sub-block the four rows of a wave hold j-side sums for the same
+//     16 j; they are added across rows on the LDS pipe (swizzle, permute) and
+//     stored per wave; after the tile the 4 wave sums of each j are added in
+//     wave order and the tile's sum is written to a per-distance slot in HBM; a
+//     reduction kernel adds the slots in a fixed order in FP64, so results are
+//     reproducible;
 //   * block pairs are visited once on a half ring: I-block g meets the J-blocks
 //     g + d (mod nb) for d = 1 .. nb/2 (d = nb/2 only for g < nb/2 when nb is
 //     even); d = 0 is the block with itself, evaluated in the ordered form (the
@@ -37,8 +39,8 @@ constexpr int kSL = 256;            // lanes per workgroup
 constexpr int kSI = 2 * kSL;        // particles per I-block / J-block
 constexpr int kST = 64;             // j-particles per LDS tile
 constexpr int kSR = 16;             // lanes per row = records per sub-block
-constexpr int kSRows = kSL / kSR;   // rows per workgroup
 constexpr int kSTiles = kSI / kST;  // tiles per J-block
+constexpr int kSW = kSL / 64;       // waves per workgroup
 
 // v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
 template <int K>
@@ -59,6 +61,8 @@ struct SymArgs {
   int nparts;       // workgroups per I-block in this chunk
   double eps;
   float fx;         // repair-radius factor max(kNearX, kNearN n^-1/3)
+  const float4* rhi;  // [npad] staged j-records: (x, y, z, m) rounded to FP32
+  const float4* rlo;  // [npad] (x, y, z) lo parts and the repair radius^2 (-1 for padding)
   float* pj;        // [D][3][npad] j-side tile sums of the chunk's distances
   double* pi;       // [nparts][3][npad] i-side sums of the chunk's workgroups
 };
@@ -83,8 +87,8 @@ struct ISet {
 // One step of a sub-block: both i of the lane against record (r + K).
 template <int K, bool NEAR>
 __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
-                                         float (&py)[2], float (&pz)[2], float& r2min, float& ajx, float& ajy,
-                                         float& ajz) {
+                                         float (&py)[2], float (&pz)[2], float (&r2min)[2], float& ajx,
+                                         float& ajy, float& ajz) {
   const float4 r = rowp[K];
   float tx = 0.f, ty = 0.f, tz = 0.f;
 #pragma unroll
@@ -97,7 +101,7 @@ __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict
     px[u] = fmaf(si, dx, px[u]);
     py[u] = fmaf(si, dy, py[u]);
     pz[u] = fmaf(si, dz, pz[u]);
-    if constexpr (NEAR) r2min = fminf(r2min, r2);
+    if constexpr (NEAR) r2min[u] = fminf(r2min[u], r2);
     const float sj = s.mneg[u] * ri3;
     if (u == 0) { tx = sj * dx; ty = sj * dy; tz = sj * dz; }
     else { tx = fmaf(sj, dx, tx); ty = fmaf(sj, dy, ty); tz = fmaf(sj, dz, tz); }
@@ -114,48 +118,33 @@ __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict
 
 template <bool NEAR, int... K>
 __device__ __forceinline__ void sym_sub(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
-                                        float (&py)[2], float (&pz)[2], float& r2min, float& ajx, float& ajy,
-                                        float& ajz, std::integer_sequence<int, K...>) {
+                                        float (&py)[2], float (&pz)[2], float (&r2min)[2], float& ajx,
+                                        float& ajy, float& ajz, std::integer_sequence<int, K...>) {
   (sym_step<K, NEAR>(s, rowp, e2, px, py, pz, r2min, ajx, ajy, ajz), ...);
 }
 
 // Loads the two i of lane t of I-block g (padding i: far away and massless, so
-// they add nothing to any j); thr = the larger of the two radii^2 that flag a
-// tile for the repair, -1 for padding.  PAIR: radii that also hold every pair
+// they add nothing to any j) and, per i, the squared radius that flags a tile
+// for the repair (-1 for padding).  PAIR: radii that also hold every pair
 // inside the j's own repair radius, since the pair serves both particles:
 // |d| < f |x_j| with |x_j| <= |x_i| + |d| gives |d| < f / (1 - f) |x_i| (f is at
 // most 1/2; the eps term is the same for both particles).
 template <bool PAIR>
-__device__ __forceinline__ void load_iset(const SymArgs& A, int g, int t, ISet& s, float& thr) {
-  thr = -1.f;
+__device__ __forceinline__ void load_iset(const SymArgs& A, int g, int t, ISet& s, float (&thr)[2]) {
   const int n = A.n;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int i = g * kSI + u * kSL + t;
+    thr[u] = -1.f;
     if (i < n) {
       const double xa = A.x[i], ya = A.x[n + i], za = A.x[2 * n + i];
       s.x[u] = (float)xa; s.y[u] = (float)ya; s.z[u] = (float)za;
       s.mneg[u] = -(float)A.m[i];
-      thr = fmaxf(thr, sym_rc2(xa, ya, za, A.eps, PAIR ? A.fx / (1.0f - A.fx) * 1.0001f : A.fx));
+      thr[u] = sym_rc2(xa, ya, za, A.eps, PAIR ? A.fx / (1.0f - A.fx) * 1.0001f : A.fx);
     } else {
       s.x[u] = s.y[u] = s.z[u] = (float)kFarAway;
       s.mneg[u] = 0.f;
     }
-  }
-}
-
-// j-record of particle j (padding past n: far away, massless, never repaired).
-template <bool NEAR>
-__device__ __forceinline__ void load_jrec(const SymArgs& A, int j, float4& hi, float4& lo) {
-  const int n = A.n;
-  if (j < n) {
-    const double xa = A.x[j], ya = A.x[n + j], za = A.x[2 * n + j];
-    hi = make_float4((float)xa, (float)ya, (float)za, (float)A.m[j]);
-    lo = make_float4((float)(xa - (double)hi.x), (float)(ya - (double)hi.y), (float)(za - (double)hi.z),
-                     NEAR ? sym_rc2(xa, ya, za, A.eps, A.fx) : -1.f);
-  } else {
-    hi = make_float4((float)kFarAway, (float)kFarAway, (float)kFarAway, 0.f);
-    lo = make_float4(0.f, 0.f, 0.f, -1.f);
   }
 }
 
@@ -173,17 +162,100 @@ __device__ __forceinline__ void near_delta(float dx, float dy, float dz, float r
   fz = fmaf(qi3, ez, -(ri3 * dz));
 }
 
+// The j-records of all npad particles (padding past n: far away, massless,
+// never repaired), converted once per evaluation so that the force kernel's
+// tiles are plain 16-byte copies.
+template <bool NEAR>
+__global__ void sym_stage_kernel(SymArgs A, float4* __restrict__ rhi, float4* __restrict__ rlo) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.npad) return;
+  float4 hi, lo;
+  const int n = A.n;
+  if (j < n) {
+    const double xa = A.x[j], ya = A.x[n + j], za = A.x[2 * n + j];
+    hi = make_float4((float)xa, (float)ya, (float)za, (float)A.m[j]);
+    lo = make_float4((float)(xa - (double)hi.x), (float)(ya - (double)hi.y), (float)(za - (double)hi.z),
+                     NEAR ? sym_rc2(xa, ya, za, A.eps, A.fx) : -1.f);
+  } else {
+    hi = make_float4((float)kFarAway, (float)kFarAway, (float)kFarAway, 0.f);
+    lo = make_float4(0.f, 0.f, 0.f, -1.f);
+  }
+  rhi[j] = hi;
+  rlo[j] = lo;
+}
+
+using lds_ptr = __attribute__((address_space(3))) void*;
+
+struct P6 {
+  float x0, x1, y0, y1, z0, z1;
+};
+
+// Near-field repair of one lane's tile (FP32C): for every pair of the lane's
+// two i with the tile's 64 j closer than the larger repair radius of its two
+// particles, the rounded-position term is replaced by the float-float one: in
+// the lane's i-side sums p (returned) and in the wave's j-side sums of the tile
+// (part: the wave's slots, components kSW * kST apart).  The j are visited in
+// the rotated order of the pair loop, so at each step the lanes of a row touch
+// distinct j; the four rows of the wave, which share the slots, take turns.
+__device__ __forceinline__ P6 sym_repair(const double* __restrict__ x, int n, double eps, float fx, int g, int t, int rl,
+                                         float e2, ISet s, P6 p, const float4* hi, const float4* lo, float* part) {
+  const int wrow = (t & 63) / kSR;
+  float px[2] = {p.x0, p.x1}, py[2] = {p.y0, p.y1}, pz[2] = {p.z0, p.z1};
+  float rc[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = g * kSI + u * kSL + t;
+    rc[u] = i < n ? sym_rc2(x[i], x[n + i], x[2 * n + i], eps, fx) : -1.f;
+  }
+  for (int jj = 0; jj < kST; ++jj) {
+    const int q = jj / kSR;
+    const int jl = q * kSR + ((rl + jj) & (kSR - 1));
+    const float4 rh = hi[q * 2 * kSR + (jl % kSR)];
+    const float4 rl4 = lo[jl];
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float dx = rh.x - s.x[u], dy = rh.y - s.y[u], dz = rh.z - s.z[u];
+      const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+      if (rc[u] >= 0.f && r2 < fmaxf(rc[u], rl4.w)) {
+        const int i = g * kSI + u * kSL + t;
+        const double xa = x[i], ya = x[n + i], za = x[2 * n + i];
+        const float ex = dx + (rl4.x - (float)(xa - (double)s.x[u]));
+        const float ey = dy + (rl4.y - (float)(ya - (double)s.y[u]));
+        const float ez = dz + (rl4.z - (float)(za - (double)s.z[u]));
+        float fx3, fy3, fz3;
+        near_delta(dx, dy, dz, r2, ex, ey, ez, e2, fx3, fy3, fz3);
+        px[u] = fmaf(rh.w, fx3, px[u]);
+        py[u] = fmaf(rh.w, fy3, py[u]);
+        pz[u] = fmaf(rh.w, fz3, pz[u]);
+        cx = fmaf(s.mneg[u], fx3, cx);
+        cy = fmaf(s.mneg[u], fy3, cy);
+        cz = fmaf(s.mneg[u], fz3, cz);
+      }
+    }
+    for (int r = 0; r < 4; ++r) {
+      if (wrow == r && (cx != 0.f || cy != 0.f || cz != 0.f)) {
+        part[jl] += cx;
+        part[kSW * kST + jl] += cy;
+        part[2 * kSW * kST + jl] += cz;
+      }
+    }
+  }
+  return P6{px[0], px[1], py[0], py[1], pz[0], pz[1]};
+}
+
 // Grid: nb * nparts workgroups; workgroup (g, part) takes the distances
 // [d_lo + part L, d_lo + (part + 1) L) of I-block g's half ring (d >= 1).
 template <bool NEAR>
-__global__ __launch_bounds__(kSL, 8) void sym_accel_kernel(SymArgs A) {
+__global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   __shared__ float4 s_hi[2][4][2 * kSR];  // (x, y, z, m) hi parts, each sub-block twice
   __shared__ float4 s_lo[2][kST];         // (x, y, z) lo parts and the repair radius^2 of j
-  __shared__ float s_part[3][kSRows][kST];
+  __shared__ float s_part[3][kSW][kST];
+  __shared__ float s_acc_lo[6][kSL];      // the lo halves of the i-side (hi, lo) sums
 
   const int t = threadIdx.x;
   const int rl = t & (kSR - 1);
-  const int row = t / kSR;
+  const int wave = t / 64;
   const int g = blockIdx.x % A.nb;
   const int part = blockIdx.x / A.nb;
   const int dbeg = A.d_lo + part * A.L;
@@ -193,104 +265,97 @@ __global__ __launch_bounds__(kSL, 8) void sym_accel_kernel(SymArgs A) {
   const float e2 = (float)(A.eps * A.eps);
 
   ISet s;
-  float thr;
+  float thr[2];
   load_iset<true>(A, g, t, s, thr);
   float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
-  float lx[2] = {0.f, 0.f}, ly[2] = {0.f, 0.f}, lz[2] = {0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s_acc_lo[c][t] = 0.f;
+  // lane address for the exchange across the two halves of a wave
+  const int xor32 = ((t & 63) ^ 32) * 4;
 
-  // the last wave stages tile k of the workgroup into LDS buffer b
+  // the last wave copies tile k's staged records into LDS buffer b, straight
+  // from global memory to LDS (no registers held): one 16-byte record per lane
+  // and copy, lanes in order.  Lanes 0-15 and 16-31 both fetch the first
+  // sub-block of a pair, lanes 32-47 and 48-63 the second, which lays each
+  // sub-block out twice in a row; a third copy fetches the lo records.
+  // per-lane byte offsets within a tile (the tile's base is uniform)
+  const unsigned lane_hi = (unsigned)((((t & 63) >> 5) * kSR + (t & (kSR - 1))) * sizeof(float4));
+  const unsigned lane_lo = (unsigned)((t & 63) * sizeof(float4));
   auto stage = [&](int k, int b) {
-    const int jl = t - 3 * 64;
-    const int J = (g + dbeg + k / kSTiles) % A.nb;
-    float4 hi, lo;
-    load_jrec<NEAR>(A, J * kSI + (k % kSTiles) * kST + jl, hi, lo);
-    s_hi[b][jl / kSR][jl % kSR] = hi;
-    s_hi[b][jl / kSR][kSR + jl % kSR] = hi;
-    s_lo[b][jl] = lo;
+    // the tile's first record, kept scalar (an address in VGPR pairs would cost
+    // registers the pair loop needs)
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + dbeg + k / kSTiles) % A.nb) * kSI + (k % kSTiles) * kST);
+    const size_t base = (size_t)rec0 * sizeof(float4);
+    const char* hb = reinterpret_cast<const char*>(A.rhi) + base;
+    const char* lb = reinterpret_cast<const char*>(A.rlo) + base;
+    // the lane offsets enter each address afresh (an empty asm statement hides
+    // them from loop-invariant hoisting), so that every copy takes the form
+    // scalar base + 32-bit lane offset instead of a 64-bit per-lane pointer
+    unsigned oh = lane_hi, ol = lane_lo;
+    asm volatile("" : "+v"(oh), "+v"(ol));
+    __builtin_amdgcn_global_load_lds(hb + oh, (lds_ptr)&s_hi[b][0][0], 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(hb + 2 * kSR * sizeof(float4) + oh, (lds_ptr)&s_hi[b][2][0], 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(lb + ol, (lds_ptr)&s_lo[b][0], 16, 0, 0);
   };
 
-  if (ntiles > 0 && t >= 3 * 64) stage(0, 0);
+  if (ntiles > 0 && t >= 3 * 64) {
+    stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
   __syncthreads();
 
   for (int k = 0; k < ntiles; ++k) {
     const int b = k & 1;
     const int d = dbeg + k / kSTiles;
     const int tt = k % kSTiles;
+    // the next tile's records travel while this one is evaluated (buffer b ^ 1
+    // was last read in tile k - 1, before the barrier that ended it)
+    if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
     float px[2] = {0.f, 0.f}, py[2] = {0.f, 0.f}, pz[2] = {0.f, 0.f};
-    float r2min = 3.0e38f;
+    float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
       float ajx = 0.f, ajy = 0.f, ajz = 0.f;
       sym_sub<NEAR>(s, &s_hi[b][q][rl], e2, px, py, pz, r2min, ajx, ajy, ajz, std::make_integer_sequence<int, kSR>{});
-      s_part[0][row][q * kSR + rl] = ajx;
-      s_part[1][row][q * kSR + rl] = ajy;
-      s_part[2][row][q * kSR + rl] = ajz;
+      // the four rows' sums of the same 16 j: rows (0 + 1) and (2 + 3) by a
+      // swizzle, then the two halves by a permute, after which all four rows
+      // hold the same totals and store the same values (no branch in the loop)
+      ajx += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajx), 0x401F));
+      ajy += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajy), 0x401F));
+      ajz += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajz), 0x401F));
+      ajx += __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajx)));
+      ajy += __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajy)));
+      ajz += __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajz)));
+      s_part[0][wave][q * kSR + rl] = ajx;
+      s_part[1][wave][q * kSR + rl] = ajy;
+      s_part[2][wave][q * kSR + rl] = ajz;
     }
     if constexpr (NEAR) {
       // rare: a pair of this tile may be closer than the larger repair radius
-      // of its two particles: replace the rounded-position term of every such
-      // pair by the float-float one, for i here and for j in the tile's row sums
-      if (r2min < thr) {
-        float rc[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int i = g * kSI + u * kSL + t;
-          rc[u] = i < n ? sym_rc2(A.x[i], A.x[n + i], A.x[2 * n + i], A.eps, A.fx) : -1.f;
-        }
-#pragma unroll 1
-        for (int jj = 0; jj < kST; ++jj) {
-          // in the rotated order of the main loop: at each step the lanes of a
-          // row touch distinct j, so the row-sum updates below never collide
-          const int q = jj / kSR;
-          const int jl = q * kSR + ((rl + jj) & (kSR - 1));
-          const float4 rh = s_hi[b][q][jl % kSR];
-          const float4 lo = s_lo[b][jl];
-          float cx = 0.f, cy = 0.f, cz = 0.f;
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const float dx = rh.x - s.x[u], dy = rh.y - s.y[u], dz = rh.z - s.z[u];
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
-            if (rc[u] >= 0.f && r2 < fmaxf(rc[u], lo.w)) {
-              const int i = g * kSI + u * kSL + t;
-              const double xa = A.x[i], ya = A.x[n + i], za = A.x[2 * n + i];
-              const float ex = dx + (lo.x - (float)(xa - (double)s.x[u]));
-              const float ey = dy + (lo.y - (float)(ya - (double)s.y[u]));
-              const float ez = dz + (lo.z - (float)(za - (double)s.z[u]));
-              float fx, fy, fz;
-              near_delta(dx, dy, dz, r2, ex, ey, ez, e2, fx, fy, fz);
-              px[u] = fmaf(rh.w, fx, px[u]);
-              py[u] = fmaf(rh.w, fy, py[u]);
-              pz[u] = fmaf(rh.w, fz, pz[u]);
-              cx = fmaf(s.mneg[u], fx, cx);
-              cy = fmaf(s.mneg[u], fy, cy);
-              cz = fmaf(s.mneg[u], fz, cz);
-            }
-          }
-          if (cx != 0.f || cy != 0.f || cz != 0.f) {
-            s_part[0][row][jl] += cx;
-            s_part[1][row][jl] += cy;
-            s_part[2][row][jl] += cz;
-          }
-        }
+      // of its two particles
+      if (r2min[0] < thr[0] || r2min[1] < thr[1]) {
+        const P6 r = sym_repair(A.x, n, A.eps, A.fx, g, t, rl, e2, s, P6{px[0], px[1], py[0], py[1], pz[0], pz[1]},
+                                &s_hi[b][0][0], &s_lo[b][0], &s_part[0][wave][0]);
+        px[0] = r.x0; px[1] = r.x1; py[0] = r.y0; py[1] = r.y1; pz[0] = r.z0; pz[1] = r.z1;
       }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      fold(hx[u], lx[u], px[u]);
-      fold(hy[u], ly[u], py[u]);
-      fold(hz[u], lz[u], pz[u]);
+      fold(hx[u], s_acc_lo[3 * u][t], px[u]);
+      fold(hy[u], s_acc_lo[3 * u + 1][t], py[u]);
+      fold(hz[u], s_acc_lo[3 * u + 2][t], pz[u]);
     }
     __syncthreads();
     if (t < 3 * 64) {
-      // the tile's j-side sums: the 16 row sums of each j, in row order
+      // the tile's j-side sums: the 4 wave sums of each j, in wave order
       const int c = t / kST, jl = t % kST;
       float v = 0.f;
 #pragma unroll
-      for (int r = 0; r < kSRows; ++r) v += s_part[c][r][jl];
+      for (int w = 0; w < kSW; ++w) v += s_part[c][w][jl];
       const int J = (g + d) % A.nb;
       A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + (size_t)J * kSI + tt * kST + jl] = v;
-    } else if (k + 1 < ntiles) {
-      stage(k + 1, b ^ 1);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);  // the next tile's copies have landed in LDS
     }
     __syncthreads();
   }
@@ -300,9 +365,9 @@ __global__ __launch_bounds__(kSL, 8) void sym_accel_kernel(SymArgs A) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const size_t i = (size_t)g * kSI + u * kSL + t;
-    o[i] = (double)hx[u] + (double)lx[u];
-    o[A.npad + i] = (double)hy[u] + (double)ly[u];
-    o[2 * (size_t)A.npad + i] = (double)hz[u] + (double)lz[u];
+    o[i] = (double)hx[u] + (double)s_acc_lo[3 * u][t];
+    o[A.npad + i] = (double)hy[u] + (double)s_acc_lo[3 * u + 1][t];
+    o[2 * (size_t)A.npad + i] = (double)hz[u] + (double)s_acc_lo[3 * u + 2][t];
   }
 }
 
@@ -318,10 +383,13 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
   const int g = blockIdx.x;
   const float e2 = (float)(A.eps * A.eps);
   ISet s;
-  float thr;
+  float thr[2];
   load_iset<false>(A, g, t, s, thr);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) load_jrec<NEAR>(A, g * kSI + u * kSL + t, s_hi[u * kSL + t], s_lo[u * kSL + t]);
+  for (int u = 0; u < 2; ++u) {
+    s_hi[u * kSL + t] = A.rhi[(size_t)g * kSI + u * kSL + t];
+    s_lo[u * kSL + t] = A.rlo[(size_t)g * kSI + u * kSL + t];
+  }
   __syncthreads();
   float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
   float lx[2] = {0.f, 0.f}, ly[2] = {0.f, 0.f}, lz[2] = {0.f, 0.f};
@@ -331,7 +399,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
 #pragma unroll 1
   for (int f = 0; f < kSI; f += kFold) {
     float px[2] = {0.f, 0.f}, py[2] = {0.f, 0.f}, pz[2] = {0.f, 0.f};
-    float r2min = 3.0e38f;
+    float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 16
     for (int j = f; j < f + kFold; ++j) {
       const float4 r = s_hi[j];
@@ -345,11 +413,11 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
         px[u] = fmaf(si, dx, px[u]);
         py[u] = fmaf(si, dy, py[u]);
         pz[u] = fmaf(si, dz, pz[u]);
-        if constexpr (NEAR) r2min = fminf(r2min, r2);
+        if constexpr (NEAR) r2min[u] = fminf(r2min[u], r2);
       }
     }
     if constexpr (NEAR) {
-      if (r2min < thr) {
+      if (r2min[0] < thr[0] || r2min[1] < thr[1]) {
         for (int j = f; j < f + kFold; ++j) {
           const float4 rh = s_hi[j];
           const float4 lo = s_lo[j];
@@ -445,7 +513,8 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const size_t pj_bytes = sizeof(float) * 3 * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
   const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
-  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes, &st));
+  const size_t rec_bytes = sizeof(float4) * (size_t)npad;
+  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes, &st));
   if (!ws) return st;
   SymArgs A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
@@ -454,7 +523,15 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   A.pj = reinterpret_cast<float*>(ws);
   A.pi = reinterpret_cast<double*>(ws + pj_bytes);
   double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);
+  float4* rhi = reinterpret_cast<float4*>(ws + pj_bytes + pi_bytes + pd_bytes);
+  float4* rlo = rhi + npad;
+  A.rhi = rhi;
+  A.rlo = rlo;
   const bool near = precision == kFP32C;
+  const unsigned sg = (unsigned)((npad + 255) / 256);
+  if (near) sym_stage_kernel<true><<<sg, 256, 0, s>>>(A, rhi, rlo);
+  else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo);
+  NB_LAUNCH_CHECK("sym_stage_kernel");
   if (near) {
     if (excl) sym_diag_kernel<true, true><<<nb, kSL, 0, s>>>(A, pd);
     else sym_diag_kernel<true, false><<<nb, kSL, 0, s>>>(A, pd);
