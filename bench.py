@@ -695,6 +695,8 @@ def main():
     ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
     ap.add_argument("--tune-cache", default=None, help="with --tune: JSON-lines file the tuner appends its choice to")
     ap.add_argument("--bitem", type=int, default=0, help="streamed ensemble: most particles per item (0 = auto)")
+    ap.add_argument("--pairs", type=int, default=0, choices=[0, 1, 2],
+                    help="FP32C/FP32 force kernel: 1 ordered, 2 symmetric (each unordered pair once), 0 automatic")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -712,7 +714,11 @@ def main():
     fn = {"twocomp1m_force": bench_force, "plummer64k_fp32c": bench_kdk64k, "ensemble512": bench_ensemble,
           "grad16k": bench_grad, "copy256m": bench_copy, "plummer1k_fp64": bench_kdk1k,
           "jerk1m": bench_jerk, "hermite6_409600": bench_hermite6}[args.workload]
+    if args.pairs:
+        nb.nbody_set_config(pairs=args.pairs)
     res = fn(args, torch, nb)
+    if args.pairs:
+        res.setdefault("config", {})["pairs"] = args.pairs
     print(json.dumps(res), flush=True)
 
 

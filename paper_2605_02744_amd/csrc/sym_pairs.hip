@@ -456,7 +456,9 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
 // Adds the chunk's slots into a: the j-side tile sums of distances
 // d_lo .. d_lo + D - 1 that were evaluated, then the i-side sums of the
 // chunk's workgroups; the first chunk starts from the distance-0 sums pd, the
-// last applies G.  One thread per (particle, component), fixed order.
+// last applies G.  One thread per (particle, component), fixed order.  Only
+// the largest distance can be missing for some blocks (the opposite block of
+// an even ring, visited from the lower half only).
 __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
                                   const float* __restrict__ pj, const double* __restrict__ pi,
                                   const double* __restrict__ pd, double* __restrict__ a, double G, int first,
@@ -466,13 +468,21 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
   if (p >= n) return;
   const int J = p / kSI;
   double acc = first ? pd[(size_t)c * npad + p] : a[(size_t)c * n + p];
-  for (int s = 0; s < D; ++s) {
-    const int d = d_lo + s;
-    if (d > dmax) break;
-    const int g = ((J - d) % nb + nb) % nb;
-    if (half && d == dmax && g >= nb / 2) continue;
-    acc += (double)pj[((size_t)s * 3 + c) * npad + p];
+  const int send = min(D, dmax - d_lo + 1);  // slots of this chunk within the ring
+  // the last slot of the ring is dropped where its block pair was not evaluated
+  const bool drop_last = half && d_lo + send - 1 == dmax && ((J - dmax) % nb + nb) % nb >= nb / 2;
+  const int sn = drop_last ? send - 1 : send;
+  const float* q = pj + (size_t)c * npad + p;
+  const size_t stride = (size_t)3 * npad;
+  int s = 0;
+  for (; s + 4 <= sn; s += 4) {
+    const float v0 = q[s * stride], v1 = q[(s + 1) * stride], v2 = q[(s + 2) * stride], v3 = q[(s + 3) * stride];
+    acc += (double)v0;
+    acc += (double)v1;
+    acc += (double)v2;
+    acc += (double)v3;
   }
+  for (; s < sn; ++s) acc += (double)q[s * stride];
   for (int k = 0; k < nparts; ++k) acc += pi[((size_t)k * 3 + c) * npad + p];
   a[(size_t)c * n + p] = last ? G * acc : acc;
 }
