@@ -85,9 +85,14 @@ typedef struct nbody_params {
 
 /* Accelerations a (3*n) of particles at x (3*n) with masses m (n).
  * Eq. (1) of Sec. 2.1 divided by m_i, softened as in App. A.
+ * FP32C and FP32 from 32768 particles on (or as nbody_config.pairs says)
+ * evaluate each unordered pair once and apply it to both particles, with
+ * sums in a fixed order; this uses a workspace of up to about 1.5 GiB
+ * (staged records and per-distance sums) and several launches per call.
  * n == 0 is a no-op.  x, m, a must not alias.  Errors: NBODY_EINVAL for null
- * pointers with n > 0, n < 0, n > 2^31 - 1024, eps < 0, eps == 0 without
- * NBODY_EXCLUDE_SELF, non-finite G, unknown precision. */
+ * pointers with n > 0, n < 0, n > 2^29, eps < 0, eps == 0 without
+ * NBODY_EXCLUDE_SELF, non-finite G, unknown precision; NBODY_ENOMEM if the
+ * workspace cannot grow. */
 int nbody_accel(int64_t n, const double* x, const double* m, double* a,
                 const nbody_params* p, void* stream);
 
