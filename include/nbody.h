@@ -280,7 +280,7 @@ typedef struct nbody_config {
                       unordered pair evaluated once and applied to both particles
                       (a_j gets the opposite of i's term scaled by m_i / m_j),
                       results summed in a fixed order (reproducible), at the cost
-                      of a workspace of about 1 GiB for large n and an FP32 sum
+                      of a workspace of about 1.5 GiB for large n and an FP32 sum
                       of up to 512 terms per j before the FP64 sums */
 } nbody_config;
 
