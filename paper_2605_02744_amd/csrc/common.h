@@ -70,6 +70,10 @@ int launch_accel(int64_t n, const double* x, const double* m, double* a, double 
 int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
                      bool exclude_self, int launches, hipStream_t s);
 
+// The same VJP from the symmetric kernel (FP32C or FP32; launches as above).
+int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
+                   double eps, int precision, bool exclude_self, int launches, hipStream_t s);
+
 // (da/dx)^T w into gx and (da/dm)^T w into gm.
 int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx,
                double* gm, double G, double eps, int precision, bool exclude_self,

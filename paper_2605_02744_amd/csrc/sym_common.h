@@ -1,0 +1,118 @@
+// Definitions shared by the symmetric all-pairs kernels (sym_pairs.hip: the
+// acceleration; sym_vjp.hip: its vector-Jacobian product): block and tile
+// sizes, the in-row rotation, the kernel arguments, the half ring of block
+// pairs and the slot sums.  Each unordered pair {i, j} is evaluated once and
+// its term applied to both particles; the layout is described in sym_pairs.hip.
+#pragma once
+
+#include "pair_math.h"
+
+namespace nb {
+namespace {
+
+constexpr int kSL = 256;            // lanes per workgroup
+constexpr int kSI = 2 * kSL;        // particles per I-block / J-block
+constexpr int kST = 64;             // j-particles per LDS tile
+constexpr int kSR = 16;             // lanes per row = records per sub-block
+constexpr int kSTiles = kSI / kST;  // tiles per J-block
+constexpr int kSW = kSL / 64;       // waves per workgroup
+
+// v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
+template <int K>
+__device__ __forceinline__ float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xF, 0xF, true));
+}
+
+struct SymArgs {
+  const double* x;  // [3][n]
+  const double* m;  // [n]
+  int n;
+  int nb;           // blocks of kSI particles
+  int npad;         // nb * kSI
+  int dmax;         // largest ring distance
+  int half;         // nb even: distance dmax only for g < nb / 2
+  int d_lo;         // first distance of this chunk
+  int L;            // distances per workgroup
+  int nparts;       // workgroups per I-block in this chunk
+  double eps;
+  float fx;         // repair-radius factor max(kNearX, kNearN n^-1/3)
+  const float4* rhi;  // [npad] staged j-records: (x, y, z, m) rounded to FP32
+  const float4* rlo;  // [npad] (x, y, z) lo parts and the repair radius^2 (-1 for padding)
+  const double* w;  // [3][n] cotangent (VJP only)
+  const float4* rw; // [npad] staged cotangents (VJP only)
+  float* pj;        // [D][C][npad] j-side tile sums of the chunk's distances (C = 3, or 4 for the VJP)
+  double* pi;       // [nparts][C][npad] i-side sums of the chunk's workgroups
+};
+
+// Largest valid distance + 1 for I-block g.
+__device__ __forceinline__ int ring_end(const SymArgs& A, int g) {
+  return (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1;
+}
+
+// Squared repair radius (the near-field rule of the ordered kernel, with its
+// n-dependent factor f given): a pair closer than max(f |x|_inf, kNearEps eps)
+// to the particle at (xa, ya, za) gets float-float displacements.
+__device__ __forceinline__ float sym_rc2(double xa, double ya, double za, double eps, float f) {
+  const float dc = fmaxf(f * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
+  return dc * dc + (float)(eps * eps);
+}
+
+using lds_ptr = __attribute__((address_space(3))) void*;
+
+// Adds the chunk's slots into the outputs (component c < 3 at out[c n + p],
+// component 3 at outm[p]): the j-side tile sums of distances d_lo .. d_lo + D - 1
+// that were evaluated, then the i-side sums of the chunk's workgroups; the
+// first chunk starts from the distance-0 sums pd, the last applies G.  One
+// thread per (particle, component), fixed order.  Only the largest distance
+// can be missing for some blocks (the opposite block of an even ring, visited
+// from the lower half only).
+template <int C>
+__global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
+                                  const float* __restrict__ pj, const double* __restrict__ pi,
+                                  const double* __restrict__ pd, double* __restrict__ out, double* __restrict__ outm,
+                                  double G, int first, int last) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (p >= n) return;
+  double* o = c < 3 ? out + (size_t)c * n + p : outm + p;
+  const int J = p / kSI;
+  double acc = first ? pd[(size_t)c * npad + p] : *o;
+  const int send = min(D, dmax - d_lo + 1);  // slots of this chunk within the ring
+  // the last slot of the ring is dropped where its block pair was not evaluated
+  const bool drop_last = half && d_lo + send - 1 == dmax && ((J - dmax) % nb + nb) % nb >= nb / 2;
+  const int sn = drop_last ? send - 1 : send;
+  const float* q = pj + (size_t)c * npad + p;
+  const size_t stride = (size_t)C * npad;
+  int s = 0;
+  for (; s + 4 <= sn; s += 4) {
+    const float v0 = q[s * stride], v1 = q[(s + 1) * stride], v2 = q[(s + 2) * stride], v3 = q[(s + 3) * stride];
+    acc += (double)v0;
+    acc += (double)v1;
+    acc += (double)v2;
+    acc += (double)v3;
+  }
+  for (; s < sn; ++s) acc += (double)q[s * stride];
+  for (int k = 0; k < nparts; ++k) acc += pi[((size_t)k * C + c) * npad + p];
+  *o = last ? G * acc : acc;
+}
+
+}  // namespace
+
+// Chunking of the half ring for n particles with C components per slot:
+// distances per workgroup (L) and per launch (D), the slots of a launch kept
+// near 1 GiB; launches > 0 asks for at least that many launches.
+inline void sym_plan(int64_t n, int launches, int C, int* nb_out, int* L_out, int* D_out) {
+  const int nb = (int)((n + kSI - 1) / kSI);
+  const int dmax = nb / 2;
+  const int64_t npad = (int64_t)nb * kSI;
+  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (4 * C * npad));
+  if (launches > 0) dcap = std::min<int64_t>(dcap, std::max(1, (dmax + launches - 1) / launches));
+  const int d0 = (int)std::max<int64_t>(1, std::min<int64_t>(dmax, dcap));
+  // at least ~4096 workgroups per launch (several rounds of 7 per CU), at most 16 distances each
+  const int L = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(16, d0), (int64_t)nb * d0 / 4096));
+  *nb_out = nb;
+  *L_out = L;
+  *D_out = (d0 + L - 1) / L * L;
+}
+
+}  // namespace nb

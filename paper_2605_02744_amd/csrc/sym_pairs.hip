@@ -30,55 +30,10 @@
 // FP32C (positions rounded to FP32 plus the near-field repair of the ordered
 // kernel: pairs closer than the larger repair radius of their two particles get
 // float-float displacements, for both sides) and FP32 (no repair) are built.
-#include "pair_math.h"
+#include "sym_common.h"
 
 namespace nb {
 namespace {
-
-constexpr int kSL = 256;            // lanes per workgroup
-constexpr int kSI = 2 * kSL;        // particles per I-block / J-block
-constexpr int kST = 64;             // j-particles per LDS tile
-constexpr int kSR = 16;             // lanes per row = records per sub-block
-constexpr int kSTiles = kSI / kST;  // tiles per J-block
-constexpr int kSW = kSL / 64;       // waves per workgroup
-
-// v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
-template <int K>
-__device__ __forceinline__ float row_ror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xF, 0xF, true));
-}
-
-struct SymArgs {
-  const double* x;  // [3][n]
-  const double* m;  // [n]
-  int n;
-  int nb;           // blocks of kSI particles
-  int npad;         // nb * kSI
-  int dmax;         // largest ring distance
-  int half;         // nb even: distance dmax only for g < nb / 2
-  int d_lo;         // first distance of this chunk
-  int L;            // distances per workgroup
-  int nparts;       // workgroups per I-block in this chunk
-  double eps;
-  float fx;         // repair-radius factor max(kNearX, kNearN n^-1/3)
-  const float4* rhi;  // [npad] staged j-records: (x, y, z, m) rounded to FP32
-  const float4* rlo;  // [npad] (x, y, z) lo parts and the repair radius^2 (-1 for padding)
-  float* pj;        // [D][3][npad] j-side tile sums of the chunk's distances
-  double* pi;       // [nparts][3][npad] i-side sums of the chunk's workgroups
-};
-
-// Largest valid distance + 1 for I-block g.
-__device__ __forceinline__ int ring_end(const SymArgs& A, int g) {
-  return (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1;
-}
-
-// Squared repair radius (the near-field rule of the ordered kernel, with its
-// n-dependent factor f given): a pair closer than max(f |x|_inf, kNearEps eps)
-// to the particle at (xa, ya, za) gets float-float displacements.
-__device__ __forceinline__ float sym_rc2(double xa, double ya, double za, double eps, float f) {
-  const float dc = fmaxf(f * (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za))), kNearEps * (float)eps);
-  return dc * dc + (float)(eps * eps);
-}
 
 struct ISet {
   float x[2], y[2], z[2], mneg[2];
@@ -183,8 +138,6 @@ __global__ void sym_stage_kernel(SymArgs A, float4* __restrict__ rhi, float4* __
   rhi[j] = hi;
   rlo[j] = lo;
 }
-
-using lds_ptr = __attribute__((address_space(3))) void*;
 
 struct P6 {
   float x0, x1, y0, y1, z0, z1;
@@ -453,59 +406,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
   }
 }
 
-// Adds the chunk's slots into a: the j-side tile sums of distances
-// d_lo .. d_lo + D - 1 that were evaluated, then the i-side sums of the
-// chunk's workgroups; the first chunk starts from the distance-0 sums pd, the
-// last applies G.  One thread per (particle, component), fixed order.  Only
-// the largest distance can be missing for some blocks (the opposite block of
-// an even ring, visited from the lower half only).
-__global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
-                                  const float* __restrict__ pj, const double* __restrict__ pi,
-                                  const double* __restrict__ pd, double* __restrict__ a, double G, int first,
-                                  int last) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (p >= n) return;
-  const int J = p / kSI;
-  double acc = first ? pd[(size_t)c * npad + p] : a[(size_t)c * n + p];
-  const int send = min(D, dmax - d_lo + 1);  // slots of this chunk within the ring
-  // the last slot of the ring is dropped where its block pair was not evaluated
-  const bool drop_last = half && d_lo + send - 1 == dmax && ((J - dmax) % nb + nb) % nb >= nb / 2;
-  const int sn = drop_last ? send - 1 : send;
-  const float* q = pj + (size_t)c * npad + p;
-  const size_t stride = (size_t)3 * npad;
-  int s = 0;
-  for (; s + 4 <= sn; s += 4) {
-    const float v0 = q[s * stride], v1 = q[(s + 1) * stride], v2 = q[(s + 2) * stride], v3 = q[(s + 3) * stride];
-    acc += (double)v0;
-    acc += (double)v1;
-    acc += (double)v2;
-    acc += (double)v3;
-  }
-  for (; s < sn; ++s) acc += (double)q[s * stride];
-  for (int k = 0; k < nparts; ++k) acc += pi[((size_t)k * 3 + c) * npad + p];
-  a[(size_t)c * n + p] = last ? G * acc : acc;
-}
-
 }  // namespace
-
-// Chunking of the half ring for n particles: distances per workgroup (L) and
-// per launch (D), bounded by the slot memory; launches > 0 asks for at least
-// that many launches.
-void sym_plan(int64_t n, int launches, int* nb_out, int* L_out, int* D_out) {
-  const int nb = (int)((n + kSI - 1) / kSI);
-  const int dmax = nb / 2;
-  const int64_t npad = (int64_t)nb * kSI;
-  // j-side slots: 12 B per particle per distance; keep a chunk's slots near 1 GiB
-  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (12 * npad));
-  if (launches > 0) dcap = std::min<int64_t>(dcap, std::max(1, (dmax + launches - 1) / launches));
-  const int d0 = (int)std::max<int64_t>(1, std::min<int64_t>(dmax, dcap));
-  // at least ~4096 workgroups per launch (several rounds of 8 per CU), at most 16 distances each
-  const int L = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(16, d0), (int64_t)nb * d0 / 4096));
-  *nb_out = nb;
-  *L_out = L;
-  *D_out = (d0 + L - 1) / L * L;
-}
 
 int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
                      bool excl, int launches, hipStream_t s) {
@@ -514,7 +415,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
     return set_error(NBODY_EUNSUPPORTED, "symmetric pair kernel: FP32C and FP32 only");
   if (n > (int64_t(1) << 30)) return set_error(NBODY_EINVAL, "symmetric pair kernel: n too large");
   int nb, L, D;
-  sym_plan(n, launches, &nb, &L, &D);
+  sym_plan(n, launches, 3, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -552,7 +453,8 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   NB_LAUNCH_CHECK("sym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {
-    sym_reduce_kernel<<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, G, 1, 1);
+    sym_reduce_kernel<3><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, nullptr, G,
+                                            1, 1);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
   }
@@ -563,8 +465,8 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
     if (near) sym_accel_kernel<true><<<grid, kSL, 0, s>>>(A);
     else sym_accel_kernel<false><<<grid, kSL, 0, s>>>(A);
     NB_LAUNCH_CHECK("sym_accel_kernel");
-    sym_reduce_kernel<<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd, a, G,
-                                         c == 0, c == nchunks - 1);
+    sym_reduce_kernel<3><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd, a,
+                                            nullptr, G, c == 0, c == nchunks - 1);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   }
   return NBODY_OK;

@@ -556,22 +556,29 @@ def test_batched_repeat_and_graph_capture(nb):
         assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
 
 
-@pytest.mark.parametrize("kind", ["kdk", "hermite6"])
+@pytest.mark.parametrize("kind", ["kdk", "kdk_sym", "hermite6"])
 def test_single_system_graph_capture(nb, kind):
-    """nbody_step and nbody_step_hermite6 captured into a HIP graph (after one
-    eager call has sized the library's workspace) replay bitwise like eager
-    calls, with eager work and synchronisation between the replays."""
+    """nbody_step (ordered and symmetric force kernels) and nbody_step_hermite6
+    captured into a HIP graph (after one eager call has sized the library's
+    workspace) replay bitwise like eager calls, with eager work and
+    synchronisation between the replays."""
     x, v, m = ics.plummer(3001, seed=19)
     dt = 1.0 / 256
     tm = dev(m)
 
     def state():
         tx, tv = dev(x), dev(v)
-        return [tx, tv] + [torch.empty_like(tx) for _ in range(1 if kind == "kdk" else 4)]
+        return [tx, tv] + [torch.empty_like(tx) for _ in range(1 if kind != "hermite6" else 4)]
 
     def call(st, valid):
         if kind == "kdk":
             nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
+        elif kind == "kdk_sym":
+            nb.nbody_set_config(pairs=2, split=2)  # two half-ring launches per evaluation
+            try:
+                nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
+            finally:
+                nb.nbody_set_config()
         else:
             nb.nbody_step_hermite6(st[0], st[1], *st[2:], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
 

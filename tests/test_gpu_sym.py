@@ -164,3 +164,112 @@ def test_sym_kdk_steps_match_ordered(nb):
 def test_sym_tune_candidate(nb):
     best = nb.nbody_tune(40000, "fp32c")
     assert best["pairs"] in (1, 2)
+
+
+# ---------------------------------------------------------------- VJP
+# (da/dx)^T w and (da/dm)^T w from the symmetric kernel: the pair term changes
+# sign under k <-> j (d and u = m_k w_j - m_j w_k both do), so each unordered
+# pair serves both particles.  Same norm-wise bars as the ordered VJP tests.
+
+VTOL = {"fp32c": 2e-5, "fp32": 2e-4}
+
+
+def sym_vjp(nb, x, m, w, launches=0, **kw):
+    nb.nbody_set_config(pairs=2, split=launches)
+    try:
+        gx, gm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), **kw)
+        return gx.cpu().numpy(), gm.cpu().numpy()
+    finally:
+        nb.nbody_set_config()
+
+
+def vjp_err(g, ref):
+    return np.linalg.norm(g - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n", [2, 511, 513, 1025, 2048, 3001])
+@pytest.mark.parametrize("prec", ["fp32c", "fp32"])
+def test_sym_vjp_matches_oracle(nb, oracle_mod, n, prec):
+    x, _, m = ics.two_component(n, seed=11)
+    w = np.random.default_rng(n).standard_normal((3, n))
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, G=0.7, eps=0.02)
+    print("sym vjp n=%d %s" % (n, prec), flush=True)
+    gx, gm = sym_vjp(nb, x, m, w, G=0.7, eps=0.02, precision=prec)
+    print("  gx %.3e gm %.3e" % (vjp_err(gx, rgx), vjp_err(gm, rgm)))
+    assert vjp_err(gx, rgx) <= VTOL[prec]
+    assert vjp_err(gm, rgm) <= VTOL[prec]
+
+
+@pytest.mark.parametrize("n,launches", [(5000, 3), (9000, 9)])
+def test_sym_vjp_launch_splits(nb, oracle_mod, n, launches):
+    x, _, m = ics.plummer(n, seed=42)
+    w = np.random.default_rng(42).standard_normal((3, n))
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
+    print("sym vjp n=%d launches=%d" % (n, launches), flush=True)
+    gx, gm = sym_vjp(nb, x, m, w, launches=launches, eps=0.01, precision="fp32c")
+    assert vjp_err(gx, rgx) <= VTOL["fp32c"]
+    assert vjp_err(gm, rgm) <= VTOL["fp32c"]
+
+
+def test_sym_vjp_tight_pairs_near_field(nb, oracle_mod):
+    x, _, m = ics.plummer(2000, seed=31)
+    x = x + np.array([[3.0], [-2.0], [5.0]])
+    rng = np.random.default_rng(31)
+    a_idx = rng.choice(1000, 200, replace=False)
+    b_idx = 1000 + np.arange(200)
+    off = rng.standard_normal((3, 200))
+    off *= 10 ** rng.uniform(-5, -3, 200) / np.linalg.norm(off, axis=0)
+    x[:, b_idx] = x[:, a_idx] + off
+    w = np.random.default_rng(2).standard_normal(x.shape)
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
+    gx, gm = sym_vjp(nb, x, m, w, eps=0.01, precision="fp32c")
+    print("sym vjp tight pairs gx %.3e gm %.3e" % (vjp_err(gx, rgx), vjp_err(gm, rgm)))
+    assert vjp_err(gx, rgx) <= VTOL["fp32c"]
+    assert vjp_err(gm, rgm) <= VTOL["fp32c"]
+
+
+def test_sym_vjp_exclude_self_eps_zero(nb, oracle_mod):
+    x, _, m = ics.random_cloud(1500, seed=3)
+    w = np.random.default_rng(5).standard_normal(x.shape)
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.0)
+    gx, gm = sym_vjp(nb, x, m, w, eps=0.0, precision="fp32c", exclude_self=True)
+    assert np.isfinite(gx).all() and np.isfinite(gm).all()
+    assert vjp_err(gx, rgx) <= 10 * VTOL["fp32c"]
+    assert vjp_err(gm, rgm) <= 10 * VTOL["fp32c"]
+
+
+def test_sym_vjp_repeat_bitwise_and_agrees_with_ordered(nb, oracle_mod):
+    x, _, m = ics.two_component(6000, seed=6)
+    w = np.random.default_rng(6).standard_normal((3, 6000))
+    runs = [sym_vjp(nb, x, m, w, launches=2, eps=0.01, precision="fp32c") for _ in range(2)]
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    nb.nbody_set_config(pairs=1)
+    try:
+        ogx, ogm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp32c")
+    finally:
+        nb.nbody_set_config()
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
+    assert vjp_err(runs[0][0], rgx) <= VTOL["fp32c"] and vjp_err(ogx.cpu().numpy(), rgx) <= VTOL["fp32c"]
+    assert vjp_err(runs[0][1], rgm) <= VTOL["fp32c"] and vjp_err(ogm.cpu().numpy(), rgm) <= VTOL["fp32c"]
+
+
+def test_sym_traj_grad_matches_ordered(nb):
+    """The checkpointed adjoint sweep with the symmetric force and VJP gives the
+    ordered kernels' gradient to the FP32C tolerance."""
+    n, steps, every, dt = 3000, 12, 4, 1.0 / 256
+    x, v, m = ics.plummer(n, seed=14)
+    tgt = x + 0.01
+    out = {}
+    for pairs in (1, 2):
+        nb.nbody_set_config(pairs=pairs)
+        try:
+            tx = dev(x).requires_grad_(True)
+            tv = dev(v).requires_grad_(True)
+            tm = dev(m).requires_grad_(True)
+            xT, _ = nb.NBodyTrajectory.apply(tx, tv, tm, dt, steps, every, 1.0, 0.01, "fp32c", None)
+            ((xT - dev(tgt)) ** 2).sum().backward()
+            out[pairs] = (tx.grad.cpu().numpy(), tv.grad.cpu().numpy(), tm.grad.cpu().numpy())
+        finally:
+            nb.nbody_set_config()
+    for a, b in zip(out[1], out[2]):
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a)
