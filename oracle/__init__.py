@@ -47,6 +47,8 @@ def _load():
                                    ctypes.c_double, _I64, _D]
         lib.oracle_energy.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D]
         lib.oracle_accel_vjp.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D, _D]
+        lib.oracle_accel_vjp_rows.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _I64,
+                                              ctypes.POINTER(ctypes.c_int64), _D, _D]
         lib.oracle_accel_jvp.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D]
         lib.oracle_kdk_adjoint.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, _I64, _D, _D, _D, _D, _D]
@@ -158,6 +160,22 @@ def accel_vjp(x, m, w, G=1.0, eps=0.0):
     gx = np.empty((3, n))
     gm = np.empty(n)
     _load().oracle_accel_vjp(n, _p(x), _p(m), _p(w), float(G), float(eps), _p(gx), _p(gm))
+    return gx, gm
+
+
+def accel_vjp_rows(x, m, w, rows, G=1.0, eps=0.0):
+    """The rows ``rows`` of ``accel_vjp`` only: gx (3, len(rows)), gm (len(rows),)."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n))
+    w = _c(w, (3, n))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if rows.size and (rows.min() < 0 or rows.max() >= n):
+        raise ValueError("row index out of range")
+    gx = np.empty((3, rows.size))
+    gm = np.empty(rows.size)
+    _load().oracle_accel_vjp_rows(n, _p(x), _p(m), _p(w), float(G), float(eps), rows.size,
+                                  rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(gx), _p(gm))
     return gx, gm
 
 

@@ -189,32 +189,57 @@ void oracle_energy(int64_t n, const double* x, const double* v, const double* m,
  *   gx_k = G sum_{j != k} K(d_kj) (m_k w_j - m_j w_k)      (d a / d x)^T w
  *   gm_k = -G sum_{j != k} s^-3/2 (d_kj . w_j)              (d a / d m)^T w
  * Both follow from differentiating Eq. (1) / m_i term by term. */
-void oracle_accel_vjp(int64_t n, const double* x, const double* m, const double* w, double G,
-                      double eps, double* gx, double* gm) {
+/* One row k of the VJP: out4 = (gx_k, gy_k, gz_k, gm_k). */
+static void vjp_row(int64_t n, const double* x, const double* m, const double* w, double G, double eps,
+                    int64_t k, double* out4) {
     const double *X = x, *Y = x + n, *Z = x + 2 * n;
     const double *WX = w, *WY = w + n, *WZ = w + 2 * n;
+    nsum gxs = {0, 0}, gys = {0, 0}, gzs = {0, 0}, gms = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == k) continue;
+        double d[3] = {X[j] - X[k], Y[j] - Y[k], Z[j] - Z[k]};
+        double u[3] = {m[k] * WX[j] - m[j] * WX[k], m[k] * WY[j] - m[j] * WY[k],
+                       m[k] * WZ[j] - m[j] * WZ[k]};
+        double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+        double s32 = 1.0 / (s * sqrt(s));
+        double s52 = s32 / s;
+        double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+        nadd(&gxs, s32 * u[0] - 3.0 * s52 * du * d[0]);
+        nadd(&gys, s32 * u[1] - 3.0 * s52 * du * d[1]);
+        nadd(&gzs, s32 * u[2] - 3.0 * s52 * du * d[2]);
+        double dw = d[0] * WX[j] + d[1] * WY[j] + d[2] * WZ[j];
+        nadd(&gms, -s32 * dw);
+    }
+    out4[0] = G * nval(&gxs);
+    out4[1] = G * nval(&gys);
+    out4[2] = G * nval(&gzs);
+    out4[3] = G * nval(&gms);
+}
+
+void oracle_accel_vjp(int64_t n, const double* x, const double* m, const double* w, double G,
+                      double eps, double* gx, double* gm) {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < n; ++k) {
-        nsum gxs = {0, 0}, gys = {0, 0}, gzs = {0, 0}, gms = {0, 0};
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == k) continue;
-            double d[3] = {X[j] - X[k], Y[j] - Y[k], Z[j] - Z[k]};
-            double u[3] = {m[k] * WX[j] - m[j] * WX[k], m[k] * WY[j] - m[j] * WY[k],
-                           m[k] * WZ[j] - m[j] * WZ[k]};
-            double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
-            double s32 = 1.0 / (s * sqrt(s));
-            double s52 = s32 / s;
-            double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
-            nadd(&gxs, s32 * u[0] - 3.0 * s52 * du * d[0]);
-            nadd(&gys, s32 * u[1] - 3.0 * s52 * du * d[1]);
-            nadd(&gzs, s32 * u[2] - 3.0 * s52 * du * d[2]);
-            double dw = d[0] * WX[j] + d[1] * WY[j] + d[2] * WZ[j];
-            nadd(&gms, -s32 * dw);
-        }
-        gx[k] = G * nval(&gxs);
-        gx[n + k] = G * nval(&gys);
-        gx[2 * n + k] = G * nval(&gzs);
-        gm[k] = G * nval(&gms);
+        double o[4];
+        vjp_row(n, x, m, w, G, eps, k, o);
+        gx[k] = o[0];
+        gx[n + k] = o[1];
+        gx[2 * n + k] = o[2];
+        gm[k] = o[3];
+    }
+}
+
+/* The rows `rows` of oracle_accel_vjp only: gx (3 x nrows), gm (nrows). */
+void oracle_accel_vjp_rows(int64_t n, const double* x, const double* m, const double* w, double G,
+                           double eps, int64_t nrows, const int64_t* rows, double* gx, double* gm) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nrows; ++k) {
+        double o[4];
+        vjp_row(n, x, m, w, G, eps, rows[k], o);
+        gx[k] = o[0];
+        gx[nrows + k] = o[1];
+        gx[2 * nrows + k] = o[2];
+        gm[k] = o[3];
     }
 }
 

@@ -1,7 +1,8 @@
 """Parity at the workloads' full sizes, in the launch configuration the
 benchmark uses, on outputs the oracle can compute one by one:
 
-* N = 2^20 two-component force (eps = 0.001): FP32C and FP64 on sampled rows;
+* N = 2^20 two-component force (eps = 0.001): FP32C and FP64 on sampled rows,
+  and the FP32C VJP on sampled rows and against the FP64 VJP;
 * N = 65536 Plummer force (eps = 0.005) on sampled rows, and 100 FP32C KDK
   steps against the FP64 GPU path (energy drift and force error reported);
 * 512-cluster ensemble: sampled clusters against the oracle's own KDK;
@@ -57,6 +58,32 @@ def test_twocomp1m_sampled_rows(nb, oracle_mod):
     e_all = row_err(a32, a64)
     print("N=2^20 fp32c vs fp64 all rows: max %.3e p99 %.3e" % (e_all.max(), np.quantile(e_all, 0.99)))
     assert np.quantile(e_all, 0.999) <= 1e-5
+
+
+def test_twocomp1m_vjp_sampled_rows(nb, oracle_mod):
+    """The FP32C VJP at N = 2^20 in the benchmark's configuration (the
+    symmetric kernel at this size): sampled rows against the oracle and all
+    rows against the FP64 GPU path, norm-wise as the smaller VJP tests."""
+    w_ = ics.WORKLOADS["twocomp1m_force"]
+    n, eps = w_["n"], w_["eps"]
+    x, _, m = ics.two_component(n, seed=w_["seed"])
+    w = np.random.default_rng(1).standard_normal((3, n))
+    tx, tm, tw = dev(x), dev(m), dev(w)
+    gx, gm = nb.nbody_accel_vjp(tx, tm, tw, eps=eps, precision="fp32c")
+    gx64, gm64 = nb.nbody_accel_vjp(tx, tm, tw, eps=eps, precision="fp64")
+    gx, gm, gx64, gm64 = gx.cpu().numpy(), gm.cpu().numpy(), gx64.cpu().numpy(), gm64.cpu().numpy()
+    ex = np.linalg.norm(gx - gx64) / np.linalg.norm(gx64)
+    em = np.linalg.norm(gm - gm64) / np.linalg.norm(gm64)
+    rows = np.random.default_rng(12).choice(n, 192, replace=False)
+    rgx, rgm = oracle_mod.accel_vjp_rows(x, m, w, rows, eps=eps)
+    ox = np.linalg.norm(gx[:, rows] - rgx) / np.linalg.norm(rgx)
+    om = np.linalg.norm(gm[rows] - rgm) / np.linalg.norm(rgm)
+    o64 = np.linalg.norm(gx64[:, rows] - rgx) / np.linalg.norm(rgx)
+    print("vjp 2^20: fp32c vs fp64 gx %.2e gm %.2e; vs oracle (192 rows) gx %.2e gm %.2e; fp64 vs oracle %.2e"
+          % (ex, em, ox, om, o64))
+    assert ex <= 2e-5 and em <= 2e-5
+    assert ox <= 2e-5 and om <= 2e-5
+    assert o64 <= 1e-11
 
 
 def test_plummer64k_force_and_drift(nb, oracle_mod):

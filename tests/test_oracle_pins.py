@@ -249,6 +249,16 @@ def test_vjp_dot_product(oracle_mod):
     assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs))
 
 
+def test_vjp_rows_match_full(oracle_mod):
+    """The sampled-row VJP is the same row computation as the full one."""
+    x, _, m = ics.plummer(300, seed=18)
+    w = np.random.default_rng(18).standard_normal((3, 300))
+    gx, gm = oracle_mod.accel_vjp(x, m, w, G=0.9, eps=0.02)
+    rows = np.array([0, 7, 150, 299, 42])
+    rgx, rgm = oracle_mod.accel_vjp_rows(x, m, w, rows, G=0.9, eps=0.02)
+    assert np.array_equal(rgx, gx[:, rows]) and np.array_equal(rgm, gm[rows])
+
+
 def test_jvp_matches_central_difference(oracle_mod):
     x, _, m = ics.random_cloud(16, seed=16)
     rng = np.random.default_rng(2)
