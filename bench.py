@@ -44,7 +44,8 @@ FLOPS_PER_PAIR = 20          # acceleration-only softened interaction convention
 # sources of the headline evaluation's kernels (the symmetric FP32C path: staging,
 # block-diagonal, half-ring chunks and slot sums); traffic figures taken on other
 # sources are not reported
-KERNEL_SOURCES = ("paper_2605_02744_amd/csrc/sym_pairs.hip", "paper_2605_02744_amd/csrc/pair_math.h")
+KERNEL_SOURCES = ("paper_2605_02744_amd/csrc/sym_pairs.hip", "paper_2605_02744_amd/csrc/sym_common.h",
+                  "paper_2605_02744_amd/csrc/pair_math.h")
 
 
 def kernel_hash():
