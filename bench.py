@@ -697,7 +697,7 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="with --tune: JSON-lines file the tuner appends its choice to")
     ap.add_argument("--bitem", type=int, default=0, help="streamed ensemble: most particles per item (0 = auto)")
     ap.add_argument("--pairs", type=int, default=0, choices=[0, 1, 2],
-                    help="FP32C/FP32 force kernel: 1 ordered, 2 symmetric (each unordered pair once), 0 automatic")
+                    help="force kernel form: 1 ordered, 2 symmetric (each unordered pair once), 0 automatic")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)

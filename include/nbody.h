@@ -85,10 +85,10 @@ typedef struct nbody_params {
 
 /* Accelerations a (3*n) of particles at x (3*n) with masses m (n).
  * Eq. (1) of Sec. 2.1 divided by m_i, softened as in App. A.
- * FP32C and FP32 from 32768 particles on (or as nbody_config.pairs says)
- * evaluate each unordered pair once and apply it to both particles, with
- * sums in a fixed order; this uses a workspace of up to about 1.5 GiB
- * (staged records and per-distance sums) and several launches per call.
+ * From 32768 particles on (or as nbody_config.pairs says) each unordered
+ * pair is evaluated once and applied to both particles, with sums in a fixed
+ * order; this uses a workspace of up to about 1.5 GiB (staged records and
+ * per-distance sums) and several launches per call.
  * n == 0 is a no-op.  x, m, a must not alias.  Errors: NBODY_EINVAL for null
  * pointers with n > 0, n < 0, n > 2^29, eps < 0, eps == 0 without
  * NBODY_EXCLUDE_SELF, non-finite G, unknown precision; NBODY_ENOMEM if the
@@ -272,16 +272,17 @@ typedef struct nbody_config {
                       wave against the system's whole j-range; or 256, 512, 1024:
                       most particles per item of a system above 256 particles,
                       evaluated by a whole workgroup */
-  int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
-                      steps (FP32C and FP32; FP64 is always ordered):
-                      0 = automatic (the tuned choice for (n, precision), else
-                      symmetric from 32768 particles on), 1 = ordered: every
-                      ordered pair evaluated for its i; 2 = symmetric: every
-                      unordered pair evaluated once and applied to both particles
-                      (a_j gets the opposite of i's term scaled by m_i / m_j),
-                      results summed in a fixed order (reproducible), at the cost
-                      of a workspace of about 1.5 GiB for large n and an FP32 sum
-                      of up to 512 terms per j before the FP64 sums */
+  int32_t pairs;   /* form of the force kernel of nbody_accel, of the KDK
+                      steps and (FP32C/FP32 only) of nbody_accel_vjp and the
+                      adjoint sweep: 0 = automatic (the tuned choice for
+                      (n, precision), else symmetric from 32768 particles on),
+                      1 = ordered: every ordered pair evaluated for its i;
+                      2 = symmetric: every unordered pair evaluated once and
+                      applied to both particles (a_j gets the opposite of i's
+                      term scaled by m_i / m_j), results summed in a fixed order
+                      (reproducible), at the cost of a workspace of about
+                      1.5 GiB for large n and, in FP32C/FP32, an FP32 sum of up
+                      to 512 terms per j before the FP64 sums */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros

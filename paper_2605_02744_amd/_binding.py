@@ -330,8 +330,8 @@ def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0):
     how many of a lane's i-particles the ensemble kernel evaluates per pass
     (1, 2, 4); bitem the streamed kernel's item size (64, the automatic
     choice: one wave per item; or 256, 512, 1024: one workgroup per item);
-    pairs the form of the FP32C/FP32 force kernel (1 ordered, 2 symmetric:
-    each unordered pair once; 0 automatic)."""
+    pairs the form of the force kernels (1 ordered, 2 symmetric: each
+    unordered pair once; 0 automatic; the VJP follows in FP32C/FP32)."""
     c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem), int(pairs))
     _check(load().nbody_set_config(ctypes.byref(c)))
 

@@ -146,14 +146,14 @@ PairConfig choose_config(int64_t n, int precision, int device) {
     if (it != g_tuned.end()) c = it->second;
     else {
       c.split = 0;
-      c.sym = (precision != NBODY_FP64 && n >= kSymMinN) ? 1 : 0;
+      c.sym = n >= kSymMinN ? 1 : 0;
     }
   }
   if (t.ipl) c.ipl = t.ipl;
   if (t.split) c.split = t.split;
   if (t.pairs) c.sym = t.pairs == 2 ? 1 : 0;
-  // the symmetric kernel reads split as a least number of launches (0 = automatic)
-  if (c.sym && precision != NBODY_FP64) {
+  // the symmetric kernels read split as a least number of launches (0 = automatic)
+  if (c.sym) {
     c.split = t.split;
     return c;
   }
@@ -668,7 +668,7 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
       if (ms < best_ms) { best_ms = ms; bc = c; }
     }
   }
-  if (precision != NBODY_FP64) {
+  {
     // the symmetric kernel (its tiling is fixed)
     PairConfig c;
     c.ipl = 2;

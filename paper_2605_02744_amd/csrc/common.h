@@ -43,13 +43,13 @@ constexpr int kBlock = 256;        // threads per workgroup of the all-pairs ker
 constexpr int kTile = 256;         // j-particles staged in LDS per tile
 constexpr int kFold = 64;          // j-terms summed in plain FP32/FP64 before a TwoSum fold
 constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
-constexpr int64_t kSymMinN = 32768;  // FP32C/FP32 systems from this size use the symmetric kernel by default
+constexpr int64_t kSymMinN = 32768;  // systems from this size use the symmetric force kernels by default
 
 // Per-call configuration of the all-pairs kernels.
 struct PairConfig {
   int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups
-  int sym = 0;    // 1: the symmetric kernel (each unordered pair once; FP32C/FP32)
+  int sym = 0;    // 1: the symmetric kernels (each unordered pair once; the VJP in FP32C/FP32 only)
 };
 
 PairConfig choose_config(int64_t n, int precision, int device);
@@ -69,6 +69,10 @@ int launch_accel(int64_t n, const double* x, const double* m, double* a, double 
 // (0 = as few as the workspace bound allows).
 int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
                      bool exclude_self, int launches, hipStream_t s);
+
+// The same accelerations in FP64 from the symmetric FP64 kernel.
+int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps,
+                       bool exclude_self, int launches, hipStream_t s);
 
 // The same VJP from the symmetric kernel (FP32C or FP32; launches as above).
 int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,

@@ -958,7 +958,10 @@ int launch_accel_jerk(int64_t n, const double* x, const double* v, const double*
 int launch_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps,
                  int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
-  if (cfg.sym && precision != kFP64) return launch_sym_accel(n, x, m, a, G, eps, precision, excl, cfg.split, s);
+  if (cfg.sym) {
+    if (precision == kFP64) return launch_sym_accel64(n, x, m, a, G, eps, excl, cfg.split, s);
+    return launch_sym_accel(n, x, m, a, G, eps, precision, excl, cfg.split, s);
+  }
   const int split = cfg.split < 1 ? 1 : cfg.split;
 #define NB_ACC(MODE, IPL) return accel_dispatch<MODE, IPL>(n, x, m, a, G, eps, excl, split, s)
   switch (precision) {

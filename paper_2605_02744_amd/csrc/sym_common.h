@@ -1,5 +1,6 @@
 // Definitions shared by the symmetric all-pairs kernels (sym_pairs.hip: the
-// acceleration; sym_vjp.hip: its vector-Jacobian product): block and tile
+// FP32C/FP32 acceleration; sym_fp64.hip: the FP64 acceleration; sym_vjp.hip:
+// the vector-Jacobian product): block and tile
 // sizes, the in-row rotation, the kernel arguments, the half ring of block
 // pairs and the slot sums.  Each unordered pair {i, j} is evaluated once and
 // its term applied to both particles; the layout is described in sym_pairs.hip.
@@ -61,14 +62,14 @@ using lds_ptr = __attribute__((address_space(3))) void*;
 
 // Adds the chunk's slots into the outputs (component c < 3 at out[c n + p],
 // component 3 at outm[p]): the j-side tile sums of distances d_lo .. d_lo + D - 1
-// that were evaluated, then the i-side sums of the chunk's workgroups; the
-// first chunk starts from the distance-0 sums pd, the last applies G.  One
-// thread per (particle, component), fixed order.  Only the largest distance
-// can be missing for some blocks (the opposite block of an even ring, visited
-// from the lower half only).
-template <int C>
+// that were evaluated (slots of type S: float, or double for the FP64 kernel),
+// then the i-side sums of the chunk's workgroups; the first chunk starts from
+// the distance-0 sums pd, the last applies G.  One thread per (particle,
+// component), fixed order.  Only the largest distance can be missing for some
+// blocks (the opposite block of an even ring, visited from the lower half only).
+template <int C, typename S>
 __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
-                                  const float* __restrict__ pj, const double* __restrict__ pi,
+                                  const S* __restrict__ pj, const double* __restrict__ pi,
                                   const double* __restrict__ pd, double* __restrict__ out, double* __restrict__ outm,
                                   double G, int first, int last) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,11 +82,11 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
   // the last slot of the ring is dropped where its block pair was not evaluated
   const bool drop_last = half && d_lo + send - 1 == dmax && ((J - dmax) % nb + nb) % nb >= nb / 2;
   const int sn = drop_last ? send - 1 : send;
-  const float* q = pj + (size_t)c * npad + p;
+  const S* q = pj + (size_t)c * npad + p;
   const size_t stride = (size_t)C * npad;
   int s = 0;
   for (; s + 4 <= sn; s += 4) {
-    const float v0 = q[s * stride], v1 = q[(s + 1) * stride], v2 = q[(s + 2) * stride], v3 = q[(s + 3) * stride];
+    const S v0 = q[s * stride], v1 = q[(s + 1) * stride], v2 = q[(s + 2) * stride], v3 = q[(s + 3) * stride];
     acc += (double)v0;
     acc += (double)v1;
     acc += (double)v2;
@@ -98,14 +99,15 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
 
 }  // namespace
 
-// Chunking of the half ring for n particles with C components per slot:
-// distances per workgroup (L) and per launch (D), the slots of a launch kept
-// near 1 GiB; launches > 0 asks for at least that many launches.
-inline void sym_plan(int64_t n, int launches, int C, int* nb_out, int* L_out, int* D_out) {
+// Chunking of the half ring for n particles with slot_bytes bytes of j-side
+// sums per particle and distance: distances per workgroup (L) and per launch
+// (D), the slots of a launch kept near 1 GiB; launches > 0 asks for at least
+// that many launches.
+inline void sym_plan(int64_t n, int launches, int slot_bytes, int* nb_out, int* L_out, int* D_out) {
   const int nb = (int)((n + kSI - 1) / kSI);
   const int dmax = nb / 2;
   const int64_t npad = (int64_t)nb * kSI;
-  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (4 * C * npad));
+  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (slot_bytes * npad));
   if (launches > 0) dcap = std::min<int64_t>(dcap, std::max(1, (dmax + launches - 1) / launches));
   const int d0 = (int)std::max<int64_t>(1, std::min<int64_t>(dmax, dcap));
   // at least ~4096 workgroups per launch (several rounds of 7 per CU), at most 16 distances each

@@ -1,0 +1,305 @@
+// Symmetric FP64 acceleration: the plain FP64 path with every unordered pair
+// evaluated once and applied to both particles, on the layout of the FP32C
+// kernel (sym_pairs.hip): I-blocks of 512 particles, two per lane; J-blocks
+// streamed through LDS in tiles of 64 as sub-blocks of 16 stored twice in a
+// row, so that at step K lane r meets record (r + K) mod 16; the j-side terms
+// of both i of a lane summed and moved to the lane owning that j by a row
+// rotation (each double as two 32-bit DPP moves, then an FP64 add); wave sums
+// across rows on the LDS pipe; tile sums to per-distance FP64 slots; a half
+// ring of block pairs in chunks; FP64 slot sums in a fixed order.  All
+// arithmetic is FP64 with the refined inverse square root of the ordered FP64
+// kernel; there is no near-field repair to do.
+#include "sym_common.h"
+
+namespace nb {
+namespace {
+
+// A double rotated within each row of 16 lanes: lane r gets lane (r - K) mod 16's value.
+template <int K>
+__device__ __forceinline__ double row_ror64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), 0x120 + K, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x120 + K, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The two 32-bit halves of a double through ds_swizzle / ds_bpermute.
+__device__ __forceinline__ double swizzle64_xor16(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_swizzle((int)(unsigned)(b & 0xffffffffull), 0x401F);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), 0x401F);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double bpermute64(int addr, double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b & 0xffffffffull));
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+struct S64Args {
+  const double* x;  // [3][n]
+  const double* m;  // [n]
+  int n, nb, npad, dmax, half, d_lo, L, nparts;
+  double eps;
+  const double4* rec;  // [npad] staged (x, y, z, m); padding far away and massless
+  double* pj;          // [D][3][npad] j-side tile sums of the chunk's distances
+  double* pi;          // [nparts][3][npad] i-side sums of the chunk's workgroups
+};
+
+struct DSet {
+  double x[2], y[2], z[2], mneg[2];
+};
+
+template <int K>
+__device__ __forceinline__ void step64(const DSet& s, const double4* __restrict__ rowp, double e2,
+                                       double (&px)[2], double (&py)[2], double (&pz)[2], double& ajx, double& ajy,
+                                       double& ajz) {
+  const double4 r = rowp[K];
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const double dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
+    const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+    const double ri = rsqrt64(r2);
+    const double ri3 = (ri * ri) * ri;
+    const double si = r.w * ri3;
+    px[u] = fma(si, dx, px[u]);
+    py[u] = fma(si, dy, py[u]);
+    pz[u] = fma(si, dz, pz[u]);
+    const double sj = s.mneg[u] * ri3;
+    if (u == 0) { tx = sj * dx; ty = sj * dy; tz = sj * dz; }
+    else { tx = fma(sj, dx, tx); ty = fma(sj, dy, ty); tz = fma(sj, dz, tz); }
+  }
+  if constexpr (K == 0) { ajx += tx; ajy += ty; ajz += tz; }
+  else {
+    ajx += row_ror64<K>(tx);
+    ajy += row_ror64<K>(ty);
+    ajz += row_ror64<K>(tz);
+  }
+}
+
+template <int... K>
+__device__ __forceinline__ void sub64(const DSet& s, const double4* __restrict__ rowp, double e2, double (&px)[2],
+                                      double (&py)[2], double (&pz)[2], double& ajx, double& ajy, double& ajz,
+                                      std::integer_sequence<int, K...>) {
+  (step64<K>(s, rowp, e2, px, py, pz, ajx, ajy, ajz), ...);
+}
+
+__device__ __forceinline__ void load_dset(const S64Args& A, int g, int t, DSet& s) {
+  const int n = A.n;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = g * kSI + u * kSL + t;
+    if (i < n) {
+      s.x[u] = A.x[i]; s.y[u] = A.x[n + i]; s.z[u] = A.x[2 * n + i];
+      s.mneg[u] = -A.m[i];
+    } else {
+      s.x[u] = s.y[u] = s.z[u] = kFarAway;
+      s.mneg[u] = 0.0;
+    }
+  }
+}
+
+__global__ void sym64_stage_kernel(S64Args A, double4* __restrict__ rec) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.npad) return;
+  const int n = A.n;
+  rec[j] = j < n ? make_double4(A.x[j], A.x[n + j], A.x[2 * n + j], A.m[j])
+                 : make_double4(kFarAway, kFarAway, kFarAway, 0.0);
+}
+
+// Grid: nb * nparts workgroups; workgroup (g, part) takes the distances
+// [d_lo + part L, d_lo + (part + 1) L) of I-block g's half ring (d >= 1).
+__global__ __launch_bounds__(kSL, 6) void sym64_kernel(S64Args A) {
+  __shared__ double4 s_rec[2][4][2 * kSR];  // each sub-block twice in a row
+  __shared__ double s_part[3][kSW][kST];
+  __shared__ double s_acc_lo[6][kSL];       // the lo halves of the i-side (hi, lo) sums
+
+  const int t = threadIdx.x;
+  const int rl = t & (kSR - 1);
+  const int wave = t / 64;
+  const int g = blockIdx.x % A.nb;
+  const int part = blockIdx.x / A.nb;
+  const int dbeg = A.d_lo + part * A.L;
+  const int dend = min(dbeg + A.L, (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1);
+  const int ntiles = dend > dbeg ? (dend - dbeg) * kSTiles : 0;
+  const double e2 = A.eps * A.eps;
+
+  DSet s;
+  load_dset(A, g, t, s);
+  double hx[2] = {0.0, 0.0}, hy[2] = {0.0, 0.0}, hz[2] = {0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s_acc_lo[c][t] = 0.0;
+  const int xor32 = ((t & 63) ^ 32) * 4;
+
+  // the last wave copies tile k into LDS buffer b, one sub-block per copy: lane
+  // L brings the half (L & 1) of record (L >> 1) mod 16, so that the 64 lanes'
+  // 16-byte pieces lay the sub-block's 16 records out twice in a row
+  const unsigned lane_off = (unsigned)((((t & 63) >> 1) & (kSR - 1)) * sizeof(double4) + (t & 1) * 16);
+  auto stage = [&](int k, int b) {
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + dbeg + k / kSTiles) % A.nb) * kSI + (k % kSTiles) * kST);
+    const char* base = reinterpret_cast<const char*>(A.rec) + (size_t)rec0 * sizeof(double4);
+    unsigned o = lane_off;
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      __builtin_amdgcn_global_load_lds(base + q * kSR * sizeof(double4) + o, (lds_ptr)&s_rec[b][q][0], 16, 0, 0);
+  };
+
+  if (ntiles > 0 && t >= 3 * 64) {
+    stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+
+  for (int k = 0; k < ntiles; ++k) {
+    const int b = k & 1;
+    const int d = dbeg + k / kSTiles;
+    const int tt = k % kSTiles;
+    if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
+    double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      double ajx = 0.0, ajy = 0.0, ajz = 0.0;
+      sub64(s, &s_rec[b][q][rl], e2, px, py, pz, ajx, ajy, ajz, std::make_integer_sequence<int, kSR>{});
+      ajx += swizzle64_xor16(ajx);
+      ajy += swizzle64_xor16(ajy);
+      ajz += swizzle64_xor16(ajz);
+      ajx += bpermute64(xor32, ajx);
+      ajy += bpermute64(xor32, ajy);
+      ajz += bpermute64(xor32, ajz);
+      s_part[0][wave][q * kSR + rl] = ajx;
+      s_part[1][wave][q * kSR + rl] = ajy;
+      s_part[2][wave][q * kSR + rl] = ajz;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      fold(hx[u], s_acc_lo[3 * u][t], px[u]);
+      fold(hy[u], s_acc_lo[3 * u + 1][t], py[u]);
+      fold(hz[u], s_acc_lo[3 * u + 2][t], pz[u]);
+    }
+    __syncthreads();
+    if (t < 3 * 64) {
+      const int c = t / kST, jl = t % kST;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < kSW; ++w) v += s_part[c][w][jl];
+      const int J = (g + d) % A.nb;
+      A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + (size_t)J * kSI + tt * kST + jl] = v;
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);  // the next tile's copies have landed in LDS
+    }
+    __syncthreads();
+  }
+
+  double* o = A.pi + (size_t)part * 3 * A.npad;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const size_t i = (size_t)g * kSI + u * kSL + t;
+    o[i] = hx[u] + s_acc_lo[3 * u][t];
+    o[A.npad + i] = hy[u] + s_acc_lo[3 * u + 1][t];
+    o[2 * (size_t)A.npad + i] = hz[u] + s_acc_lo[3 * u + 2][t];
+  }
+}
+
+// The block with itself (distance 0), ordered form, i-side only, own pair
+// masked when asked.  Writes hi + lo into pd[3][npad].
+template <bool EXCL>
+__global__ __launch_bounds__(kSL) void sym64_diag_kernel(S64Args A, double* __restrict__ pd) {
+  __shared__ double4 s_rec[kSI];
+  const int t = threadIdx.x;
+  const int g = blockIdx.x;
+  const double e2 = A.eps * A.eps;
+  DSet s;
+  load_dset(A, g, t, s);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) s_rec[u * kSL + t] = A.rec[(size_t)g * kSI + u * kSL + t];
+  __syncthreads();
+  double hx[2] = {0.0, 0.0}, hy[2] = {0.0, 0.0}, hz[2] = {0.0, 0.0};
+  double lx[2] = {0.0, 0.0}, ly[2] = {0.0, 0.0}, lz[2] = {0.0, 0.0};
+#pragma unroll 1
+  for (int f = 0; f < kSI; f += kFold) {
+    double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};
+#pragma unroll 8
+    for (int j = f; j < f + kFold; ++j) {
+      const double4 r = s_rec[j];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
+        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+        const double ri = rsqrt64(r2);
+        double si = (r.w * ri) * (ri * ri);
+        if (EXCL) si = (j == u * kSL + t) ? 0.0 : si;
+        px[u] = fma(si, dx, px[u]);
+        py[u] = fma(si, dy, py[u]);
+        pz[u] = fma(si, dz, pz[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      fold(hx[u], lx[u], px[u]);
+      fold(hy[u], ly[u], py[u]);
+      fold(hz[u], lz[u], pz[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const size_t i = (size_t)g * kSI + u * kSL + t;
+    pd[i] = hx[u] + lx[u];
+    pd[A.npad + i] = hy[u] + ly[u];
+    pd[2 * (size_t)A.npad + i] = hz[u] + lz[u];
+  }
+}
+
+}  // namespace
+
+int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps, bool excl,
+                       int launches, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  int nb, L, D;
+  sym_plan(n, launches, 3 * sizeof(double), &nb, &L, &D);
+  const int dmax = nb / 2;
+  const int half = (nb % 2 == 0) ? 1 : 0;
+  const int64_t npad = (int64_t)nb * kSI;
+  const int nparts = D / L;
+  int st = NBODY_OK;
+  const size_t pj_bytes = sizeof(double) * 3 * (size_t)npad * D;
+  const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
+  const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
+  const size_t rec_bytes = sizeof(double4) * (size_t)npad;
+  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes + rec_bytes, &st));
+  if (!ws) return st;
+  S64Args A;
+  A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
+  A.L = L; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  A.pj = reinterpret_cast<double*>(ws);
+  A.pi = reinterpret_cast<double*>(ws + pj_bytes);
+  double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);
+  double4* rec = reinterpret_cast<double4*>(ws + pj_bytes + pi_bytes + pd_bytes);
+  A.rec = rec;
+  sym64_stage_kernel<<<(unsigned)((npad + 255) / 256), 256, 0, s>>>(A, rec);
+  NB_LAUNCH_CHECK("sym64_stage_kernel");
+  if (excl) sym64_diag_kernel<true><<<nb, kSL, 0, s>>>(A, pd);
+  else sym64_diag_kernel<false><<<nb, kSL, 0, s>>>(A, pd);
+  NB_LAUNCH_CHECK("sym64_diag_kernel");
+  const dim3 rg((unsigned)((n + 255) / 256), 3);
+  if (dmax == 0) {
+    sym_reduce_kernel<3, double><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a,
+                                                    nullptr, G, 1, 1);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+    return NBODY_OK;
+  }
+  const int nchunks = (dmax + D - 1) / D;
+  for (int c = 0; c < nchunks; ++c) {
+    A.d_lo = 1 + c * D;
+    sym64_kernel<<<(unsigned)nb * (unsigned)nparts, kSL, 0, s>>>(A);
+    NB_LAUNCH_CHECK("sym64_kernel");
+    sym_reduce_kernel<3, double><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi,
+                                                    pd, a, nullptr, G, c == 0, c == nchunks - 1);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace nb

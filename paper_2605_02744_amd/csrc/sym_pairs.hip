@@ -415,7 +415,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
     return set_error(NBODY_EUNSUPPORTED, "symmetric pair kernel: FP32C and FP32 only");
   if (n > (int64_t(1) << 30)) return set_error(NBODY_EINVAL, "symmetric pair kernel: n too large");
   int nb, L, D;
-  sym_plan(n, launches, 3, &nb, &L, &D);
+  sym_plan(n, launches, 3 * sizeof(float), &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -453,7 +453,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   NB_LAUNCH_CHECK("sym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {
-    sym_reduce_kernel<3><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, nullptr, G,
+    sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, nullptr, G,
                                             1, 1);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
@@ -465,7 +465,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
     if (near) sym_accel_kernel<true><<<grid, kSL, 0, s>>>(A);
     else sym_accel_kernel<false><<<grid, kSL, 0, s>>>(A);
     NB_LAUNCH_CHECK("sym_accel_kernel");
-    sym_reduce_kernel<3><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd, a,
+    sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd, a,
                                             nullptr, G, c == 0, c == nchunks - 1);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   }

@@ -409,7 +409,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   if (precision != kFP32C && precision != kFP32)
     return set_error(NBODY_EUNSUPPORTED, "symmetric VJP kernel: FP32C and FP32 only");
   int nb, L, D;
-  sym_plan(n, launches, kVC, &nb, &L, &D);
+  sym_plan(n, launches, kVC * sizeof(float), &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -446,7 +446,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   NB_LAUNCH_CHECK("vsym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), kVC);
   if (dmax == 0) {
-    sym_reduce_kernel<kVC><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, gx, gm, G,
+    sym_reduce_kernel<kVC, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, gx, gm, G,
                                               1, 1);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
@@ -458,7 +458,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
     if (near) vsym_kernel<true><<<grid, kSL, 0, s>>>(A);
     else vsym_kernel<false><<<grid, kSL, 0, s>>>(A);
     NB_LAUNCH_CHECK("vsym_kernel");
-    sym_reduce_kernel<kVC><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
+    sym_reduce_kernel<kVC, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
                                               gx, gm, G, c == 0, c == nchunks - 1);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   }

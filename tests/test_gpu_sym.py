@@ -273,3 +273,39 @@ def test_sym_traj_grad_matches_ordered(nb):
             nb.nbody_set_config()
     for a, b in zip(out[1], out[2]):
         assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a)
+
+
+# ---------------------------------------------------------------- FP64
+# The symmetric FP64 kernel (selected with pairs = 2): the plain FP64 path's
+# 1e-12 bar against the oracle.
+
+@pytest.mark.parametrize("n", [1, 2, 511, 513, 1025, 2048, 3001])
+def test_sym_accel_fp64_matches_oracle(nb, oracle_mod, n):
+    x, _, m = ics.two_component(n, seed=60 + n)
+    ref = oracle_mod.accel(x, m, G=0.8, eps=0.01)
+    print("sym fp64 n=%d" % n, flush=True)
+    a = sym_accel(nb, x, m, G=0.8, eps=0.01, precision="fp64")
+    if n == 1:
+        assert np.all(a == 0.0)
+        return
+    e = rel_err(a, ref)
+    print("  max rel err %.3e" % e)
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("n,launches", [(5000, 3), (9000, 9)])
+def test_sym_accel_fp64_launch_splits_and_repeat(nb, oracle_mod, n, launches):
+    x, _, m = ics.plummer(n, seed=61)
+    ref = oracle_mod.accel(x, m, eps=0.005)
+    a1 = sym_accel(nb, x, m, launches=launches, eps=0.005, precision="fp64")
+    a2 = sym_accel(nb, x, m, launches=launches, eps=0.005, precision="fp64")
+    assert np.array_equal(a1, a2)
+    assert rel_err(a1, ref) <= 1e-12
+
+
+def test_sym_accel_fp64_exclude_self_eps_zero(nb, oracle_mod):
+    x, _, m = ics.random_cloud(1500, seed=62)
+    ref = oracle_mod.accel(x, m, eps=0.0)
+    a = sym_accel(nb, x, m, eps=0.0, precision="fp64", exclude_self=True)
+    assert np.isfinite(a).all()
+    assert rel_err(a, ref) <= 1e-11
