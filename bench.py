@@ -369,7 +369,8 @@ def bench_ensemble(args, torch, nb):
         e0 = energies(tx, tv)
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=prec)  # plan + a(x)
         steps = args.steps
-        # all clusters, all steps: one persistent launch (modes 0-2) or two launches per step (mode 3),
+        # all clusters, all steps: one persistent launch (modes 0-2), or two (mode 3) or three (mode 4)
+        # launches per step,
         # captured in a HIP graph and replayed once
         gs = torch.cuda.Stream()
         torch.cuda.synchronize()
@@ -416,7 +417,7 @@ def bench_ensemble(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": 2 * args.steps + 1 if mode == 3 else 1, "hip_graph": True, "kernel_mode": mode,
+                       "launches": {3: 2 * args.steps + 1, 4: 3 * args.steps + 1}.get(mode, 1), "hip_graph": True, "kernel_mode": mode,
                        "autotuned": tuned or None, "bpass": args.bpass, "bitem": args.bitem},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift_per_cluster": drift,
@@ -691,8 +692,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU baseline")
     ap.add_argument("--split", action="store_true", help="ensemble: split the largest systems over workgroups")
-    ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2, 3],
-                    help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items")
+    ap.add_argument("--bsplit", type=int, default=None, choices=[0, 1, 2, 3, 4],
+                    help="ensemble kernel: 0 resident systems, 1 resident + split, 2 streamed items, "
+                         "3 per-step items of 64, 4 the same with each unordered pair once")
     ap.add_argument("--bpass", type=int, default=0, help="ensemble: i-particles per lane per pass (0 = auto)")
     ap.add_argument("--tune-cache", default=None, help="with --tune: JSON-lines file the tuner appends its choice to")
     ap.add_argument("--bitem", type=int, default=0, help="streamed ensemble: most particles per item (0 = auto)")

@@ -260,11 +260,18 @@ typedef struct nbody_config {
                       resident for all steps, records streamed through LDS, the
                       items of a system synchronised every step; 3 = the items of
                       64 particles of mode 2, with two launches per step (kicks and
-                      drift, then the forces) instead of one persistent launch.
+                      drift, then the forces) instead of one persistent launch;
+                      4 = as 3, but each unordered pair of a system evaluated once
+                      (Eq. 1's antisymmetry: an item's block of 64 meets its own
+                      block and half of its system's other blocks, and the terms
+                      of the far side are added per particle in FP64 in a fixed
+                      order by a third launch per step); FP32C and FP32 only (FP64
+                      runs mode 3), and layouts whose per-distance sums would
+                      exceed 1 GiB (about 3 x sum of N_c^2 / 128 floats) run mode 3.
                       Modes 1 and 2 need every workgroup of the launch resident at
                       once: with another kernel occupying the GPU a bounded wait can
                       expire, and the affected systems then end NaN.  Modes 0 and 3
-                      have no such requirement. */
+                      have no such requirement, nor has 4. */
   int32_t bpass;   /* batched kernel: i-particles per lane evaluated together in one
                       pass over a system's records: 0 = automatic (4), or 1, 2, 4 */
   int32_t bitem;   /* streamed batched kernel (bsplit = 2): 64 (or 0 = automatic):
@@ -306,8 +313,8 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * steps, from the state (x, v, m), on the
  * library's own copies (the caller's arrays are only read), and keeps the
  * fastest whose state stays finite.  Candidates: the resident kernel with 1, 2
- * or 4 i-particles per lane per pass and the per-step items of 64 (mode 3);
- * with allow_cooperative != 0 also the
+ * or 4 i-particles per lane per pass, the per-step items of 64 (mode 3) and,
+ * for FP32C and FP32, their symmetric form (mode 4); with allow_cooperative != 0 also the
  * split mode and the streamed kernel with items of 64, 256, 512 or 1024 particles
  * (the modes that need every workgroup of a launch resident at once). allow_cooperative = 2 keeps
  * to the single-launch modes 0, 1 and 2 (all steps in one persistent launch).  The

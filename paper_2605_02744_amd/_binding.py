@@ -232,7 +232,7 @@ def nbody_tune_batched(off, eps, x, v, m, dt, nsteps, *, G=1.0, precision="fp32c
     """Times the batched kernels' configurations on copies of (x, v) for this
     layout, records the fastest for later nbody_step_batched calls, and
     returns it as {"bsplit", "bpass", "bitem"}.  allow_cooperative: False keeps
-    to the modes that need no co-resident workgroups (0, 3), True allows all,
+    to the modes that need no co-resident workgroups (0, 3, 4), True allows all,
     "persistent" keeps to the single-launch modes (0, 1, 2)."""
     import numpy as np
     lib = load()
@@ -326,7 +326,8 @@ def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0):
     bsplit=1 lets the ensemble kernel split its largest systems over up to 4
     workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
     items, one persistent launch), bsplit=3 its items of 64 particles with two
-    launches per step, default 0: one workgroup per system; bpass sets
+    launches per step, bsplit=4 as 3 with each unordered pair of a system
+    evaluated once (FP32C, FP32), default 0: one workgroup per system; bpass sets
     how many of a lane's i-particles the ensemble kernel evaluates per pass
     (1, 2, 4); bitem the streamed kernel's item size (64, the automatic
     choice: one wave per item; or 256, 512, 1024: one workgroup per item);

@@ -21,6 +21,7 @@ int run_traj_grad(int64_t n, const double* ckx, const double* ckv, int64_t every
                   hipStream_t s);
 void release_batched_plans();
 void release_stream_plans();
+void release_sym_ensemble_plans();
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -418,7 +419,10 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   const int dev = current_device();
   std::vector<BatchConfig> cand;
   for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0});
-  if (allow_cooperative != 2) cand.push_back(BatchConfig{3, 0, 64});
+  if (allow_cooperative != 2) {
+    cand.push_back(BatchConfig{3, 0, 64});
+    if (p->precision != NBODY_FP64) cand.push_back(BatchConfig{4, 0, 0});
+  }
   if (allow_cooperative) {
     cand.push_back(BatchConfig{1, 0, 0});
     for (int item : {64, 256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});
@@ -590,7 +594,7 @@ int nbody_set_config(const nbody_config* cfg) {
   if (cfg->ipl != 0 && cfg->ipl != 1 && cfg->ipl != 2 && cfg->ipl != 4)
     return set_error(NBODY_EINVAL, "ipl must be 0, 1, 2 or 4");
   if (cfg->split < 0 || cfg->split > 1024) return set_error(NBODY_EINVAL, "split must be in 0..1024");
-  if (cfg->bsplit < 0 || cfg->bsplit > 3) return set_error(NBODY_EINVAL, "bsplit must be 0, 1, 2 or 3");
+  if (cfg->bsplit < 0 || cfg->bsplit > 4) return set_error(NBODY_EINVAL, "bsplit must be 0 .. 4");
   if (cfg->bpass != 0 && cfg->bpass != 1 && cfg->bpass != 2 && cfg->bpass != 4)
     return set_error(NBODY_EINVAL, "bpass must be 0, 1, 2 or 4");
   if (cfg->bitem != 0 && cfg->bitem != 64 && cfg->bitem != 256 && cfg->bitem != 512 && cfg->bitem != 1024)
@@ -712,6 +716,7 @@ const char* nbody_last_error(void) { return g_err.c_str(); }
 int nbody_finalize(void) {
   release_batched_plans();
   release_stream_plans();
+  release_sym_ensemble_plans();
   {
     std::lock_guard<std::mutex> lk(g_tb_mu);
     g_tuned_batch.clear();

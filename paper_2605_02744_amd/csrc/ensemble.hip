@@ -587,9 +587,15 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
                        bool acc_valid, int bitem, bool per_step, hipStream_t s);
 
+int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                    const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
+                    hipStream_t s);
+
 int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
                 const BatchConfig& bc, hipStream_t s) {
+  if (bc.mode == 4)
+    return run_batched_sym(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, s);
   if (bc.mode == 2 || bc.mode == 3)
     return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, bc.item,
                               bc.mode == 3, s);

@@ -1,0 +1,583 @@
+// Symmetric per-step ensemble (nbody_config.bsplit = 4; FP32C and FP32).
+//
+// Every unordered pair of a system is evaluated once and its term applied to
+// both particles (the antisymmetry of Eq. 1), as in the single-system symmetric
+// kernel, but at the size of one wave, so that systems of 64 to a few thousand
+// particles fill the chip.  An item is one block of 64 particles of one system
+// (lane t owns its particle t); the wave that takes it evaluates
+//   * the block with itself in the ordered form (the i-side of every ordered
+//     pair, the own pair masked when asked);
+//   * the blocks b + d (mod nb_c) of its system for d = 1 .. nb_c / 2 (d = nb_c / 2
+//     only for b < nb_c / 2 when nb_c is even), each pair once.  The lanes form
+//     4 rows of 16 and a J-block is 4 sub-blocks of 16 records, each stored
+//     twice in a row in LDS, so that at step K lane r of every row reads record
+//     (r + K) of the sub-block at an immediate offset.  The i-side terms stay
+//     in the lane; the j-side term of a step belongs to the lane that met that
+//     j at step 0 and moves there through a DPP row rotation fused into the
+//     add; after a sub-block the four rows' sums of its 16 j are added on the
+//     LDS pipe; the J-block's 64 sums go to the system's slot for distance d.
+// Each step is three launches: publish (the kicks, the drift and the pair
+// records of the new positions), force (the i-side sums into a, unscaled; the
+// j-side sums into the slots) and reduce (per particle, its i-side sum plus its
+// slots in distance order, in FP64, times G), so results are reproducible.
+// Items are placed longest first over the workgroups and a workgroup's waves
+// take its items from an LDS counter.  FP32C positions are rounded to FP32 and
+// the near-field rule of the ordered kernels applies: in the ordered block a
+// pair closer than particle i's repair radius, in a block pair a pair closer
+// than the larger radius of its two particles, gets float-float displacements.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <queue>
+#include <vector>
+
+#include "sym_common.h"
+
+namespace nb {
+namespace {
+
+constexpr int kEBlock = 1024;          // lanes per workgroup
+constexpr int kEWaves = kEBlock / 64;  // waves (items in flight) per workgroup
+constexpr int kEOcc = 8;               // waves per SIMD the force kernel is built for (<= 64 VGPRs)
+constexpr int kEMaxPerCu = 2;          // resident workgroups per CU at most
+constexpr size_t kESlotCap = size_t(1) << 30;  // bytes of j-side slots a plan may hold
+
+struct EItem {
+  int sys;  // system
+  int b;    // block of 64 particles within the system
+  int ni;   // particles in the block
+  int dend; // ring distances 1 .. dend - 1
+};
+
+// Per-system geometry: particles [o, o + nc) of the concatenated arrays, nb
+// blocks of 64, slots [dmax][3][nb * 64] floats from sbase.
+struct ESys {
+  int64_t o;
+  int64_t sbase;
+  double eps;
+  int nc, nb, dmax, half;
+  float fx;  // repair-radius factor max(kNearX, kNearN nc^-1/3)
+  int pad;
+};
+
+// Orders a wave's LDS accesses around a rewrite by other lanes (LDS
+// instructions of one wave execute in order; this keeps the compiler from
+// moving reads and writes across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// kicks = 0: records only; 1: v += h a, x += dt v; 2: v += h a twice (the
+// closing half-kick of the previous step and the opening one of this step,
+// rounded separately), x += dt v.  Then the pair records of the new position:
+// hi = (x, y, z, m) rounded to FP32, lo = (x - hi, y - hi, z - hi, repair
+// radius^2, or -1 without the repair).
+template <bool NEAR>
+__global__ void esym_publish_kernel(int nitems, const EItem* __restrict__ items, const ESys* __restrict__ sys,
+                                    int64_t total, double* __restrict__ x, double* __restrict__ v,
+                                    const double* __restrict__ a, const double* __restrict__ m,
+                                    float4* __restrict__ rhi, float4* __restrict__ rlo, double h, double dt,
+                                    int kicks) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nitems * 64;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const EItem it = items[g >> 6];
+    const int lane = (int)(g & 63);
+    if (lane >= it.ni) continue;
+    const ESys& S = sys[it.sys];
+    const int64_t i = S.o + (int64_t)it.b * 64 + lane;
+    double xn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t e = d * total + i;
+      if (kicks > 0) {
+        const double ae = a[e];
+        double ve = fma(h, ae, v[e]);
+        if (kicks > 1) ve = fma(h, ae, ve);
+        v[e] = ve;
+        xn[d] = fma(dt, ve, x[e]);
+        x[e] = xn[d];
+      } else {
+        xn[d] = x[e];
+      }
+    }
+    const float4 hi = make_float4((float)xn[0], (float)xn[1], (float)xn[2], (float)m[i]);
+    rhi[i] = hi;
+    rlo[i] = make_float4((float)(xn[0] - (double)hi.x), (float)(xn[1] - (double)hi.y), (float)(xn[2] - (double)hi.z),
+                         NEAR ? sym_rc2(xn[0], xn[1], xn[2], S.eps, S.fx) : -1.f);
+  }
+}
+
+__global__ void esym_kick_kernel(int64_t total, double* __restrict__ v, const double* __restrict__ a, double h) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * total; e += (int64_t)gridDim.x * blockDim.x)
+    v[e] = fma(h, a[e], v[e]);
+}
+
+// One step of a sub-block: the lane's i against record (r + K) of its row.
+template <int K, bool NEAR>
+__device__ __forceinline__ void esym_step(const float4& ip, float mneg, const float4* __restrict__ rowp, float e2,
+                                          float& px, float& py, float& pz, float& r2m, float& ajx, float& ajy,
+                                          float& ajz) {
+  const float4 r = rowp[K];
+  const float dx = r.x - ip.x, dy = r.y - ip.y, dz = r.z - ip.z;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+  const float ri = rsqrt32(r2);
+  const float ri3 = (ri * ri) * ri;
+  const float si = r.w * ri3;
+  px = fmaf(si, dx, px);
+  py = fmaf(si, dy, py);
+  pz = fmaf(si, dz, pz);
+  if constexpr (NEAR) r2m = fminf(r2m, r2);
+  const float sj = mneg * ri3;
+  const float tx = sj * dx, ty = sj * dy, tz = sj * dz;
+  // the j met here sits at row position (r + K): its owner is K lanes further on
+  if constexpr (K == 0) { ajx += tx; ajy += ty; ajz += tz; }
+  else {
+    ajx += row_ror<K>(tx);
+    ajy += row_ror<K>(ty);
+    ajz += row_ror<K>(tz);
+  }
+}
+
+template <bool NEAR, int... K>
+__device__ __forceinline__ void esym_sub(const float4& ip, float mneg, const float4* __restrict__ rowp, float e2,
+                                         float& px, float& py, float& pz, float& r2m, float& ajx, float& ajy,
+                                         float& ajz, std::integer_sequence<int, K...>) {
+  (esym_step<K, NEAR>(ip, mneg, rowp, e2, px, py, pz, r2m, ajx, ajy, ajz), ...);
+}
+
+template <bool NEAR, bool EXCL>
+__global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
+    const ESys* __restrict__ sys, const EItem* __restrict__ items, const int* __restrict__ wg_off,
+    const int* __restrict__ wg_list, const float4* __restrict__ rhi, const float4* __restrict__ rlo,
+    double* __restrict__ a, float* __restrict__ slots, int64_t total) {
+  __shared__ float4 s_hi[kEWaves][4][2 * kSR];  // (x, y, z, m) hi parts, each sub-block twice
+  __shared__ float4 s_lo[kEWaves][64];          // lo parts and the repair radius^2
+  __shared__ float s_j[kEWaves][3][64];         // the block pair's j-side sums
+  __shared__ int next_item;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, lane = t & 63, rl = lane & (kSR - 1), row = lane >> 4;
+  const int xor32 = (lane ^ 32) * 4;
+  const int q0 = wg_off[blockIdx.x], q1 = wg_off[blockIdx.x + 1];
+  const float4 far_hi = make_float4((float)kFarAway, (float)kFarAway, (float)kFarAway, 0.f);
+  const float4 far_lo = make_float4(0.f, 0.f, 0.f, -1.f);
+  if (t == 0) next_item = 0;
+  __syncthreads();
+  for (;;) {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(&next_item, 1);
+    k = __builtin_amdgcn_readfirstlane(k);
+    if (k >= q1 - q0) break;
+    const EItem it = items[wg_list[q0 + k]];
+    const ESys& S = sys[it.sys];
+    const int nc = S.nc, nb = S.nb;
+    const float4* hs = rhi + S.o;
+    const float4* ls = rlo + S.o;
+    const float e2 = (float)(S.eps * S.eps);
+    const int il = it.b * 64 + lane;
+    const bool valid = lane < it.ni;
+    const float4 ip = valid ? hs[il] : far_hi;
+    const float4 iq = valid ? ls[il] : far_lo;
+    const float mneg = -ip.w;
+    // flags a block pair for the repair: every pair inside the larger radius of
+    // its two particles is inside this one (|d| < f |x_j| with |x_j| <= |x_i| + |d|
+    // gives |d| < f / (1 - f) |x_i|; the eps term is the same for both)
+    const float thr = (NEAR && valid)
+                          ? sym_rc2((double)ip.x, (double)ip.y, (double)ip.z, S.eps, S.fx / (1.0f - S.fx) * 1.0001f)
+                          : -1.f;
+    auto fetch = [&](int J, float4& rh, float4& rq) {
+      const int jl = J * 64 + lane;
+      rh = jl < nc ? hs[jl] : far_hi;
+      rq = jl < nc ? ls[jl] : far_lo;
+    };
+    auto put = [&](const float4& rh, const float4& rq) {
+      wave_sync();
+      s_hi[wv][row][rl] = rh;
+      s_hi[wv][row][rl + kSR] = rh;
+      s_lo[wv][lane] = rq;
+      wave_sync();
+    };
+    float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+    float4 nh, nq;
+    fetch(it.b, nh, nq);
+    put(nh, nq);
+    if (1 < it.dend) fetch(it.b + 1 < nb ? it.b + 1 : it.b + 1 - nb, nh, nq);
+    {
+      // the block with itself: ordered pairs, i-side only
+      float px = 0.f, py = 0.f, pz = 0.f, r2min = 3.0e38f;
+#pragma unroll 16
+      for (int jj = 0; jj < 64; ++jj) {
+        const float4 r = s_hi[wv][jj >> 4][jj & (kSR - 1)];
+        const float dx = r.x - ip.x, dy = r.y - ip.y, dz = r.z - ip.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+        const float ri = rsqrt32(r2);
+        float sc = (r.w * ri) * (ri * ri);
+        if constexpr (EXCL) sc = jj == lane ? 0.f : sc;
+        px = fmaf(sc, dx, px);
+        py = fmaf(sc, dy, py);
+        pz = fmaf(sc, dz, pz);
+        if constexpr (NEAR) r2min = fminf(r2min, jj == lane ? 3.0e38f : r2);
+      }
+      if constexpr (NEAR) {
+        if (r2min < iq.w) {
+          // rare: redo the block with float-float displacements for the pairs
+          // closer than particle i's repair radius
+          float qx = 0.f, qy = 0.f, qz = 0.f;
+          for (int jj = 0; jj < 64; ++jj) {
+            const float4 r = s_hi[wv][jj >> 4][jj & (kSR - 1)];
+            const float4 q = s_lo[wv][jj];
+            float dx = r.x - ip.x, dy = r.y - ip.y, dz = r.z - ip.z;
+            float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            if (r2 < iq.w) {
+              dx += q.x - iq.x;
+              dy += q.y - iq.y;
+              dz += q.z - iq.z;
+              r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            }
+            const float ri = rsqrt32(r2);
+            float sc = (r.w * ri) * (ri * ri);
+            if constexpr (EXCL) sc = jj == lane ? 0.f : sc;
+            qx = fmaf(sc, dx, qx);
+            qy = fmaf(sc, dy, qy);
+            qz = fmaf(sc, dz, qz);
+          }
+          px = qx;
+          py = qy;
+          pz = qz;
+        }
+      }
+      fold(hx, lx, px);
+      fold(hy, ly, py);
+      fold(hz, lz, pz);
+    }
+    const size_t npad = (size_t)nb * 64;
+#pragma unroll 1
+    for (int d = 1; d < it.dend; ++d) {
+      const int J = it.b + d < nb ? it.b + d : it.b + d - nb;
+      put(nh, nq);
+      if (d + 1 < it.dend) fetch(J + 1 < nb ? J + 1 : J + 1 - nb, nh, nq);
+      float px = 0.f, py = 0.f, pz = 0.f, r2m = 3.0e38f;
+#pragma unroll 1
+      for (int q = 0; q < 4; ++q) {
+        float ajx = 0.f, ajy = 0.f, ajz = 0.f;
+        esym_sub<NEAR>(ip, mneg, &s_hi[wv][q][rl], e2, px, py, pz, r2m, ajx, ajy, ajz,
+                       std::make_integer_sequence<int, kSR>{});
+        // the four rows' sums of the same 16 j: rows (0 + 1) and (2 + 3) by a
+        // swizzle, then the two halves by a permute; every row then holds the
+        // totals and stores the same values
+        ajx += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajx), 0x401F));
+        ajy += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajy), 0x401F));
+        ajz += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajz), 0x401F));
+        ajx += __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajx)));
+        ajy += __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajy)));
+        ajz += __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajz)));
+        s_j[wv][0][q * kSR + rl] = ajx;
+        s_j[wv][1][q * kSR + rl] = ajy;
+        s_j[wv][2][q * kSR + rl] = ajz;
+      }
+      if constexpr (NEAR) {
+        wave_sync();
+        if (r2m < thr) {
+          // rare: for every pair of the lane's i closer than the larger repair
+          // radius of its two particles, the rounded-position term is replaced
+          // by the float-float one on both sides.  The j are visited in the
+          // rotated order of the pair loop, so at each step the lanes of a row
+          // touch distinct j; the four rows, which share the j, take turns.
+          for (int jj = 0; jj < 64; ++jj) {
+            const int q = jj >> 4;
+            const int jl = q * kSR + ((rl + jj) & (kSR - 1));
+            const float4 r = s_hi[wv][q][jl & (kSR - 1)];
+            const float4 ql = s_lo[wv][jl];
+            const float dx = r.x - ip.x, dy = r.y - ip.y, dz = r.z - ip.z;
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            float cx = 0.f, cy = 0.f, cz = 0.f;
+            if (r2 < fmaxf(iq.w, ql.w)) {
+              const float ex = dx + (ql.x - iq.x), ey = dy + (ql.y - iq.y), ez = dz + (ql.z - iq.z);
+              const float ri = rsqrt32(r2);
+              const float ri3 = (ri * ri) * ri;
+              const float q2 = fmaf(ez, ez, fmaf(ey, ey, fmaf(ex, ex, e2)));
+              const float qi = rsqrt32(q2);
+              const float qi3 = (qi * qi) * qi;
+              // float-float term minus rounded term, per unit mass
+              const float fx3 = fmaf(qi3, ex, -(ri3 * dx));
+              const float fy3 = fmaf(qi3, ey, -(ri3 * dy));
+              const float fz3 = fmaf(qi3, ez, -(ri3 * dz));
+              px = fmaf(r.w, fx3, px);
+              py = fmaf(r.w, fy3, py);
+              pz = fmaf(r.w, fz3, pz);
+              cx = mneg * fx3;
+              cy = mneg * fy3;
+              cz = mneg * fz3;
+            }
+            for (int rr = 0; rr < 4; ++rr) {
+              if (row == rr && (cx != 0.f || cy != 0.f || cz != 0.f)) {
+                s_j[wv][0][jl] += cx;
+                s_j[wv][1][jl] += cy;
+                s_j[wv][2][jl] += cz;
+              }
+            }
+          }
+        }
+      }
+      fold(hx, lx, px);
+      fold(hy, ly, py);
+      fold(hz, lz, pz);
+      wave_sync();
+      float* dst = slots + S.sbase + (size_t)(d - 1) * 3 * npad + (size_t)J * 64 + lane;
+      dst[0] = s_j[wv][0][lane];
+      dst[npad] = s_j[wv][1][lane];
+      dst[2 * npad] = s_j[wv][2][lane];
+    }
+    if (valid) {
+      const int64_t i = S.o + il;
+      a[i] = (double)hx + (double)lx;
+      a[total + i] = (double)hy + (double)ly;
+      a[2 * total + i] = (double)hz + (double)lz;
+    }
+  }
+}
+
+// a = G (i-side sum + the particle's j-side slots in distance order), in FP64;
+// one thread per (particle, component: blockIdx.y), the slots loaded eight at
+// a time.  Only the largest distance can be missing: the slot of a block whose
+// partner at distance dmax lies in the upper half of an even ring (that block
+// pair is visited from the lower half only, where it is distance dmax the
+// other way).
+__global__ void esym_reduce_kernel(int nitems, const EItem* __restrict__ items, const ESys* __restrict__ sys,
+                                   int64_t total, const float* __restrict__ slots, double* __restrict__ a, double G) {
+  const int c = blockIdx.y;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nitems * 64;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const EItem it = items[g >> 6];
+    const int lane = (int)(g & 63);
+    if (lane >= it.ni) continue;
+    const ESys& S = sys[it.sys];
+    const int p = it.b * 64 + lane;
+    const int64_t i = S.o + p;
+    const size_t npad = (size_t)S.nb * 64;
+    int dn = S.dmax;
+    if (S.half && dn > 0) {
+      int src = it.b - S.dmax;
+      if (src < 0) src += S.nb;
+      if (src >= S.nb / 2) --dn;
+    }
+    const size_t stride = 3 * npad;
+    const float* q = slots + S.sbase + c * npad + p;
+    double acc = a[c * total + i];
+    int d = 0;
+    for (; d + 8 <= dn; d += 8) {
+      float f[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f[u] = q[(size_t)(d + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)f[u];
+    }
+    for (; d < dn; ++d) acc += (double)q[(size_t)d * stride];
+    a[c * total + i] = G * acc;
+  }
+}
+
+// ------------------------------------------------------------------ plans
+struct EPlan {
+  std::vector<int64_t> off;
+  std::vector<double> eps;
+  int precision = 0, device = 0, ncl = 0, nwg = 0, nitems = 0;
+  int64_t total = 0;
+  ESys* d_sys = nullptr;
+  EItem* d_items = nullptr;
+  int* d_wg_off = nullptr;
+  int* d_wg_list = nullptr;
+  float4* d_rhi = nullptr;
+  float4* d_rlo = nullptr;
+  float* d_slots = nullptr;
+};
+
+std::mutex g_eplan_mu;
+std::vector<EPlan*> g_eplans;
+
+void free_eplan(EPlan* p) {
+  for (void* q : {(void*)p->d_sys, (void*)p->d_items, (void*)p->d_wg_off, (void*)p->d_wg_list, (void*)p->d_rhi,
+                  (void*)p->d_rlo, (void*)p->d_slots})
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+template <typename T>
+bool eupload(T** dst, const std::vector<T>& src) {
+  const size_t bytes = sizeof(T) * std::max<size_t>(1, src.size());
+  if (hipMalloc(dst, bytes) != hipSuccess) return false;
+  return src.empty() || hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// Bytes of j-side slots the layout needs: per system, dmax distances x 3
+// components x its padded particle count, in FP32.
+size_t esym_slot_bytes(int32_t ncl, const int64_t* off) {
+  size_t f = 0;
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nb = (off[c + 1] - off[c] + 63) / 64;
+    f += (size_t)(nb / 2) * 3 * (size_t)nb * 64;
+  }
+  return f * sizeof(float);
+}
+
+// Items: every system cut into blocks of 64; an item's cost is its ordered block
+// (64 pairs per lane, counted at 3/4 of a symmetric step) plus 64 steps per ring
+// distance plus a fixed set-up; items go longest first to the least loaded
+// workgroup, and each workgroup's list stays in decreasing cost (the order its
+// waves take them in).
+int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, EPlan** out) {
+  EPlan* p = new EPlan();
+  p->off.assign(off, off + ncl + 1);
+  p->eps.assign(eps, eps + ncl);
+  p->precision = precision;
+  p->device = device;
+  p->ncl = ncl;
+  p->total = off[ncl];
+  std::vector<ESys> sys(std::max(1, ncl));
+  std::vector<EItem> items;
+  std::vector<double> cost;
+  int64_t sbase = 0;
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nc = off[c + 1] - off[c];
+    ESys& S = sys[c];
+    S.o = off[c];
+    S.sbase = sbase;
+    S.eps = eps[c];
+    S.nc = (int)nc;
+    S.nb = (int)((nc + 63) / 64);
+    S.dmax = S.nb / 2;
+    S.half = S.nb % 2 == 0 ? 1 : 0;
+    S.fx = std::max(kNearX, kNearN / std::cbrt((float)std::max<int64_t>(1, nc)));
+    S.pad = 0;
+    sbase += (int64_t)S.dmax * 3 * S.nb * 64;
+    for (int b = 0; b < S.nb; ++b) {
+      const int dend = (S.half && b >= S.nb / 2) ? S.dmax : S.dmax + 1;
+      items.push_back(EItem{c, b, (int)std::min<int64_t>(64, nc - (int64_t)b * 64), dend});
+      cost.push_back(48.0 + 64.0 * (dend - 1) + 32.0);
+    }
+  }
+  int per_cu = 0, per_cu1 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&esym_force_kernel<true, false>),
+                                                   kEBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, reinterpret_cast<const void*>(&esym_force_kernel<true, true>),
+                                                   kEBlock, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = per_cu1 = 1;
+  }
+  per_cu = std::max(1, std::min(kEMaxPerCu, std::min(per_cu, per_cu1)));
+  const int cap_wg = std::max(1, per_cu * cu_count(device));
+  const int nwg = std::max(1, std::min<int>((int)((items.size() + kEWaves - 1) / kEWaves), cap_wg));
+  std::vector<int> order(items.size());
+  for (size_t k = 0; k < items.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int w) { return cost[u] > cost[w]; });
+  std::vector<std::vector<int>> lists(nwg);
+  using Slot = std::pair<double, int>;
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+  for (int w = 0; w < nwg; ++w) heap.push({0.0, w});
+  for (int k : order) {
+    Slot sl = heap.top();
+    heap.pop();
+    lists[sl.second].push_back(k);
+    heap.push({sl.first + cost[k], sl.second});
+  }
+  std::vector<int> wg_off(nwg + 1, 0), wg_list;
+  for (int w = 0; w < nwg; ++w) {
+    wg_list.insert(wg_list.end(), lists[w].begin(), lists[w].end());
+    wg_off[w + 1] = (int)wg_list.size();
+  }
+  p->nwg = nwg;
+  p->nitems = (int)items.size();
+  const size_t nrec = (size_t)std::max<int64_t>(1, p->total);
+  bool ok = eupload(&p->d_sys, sys) && eupload(&p->d_items, items) && eupload(&p->d_wg_off, wg_off) &&
+            eupload(&p->d_wg_list, wg_list) && hipMalloc(&p->d_rhi, nrec * sizeof(float4)) == hipSuccess &&
+            hipMalloc(&p->d_rlo, nrec * sizeof(float4)) == hipSuccess &&
+            hipMalloc(&p->d_slots, sizeof(float) * (size_t)std::max<int64_t>(1, sbase)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_eplan(p);
+    return set_error(NBODY_ENOMEM, "batched: plan upload failed");
+  }
+  *out = p;
+  return NBODY_OK;
+}
+
+EPlan* find_eplan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
+  for (EPlan* p : g_eplans) {
+    if (p->device != device || p->precision != precision || p->ncl != ncl) continue;
+    if (std::equal(p->off.begin(), p->off.end(), off) && std::equal(p->eps.begin(), p->eps.end(), eps)) return p;
+  }
+  return nullptr;
+}
+
+template <bool NEAR>
+int launch_esteps(const EPlan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
+                  double G, bool acc_valid, bool excl, hipStream_t s) {
+  if (p->total == 0 || (nsteps == 0 && acc_valid)) return NBODY_OK;
+  const double h = 0.5 * dt;
+  const unsigned ew = (unsigned)std::min<int64_t>(((int64_t)p->nitems * 64 + 255) / 256, 4096);
+  const unsigned kw = (unsigned)std::min<int64_t>((3 * p->total + 255) / 256, 4096);
+  auto step = [&](int kicks) -> int {
+    esym_publish_kernel<NEAR><<<ew, 256, 0, s>>>(p->nitems, p->d_items, p->d_sys, p->total, x, v, a, m, p->d_rhi,
+                                                  p->d_rlo, h, dt, kicks);
+    NB_LAUNCH_CHECK("esym_publish_kernel");
+    if (excl)
+      esym_force_kernel<NEAR, true><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
+                                                               p->d_rhi, p->d_rlo, a, p->d_slots, p->total);
+    else
+      esym_force_kernel<NEAR, false><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
+                                                                p->d_rhi, p->d_rlo, a, p->d_slots, p->total);
+    NB_LAUNCH_CHECK("esym_force_kernel");
+    esym_reduce_kernel<<<dim3(ew, 3), 256, 0, s>>>(p->nitems, p->d_items, p->d_sys, p->total, p->d_slots, a, G);
+    NB_LAUNCH_CHECK("esym_reduce_kernel");
+    return NBODY_OK;
+  };
+  int st;
+  if (!acc_valid && (st = step(0))) return st;
+  for (int64_t k = 0; k < nsteps; ++k)
+    if ((st = step(k == 0 ? 1 : 2))) return st;
+  if (nsteps > 0) {
+    esym_kick_kernel<<<kw, 256, 0, s>>>(p->total, v, a, h);
+    NB_LAUNCH_CHECK("esym_kick_kernel");
+  }
+  return NBODY_OK;
+}
+
+}  // namespace
+
+int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                       const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
+                       bool acc_valid, int bitem, bool per_step, hipStream_t s);
+
+// Mode 4.  FP64, and layouts whose slots would exceed kESlotCap, run the
+// ordered per-step wave items (mode 3) instead.
+int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
+                    const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
+                    hipStream_t s) {
+  if (precision == NBODY_FP64 || esym_slot_bytes(ncl, off) > kESlotCap)
+    return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, 64, true, s);
+  for (int c = 0; c < ncl; ++c)
+    if (off[c + 1] - off[c] > (int64_t(1) << 24))
+      return set_error(NBODY_EUNSUPPORTED, "batched: a system of more than 2^24 particles");
+  const int device = current_device();
+  std::lock_guard<std::mutex> lk(g_eplan_mu);
+  EPlan* p = find_eplan(ncl, off, eps, precision, device);
+  if (!p) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return set_error(NBODY_EINVAL, "batched: the plan for this layout must be built by one call outside stream capture");
+    int st = build_eplan(ncl, off, eps, precision, device, &p);
+    if (st) return st;
+    g_eplans.push_back(p);
+  }
+  if (precision == NBODY_FP32C) return launch_esteps<true>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  return launch_esteps<false>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+}
+
+void release_sym_ensemble_plans() {
+  std::lock_guard<std::mutex> lk(g_eplan_mu);
+  for (EPlan* p : g_eplans) free_eplan(p);
+  g_eplans.clear();
+}
+
+}  // namespace nb

@@ -143,7 +143,7 @@ def test_set_config_validation(lib):
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(split=5000)
     with pytest.raises(nb.NBodyError):
-        nb.nbody_set_config(bsplit=4)
+        nb.nbody_set_config(bsplit=5)
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(bpass=3)
     with pytest.raises(nb.NBodyError):
@@ -151,5 +151,6 @@ def test_set_config_validation(lib):
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(bitem=32)
     nb.nbody_set_config(bsplit=2, bitem=64)
+    nb.nbody_set_config(bsplit=4)
     nb.nbody_set_config(ipl=2, split=4)
     nb.nbody_set_config()

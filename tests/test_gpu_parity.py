@@ -361,7 +361,7 @@ def _stream(nb, fn, bitem=0, mode=2):
         nb.nbody_set_config()
 
 
-@pytest.mark.parametrize("mode,bitem", [(2, 1024), (2, 64), (3, 0)])
+@pytest.mark.parametrize("mode,bitem", [(2, 1024), (2, 64), (3, 0), (4, 0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_stream_batched_matches_oracle(nb, oracle_mod, prec, mode, bitem):
     """Streamed ensemble kernels against the oracle's KDK: items of <= 1024
@@ -492,7 +492,7 @@ def test_tune_batched_records_and_applies_choice(nb):
     off, epsv, x, v, m = ics.ensemble(len(sizes), seed=27, sizes=sizes)
     tx, tv, tm = dev(x), dev(v), dev(m)
     best = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 4, precision="fp32c")
-    assert best["bsplit"] in (0, 1, 2, 3) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 64, 256, 512, 1024)
+    assert best["bsplit"] in (0, 1, 2, 3, 4) and best["bpass"] in (0, 1, 2, 4) and best["bitem"] in (0, 64, 256, 512, 1024)
     assert torch.equal(tx, dev(x)) and torch.equal(tv, dev(v))
     out = []
     for forced in (False, True):
@@ -509,6 +509,8 @@ def test_tune_batched_records_and_applies_choice(nb):
     # the search without co-residency returns a configuration that needs none (resident kernel or per-step items)
     best0 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp64", allow_cooperative=False)
     assert best0["bsplit"] in (0, 3)
+    best2 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp32c", allow_cooperative=False)
+    assert best2["bsplit"] in (0, 3, 4)
     # the single-launch search returns a configuration that runs all steps in one launch
     best1 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp32c",
                                   allow_cooperative="persistent")
