@@ -16,12 +16,16 @@
 //     j at step 0 and moves there through a DPP row rotation fused into the
 //     add; after a sub-block the four rows' sums of its 16 j are added on the
 //     LDS pipe; the J-block's 64 sums go to the system's slot for distance d.
-// Each step is three launches: publish (the kicks, the drift and the pair
-// records of the new positions), force (the i-side sums into a, unscaled; the
-// j-side sums into the slots) and reduce (per particle, its i-side sum plus its
-// slots in distance order, in FP64, times G), so results are reproducible.
-// Items are placed longest first over the workgroups and a workgroup's waves
-// take its items from an LDS counter.  FP32C positions are rounded to FP32 and
+// A block's distances (0, the block itself, to its last ring distance) are cut
+// into parts of a few distances, one item each, so that the items of the
+// largest systems are not much longer than the rest.  Each step is three
+// launches: publish (the kicks, the drift and the pair records of the new
+// positions), force (each item's i-side sums into a for the first part, else
+// into its part's slot, the j-side sums into the distance slots) and reduce
+// (per particle, its part sums in part order, then its distance slots in
+// distance order, in FP64, times G), so
+// results are reproducible.  Items are placed longest first over the
+// workgroups and a workgroup's waves take its items from an LDS counter.  FP32C positions are rounded to FP32 and
 // the near-field rule of the ordered kernels applies: in the ordered block a
 // pair closer than particle i's repair radius, in a block pair a pair closer
 // than the larger radius of its two particles, gets float-float displacements.
@@ -42,23 +46,34 @@ constexpr int kEOcc = 8;               // waves per SIMD the force kernel is bui
 constexpr int kEMaxPerCu = 2;          // resident workgroups per CU at most
 constexpr size_t kESlotCap = size_t(1) << 30;  // bytes of j-side slots a plan may hold
 
+// A block of 64 particles of a system, or (in the force kernel's work list)
+// one part of its distances: [d0, d1), distance 0 being the block with itself.
 struct EItem {
-  int sys;  // system
-  int b;    // block of 64 particles within the system
-  int ni;   // particles in the block
-  int dend; // ring distances 1 .. dend - 1
+  int sys;   // system
+  int b;     // block of 64 particles within the system
+  int ni;    // particles in the block
+  int d0, d1;
+  int part;  // index of the part among the block's parts
 };
 
 // Per-system geometry: particles [o, o + nc) of the concatenated arrays, nb
-// blocks of 64, slots [dmax][3][nb * 64] floats from sbase.
+// blocks of 64, j-side slots [dmax][3][nb * 64] floats from sbase, i-side
+// slots [parts - 1][3][nb * 64] doubles from ibase for the parts after the
+// first (a block's distances cut into parts of lp).
 struct ESys {
   int64_t o;
   int64_t sbase;
+  int64_t ibase;
   double eps;
   int nc, nb, dmax, half;
   float fx;  // repair-radius factor max(kNearX, kNearN nc^-1/3)
-  int pad;
+  int lp;
 };
+
+// End of block b's distances: 0 (itself) .. dend - 1.
+__host__ __device__ inline int esym_dend(const ESys& S, int b) {
+  return (S.half && b >= S.nb / 2) ? S.dmax : S.dmax + 1;
+}
 
 // Orders a wave's LDS accesses around a rewrite by other lanes (LDS
 // instructions of one wave execute in order; this keeps the compiler from
@@ -75,14 +90,14 @@ __device__ __forceinline__ void wave_sync() {
 // hi = (x, y, z, m) rounded to FP32, lo = (x - hi, y - hi, z - hi, repair
 // radius^2, or -1 without the repair).
 template <bool NEAR>
-__global__ void esym_publish_kernel(int nitems, const EItem* __restrict__ items, const ESys* __restrict__ sys,
+__global__ void esym_publish_kernel(int nblocks, const EItem* __restrict__ blocks, const ESys* __restrict__ sys,
                                     int64_t total, double* __restrict__ x, double* __restrict__ v,
                                     const double* __restrict__ a, const double* __restrict__ m,
                                     float4* __restrict__ rhi, float4* __restrict__ rlo, double h, double dt,
                                     int kicks) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nitems * 64;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nblocks * 64;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const EItem it = items[g >> 6];
+    const EItem it = blocks[g >> 6];
     const int lane = (int)(g & 63);
     if (lane >= it.ni) continue;
     const ESys& S = sys[it.sys];
@@ -151,7 +166,7 @@ template <bool NEAR, bool EXCL>
 __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
     const ESys* __restrict__ sys, const EItem* __restrict__ items, const int* __restrict__ wg_off,
     const int* __restrict__ wg_list, const float4* __restrict__ rhi, const float4* __restrict__ rlo,
-    double* __restrict__ a, float* __restrict__ slots, int64_t total) {
+    double* __restrict__ a, double* __restrict__ islot, float* __restrict__ slots, int64_t total) {
   __shared__ float4 s_hi[kEWaves][4][2 * kSR];  // (x, y, z, m) hi parts, each sub-block twice
   __shared__ float4 s_lo[kEWaves][64];          // lo parts and the repair radius^2
   __shared__ float s_j[kEWaves][3][64];         // the block pair's j-side sums
@@ -160,8 +175,6 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
   const int wv = t >> 6, lane = t & 63, rl = lane & (kSR - 1), row = lane >> 4;
   const int xor32 = (lane ^ 32) * 4;
   const int q0 = wg_off[blockIdx.x], q1 = wg_off[blockIdx.x + 1];
-  const float4 far_hi = make_float4((float)kFarAway, (float)kFarAway, (float)kFarAway, 0.f);
-  const float4 far_lo = make_float4(0.f, 0.f, 0.f, -1.f);
   if (t == 0) next_item = 0;
   __syncthreads();
   for (;;) {
@@ -177,8 +190,18 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
     const float e2 = (float)(S.eps * S.eps);
     const int il = it.b * 64 + lane;
     const bool valid = lane < it.ni;
-    const float4 ip = valid ? hs[il] : far_hi;
-    const float4 iq = valid ? ls[il] : far_lo;
+    // padding (past the system's end): far away, massless, never repaired
+    auto load = [&](int j, float4& rh, float4& rq) {
+      if (j < nc) {
+        rh = hs[j];
+        rq = ls[j];
+      } else {
+        rh = make_float4((float)kFarAway, (float)kFarAway, (float)kFarAway, 0.f);
+        rq = make_float4(0.f, 0.f, 0.f, -1.f);
+      }
+    };
+    float4 ip, iq;
+    load(valid ? il : nc, ip, iq);
     const float mneg = -ip.w;
     // flags a block pair for the repair: every pair inside the larger radius of
     // its two particles is inside this one (|d| < f |x_j| with |x_j| <= |x_i| + |d|
@@ -186,11 +209,7 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
     const float thr = (NEAR && valid)
                           ? sym_rc2((double)ip.x, (double)ip.y, (double)ip.z, S.eps, S.fx / (1.0f - S.fx) * 1.0001f)
                           : -1.f;
-    auto fetch = [&](int J, float4& rh, float4& rq) {
-      const int jl = J * 64 + lane;
-      rh = jl < nc ? hs[jl] : far_hi;
-      rq = jl < nc ? ls[jl] : far_lo;
-    };
+    auto fetch = [&](int J, float4& rh, float4& rq) { load(J * 64 + lane, rh, rq); };
     auto put = [&](const float4& rh, const float4& rq) {
       wave_sync();
       s_hi[wv][row][rl] = rh;
@@ -200,10 +219,13 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
     };
     float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
     float4 nh, nq;
-    fetch(it.b, nh, nq);
-    put(nh, nq);
-    if (1 < it.dend) fetch(it.b + 1 < nb ? it.b + 1 : it.b + 1 - nb, nh, nq);
-    {
+    const int r0 = it.d0 > 0 ? it.d0 : 1;  // first distance of the ring in this part
+    if (it.d0 == 0) {
+      fetch(it.b, nh, nq);
+      put(nh, nq);
+    }
+    if (r0 < it.d1) fetch(it.b + r0 < nb ? it.b + r0 : it.b + r0 - nb, nh, nq);
+    if (it.d0 == 0) {
       // the block with itself: ordered pairs, i-side only
       float px = 0.f, py = 0.f, pz = 0.f, r2min = 3.0e38f;
 #pragma unroll 16
@@ -253,10 +275,10 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
     }
     const size_t npad = (size_t)nb * 64;
 #pragma unroll 1
-    for (int d = 1; d < it.dend; ++d) {
+    for (int d = r0; d < it.d1; ++d) {
       const int J = it.b + d < nb ? it.b + d : it.b + d - nb;
       put(nh, nq);
-      if (d + 1 < it.dend) fetch(J + 1 < nb ? J + 1 : J + 1 - nb, nh, nq);
+      if (d + 1 < it.d1) fetch(J + 1 < nb ? J + 1 : J + 1 - nb, nh, nq);
       float px = 0.f, py = 0.f, pz = 0.f, r2m = 3.0e38f;
 #pragma unroll 1
       for (int q = 0; q < 4; ++q) {
@@ -330,26 +352,30 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
       dst[2 * npad] = s_j[wv][2][lane];
     }
     if (valid) {
-      const int64_t i = S.o + il;
-      a[i] = (double)hx + (double)lx;
-      a[total + i] = (double)hy + (double)ly;
-      a[2 * total + i] = (double)hz + (double)lz;
+      // part 0 (the one with the block itself) writes a, unscaled; the others their slots
+      double* o = it.part == 0 ? a + S.o + il : islot + S.ibase + (size_t)(it.part - 1) * 3 * npad + il;
+      const size_t st = it.part == 0 ? (size_t)total : npad;
+      o[0] = (double)hx + (double)lx;
+      o[st] = (double)hy + (double)ly;
+      o[2 * st] = (double)hz + (double)lz;
     }
   }
 }
 
-// a = G (i-side sum + the particle's j-side slots in distance order), in FP64;
+// a = G (the particle's i-side sums in part order, part 0 in a itself, + its
+// j-side slots in distance order), in FP64;
 // one thread per (particle, component: blockIdx.y), the slots loaded eight at
 // a time.  Only the largest distance can be missing: the slot of a block whose
 // partner at distance dmax lies in the upper half of an even ring (that block
 // pair is visited from the lower half only, where it is distance dmax the
 // other way).
-__global__ void esym_reduce_kernel(int nitems, const EItem* __restrict__ items, const ESys* __restrict__ sys,
-                                   int64_t total, const float* __restrict__ slots, double* __restrict__ a, double G) {
+__global__ void esym_reduce_kernel(int nblocks, const EItem* __restrict__ blocks, const ESys* __restrict__ sys,
+                                   int64_t total, const double* __restrict__ islot, const float* __restrict__ slots,
+                                   double* __restrict__ a, double G) {
   const int c = blockIdx.y;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nitems * 64;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nblocks * 64;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const EItem it = items[g >> 6];
+    const EItem it = blocks[g >> 6];
     const int lane = (int)(g & 63);
     if (lane >= it.ni) continue;
     const ESys& S = sys[it.sys];
@@ -363,8 +389,11 @@ __global__ void esym_reduce_kernel(int nitems, const EItem* __restrict__ items, 
       if (src >= S.nb / 2) --dn;
     }
     const size_t stride = 3 * npad;
-    const float* q = slots + S.sbase + c * npad + p;
+    const int np = (esym_dend(S, it.b) + S.lp - 1) / S.lp;
+    const double* iq = islot + S.ibase + c * npad + p;
     double acc = a[c * total + i];
+    for (int k = 1; k < np; ++k) acc += iq[(size_t)(k - 1) * stride];
+    const float* q = slots + S.sbase + c * npad + p;
     int d = 0;
     for (; d + 8 <= dn; d += 8) {
       float f[8];
@@ -382,10 +411,12 @@ __global__ void esym_reduce_kernel(int nitems, const EItem* __restrict__ items, 
 struct EPlan {
   std::vector<int64_t> off;
   std::vector<double> eps;
-  int precision = 0, device = 0, ncl = 0, nwg = 0, nitems = 0;
+  int precision = 0, device = 0, ncl = 0, nwg = 0, nblocks = 0;
   int64_t total = 0;
   ESys* d_sys = nullptr;
-  EItem* d_items = nullptr;
+  EItem* d_blocks = nullptr;  // one per block of 64 (publish, reduce)
+  EItem* d_items = nullptr;   // the parts (force)
+  double* d_islot = nullptr;
   int* d_wg_off = nullptr;
   int* d_wg_list = nullptr;
   float4* d_rhi = nullptr;
@@ -397,7 +428,7 @@ std::mutex g_eplan_mu;
 std::vector<EPlan*> g_eplans;
 
 void free_eplan(EPlan* p) {
-  for (void* q : {(void*)p->d_sys, (void*)p->d_items, (void*)p->d_wg_off, (void*)p->d_wg_list, (void*)p->d_rhi,
+  for (void* q : {(void*)p->d_sys, (void*)p->d_blocks, (void*)p->d_items, (void*)p->d_islot, (void*)p->d_wg_off, (void*)p->d_wg_list, (void*)p->d_rhi,
                   (void*)p->d_rlo, (void*)p->d_slots})
     if (q) (void)hipFree(q);
   delete p;
@@ -421,11 +452,14 @@ size_t esym_slot_bytes(int32_t ncl, const int64_t* off) {
   return f * sizeof(float);
 }
 
-// Items: every system cut into blocks of 64; an item's cost is its ordered block
-// (64 pairs per lane, counted at 3/4 of a symmetric step) plus 64 steps per ring
-// distance plus a fixed set-up; items go longest first to the least loaded
-// workgroup, and each workgroup's list stays in decreasing cost (the order its
-// waves take them in).
+// Blocks: every system cut into blocks of 64.  Items: each block's distances
+// 0 .. dend - 1 cut into parts of lp, lp chosen so that the parts number about
+// four per wave the launch holds (whole half rings of the largest systems would
+// leave a few long items at the end of the step).  An item's cost is 48 for
+// its ordered block (64 pairs per lane at about 3/4 of a symmetric step) plus
+// 64 per ring distance plus a fixed 32; items go longest first to the least
+// loaded workgroup, and each workgroup's list stays in decreasing cost (the
+// order its waves take them in).
 int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precision, int device, EPlan** out) {
   EPlan* p = new EPlan();
   p->off.assign(off, off + ncl + 1);
@@ -434,29 +468,6 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   p->device = device;
   p->ncl = ncl;
   p->total = off[ncl];
-  std::vector<ESys> sys(std::max(1, ncl));
-  std::vector<EItem> items;
-  std::vector<double> cost;
-  int64_t sbase = 0;
-  for (int c = 0; c < ncl; ++c) {
-    const int64_t nc = off[c + 1] - off[c];
-    ESys& S = sys[c];
-    S.o = off[c];
-    S.sbase = sbase;
-    S.eps = eps[c];
-    S.nc = (int)nc;
-    S.nb = (int)((nc + 63) / 64);
-    S.dmax = S.nb / 2;
-    S.half = S.nb % 2 == 0 ? 1 : 0;
-    S.fx = std::max(kNearX, kNearN / std::cbrt((float)std::max<int64_t>(1, nc)));
-    S.pad = 0;
-    sbase += (int64_t)S.dmax * 3 * S.nb * 64;
-    for (int b = 0; b < S.nb; ++b) {
-      const int dend = (S.half && b >= S.nb / 2) ? S.dmax : S.dmax + 1;
-      items.push_back(EItem{c, b, (int)std::min<int64_t>(64, nc - (int64_t)b * 64), dend});
-      cost.push_back(48.0 + 64.0 * (dend - 1) + 32.0);
-    }
-  }
   int per_cu = 0, per_cu1 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&esym_force_kernel<true, false>),
                                                    kEBlock, 0) != hipSuccess ||
@@ -467,6 +478,42 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   }
   per_cu = std::max(1, std::min(kEMaxPerCu, std::min(per_cu, per_cu1)));
   const int cap_wg = std::max(1, per_cu * cu_count(device));
+  std::vector<ESys> sys(std::max(1, ncl));
+  int64_t work = 0;  // block distances (the ordered block counted as one)
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nb = (off[c + 1] - off[c] + 63) / 64;
+    work += nb * (nb / 2) + nb - ((nb % 2 == 0) ? nb / 2 : 0);
+  }
+  const int lp = (int)std::max<int64_t>(4, std::min<int64_t>(64, work / (4 * (int64_t)cap_wg * kEWaves)));
+  std::vector<EItem> blocks, items;
+  std::vector<double> cost;
+  int64_t sbase = 0, ibase = 0;
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nc = off[c + 1] - off[c];
+    ESys& S = sys[c];
+    S.o = off[c];
+    S.sbase = sbase;
+    S.ibase = ibase;
+    S.eps = eps[c];
+    S.nc = (int)nc;
+    S.nb = (int)((nc + 63) / 64);
+    S.dmax = S.nb / 2;
+    S.half = S.nb % 2 == 0 ? 1 : 0;
+    S.fx = std::max(kNearX, kNearN / std::cbrt((float)std::max<int64_t>(1, nc)));
+    S.lp = lp;
+    sbase += (int64_t)S.dmax * 3 * S.nb * 64;
+    ibase += (int64_t)((S.dmax + 1 + lp - 1) / lp - 1) * 3 * S.nb * 64;
+    for (int b = 0; b < S.nb; ++b) {
+      const int ni = (int)std::min<int64_t>(64, nc - (int64_t)b * 64);
+      const int dend = esym_dend(S, b);
+      blocks.push_back(EItem{c, b, ni, 0, dend, 0});
+      for (int d0 = 0, part = 0; d0 < dend; d0 += lp, ++part) {
+        const int d1 = std::min(dend, d0 + lp);
+        items.push_back(EItem{c, b, ni, d0, d1, part});
+        cost.push_back((d0 == 0 ? 48.0 : 0.0) + 64.0 * (d1 - std::max(d0, 1)) + 32.0);
+      }
+    }
+  }
   const int nwg = std::max(1, std::min<int>((int)((items.size() + kEWaves - 1) / kEWaves), cap_wg));
   std::vector<int> order(items.size());
   for (size_t k = 0; k < items.size(); ++k) order[k] = (int)k;
@@ -487,9 +534,10 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
     wg_off[w + 1] = (int)wg_list.size();
   }
   p->nwg = nwg;
-  p->nitems = (int)items.size();
+  p->nblocks = (int)blocks.size();
   const size_t nrec = (size_t)std::max<int64_t>(1, p->total);
-  bool ok = eupload(&p->d_sys, sys) && eupload(&p->d_items, items) && eupload(&p->d_wg_off, wg_off) &&
+  bool ok = eupload(&p->d_sys, sys) && eupload(&p->d_blocks, blocks) && eupload(&p->d_items, items) &&
+            hipMalloc(&p->d_islot, sizeof(double) * (size_t)std::max<int64_t>(1, ibase)) == hipSuccess && eupload(&p->d_wg_off, wg_off) &&
             eupload(&p->d_wg_list, wg_list) && hipMalloc(&p->d_rhi, nrec * sizeof(float4)) == hipSuccess &&
             hipMalloc(&p->d_rlo, nrec * sizeof(float4)) == hipSuccess &&
             hipMalloc(&p->d_slots, sizeof(float) * (size_t)std::max<int64_t>(1, sbase)) == hipSuccess;
@@ -515,20 +563,21 @@ int launch_esteps(const EPlan* p, double* x, double* v, double* a, const double*
                   double G, bool acc_valid, bool excl, hipStream_t s) {
   if (p->total == 0 || (nsteps == 0 && acc_valid)) return NBODY_OK;
   const double h = 0.5 * dt;
-  const unsigned ew = (unsigned)std::min<int64_t>(((int64_t)p->nitems * 64 + 255) / 256, 4096);
+  const unsigned ew = (unsigned)std::min<int64_t>(((int64_t)p->nblocks * 64 + 255) / 256, 4096);
   const unsigned kw = (unsigned)std::min<int64_t>((3 * p->total + 255) / 256, 4096);
   auto step = [&](int kicks) -> int {
-    esym_publish_kernel<NEAR><<<ew, 256, 0, s>>>(p->nitems, p->d_items, p->d_sys, p->total, x, v, a, m, p->d_rhi,
+    esym_publish_kernel<NEAR><<<ew, 256, 0, s>>>(p->nblocks, p->d_blocks, p->d_sys, p->total, x, v, a, m, p->d_rhi,
                                                   p->d_rlo, h, dt, kicks);
     NB_LAUNCH_CHECK("esym_publish_kernel");
     if (excl)
       esym_force_kernel<NEAR, true><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
-                                                               p->d_rhi, p->d_rlo, a, p->d_slots, p->total);
+                                                               p->d_rhi, p->d_rlo, a, p->d_islot, p->d_slots, p->total);
     else
       esym_force_kernel<NEAR, false><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
-                                                                p->d_rhi, p->d_rlo, a, p->d_slots, p->total);
+                                                                p->d_rhi, p->d_rlo, a, p->d_islot, p->d_slots, p->total);
     NB_LAUNCH_CHECK("esym_force_kernel");
-    esym_reduce_kernel<<<dim3(ew, 3), 256, 0, s>>>(p->nitems, p->d_items, p->d_sys, p->total, p->d_slots, a, G);
+    esym_reduce_kernel<<<dim3(ew, 3), 256, 0, s>>>(p->nblocks, p->d_blocks, p->d_sys, p->total, p->d_islot,
+                                                   p->d_slots, a, G);
     NB_LAUNCH_CHECK("esym_reduce_kernel");
     return NBODY_OK;
   };
