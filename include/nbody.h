@@ -252,7 +252,8 @@ typedef struct nbody_config {
                       launches its half ring of block pairs is cut into */
   int32_t bsplit;  /* batched kernel, used when any of bsplit, bpass, bitem is
                       non-zero (all zero: the tuned choice for the layout, else
-                      mode 3): 0 = one workgroup per system, its records
+                      mode 4 for FP32C and FP32 when the layout's block pairs
+                      outnumber its blocks of 64, else mode 3): 0 = one workgroup per system, its records
                       resident in LDS (force it with bpass); 1 = as 0, but systems costlier than
                       the per-CU average split across up to 4 workgroups that
                       exchange positions every step; 2 = streamed: every system cut

@@ -22,6 +22,7 @@ int run_traj_grad(int64_t n, const double* ckx, const double* ckv, int64_t every
 void release_batched_plans();
 void release_stream_plans();
 void release_sym_ensemble_plans();
+bool sym_ensemble_default(int32_t ncl, const int64_t* off);
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -270,8 +271,9 @@ std::mutex g_tb_mu;
 std::vector<TunedBatch> g_tuned_batch;
 
 // The thread's forced configuration if it sets any batched field, else the
-// tuned one for this layout, else the per-step wave items (mode 3: the fastest
-// of the modes that need no co-resident workgroups on every measured layout).
+// tuned one for this layout, else the per-step wave items: their symmetric form
+// (mode 4) for FP32C/FP32 layouts whose systems mostly span several blocks of
+// 64, else the ordered form (mode 3).
 BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
   const nbody_config& t = t_cfg;
   BatchConfig bc;
@@ -286,7 +288,7 @@ BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps,
     if (e.device == device && e.precision == precision && (int)e.eps.size() == ncl &&
         std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps))
       return e.bc;
-  bc.mode = 3;
+  bc.mode = (precision != NBODY_FP64 && sym_ensemble_default(ncl, off)) ? 4 : 3;
   return bc;
 }
 

@@ -623,6 +623,20 @@ int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* 
   return launch_esteps<false>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
 }
 
+// The untuned default takes the symmetric items when the layout's block pairs
+// outnumber its blocks (its systems mostly span several blocks of 64): a
+// layout of single-block systems has no pair to save and would only pay the
+// third launch.
+bool sym_ensemble_default(int32_t ncl, const int64_t* off) {
+  int64_t blocks = 0, ring = 0;
+  for (int c = 0; c < ncl; ++c) {
+    const int64_t nb = (off[c + 1] - off[c] + 63) / 64;
+    blocks += nb;
+    ring += nb * (nb / 2) - ((nb % 2 == 0) ? nb / 2 : 0);
+  }
+  return ring >= blocks && esym_slot_bytes(ncl, off) <= kESlotCap;
+}
+
 void release_sym_ensemble_plans() {
   std::lock_guard<std::mutex> lk(g_eplan_mu);
   for (EPlan* p : g_eplans) free_eplan(p);

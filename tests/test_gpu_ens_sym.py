@@ -212,3 +212,17 @@ def test_ens_sym_fp64_runs_ordered_items(nb):
     o4 = run(nb, off, epsv, x, v, m, 3, mode=4, precision="fp64")
     for p_, q_ in zip(o3, o4):
         assert np.array_equal(p_, q_)
+
+
+def test_ens_sym_untuned_default(nb):
+    """Without a forced or tuned choice, FP32C runs mode 4 on a layout whose
+    systems span several blocks of 64 and mode 3 on one of single-block
+    systems (bitwise the forced modes' states)."""
+    for sizes, mode in (([4096, 3000, 700, 129], 4), ([64, 40, 64, 17], 3)):
+        off, epsv, x, v, m = ics.ensemble(len(sizes), seed=47, sizes=sizes)
+        tx, tv, tm = dev(x), dev(v), dev(m)
+        ta = torch.empty_like(tx)
+        nb.nbody_set_config()
+        nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 3, precision="fp32c")
+        fx, fv, _ = run(nb, off, epsv, x, v, m, 3, mode=mode, precision="fp32c")
+        assert np.array_equal(tx.cpu().numpy(), fx) and np.array_equal(tv.cpu().numpy(), fv), sizes
