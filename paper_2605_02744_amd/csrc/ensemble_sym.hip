@@ -3,9 +3,9 @@
 // Every unordered pair of a system is evaluated once and its term applied to
 // both particles (the antisymmetry of Eq. 1), as in the single-system symmetric
 // kernel, but at the size of one wave, so that systems of 64 to a few thousand
-// particles fill the chip.  An item is one block of 64 particles of one system
-// (lane t owns its particle t); the wave that takes it evaluates
-//   * the block with itself in the ordered form (the i-side of every ordered
+// particles fill the chip.  Each system is cut into blocks of 64 particles
+// (lane t owns particle t of a block); block b meets
+//   * itself at distance 0, in the ordered form (the i-side of every ordered
 //     pair, the own pair masked when asked);
 //   * the blocks b + d (mod nb_c) of its system for d = 1 .. nb_c / 2 (d = nb_c / 2
 //     only for b < nb_c / 2 when nb_c is even), each pair once.  The lanes form
@@ -16,19 +16,19 @@
 //     j at step 0 and moves there through a DPP row rotation fused into the
 //     add; after a sub-block the four rows' sums of its 16 j are added on the
 //     LDS pipe; the J-block's 64 sums go to the system's slot for distance d.
-// A block's distances (0, the block itself, to its last ring distance) are cut
-// into parts of a few distances, one item each, so that the items of the
-// largest systems are not much longer than the rest.  Each step is three
-// launches: publish (the kicks, the drift and the pair records of the new
-// positions), force (each item's i-side sums into a for the first part, else
-// into its part's slot, the j-side sums into the distance slots) and reduce
-// (per particle, its part sums in part order, then its distance slots in
-// distance order, in FP64, times G), so
-// results are reproducible.  Items are placed longest first over the
-// workgroups and a workgroup's waves take its items from an LDS counter.  FP32C positions are rounded to FP32 and
-// the near-field rule of the ordered kernels applies: in the ordered block a
-// pair closer than particle i's repair radius, in a block pair a pair closer
-// than the larger radius of its two particles, gets float-float displacements.
+// A block's distances are cut into parts of a few distances; an item is one
+// part, evaluated by one wave, so that the items of the largest systems are
+// not much longer than the rest.  Each step is three launches: publish (the
+// kicks, the drift and the pair records of the new positions), force (each
+// item's i-side sums into a for the first part, else into its part's slot;
+// the j-side sums into the distance slots) and reduce (per particle, its part
+// sums in part order, then its distance slots in distance order, in FP64,
+// times G), so results are reproducible.  Items are placed longest first over
+// the workgroups and a workgroup's waves take its items from an LDS counter.
+// FP32C positions are rounded to FP32 and the near-field rule of the ordered
+// kernels applies: in the ordered block a pair closer than particle i's repair
+// radius, in a block pair a pair closer than the larger radius of its two
+// particles, gets float-float displacements.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
