@@ -96,6 +96,26 @@ typedef struct nbody_params {
 int nbody_accel(int64_t n, const double* x, const double* m, double* a,
                 const nbody_params* p, void* stream);
 
+/* For callers that cannot allocate memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The accelerations of
+ * nbody_accel (same arguments, same kernels and the same accuracy), with every
+ * scratch byte (staged records, partial and per-distance sums) taken from one
+ * fixed device array of NBODY_NOALLOC_SCRATCH_BYTES (256 MiB) that the library
+ * holds on each GPU it runs on until the process ends.  The call never
+ * allocates or frees memory and never synchronises.  The symmetric path fits
+ * its half ring into that array, in more launches than nbody_accel uses at the
+ * largest sizes (its sums then run in another order: results agree with
+ * nbody_accel to the precision's tolerance, not bitwise).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (nothing in it needs to start at zero): calls that overlap on one GPU
+ * (on different streams, or from different threads) race and must not be
+ * issued.
+ * Errors: as nbody_accel; NBODY_EINVAL also for n > NBODY_NOALLOC_MAX_N (2^21)
+ * and for NBODY_CHECK_FINITE (which waits for the stream). */
+enum { NBODY_NOALLOC_SCRATCH_BYTES = 268435456, NBODY_NOALLOC_MAX_N = 2097152 };
+int nbody_accel_noalloc(int64_t n, const double* x, const double* m, double* a, const nbody_params* p,
+                        void* stream);
+
 /* nsteps kick-drift-kick leapfrog steps of size dt, in place on x, v, a:
  *   v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a
  * (the workloads' integrator; the paper's Sec. 2.1 predict-evaluate-correct

@@ -68,6 +68,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     PP = ctypes.POINTER(nbody_params)
     lib.nbody_accel.argtypes = [_I64, _P, _P, _P, PP, _P]
+    lib.nbody_accel_noalloc.argtypes = [_I64, _P, _P, _P, PP, _P]
     lib.nbody_step.argtypes = [_I64, _P, _P, _P, _P, _D, _I64, PP, _P]
     lib.nbody_energy.argtypes = [_I64, _P, _P, _P, PP, _P, _P]
     lib.nbody_accel_vjp.argtypes = [_I64, _P, _P, _P, _P, _P, PP, _P]
@@ -87,7 +88,7 @@ def load():
     lib.nbody_last_error.argtypes = []
     lib.nbody_finalize.argtypes = []
     lib.nbody_version.argtypes = []
-    for f in ("nbody_accel", "nbody_step", "nbody_energy", "nbody_accel_vjp", "nbody_traj_grad",
+    for f in ("nbody_accel", "nbody_accel_noalloc", "nbody_step", "nbody_energy", "nbody_accel_vjp", "nbody_traj_grad",
               "nbody_step_batched", "nbody_set_config", "nbody_tune", "nbody_finalize", "nbody_version",
               "nbody_accel_jerk", "nbody_step_hermite", "nbody_accel_jerk_snap", "nbody_step_hermite6",
               "nbody_potential", "nbody_tune_batched"):
@@ -140,6 +141,21 @@ def nbody_accel(x, m, *, G=1.0, eps, precision="fp32c", exclude_self=False, chec
     with torch.cuda.device(x.device):
         _check(lib.nbody_accel(n, _ptr(x, "x", (3, n)), _ptr(m, "m", (n,)), _ptr(out, "a", (3, n)),
                                ctypes.byref(p), _stream(x.device)))
+    return out
+
+
+def nbody_accel_noalloc(x, m, *, G=1.0, eps, precision="fp32c", exclude_self=False, out=None):
+    """nbody_accel with every scratch byte taken from the library's fixed
+    per-GPU array (no allocation inside the call; N <= 2^21; calls on one GPU
+    must not overlap).  Allocates `out` here only when it is not given."""
+    lib = load()
+    n = m.shape[0]
+    if out is None:
+        out = torch.empty((3, n), dtype=torch.float64, device=x.device)
+    p = _params(G, eps, precision, _flags(exclude_self))
+    with torch.cuda.device(x.device):
+        _check(lib.nbody_accel_noalloc(n, _ptr(x, "x", (3, n)), _ptr(m, "m", (n,)), _ptr(out, "a", (3, n)),
+                                       ctypes.byref(p), _stream(x.device)))
     return out
 
 

@@ -91,6 +91,16 @@ void* workspace(int device, int slot, size_t bytes, int* status) {
   return p;
 }
 
+void* pair_scratch(const PairConfig& cfg, size_t bytes, int* status) {
+  if (!cfg.scratch) return workspace(current_device(), 0, bytes, status);
+  if (bytes > cfg.scratch_bytes) {
+    *status = set_error(NBODY_EINVAL, "the call needs " + std::to_string(bytes) + " bytes of scratch, more than the " +
+                                          std::to_string(cfg.scratch_bytes) + " it was given");
+    return nullptr;
+  }
+  return cfg.scratch;
+}
+
 void release_workspaces() {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (int d = 0; d < kMaxDev; ++d)
@@ -292,9 +302,68 @@ BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps,
   return bc;
 }
 
+// --------------------------------------------- fixed scratch, no allocation
+// The device memory of nbody_accel_noalloc: a file-scope array that the code
+// object brings along, one copy on every GPU the library runs on, held until
+// the process ends.  On the host `scratch` is only a stand-in for the symbol;
+// host code takes each device's address from hipGetSymbolAddress and uses
+// that address (kernel arguments, offsets) instead of the name.
+constexpr size_t kNoAllocBytes = (size_t)NBODY_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];  // per device, looked up on the device's first call
+
+// This device's address of `scratch`, looked up once per device with that
+// device current (the caller's current device).
+int noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= 64) return set_error(NBODY_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return set_error(NBODY_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return NBODY_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int nbody_accel_noalloc(int64_t n, const double* x, const double* m, double* a, const nbody_params* p,
+                        void* stream) {
+  NB_TRY(check_common(n, p, true));
+  if (n > NBODY_NOALLOC_MAX_N)
+    return set_error(NBODY_EINVAL, "nbody_accel_noalloc: n = " + std::to_string(n) + " exceeds " +
+                                       std::to_string((long long)NBODY_NOALLOC_MAX_N) +
+                                       ", the largest system its fixed scratch serves (use nbody_accel)");
+  if (p->flags & NBODY_CHECK_FINITE)
+    return set_error(NBODY_EINVAL, "nbody_accel_noalloc: NBODY_CHECK_FINITE waits for the stream and needs a "
+                                   "status buffer; use nbody_accel");
+  if (n == 0) return NBODY_OK;
+  const size_t b3 = sizeof(double) * 3 * (size_t)n, b1 = sizeof(double) * (size_t)n;
+  NB_TRY(check_dev_range(x, b3, "x"));
+  NB_TRY(check_dev_range(m, b1, "m"));
+  NB_TRY(check_dev_range(a, b3, "a"));
+  if ((const void*)a == (const void*)x || (const void*)a == (const void*)m)
+    return set_error(NBODY_EINVAL, "a aliases an input");
+  const int dev = current_device();
+  void* scr = nullptr;
+  NB_TRY(noalloc_scratch(dev, &scr));
+  PairConfig cfg = choose_config(n, p->precision, dev);
+  cfg.scratch = scr;
+  cfg.scratch_bytes = kNoAllocBytes;
+  if (!cfg.sym) {
+    // the ordered kernels keep 3 n FP64 partial sums per slice of the j-range
+    const int64_t most = std::max<int64_t>(1, (int64_t)(kNoAllocBytes / (sizeof(double) * 3 * (size_t)n)));
+    cfg.split = (int)std::min<int64_t>(cfg.split, most);
+  }
+  return launch_accel(n, x, m, a, p->G, p->eps, p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0, cfg,
+                      static_cast<hipStream_t>(stream));
+}
 
 int nbody_accel(int64_t n, const double* x, const double* m, double* a, const nbody_params* p, void* stream) {
   NB_TRY(check_common(n, p, true));

@@ -50,7 +50,16 @@ struct PairConfig {
   int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups
   int sym = 0;    // 1: the symmetric kernels (each unordered pair once; the VJP in FP32C/FP32 only)
+  // Device memory the caller lends for this call's partial sums, staged
+  // records and slots.  When set, the all-pairs launchers fit their plans into
+  // scratch_bytes and never touch the library workspace (no allocation).
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
 };
+
+// `bytes` of scratch for one all-pairs launch: cfg.scratch when the caller lent
+// memory (NBODY_EINVAL if it is smaller), else workspace slot 0.
+void* pair_scratch(const PairConfig& cfg, size_t bytes, int* status);
 
 PairConfig choose_config(int64_t n, int precision, int device);
 void set_thread_config(const nbody_config& c);
@@ -64,19 +73,19 @@ int launch_accel(int64_t n, const double* x, const double* m, double* a, double 
                  int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
 
 // The same accelerations from the symmetric kernel (FP32C or FP32): every
-// unordered pair once, applied to both particles; slot sums in the workspace.
-// launches > 0: at least that many kernel launches over the half ring
-// (0 = as few as the workspace bound allows).
+// unordered pair once, applied to both particles; slot sums in the workspace
+// (or in cfg.scratch).  cfg.split > 0: at least that many kernel launches over
+// the half ring (0 = as few as the scratch bound allows).
 int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
-                     bool exclude_self, int launches, hipStream_t s);
+                     bool exclude_self, const PairConfig& cfg, hipStream_t s);
 
 // The same accelerations in FP64 from the symmetric FP64 kernel.
 int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps,
-                       bool exclude_self, int launches, hipStream_t s);
+                       bool exclude_self, const PairConfig& cfg, hipStream_t s);
 
 // The same VJP from the symmetric kernel (FP32C or FP32; launches as above).
 int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
-                   double eps, int precision, bool exclude_self, int launches, hipStream_t s);
+                   double eps, int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
 
 // (da/dx)^T w into gx and (da/dm)^T w into gm.
 int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx,

@@ -824,14 +824,14 @@ inline int effective_split(int64_t n, int split) {
 
 template <int MODE, int IPL>
 int accel_dispatch(int64_t n, const double* x, const double* m, double* a, double G, double eps,
-                   bool excl, int split, hipStream_t s) {
+                   bool excl, int split, const PairConfig& cfg, hipStream_t s) {
   const int chunk = split_chunk(n, split);
   const int sp = effective_split(n, split);
   dim3 grid((unsigned)((n + kBlock * IPL - 1) / (kBlock * IPL)), (unsigned)sp);
   double* out = a;
   int st = NBODY_OK;
   if (sp > 1) {
-    out = static_cast<double*>(workspace(current_device(), 0, sizeof(double) * 3 * (size_t)n * sp, &st));
+    out = static_cast<double*>(pair_scratch(cfg, sizeof(double) * 3 * (size_t)n * sp, &st));
     if (!out) return st;
   }
   constexpr bool kNear = MODE == kFP32C;
@@ -959,11 +959,11 @@ int launch_accel(int64_t n, const double* x, const double* m, double* a, double 
                  int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   if (cfg.sym) {
-    if (precision == kFP64) return launch_sym_accel64(n, x, m, a, G, eps, excl, cfg.split, s);
-    return launch_sym_accel(n, x, m, a, G, eps, precision, excl, cfg.split, s);
+    if (precision == kFP64) return launch_sym_accel64(n, x, m, a, G, eps, excl, cfg, s);
+    return launch_sym_accel(n, x, m, a, G, eps, precision, excl, cfg, s);
   }
   const int split = cfg.split < 1 ? 1 : cfg.split;
-#define NB_ACC(MODE, IPL) return accel_dispatch<MODE, IPL>(n, x, m, a, G, eps, excl, split, s)
+#define NB_ACC(MODE, IPL) return accel_dispatch<MODE, IPL>(n, x, m, a, G, eps, excl, split, cfg, s)
   switch (precision) {
     case kFP64:
       if (cfg.ipl == 1) NB_ACC(kFP64, 1);
@@ -985,7 +985,7 @@ int launch_accel(int64_t n, const double* x, const double* m, double* a, double 
 int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm,
                double G, double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
-  if (cfg.sym && precision != kFP64) return launch_sym_vjp(n, x, m, w, gx, gm, G, eps, precision, excl, cfg.split, s);
+  if (cfg.sym && precision != kFP64) return launch_sym_vjp(n, x, m, w, gx, gm, G, eps, precision, excl, cfg, s);
   const int split = cfg.split < 1 ? 1 : cfg.split;
   // The VJP keeps twice the accumulators of the force, so it runs at most 2 i per lane.
   const bool one = cfg.ipl <= 1;

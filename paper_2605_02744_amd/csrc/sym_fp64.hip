@@ -255,10 +255,13 @@ __global__ __launch_bounds__(kSL) void sym64_diag_kernel(S64Args A, double* __re
 }  // namespace
 
 int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps, bool excl,
-                       int launches, hipStream_t s) {
+                       const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   int nb, L, D;
-  sym_plan(n, launches, 3 * sizeof(double), &nb, &L, &D);
+  // per particle: FP64 j-side slot sums per distance, FP64 i-side sums per workgroup,
+  // FP64 block-diagonal sums and one staged double4 record
+  sym_plan(n, cfg.split, 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double) + sizeof(double4),
+           cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -268,7 +271,7 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
   const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
   const size_t rec_bytes = sizeof(double4) * (size_t)npad;
-  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes + rec_bytes, &st));
+  char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + rec_bytes, &st));
   if (!ws) return st;
   S64Args A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;

@@ -409,13 +409,16 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
 }  // namespace
 
 int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
-                     bool excl, int launches, hipStream_t s) {
+                     bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   if (precision != kFP32C && precision != kFP32)
     return set_error(NBODY_EUNSUPPORTED, "symmetric pair kernel: FP32C and FP32 only");
   if (n > (int64_t(1) << 30)) return set_error(NBODY_EINVAL, "symmetric pair kernel: n too large");
   int nb, L, D;
-  sym_plan(n, launches, 3 * sizeof(float), &nb, &L, &D);
+  // per particle: FP32 j-side slot sums per distance, FP64 i-side sums per workgroup,
+  // FP64 block-diagonal sums and two staged float4 records
+  sym_plan(n, cfg.split, 3 * sizeof(float), 3 * sizeof(double), 3 * sizeof(double) + 2 * sizeof(float4),
+           cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -425,7 +428,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
   const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
   const size_t rec_bytes = sizeof(float4) * (size_t)npad;
-  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes, &st));
+  char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes, &st));
   if (!ws) return st;
   SymArgs A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;

@@ -404,12 +404,15 @@ __global__ __launch_bounds__(kSL) void vsym_diag_kernel(SymArgs A, double* __res
 }  // namespace
 
 int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
-                   double eps, int precision, bool excl, int launches, hipStream_t s) {
+                   double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   if (precision != kFP32C && precision != kFP32)
     return set_error(NBODY_EUNSUPPORTED, "symmetric VJP kernel: FP32C and FP32 only");
   int nb, L, D;
-  sym_plan(n, launches, kVC * sizeof(float), &nb, &L, &D);
+  // per particle: FP32 j-side slot sums per distance, FP64 i-side sums per workgroup,
+  // FP64 block-diagonal sums and three staged float4 records
+  sym_plan(n, cfg.split, kVC * sizeof(float), kVC * sizeof(double), kVC * sizeof(double) + 3 * sizeof(float4),
+           cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -419,7 +422,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   const size_t pi_bytes = sizeof(double) * kVC * (size_t)npad * nparts;
   const size_t pd_bytes = sizeof(double) * kVC * (size_t)npad;
   const size_t rec_bytes = sizeof(float4) * (size_t)npad;
-  char* ws = static_cast<char*>(workspace(current_device(), 0, pj_bytes + pi_bytes + pd_bytes + 3 * rec_bytes, &st));
+  char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + 3 * rec_bytes, &st));
   if (!ws) return st;
   SymArgs A;
   A.x = x; A.m = m; A.w = w; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
