@@ -49,6 +49,7 @@ def _load():
         lib.oracle_accel_vjp.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D, _D]
         lib.oracle_accel_vjp_rows.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _I64,
                                               ctypes.POINTER(ctypes.c_int64), _D, _D]
+        lib.oracle_accel_vjp_scale_rows.argtypes = lib.oracle_accel_vjp_rows.argtypes
         lib.oracle_accel_jvp.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D]
         lib.oracle_kdk_adjoint.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, _I64, _D, _D, _D, _D, _D]
@@ -114,7 +115,9 @@ def accel_rows(x, m, rows, G=1.0, eps=0.0):
 
 
 def term_scale_rows(x, m, rows, G=1.0, eps=0.0):
-    """G sum_{j != i} m_j / (|d_ij|^2 + eps^2) for each listed row i."""
+    """|G| sum_{j != i} m_j / (|d_ij|^2 + eps^2) for each listed row i: an upper
+    bound of the sum of the magnitudes of the row's terms (|d| <= |d|^2 + eps^2
+    under the root), the scale of the condition-normalised force error."""
     m = _c(m)
     n = m.shape[0]
     x = _c(x, (3, n))
@@ -123,6 +126,24 @@ def term_scale_rows(x, m, rows, G=1.0, eps=0.0):
     _load().oracle_term_scale_rows(n, _p(x), _p(m), float(G), float(eps), rows.size,
                                    rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out))
     return out
+
+
+def accel_vjp_scale_rows(x, m, w, rows, G=1.0, eps=0.0):
+    """Sums of the magnitudes of the terms of the listed rows of ``accel_vjp``:
+    sx (len(rows),) of the 2-norms of the gx terms and sm (len(rows),) of the
+    absolute gm terms; the scales of the condition-normalised VJP error."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n))
+    w = _c(w, (3, n))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if rows.size and (rows.min() < 0 or rows.max() >= n):
+        raise ValueError("row index out of range")
+    sx = np.empty(rows.size)
+    sm = np.empty(rows.size)
+    _load().oracle_accel_vjp_scale_rows(n, _p(x), _p(m), _p(w), float(G), float(eps), rows.size,
+                                        rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(sx), _p(sm))
+    return sx, sm
 
 
 def kdk(x, v, m, dt, nsteps, G=1.0, eps=0.0, trajectory=False):

@@ -121,7 +121,39 @@ void oracle_term_scale_rows(int64_t n, const double* x, const double* m, double 
             double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
             nadd(&s, m[j] / (dx * dx + dy * dy + dz * dz + eps * eps));
         }
-        out[k] = G * nval(&s);
+        out[k] = fabs(G) * nval(&s);
+    }
+}
+
+/* Per-row scales of the VJP terms, the condition of the sums of
+ * oracle_accel_vjp: for each listed row k,
+ *   sx[k] = G sum_{j != k} |K(d_kj) u_kj|_2   (u_kj = m_k w_j - m_j w_k),
+ *   sm[k] = G sum_{j != k} |s^-3/2 (d_kj . w_j)|,
+ * so that |gx_k| <= sx[k] and |gm_k| <= sm[k], with equality for one term. */
+void oracle_accel_vjp_scale_rows(int64_t n, const double* x, const double* m, const double* w, double G,
+                                 double eps, int64_t nrows, const int64_t* rows, double* sx, double* sm) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t k = rows[r];
+        nsum ax = {0, 0}, am = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == k) continue;
+            double d[3], u[3];
+            for (int c = 0; c < 3; ++c) {
+                d[c] = x[c * n + j] - x[c * n + k];
+                u[c] = m[k] * w[c * n + j] - m[j] * w[c * n + k];
+            }
+            double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+            double s32 = 1.0 / (s * sqrt(s));
+            double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+            double t[3];
+            for (int c = 0; c < 3; ++c) t[c] = s32 * u[c] - 3.0 * (s32 / s) * du * d[c];
+            nadd(&ax, sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]));
+            double dw = d[0] * w[j] + d[1] * w[n + j] + d[2] * w[2 * n + j];
+            nadd(&am, fabs(s32 * dw));
+        }
+        sx[r] = fabs(G) * nval(&ax);
+        sm[r] = fabs(G) * nval(&am);
     }
 }
 

@@ -531,3 +531,62 @@ def test_potential_gradient_is_minus_acceleration(oracle_mod):
             xm[c, i] -= h
             d = (oracle_mod.potential(xp, m, eps=0.05)[i] - oracle_mod.potential(xm, m, eps=0.05)[i]) / (2 * h)
             assert abs(d + a[c, i]) <= 1e-7 * np.abs(a[:, i]).max()
+
+
+# ---- term scales (the denominators of the condition-normalised errors) -----
+
+def test_term_scale_two_body_and_collinear(oracle_mod):
+    """N = 2: |G| m_2 / (r^2 + eps^2) in closed form.  All partners on one ray
+    from particle 0 with eps = 0: every term points the same way and has
+    magnitude G m_j / r_j^2, so the separately pinned acceleration reaches
+    the scale exactly; elsewhere it stays below it."""
+    x = np.array([[0.1, 0.4], [0.2, -0.1], [-0.3, 0.5]])
+    m = np.array([0.7, 1.9])
+    r2 = ((x[:, 1] - x[:, 0]) ** 2).sum()
+    s = oracle_mod.term_scale_rows(x, m, [0, 1], G=1.3, eps=0.1)
+    assert np.allclose(s, [1.3 * 1.9 / (r2 + 0.01), 1.3 * 0.7 / (r2 + 0.01)], rtol=1e-15)
+    rng = np.random.default_rng(3)
+    r = np.concatenate([[0.0], rng.uniform(0.1, 3.0, 20)])
+    xr = np.outer(np.array([2.0, -1.0, 0.5]) / np.linalg.norm([2.0, -1.0, 0.5]), r)
+    mr = rng.uniform(0.5, 2.0, 21)
+    a0 = oracle_mod.accel_rows(xr, mr, [0], G=0.9, eps=0.0)
+    s0 = oracle_mod.term_scale_rows(xr, mr, [0], G=0.9, eps=0.0)[0]
+    assert abs(np.linalg.norm(a0) - s0) <= 1e-14 * s0
+    xp, _, mp = ics.plummer(300, seed=4)
+    rows = np.arange(300)
+    sp = oracle_mod.term_scale_rows(xp, mp, rows, eps=0.01)
+    ap = oracle_mod.accel(xp, mp, eps=0.01)
+    assert (np.linalg.norm(ap, axis=0) <= sp * (1 + 1e-14)).all()
+
+
+def test_vjp_scale_two_body_aligned_and_bound(oracle_mod):
+    """The VJP term scales against the separately pinned VJP: equal to |gx_k|
+    and |gm_k| when a row has one term (N = 2) or when all its terms are
+    parallel (partners on one ray with eps = 0, cotangents along that ray and
+    none on the row itself), and never below them otherwise; linear in w and
+    in a common scale of the masses (for gx)."""
+    x = np.array([[0.1, 0.4], [0.2, -0.1], [-0.3, 0.5]])
+    m = np.array([0.7, 1.9])
+    w = np.array([[0.3, -1.2], [2.0, 0.4], [-0.5, 0.9]])
+    gx, gm = oracle_mod.accel_vjp(x, m, w, G=-0.8, eps=0.05)
+    sx, sm = oracle_mod.accel_vjp_scale_rows(x, m, w, [0, 1], G=-0.8, eps=0.05)
+    assert np.allclose(sx, np.linalg.norm(gx, axis=0), rtol=1e-14)
+    assert np.allclose(sm, np.abs(gm), rtol=1e-14)
+    rng = np.random.default_rng(5)
+    e = np.array([1.0, 2.0, -2.0]) / 3.0
+    r = np.concatenate([[0.0], rng.uniform(0.2, 2.0, 15)])
+    xr = np.outer(e, r)
+    mr = rng.uniform(0.5, 2.0, 16)
+    wr = np.outer(e, np.concatenate([[0.0], rng.uniform(0.1, 1.0, 15)]))
+    gx, gm = oracle_mod.accel_vjp(xr, mr, wr, eps=0.0)
+    sx, sm = oracle_mod.accel_vjp_scale_rows(xr, mr, wr, [0], eps=0.0)
+    assert abs(np.linalg.norm(gx[:, 0]) - sx[0]) <= 1e-14 * sx[0]
+    assert abs(abs(gm[0]) - sm[0]) <= 1e-14 * sm[0]
+    xp, _, mp = ics.two_component(400, seed=6)
+    wp = rng.standard_normal((3, 400))
+    rows = np.arange(400)
+    gx, gm = oracle_mod.accel_vjp(xp, mp, wp, G=0.7, eps=0.02)
+    sx, sm = oracle_mod.accel_vjp_scale_rows(xp, mp, wp, rows, G=0.7, eps=0.02)
+    assert (np.linalg.norm(gx, axis=0) <= sx * (1 + 1e-14)).all() and (np.abs(gm) <= sm * (1 + 1e-14)).all()
+    sx2, sm2 = oracle_mod.accel_vjp_scale_rows(xp, 3.0 * mp, -2.0 * wp, rows, G=0.7, eps=0.02)
+    assert np.allclose(sx2, 6.0 * sx, rtol=1e-13) and np.allclose(sm2, 2.0 * sm, rtol=1e-13)
