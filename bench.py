@@ -41,6 +41,14 @@ UNIT = "G pair-interactions/s"
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector (packed) peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
 FLOPS_PER_PAIR = 20          # acceleration-only softened interaction convention
+# flops per interaction of the other pair evaluations, counted from their formulas the same way
+# (fused multiply-add = 2, inverse square root = 1): the VJP term (d 3, r^2 6, rsqrt 1, r^-2 r^-3
+# r^-5 3, u 9, d.u 5, 3 r^-5 d.u 2, g 12, d.w 5, gm 2), acceleration + jerk (d, v 6, r^2 6,
+# rsqrt 1, r^-2 r^-3 t 3, alpha 6, a 6, jerk 14) and acceleration + jerk + snap (d, v, acc 9,
+# r^2 6, rsqrt 1, r^-2 r^-3 t 3, alpha 6, beta 14, a 6, jerk 14, snap 21)
+FLOPS_VJP = 48
+FLOPS_JERK = 42
+FLOPS_SNAP = 80
 # sources of the headline evaluation's kernels (the symmetric FP32C path: staging,
 # block-diagonal, half-ring chunks and slot sums); traffic figures taken on other
 # sources are not reported
@@ -56,17 +64,35 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+def load_profile(kind, workload):
+    """A committed counter summary (profiles/<kind>_<workload>.json) if it was
+    taken on the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", "%s_%s.json" % (kind, workload))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_hash") != kernel_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def load_traffic(workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    rec = load_profile("traffic", workload)
+    return rec.get("hbm_bytes_per_launch") if rec else None
+
+
+def roofline(kernel, flops, ms, peak=FP32_PEAK_TFLOPS, traffic=None, **extra):
+    """Roofline entry of a kernel bound by vector-ALU arithmetic: the
+    algorithmic flops of one launch (or of the launches that form one
+    evaluation) over its duration measured here with HIP events."""
+    ach = flops / (ms * 1e-3) / 1e12
+    r = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+         "traffic": traffic, "kernel": kernel, "flops_per_launch": flops, "ms_per_launch": round(ms, 5)}
+    r.update(extra)
+    return r
 
 
 class GpuEnergy:
@@ -102,12 +128,23 @@ class GpuEnergy:
             return None
 
 
-def energy_per_call(fn, reps, torch, meter, settle=0.5):
+def idle_power(meter, seconds=2.0):
+    """Board power (W) over a quiet window, or None."""
+    if meter is None or meter.joules() is None:
+        return None
+    ja = meter.joules()
+    time.sleep(seconds)
+    return (meter.joules() - ja) / seconds
+
+
+def energy_per_call(fn, reps, torch, meter, idle_before=None, settle=0.5):
     """GPU board energy (J) of one call of fn, from the amdsmi energy counter
     over `reps` back-to-back calls.  The counter is refreshed with some delay,
     so every read follows a settling pause, and the idle energy of the pauses
-    (idle power from a separate one-second window) is subtracted.  Returns
-    (joules per call, busy seconds per call, idle watts) or None."""
+    is subtracted: with the idle power measured before the program's first GPU
+    work (idle_before) when given, else with that of a one-second window just
+    before the calls; the second figure is returned too, since a board that
+    has just been busy still draws more.  Returns a dict or None."""
     if meter is None or meter.joules() is None:
         return None
     torch.cuda.synchronize()
@@ -116,7 +153,7 @@ def energy_per_call(fn, reps, torch, meter, settle=0.5):
     time.sleep(1.0)
     jb = meter.joules()
     tb = time.perf_counter()
-    idle_w = (jb - ja) / 1.0
+    idle_recent = (jb - ja) / 1.0
     t0 = time.perf_counter()
     for _ in range(reps):
         fn()
@@ -125,8 +162,15 @@ def energy_per_call(fn, reps, torch, meter, settle=0.5):
     time.sleep(settle)
     jc = meter.joules()
     window = time.perf_counter() - tb
-    e_busy = (jc - jb) - idle_w * (window - busy)
-    return e_busy / reps, busy / reps, idle_w
+    idle = idle_before if idle_before is not None else idle_recent
+    e_busy = ((jc - jb) - idle * (window - busy)) / reps
+    e_recent = ((jc - jb) - idle_recent * (window - busy)) / reps
+    return {"joules": e_busy, "busy_s": busy / reps, "idle_w": idle, "idle_w_recent": idle_recent,
+            "joules_recent_idle": e_recent, "idle_measured_before_gpu_work": idle_before is not None}
+
+
+METER = None   # GpuEnergy of cuda:0, where the workload reports energy
+IDLE_W = None  # its idle power, measured before any GPU work
 
 
 def timed(fn, steps, warmup, torch):
@@ -208,11 +252,16 @@ def bench_force(args, torch, nb):
            "pct_fp32_peak": round(100 * c20_tflops / FP32_PEAK_TFLOPS, 2),
            "ms_per_step_std": round(float(np.std(per)), 4),
            "wall_ms_timed_region": round(wall, 2)}
-    en = energy_per_call(f32, args.steps, torch, GpuEnergy())
+    en = energy_per_call(f32, args.steps, torch, METER, IDLE_W)
     if en:
         # GPU board energy of one evaluation (amdsmi energy counter, untimed repeat), for context
-        res["gpu_energy"] = {"joules_per_eval": round(en[0], 2), "avg_power_w": round(en[0] / en[1], 1),
-                             "idle_power_w": round(en[2], 1), "interactions_per_joule": round(pairs / en[0], 1)}
+        res["gpu_energy"] = {"joules_per_eval": round(en["joules"], 2),
+                             "avg_power_w": round(en["joules"] / en["busy_s"], 1),
+                             "idle_power_w": round(en["idle_w"], 1),
+                             "idle_measured_before_gpu_work": en["idle_measured_before_gpu_work"],
+                             "idle_power_w_after_work": round(en["idle_w_recent"], 1),
+                             "joules_per_eval_with_idle_after_work": round(en["joules_recent_idle"], 2),
+                             "interactions_per_joule": round(pairs / en["joules"], 1)}
     if tuned:
         res["tuned"] = tuned
 
@@ -241,9 +290,11 @@ def bench_force(args, torch, nb):
         A32, A64 = a32.cpu().numpy(), a64.cpu().numpy()
         e_all = rel_err_rows(A32, A64)
         res["accuracy"] = {"fp32c_vs_fp64gpu_max_rel": float(e_all.max()),
+                           "fp32c_vs_fp64gpu_p99_9": float(np.quantile(e_all, 0.999)),
                            "fp32c_vs_fp64gpu_p99": float(np.quantile(e_all, 0.99)),
                            "fp32c_vs_fp64gpu_median": float(np.median(e_all)),
-                           "fp32c_vs_fp64gpu_rows_over_1e-5": int((e_all > 1e-5).sum())}
+                           "fp32c_vs_fp64gpu_rows_over_1e-5": int((e_all > 1e-5).sum()),
+                           "statistic": "per row |a - a_ref| / |a_ref|, FP64 GPU path over all rows"}
 
     # roofline of the force evaluation: C20 flops of the N(N-1) ordered interactions
     # / measured duration of one evaluation.  At this size the automatic choice is
@@ -255,6 +306,15 @@ def bench_force(args, torch, nb):
                        "traffic": load_traffic("twocomp1m_force"),
                        "kernel": "sym_accel_kernel<FP32C> (one evaluation: all launches of the symmetric path)",
                        "flops_per_launch": pairs * FLOPS_PER_PAIR, "pair_evaluations": pairs / 2}
+    # hardware-counted FP32 work of the same evaluation (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes from a
+    # committed counter run on these sources), over the time measured here
+    valu = load_profile("valu", "twocomp1m_force")
+    if valu and (args.pairs or 0) != 1 and args.precision == "fp32c" and n == w["n"]:
+        cf = valu["fp32_flops_per_eval"]
+        res["roofline"]["counted"] = {"fp32_flops_per_interaction": round(cf / pairs, 3),
+                                      "achieved": round(cf / (ms * 1e-3) / 1e12, 3),
+                                      "frac": round(cf / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                                      "source": "profiles/valu_twocomp1m_force.json"}
 
     if not args.no_cpu:
         import oracle
@@ -278,6 +338,15 @@ def bench_force(args, torch, nb):
             res["accuracy"]["fp32c_vs_oracle_sampled_max_rel"] = float(e32.max())
             res["accuracy"]["fp64gpu_vs_oracle_sampled_max_rel"] = float(e64.max())
             res["accuracy"]["sampled_rows"] = int(len(rows))
+            # condition-normalised error |a - a_ref| / (|G| sum_j m_j / s_ij) (the scale of the row's
+            # terms) on the rows where FP32C is worst against FP64 and on 256 of the sampled rows
+            crow = np.unique(np.concatenate([np.argsort(e_all)[-64:], rows[::max(1, len(rows) // 256)]]))
+            cref = oracle.accel_rows(x, m, crow, eps=eps)
+            csc = oracle.term_scale_rows(x, m, crow, eps=eps)
+            cn = np.linalg.norm(A32[:, crow] - cref, axis=0) / csc
+            res["accuracy"]["fp32c_condition_normalised_max"] = float(cn.max())
+            res["accuracy"]["fp32c_vs_oracle_worst_rows_max_rel"] = float(rel_err_rows(A32[:, crow], cref).max())
+            res["accuracy"]["condition_normalised_rows"] = int(crow.size)
     return res
 
 
@@ -318,10 +387,28 @@ def bench_kdk64k(args, torch, nb):
         return r
 
     ferr = {"t0": force_error(x), "final": force_error(out[args.precision]["x"])}
+    # roofline of the step's dominant launches: one force evaluation at this size and precision (the
+    # symmetric path at N = 65536: staging, block diagonal, one half-ring launch, slot sums), timed
+    # alone with HIP events on the launch stream; the step adds one kick-drift pass over the state
+    txs = torch.tensor(x, device=dev)
+    fa = torch.empty_like(txs)
+    msf, _, _ = timed(lambda: nb.nbody_accel(txs, tm, eps=eps, precision=args.precision, out=fa), 50, 5, torch)
+    roof = roofline("sym_accel_kernel<FP32C> (one evaluation: all launches of the symmetric path)",
+                    pairs * FLOPS_PER_PAIR, msf, step_frac=round(pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4))
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oracle.accel_rows(x, m, np.arange(8), eps=eps)  # thread pool start-up, untimed
+        t0 = time.perf_counter()
+        oracle.kdk(x, v, m, dt, 1, eps=eps)
+        el = time.perf_counter() - t0
+        cpu = {"value": round(2 * pairs / el / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "one KDK step of the same system: the initial and one further evaluation (%.1f s)" % el}
     return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
             "steps": args.steps, "warmup": 0, "ms_per_step": round(ms, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "plummer64k_fp32c", "n": n, "eps": eps, "dt": dt, "precision": args.precision},
+            "roofline": roof, "cpu_baseline": cpu,
             "force_error": ferr,
             "pct_fp32_peak": round(100 * pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift": {p: out[p]["dE"] for p in out},
@@ -412,8 +499,33 @@ def bench_ensemble(args, torch, nb):
                                        "value": round(pairs * naive_steps / (msn * 1e-3) / 1e9, 3),
                                        "note": "one nbody_step call per cluster, %d steps each" % naive_steps}
     ms = res[args.precision]
+    kname = {0: "ensemble_kernel", 1: "ensemble_kernel (split)", 2: "ens_stream_kernel / ens_wave_kernel",
+             3: "ens_waveforce_kernel (one step: publish and force launches)",
+             4: "esym_force_kernel (one step: publish, force and far-side sum launches)"}[mode]
+    # one step of the graph-replayed run: C20 flops of every system's ordered pairs over the step time
+    roof = roofline(kname, pairs * FLOPS_PER_PAIR, ms / args.steps)
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's KDK, one step per cluster, clusters in a seeded order until about
+        # --cpu-budget seconds have been spent
+        import oracle
+        order = np.random.default_rng(4).permutation(len(sizes))
+        oracle.accel_rows(x[:, :64], m[:64], np.arange(8), eps=float(epsv[0]))  # thread pool start-up
+        el, work, ncl = 0.0, 0.0, 0
+        for c in order:
+            s_, e_ = int(off[c]), int(off[c + 1])
+            t0 = time.perf_counter()
+            oracle.kdk(x[:, s_:e_], v[:, s_:e_], m[s_:e_], w["dt"], 1, eps=float(epsv[c]))
+            el += time.perf_counter() - t0
+            work += 2.0 * sizes[c] * (sizes[c] - 1)
+            ncl += 1
+            if el >= args.cpu_budget:
+                break
+        cpu = {"value": round(work / el / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "one KDK step (two evaluations) of each of %d clusters in a seeded order (%.1f s)" % (ncl, el)}
     return {"metric": METRIC, "value": round(pairs * args.steps / (ms * 1e-3) / 1e9, 3), "unit": UNIT,
             "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": round(ms / args.steps, 5),
+            "roofline": roof, "cpu_baseline": cpu,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
@@ -437,17 +549,18 @@ def bench_grad(args, torch, nb):
     # fresh device has been seen to run the first 100 ms several times slower) stay outside
     # the timing: one full forward + backward per precision, twice
     # (the loss's own torch kernels are loaded here too: their first use costs tens of ms)
-    # runs: (label, forward precision, adjoint precision); the third is the mixed form, an FP64
-    # trajectory differentiated by the FP32C adjoint sweep
-    runs = [(args.precision, args.precision, args.precision), ("fp64", "fp64", "fp64"),
-            ("fp64_fwd_%s_adjoint" % args.precision, "fp64", args.precision)]
+    # runs: (label, forward precision, sweep precision).  The first is the library's gradient
+    # for the requested precision (for FP32C: an FP64 forward and checkpoints, an FP32C reverse
+    # sweep, i.e. the FP64 map's gradient), the third the all-FP32C form (the FP32C map's)
+    runs = [(args.precision, None, args.precision), ("fp64", "fp64", "fp64"),
+            ("all_%s" % args.precision, args.precision, args.precision)]
     wtgt = torch.tensor(xp, device=dev)
     for _ in range(2):
         for _, prec, aprec in runs:
             wx = torch.tensor(x, device=dev, requires_grad=True)
             wv = torch.tensor(v, device=dev, requires_grad=True)
             wm = torch.tensor(m, device=dev, requires_grad=True)
-            wT, _ = nb.NBodyTrajectory.apply(wx, wv, wm, dt, steps, every, 1.0, eps, prec, aprec)
+            wT, _ = nb.NBodyTrajectory.apply(wx, wv, wm, dt, steps, every, 1.0, eps, aprec, prec)
             (((wT - wtgt) ** 2).sum() / n).backward()
     torch.cuda.synchronize()
     for label, prec, aprec in runs:
@@ -461,7 +574,7 @@ def bench_grad(args, torch, nb):
         tmg = torch.tensor(m, device=dev, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xT, _ = nb.NBodyTrajectory.apply(tx, tv, tmg, dt, steps, every, 1.0, eps, prec, aprec)
+        xT, _ = nb.NBodyTrajectory.apply(tx, tv, tmg, dt, steps, every, 1.0, eps, aprec, prec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss = ((xT - tgt_x) ** 2).sum() / n
@@ -505,6 +618,32 @@ def bench_grad(args, torch, nb):
             worst[prec] = max(worst[prec], abs(g[idx] - fd) / max(abs(fd), 1e-3 * np.abs(g).max()))
     pairs = float(n) * (n - 1)
     p = out[args.precision]
+    # roofline of the gradient's dominant kernel, the VJP of the reverse sweep (vjp_kernel at this size:
+    # one launch and its slice sum), timed alone with HIP events in the sweep's configuration; beside it
+    # the force kernels of the forward pass (FP64) and of the sweep's recompute (FP32C)
+    tx0 = torch.tensor(x, device=dev)
+    tw = torch.tensor(np.random.default_rng(3).standard_normal((3, n)), device=dev)
+    msv, _, _ = timed(lambda: nb.nbody_accel_vjp(tx0, tm, tw, eps=eps, precision=args.precision), 50, 5, torch)
+    fa = torch.empty_like(tx0)
+    msa, _, _ = timed(lambda: nb.nbody_accel(tx0, tm, eps=eps, precision=args.precision, out=fa), 50, 5, torch)
+    msa64, _, _ = timed(lambda: nb.nbody_accel(tx0, tm, eps=eps, precision="fp64", out=fa), 50, 5, torch)
+    roof = roofline("vjp_kernel<%s> (48 flops per interaction)" % args.precision.upper(), pairs * FLOPS_VJP, msv,
+                    force=roofline("accel_kernel<%s>" % args.precision.upper(), pairs * FLOPS_PER_PAIR, msa),
+                    force_fp64=roofline("accel_kernel<FP64>", pairs * FLOPS_PER_PAIR, msa64, peak=FP64_PEAK_TFLOPS))
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's gradient (forward, then the discrete adjoint with two VJPs per step) of a
+        # 2-step run of the same system
+        import oracle
+        cs = 2
+        tgt2, _ = oracle.kdk(xp, vp, m, dt, cs, eps=eps)
+        t0 = time.perf_counter()
+        oracle.loss_grad(x, v, m, tgt2, dt, cs, eps=eps)
+        el = time.perf_counter() - t0
+        cwork = pairs * (2 * (cs + 1) + 2 * cs)  # two forward passes (loss and adjoint) + 2 VJPs per step
+        cpu = {"value": round(cwork / el / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "loss and gradient of a 2-step run of the same system: %d force evaluations and %d "
+                         "VJPs (%.1f s)" % (2 * (cs + 1), 2 * cs, el)}
     # forward: steps + 1 evaluations; backward: recompute (steps + nseg) + steps + 1 VJPs
     nseg = -(-steps // every)
     work = pairs * ((steps + 1) + (steps + nseg) + (steps + 1))
@@ -512,13 +651,17 @@ def bench_grad(args, torch, nb):
             "steps": steps, "warmup": 0, "ms_per_step": round(1e3 * (p["fwd"] + p["bwd"]) / steps, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "grad16k", "n": n, "eps": eps, "dt": dt, "every": every, "precision": args.precision},
+            "roofline": roof, "cpu_baseline": cpu,
             "fwd_s": p["fwd"], "bwd_s": p["bwd"], "bwd_over_fwd": p["bwd"] / p["fwd"], "loss": p["loss"],
             "gradient_vs_central_differences": {"coords": len(coords), "h": h, "worst_rel": worst[args.precision],
-                                                "fp64_worst_rel": worst["fp64"], "mixed_worst_rel": worst[runs[2][0]],
+                                                "fp64_worst_rel": worst["fp64"],
+                                                "all_%s_worst_rel" % args.precision: worst[runs[2][0]],
                                                 "tolerance": 1e-4},
+            "forward_precision": "fp64",
             "fp64_path": {"fwd_s": out["fp64"]["fwd"], "bwd_s": out["fp64"]["bwd"], "loss": out["fp64"]["loss"]},
-            "mixed_path": {"forward": "fp64", "adjoint": args.precision, "fwd_s": out[runs[2][0]]["fwd"],
-                           "bwd_s": out[runs[2][0]]["bwd"], "loss": out[runs[2][0]]["loss"]}}
+            "all_%s_path" % args.precision: {"forward": args.precision, "adjoint": args.precision,
+                                              "fwd_s": out[runs[2][0]]["fwd"], "bwd_s": out[runs[2][0]]["bwd"],
+                                              "loss": out[runs[2][0]]["loss"]}}
 
 
 def bench_kdk1k(args, torch, nb):
@@ -554,11 +697,16 @@ def bench_kdk1k(args, torch, nb):
     finally:
         oracle.set_num_threads(cores)
     pairs = float(n) * (n - 1) * (steps + 1)
+    fa = torch.empty_like(tx)
+    msf, _, _ = timed(lambda: nb.nbody_accel(tx, tm, eps=eps, precision="fp64", out=fa), 200, 50, torch)
+    roof = roofline("accel_kernel<FP64> (launch-latency bound at this size)", float(n) * (n - 1) * FLOPS_PER_PAIR,
+                    msf, peak=FP64_PEAK_TFLOPS)
     return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "plummer1k_fp64", "n": n, "eps": eps, "dt": dt, "kdk_steps_per_run": steps,
                        "precision": "fp64"},
+            "roofline": roof,
             "max_abs_dx_vs_oracle": float(np.abs(gx - rx).max()),
             "max_abs_dv_vs_oracle": float(np.abs(gv - rv).max()),
             "cpu_baseline": {"value": round(pairs / cpu / 1e9, 4), "unit": UNIT, "cores": cores,
@@ -599,6 +747,8 @@ def bench_jerk(args, torch, nb):
             "steps": max(2, args.steps // 3), "warmup": 1, "ms_per_step": round(ms, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "jerk1m", "n": n, "eps": 0.001, "precision": args.precision},
+            "roofline": roofline("jerk_kernel<%s> (42 flops per interaction)" % args.precision.upper(),
+                                 pairs * FLOPS_JERK, ms),
             "fp64_path": {"value": round(pairs / (out["fp64"] * 1e-3) / 1e9, 3), "ms_per_eval": round(out["fp64"], 4)},
             "accuracy": {"accel_max_rel_vs_fp64": float(ea.max()), "jerk_max_rel_vs_fp64": float(ej.max()),
                          "jerk_p99_rel_vs_fp64": float(np.quantile(ej, 0.99))},
@@ -618,7 +768,7 @@ def bench_hermite6(args, torch, nb):
     tm = torch.tensor(m, device=dev)
     pairs = float(n) * (n - 1)
     res = {}
-    meter = GpuEnergy()
+    meter = METER
     for prec in (args.precision, "fp64"):
         # warm-up run (module load, workspace, clock ramp), then the timed run from the initial state
         wx, wv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
@@ -642,11 +792,36 @@ def bench_hermite6(args, torch, nb):
             sx, sv = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
             nb.nbody_step_hermite6(sx, sv, *[torch.empty_like(sx) for _ in range(4)], tm, dt, steps, eps=eps,
                                    precision=prec)
-        en = energy_per_call(solve, max(3, int(3000.0 / ms_tts) + 1), torch, meter)
+        en = energy_per_call(solve, max(3, int(3000.0 / ms_tts) + 1), torch, meter, IDLE_W)
         if en:
-            res[prec]["gpu_energy_to_solution_j"] = round(en[0], 1)
-            res[prec]["gpu_edp_j_s"] = round(en[0] * ms_tts * 1e-3, 2)
-            res[prec]["avg_power_w"] = round(en[0] / en[1], 1)
+            res[prec]["gpu_energy_to_solution_j"] = round(en["joules"], 1)
+            res[prec]["gpu_edp_j_s"] = round(en["joules"] * ms_tts * 1e-3, 2)
+            res[prec]["avg_power_w"] = round(en["joules"] / en["busy_s"], 1)
+            res[prec]["idle_power_w"] = round(en["idle_w"], 1)
+            res[prec]["gpu_energy_to_solution_j_with_idle_after_work"] = round(en["joules_recent_idle"], 1)
+    # roofline of the step's dominant kernel: one acceleration + jerk + snap evaluation (snap_kernel
+    # and its slice sum), timed alone with HIP events on the step's input
+    accs = torch.tensor(ics.plummer_mean_field(x), device=dev)
+    tx0, tv0 = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
+    mss, _, _ = timed(lambda: nb.nbody_accel_jerk_snap(tx0, tv0, accs, tm, eps=eps, precision=args.precision),
+                      5, 1, torch)
+    roof = roofline("snap_kernel<%s> (80 flops per interaction)" % args.precision.upper(), pairs * FLOPS_SNAP, mss)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rows_all = np.random.default_rng(9).permutation(n)
+        acc_h = ics.plummer_mean_field(x)
+        oracle.accel_jerk_snap_rows(x, v, acc_h, m, rows_all[:8], eps=eps)  # thread pool start-up
+        el, done, chunk = 0.0, 0, 512
+        while el < args.cpu_budget and done < n:
+            rr = rows_all[done:done + chunk]
+            t0 = time.perf_counter()
+            oracle.accel_jerk_snap_rows(x, v, acc_h, m, rr, eps=eps)
+            el += time.perf_counter() - t0
+            done += rr.size
+        cpu = {"value": round(done * (n - 1) / el / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "acceleration, jerk and snap of %d sampled rows x %d j (%.1f s)"
+                                           % (done, n - 1, el)}
     # per-particle potential (FP64) of the final state: the energy-distribution diagnostic
     ms_phi, _, _ = timed(lambda: nb.nbody_potential(tx, tm, eps=eps), 3, 1, torch)
     res["potential_fp64"] = {"ms": round(ms_phi, 3), "pairs_per_s_g": round(pairs / (ms_phi * 1e-3) / 1e9, 3)}
@@ -656,6 +831,7 @@ def bench_hermite6(args, torch, nb):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "hermite6_409600", "n": n, "eps": eps, "dt": dt, "steps_to_solution": steps,
                        "precision": args.precision, "evaluation": "acceleration + jerk + snap per step"},
+            "roofline": roof, "cpu_baseline": cpu,
             "paths": res,
             "paper_context": {"time_to_solution_s": {"1 Wormhole n300 chip": 1459.46, "CPU 32 threads": 2875.39},
                               "energy_to_solution_kj": {"1 Wormhole n300 chip": 385.8, "CPU 32 threads": 670.4},
@@ -712,6 +888,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    global METER, IDLE_W
+    if args.workload in ("twocomp1m_force", "hermite6_409600"):
+        # board idle power before this program's first kernel (for the energy figures)
+        METER = GpuEnergy()
+        IDLE_W = idle_power(METER)
     import paper_2605_02744_amd as nb
     nb.load()
     fn = {"twocomp1m_force": bench_force, "plummer64k_fp32c": bench_kdk64k, "ensemble512": bench_ensemble,

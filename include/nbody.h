@@ -162,7 +162,9 @@ int nbody_accel_vjp(int64_t n, const double* x, const double* m, const double* w
                     double* gx, double* gm, const nbody_params* p, void* stream);
 
 /* Reverse-mode derivative of `nsteps` KDK steps from (x0, v0) (the map of
- * nbody_step starting without NBODY_ACC_VALID), using checkpoints.
+ * nbody_step starting without NBODY_ACC_VALID), using checkpoints.  The
+ * paper defines no adjoint: this is the exact derivative of the workloads'
+ * integrator, built from the pairwise VJP above.
  *   ckpt_x, ckpt_v: [nckpt][3][n] states at steps 0, every, 2*every, ...,
  *                   nckpt = ceil(nsteps / every); checkpoint 0 is (x0, v0).
  *   gxT, gvT:       cotangents of the final positions and velocities (3*n).
@@ -181,19 +183,27 @@ int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64
                     const double* gvT, double* gx0, double* gv0, double* gm,
                     const nbody_params* p, void* stream);
 
-/* Batched ensemble: ncl independent systems concatenated along the particle
- * axis; system c owns columns [off[c], off[c+1]) of x, v, a (each 3*total,
- * SoA over the whole concatenation, total = off[ncl]) and m (total), and has
- * softening eps[c].  Each system advances nsteps KDK steps exactly as
- * nbody_step would advance it alone (same pair arithmetic, FP64 state), all
- * systems and all steps inside ONE persistent kernel launch.  off (ncl+1,
- * int64, off[0] == 0, non-decreasing) and eps (ncl) are HOST arrays; the
- * work plan built from them is cached, so a repeated call with the same
- * layout enqueues only the launch (and may be captured into a HIP graph).
- * Systems of more than 4096 particles return NBODY_EUNSUPPORTED.  The
- * largest systems may optionally be split over up to 4 workgroups that
- * exchange their positions through global memory every step
- * (nbody_config.bsplit = 1); if
+/* Batched ensemble (the workloads' ensemble of independent clusters; the
+ * paper defines no such call): ncl independent systems concatenated along the
+ * particle axis; system c owns columns [off[c], off[c+1]) of x, v, a (each
+ * 3*total, SoA over the whole concatenation, total = off[ncl]) and m (total),
+ * and has softening eps[c].  Each system advances nsteps KDK steps exactly as
+ * nbody_step would advance it alone (same pair arithmetic, FP64 state).  By
+ * default (nbody_config.bsplit and friends all zero, no tuned choice) every
+ * step is a few launches over items of 64 particles of all systems: two per
+ * step (mode 3: kicks and records, then forces), or three for FP32C/FP32
+ * layouts whose systems span several blocks of 64 (mode 4: each unordered
+ * pair of a system once, then a fixed-order sum of the far-side terms); the
+ * steps of a call may be captured into a HIP graph.  All systems and all
+ * steps run inside ONE persistent kernel launch in modes 0-2 (bsplit 0, 1, 2
+ * or nbody_tune_batched with allow_cooperative).  off (ncl+1, int64,
+ * off[0] == 0, non-decreasing) and eps (ncl) are HOST arrays; the work plan
+ * built from them is cached, so a repeated call with the same layout enqueues
+ * only the launches.  Systems of up to 2^24 particles are served by modes 2-4;
+ * the resident kernel (modes 0 and 1) returns NBODY_EUNSUPPORTED for a system
+ * of more than 4096.  In mode 1 the largest systems are split over up to 4
+ * workgroups that exchange their positions through global memory every step,
+ * and mode 2 synchronises the items of a system every step the same way; if
  * such an exchange ever waits more than about a second (the GPU shared with
  * other work), that system's x, v and a are set to NaN rather than hanging,
  * which NBODY_CHECK_FINITE reports.  p->eps is ignored; p->precision must be
@@ -319,16 +329,19 @@ typedef struct nbody_config {
  * values outside the lists above. */
 int nbody_set_config(const nbody_config* cfg);
 
-/* Autotuner: for a system of n particles and the given precision, time every
- * supported tile configuration of the force kernel with HIP events on a
- * synthetic input (synchronous; allocates and frees its own buffers) and
- * record the fastest in the library's per-device table, which automatic
- * selection then uses for that (n, precision).  If cache_path is non-NULL the
- * table is also appended there as one JSON object per line.  best (host,
+/* Autotuner (a tool of this library; the paper defines no tuner): for a
+ * system of n particles and the given precision, time every supported tile
+ * configuration of the force kernel with HIP events on a synthetic input
+ * (synchronous; allocates and frees its own buffers) and record the fastest
+ * in the library's per-device table, which automatic selection then uses for
+ * that (n, precision).  The choice is per (n, precision) because the fastest
+ * tiling depends on both, hence those arguments.  If cache_path is non-NULL
+ * the table is also appended there as one JSON object per line.  best (host,
  * may be NULL) receives the chosen configuration. */
 int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_config* best);
 
-/* Autotuner of the batched kernels for one ensemble layout (off, eps as in
+/* Autotuner of the batched kernels (a tool of this library, like
+ * nbody_tune) for one ensemble layout (off, eps as in
  * nbody_step_batched, precision and flags from p): times every candidate
  * configuration for nsteps (>= 1) KDK steps, after an untimed run of nsteps
  * steps, from the state (x, v, m), on the
@@ -342,7 +355,9 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * choice is recorded for this (device, precision, layout): later
  * nbody_step_batched calls on the same layout use it whenever the thread has
  * not forced a batched configuration with nbody_set_config.  best (may be
- * NULL) receives it as bsplit/bpass/bitem.  Synchronous; allocates and frees
+ * NULL) receives it as bsplit/bpass/bitem.  Candidates that cannot serve the
+ * layout (the resident kernel with a system above 4096 particles) are skipped.
+ * Synchronous; allocates and frees
  * its own buffers and builds (and caches) one plan per candidate.  Errors: as
  * nbody_step_batched; NBODY_EINVAL for allow_cooperative outside 0..2;
  * NBODY_ENONFINITE if no candidate stayed finite. */

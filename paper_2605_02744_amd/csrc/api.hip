@@ -522,6 +522,7 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
       return set_error(NBODY_EHIP, "tune_batched: copy failed");
     }
     int st = run_batched(ncl, off, eps, sx, sv, sa, m, dt, 0, p->G, p->precision, excl, false, cand[k], nullptr);
+    if (st == NBODY_EUNSUPPORTED) continue;  // e.g. the resident kernel with a system above 4096 particles
     if (st) { cleanup(); return st; }
     // an untimed run of the same length first: a short timed run straight after the copies
     // above mostly measures the GPU coming back to its clock, not the configuration

@@ -75,15 +75,6 @@ __host__ __device__ inline int esym_dend(const ESys& S, int b) {
   return (S.half && b >= S.nb / 2) ? S.dmax : S.dmax + 1;
 }
 
-// Orders a wave's LDS accesses around a rewrite by other lanes (LDS
-// instructions of one wave execute in order; this keeps the compiler from
-// moving reads and writes across the point).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // kicks = 0: records only; 1: v += h a, x += dt v; 2: v += h a twice (the
 // closing half-kick of the previous step and the opening one of this step,
 // rounded separately), x += dt v.  Then the pair records of the new position:
@@ -338,6 +329,7 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
                 s_j[wv][1][jl] += cy;
                 s_j[wv][2][jl] += cz;
               }
+              wave_sync();  // one row's turn ends before the next row reads the sums
             }
           }
         }

@@ -192,6 +192,7 @@ __device__ __forceinline__ P6 sym_repair(const double* __restrict__ x, int n, do
         part[kSW * kST + jl] += cy;
         part[2 * kSW * kST + jl] += cz;
       }
+      wave_sync();  // one row's turn ends before the next row reads the sums
     }
   }
   return P6{px[0], px[1], py[0], py[1], pz[0], pz[1]};

@@ -192,6 +192,7 @@ __device__ __forceinline__ void vsym_repair(const SymArgs& A, int g, int t, int 
 #pragma unroll
         for (int k = 0; k < kVC; ++k) part[k * kSW * kST + jl] += c[k];
       }
+      wave_sync();  // one row's turn ends before the next row reads the sums
     }
   }
 }

@@ -4,11 +4,23 @@ Error statistic for accelerations: per particle e_i = |a_i - a_i^ref| / |a_i^ref
 gated on the maximum over particles.  Tolerances: 1e-12 for the FP64 path and
 1e-5 for FP32C (FP32 pair arithmetic on float-float positions with compensated
 sums); FP32 (rounded positions) is held to 1e-4 on these well-separated inputs.
+
+The VJP is gated per row on its condition-normalised error |g_k - ref_k| /
+scale_k, scale_k the sum of the magnitudes of row k's terms (oracle): with
+random cotangents a row's terms cancel, so |ref_k| alone says little about the
+accuracy of its sum.  Bars (CTOL): 1e-13 for FP64; 2e-5 for FP32C, the rounding
+bound of a pair just outside the near-field radius f |x_i| (f >= 0.02), whose
+FP32 displacement is off by up to u (|x_i| + |x_j|) / |d| <= 101 u relative
+and whose term (s^-3/2, s^-5/2 d d^T) moves by about three times that; 5e-4
+for FP32 (rounded positions, no repair; these inputs hold no pair closer than
+about 1e-3 of |x|).  Trajectory gradients are gated per coordinate with
+|g - r| / max(|r|, 1e-3 max|r|) for each kind (positions, velocities, masses).
 """
 import numpy as np
 import pytest
 
 import ics
+from parity_stats import cond_err, coord_err, row_rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -124,10 +136,10 @@ def test_accel_tight_pairs_near_field(nb, oracle_mod, prec, tol):
 def test_vjp_tight_pairs_near_field(nb, oracle_mod):
     x, m = _tight_pairs_far_away(2000, seed=31)
     w = np.random.default_rng(2).standard_normal(x.shape)
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
     gx, gm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp32c")
-    assert np.linalg.norm(gx.cpu().numpy() - rgx) <= 2e-5 * np.linalg.norm(rgx)
-    assert np.linalg.norm(gm.cpu().numpy() - rgm) <= 2e-5 * np.linalg.norm(rgm)
+    cx, cm, _, _ = vjp_cond(oracle_mod, x, m, w, gx.cpu().numpy(), gm.cpu().numpy(), 1.0, 0.01)
+    print("vjp tight pairs: cond gx %.2e gm %.2e" % (cx.max(), cm.max()))
+    assert cx.max() <= CTOL["fp32c"] and cm.max() <= CTOL["fp32c"]
 
 
 def test_accel_plummer1k_fp64(nb, oracle_mod):
@@ -226,46 +238,68 @@ def test_energy_eps_zero_excludes_self(nb, oracle_mod):
     assert abs(e[1] - ref[1]) <= 1e-12 * abs(ref[1])
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32c", 2e-5), ("fp32", 2e-4)])
+CTOL = {"fp64": 1e-13, "fp32c": 2e-5, "fp32": 5e-4}
+
+
+def vjp_cond(oracle_mod, x, m, w, gx, gm, G, eps):
+    """Per-row condition-normalised errors of (gx, gm) against the oracle."""
+    rows = np.arange(m.shape[0])
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, G=G, eps=eps)
+    sx, sm = oracle_mod.accel_vjp_scale_rows(x, m, w, rows, G=G, eps=eps)
+    return cond_err(gx, rgx, sx), cond_err(gm, rgm, sm), row_rel(gx, rgx), row_rel(gm, rgm)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 @pytest.mark.parametrize("n", [2, 65, 1000, 2049])
-def test_vjp_matches_oracle(nb, oracle_mod, prec, tol, n):
+def test_vjp_matches_oracle(nb, oracle_mod, prec, n):
     x, _, m = ics.two_component(n, seed=11)
     w = np.random.default_rng(n).standard_normal((3, n))
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, G=0.7, eps=0.02)
     gx, gm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), G=0.7, eps=0.02, precision=prec)
-    gx, gm = gx.cpu().numpy(), gm.cpu().numpy()
-    assert np.linalg.norm(gx - rgx) <= tol * np.linalg.norm(rgx)
-    assert np.linalg.norm(gm - rgm) <= tol * np.linalg.norm(rgm)
+    cx, cm, rx, rm = vjp_cond(oracle_mod, x, m, w, gx.cpu().numpy(), gm.cpu().numpy(), 0.7, 0.02)
+    print("vjp n=%d %s: cond gx %.2e gm %.2e; rel gx %.2e gm %.2e (max over rows)"
+          % (n, prec, cx.max(), cm.max(), rx.max(), rm.max()))
+    assert cx.max() <= CTOL[prec] and cm.max() <= CTOL[prec]
 
 
 def test_vjp_split_configs_agree(nb, oracle_mod):
     n = 3000
     x, _, m = ics.plummer(n, seed=12)
     w = np.random.default_rng(1).standard_normal((3, n))
-    rgx, _ = oracle_mod.accel_vjp(x, m, w, eps=0.01)
     for ipl, split in ((1, 1), (2, 5), (1, 11)):
         nb.nbody_set_config(ipl=ipl, split=split)
         try:
-            gx, _ = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp64")
+            gx, gm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp64")
         finally:
             nb.nbody_set_config()
-        assert np.linalg.norm(gx.cpu().numpy() - rgx) <= 1e-11 * np.linalg.norm(rgx)
+        cx, cm, _, _ = vjp_cond(oracle_mod, x, m, w, gx.cpu().numpy(), gm.cpu().numpy(), 1.0, 0.01)
+        assert cx.max() <= CTOL["fp64"] and cm.max() <= CTOL["fp64"], (ipl, split, cx.max(), cm.max())
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32c", 1e-4)])
-def test_traj_grad_matches_oracle(nb, oracle_mod, prec, tol):
+@pytest.mark.parametrize("prec,fwd,tol", [("fp64", None, 1e-9), ("fp32c", None, 1e-4), ("fp32c", "fp32c", 1e-4)])
+def test_traj_grad_matches_oracle(nb, oracle_mod, prec, fwd, tol):
+    """Checkpointed trajectory gradient against the oracle's full adjoint, per
+    coordinate.  ("fp32c", None) is the library's FP32C gradient (FP64
+    forward, FP32C sweep); ("fp32c", "fp32c") differentiates the FP32C
+    trajectory, a different map, and is held to the same bar relative to the
+    largest component of each kind."""
     n, steps, every, dt, eps = 512, 23, 5, 1.0 / 256, 0.01
     x, v, m = ics.plummer(n, seed=13)
     tgt, _ = ics.perturb(x, v, 1e-3, seed=14)
     loss, (rgx, rgv, rgm) = oracle_mod.loss_grad(x, v, m, tgt, dt, steps, eps=eps)
     tx, tv, tm = dev(x).requires_grad_(), dev(v).requires_grad_(), dev(m).requires_grad_()
-    xT, _ = nb.NBodyTrajectory.apply(tx, tv, tm, dt, steps, every, 1.0, eps, prec)
+    xT, _ = nb.NBodyTrajectory.apply(tx, tv, tm, dt, steps, every, 1.0, eps, prec, fwd)
     L = ((xT - dev(tgt)) ** 2).sum() / n
     L.backward()
-    assert abs(L.item() - loss) <= (1e-12 if prec == "fp64" else 1e-5) * loss
-    for g, r in ((tx.grad, rgx), (tv.grad, rgv), (tm.grad, rgm)):
+    assert abs(L.item() - loss) <= (1e-5 if fwd == "fp32c" else 1e-12) * loss
+    for kind, g, r in (("x", tx.grad, rgx), ("v", tv.grad, rgv), ("m", tm.grad, rgm)):
         g = g.cpu().numpy()
-        assert np.linalg.norm(g - r) <= tol * np.linalg.norm(r), (prec, np.linalg.norm(g - r) / np.linalg.norm(r))
+        e = coord_err(g, r)
+        ek = np.abs(g - r).max() / np.abs(r).max()
+        print("traj grad %s (forward %s) %s: per coordinate %.2e, vs largest %.2e" % (prec, fwd, kind, e.max(), ek))
+        if fwd == "fp32c":
+            assert ek <= tol, kind
+        else:
+            assert e.max() <= tol, kind
 
 
 def test_traj_grad_recompute_matches_forward(nb):
@@ -273,7 +307,7 @@ def test_traj_grad_recompute_matches_forward(nb):
     n, steps = 700, 13
     x, v, m = ics.plummer(n, seed=15)
     tx, tv, tm = dev(x), dev(v), dev(m)
-    xT, vT = nb.trajectory(tx, tv, tm, 1.0 / 128, steps, 4, 1.0, 0.01, "fp32c")
+    xT, vT = nb.trajectory(tx, tv, tm, 1.0 / 128, steps, 4, 1.0, 0.01, "fp32c", "fp32c")
     ax, av = dev(x), dev(v)
     aa = torch.empty_like(ax)
     nb.nbody_step(ax, av, aa, tm, 1.0 / 128, steps, eps=0.01, precision="fp32c")
@@ -515,6 +549,34 @@ def test_tune_batched_records_and_applies_choice(nb):
     best1 = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision="fp32c",
                                   allow_cooperative="persistent")
     assert best1["bsplit"] in (0, 1, 2)
+
+
+def test_tune_batched_skips_candidates_that_cannot_serve_the_layout(nb, oracle_mod):
+    """A layout with a system above 4096 particles: the resident kernel
+    cannot hold it (NBODY_EUNSUPPORTED), so the tuner skips it and picks one
+    of the per-step item modes, which then runs the layout to the oracle's
+    accelerations (1e-5 per row)."""
+    sizes = [8192, 100, 300]
+    off, epsv, x, v, m = ics.ensemble(len(sizes), seed=28, sizes=sizes)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    nb.nbody_set_config(bsplit=0, bpass=4)
+    try:
+        with pytest.raises(nb.NBodyError) as ei:
+            nb.nbody_step_batched(off, epsv, tx.clone(), tv.clone(), torch.empty_like(tx), tm, 1.0 / 512, 1,
+                                  precision="fp32c")
+        assert ei.value.status == nb.NBODY_EUNSUPPORTED
+    finally:
+        nb.nbody_set_config()
+    for prec, modes in (("fp32c", (3, 4)), ("fp64", (3,))):
+        best = nb.nbody_tune_batched(off, epsv, tx, tv, tm, 1.0 / 512, 2, precision=prec, allow_cooperative=False)
+        assert best["bsplit"] in modes, (prec, best)
+    ta = torch.empty_like(tx)
+    nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 0, precision="fp32c")
+    a = ta.cpu().numpy()
+    for c in range(len(sizes)):
+        s_, e_ = off[c], off[c + 1]
+        ref = oracle_mod.accel(x[:, s_:e_], m[s_:e_], eps=float(epsv[c]))
+        assert row_rel(a[:, s_:e_], ref).max() <= 1e-5, c
 
 
 def test_batched_matches_oracle_fp64(nb, oracle_mod):

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import ics
+from parity_stats import cond_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -169,9 +170,12 @@ def test_sym_tune_candidate(nb):
 # ---------------------------------------------------------------- VJP
 # (da/dx)^T w and (da/dm)^T w from the symmetric kernel: the pair term changes
 # sign under k <-> j (d and u = m_k w_j - m_j w_k both do), so each unordered
-# pair serves both particles.  Same norm-wise bars as the ordered VJP tests.
+# pair serves both particles.  Gated per row on the condition-normalised error
+# |g_k - ref_k| / scale_k (scale_k: the sum of the magnitudes of row k's terms,
+# from the oracle), with the ordered VJP's bars: 2e-5 for FP32C (the rounding
+# bound of a pair just outside the near-field radius), 5e-4 for FP32.
 
-VTOL = {"fp32c": 2e-5, "fp32": 2e-4}
+CTOL = {"fp32c": 2e-5, "fp32": 5e-4}
 
 
 def sym_vjp(nb, x, m, w, launches=0, **kw):
@@ -183,8 +187,11 @@ def sym_vjp(nb, x, m, w, launches=0, **kw):
         nb.nbody_set_config()
 
 
-def vjp_err(g, ref):
-    return np.linalg.norm(g - ref) / np.linalg.norm(ref)
+def vjp_cond(oracle_mod, x, m, w, gx, gm, G=1.0, eps=0.0):
+    """Largest per-row condition-normalised errors of gx and gm."""
+    rgx, rgm = oracle_mod.accel_vjp(x, m, w, G=G, eps=eps)
+    sx, sm = oracle_mod.accel_vjp_scale_rows(x, m, w, np.arange(m.shape[0]), G=G, eps=eps)
+    return cond_err(gx, rgx, sx).max(), cond_err(gm, rgm, sm).max()
 
 
 @pytest.mark.parametrize("n", [2, 511, 513, 1025, 2048, 3001])
@@ -192,23 +199,21 @@ def vjp_err(g, ref):
 def test_sym_vjp_matches_oracle(nb, oracle_mod, n, prec):
     x, _, m = ics.two_component(n, seed=11)
     w = np.random.default_rng(n).standard_normal((3, n))
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, G=0.7, eps=0.02)
     print("sym vjp n=%d %s" % (n, prec), flush=True)
     gx, gm = sym_vjp(nb, x, m, w, G=0.7, eps=0.02, precision=prec)
-    print("  gx %.3e gm %.3e" % (vjp_err(gx, rgx), vjp_err(gm, rgm)))
-    assert vjp_err(gx, rgx) <= VTOL[prec]
-    assert vjp_err(gm, rgm) <= VTOL[prec]
+    ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, G=0.7, eps=0.02)
+    print("  cond gx %.3e gm %.3e" % (ex, em))
+    assert ex <= CTOL[prec] and em <= CTOL[prec]
 
 
 @pytest.mark.parametrize("n,launches", [(5000, 3), (9000, 9)])
 def test_sym_vjp_launch_splits(nb, oracle_mod, n, launches):
     x, _, m = ics.plummer(n, seed=42)
     w = np.random.default_rng(42).standard_normal((3, n))
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
     print("sym vjp n=%d launches=%d" % (n, launches), flush=True)
     gx, gm = sym_vjp(nb, x, m, w, launches=launches, eps=0.01, precision="fp32c")
-    assert vjp_err(gx, rgx) <= VTOL["fp32c"]
-    assert vjp_err(gm, rgm) <= VTOL["fp32c"]
+    ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.01)
+    assert ex <= CTOL["fp32c"] and em <= CTOL["fp32c"]
 
 
 def test_sym_vjp_tight_pairs_near_field(nb, oracle_mod):
@@ -221,21 +226,22 @@ def test_sym_vjp_tight_pairs_near_field(nb, oracle_mod):
     off *= 10 ** rng.uniform(-5, -3, 200) / np.linalg.norm(off, axis=0)
     x[:, b_idx] = x[:, a_idx] + off
     w = np.random.default_rng(2).standard_normal(x.shape)
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
     gx, gm = sym_vjp(nb, x, m, w, eps=0.01, precision="fp32c")
-    print("sym vjp tight pairs gx %.3e gm %.3e" % (vjp_err(gx, rgx), vjp_err(gm, rgm)))
-    assert vjp_err(gx, rgx) <= VTOL["fp32c"]
-    assert vjp_err(gm, rgm) <= VTOL["fp32c"]
+    ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.01)
+    print("sym vjp tight pairs cond gx %.3e gm %.3e" % (ex, em))
+    assert ex <= CTOL["fp32c"] and em <= CTOL["fp32c"]
 
 
 def test_sym_vjp_exclude_self_eps_zero(nb, oracle_mod):
+    """eps = 0 with the own pair excluded: the unsoftened terms of the closest
+    pairs dominate their rows, so the FP32C bar is taken ten times looser."""
     x, _, m = ics.random_cloud(1500, seed=3)
     w = np.random.default_rng(5).standard_normal(x.shape)
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.0)
     gx, gm = sym_vjp(nb, x, m, w, eps=0.0, precision="fp32c", exclude_self=True)
     assert np.isfinite(gx).all() and np.isfinite(gm).all()
-    assert vjp_err(gx, rgx) <= 10 * VTOL["fp32c"]
-    assert vjp_err(gm, rgm) <= 10 * VTOL["fp32c"]
+    ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.0)
+    print("sym vjp eps=0 cond gx %.3e gm %.3e" % (ex, em))
+    assert ex <= 10 * CTOL["fp32c"] and em <= 10 * CTOL["fp32c"]
 
 
 def test_sym_vjp_repeat_bitwise_and_agrees_with_ordered(nb, oracle_mod):
@@ -248,9 +254,9 @@ def test_sym_vjp_repeat_bitwise_and_agrees_with_ordered(nb, oracle_mod):
         ogx, ogm = nb.nbody_accel_vjp(dev(x), dev(m), dev(w), eps=0.01, precision="fp32c")
     finally:
         nb.nbody_set_config()
-    rgx, rgm = oracle_mod.accel_vjp(x, m, w, eps=0.01)
-    assert vjp_err(runs[0][0], rgx) <= VTOL["fp32c"] and vjp_err(ogx.cpu().numpy(), rgx) <= VTOL["fp32c"]
-    assert vjp_err(runs[0][1], rgm) <= VTOL["fp32c"] and vjp_err(ogm.cpu().numpy(), rgm) <= VTOL["fp32c"]
+    for gx, gm in (runs[0], (ogx.cpu().numpy(), ogm.cpu().numpy())):
+        ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.01)
+        assert ex <= CTOL["fp32c"] and em <= CTOL["fp32c"]
 
 
 def test_sym_traj_grad_matches_ordered(nb):
@@ -266,13 +272,14 @@ def test_sym_traj_grad_matches_ordered(nb):
             tx = dev(x).requires_grad_(True)
             tv = dev(v).requires_grad_(True)
             tm = dev(m).requires_grad_(True)
-            xT, _ = nb.NBodyTrajectory.apply(tx, tv, tm, dt, steps, every, 1.0, 0.01, "fp32c", None)
+            xT, _ = nb.NBodyTrajectory.apply(tx, tv, tm, dt, steps, every, 1.0, 0.01, "fp32c", "fp32c")
             ((xT - dev(tgt)) ** 2).sum().backward()
             out[pairs] = (tx.grad.cpu().numpy(), tv.grad.cpu().numpy(), tm.grad.cpu().numpy())
         finally:
             nb.nbody_set_config()
     for a, b in zip(out[1], out[2]):
-        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a)
+        # per coordinate, relative to the largest component of each kind
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
 
 
 # ---------------------------------------------------------------- FP64
