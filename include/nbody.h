@@ -321,6 +321,21 @@ typedef struct nbody_config {
                       (reproducible), at the cost of a workspace of about
                       1.5 GiB for large n and, in FP32C/FP32, an FP32 sum of up
                       to 512 terms per j before the FP64 sums */
+  int32_t rescue;  /* FP32C force of nbody_accel, nbody_accel_noalloc, the
+                      KDK steps of nbody_step and of the adjoint's recompute,
+                      and of nbody_step_batched with the per-step items of 64
+                      (mode 3): 0 = automatic (on where the kernels carry it),
+                      1 = on (batched modes other than 3 then return
+                      NBODY_EUNSUPPORTED), 2 = off.  On: while summing, the
+                      kernels estimate each row's FP32 rounding error (per
+                      block of terms summed in FP32: the magnitude of the
+                      block's partial sum, weighted by the distance of its
+                      closest pair left in rounded positions; blocks combined
+                      as independent errors), and rows whose estimate exceeds
+                      4e-6 |a_i| (rows whose terms cancel strongly) are
+                      recomputed in FP64; this keeps such rows inside the 1e-5
+                      FP32C bound at the cost of one FP64 row evaluation each
+                      (0.4 % of the rows of the 2^20 two-component model). */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros
@@ -351,8 +366,12 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * for FP32C and FP32, their symmetric form (mode 4); with allow_cooperative != 0 also the
  * split mode and the streamed kernel with items of 64, 256, 512 or 1024 particles
  * (the modes that need every workgroup of a launch resident at once). allow_cooperative = 2 keeps
- * to the single-launch modes 0, 1 and 2 (all steps in one persistent launch).  The
- * choice is recorded for this (device, precision, layout): later
+ * to the single-launch modes 0, 1 and 2 (all steps in one persistent launch).
+ * FP32C with the rescue on (nbody_config.rescue 0 or 1) has one candidate, the
+ * per-step items of 64 (mode 3), the only batched form that carries it; the
+ * single-launch search (allow_cooperative = 2) then goes without the rescue,
+ * or returns NBODY_EUNSUPPORTED if the rescue was asked for explicitly.  The
+ * choice is recorded for this (device, precision, rescue, layout): later
  * nbody_step_batched calls on the same layout use it whenever the thread has
  * not forced a batched configuration with nbody_set_config.  best (may be
  * NULL) receives it as bsplit/bpass/bitem.  Candidates that cannot serve the

@@ -48,7 +48,7 @@ class nbody_params(ctypes.Structure):
 class nbody_config(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32), ("bitem", ctypes.c_int32),
-                ("pairs", ctypes.c_int32)]
+                ("pairs", ctypes.c_int32), ("rescue", ctypes.c_int32)]
 
 
 _lib = None
@@ -337,19 +337,22 @@ def nbody_step_hermite6(x, v, a, jk, sn, cr, m, dt, nsteps, *, G=1.0, eps, preci
                                        _stream(x.device)))
 
 
-def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0):
-    """Forces a tile configuration on this thread (all zeros = automatic);
-    bsplit=1 lets the ensemble kernel split its largest systems over up to 4
-    workgroups, bsplit=2 selects the streamed ensemble kernel (systems cut into
-    items, one persistent launch), bsplit=3 its items of 64 particles with two
-    launches per step, bsplit=4 as 3 with each unordered pair of a system
-    evaluated once (FP32C, FP32), default 0: one workgroup per system; bpass sets
-    how many of a lane's i-particles the ensemble kernel evaluates per pass
-    (1, 2, 4); bitem the streamed kernel's item size (64, the automatic
-    choice: one wave per item; or 256, 512, 1024: one workgroup per item);
-    pairs the form of the force kernels (1 ordered, 2 symmetric: each
-    unordered pair once; 0 automatic; the VJP follows in FP32C/FP32)."""
-    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem), int(pairs))
+def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0, rescue=0):
+    """Forces a tile configuration on this thread (all zeros = automatic).
+    Ensemble (nbody_step_batched): bsplit=0 with bpass set runs one workgroup
+    per system (its records resident in LDS), bsplit=1 as 0 with the largest
+    systems split over up to 4 workgroups, bsplit=2 the streamed kernel
+    (systems cut into items, one persistent launch), bsplit=3 its items of 64
+    particles with two launches per step, bsplit=4 as 3 with each unordered pair
+    of a system evaluated once (FP32C, FP32); all zero: the tuned choice for the
+    layout, else mode 4 or 3.  bpass sets how many of a lane's i-particles the
+    resident kernel evaluates per pass (1, 2, 4); bitem the streamed kernel's
+    item size (64, the automatic choice: one wave per item; or 256, 512, 1024:
+    one workgroup per item).  pairs: the form of the force kernels (1 ordered,
+    2 symmetric: each unordered pair once; 0 automatic; the VJP follows in
+    FP32C/FP32).  rescue: FP32C force rows flagged by the kernels' error
+    estimate recomputed in FP64 (0 automatic = on, 1 on, 2 off)."""
+    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem), int(pairs), int(rescue))
     _check(load().nbody_set_config(ctypes.byref(c)))
 
 

@@ -118,7 +118,7 @@ void release_workspaces() {
 
 // ------------------------------------------------------------- configuration
 namespace {
-thread_local nbody_config t_cfg = {0, 0, 0, 0, 0};
+thread_local nbody_config t_cfg = {0, 0, 0, 0, 0, 0, 0};
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int64_t>, PairConfig> g_tuned;  // (device, precision, n)
 }  // namespace
@@ -164,6 +164,7 @@ PairConfig choose_config(int64_t n, int precision, int device) {
   if (t.ipl) c.ipl = t.ipl;
   if (t.split) c.split = t.split;
   if (t.pairs) c.sym = t.pairs == 2 ? 1 : 0;
+  c.rescue = t.rescue == 2 ? 0 : 1;
   // the symmetric kernels read split as a least number of launches (0 = automatic)
   if (c.sym) {
     c.split = t.split;
@@ -287,6 +288,7 @@ std::vector<TunedBatch> g_tuned_batch;
 BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps, int precision, int device) {
   const nbody_config& t = t_cfg;
   BatchConfig bc;
+  bc.rescue = t.rescue == 2 ? 0 : 1;
   if (t.bsplit || t.bpass || t.bitem) {
     bc.mode = t.bsplit;
     bc.pass = t.bpass;
@@ -296,9 +298,13 @@ BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps,
   std::lock_guard<std::mutex> lk(g_tb_mu);
   for (const TunedBatch& e : g_tuned_batch)
     if (e.device == device && e.precision == precision && (int)e.eps.size() == ncl &&
-        std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps))
+        std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps) &&
+        e.bc.rescue == bc.rescue)
       return e.bc;
-  bc.mode = (precision != NBODY_FP64 && sym_ensemble_default(ncl, off)) ? 4 : 3;
+  // FP32C with the rescue runs the per-step wave items (mode 3, the batched
+  // form with the rescue); otherwise their symmetric form where it pays
+  const bool sym = precision == NBODY_FP32 || (precision == NBODY_FP32C && !bc.rescue);
+  bc.mode = (sym && sym_ensemble_default(ncl, off)) ? 4 : 3;
   return bc;
 }
 
@@ -469,6 +475,8 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
   if (x == v || x == a || v == a) return set_error(NBODY_EINVAL, "x, v and a must be distinct");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const BatchConfig bc = batch_config_for(ncl, off, eps, p->precision, current_device());
+  if (p->precision == NBODY_FP32C && t_cfg.rescue == 1 && bc.mode != 3)
+    return set_error(NBODY_EUNSUPPORTED, "batched: the FP32C rescue runs with the per-step wave items (bsplit 3) only");
   int st = run_batched(ncl, off, eps, x, v, a, m, dt, nsteps, p->G, p->precision,
                        (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, bc, s);
   return finish(st, s, p, {{x, 3 * total}, {v, 3 * total}, {a, 3 * total}});
@@ -488,15 +496,24 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   NB_TRY(check_dev_range(v, b3, "v"));
   NB_TRY(check_dev_range(m, b1, "m"));
   const int dev = current_device();
+  const int rescue = t_cfg.rescue == 2 ? 0 : 1;
   std::vector<BatchConfig> cand;
-  for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0});
-  if (allow_cooperative != 2) {
-    cand.push_back(BatchConfig{3, 0, 64});
-    if (p->precision != NBODY_FP64) cand.push_back(BatchConfig{4, 0, 0});
-  }
-  if (allow_cooperative) {
-    cand.push_back(BatchConfig{1, 0, 0});
-    for (int item : {64, 256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item});
+  if (p->precision == NBODY_FP32C && rescue && (allow_cooperative != 2 || t_cfg.rescue == 1)) {
+    // only the per-step wave items carry the FP32C rescue (the single-launch
+    // search, allow_cooperative = 2, goes without it unless it was asked for)
+    if (allow_cooperative == 2)
+      return set_error(NBODY_EUNSUPPORTED, "tune_batched: no single-launch mode carries the FP32C rescue");
+    cand.push_back(BatchConfig{3, 0, 64, 1});
+  } else {
+    for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0, rescue});
+    if (allow_cooperative != 2) {
+      cand.push_back(BatchConfig{3, 0, 64, rescue});
+      if (p->precision != NBODY_FP64) cand.push_back(BatchConfig{4, 0, 0, rescue});
+    }
+    if (allow_cooperative) {
+      cand.push_back(BatchConfig{1, 0, 0, rescue});
+      for (int item : {64, 256, 512, 1024}) cand.push_back(BatchConfig{2, 0, item, rescue});
+    }
   }
   double *sx = nullptr, *sv = nullptr, *sa = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -550,7 +567,8 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
     bool found = false;
     for (TunedBatch& e : g_tuned_batch)
       if (e.device == dev && e.precision == p->precision && (int)e.eps.size() == ncl &&
-          std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps)) {
+          std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps) &&
+          e.bc.rescue == bc.rescue) {
         e.bc = bc;
         found = true;
       }
@@ -558,7 +576,7 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
       g_tuned_batch.push_back(TunedBatch{dev, p->precision, std::vector<int64_t>(off, off + ncl + 1),
                                          std::vector<double>(eps, eps + ncl), bc});
   }
-  if (best) *best = nbody_config{0, 0, bc.mode, bc.pass, bc.item};
+  if (best) *best = nbody_config{0, 0, bc.mode, bc.pass, bc.item, 0, 0};
   return NBODY_OK;
 }
 
@@ -672,6 +690,7 @@ int nbody_set_config(const nbody_config* cfg) {
   if (cfg->bitem != 0 && cfg->bitem != 64 && cfg->bitem != 256 && cfg->bitem != 512 && cfg->bitem != 1024)
     return set_error(NBODY_EINVAL, "bitem must be 0, 64, 256, 512 or 1024");
   if (cfg->pairs < 0 || cfg->pairs > 2) return set_error(NBODY_EINVAL, "pairs must be 0, 1 or 2");
+  if (cfg->rescue < 0 || cfg->rescue > 2) return set_error(NBODY_EINVAL, "rescue must be 0, 1 or 2");
   set_thread_config(*cfg);
   return NBODY_OK;
 }
@@ -765,7 +784,7 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
   }
   cleanup();
   record_tuned(dev, n, precision, bc);
-  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0, 0, bc.sym ? 2 : 1};
+  if (best) *best = nbody_config{bc.ipl, bc.split, 0, 0, 0, bc.sym ? 2 : 1, 0};
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {

@@ -50,6 +50,7 @@ struct PairConfig {
   int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups
   int sym = 0;    // 1: the symmetric kernels (each unordered pair once; the VJP in FP32C/FP32 only)
+  int rescue = 1;  // FP32C force: recompute rows flagged by the error estimate in FP64
   // Device memory the caller lends for this call's partial sums, staged
   // records and slots.  When set, the all-pairs launchers fit their plans into
   // scratch_bytes and never touch the library workspace (no allocation).
@@ -112,6 +113,13 @@ int run_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double*
                  double dt, int64_t nsteps, double G, double eps, int precision, bool exclude_self, bool acc_valid,
                  const PairConfig& cfg, hipStream_t s);
 
+// FP64 rescue of ill-conditioned FP32C rows: flags the rows whose error
+// estimate (the sum of nslices float slices of est, stride apart) is too large
+// against |a_i| and recomputes them in FP64 in place in a.  list (n ints) and
+// count (one int) are scratch.
+int launch_rescue(int64_t n, const double* x, const double* m, double eps, double G, bool excl, const float* est,
+                  int nslices, size_t stride, double* a, int* list, int* count, hipStream_t s);
+
 // Elementwise KDK pieces over 3n entries.
 int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s);
 int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double h, double dt,
@@ -129,7 +137,15 @@ struct BatchConfig {
   int mode = 0;
   int pass = 0;
   int item = 0;
+  int rescue = 1;  // FP32C, mode 3: rows flagged by the error estimate recomputed in FP64
 };
+
+// FP64 rescue of flagged FP32C rows of an ensemble (the layout's offsets and
+// softenings on the device): as launch_rescue, each row against its own
+// system.
+int launch_rescue_batched(int64_t total, int ncl, const int64_t* off, const double* epsv, const double* x,
+                          const double* m, double G, bool excl, const float* est, double* a, int* list, int* count,
+                          hipStream_t s);
 
 // nsteps KDK steps of every system of the ensemble with the given kernel configuration.
 int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,

@@ -585,20 +585,20 @@ int launch_plan(const Plan* p, double* x, double* v, double* a, const double* m,
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                       bool acc_valid, int bitem, bool per_step, hipStream_t s);
+                       bool acc_valid, int bitem, bool per_step, bool rescue, hipStream_t s);
 
 int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                     const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
-                    hipStream_t s);
+                    bool rescue, hipStream_t s);
 
 int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                 const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
                 const BatchConfig& bc, hipStream_t s) {
   if (bc.mode == 4)
-    return run_batched_sym(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, s);
+    return run_batched_sym(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, bc.rescue != 0, s);
   if (bc.mode == 2 || bc.mode == 3)
     return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, bc.item,
-                              bc.mode == 3, s);
+                              bc.mode == 3, bc.rescue != 0, s);
   const int device = current_device();
   const bool allow_split = bc.mode == 1;
   std::lock_guard<std::mutex> lk(g_plan_mu);

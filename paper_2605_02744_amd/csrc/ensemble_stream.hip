@@ -544,11 +544,13 @@ __global__ void ens_kick_kernel(int64_t total, double* __restrict__ v, const dou
     v[e] = fma(h, a[e], v[e]);
 }
 
+// With est (FP32C): each particle's rounding-error estimate for the rescue
+// (one share per block of 64 j, see rescue.hip) goes to est[i].
 template <int MODE, bool EXCL>
 __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_waveforce_kernel(
     const int64_t* __restrict__ off, const double* __restrict__ epsv, const SItem* __restrict__ items,
     const int* __restrict__ wg_off, const int* __restrict__ wg_list, const JRec<MODE>* __restrict__ xrec,
-    double* __restrict__ a, int64_t total, double G) {
+    double* __restrict__ a, int64_t total, double G, float* __restrict__ est) {
   using R = Real<MODE>;
   constexpr bool kNear = MODE == kFP32C;
   __shared__ JRec<MODE> slot[kWWaves][64];
@@ -575,7 +577,11 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
     IPos<MODE> pi;
     pi.from(src[ii]);
     R rc2 = R(0);
-    if constexpr (kNear) rc2 = near_rc2(pi.hx, pi.hy, pi.hz, eps, nc);
+    float xinf = 0.f, eacc = 0.f;
+    if constexpr (kNear) {
+      rc2 = near_rc2(pi.hx, pi.hy, pi.hz, eps, nc);
+      xinf = fmaxf(fabsf(pi.hx), fmaxf(fabsf(pi.hy), fabsf(pi.hz)));
+    }
     R hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
     JRec<MODE> nxt = lane < nc ? src[lane] : JRec<MODE>::make(kFarAway, kFarAway, kFarAway, 0.0);
 #pragma unroll 1
@@ -610,7 +616,7 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
         if constexpr (kNear) {
           if (r2min < rc2) {
             // rare: redo this block with float-float displacements for the close pairs
-            R qx = 0, qy = 0, qz = 0;
+            R qx = 0, qy = 0, qz = 0, r2nr = R(3.0e38f);
             for (int jj = 0; jj < jend; ++jj) {
               const JRec<MODE> rj = buf[jj];
               R dx, dy, dz;
@@ -619,6 +625,8 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
               if (r2 < rc2) {
                 disp(rj, pi, dx, dy, dz);
                 r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              } else {
+                r2nr = fminf(r2nr, r2);
               }
               const R ri = rsq(r2);
               R sc = (jmass(rj) * ri) * (ri * ri);
@@ -630,7 +638,9 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
             px = qx;
             py = qy;
             pz = qz;
+            r2min = r2nr;
           }
+          if (est) eacc = est_add(eacc, px, py, pz, xinf, r2min);
         }
         fold(hx, lx, px);
         fold(hy, ly, py);
@@ -650,6 +660,7 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
       a[i] = G * ((double)hx + (double)lx);
       a[total + i] = G * ((double)hy + (double)ly);
       a[2 * total + i] = G * ((double)hz + (double)lz);
+      if (kNear && est) est[i] = eacc;
     }
   }
 }
@@ -675,6 +686,8 @@ struct SPlan {
   int2* d_ws_sys = nullptr;  // wave items: (system, items of it held by the workgroup)
   void* d_xrec = nullptr;
   int* d_cnt = nullptr;
+  float* d_est = nullptr;  // per-step wave items, FP32C: the rescue's error estimates (total)
+  int* d_list = nullptr;   // and its count and list of flagged rows (64 + total)
 };
 
 std::mutex g_splan_mu;
@@ -682,7 +695,8 @@ std::vector<SPlan*> g_splans;
 
 void free_splan(SPlan* p) {
   for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_nparts, (void*)p->d_items, (void*)p->d_wg_off,
-                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt})
+                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt,
+                  (void*)p->d_est, (void*)p->d_list})
     if (q) (void)hipFree(q);
   delete p;
 }
@@ -890,6 +904,9 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
             supload(&p->d_ws_off, ws_off) && supload(&p->d_ws_sys, ws_sys) &&
             hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
             hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
+  if (ok && MODE == kFP32C)
+    ok = hipMalloc(&p->d_est, sizeof(float) * (size_t)std::max<int64_t>(1, p->total)) == hipSuccess &&
+         hipMalloc(&p->d_list, sizeof(int) * (size_t)(64 + std::max<int64_t>(1, p->total))) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     free_splan(p);
@@ -942,19 +959,25 @@ int launch_splan(const SPlan* p, double* x, double* v, double* a, const double* 
 
 template <int MODE>
 int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
-                  double G, bool acc_valid, bool excl, hipStream_t s) {
+                  double G, bool acc_valid, bool excl, bool rescue, hipStream_t s) {
   if (p->total == 0 || (nsteps == 0 && acc_valid)) return NBODY_OK;
   auto* rec = static_cast<JRec<MODE>*>(p->d_xrec);
   const double h = 0.5 * dt;
   const unsigned ew = (unsigned)std::min<int64_t>((p->total + 255) / 256, 4096);
+  rescue = rescue && MODE == kFP32C && p->d_est;
+  float* est = rescue ? p->d_est : nullptr;
   auto force = [&]() -> int {
     if (excl)
       ens_waveforce_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
-                                                                  p->d_wg_list, rec, a, p->total, G);
+                                                                  p->d_wg_list, rec, a, p->total, G, est);
     else
       ens_waveforce_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
-                                                                   p->d_wg_list, rec, a, p->total, G);
+                                                                   p->d_wg_list, rec, a, p->total, G, est);
     NB_LAUNCH_CHECK("ens_waveforce_kernel");
+    // the rows whose error estimate is too large, recomputed in FP64 from the new positions
+    if (rescue)
+      return launch_rescue_batched(p->total, p->ncl, p->d_off, p->d_eps, x, m, G, excl, est, a, p->d_list + 64,
+                                   p->d_list, s);
     return NBODY_OK;
   };
   int st;
@@ -979,7 +1002,7 @@ int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double*
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                       bool acc_valid, int bitem, bool per_step, hipStream_t s) {
+                       bool acc_valid, int bitem, bool per_step, bool rescue, hipStream_t s) {
   const int device = current_device();
   // automatic item size: items of 64 particles evaluated by one wave each (faster than
   // items of 1024 on every measured layout but one, 64 x 4096, where it is 2 % slower)
@@ -1006,9 +1029,11 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
     g_splans.push_back(p);
   }
   if (per_step) {
-    if (precision == NBODY_FP64) return launch_wsteps<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
-    if (precision == NBODY_FP32C) return launch_wsteps<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
-    return launch_wsteps<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+    if (precision == NBODY_FP64)
+      return launch_wsteps<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, false, s);
+    if (precision == NBODY_FP32C)
+      return launch_wsteps<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, rescue, s);
+    return launch_wsteps<NBODY_FP32>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, false, s);
   }
   if (precision == NBODY_FP64) return launch_splan<NBODY_FP64>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
   if (precision == NBODY_FP32C) return launch_splan<NBODY_FP32C>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);

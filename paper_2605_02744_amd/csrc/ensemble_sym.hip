@@ -588,15 +588,17 @@ int launch_esteps(const EPlan* p, double* x, double* v, double* a, const double*
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,
-                       bool acc_valid, int bitem, bool per_step, hipStream_t s);
+                       bool acc_valid, int bitem, bool per_step, bool rescue, hipStream_t s);
 
 // Mode 4.  FP64, and layouts whose slots would exceed kESlotCap, run the
-// ordered per-step wave items (mode 3) instead.
+// ordered per-step wave items (mode 3) instead, with the FP32C rescue as asked.
+// Mode 4 itself has no rescue.
 int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                     const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
-                    hipStream_t s) {
+                    bool rescue, hipStream_t s) {
   if (precision == NBODY_FP64 || esym_slot_bytes(ncl, off) > kESlotCap)
-    return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, 64, true, s);
+    return run_batched_stream(ncl, off, eps, x, v, a, m, dt, nsteps, G, precision, excl, acc_valid, 64, true, rescue,
+                              s);
   for (int c = 0; c < ncl; ++c)
     if (off[c + 1] - off[c] > (int64_t(1) << 24))
       return set_error(NBODY_EUNSUPPORTED, "batched: a system of more than 2^24 particles");

@@ -119,6 +119,24 @@ constexpr float kNearX = 2.0e-2f;
 constexpr float kNearN = 0.5f;
 constexpr float kNearEps = 2.0f;
 
+// Error estimate of FP32C rows and the threshold of their FP64 rescue (the
+// estimate and its use are described in rescue.hip): a block of terms with
+// partial sum P and closest non-repaired pair at softened distance d adds
+// ((1 + kEstNear |x_i|_inf / d) |P|)^2 to E_i, and the row is recomputed in
+// FP64 when kEstC u |G| sqrt(E_i) > kRescueTol |a_i|.  kEstC prices the
+// arithmetic of an FP32 term (a few roundings of u); kEstNear the rounding of
+// both positions to FP32, about 3 sqrt(3) u (|x_i| + |x_j|) / d relative, in
+// units of kEstC u.
+constexpr float kEstNear = 1.5f;
+constexpr double kEstC = 4.0;
+constexpr double kRescueTol = 4.0e-6;
+
+// Adds one block's share to the error estimate e (see above).
+__device__ __forceinline__ float est_add(float e, float px, float py, float pz, float xinf, float r2nr) {
+  const float w = fmaf(kEstNear * xinf, __builtin_amdgcn_rsqf(r2nr), 1.0f);
+  return fmaf(w * w, fmaf(px, px, fmaf(py, py, pz * pz)), e);
+}
+
 // Squared repair radius of lane particle i (positions given in double) in a
 // system of n particles.
 __device__ __forceinline__ float near_rc2(double xa, double ya, double za, double eps, int n) {

@@ -54,11 +54,13 @@ __device__ __forceinline__ JRec<MODE> load_rec(const double* __restrict__ x, con
 // split == 1: writes G*(hi+lo) to a[c*n+i].  split > 1: writes hi+lo to
 // part[(y*3+c)*n+i] and a second kernel sums the slices in order.
 // NEAR (FP32C only): rounded-position pairs with the near-field repair above;
-// otherwise FP32C uses float-float displacements for every pair.
+// otherwise FP32C uses float-float displacements for every pair.  With NEAR
+// and est != nullptr, the row's rounding-error estimate over this slice (one
+// share per fold block, see rescue.hip) goes to est[y*n+i].
 template <int MODE, int IPL, bool EXCL, bool NEAR>
 __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __restrict__ x,
                                                        const double* __restrict__ m, double eps, double G,
-                                                       int chunk, double* __restrict__ out) {
+                                                       int chunk, double* __restrict__ out, float* __restrict__ est) {
   using R = Real<MODE>;
   static_assert(!NEAR || MODE == kFP32C, "the near-field repair needs float-float records");
   __shared__ JRec<MODE> tile[2][kTile];
@@ -71,6 +73,7 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
   IPos<MODE> pi[IPL];
   int iidx[IPL];
   R rc2[IPL];
+  float xinf[IPL], eacc[IPL];
 #pragma unroll
   for (int k = 0; k < IPL; ++k) {
     int i = ibase + k * kBlock;
@@ -79,6 +82,8 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
     const double xa = x[ic], ya = x[n + ic], za = x[2 * n + ic];
     pi[k].set(xa, ya, za);
     rc2[k] = (R)near_rc2(xa, ya, za, eps, n);
+    xinf[k] = (float)fmax(fabs(xa), fmax(fabs(ya), fabs(za)));
+    eacc[k] = 0.f;
   }
   R hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
 #pragma unroll
@@ -132,11 +137,14 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
           // other than the own pair, replace its term from rounded positions
           // by its term from float-float displacements
           if (r2min[k] < rc2[k]) {
+            // the closest pair left in rounded positions, for the error estimate
+            R r2nr = R(3.0e38f);
             for (int jj = f; jj < f + kFold; ++jj) {
               const JRec<MODE> r = cur[jj];
               R dx, dy, dz;
               disp_hi(r, pi[k], dx, dy, dz);
               const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+              if (r2 >= rc2[k]) r2nr = fminf(r2nr, r2);
               if (r2 < rc2[k] && jt + jj != iidx[k]) {
                 const R ri = rsq(r2);
                 const R s = (jmass(r) * ri) * (ri * ri);
@@ -150,7 +158,9 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
                 pz[k] = fma(t, ez, fma(-s, dz, pz[k]));
               }
             }
+            r2min[k] = r2nr;
           }
+          if (est) eacc[k] = est_add(eacc[k], px[k], py[k], pz[k], xinf[k], r2min[k]);
         }
       }
 #pragma unroll
@@ -177,6 +187,7 @@ __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __re
       o[i] = scale * ((double)hx[k] + (double)lx[k]);
       o[n + i] = scale * ((double)hy[k] + (double)ly[k]);
       o[2 * n + i] = scale * ((double)hz[k] + (double)lz[k]);
+      if (NEAR && est) est[(size_t)blockIdx.y * n + i] = eacc[k];
     }
   }
 }
@@ -828,23 +839,33 @@ int accel_dispatch(int64_t n, const double* x, const double* m, double* a, doubl
   const int chunk = split_chunk(n, split);
   const int sp = effective_split(n, split);
   dim3 grid((unsigned)((n + kBlock * IPL - 1) / (kBlock * IPL)), (unsigned)sp);
-  double* out = a;
-  int st = NBODY_OK;
-  if (sp > 1) {
-    out = static_cast<double*>(pair_scratch(cfg, sizeof(double) * 3 * (size_t)n * sp, &st));
-    if (!out) return st;
-  }
   constexpr bool kNear = MODE == kFP32C;
+  const bool rescue = kNear && cfg.rescue;
+  // scratch: the slices' partial sums (split > 1), then for the rescue the
+  // slices' error estimates, the list of flagged rows and its count
+  const size_t part_bytes = sp > 1 ? sizeof(double) * 3 * (size_t)n * sp : 0;
+  const size_t est_bytes = rescue ? (sizeof(float) * (size_t)n * sp + 255) / 256 * 256 : 0;
+  const size_t list_bytes = rescue ? sizeof(int) * ((size_t)n + 64) : 0;
+  int st = NBODY_OK;
+  char* ws = nullptr;
+  if (part_bytes + est_bytes + list_bytes > 0) {
+    ws = static_cast<char*>(pair_scratch(cfg, part_bytes + est_bytes + list_bytes, &st));
+    if (!ws) return st;
+  }
+  double* out = sp > 1 ? reinterpret_cast<double*>(ws) : a;
+  float* est = rescue ? reinterpret_cast<float*>(ws + part_bytes) : nullptr;
+  int* list = rescue ? reinterpret_cast<int*>(ws + part_bytes + est_bytes) : nullptr;
   if (excl)
-    accel_kernel<MODE, IPL, true, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
+    accel_kernel<MODE, IPL, true, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out, est);
   else
-    accel_kernel<MODE, IPL, false, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out);
+    accel_kernel<MODE, IPL, false, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out, est);
   NB_LAUNCH_CHECK("accel_kernel");
   if (sp > 1) {
     const int64_t cnt = 3 * n;
     sum_slices_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(cnt, sp, out, G, cnt, a, cnt, nullptr, nullptr);
     NB_LAUNCH_CHECK("sum_slices_kernel");
   }
+  if (rescue) return launch_rescue(n, x, m, eps, G, excl, est, sp, (size_t)n, a, list + 64, list, s);
   return NBODY_OK;
 }
 

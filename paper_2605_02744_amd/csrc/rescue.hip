@@ -1,0 +1,216 @@
+// Rescue of ill-conditioned rows of the FP32C force.
+//
+// An FP32C row a_i is a sum of FP32 pair terms, each carrying a relative
+// rounding error of a few u (u = 2^-24): the inverse square root, its cube,
+// the weight and the products, and, for pairs outside the near-field radius,
+// the rounding of both positions to FP32, which moves the displacement by up
+// to about u (|x_i| + |x_j|).  Where the terms of a row cancel (|a_i| much
+// smaller than the sum of their magnitudes, e.g. particles near the centre of
+// a cluster) those errors are large relative to |a_i|; the largest come from
+// strong pairs just outside the near-field radius, whose terms keep the
+// rounding of both positions.  The pair kernels keep a cheap estimate of each
+// row's error: for every block of terms they sum in FP32 (64 terms of the
+// row's own j-loop, or, for the far side of the symmetric kernels, one slot of
+// up to 512 terms) they add the square of the block's partial sum |P_b|,
+// weighted by 1 + kEstNear |x_i|_inf / d_b, d_b the smallest softened distance
+// of a pair of that block that was not repaired with float-float
+// displacements:
+//   E_i = sum_b ((1 + kEstNear |x_i| / d_b) |P_b|)^2 .
+// The rounding error of a block's sum grows like the magnitude of its partial
+// sum both when one term dominates the block and when its terms have random
+// directions (both the sum and the error then grow like the square root of the
+// number of terms), the distance factor prices the position rounding of the
+// block's closest pair, and the errors of different blocks (different j,
+// different roundings) add like independent variables, hence the root of the
+// sum of squares.  A row is recomputed in FP64 when
+//   kEstC u |G| sqrt(E_i) > kRescueTol |a_i| .
+// kEstC and kRescueTol were set against measured errors: over half a million
+// rows of Plummer spheres (512 to 2^20 particles, softenings down to
+// 6.25e-4) and the two-component model, the estimate exceeded the actual
+// error of FP32C (without rescue, against FP64) by 4 to 10 at the median and
+// the row left unflagged with the largest error stayed at 2.7e-6, against 4e-5
+// for the largest error without rescue; 0.4 % (2^20) to 2 % (4096 particles
+// with softening 6.25e-4) of the rows are recomputed.  The estimate misses
+// cancellation that is systematic inside one block of consecutive indices
+// (terms of a block that cancel each other more than random directions do);
+// the far side of the symmetric kernels carries no distance factor.
+//
+// The flagged rows go to a list (an atomic counter orders them, which does not
+// change any result: every row is recomputed on its own, in a fixed order) and
+// a grid-stride kernel recomputes them in FP64, eight rows per workgroup pass
+// over the j-range so that each j record is loaded once per eight rows.
+#include "pair_math.h"
+
+namespace nb {
+namespace {
+
+constexpr int kRB = 256;   // lanes per workgroup of the rescue kernel
+constexpr int kRRows = 8;  // rows per workgroup pass
+
+__global__ void zero_count_kernel(int* count) { *count = 0; }
+
+// One thread per particle: sums the nslices slices of the estimate (stride
+// apart) and appends the row to the list if scale * sqrt(E_i) > |a_i|.
+__global__ void flag_rows_kernel(int n, const float* __restrict__ est, int nslices, size_t stride,
+                                 const double* __restrict__ a, double scale, int* __restrict__ list,
+                                 int* __restrict__ count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float e = 0.f;
+  for (int k = 0; k < nslices; ++k) e += est[(size_t)k * stride + i];
+  const double ax = a[i], ay = a[n + i], az = a[2 * n + i];
+  const double an = sqrt(ax * ax + ay * ay + az * az);
+  if (sqrt((double)e) * scale > an) list[atomicAdd(count, 1)] = i;
+}
+
+// Recomputes the listed rows of a = G sum_j m_j d / (|d|^2 + eps^2)^(3/2) in
+// FP64: each pass takes kRRows rows of the list, the lanes split the j-range
+// (lane t takes j = t, t + 256, ...), and the lane sums are added in a fixed
+// order: a butterfly inside each wave, then the four wave sums in wave order.
+__global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* __restrict__ x,
+                                                          const double* __restrict__ m, double eps, double G,
+                                                          int excl, const int* __restrict__ list,
+                                                          const int* __restrict__ count, double* __restrict__ a) {
+  __shared__ double red[3][kRRows][kRB / 64];
+  const int t = threadIdx.x;
+  const int wave = t / 64, lane = t % 64;
+  const int cnt = *count;
+  const double e2 = eps * eps;
+  for (int r0 = blockIdx.x * kRRows; r0 < cnt; r0 += gridDim.x * kRRows) {
+    int row[kRRows];
+    double xi[kRRows], yi[kRRows], zi[kRRows], sx[kRRows], sy[kRRows], sz[kRRows];
+#pragma unroll
+    for (int k = 0; k < kRRows; ++k) {
+      row[k] = r0 + k < cnt ? list[r0 + k] : -1;
+      const int i = row[k] < 0 ? 0 : row[k];
+      xi[k] = x[i];
+      yi[k] = x[n + i];
+      zi[k] = x[2 * n + i];
+      sx[k] = sy[k] = sz[k] = 0.0;
+    }
+    for (int j = t; j < n; j += kRB) {
+      const double xj = x[j], yj = x[n + j], zj = x[2 * n + j], mj = m[j];
+#pragma unroll
+      for (int k = 0; k < kRRows; ++k) {
+        const double dx = xj - xi[k], dy = yj - yi[k], dz = zj - zi[k];
+        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+        const double ri = rsqrt64(r2);
+        double s = (mj * ri) * (ri * ri);
+        if (excl && j == row[k]) s = 0.0;
+        sx[k] = fma(s, dx, sx[k]);
+        sy[k] = fma(s, dy, sy[k]);
+        sz[k] = fma(s, dz, sz[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRRows; ++k) {
+      for (int off = 32; off > 0; off >>= 1) {
+        sx[k] += __shfl_xor(sx[k], off, 64);
+        sy[k] += __shfl_xor(sy[k], off, 64);
+        sz[k] += __shfl_xor(sz[k], off, 64);
+      }
+      if (lane == 0) {
+        red[0][k][wave] = sx[k];
+        red[1][k][wave] = sy[k];
+        red[2][k][wave] = sz[k];
+      }
+    }
+    __syncthreads();
+    if (t < kRRows && row[t] >= 0) {
+      const int i = row[t];
+      double v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v[c] = red[c][t][0];
+#pragma unroll
+        for (int w = 1; w < kRB / 64; ++w) v[c] += red[c][t][w];
+      }
+      a[i] = G * v[0];
+      a[n + i] = G * v[1];
+      a[2 * n + i] = G * v[2];
+    }
+    __syncthreads();
+  }
+}
+
+// The batched form: one wave per listed row of a concatenated ensemble, the
+// row's system found by bisection of the offsets, its lanes splitting the
+// system's j-range; the lane sums added by a butterfly (fixed order).
+__global__ __launch_bounds__(kRB) void rescue_sys_rows_kernel(int64_t total, int ncl, const int64_t* __restrict__ off,
+                                                              const double* __restrict__ epsv,
+                                                              const double* __restrict__ x,
+                                                              const double* __restrict__ m, double G, int excl,
+                                                              const int* __restrict__ list,
+                                                              const int* __restrict__ count, double* __restrict__ a) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int cnt = *count;
+  for (int r = blockIdx.x * (kRB / 64) + wave; r < cnt; r += gridDim.x * (kRB / 64)) {
+    const int64_t i = list[r];
+    int lo = 0, hi = ncl;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (off[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const int64_t o = off[lo], e = off[lo + 1];
+    const double e2 = epsv[lo] * epsv[lo];
+    const double xi = x[i], yi = x[total + i], zi = x[2 * total + i];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t j = o + lane; j < e; j += 64) {
+      const double dx = x[j] - xi, dy = x[total + j] - yi, dz = x[2 * total + j] - zi;
+      const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+      const double ri = rsqrt64(r2);
+      double sc = (m[j] * ri) * (ri * ri);
+      if (excl && j == i) sc = 0.0;
+      sx = fma(sc, dx, sx);
+      sy = fma(sc, dy, sy);
+      sz = fma(sc, dz, sz);
+    }
+    for (int w = 32; w > 0; w >>= 1) {
+      sx += __shfl_xor(sx, w, 64);
+      sy += __shfl_xor(sy, w, 64);
+      sz += __shfl_xor(sz, w, 64);
+    }
+    if (lane == 0) {
+      a[i] = G * sx;
+      a[total + i] = G * sy;
+      a[2 * total + i] = G * sz;
+    }
+  }
+}
+
+}  // namespace
+
+int launch_rescue_batched(int64_t total, int ncl, const int64_t* off, const double* epsv, const double* x,
+                          const double* m, double G, bool excl, const float* est, double* a, int* list, int* count,
+                          hipStream_t s) {
+  if (total == 0) return NBODY_OK;
+  zero_count_kernel<<<1, 1, 0, s>>>(count);
+  NB_LAUNCH_CHECK("zero_count_kernel");
+  const double scale = kEstC * 5.9604644775390625e-8 * std::fabs(G) / kRescueTol;
+  flag_rows_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>((int)total, est, 1, (size_t)total, a, scale, list,
+                                                                 count);
+  NB_LAUNCH_CHECK("flag_rows_kernel");
+  const unsigned grid =
+      (unsigned)std::min<int64_t>((total + kRB / 64 - 1) / (kRB / 64), 4 * (int64_t)cu_count(current_device()));
+  rescue_sys_rows_kernel<<<grid, kRB, 0, s>>>(total, ncl, off, epsv, x, m, G, excl ? 1 : 0, list, count, a);
+  NB_LAUNCH_CHECK("rescue_sys_rows_kernel");
+  return NBODY_OK;
+}
+
+int launch_rescue(int64_t n, const double* x, const double* m, double eps, double G, bool excl, const float* est,
+                  int nslices, size_t stride, double* a, int* list, int* count, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  zero_count_kernel<<<1, 1, 0, s>>>(count);
+  NB_LAUNCH_CHECK("zero_count_kernel");
+  const double scale = kEstC * 5.9604644775390625e-8 * std::fabs(G) / kRescueTol;
+  flag_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((int)n, est, nslices, stride, a, scale, list, count);
+  NB_LAUNCH_CHECK("flag_rows_kernel");
+  const int64_t passes = (n + kRRows - 1) / kRRows;
+  const unsigned grid = (unsigned)std::min<int64_t>(passes, 4 * (int64_t)cu_count(current_device()));
+  rescue_rows_kernel<<<grid, kRB, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list, count, a);
+  NB_LAUNCH_CHECK("rescue_rows_kernel");
+  return NBODY_OK;
+}
+
+}  // namespace nb

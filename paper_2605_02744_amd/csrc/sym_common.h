@@ -53,6 +53,8 @@ struct SymArgs {
   const float4* rw; // [npad] staged cotangents (VJP only)
   float* pj;        // [D][C][npad] j-side tile sums of the chunk's distances (C = 3, or 4 for the VJP)
   double* pi;       // [nparts][C][npad] i-side sums of the chunk's workgroups
+  float* pe;        // [nparts][npad] i-side error estimates of the chunk's workgroups (FP32C force), or null
+  float* pw;        // [D][npad] j-side error estimates of the chunk's distances (FP32C force), or null
 };
 
 // Largest valid distance + 1 for I-block g.
@@ -77,17 +79,26 @@ using lds_ptr = __attribute__((address_space(3))) void*;
 // the distance-0 sums pd, the last applies G.  One thread per (particle,
 // component), fixed order.  Only the largest distance can be missing for some
 // blocks (the opposite block of an even ring, visited from the lower half only).
+// With eo (FP32C force only; the thread of component 0 does it): the error
+// estimate of the rescue in eo[npad], the far side's shares pw of the chunk's
+// distances and the workgroups' i-side shares pe added to what earlier chunks
+// left, or to the block-diagonal share ed in the first chunk.
 template <int C, typename S>
 __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
                                   const S* __restrict__ pj, const double* __restrict__ pi,
                                   const double* __restrict__ pd, double* __restrict__ out, double* __restrict__ outm,
-                                  double G, int first, int last) {
+                                  double G, int first, int last, const float* __restrict__ pe = nullptr,
+                                  const float* __restrict__ pw = nullptr, const float* __restrict__ ed = nullptr,
+                                  float* __restrict__ eo = nullptr) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (p >= n) return;
   double* o = c < 3 ? out + (size_t)c * n + p : outm + p;
   const int J = p / kSI;
   double acc = first ? pd[(size_t)c * npad + p] : *o;
+  const bool est = eo && c == 0;
+  float ea = 0.f;
+  if (est) ea = first ? ed[p] : eo[p];
   const int send = min(D, dmax - d_lo + 1);  // slots of this chunk within the ring
   // the last slot of the ring is dropped where its block pair was not evaluated
   const bool drop_last = half && d_lo + send - 1 == dmax && ((J - dmax) % nb + nb) % nb >= nb / 2;
@@ -104,6 +115,11 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
   }
   for (; s < sn; ++s) acc += (double)q[s * stride];
   for (int k = 0; k < nparts; ++k) acc += pi[((size_t)k * C + c) * npad + p];
+  if (est) {
+    for (int d = 0; d < sn; ++d) ea += pw[(size_t)d * npad + p];
+    for (int k = 0; k < nparts; ++k) ea += pe[(size_t)k * npad + p];
+    eo[p] = ea;
+  }
   *o = last ? G * acc : acc;
 }
 

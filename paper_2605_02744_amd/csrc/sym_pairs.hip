@@ -39,17 +39,22 @@ struct ISet {
   float x[2], y[2], z[2], mneg[2];
 };
 
-// One step of a sub-block: both i of the lane against record (r + K).
-template <int K, bool NEAR>
+// One step of a sub-block: both i of the lane against record (r + K).  EST
+// (FP32C with the rescue): the j's smallest squared distance to the lane's
+// two i also travels to its owner lane (a DPP row rotation fused into a min),
+// for the far side's share of the error estimate.
+template <int K, bool NEAR, bool EST>
 __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
                                          float (&py)[2], float (&pz)[2], float (&r2min)[2], float& ajx,
-                                         float& ajy, float& ajz) {
+                                         float& ajy, float& ajz, float& ajm) {
   const float4 r = rowp[K];
   float tx = 0.f, ty = 0.f, tz = 0.f;
+  float r2u[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const float dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+    r2u[u] = r2;
     const float ri = rsqrt32(r2);
     const float ri3 = (ri * ri) * ri;
     const float si = r.w * ri3;
@@ -63,19 +68,22 @@ __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict
   }
   // the j met here sits at row position (r + K): its owner, the lane that met it
   // at step 0, is K lanes further on
-  if constexpr (K == 0) { ajx += tx; ajy += ty; ajz += tz; }
-  else {
+  if constexpr (K == 0) {
+    ajx += tx; ajy += ty; ajz += tz;
+    if constexpr (EST) ajm = fminf(ajm, fminf(r2u[0], r2u[1]));
+  } else {
     ajx += row_ror<K>(tx);
     ajy += row_ror<K>(ty);
     ajz += row_ror<K>(tz);
+    if constexpr (EST) ajm = fminf(ajm, row_ror<K>(fminf(r2u[0], r2u[1])));
   }
 }
 
-template <bool NEAR, int... K>
+template <bool NEAR, bool EST, int... K>
 __device__ __forceinline__ void sym_sub(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
                                         float (&py)[2], float (&pz)[2], float (&r2min)[2], float& ajx,
-                                        float& ajy, float& ajz, std::integer_sequence<int, K...>) {
-  (sym_step<K, NEAR>(s, rowp, e2, px, py, pz, r2min, ajx, ajy, ajz), ...);
+                                        float& ajy, float& ajz, float& ajm, std::integer_sequence<int, K...>) {
+  (sym_step<K, NEAR, EST>(s, rowp, e2, px, py, pz, r2min, ajx, ajy, ajz, ajm), ...);
 }
 
 // Loads the two i of lane t of I-block g (padding i: far away and massless, so
@@ -150,11 +158,15 @@ struct P6 {
 // (part: the wave's slots, components kSW * kST apart).  The j are visited in
 // the rotated order of the pair loop, so at each step the lanes of a row touch
 // distinct j; the four rows of the wave, which share the slots, take turns.
+// r2nr receives, per i, the smallest squared distance of the tile's pairs that
+// keep their rounded-position terms (for the error estimate of the rescue).
 __device__ __forceinline__ P6 sym_repair(const double* __restrict__ x, int n, double eps, float fx, int g, int t, int rl,
-                                         float e2, ISet s, P6 p, const float4* hi, const float4* lo, float* part) {
+                                         float e2, ISet s, P6 p, const float4* hi, const float4* lo, float* part,
+                                         float (&r2nr)[2]) {
   const int wrow = (t & 63) / kSR;
   float px[2] = {p.x0, p.x1}, py[2] = {p.y0, p.y1}, pz[2] = {p.z0, p.z1};
   float rc[2];
+  r2nr[0] = r2nr[1] = 3.0e38f;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int i = g * kSI + u * kSL + t;
@@ -170,6 +182,7 @@ __device__ __forceinline__ P6 sym_repair(const double* __restrict__ x, int n, do
     for (int u = 0; u < 2; ++u) {
       const float dx = rh.x - s.x[u], dy = rh.y - s.y[u], dz = rh.z - s.z[u];
       const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+      if (!(r2 < fmaxf(rc[u], rl4.w))) r2nr[u] = fminf(r2nr[u], r2);
       if (rc[u] >= 0.f && r2 < fmaxf(rc[u], rl4.w)) {
         const int i = g * kSI + u * kSL + t;
         const double xa = x[i], ya = x[n + i], za = x[2 * n + i];
@@ -200,12 +213,14 @@ __device__ __forceinline__ P6 sym_repair(const double* __restrict__ x, int n, do
 
 // Grid: nb * nparts workgroups; workgroup (g, part) takes the distances
 // [d_lo + part L, d_lo + (part + 1) L) of I-block g's half ring (d >= 1).
-template <bool NEAR>
+template <bool NEAR, bool EST>
 __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   __shared__ float4 s_hi[2][4][2 * kSR];  // (x, y, z, m) hi parts, each sub-block twice
   __shared__ float4 s_lo[2][kST];         // (x, y, z) lo parts and the repair radius^2 of j
   __shared__ float s_part[3][kSW][kST];
   __shared__ float s_acc_lo[6][kSL];      // the lo halves of the i-side (hi, lo) sums
+  __shared__ float s_est[2][kSL];         // the i-side error estimates (EST)
+  __shared__ float s_pmin[kSW][kST];      // the j's smallest squared distance per wave (EST)
 
   const int t = threadIdx.x;
   const int rl = t & (kSR - 1);
@@ -224,6 +239,7 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < 6; ++c) s_acc_lo[c][t] = 0.f;
+  s_est[0][t] = s_est[1][t] = 0.f;
   // lane address for the exchange across the two halves of a wave
   const int xor32 = ((t & 63) ^ 32) * 4;
 
@@ -269,8 +285,9 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
     float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
-      float ajx = 0.f, ajy = 0.f, ajz = 0.f;
-      sym_sub<NEAR>(s, &s_hi[b][q][rl], e2, px, py, pz, r2min, ajx, ajy, ajz, std::make_integer_sequence<int, kSR>{});
+      float ajx = 0.f, ajy = 0.f, ajz = 0.f, ajm = 3.0e38f;
+      sym_sub<NEAR, EST>(s, &s_hi[b][q][rl], e2, px, py, pz, r2min, ajx, ajy, ajz, ajm,
+                         std::make_integer_sequence<int, kSR>{});
       // the four rows' sums of the same 16 j: rows (0 + 1) and (2 + 3) by a
       // swizzle, then the two halves by a permute, after which all four rows
       // hold the same totals and store the same values (no branch in the loop)
@@ -283,14 +300,28 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
       s_part[0][wave][q * kSR + rl] = ajx;
       s_part[1][wave][q * kSR + rl] = ajy;
       s_part[2][wave][q * kSR + rl] = ajz;
+      if constexpr (EST) {
+        ajm = fminf(ajm, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajm), 0x401F)));
+        ajm = fminf(ajm, __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajm))));
+        s_pmin[wave][q * kSR + rl] = ajm;
+      }
     }
     if constexpr (NEAR) {
       // rare: a pair of this tile may be closer than the larger repair radius
       // of its two particles
       if (r2min[0] < thr[0] || r2min[1] < thr[1]) {
         const P6 r = sym_repair(A.x, n, A.eps, A.fx, g, t, rl, e2, s, P6{px[0], px[1], py[0], py[1], pz[0], pz[1]},
-                                &s_hi[b][0][0], &s_lo[b][0], &s_part[0][wave][0]);
+                                &s_hi[b][0][0], &s_lo[b][0], &s_part[0][wave][0], r2min);
         px[0] = r.x0; px[1] = r.x1; py[0] = r.y0; py[1] = r.y1; pz[0] = r.z0; pz[1] = r.z1;
+      }
+      // the error estimate of the rescue: this tile's partial sums, weighted by
+      // the distance of their closest pair left in rounded positions
+      if constexpr (EST) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const float xinf = fmaxf(fabsf(s.x[u]), fmaxf(fabsf(s.y[u]), fabsf(s.z[u])));
+          s_est[u][t] = est_add(s_est[u][t], px[u], py[u], pz[u], xinf, r2min[u]);
+        }
       }
     }
 #pragma unroll
@@ -300,15 +331,34 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
       fold(hz[u], s_acc_lo[3 * u + 2][t], pz[u]);
     }
     __syncthreads();
-    if (t < 3 * 64) {
+    if (t < kST) {
       // the tile's j-side sums: the 4 wave sums of each j, in wave order
-      const int c = t / kST, jl = t % kST;
-      float v = 0.f;
+      const int jl = t;
+      float v[3];
 #pragma unroll
-      for (int w = 0; w < kSW; ++w) v += s_part[c][w][jl];
+      for (int c = 0; c < 3; ++c) {
+        v[c] = 0.f;
+#pragma unroll
+        for (int w = 0; w < kSW; ++w) v[c] += s_part[c][w][jl];
+      }
       const int J = (g + d) % A.nb;
-      A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + (size_t)J * kSI + tt * kST + jl] = v;
-    } else {
+      const size_t col = (size_t)J * kSI + tt * kST + jl;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + col] = v[c];
+      if constexpr (EST) {
+        // the far side's share of j's error estimate: this tile's sum over the
+        // workgroup's i, weighted by the distance of the closest pair left in
+        // rounded positions; a pair closer than j's own repair radius was
+        // repaired, so that radius bounds the distance from below
+        float dm = s_pmin[0][jl];
+#pragma unroll
+        for (int w = 1; w < kSW; ++w) dm = fminf(dm, s_pmin[w][jl]);
+        const float4 rj = s_hi[b][jl / kSR][jl % kSR];
+        const float xinf = fmaxf(fabsf(rj.x), fmaxf(fabsf(rj.y), fabsf(rj.z)));
+        const float wj = fmaf(kEstNear * xinf, rsqrt32(fmaxf(dm, s_lo[b][jl].w)), 1.0f);
+        A.pw[(size_t)(d - A.d_lo) * A.npad + col] = wj * wj * fmaf(v[0], v[0], fmaf(v[1], v[1], v[2] * v[2]));
+      }
+    } else if (t >= 3 * 64) {
       __builtin_amdgcn_s_waitcnt(0);  // the next tile's copies have landed in LDS
     }
     __syncthreads();
@@ -322,6 +372,7 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
     o[i] = (double)hx[u] + (double)s_acc_lo[3 * u][t];
     o[A.npad + i] = (double)hy[u] + (double)s_acc_lo[3 * u + 1][t];
     o[2 * (size_t)A.npad + i] = (double)hz[u] + (double)s_acc_lo[3 * u + 2][t];
+    if (EST) A.pe[(size_t)part * A.npad + i] = s_est[u][t];
   }
 }
 
@@ -330,7 +381,7 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
 // the own pair masked when asked and the near-field repair of the force kernel.
 // Writes hi + lo into pd[3][npad].
 template <bool NEAR, bool EXCL>
-__global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __restrict__ pd) {
+__global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __restrict__ pd, float* __restrict__ ed) {
   __shared__ float4 s_hi[kSI];
   __shared__ float4 s_lo[kSI];
   const int t = threadIdx.x;
@@ -347,7 +398,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
   __syncthreads();
   float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
   float lx[2] = {0.f, 0.f}, ly[2] = {0.f, 0.f}, lz[2] = {0.f, 0.f};
-  float rc[2];
+  float rc[2], ea[2] = {0.f, 0.f};
 #pragma unroll
   for (int u = 0; u < 2; ++u) rc[u] = s_lo[u * kSL + t].w;
 #pragma unroll 1
@@ -372,6 +423,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
     }
     if constexpr (NEAR) {
       if (r2min[0] < thr[0] || r2min[1] < thr[1]) {
+        float r2nr[2] = {3.0e38f, 3.0e38f};
         for (int j = f; j < f + kFold; ++j) {
           const float4 rh = s_hi[j];
           const float4 lo = s_lo[j];
@@ -379,6 +431,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
           for (int u = 0; u < 2; ++u) {
             const float dx = rh.x - s.x[u], dy = rh.y - s.y[u], dz = rh.z - s.z[u];
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            if (!(r2 < rc[u]) && j != u * kSL + t) r2nr[u] = fminf(r2nr[u], r2);
             if (rc[u] >= 0.f && r2 < rc[u] && j != u * kSL + t) {
               const float4 li = s_lo[u * kSL + t];
               float fx, fy, fz;
@@ -388,6 +441,15 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
               pz[u] = fmaf(rh.w, fz, pz[u]);
             }
           }
+        }
+        r2min[0] = r2nr[0];
+        r2min[1] = r2nr[1];
+      }
+      if (ed) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const float xinf = fmaxf(fabsf(s.x[u]), fmaxf(fabsf(s.y[u]), fabsf(s.z[u])));
+          ea[u] = est_add(ea[u], px[u], py[u], pz[u], xinf, r2min[u]);
         }
       }
     }
@@ -404,6 +466,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
     pd[i] = (double)hx[u] + (double)lx[u];
     pd[A.npad + i] = (double)hy[u] + (double)ly[u];
     pd[2 * (size_t)A.npad + i] = (double)hz[u] + (double)lz[u];
+    if (NEAR && ed) ed[i] = ea[u];
   }
 }
 
@@ -415,11 +478,18 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   if (precision != kFP32C && precision != kFP32)
     return set_error(NBODY_EUNSUPPORTED, "symmetric pair kernel: FP32C and FP32 only");
   if (n > (int64_t(1) << 30)) return set_error(NBODY_EINVAL, "symmetric pair kernel: n too large");
+  const bool near = precision == kFP32C;
+  const bool rescue = near && cfg.rescue;
   int nb, L, D;
-  // per particle: FP32 j-side slot sums per distance, FP64 i-side sums per workgroup,
-  // FP64 block-diagonal sums and two staged float4 records
-  sym_plan(n, cfg.split, 3 * sizeof(float), 3 * sizeof(double), 3 * sizeof(double) + 2 * sizeof(float4),
-           cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
+  // per particle: FP32 j-side slot sums per distance, FP64 i-side sums (and, for the
+  // rescue, an FP32 error estimate) per workgroup, FP64 block-diagonal sums, two staged
+  // float4 records and, for the rescue, four FP32 estimates and a list entry
+  const int est_fixed = rescue ? 2 * (int)sizeof(float) + (int)sizeof(int) : 0;
+  const int est_part = rescue ? (int)sizeof(float) : 0;
+  const int est_slot = rescue ? (int)sizeof(float) : 0;
+  sym_plan(n, cfg.split, 3 * sizeof(float) + est_slot, 3 * sizeof(double) + est_part,
+           3 * sizeof(double) + 2 * sizeof(float4) + est_fixed, cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L,
+           &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -429,7 +499,12 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
   const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
   const size_t rec_bytes = sizeof(float4) * (size_t)npad;
-  char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes, &st));
+  const size_t pe_bytes = rescue ? sizeof(float) * (size_t)npad * nparts : 0;
+  const size_t pw_bytes = rescue ? sizeof(float) * (size_t)npad * D : 0;
+  const size_t eo_bytes = rescue ? sizeof(float) * 2 * (size_t)npad : 0;  // eo [npad], ed [npad]
+  const size_t list_bytes = rescue ? sizeof(int) * (size_t)npad : 0;     // the count, then the list
+  char* ws = static_cast<char*>(pair_scratch(
+      cfg, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes + pe_bytes + pw_bytes + eo_bytes + list_bytes, &st));
   if (!ws) return st;
   SymArgs A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
@@ -440,39 +515,46 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);
   float4* rhi = reinterpret_cast<float4*>(ws + pj_bytes + pi_bytes + pd_bytes);
   float4* rlo = rhi + npad;
+  char* tail = ws + pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes;
   A.rhi = rhi;
   A.rlo = rlo;
-  const bool near = precision == kFP32C;
+  A.pe = rescue ? reinterpret_cast<float*>(tail) : nullptr;
+  A.pw = rescue ? reinterpret_cast<float*>(tail + pe_bytes) : nullptr;
+  float* eo = rescue ? reinterpret_cast<float*>(tail + pe_bytes + pw_bytes) : nullptr;
+  float* ed = rescue ? eo + npad : nullptr;
+  int* list = rescue ? reinterpret_cast<int*>(tail + pe_bytes + pw_bytes + eo_bytes) : nullptr;
   const unsigned sg = (unsigned)((npad + 255) / 256);
   if (near) sym_stage_kernel<true><<<sg, 256, 0, s>>>(A, rhi, rlo);
   else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo);
   NB_LAUNCH_CHECK("sym_stage_kernel");
   if (near) {
-    if (excl) sym_diag_kernel<true, true><<<nb, kSL, 0, s>>>(A, pd);
-    else sym_diag_kernel<true, false><<<nb, kSL, 0, s>>>(A, pd);
+    if (excl) sym_diag_kernel<true, true><<<nb, kSL, 0, s>>>(A, pd, ed);
+    else sym_diag_kernel<true, false><<<nb, kSL, 0, s>>>(A, pd, ed);
   } else {
-    if (excl) sym_diag_kernel<false, true><<<nb, kSL, 0, s>>>(A, pd);
-    else sym_diag_kernel<false, false><<<nb, kSL, 0, s>>>(A, pd);
+    if (excl) sym_diag_kernel<false, true><<<nb, kSL, 0, s>>>(A, pd, ed);
+    else sym_diag_kernel<false, false><<<nb, kSL, 0, s>>>(A, pd, ed);
   }
   NB_LAUNCH_CHECK("sym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {
     sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, nullptr, G,
-                                            1, 1);
+                                            1, 1, A.pe, A.pw, ed, eo);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
-    return NBODY_OK;
+  } else {
+    const int nchunks = (dmax + D - 1) / D;
+    for (int c = 0; c < nchunks; ++c) {
+      A.d_lo = 1 + c * D;
+      const unsigned grid = (unsigned)nb * (unsigned)nparts;
+      if (rescue) sym_accel_kernel<true, true><<<grid, kSL, 0, s>>>(A);
+      else if (near) sym_accel_kernel<true, false><<<grid, kSL, 0, s>>>(A);
+      else sym_accel_kernel<false, false><<<grid, kSL, 0, s>>>(A);
+      NB_LAUNCH_CHECK("sym_accel_kernel");
+      sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
+                                              a, nullptr, G, c == 0, c == nchunks - 1, A.pe, A.pw, ed, eo);
+      NB_LAUNCH_CHECK("sym_reduce_kernel");
+    }
   }
-  const int nchunks = (dmax + D - 1) / D;
-  for (int c = 0; c < nchunks; ++c) {
-    A.d_lo = 1 + c * D;
-    const unsigned grid = (unsigned)nb * (unsigned)nparts;
-    if (near) sym_accel_kernel<true><<<grid, kSL, 0, s>>>(A);
-    else sym_accel_kernel<false><<<grid, kSL, 0, s>>>(A);
-    NB_LAUNCH_CHECK("sym_accel_kernel");
-    sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd, a,
-                                            nullptr, G, c == 0, c == nchunks - 1);
-    NB_LAUNCH_CHECK("sym_reduce_kernel");
-  }
+  if (rescue) return launch_rescue(n, x, m, eps, G, excl, eo, 1, (size_t)npad, a, list + 64, list, s);
   return NBODY_OK;
 }
 

@@ -426,6 +426,8 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + 3 * rec_bytes, &st));
   if (!ws) return st;
   SymArgs A;
+  A.pe = nullptr;
+  A.pw = nullptr;
   A.x = x; A.m = m; A.w = w; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
   A.L = L; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
   A.fx = std::max(kNearX, kNearN / std::cbrt((float)n));

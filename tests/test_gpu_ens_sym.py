@@ -39,11 +39,11 @@ def rel_err(a, ref):
     return (num / np.where(den > 0, den, 1.0)).max()
 
 
-def run(nb, off, epsv, x, v, m, steps, mode=4, **kw):
+def run(nb, off, epsv, x, v, m, steps, mode=4, rescue=0, **kw):
     """nbody_step_batched with the batched mode forced; returns (x, v, a) on the host."""
     tx, tv, tm = dev(x), dev(v), dev(m)
     ta = torch.empty_like(tx)
-    nb.nbody_set_config(bsplit=mode)
+    nb.nbody_set_config(bsplit=mode, rescue=rescue)
     try:
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, steps, **kw)
     finally:
@@ -215,14 +215,20 @@ def test_ens_sym_fp64_runs_ordered_items(nb):
 
 
 def test_ens_sym_untuned_default(nb):
-    """Without a forced or tuned choice, FP32C runs mode 4 on a layout whose
-    systems span several blocks of 64 and mode 3 on one of single-block
-    systems (bitwise the forced modes' states)."""
-    for sizes, mode in (([4096, 3000, 700, 129], 4), ([64, 40, 64, 17], 3)):
+    """Without a forced or tuned choice, FP32C runs the per-step wave items
+    (mode 3), the batched form that carries the FP64 rescue of ill-conditioned
+    rows; with the rescue off it runs mode 4 on a layout whose systems span
+    several blocks of 64 and mode 3 on one of single-block systems (bitwise
+    the forced modes' states)."""
+    for rescue, sizes, mode in ((0, [4096, 3000, 700, 129], 3), (2, [4096, 3000, 700, 129], 4),
+                                (2, [64, 40, 64, 17], 3)):
         off, epsv, x, v, m = ics.ensemble(len(sizes), seed=47, sizes=sizes)
         tx, tv, tm = dev(x), dev(v), dev(m)
         ta = torch.empty_like(tx)
-        nb.nbody_set_config()
-        nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 3, precision="fp32c")
-        fx, fv, _ = run(nb, off, epsv, x, v, m, 3, mode=mode, precision="fp32c")
-        assert np.array_equal(tx.cpu().numpy(), fx) and np.array_equal(tv.cpu().numpy(), fv), sizes
+        nb.nbody_set_config(rescue=rescue)
+        try:
+            nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 3, precision="fp32c")
+        finally:
+            nb.nbody_set_config()
+        fx, fv, _ = run(nb, off, epsv, x, v, m, 3, mode=mode, rescue=rescue, precision="fp32c")
+        assert np.array_equal(tx.cpu().numpy(), fx) and np.array_equal(tv.cpu().numpy(), fv), (rescue, sizes)
