@@ -140,10 +140,10 @@ struct BatchConfig {
   int rescue = 1;  // FP32C, mode 3: rows flagged by the error estimate recomputed in FP64
 };
 
-// FP64 rescue of flagged FP32C rows of an ensemble (the layout's offsets and
-// softenings on the device): as launch_rescue, each row against its own
-// system.
-int launch_rescue_batched(int64_t total, int ncl, const int64_t* off, const double* epsv, const double* x,
+// FP64 rescue of flagged FP32C rows of an ensemble (the layout's offsets,
+// softenings and per-particle system index on the device): as launch_rescue,
+// each row against its own system.
+int launch_rescue_batched(int64_t total, const int* sysid, const int64_t* off, const double* epsv, const double* x,
                           const double* m, double G, bool excl, const float* est, double* a, int* list, int* count,
                           hipStream_t s);
 

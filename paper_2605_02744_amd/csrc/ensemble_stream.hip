@@ -686,8 +686,9 @@ struct SPlan {
   int2* d_ws_sys = nullptr;  // wave items: (system, items of it held by the workgroup)
   void* d_xrec = nullptr;
   int* d_cnt = nullptr;
-  float* d_est = nullptr;  // per-step wave items, FP32C: the rescue's error estimates (total)
-  int* d_list = nullptr;   // and its count and list of flagged rows (64 + total)
+  float* d_est = nullptr;  // per-step wave items, FP32C: the rescue's error estimates (total),
+  int* d_list = nullptr;   // its count and list of flagged rows (64 + total)
+  int* d_sysid = nullptr;  // and each particle's system (total)
 };
 
 std::mutex g_splan_mu;
@@ -696,7 +697,7 @@ std::vector<SPlan*> g_splans;
 void free_splan(SPlan* p) {
   for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_nparts, (void*)p->d_items, (void*)p->d_wg_off,
                   (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt,
-                  (void*)p->d_est, (void*)p->d_list})
+                  (void*)p->d_est, (void*)p->d_list, (void*)p->d_sysid})
     if (q) (void)hipFree(q);
   delete p;
 }
@@ -904,9 +905,14 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
             supload(&p->d_ws_off, ws_off) && supload(&p->d_ws_sys, ws_sys) &&
             hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
             hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
-  if (ok && MODE == kFP32C)
+  if (ok && MODE == kFP32C) {
+    std::vector<int> sysid((size_t)p->total);
+    for (int c = 0; c < ncl; ++c)
+      for (int64_t i = off[c]; i < off[c + 1]; ++i) sysid[(size_t)i] = c;
     ok = hipMalloc(&p->d_est, sizeof(float) * (size_t)std::max<int64_t>(1, p->total)) == hipSuccess &&
-         hipMalloc(&p->d_list, sizeof(int) * (size_t)(64 + std::max<int64_t>(1, p->total))) == hipSuccess;
+         hipMalloc(&p->d_list, sizeof(int) * (size_t)(64 + std::max<int64_t>(1, p->total))) == hipSuccess &&
+         supload(&p->d_sysid, sysid);
+  }
   if (!ok) {
     (void)hipGetLastError();
     free_splan(p);
@@ -976,7 +982,7 @@ int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double*
     NB_LAUNCH_CHECK("ens_waveforce_kernel");
     // the rows whose error estimate is too large, recomputed in FP64 from the new positions
     if (rescue)
-      return launch_rescue_batched(p->total, p->ncl, p->d_off, p->d_eps, x, m, G, excl, est, a, p->d_list + 64,
+      return launch_rescue_batched(p->total, p->d_sysid, p->d_off, p->d_eps, x, m, G, excl, est, a, p->d_list + 64,
                                    p->d_list, s);
     return NBODY_OK;
   };

@@ -50,17 +50,27 @@ constexpr int kRRows = 8;  // rows per workgroup pass
 __global__ void zero_count_kernel(int* count) { *count = 0; }
 
 // One thread per particle: sums the nslices slices of the estimate (stride
-// apart) and appends the row to the list if scale * sqrt(E_i) > |a_i|.
+// apart) and appends the row to the list if scale * sqrt(E_i) > |a_i|.  A
+// wave reserves the places of all its flagged rows with one atomic add.
 __global__ void flag_rows_kernel(int n, const float* __restrict__ est, int nslices, size_t stride,
                                  const double* __restrict__ a, double scale, int* __restrict__ list,
                                  int* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float e = 0.f;
-  for (int k = 0; k < nslices; ++k) e += est[(size_t)k * stride + i];
-  const double ax = a[i], ay = a[n + i], az = a[2 * n + i];
-  const double an = sqrt(ax * ax + ay * ay + az * az);
-  if (sqrt((double)e) * scale > an) list[atomicAdd(count, 1)] = i;
+  bool flag = false;
+  if (i < n) {
+    float e = 0.f;
+    for (int k = 0; k < nslices; ++k) e += est[(size_t)k * stride + i];
+    const double ax = a[i], ay = a[n + i], az = a[2 * n + i];
+    const double an = sqrt(ax * ax + ay * ay + az * az);
+    flag = sqrt((double)e) * scale > an;
+  }
+  const unsigned long long mask = __ballot(flag);
+  if (mask == 0) return;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == __ffsll((long long)mask) - 1) base = atomicAdd(count, __popcll(mask));
+  base = __shfl(base, __ffsll((long long)mask) - 1, 64);
+  if (flag) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = i;
 }
 
 // Recomputes the listed rows of a = G sum_j m_j d / (|d|^2 + eps^2)^(3/2) in
@@ -133,10 +143,11 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
   }
 }
 
-// The batched form: one wave per listed row of a concatenated ensemble, the
-// row's system found by bisection of the offsets, its lanes splitting the
-// system's j-range; the lane sums added by a butterfly (fixed order).
-__global__ __launch_bounds__(kRB) void rescue_sys_rows_kernel(int64_t total, int ncl, const int64_t* __restrict__ off,
+// The batched form: one wave per listed row of a concatenated ensemble (the
+// row's system from the per-particle system index sysid), its lanes splitting
+// the system's j-range; the lane sums added by a butterfly (fixed order).
+__global__ __launch_bounds__(kRB) void rescue_sys_rows_kernel(int64_t total, const int* __restrict__ sysid,
+                                                              const int64_t* __restrict__ off,
                                                               const double* __restrict__ epsv,
                                                               const double* __restrict__ x,
                                                               const double* __restrict__ m, double G, int excl,
@@ -146,16 +157,12 @@ __global__ __launch_bounds__(kRB) void rescue_sys_rows_kernel(int64_t total, int
   const int cnt = *count;
   for (int r = blockIdx.x * (kRB / 64) + wave; r < cnt; r += gridDim.x * (kRB / 64)) {
     const int64_t i = list[r];
-    int lo = 0, hi = ncl;  // off[lo] <= i < off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) / 2;
-      if (off[mid] <= i) lo = mid;
-      else hi = mid;
-    }
-    const int64_t o = off[lo], e = off[lo + 1];
-    const double e2 = epsv[lo] * epsv[lo];
+    const int c = sysid[i];
+    const int64_t o = off[c], e = off[c + 1];
+    const double e2 = epsv[c] * epsv[c];
     const double xi = x[i], yi = x[total + i], zi = x[2 * total + i];
     double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll 4
     for (int64_t j = o + lane; j < e; j += 64) {
       const double dx = x[j] - xi, dy = x[total + j] - yi, dz = x[2 * total + j] - zi;
       const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(kRB) void rescue_sys_rows_kernel(int64_t total, int
 
 }  // namespace
 
-int launch_rescue_batched(int64_t total, int ncl, const int64_t* off, const double* epsv, const double* x,
+int launch_rescue_batched(int64_t total, const int* sysid, const int64_t* off, const double* epsv, const double* x,
                           const double* m, double G, bool excl, const float* est, double* a, int* list, int* count,
                           hipStream_t s) {
   if (total == 0) return NBODY_OK;
@@ -191,9 +198,11 @@ int launch_rescue_batched(int64_t total, int ncl, const int64_t* off, const doub
   flag_rows_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>((int)total, est, 1, (size_t)total, a, scale, list,
                                                                  count);
   NB_LAUNCH_CHECK("flag_rows_kernel");
+  // enough waves for a few percent of the rows at one row each: every row's
+  // short j-loop then runs beside the others instead of after them
   const unsigned grid =
-      (unsigned)std::min<int64_t>((total + kRB / 64 - 1) / (kRB / 64), 4 * (int64_t)cu_count(current_device()));
-  rescue_sys_rows_kernel<<<grid, kRB, 0, s>>>(total, ncl, off, epsv, x, m, G, excl ? 1 : 0, list, count, a);
+      (unsigned)std::min<int64_t>((total + kRB / 64 - 1) / (kRB / 64), 32 * (int64_t)cu_count(current_device()));
+  rescue_sys_rows_kernel<<<grid, kRB, 0, s>>>(total, sysid, off, epsv, x, m, G, excl ? 1 : 0, list, count, a);
   NB_LAUNCH_CHECK("rescue_sys_rows_kernel");
   return NBODY_OK;
 }

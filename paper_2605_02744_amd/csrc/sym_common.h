@@ -126,19 +126,20 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
 }  // namespace
 
 // Chunking of the half ring for n particles, with slot_bytes bytes of j-side
-// sums per particle and distance, part_bytes of i-side sums per particle and
-// workgroup of a block, and fixed_bytes per particle of staged records and
+// sums (sum_bytes of them the sums themselves, the rest error estimates) per
+// particle and distance, part_bytes of i-side sums per particle and workgroup
+// of a block, and fixed_bytes per particle of staged records and
 // block-diagonal sums: distances per workgroup (L) and per launch (D), the
-// slots of a launch kept near 1 GiB and the whole layout within budget bytes;
-// launches > 0 asks for at least that many launches.  Returns the bytes the
-// layout needs, which exceed budget only if one distance per launch does not
-// fit.
-inline size_t sym_plan(int64_t n, int launches, int slot_bytes, int part_bytes, int fixed_bytes, size_t budget,
-                       int* nb_out, int* L_out, int* D_out) {
+// sum slots of a launch kept near 1 GiB and the whole layout within budget
+// bytes; launches > 0 asks for at least that many launches.  Returns the bytes
+// the layout needs, which exceed budget only if one distance per launch does
+// not fit.
+inline size_t sym_plan(int64_t n, int launches, int slot_bytes, int sum_bytes, int part_bytes, int fixed_bytes,
+                       size_t budget, int* nb_out, int* L_out, int* D_out) {
   const int nb = (int)((n + kSI - 1) / kSI);
   const int dmax = nb / 2;
   const int64_t npad = (int64_t)nb * kSI;
-  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (slot_bytes * npad));
+  int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (sum_bytes * npad));
   if (launches > 0) dcap = std::min<int64_t>(dcap, std::max(1, (dmax + launches - 1) / launches));
   int d0 = (int)std::max<int64_t>(1, std::min<int64_t>(dmax, dcap));
   int L = 1, D = 1;

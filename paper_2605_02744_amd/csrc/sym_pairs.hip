@@ -331,9 +331,10 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
       fold(hz[u], s_acc_lo[3 * u + 2][t], pz[u]);
     }
     __syncthreads();
-    if (t < kST) {
-      // the tile's j-side sums: the 4 wave sums of each j, in wave order
-      const int jl = t;
+    if (t < 2 * kST && (t < kST || EST)) {
+      // the tile's j-side sums: the 4 wave sums of each j, in wave order; the
+      // first wave writes them, the second (EST) their share of the estimate
+      const int jl = t % kST;
       float v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -343,9 +344,10 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
       }
       const int J = (g + d) % A.nb;
       const size_t col = (size_t)J * kSI + tt * kST + jl;
+      if (t < kST) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + col] = v[c];
-      if constexpr (EST) {
+        for (int c = 0; c < 3; ++c) A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + col] = v[c];
+      } else if constexpr (EST) {
         // the far side's share of j's error estimate: this tile's sum over the
         // workgroup's i, weighted by the distance of the closest pair left in
         // rounded positions; a pair closer than j's own repair radius was
@@ -487,7 +489,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const int est_fixed = rescue ? 2 * (int)sizeof(float) + (int)sizeof(int) : 0;
   const int est_part = rescue ? (int)sizeof(float) : 0;
   const int est_slot = rescue ? (int)sizeof(float) : 0;
-  sym_plan(n, cfg.split, 3 * sizeof(float) + est_slot, 3 * sizeof(double) + est_part,
+  sym_plan(n, cfg.split, 3 * sizeof(float) + est_slot, 3 * sizeof(float), 3 * sizeof(double) + est_part,
            3 * sizeof(double) + 2 * sizeof(float4) + est_fixed, cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L,
            &D);
   const int dmax = nb / 2;
