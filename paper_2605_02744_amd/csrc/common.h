@@ -116,7 +116,8 @@ int run_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double*
 // FP64 rescue of ill-conditioned FP32C rows: flags the rows whose error
 // estimate (the sum of nslices float slices of est, stride apart) is too large
 // against |a_i| and recomputes them in FP64 in place in a.  list (n ints) and
-// count (one int) are scratch.
+// count (one int) are scratch; count must be zero when the flag kernel starts
+// (the evaluation's first kernel clears it).
 int launch_rescue(int64_t n, const double* x, const double* m, double eps, double G, bool excl, const float* est,
                   int nslices, size_t stride, double* a, int* list, int* count, hipStream_t s);
 
@@ -140,12 +141,6 @@ struct BatchConfig {
   int rescue = 1;  // FP32C, mode 3: rows flagged by the error estimate recomputed in FP64
 };
 
-// FP64 rescue of flagged FP32C rows of an ensemble (the layout's offsets,
-// softenings and per-particle system index on the device): as launch_rescue,
-// each row against its own system.
-int launch_rescue_batched(int64_t total, const int* sysid, const int64_t* off, const double* epsv, const double* x,
-                          const double* m, double G, bool excl, const float* est, double* a, int* list, int* count,
-                          hipStream_t s);
 
 // nsteps KDK steps of every system of the ensemble with the given kernel configuration.
 int run_batched(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,

@@ -544,13 +544,16 @@ __global__ void ens_kick_kernel(int64_t total, double* __restrict__ v, const dou
     v[e] = fma(h, a[e], v[e]);
 }
 
-// With est (FP32C): each particle's rounding-error estimate for the rescue
-// (one share per block of 64 j, see rescue.hip) goes to est[i].
+// With rescue (FP32C): the wave keeps each row's rounding-error estimate (one
+// share per block of 64 j, as the pair kernels do; see rescue.hip) and
+// recomputes the rows whose estimate is too large in FP64 itself, one row at a
+// time over the system's FP64 positions x and masses m, before it stores them.
 template <int MODE, bool EXCL>
 __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_waveforce_kernel(
     const int64_t* __restrict__ off, const double* __restrict__ epsv, const SItem* __restrict__ items,
     const int* __restrict__ wg_off, const int* __restrict__ wg_list, const JRec<MODE>* __restrict__ xrec,
-    double* __restrict__ a, int64_t total, double G, float* __restrict__ est) {
+    double* __restrict__ a, int64_t total, double G, int rescue, const double* __restrict__ x,
+    const double* __restrict__ m) {
   using R = Real<MODE>;
   constexpr bool kNear = MODE == kFP32C;
   __shared__ JRec<MODE> slot[kWWaves][64];
@@ -640,7 +643,7 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
             pz = qz;
             r2min = r2nr;
           }
-          if (est) eacc = est_add(eacc, px, py, pz, xinf, r2min);
+          if (rescue) eacc = est_add(eacc, px, py, pz, xinf, r2min);
         }
         fold(hx, lx, px);
         fold(hy, ly, py);
@@ -655,12 +658,30 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
         else block(std::false_type{}, std::false_type{}, cnt);
       }
     }
+    const double ax = G * ((double)hx + (double)lx), ay = G * ((double)hy + (double)ly),
+                 az = G * ((double)hz + (double)lz);
+    bool flag = false;
     if (lane < it.ni) {
       const int64_t i = o + ii;
-      a[i] = G * ((double)hx + (double)lx);
-      a[total + i] = G * ((double)hy + (double)ly);
-      a[2 * total + i] = G * ((double)hz + (double)lz);
-      if (kNear && est) est[i] = eacc;
+      a[i] = ax;
+      a[total + i] = ay;
+      a[2 * total + i] = az;
+      if (kNear && rescue) flag = sqrt((double)eacc) * (kRescueScale * fabs(G)) > sqrt(ax * ax + ay * ay + az * az);
+    }
+    if constexpr (kNear) {
+      // the flagged rows, one at a time by the whole wave; the owner lane
+      // overwrites its row
+      for (unsigned long long mask = __ballot(flag); mask; mask &= mask - 1) {
+        const int k = __ffsll((long long)mask) - 1;
+        const int64_t i = o + it.i0 + k;
+        double sx, sy, sz;
+        wave_row_fp64(x, m, total, o, nc, i, (double)eps * eps, EXCL, sx, sy, sz);
+        if (lane == k) {
+          a[i] = G * sx;
+          a[total + i] = G * sy;
+          a[2 * total + i] = G * sz;
+        }
+      }
     }
   }
 }
@@ -686,9 +707,6 @@ struct SPlan {
   int2* d_ws_sys = nullptr;  // wave items: (system, items of it held by the workgroup)
   void* d_xrec = nullptr;
   int* d_cnt = nullptr;
-  float* d_est = nullptr;  // per-step wave items, FP32C: the rescue's error estimates (total),
-  int* d_list = nullptr;   // its count and list of flagged rows (64 + total)
-  int* d_sysid = nullptr;  // and each particle's system (total)
 };
 
 std::mutex g_splan_mu;
@@ -696,8 +714,7 @@ std::vector<SPlan*> g_splans;
 
 void free_splan(SPlan* p) {
   for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_nparts, (void*)p->d_items, (void*)p->d_wg_off,
-                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt,
-                  (void*)p->d_est, (void*)p->d_list, (void*)p->d_sysid})
+                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt})
     if (q) (void)hipFree(q);
   delete p;
 }
@@ -905,14 +922,6 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
             supload(&p->d_ws_off, ws_off) && supload(&p->d_ws_sys, ws_sys) &&
             hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
             hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
-  if (ok && MODE == kFP32C) {
-    std::vector<int> sysid((size_t)p->total);
-    for (int c = 0; c < ncl; ++c)
-      for (int64_t i = off[c]; i < off[c + 1]; ++i) sysid[(size_t)i] = c;
-    ok = hipMalloc(&p->d_est, sizeof(float) * (size_t)std::max<int64_t>(1, p->total)) == hipSuccess &&
-         hipMalloc(&p->d_list, sizeof(int) * (size_t)(64 + std::max<int64_t>(1, p->total))) == hipSuccess &&
-         supload(&p->d_sysid, sysid);
-  }
   if (!ok) {
     (void)hipGetLastError();
     free_splan(p);
@@ -970,20 +979,15 @@ int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double*
   auto* rec = static_cast<JRec<MODE>*>(p->d_xrec);
   const double h = 0.5 * dt;
   const unsigned ew = (unsigned)std::min<int64_t>((p->total + 255) / 256, 4096);
-  rescue = rescue && MODE == kFP32C && p->d_est;
-  float* est = rescue ? p->d_est : nullptr;
+  const int rs = rescue && MODE == kFP32C ? 1 : 0;
   auto force = [&]() -> int {
     if (excl)
       ens_waveforce_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
-                                                                  p->d_wg_list, rec, a, p->total, G, est);
+                                                                  p->d_wg_list, rec, a, p->total, G, rs, x, m);
     else
       ens_waveforce_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
-                                                                   p->d_wg_list, rec, a, p->total, G, est);
+                                                                   p->d_wg_list, rec, a, p->total, G, rs, x, m);
     NB_LAUNCH_CHECK("ens_waveforce_kernel");
-    // the rows whose error estimate is too large, recomputed in FP64 from the new positions
-    if (rescue)
-      return launch_rescue_batched(p->total, p->d_sysid, p->d_off, p->d_eps, x, m, G, excl, est, a, p->d_list + 64,
-                                   p->d_list, s);
     return NBODY_OK;
   };
   int st;

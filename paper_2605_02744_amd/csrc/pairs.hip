@@ -60,11 +60,13 @@ __device__ __forceinline__ JRec<MODE> load_rec(const double* __restrict__ x, con
 template <int MODE, int IPL, bool EXCL, bool NEAR>
 __global__ __launch_bounds__(kBlock) void accel_kernel(int n, const double* __restrict__ x,
                                                        const double* __restrict__ m, double eps, double G,
-                                                       int chunk, double* __restrict__ out, float* __restrict__ est) {
+                                                       int chunk, double* __restrict__ out, float* __restrict__ est,
+                                                       int* __restrict__ zc) {
   using R = Real<MODE>;
   static_assert(!NEAR || MODE == kFP32C, "the near-field repair needs float-float records");
   __shared__ JRec<MODE> tile[2][kTile];
   const int t = threadIdx.x;
+  if (zc && blockIdx.x == 0 && blockIdx.y == 0 && t == 0) *zc = 0;  // the rescue's count of flagged rows
   const int ibase = blockIdx.x * (kBlock * IPL) + t;
   const int js = blockIdx.y * chunk;
   const int je = min(n, js + chunk);
@@ -856,9 +858,9 @@ int accel_dispatch(int64_t n, const double* x, const double* m, double* a, doubl
   float* est = rescue ? reinterpret_cast<float*>(ws + part_bytes) : nullptr;
   int* list = rescue ? reinterpret_cast<int*>(ws + part_bytes + est_bytes) : nullptr;
   if (excl)
-    accel_kernel<MODE, IPL, true, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out, est);
+    accel_kernel<MODE, IPL, true, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out, est, list);
   else
-    accel_kernel<MODE, IPL, false, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out, est);
+    accel_kernel<MODE, IPL, false, kNear><<<grid, kBlock, 0, s>>>((int)n, x, m, eps, G, chunk, out, est, list);
   NB_LAUNCH_CHECK("accel_kernel");
   if (sp > 1) {
     const int64_t cnt = 3 * n;

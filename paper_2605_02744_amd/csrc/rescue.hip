@@ -35,19 +35,21 @@
 // (terms of a block that cancel each other more than random directions do);
 // the far side of the symmetric kernels carries no distance factor.
 //
-// The flagged rows go to a list (an atomic counter orders them, which does not
-// change any result: every row is recomputed on its own, in a fixed order) and
-// a grid-stride kernel recomputes them in FP64, eight rows per workgroup pass
-// over the j-range so that each j record is loaded once per eight rows.
+// Here, for the force of one system: the flagged rows go to a list (an atomic
+// counter, one add per wave, orders them, which does not change any result:
+// every row is recomputed on its own, in a fixed order) and a grid-stride
+// kernel recomputes them in FP64.  The count of flagged rows is cleared by the
+// first kernel of the evaluation (its block 0, thread 0), so that the flag
+// kernel starts from zero without a launch of its own.  The batched wave items
+// (ensemble_stream.hip) flag and recompute their rows inside the force kernel,
+// where each wave holds whole rows.
 #include "pair_math.h"
 
 namespace nb {
 namespace {
 
-constexpr int kRB = 256;   // lanes per workgroup of the rescue kernel
-constexpr int kRRows = 8;  // rows per workgroup pass
-
-__global__ void zero_count_kernel(int* count) { *count = 0; }
+constexpr int kRB = 256;           // lanes per workgroup of the rescue kernel
+constexpr int64_t kRSmall = 131072;  // systems up to this size take one row per workgroup pass
 
 // One thread per particle: sums the nslices slices of the estimate (stride
 // apart) and appends the row to the list if scale * sqrt(E_i) > |a_i|.  A
@@ -74,23 +76,26 @@ __global__ void flag_rows_kernel(int n, const float* __restrict__ est, int nslic
 }
 
 // Recomputes the listed rows of a = G sum_j m_j d / (|d|^2 + eps^2)^(3/2) in
-// FP64: each pass takes kRRows rows of the list, the lanes split the j-range
-// (lane t takes j = t, t + 256, ...), and the lane sums are added in a fixed
-// order: a butterfly inside each wave, then the four wave sums in wave order.
+// FP64: each pass takes R rows of the list (8 for large systems, where each j
+// record then serves eight rows; 1 for small ones, where the few flagged rows
+// should run side by side), the lanes split the j-range (lane t takes j = t,
+// t + 256, ...), and the lane sums are added in a fixed order: a butterfly
+// inside each wave, then the four wave sums in wave order.
+template <int R>
 __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* __restrict__ x,
                                                           const double* __restrict__ m, double eps, double G,
                                                           int excl, const int* __restrict__ list,
                                                           const int* __restrict__ count, double* __restrict__ a) {
-  __shared__ double red[3][kRRows][kRB / 64];
+  __shared__ double red[3][R][kRB / 64];
   const int t = threadIdx.x;
   const int wave = t / 64, lane = t % 64;
   const int cnt = *count;
   const double e2 = eps * eps;
-  for (int r0 = blockIdx.x * kRRows; r0 < cnt; r0 += gridDim.x * kRRows) {
-    int row[kRRows];
-    double xi[kRRows], yi[kRRows], zi[kRRows], sx[kRRows], sy[kRRows], sz[kRRows];
+  for (int r0 = blockIdx.x * R; r0 < cnt; r0 += gridDim.x * R) {
+    int row[R];
+    double xi[R], yi[R], zi[R], sx[R], sy[R], sz[R];
 #pragma unroll
-    for (int k = 0; k < kRRows; ++k) {
+    for (int k = 0; k < R; ++k) {
       row[k] = r0 + k < cnt ? list[r0 + k] : -1;
       const int i = row[k] < 0 ? 0 : row[k];
       xi[k] = x[i];
@@ -98,10 +103,11 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
       zi[k] = x[2 * n + i];
       sx[k] = sy[k] = sz[k] = 0.0;
     }
+#pragma unroll(R == 1 ? 4 : 1)
     for (int j = t; j < n; j += kRB) {
       const double xj = x[j], yj = x[n + j], zj = x[2 * n + j], mj = m[j];
 #pragma unroll
-      for (int k = 0; k < kRRows; ++k) {
+      for (int k = 0; k < R; ++k) {
         const double dx = xj - xi[k], dy = yj - yi[k], dz = zj - zi[k];
         const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
         const double ri = rsqrt64(r2);
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
       }
     }
 #pragma unroll
-    for (int k = 0; k < kRRows; ++k) {
+    for (int k = 0; k < R; ++k) {
       for (int off = 32; off > 0; off >>= 1) {
         sx[k] += __shfl_xor(sx[k], off, 64);
         sy[k] += __shfl_xor(sy[k], off, 64);
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
       }
     }
     __syncthreads();
-    if (t < kRRows && row[t] >= 0) {
+    if (t < R && row[t] >= 0) {
       const int i = row[t];
       double v[3];
 #pragma unroll
@@ -143,81 +149,22 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
   }
 }
 
-// The batched form: one wave per listed row of a concatenated ensemble (the
-// row's system from the per-particle system index sysid), its lanes splitting
-// the system's j-range; the lane sums added by a butterfly (fixed order).
-__global__ __launch_bounds__(kRB) void rescue_sys_rows_kernel(int64_t total, const int* __restrict__ sysid,
-                                                              const int64_t* __restrict__ off,
-                                                              const double* __restrict__ epsv,
-                                                              const double* __restrict__ x,
-                                                              const double* __restrict__ m, double G, int excl,
-                                                              const int* __restrict__ list,
-                                                              const int* __restrict__ count, double* __restrict__ a) {
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int cnt = *count;
-  for (int r = blockIdx.x * (kRB / 64) + wave; r < cnt; r += gridDim.x * (kRB / 64)) {
-    const int64_t i = list[r];
-    const int c = sysid[i];
-    const int64_t o = off[c], e = off[c + 1];
-    const double e2 = epsv[c] * epsv[c];
-    const double xi = x[i], yi = x[total + i], zi = x[2 * total + i];
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll 4
-    for (int64_t j = o + lane; j < e; j += 64) {
-      const double dx = x[j] - xi, dy = x[total + j] - yi, dz = x[2 * total + j] - zi;
-      const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-      const double ri = rsqrt64(r2);
-      double sc = (m[j] * ri) * (ri * ri);
-      if (excl && j == i) sc = 0.0;
-      sx = fma(sc, dx, sx);
-      sy = fma(sc, dy, sy);
-      sz = fma(sc, dz, sz);
-    }
-    for (int w = 32; w > 0; w >>= 1) {
-      sx += __shfl_xor(sx, w, 64);
-      sy += __shfl_xor(sy, w, 64);
-      sz += __shfl_xor(sz, w, 64);
-    }
-    if (lane == 0) {
-      a[i] = G * sx;
-      a[total + i] = G * sy;
-      a[2 * total + i] = G * sz;
-    }
-  }
-}
-
 }  // namespace
-
-int launch_rescue_batched(int64_t total, const int* sysid, const int64_t* off, const double* epsv, const double* x,
-                          const double* m, double G, bool excl, const float* est, double* a, int* list, int* count,
-                          hipStream_t s) {
-  if (total == 0) return NBODY_OK;
-  zero_count_kernel<<<1, 1, 0, s>>>(count);
-  NB_LAUNCH_CHECK("zero_count_kernel");
-  const double scale = kEstC * 5.9604644775390625e-8 * std::fabs(G) / kRescueTol;
-  flag_rows_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>((int)total, est, 1, (size_t)total, a, scale, list,
-                                                                 count);
-  NB_LAUNCH_CHECK("flag_rows_kernel");
-  // enough waves for a few percent of the rows at one row each: every row's
-  // short j-loop then runs beside the others instead of after them
-  const unsigned grid =
-      (unsigned)std::min<int64_t>((total + kRB / 64 - 1) / (kRB / 64), 32 * (int64_t)cu_count(current_device()));
-  rescue_sys_rows_kernel<<<grid, kRB, 0, s>>>(total, sysid, off, epsv, x, m, G, excl ? 1 : 0, list, count, a);
-  NB_LAUNCH_CHECK("rescue_sys_rows_kernel");
-  return NBODY_OK;
-}
 
 int launch_rescue(int64_t n, const double* x, const double* m, double eps, double G, bool excl, const float* est,
                   int nslices, size_t stride, double* a, int* list, int* count, hipStream_t s) {
   if (n == 0) return NBODY_OK;
-  zero_count_kernel<<<1, 1, 0, s>>>(count);
-  NB_LAUNCH_CHECK("zero_count_kernel");
-  const double scale = kEstC * 5.9604644775390625e-8 * std::fabs(G) / kRescueTol;
+  const double scale = kRescueScale * std::fabs(G);
   flag_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((int)n, est, nslices, stride, a, scale, list, count);
   NB_LAUNCH_CHECK("flag_rows_kernel");
-  const int64_t passes = (n + kRRows - 1) / kRRows;
-  const unsigned grid = (unsigned)std::min<int64_t>(passes, 4 * (int64_t)cu_count(current_device()));
-  rescue_rows_kernel<<<grid, kRB, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list, count, a);
+  const int cus = cu_count(current_device());
+  if (n <= kRSmall) {
+    const unsigned grid = (unsigned)std::min<int64_t>(n, 8 * (int64_t)cus);
+    rescue_rows_kernel<1><<<grid, kRB, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list, count, a);
+  } else {
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 7) / 8, 4 * (int64_t)cus);
+    rescue_rows_kernel<8><<<grid, kRB, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list, count, a);
+  }
   NB_LAUNCH_CHECK("rescue_rows_kernel");
   return NBODY_OK;
 }

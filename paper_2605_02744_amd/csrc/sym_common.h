@@ -17,6 +17,8 @@ constexpr int kST = 64;             // j-particles per LDS tile
 constexpr int kSR = 16;             // lanes per row = records per sub-block
 constexpr int kSTiles = kSI / kST;  // tiles per J-block
 constexpr int kSW = kSL / 64;       // waves per workgroup
+constexpr int kDiagG = 4;          // lane groups of the block-diagonal kernels, each over kSI / kDiagG of the j
+static_assert(kSI % (kDiagG * kFold) == 0, "each diagonal lane group takes whole folds");
 
 // v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
 template <int K>

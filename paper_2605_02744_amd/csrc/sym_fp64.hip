@@ -204,22 +204,23 @@ __global__ __launch_bounds__(kSL, 6) void sym64_kernel(S64Args A) {
 }
 
 // The block with itself (distance 0), ordered form, i-side only, own pair
-// masked when asked.  Writes hi + lo into pd[3][npad].
+// masked when asked.  kDiagG groups of kSL lanes each take kSI / kDiagG of the
+// j; group 0 adds the groups' hi + lo in group order into pd[3][npad].
 template <bool EXCL>
-__global__ __launch_bounds__(kSL) void sym64_diag_kernel(S64Args A, double* __restrict__ pd) {
+__global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, double* __restrict__ pd) {
   __shared__ double4 s_rec[kSI];
-  const int t = threadIdx.x;
+  __shared__ double s_part[kDiagG - 1][3][kSI];
+  const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
   const int g = blockIdx.x;
   const double e2 = A.eps * A.eps;
   DSet s;
   load_dset(A, g, t, s);
-#pragma unroll
-  for (int u = 0; u < 2; ++u) s_rec[u * kSL + t] = A.rec[(size_t)g * kSI + u * kSL + t];
+  for (int k = threadIdx.x; k < kSI; k += kSL * kDiagG) s_rec[k] = A.rec[(size_t)g * kSI + k];
   __syncthreads();
   double hx[2] = {0.0, 0.0}, hy[2] = {0.0, 0.0}, hz[2] = {0.0, 0.0};
   double lx[2] = {0.0, 0.0}, ly[2] = {0.0, 0.0}, lz[2] = {0.0, 0.0};
 #pragma unroll 1
-  for (int f = 0; f < kSI; f += kFold) {
+  for (int f = grp * (kSI / kDiagG); f < (grp + 1) * (kSI / kDiagG); f += kFold) {
     double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};
 #pragma unroll 8
     for (int j = f; j < f + kFold; ++j) {
@@ -243,12 +244,30 @@ __global__ __launch_bounds__(kSL) void sym64_diag_kernel(S64Args A, double* __re
       fold(hz[u], lz[u], pz[u]);
     }
   }
+  if (grp > 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      s_part[grp - 1][0][u * kSL + t] = hx[u] + lx[u];
+      s_part[grp - 1][1][u * kSL + t] = hy[u] + ly[u];
+      s_part[grp - 1][2][u * kSL + t] = hz[u] + lz[u];
+    }
+  }
+  __syncthreads();
+  if (grp > 0) return;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const size_t i = (size_t)g * kSI + u * kSL + t;
-    pd[i] = hx[u] + lx[u];
-    pd[A.npad + i] = hy[u] + ly[u];
-    pd[2 * (size_t)A.npad + i] = hz[u] + lz[u];
+    const int k = u * kSL + t;
+    const size_t i = (size_t)g * kSI + k;
+    double vx = hx[u] + lx[u], vy = hy[u] + ly[u], vz = hz[u] + lz[u];
+#pragma unroll
+    for (int q = 0; q < kDiagG - 1; ++q) {
+      vx += s_part[q][0][k];
+      vy += s_part[q][1][k];
+      vz += s_part[q][2][k];
+    }
+    pd[i] = vx;
+    pd[A.npad + i] = vy;
+    pd[2 * (size_t)A.npad + i] = vz;
   }
 }
 
@@ -283,8 +302,8 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   A.rec = rec;
   sym64_stage_kernel<<<(unsigned)((npad + 255) / 256), 256, 0, s>>>(A, rec);
   NB_LAUNCH_CHECK("sym64_stage_kernel");
-  if (excl) sym64_diag_kernel<true><<<nb, kSL, 0, s>>>(A, pd);
-  else sym64_diag_kernel<false><<<nb, kSL, 0, s>>>(A, pd);
+  if (excl) sym64_diag_kernel<true><<<nb, kSL * kDiagG, 0, s>>>(A, pd);
+  else sym64_diag_kernel<false><<<nb, kSL * kDiagG, 0, s>>>(A, pd);
   NB_LAUNCH_CHECK("sym64_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {

@@ -129,8 +129,9 @@ __device__ __forceinline__ void near_delta(float dx, float dy, float dz, float r
 // never repaired), converted once per evaluation so that the force kernel's
 // tiles are plain 16-byte copies.
 template <bool NEAR>
-__global__ void sym_stage_kernel(SymArgs A, float4* __restrict__ rhi, float4* __restrict__ rlo) {
+__global__ void sym_stage_kernel(SymArgs A, float4* __restrict__ rhi, float4* __restrict__ rlo, int* __restrict__ zc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (zc && j == 0) *zc = 0;  // the rescue's count of flagged rows
   if (j >= A.npad) return;
   float4 hi, lo;
   const int n = A.n;
@@ -381,21 +382,25 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
 // The block with itself (distance 0): the i-side of all ordered pairs inside
 // I-block g, in the ordered form (the LDS record broadcast to every lane), with
 // the own pair masked when asked and the near-field repair of the force kernel.
-// Writes hi + lo into pd[3][npad].
+// kDiagG groups of kSL lanes each take kSI / kDiagG of the j (so that the
+// launch has several waves per SIMD); group 0 adds the groups' hi + lo in
+// group order and writes the sums into pd[3][npad].
 template <bool NEAR, bool EXCL>
-__global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __restrict__ pd, float* __restrict__ ed) {
+__global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double* __restrict__ pd,
+                                                                float* __restrict__ ed) {
   __shared__ float4 s_hi[kSI];
   __shared__ float4 s_lo[kSI];
-  const int t = threadIdx.x;
+  __shared__ double s_part[kDiagG - 1][3][kSI];
+  __shared__ float s_epart[kDiagG - 1][kSI];
+  const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
   const int g = blockIdx.x;
   const float e2 = (float)(A.eps * A.eps);
   ISet s;
   float thr[2];
   load_iset<false>(A, g, t, s, thr);
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    s_hi[u * kSL + t] = A.rhi[(size_t)g * kSI + u * kSL + t];
-    s_lo[u * kSL + t] = A.rlo[(size_t)g * kSI + u * kSL + t];
+  for (int k = threadIdx.x; k < kSI; k += kSL * kDiagG) {
+    s_hi[k] = A.rhi[(size_t)g * kSI + k];
+    s_lo[k] = A.rlo[(size_t)g * kSI + k];
   }
   __syncthreads();
   float hx[2] = {0.f, 0.f}, hy[2] = {0.f, 0.f}, hz[2] = {0.f, 0.f};
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
 #pragma unroll
   for (int u = 0; u < 2; ++u) rc[u] = s_lo[u * kSL + t].w;
 #pragma unroll 1
-  for (int f = 0; f < kSI; f += kFold) {
+  for (int f = grp * (kSI / kDiagG); f < (grp + 1) * (kSI / kDiagG); f += kFold) {
     float px[2] = {0.f, 0.f}, py[2] = {0.f, 0.f}, pz[2] = {0.f, 0.f};
     float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 16
@@ -462,13 +467,34 @@ __global__ __launch_bounds__(kSL) void sym_diag_kernel(SymArgs A, double* __rest
       fold(hz[u], lz[u], pz[u]);
     }
   }
+  if (grp > 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      s_part[grp - 1][0][u * kSL + t] = (double)hx[u] + (double)lx[u];
+      s_part[grp - 1][1][u * kSL + t] = (double)hy[u] + (double)ly[u];
+      s_part[grp - 1][2][u * kSL + t] = (double)hz[u] + (double)lz[u];
+      s_epart[grp - 1][u * kSL + t] = ea[u];
+    }
+  }
+  __syncthreads();
+  if (grp > 0) return;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const size_t i = (size_t)g * kSI + u * kSL + t;
-    pd[i] = (double)hx[u] + (double)lx[u];
-    pd[A.npad + i] = (double)hy[u] + (double)ly[u];
-    pd[2 * (size_t)A.npad + i] = (double)hz[u] + (double)lz[u];
-    if (NEAR && ed) ed[i] = ea[u];
+    const int k = u * kSL + t;
+    const size_t i = (size_t)g * kSI + k;
+    double vx = (double)hx[u] + (double)lx[u], vy = (double)hy[u] + (double)ly[u], vz = (double)hz[u] + (double)lz[u];
+    float e = ea[u];
+#pragma unroll
+    for (int q = 0; q < kDiagG - 1; ++q) {
+      vx += s_part[q][0][k];
+      vy += s_part[q][1][k];
+      vz += s_part[q][2][k];
+      e += s_epart[q][k];
+    }
+    pd[i] = vx;
+    pd[A.npad + i] = vy;
+    pd[2 * (size_t)A.npad + i] = vz;
+    if (NEAR && ed) ed[i] = e;
   }
 }
 
@@ -526,15 +552,15 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   float* ed = rescue ? eo + npad : nullptr;
   int* list = rescue ? reinterpret_cast<int*>(tail + pe_bytes + pw_bytes + eo_bytes) : nullptr;
   const unsigned sg = (unsigned)((npad + 255) / 256);
-  if (near) sym_stage_kernel<true><<<sg, 256, 0, s>>>(A, rhi, rlo);
-  else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo);
+  if (near) sym_stage_kernel<true><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
+  else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
   NB_LAUNCH_CHECK("sym_stage_kernel");
   if (near) {
-    if (excl) sym_diag_kernel<true, true><<<nb, kSL, 0, s>>>(A, pd, ed);
-    else sym_diag_kernel<true, false><<<nb, kSL, 0, s>>>(A, pd, ed);
+    if (excl) sym_diag_kernel<true, true><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
+    else sym_diag_kernel<true, false><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
   } else {
-    if (excl) sym_diag_kernel<false, true><<<nb, kSL, 0, s>>>(A, pd, ed);
-    else sym_diag_kernel<false, false><<<nb, kSL, 0, s>>>(A, pd, ed);
+    if (excl) sym_diag_kernel<false, true><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
+    else sym_diag_kernel<false, false><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
   }
   NB_LAUNCH_CHECK("sym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
