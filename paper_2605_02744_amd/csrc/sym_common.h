@@ -30,6 +30,23 @@ __device__ __forceinline__ float row_ror(float v) {
 // instructions of one wave execute in order; this keeps the compiler from
 // moving, merging or dropping reads and writes across the point, which it may
 // otherwise do because to it different lanes are different threads).
+// Workgroups go to the chip's 8 XCDs round-robin (workgroup id mod 8), and
+// each XCD has its own L2.  This logical index gives each XCD runs of
+// kXCDRun consecutive indices (the runs dealt to the XCDs in turn), so that
+// the workgroups of neighbouring I-blocks, which read the same J-blocks one
+// ring distance apart, share an L2, while every XCD still gets a share of the
+// whole grid (whole-grid ranges per XCD leave the XCDs unevenly loaded where
+// the half ring ends).  A bijection on [0, grid): the tail past the last whole
+// round of runs keeps its index.
+constexpr int kXCDs = 8;
+constexpr int kXCDRun = 16;
+__device__ __forceinline__ int xcd_local_index(int bid, int grid) {
+  const int whole = grid / (kXCDs * kXCDRun) * (kXCDs * kXCDRun);
+  if (bid >= whole) return bid;
+  const int x = bid % kXCDs, k = bid / kXCDs;
+  return ((k / kXCDRun) * kXCDs + x) * kXCDRun + k % kXCDRun;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

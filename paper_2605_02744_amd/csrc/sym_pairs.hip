@@ -226,8 +226,9 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   const int t = threadIdx.x;
   const int rl = t & (kSR - 1);
   const int wave = t / 64;
-  const int g = blockIdx.x % A.nb;
-  const int part = blockIdx.x / A.nb;
+  const int lid = xcd_local_index(blockIdx.x, gridDim.x);
+  const int g = lid % A.nb;
+  const int part = lid / A.nb;
   const int dbeg = A.d_lo + part * A.L;
   const int dend = min(dbeg + A.L, ring_end(A, g));
   const int ntiles = dend > dbeg ? (dend - dbeg) * kSTiles : 0;
