@@ -165,11 +165,10 @@ PairConfig choose_config(int64_t n, int precision, int device) {
   if (t.split) c.split = t.split;
   if (t.pairs) c.sym = t.pairs == 2 ? 1 : 0;
   c.rescue = t.rescue == 2 ? 0 : 1;
-  // the symmetric kernels read split as a least number of launches (0 = automatic)
-  if (c.sym) {
-    c.split = t.split;
-    return c;
-  }
+  // the symmetric kernels read a set split as a least number of launches (0 =
+  // automatic); the ordered kernels that serve the same sizes (acceleration +
+  // jerk, + snap, the FP64 VJP) keep their own j-split
+  c.launches = c.sym ? t.split : 0;
   if (c.split <= 0) c.split = auto_split(n, c.ipl, device);
   return c;
 }

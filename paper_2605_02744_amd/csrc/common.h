@@ -48,8 +48,9 @@ constexpr int64_t kSymMinN = 32768;  // systems from this size use the symmetric
 // Per-call configuration of the all-pairs kernels.
 struct PairConfig {
   int ipl = 1;    // i-particles per lane
-  int split = 1;  // j-range split across workgroups
+  int split = 1;  // j-range split across workgroups (the ordered kernels)
   int sym = 0;    // 1: the symmetric kernels (each unordered pair once; the VJP in FP32C/FP32 only)
+  int launches = 0;  // symmetric kernels: least number of launches of the half ring (0 = automatic)
   int rescue = 1;  // FP32C force: recompute rows flagged by the error estimate in FP64
   // Device memory the caller lends for this call's partial sums, staged
   // records and slots.  When set, the all-pairs launchers fit their plans into

@@ -280,7 +280,7 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   int nb, L, D;
   // per particle: FP64 j-side slot sums per distance, FP64 i-side sums per workgroup,
   // FP64 block-diagonal sums and one staged double4 record
-  sym_plan(n, cfg.split, 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double) + sizeof(double4),
+  sym_plan(n, cfg.launches, 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double) + sizeof(double4),
            cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;

@@ -516,7 +516,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const int est_fixed = rescue ? 2 * (int)sizeof(float) + (int)sizeof(int) : 0;
   const int est_part = rescue ? (int)sizeof(float) : 0;
   const int est_slot = rescue ? (int)sizeof(float) : 0;
-  sym_plan(n, cfg.split, 3 * sizeof(float) + est_slot, 3 * sizeof(float), 3 * sizeof(double) + est_part,
+  sym_plan(n, cfg.launches, 3 * sizeof(float) + est_slot, 3 * sizeof(float), 3 * sizeof(double) + est_part,
            3 * sizeof(double) + 2 * sizeof(float4) + est_fixed, cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L,
            &D);
   const int dmax = nb / 2;

@@ -413,7 +413,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   int nb, L, D;
   // per particle: FP32 j-side slot sums per distance, FP64 i-side sums per workgroup,
   // FP64 block-diagonal sums and three staged float4 records
-  sym_plan(n, cfg.split, kVC * sizeof(float), kVC * sizeof(float), kVC * sizeof(double), kVC * sizeof(double) + 3 * sizeof(float4),
+  sym_plan(n, cfg.launches, kVC * sizeof(float), kVC * sizeof(float), kVC * sizeof(double), kVC * sizeof(double) + 3 * sizeof(float4),
            cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
