@@ -289,6 +289,20 @@ def bench_force(args, torch, nb):
         nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
         A32, A64 = a32.cpu().numpy(), a64.cpu().numpy()
         e_all = rel_err_rows(A32, A64)
+        if args.precision == "fp32c":
+            # the same evaluation with the FP64 rescue off: its time and its error, for the
+            # rescue's cost and what it buys (the library default keeps it on)
+            nb.nbody_set_config(pairs=args.pairs or 0, rescue=2)
+            try:
+                ms_off, _, _ = timed(f32, max(1, args.steps // 2), 1, torch)
+                nb.nbody_accel(tx, tm, eps=eps, precision=args.precision, out=a32)
+                e_off = rel_err_rows(a32.cpu().numpy(), A64)
+            finally:
+                nb.nbody_set_config(pairs=args.pairs or 0)
+            res["rescue_off"] = {"ms_per_eval": round(ms_off, 4), "rescue_cost": round(ms / ms_off - 1.0, 4),
+                                 "max_rel_vs_fp64gpu": float(e_off.max()),
+                                 "rows_over_1e-5": int((e_off > 1e-5).sum()),
+                                 "rows_recomputed_in_fp64": int(np.any(A32 != a32.cpu().numpy(), axis=0).sum())}
         res["accuracy"] = {"fp32c_vs_fp64gpu_max_rel": float(e_all.max()),
                            "fp32c_vs_fp64gpu_p99_9": float(np.quantile(e_all, 0.999)),
                            "fp32c_vs_fp64gpu_p99": float(np.quantile(e_all, 0.99)),
