@@ -85,10 +85,11 @@ typedef struct nbody_params {
 
 /* Accelerations a (3*n) of particles at x (3*n) with masses m (n).
  * Eq. (1) of Sec. 2.1 divided by m_i, softened as in App. A.
- * From 32768 particles on (or as nbody_config.pairs says) each unordered
- * pair is evaluated once and applied to both particles, with sums in a fixed
- * order; this uses a workspace of up to about 1.5 GiB (staged records and
- * per-distance sums) and several launches per call.
+ * From 49152 particles on in FP32C and FP32, from 16384 in FP64 (or as
+ * nbody_config.pairs says), each unordered pair is evaluated once and applied
+ * to both particles, with sums in a fixed order; this uses a workspace of up
+ * to about 2 GiB (staged records and per-distance sums) and several launches
+ * per call.
  * n == 0 is a no-op.  x, m, a must not alias.  Errors: NBODY_EINVAL for null
  * pointers with n > 0, n < 0, n > 2^29, eps < 0, eps == 0 without
  * NBODY_EXCLUDE_SELF, non-finite G, unknown precision; NBODY_ENOMEM if the
@@ -313,13 +314,15 @@ typedef struct nbody_config {
   int32_t pairs;   /* form of the force kernel of nbody_accel, of the KDK
                       steps and (FP32C/FP32 only) of nbody_accel_vjp and the
                       adjoint sweep: 0 = automatic (the tuned choice for
-                      (n, precision), else symmetric from 32768 particles on),
+                      (n, precision), else symmetric from 49152 particles
+                      on in FP32C/FP32 and from 16384 in FP64 for the force,
+                      from 32768 for the VJP),
                       1 = ordered: every ordered pair evaluated for its i;
                       2 = symmetric: every unordered pair evaluated once and
                       applied to both particles (a_j gets the opposite of i's
                       term scaled by m_i / m_j), results summed in a fixed order
                       (reproducible), at the cost of a workspace of about
-                      1.5 GiB for large n and, in FP32C/FP32, an FP32 sum of up
+                      2 GiB for large n and, in FP32C/FP32, an FP32 sum of up
                       to 512 terms per j before the FP64 sums */
   int32_t rescue;  /* FP32C force of nbody_accel, nbody_accel_noalloc, the
                       KDK steps of nbody_step and of the adjoint's recompute,
@@ -339,7 +342,8 @@ typedef struct nbody_config {
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros
- * restores the automatic choice).  A batched plan is built with the bsplit
+ * restores the automatic choice); like the tuners, a tool of this library,
+ * not a call the paper defines.  A batched plan is built with the bsplit
  * value in force when its layout is first seen.  Errors: NBODY_EINVAL for
  * values outside the lists above. */
 int nbody_set_config(const nbody_config* cfg);

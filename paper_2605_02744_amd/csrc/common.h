@@ -43,13 +43,19 @@ constexpr int kBlock = 256;        // threads per workgroup of the all-pairs ker
 constexpr int kTile = 256;         // j-particles staged in LDS per tile
 constexpr int kFold = 64;          // j-terms summed in plain FP32/FP64 before a TwoSum fold
 constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
-constexpr int64_t kSymMinN = 32768;  // systems from this size use the symmetric force kernels by default
+// Sizes from which the symmetric kernels are the default (measured crossovers
+// against the ordered kernels): the FP32C/FP32 force from 49152 particles, the
+// FP64 force from 16384, the FP32C/FP32 VJP from 32768.
+constexpr int64_t kSymMinN = 49152;
+constexpr int64_t kSymMinN64 = 16384;
+constexpr int64_t kSymMinNVjp = 32768;
 
 // Per-call configuration of the all-pairs kernels.
 struct PairConfig {
   int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups (the ordered kernels)
-  int sym = 0;    // 1: the symmetric kernels (each unordered pair once; the VJP in FP32C/FP32 only)
+  int sym = 0;      // 1: the symmetric force kernels (each unordered pair once)
+  int sym_vjp = 0;  // 1: the symmetric VJP (FP32C/FP32 only)
   int launches = 0;  // symmetric kernels: least number of launches of the half ring (0 = automatic)
   int rescue = 1;  // FP32C force: recompute rows flagged by the error estimate in FP64
   // Device memory the caller lends for this call's partial sums, staged

@@ -126,8 +126,8 @@ def test_sym_accel_repeat_bitwise(nb):
 
 
 def test_sym_and_ordered_agree(nb, oracle_mod):
-    x, _, m = ics.plummer(40000, seed=8)
-    rows = np.random.default_rng(8).choice(40000, 400, replace=False)
+    x, _, m = ics.plummer(50000, seed=8)
+    rows = np.random.default_rng(8).choice(50000, 400, replace=False)
     ref = oracle_mod.accel_rows(x, m, rows, eps=0.01)
     nb.nbody_set_config(pairs=1)
     try:
@@ -135,13 +135,28 @@ def test_sym_and_ordered_agree(nb, oracle_mod):
     finally:
         nb.nbody_set_config()
     asym = sym_accel(nb, x, m, eps=0.01, precision="fp32c")
-    # the automatic choice at this size is the symmetric kernel
+    # the automatic choice at this size (FP32C: from 49152 particles) is the symmetric kernel
     aauto = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp32c").cpu().numpy()
     assert np.array_equal(aauto, asym)
     a64 = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp64").cpu().numpy()
     assert rel_err(asym, a64) <= TOL["fp32c"]
     assert rel_err(ao, a64) <= TOL["fp32c"]
     assert rel_err(asym[:, rows], ref) <= TOL["fp32c"]
+
+
+def test_sym_fp64_automatic_threshold(nb):
+    """The FP64 force runs the symmetric kernel from 16384 particles on (the
+    measured crossover) and the ordered one below: the automatic result equals
+    the forced form's bitwise on each side."""
+    for n, pairs in ((16384, 2), (16383, 1)):
+        x, _, m = ics.plummer(n, seed=10)
+        nb.nbody_set_config(pairs=pairs)
+        try:
+            forced = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp64").cpu().numpy()
+        finally:
+            nb.nbody_set_config()
+        auto = nb.nbody_accel(dev(x), dev(m), eps=0.01, precision="fp64").cpu().numpy()
+        assert np.array_equal(auto, forced), n
 
 
 def test_sym_kdk_steps_match_ordered(nb):
