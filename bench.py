@@ -642,8 +642,11 @@ def bench_grad(args, torch, nb):
     msa, _, _ = timed(lambda: nb.nbody_accel(tx0, tm, eps=eps, precision=args.precision, out=fa), 50, 5, torch)
     msa64, _, _ = timed(lambda: nb.nbody_accel(tx0, tm, eps=eps, precision="fp64", out=fa), 50, 5, torch)
     roof = roofline("vjp_kernel<%s> (48 flops per interaction)" % args.precision.upper(), pairs * FLOPS_VJP, msv,
-                    force=roofline("accel_kernel<%s>" % args.precision.upper(), pairs * FLOPS_PER_PAIR, msa),
-                    force_fp64=roofline("accel_kernel<FP64>", pairs * FLOPS_PER_PAIR, msa64, peak=FP64_PEAK_TFLOPS))
+                    force=roofline("accel_kernel<%s> (with its slice sum and the FP64 rescue)" % args.precision.upper(),
+                                   pairs * FLOPS_PER_PAIR, msa),
+                    force_fp64=roofline("sym64_kernel (FP64, symmetric from 16384 particles: staging, block "
+                                        "diagonal, half ring, slot sum)" if n >= 16384 else "accel_kernel<FP64>",
+                                        pairs * FLOPS_PER_PAIR, msa64, peak=FP64_PEAK_TFLOPS))
     cpu = None
     if not args.no_cpu:
         # the oracle's gradient (forward, then the discrete adjoint with two VJPs per step) of a
