@@ -515,10 +515,15 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wave_k
 // kicks = 0: publish only; 1: v += h a, x += dt v; 2: v += h a twice (closing
 // half-kick of the previous step, opening half-kick of this one, rounded
 // separately), x += dt v.  Then the pair record of the new position.
+// With rcnt (FP32C with the rescue): the per-system counts of flagged rows
+// start the step at zero.
 template <int MODE>
 __global__ void ens_publish_kernel(int64_t total, double* __restrict__ x, double* __restrict__ v,
                                    const double* __restrict__ a, const double* __restrict__ m,
-                                   JRec<MODE>* __restrict__ xrec, double h, double dt, int kicks) {
+                                   JRec<MODE>* __restrict__ xrec, double h, double dt, int kicks,
+                                   int* __restrict__ rcnt, int ncl) {
+  if (rcnt)
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) rcnt[c] = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     double xn[3];
 #pragma unroll
@@ -544,16 +549,16 @@ __global__ void ens_kick_kernel(int64_t total, double* __restrict__ v, const dou
     v[e] = fma(h, a[e], v[e]);
 }
 
-// With rescue (FP32C): the wave keeps each row's rounding-error estimate (one
-// share per block of 64 j, as the pair kernels do; see rescue.hip) and
-// recomputes the rows whose estimate is too large in FP64 itself, one row at a
-// time over the system's FP64 positions x and masses m, before it stores them.
+// With rcnt (FP32C with the rescue): the wave keeps each row's rounding-error
+// estimate (one share per block of 64 j, as the pair kernels do; see
+// rescue.hip) and appends the rows whose estimate is too large to its system's
+// list (rlist from the system's first particle on, rcnt[system] rows; one
+// atomic add per wave reserves the places), for ens_rescue_kernel.
 template <int MODE, bool EXCL>
 __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_waveforce_kernel(
     const int64_t* __restrict__ off, const double* __restrict__ epsv, const SItem* __restrict__ items,
     const int* __restrict__ wg_off, const int* __restrict__ wg_list, const JRec<MODE>* __restrict__ xrec,
-    double* __restrict__ a, int64_t total, double G, int rescue, const double* __restrict__ x,
-    const double* __restrict__ m) {
+    double* __restrict__ a, int64_t total, double G, int* __restrict__ rcnt, int* __restrict__ rlist) {
   using R = Real<MODE>;
   constexpr bool kNear = MODE == kFP32C;
   __shared__ JRec<MODE> slot[kWWaves][64];
@@ -643,7 +648,7 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
             pz = qz;
             r2min = r2nr;
           }
-          if (rescue) eacc = est_add(eacc, px, py, pz, xinf, r2min);
+          if (rcnt) eacc = est_add(eacc, px, py, pz, xinf, r2min);
         }
         fold(hx, lx, px);
         fold(hy, ly, py);
@@ -666,21 +671,111 @@ __global__ __launch_bounds__(kSBlock, wave_kernel_waves<MODE>()) void ens_wavefo
       a[i] = ax;
       a[total + i] = ay;
       a[2 * total + i] = az;
-      if (kNear && rescue) flag = sqrt((double)eacc) * (kRescueScale * fabs(G)) > sqrt(ax * ax + ay * ay + az * az);
+      if (kNear && rcnt) flag = sqrt((double)eacc) * (kRescueScale * fabs(G)) > sqrt(ax * ax + ay * ay + az * az);
     }
     if constexpr (kNear) {
-      // the flagged rows, one at a time by the whole wave; the owner lane
-      // overwrites its row
-      for (unsigned long long mask = __ballot(flag); mask; mask &= mask - 1) {
-        const int k = __ffsll((long long)mask) - 1;
-        const int64_t i = o + it.i0 + k;
-        double sx, sy, sz;
-        wave_row_fp64(x, m, total, o, nc, i, (double)eps * eps, EXCL, sx, sy, sz);
-        if (lane == k) {
-          a[i] = G * sx;
-          a[total + i] = G * sy;
-          a[2 * total + i] = G * sz;
+      const unsigned long long mask = __ballot(flag);
+      if (mask) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&rcnt[it.sys], __popcll(mask));
+        base = __shfl(base, 0, 64);
+        if (flag) rlist[o + base + __popcll(mask & ((1ull << lane) - 1ull))] = ii;
+      }
+    }
+  }
+}
+
+// The FP64 rescue of the rows the force kernel flagged: kRSplit workgroups
+// per system (kRWaves waves each) share its listed rows, kRRow rows per wave
+// and pass, workgroup p taking the passes p, p + kRSplit, ...; each stages
+// the system's FP64 positions and masses in LDS (kRStage records at a time; a
+// system that fits is staged once) unless it has no rows, and lane l of a wave
+// takes j = l, l + 64, ... of each stage; the lane sums are added by a
+// butterfly, so the result does not depend on the list's order or the grid.
+constexpr int kRWaves = 8;
+constexpr int kRRow = 2;
+constexpr int kRStage = 2048;
+constexpr int kRSplit = 8;
+template <bool EXCL>
+__global__ __launch_bounds__(64 * kRWaves) void ens_rescue_kernel(const int64_t* __restrict__ off,
+                                                                  const double* __restrict__ epsv, int64_t total,
+                                                                  const double* __restrict__ x,
+                                                                  const double* __restrict__ m, double G,
+                                                                  const int* __restrict__ rcnt,
+                                                                  const int* __restrict__ rlist,
+                                                                  double* __restrict__ a) {
+  __shared__ double sj[4][kRStage];
+  const int c = blockIdx.x;
+  const int nf = rcnt[c];
+  constexpr int kPass = kRWaves * kRRow;
+  if ((int)blockIdx.y * kPass >= nf) return;
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  const int64_t o = off[c];
+  const int nc = (int)(off[c + 1] - o);
+  const double e2 = epsv[c] * epsv[c];
+  auto stage = [&](int c0) {
+    const int cn = min(kRStage, nc - c0);
+    for (int j = t; j < cn; j += 64 * kRWaves) {
+      sj[0][j] = x[o + c0 + j];
+      sj[1][j] = x[total + o + c0 + j];
+      sj[2][j] = x[2 * total + o + c0 + j];
+      sj[3][j] = m[o + c0 + j];
+    }
+  };
+  const bool once = nc <= kRStage;
+  if (once) {
+    stage(0);
+    __syncthreads();
+  }
+  for (int g0 = blockIdx.y * kPass; g0 < nf; g0 += kRSplit * kPass) {
+    int li[kRRow];
+    double xi[kRRow], yi[kRRow], zi[kRRow], sx[kRRow], sy[kRRow], sz[kRRow];
+#pragma unroll
+    for (int k = 0; k < kRRow; ++k) {
+      const int r = g0 + wave * kRRow + k;
+      li[k] = r < nf ? rlist[o + r] : -1;
+      const int64_t i = o + (li[k] < 0 ? 0 : li[k]);
+      xi[k] = x[i];
+      yi[k] = x[total + i];
+      zi[k] = x[2 * total + i];
+      sx[k] = sy[k] = sz[k] = 0.0;
+    }
+    for (int c0 = 0; c0 < nc; c0 += kRStage) {
+      if (!once) {
+        __syncthreads();  // the previous stage has been read
+        stage(c0);
+        __syncthreads();
+      }
+      if (li[0] < 0) continue;
+      const int cn = min(kRStage, nc - c0);
+#pragma unroll 2
+      for (int j = lane; j < cn; j += 64) {
+        const double xj = sj[0][j], yj = sj[1][j], zj = sj[2][j], mj = sj[3][j];
+#pragma unroll
+        for (int k = 0; k < kRRow; ++k) {
+          const double dx = xj - xi[k], dy = yj - yi[k], dz = zj - zi[k];
+          const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          const double rr = rsqrt64(r2);
+          double sc = (mj * rr) * (rr * rr);
+          if (EXCL && c0 + j == li[k]) sc = 0.0;
+          sx[k] = fma(sc, dx, sx[k]);
+          sy[k] = fma(sc, dy, sy[k]);
+          sz[k] = fma(sc, dz, sz[k]);
         }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRRow; ++k) {
+      for (int w = 32; w > 0; w >>= 1) {
+        sx[k] += __shfl_xor(sx[k], w, 64);
+        sy[k] += __shfl_xor(sy[k], w, 64);
+        sz[k] += __shfl_xor(sz[k], w, 64);
+      }
+      if (lane == 0 && li[k] >= 0) {
+        const int64_t i = o + li[k];
+        a[i] = G * sx[k];
+        a[total + i] = G * sy[k];
+        a[2 * total + i] = G * sz[k];
       }
     }
   }
@@ -707,6 +802,8 @@ struct SPlan {
   int2* d_ws_sys = nullptr;  // wave items: (system, items of it held by the workgroup)
   void* d_xrec = nullptr;
   int* d_cnt = nullptr;
+  int* d_rcnt = nullptr;   // per-step wave items, FP32C: flagged rows per system (ncl)
+  int* d_rlist = nullptr;  // and their lists (total, each system's from its first particle on)
 };
 
 std::mutex g_splan_mu;
@@ -714,7 +811,8 @@ std::vector<SPlan*> g_splans;
 
 void free_splan(SPlan* p) {
   for (void* q : {(void*)p->d_off, (void*)p->d_eps, (void*)p->d_nparts, (void*)p->d_items, (void*)p->d_wg_off,
-                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt})
+                  (void*)p->d_wg_list, (void*)p->d_ws_off, (void*)p->d_ws_sys, p->d_xrec, (void*)p->d_cnt,
+                  (void*)p->d_rcnt, (void*)p->d_rlist})
     if (q) (void)hipFree(q);
   delete p;
 }
@@ -921,7 +1019,10 @@ int build_wplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
             supload(&p->d_items, items) && supload(&p->d_wg_off, wg_off) && supload(&p->d_wg_list, wg_list) &&
             supload(&p->d_ws_off, ws_off) && supload(&p->d_ws_sys, ws_sys) &&
             hipMalloc(&p->d_xrec, 2 * (size_t)std::max<int64_t>(1, p->total) * sizeof(JRec<MODE>)) == hipSuccess &&
-            hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess;
+            hipMalloc(&p->d_cnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess &&
+            (MODE != kFP32C ||
+             (hipMalloc(&p->d_rcnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess &&
+              hipMalloc(&p->d_rlist, sizeof(int) * (size_t)std::max<int64_t>(1, p->total)) == hipSuccess));
   if (!ok) {
     (void)hipGetLastError();
     free_splan(p);
@@ -979,25 +1080,37 @@ int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double*
   auto* rec = static_cast<JRec<MODE>*>(p->d_xrec);
   const double h = 0.5 * dt;
   const unsigned ew = (unsigned)std::min<int64_t>((p->total + 255) / 256, 4096);
-  const int rs = rescue && MODE == kFP32C ? 1 : 0;
+  // FP32C with the rescue: the force kernel lists each system's flagged rows
+  // (counts cleared by the publish kernel) and ens_rescue_kernel recomputes them
+  int* rcnt = rescue && MODE == kFP32C ? p->d_rcnt : nullptr;
+  int* rlist = rcnt ? p->d_rlist : nullptr;
   auto force = [&]() -> int {
     if (excl)
       ens_waveforce_kernel<MODE, true><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
-                                                                  p->d_wg_list, rec, a, p->total, G, rs, x, m);
+                                                                  p->d_wg_list, rec, a, p->total, G, rcnt, rlist);
     else
       ens_waveforce_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
-                                                                   p->d_wg_list, rec, a, p->total, G, rs, x, m);
+                                                                   p->d_wg_list, rec, a, p->total, G, rcnt, rlist);
     NB_LAUNCH_CHECK("ens_waveforce_kernel");
+    if (rcnt) {
+      if (excl)
+        ens_rescue_kernel<true><<<dim3(p->ncl, kRSplit), 64 * kRWaves, 0, s>>>(p->d_off, p->d_eps, p->total, x, m, G,
+                                                                              rcnt, rlist, a);
+      else
+        ens_rescue_kernel<false><<<dim3(p->ncl, kRSplit), 64 * kRWaves, 0, s>>>(p->d_off, p->d_eps, p->total, x, m, G,
+                                                                               rcnt, rlist, a);
+      NB_LAUNCH_CHECK("ens_rescue_kernel");
+    }
     return NBODY_OK;
   };
   int st;
   if (!acc_valid) {
-    ens_publish_kernel<MODE><<<ew, 256, 0, s>>>(p->total, x, v, a, m, rec, h, dt, 0);
+    ens_publish_kernel<MODE><<<ew, 256, 0, s>>>(p->total, x, v, a, m, rec, h, dt, 0, rcnt, p->ncl);
     NB_LAUNCH_CHECK("ens_publish_kernel");
     if ((st = force())) return st;
   }
   for (int64_t k = 0; k < nsteps; ++k) {
-    ens_publish_kernel<MODE><<<ew, 256, 0, s>>>(p->total, x, v, a, m, rec, h, dt, k == 0 ? 1 : 2);
+    ens_publish_kernel<MODE><<<ew, 256, 0, s>>>(p->total, x, v, a, m, rec, h, dt, k == 0 ? 1 : 2, rcnt, p->ncl);
     NB_LAUNCH_CHECK("ens_publish_kernel");
     if ((st = force())) return st;
   }

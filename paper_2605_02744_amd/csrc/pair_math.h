@@ -147,33 +147,4 @@ __device__ __forceinline__ float near_rc2(double xa, double ya, double za, doubl
   return dc * dc + (float)(eps * eps);
 }
 
-// FP64 row of the force for one wave: a_i / G = sum_j m_j d / (|d|^2 + eps^2)^(3/2)
-// over j in [o, o + nc) (positions x in SoA with component stride total), lane
-// l taking j = o + l, o + l + 64, ...; the lane sums are added by a butterfly,
-// so every lane returns the same sums, in a fixed order.  i is the row (left
-// out of its own sum when excl).
-__device__ inline void wave_row_fp64(const double* __restrict__ x, const double* __restrict__ m, int64_t total,
-                                     int64_t o, int nc, int64_t i, double e2, bool excl, double& sx, double& sy,
-                                     double& sz) {
-  const int lane = threadIdx.x & 63;
-  const double xi = x[i], yi = x[total + i], zi = x[2 * total + i];
-  sx = sy = sz = 0.0;
-#pragma unroll 2
-  for (int64_t j = o + lane; j < o + nc; j += 64) {
-    const double dx = x[j] - xi, dy = x[total + j] - yi, dz = x[2 * total + j] - zi;
-    const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-    const double rr = rsqrt64(r2);
-    double sc = (m[j] * rr) * (rr * rr);
-    if (excl && j == i) sc = 0.0;
-    sx = fma(sc, dx, sx);
-    sy = fma(sc, dy, sy);
-    sz = fma(sc, dz, sz);
-  }
-  for (int w = 32; w > 0; w >>= 1) {
-    sx += __shfl_xor(sx, w, 64);
-    sy += __shfl_xor(sy, w, 64);
-    sz += __shfl_xor(sz, w, 64);
-  }
-}
-
 }  // namespace nb
