@@ -41,8 +41,8 @@
 // kernel recomputes them in FP64.  The count of flagged rows is cleared by the
 // first kernel of the evaluation (its block 0, thread 0), so that the flag
 // kernel starts from zero without a launch of its own.  The batched wave items
-// (ensemble_stream.hip) flag and recompute their rows inside the force kernel,
-// where each wave holds whole rows.
+// (ensemble_stream.hip) flag their rows in the force kernel, where each wave
+// holds whole rows, into per-system lists that their own rescue kernel reads.
 #include "pair_math.h"
 
 namespace nb {
