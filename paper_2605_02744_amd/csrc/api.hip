@@ -363,8 +363,13 @@ int nbody_accel_noalloc(int64_t n, const double* x, const double* m, double* a, 
   cfg.scratch = scr;
   cfg.scratch_bytes = kNoAllocBytes;
   if (!cfg.sym) {
-    // the ordered kernels keep 3 n FP64 partial sums per slice of the j-range
-    const int64_t most = std::max<int64_t>(1, (int64_t)(kNoAllocBytes / (sizeof(double) * 3 * (size_t)n)));
+    // the ordered kernels keep 3 n FP64 partial sums per slice of the j-range and,
+    // with the FP32C rescue, n FP32 estimate shares per slice and the flagged-row
+    // list (n + 64 ints, after 256-byte alignment of the shares)
+    const bool resc = p->precision == NBODY_FP32C && cfg.rescue;
+    const size_t per = sizeof(double) * 3 * (size_t)n + (resc ? sizeof(float) * (size_t)n : 0);
+    const size_t fixed = resc ? sizeof(int) * ((size_t)n + 64) + 256 : 0;
+    const int64_t most = std::max<int64_t>(1, (int64_t)((kNoAllocBytes - fixed) / per));
     cfg.split = (int)std::min<int64_t>(cfg.split, most);
   }
   return launch_accel(n, x, m, a, p->G, p->eps, p->precision, (p->flags & NBODY_EXCLUDE_SELF) != 0, cfg,

@@ -510,15 +510,17 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const bool near = precision == kFP32C;
   const bool rescue = near && cfg.rescue;
   int nb, L, D;
-  // per particle: FP32 j-side slot sums per distance, FP64 i-side sums (and, for the
-  // rescue, an FP32 error estimate) per workgroup, FP64 block-diagonal sums, two staged
-  // float4 records and, for the rescue, four FP32 estimates and a list entry
+  // per particle: FP32 j-side slot sums (and, for the rescue, an FP32 error estimate)
+  // per distance, FP64 i-side sums (and an FP32 estimate) per workgroup, FP64
+  // block-diagonal sums, two staged float4 records and, for the rescue, two FP32
+  // estimates and a list entry; the list's count takes 64 more ints
   const int est_fixed = rescue ? 2 * (int)sizeof(float) + (int)sizeof(int) : 0;
+  const size_t count_bytes = rescue ? 64 * sizeof(int) : 0;
   const int est_part = rescue ? (int)sizeof(float) : 0;
   const int est_slot = rescue ? (int)sizeof(float) : 0;
   sym_plan(n, cfg.launches, 3 * sizeof(float) + est_slot, 3 * sizeof(float), 3 * sizeof(double) + est_part,
-           3 * sizeof(double) + 2 * sizeof(float4) + est_fixed, cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L,
-           &D);
+           3 * sizeof(double) + 2 * sizeof(float4) + est_fixed,
+           cfg.scratch ? cfg.scratch_bytes - count_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -531,7 +533,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const size_t pe_bytes = rescue ? sizeof(float) * (size_t)npad * nparts : 0;
   const size_t pw_bytes = rescue ? sizeof(float) * (size_t)npad * D : 0;
   const size_t eo_bytes = rescue ? sizeof(float) * 2 * (size_t)npad : 0;  // eo [npad], ed [npad]
-  const size_t list_bytes = rescue ? sizeof(int) * (size_t)npad : 0;     // the count, then the list
+  const size_t list_bytes = rescue ? sizeof(int) * (size_t)npad + count_bytes : 0;  // the count, then the list
   char* ws = static_cast<char*>(pair_scratch(
       cfg, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes + pe_bytes + pw_bytes + eo_bytes + list_bytes, &st));
   if (!ws) return st;
