@@ -644,8 +644,8 @@ def bench_grad(args, torch, nb):
     roof = roofline("vjp_kernel<%s> (48 flops per interaction)" % args.precision.upper(), pairs * FLOPS_VJP, msv,
                     force=roofline("accel_kernel<%s> (with its slice sum and the FP64 rescue)" % args.precision.upper(),
                                    pairs * FLOPS_PER_PAIR, msa),
-                    force_fp64=roofline("sym64_kernel (FP64, symmetric from 16384 particles: staging, block "
-                                        "diagonal, half ring, slot sum)" if n >= 16384 else "accel_kernel<FP64>",
+                    force_fp64=roofline("sym64_kernel (FP64, symmetric from 12288 particles: staging, block "
+                                        "diagonal, half ring, slot sum)" if n >= 12288 else "accel_kernel<FP64>",
                                         pairs * FLOPS_PER_PAIR, msa64, peak=FP64_PEAK_TFLOPS))
     cpu = None
     if not args.no_cpu:

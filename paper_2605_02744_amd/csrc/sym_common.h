@@ -18,7 +18,12 @@ constexpr int kSR = 16;             // lanes per row = records per sub-block
 constexpr int kSTiles = kSI / kST;  // tiles per J-block
 constexpr int kSW = kSL / 64;       // waves per workgroup
 constexpr int kDiagG = 4;          // lane groups of the block-diagonal kernels, each over kSI / kDiagG of the j
-static_assert(kSI % (kDiagG * kFold) == 0, "each diagonal lane group takes whole folds");
+// Workgroups per block of the block-diagonal kernels (each over a slice of the
+// j, the slices summed by the slot-sum kernel): several where the blocks are
+// too few to fill the chip, one where the slices' extra sums would only cost
+// memory.
+inline int diag_slices(int nb) { return nb < 256 ? 4 : 1; }
+static_assert(kSI % (4 * kDiagG * 16) == 0, "each diagonal lane group takes whole runs of 16 j");
 
 // v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
 template <int K>
@@ -101,23 +106,32 @@ using lds_ptr = __attribute__((address_space(3))) void*;
 // With eo (FP32C force only; the thread of component 0 does it): the error
 // estimate of the rescue in eo[npad], the far side's shares pw of the chunk's
 // distances and the workgroups' i-side shares pe added to what earlier chunks
-// left, or to the block-diagonal share ed in the first chunk.
+// left, or to the block-diagonal shares ed in the first chunk.  The
+// block-diagonal sums come in pds slices (pd[pds][C][npad], ed[pds][npad]),
+// added in slice order.
 template <int C, typename S>
 __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, int d_lo, int D, int nparts,
                                   const S* __restrict__ pj, const double* __restrict__ pi,
                                   const double* __restrict__ pd, double* __restrict__ out, double* __restrict__ outm,
                                   double G, int first, int last, const float* __restrict__ pe = nullptr,
                                   const float* __restrict__ pw = nullptr, const float* __restrict__ ed = nullptr,
-                                  float* __restrict__ eo = nullptr) {
+                                  float* __restrict__ eo = nullptr, int pds = 1) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (p >= n) return;
   double* o = c < 3 ? out + (size_t)c * n + p : outm + p;
   const int J = p / kSI;
-  double acc = first ? pd[(size_t)c * npad + p] : *o;
+  double acc = first ? 0.0 : *o;
+  if (first)
+    for (int k = 0; k < pds; ++k) acc += pd[((size_t)k * C + c) * npad + p];
   const bool est = eo && c == 0;
   float ea = 0.f;
-  if (est) ea = first ? ed[p] : eo[p];
+  if (est) {
+    if (first)
+      for (int k = 0; k < pds; ++k) ea += ed[(size_t)k * npad + p];
+    else
+      ea = eo[p];
+  }
   const int send = min(D, dmax - d_lo + 1);  // slots of this chunk within the ring
   // the last slot of the ring is dropped where its block pair was not evaluated
   const bool drop_last = half && d_lo + send - 1 == dmax && ((J - dmax) % nb + nb) % nb >= nb / 2;

@@ -205,8 +205,9 @@ __global__ __launch_bounds__(kSL, 6) void sym64_kernel(S64Args A) {
 }
 
 // The block with itself (distance 0), ordered form, i-side only, own pair
-// masked when asked.  kDiagG groups of kSL lanes each take kSI / kDiagG of the
-// j; group 0 adds the groups' hi + lo in group order into pd[3][npad].
+// masked when asked.  The gridDim.y workgroups of a block each take a slice of
+// its j, and their kDiagG groups of kSL lanes each a part of the slice; group 0
+// adds the groups' hi + lo in group order into pd[slice][3][npad].
 template <bool EXCL>
 __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, double* __restrict__ pd) {
   __shared__ double4 s_rec[kSI];
@@ -214,6 +215,8 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, doub
   const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
   const int g = blockIdx.x;
   const double e2 = A.eps * A.eps;
+  const int span = kSI / ((int)gridDim.y * kDiagG), fl = span < kFold ? span : kFold;
+  const int f0 = ((int)blockIdx.y * kDiagG + grp) * span;
   DSet s;
   load_dset(A, g, t, s);
   for (int k = threadIdx.x; k < kSI; k += kSL * kDiagG) s_rec[k] = A.rec[(size_t)g * kSI + k];
@@ -221,10 +224,10 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, doub
   double hx[2] = {0.0, 0.0}, hy[2] = {0.0, 0.0}, hz[2] = {0.0, 0.0};
   double lx[2] = {0.0, 0.0}, ly[2] = {0.0, 0.0}, lz[2] = {0.0, 0.0};
 #pragma unroll 1
-  for (int f = grp * (kSI / kDiagG); f < (grp + 1) * (kSI / kDiagG); f += kFold) {
+  for (int f = f0; f < f0 + span; f += fl) {
     double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};
 #pragma unroll 8
-    for (int j = f; j < f + kFold; ++j) {
+    for (int j = f; j < f + fl; ++j) {
       const double4 r = s_rec[j];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -259,6 +262,7 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, doub
   for (int u = 0; u < 2; ++u) {
     const int k = u * kSL + t;
     const size_t i = (size_t)g * kSI + k;
+    double* const pds = pd + (size_t)blockIdx.y * 3 * A.npad;
     double vx = hx[u] + lx[u], vy = hy[u] + ly[u], vz = hz[u] + lz[u];
 #pragma unroll
     for (int q = 0; q < kDiagG - 1; ++q) {
@@ -266,9 +270,9 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, doub
       vy += s_part[q][1][k];
       vz += s_part[q][2][k];
     }
-    pd[i] = vx;
-    pd[A.npad + i] = vy;
-    pd[2 * (size_t)A.npad + i] = vz;
+    pds[i] = vx;
+    pds[A.npad + i] = vy;
+    pds[2 * (size_t)A.npad + i] = vz;
   }
 }
 
@@ -279,9 +283,11 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   if (n == 0) return NBODY_OK;
   int nb, L, D;
   // per particle: FP64 j-side slot sums per distance, FP64 i-side sums per workgroup,
-  // FP64 block-diagonal sums and one staged double4 record
-  sym_plan(n, cfg.launches, 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double) + sizeof(double4),
-           cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
+  // FP64 block-diagonal sums (in pds slices) and one staged double4 record
+  const int pds = diag_slices((int)((n + kSI - 1) / kSI));
+  sym_plan(n, cfg.launches, 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double),
+           pds * 3 * (int)sizeof(double) + (int)sizeof(double4), cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L,
+           &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
@@ -289,7 +295,7 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(double) * 3 * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
-  const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
+  const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad * pds;
   const size_t rec_bytes = sizeof(double4) * (size_t)npad;
   char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + rec_bytes, &st));
   if (!ws) return st;
@@ -303,13 +309,14 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   A.rec = rec;
   sym64_stage_kernel<<<(unsigned)((npad + 255) / 256), 256, 0, s>>>(A, rec);
   NB_LAUNCH_CHECK("sym64_stage_kernel");
-  if (excl) sym64_diag_kernel<true><<<nb, kSL * kDiagG, 0, s>>>(A, pd);
-  else sym64_diag_kernel<false><<<nb, kSL * kDiagG, 0, s>>>(A, pd);
+  const dim3 dg((unsigned)nb, (unsigned)pds);
+  if (excl) sym64_diag_kernel<true><<<dg, kSL * kDiagG, 0, s>>>(A, pd);
+  else sym64_diag_kernel<false><<<dg, kSL * kDiagG, 0, s>>>(A, pd);
   NB_LAUNCH_CHECK("sym64_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {
     sym_reduce_kernel<3, double><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a,
-                                                    nullptr, G, 1, 1);
+                                                    nullptr, G, 1, 1, nullptr, nullptr, nullptr, nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
   }
@@ -319,7 +326,8 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
     sym64_kernel<<<(unsigned)nb * (unsigned)nparts, kSL, 0, s>>>(A);
     NB_LAUNCH_CHECK("sym64_kernel");
     sym_reduce_kernel<3, double><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi,
-                                                    pd, a, nullptr, G, c == 0, c == nchunks - 1);
+                                                    pd, a, nullptr, G, c == 0, c == nchunks - 1, nullptr, nullptr, nullptr,
+                                                    nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   }
   return NBODY_OK;

@@ -383,9 +383,10 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
 // The block with itself (distance 0): the i-side of all ordered pairs inside
 // I-block g, in the ordered form (the LDS record broadcast to every lane), with
 // the own pair masked when asked and the near-field repair of the force kernel.
-// kDiagG groups of kSL lanes each take kSI / kDiagG of the j (so that the
-// launch has several waves per SIMD); group 0 adds the groups' hi + lo in
-// group order and writes the sums into pd[3][npad].
+// The gridDim.y workgroups of a block each take a slice of its j, and their
+// kDiagG groups of kSL lanes each a part of the slice (so that the launch has
+// several waves per SIMD); group 0 adds the groups' hi + lo in group order and
+// writes the slice's sums into pd[slice][3][npad] (ed[slice][npad]).
 template <bool NEAR, bool EXCL>
 __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double* __restrict__ pd,
                                                                 float* __restrict__ ed) {
@@ -396,6 +397,9 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
   const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
   const int g = blockIdx.x;
   const float e2 = (float)(A.eps * A.eps);
+  // this lane group's j: a run of span records, folded fl at a time
+  const int span = kSI / ((int)gridDim.y * kDiagG), fl = span < kFold ? span : kFold;
+  const int f0 = ((int)blockIdx.y * kDiagG + grp) * span;
   ISet s;
   float thr[2];
   load_iset<false>(A, g, t, s, thr);
@@ -410,11 +414,11 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
 #pragma unroll
   for (int u = 0; u < 2; ++u) rc[u] = s_lo[u * kSL + t].w;
 #pragma unroll 1
-  for (int f = grp * (kSI / kDiagG); f < (grp + 1) * (kSI / kDiagG); f += kFold) {
+  for (int f = f0; f < f0 + span; f += fl) {
     float px[2] = {0.f, 0.f}, py[2] = {0.f, 0.f}, pz[2] = {0.f, 0.f};
     float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 16
-    for (int j = f; j < f + kFold; ++j) {
+    for (int j = f; j < f + fl; ++j) {
       const float4 r = s_hi[j];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -432,7 +436,7 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
     if constexpr (NEAR) {
       if (r2min[0] < thr[0] || r2min[1] < thr[1]) {
         float r2nr[2] = {3.0e38f, 3.0e38f};
-        for (int j = f; j < f + kFold; ++j) {
+        for (int j = f; j < f + fl; ++j) {
           const float4 rh = s_hi[j];
           const float4 lo = s_lo[j];
 #pragma unroll
@@ -483,6 +487,7 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
   for (int u = 0; u < 2; ++u) {
     const int k = u * kSL + t;
     const size_t i = (size_t)g * kSI + k;
+    double* const pds = pd + (size_t)blockIdx.y * 3 * A.npad;
     double vx = (double)hx[u] + (double)lx[u], vy = (double)hy[u] + (double)ly[u], vz = (double)hz[u] + (double)lz[u];
     float e = ea[u];
 #pragma unroll
@@ -492,10 +497,10 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
       vz += s_part[q][2][k];
       e += s_epart[q][k];
     }
-    pd[i] = vx;
-    pd[A.npad + i] = vy;
-    pd[2 * (size_t)A.npad + i] = vz;
-    if (NEAR && ed) ed[i] = e;
+    pds[i] = vx;
+    pds[A.npad + i] = vy;
+    pds[2 * (size_t)A.npad + i] = vz;
+    if (NEAR && ed) ed[(size_t)blockIdx.y * A.npad + i] = e;
   }
 }
 
@@ -518,8 +523,11 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const size_t count_bytes = rescue ? 64 * sizeof(int) : 0;
   const int est_part = rescue ? (int)sizeof(float) : 0;
   const int est_slot = rescue ? (int)sizeof(float) : 0;
+  // the block-diagonal sums (and estimate shares) come in pds slices
+  const int pds = diag_slices((int)((n + kSI - 1) / kSI));
   sym_plan(n, cfg.launches, 3 * sizeof(float) + est_slot, 3 * sizeof(float), 3 * sizeof(double) + est_part,
-           3 * sizeof(double) + 2 * sizeof(float4) + est_fixed,
+           pds * (3 * (int)sizeof(double) + (rescue ? (int)sizeof(float) : 0)) + 2 * sizeof(float4) + est_fixed -
+               (rescue ? (int)sizeof(float) : 0),
            cfg.scratch ? cfg.scratch_bytes - count_bytes : SIZE_MAX, &nb, &L, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
@@ -528,11 +536,11 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(float) * 3 * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
-  const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad;
+  const size_t pd_bytes = sizeof(double) * 3 * (size_t)npad * pds;
   const size_t rec_bytes = sizeof(float4) * (size_t)npad;
   const size_t pe_bytes = rescue ? sizeof(float) * (size_t)npad * nparts : 0;
   const size_t pw_bytes = rescue ? sizeof(float) * (size_t)npad * D : 0;
-  const size_t eo_bytes = rescue ? sizeof(float) * 2 * (size_t)npad : 0;  // eo [npad], ed [npad]
+  const size_t eo_bytes = rescue ? sizeof(float) * (1 + pds) * (size_t)npad : 0;  // eo [npad], ed [pds][npad]
   const size_t list_bytes = rescue ? sizeof(int) * (size_t)npad + count_bytes : 0;  // the count, then the list
   char* ws = static_cast<char*>(pair_scratch(
       cfg, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes + pe_bytes + pw_bytes + eo_bytes + list_bytes, &st));
@@ -558,18 +566,19 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   if (near) sym_stage_kernel<true><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
   else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
   NB_LAUNCH_CHECK("sym_stage_kernel");
+  const dim3 dg((unsigned)nb, (unsigned)pds);
   if (near) {
-    if (excl) sym_diag_kernel<true, true><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
-    else sym_diag_kernel<true, false><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
+    if (excl) sym_diag_kernel<true, true><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
+    else sym_diag_kernel<true, false><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
   } else {
-    if (excl) sym_diag_kernel<false, true><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
-    else sym_diag_kernel<false, false><<<nb, kSL * kDiagG, 0, s>>>(A, pd, ed);
+    if (excl) sym_diag_kernel<false, true><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
+    else sym_diag_kernel<false, false><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
   }
   NB_LAUNCH_CHECK("sym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {
     sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, nullptr, G,
-                                            1, 1, A.pe, A.pw, ed, eo);
+                                            1, 1, A.pe, A.pw, ed, eo, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   } else {
     const int nchunks = (dmax + D - 1) / D;
@@ -581,7 +590,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
       else sym_accel_kernel<false, false><<<grid, kSL, 0, s>>>(A);
       NB_LAUNCH_CHECK("sym_accel_kernel");
       sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
-                                              a, nullptr, G, c == 0, c == nchunks - 1, A.pe, A.pw, ed, eo);
+                                              a, nullptr, G, c == 0, c == nchunks - 1, A.pe, A.pw, ed, eo, pds);
       NB_LAUNCH_CHECK("sym_reduce_kernel");
     }
   }
