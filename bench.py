@@ -641,11 +641,13 @@ def bench_grad(args, torch, nb):
     fa = torch.empty_like(tx0)
     msa, _, _ = timed(lambda: nb.nbody_accel(tx0, tm, eps=eps, precision=args.precision, out=fa), 50, 5, torch)
     msa64, _, _ = timed(lambda: nb.nbody_accel(tx0, tm, eps=eps, precision="fp64", out=fa), 50, 5, torch)
-    roof = roofline("vjp_kernel<%s> (48 flops per interaction)" % args.precision.upper(), pairs * FLOPS_VJP, msv,
+    vk = "vsym_kernel<%s> (symmetric from 12288 particles: staging, block diagonal, half ring, slot sums; " \
+         "48 flops per interaction)" if n >= 12288 and args.precision != "fp64" else "vjp_kernel<%s> (48 flops per interaction)"
+    roof = roofline(vk % args.precision.upper(), pairs * FLOPS_VJP, msv,
                     force=roofline("accel_kernel<%s> (with its slice sum and the FP64 rescue)" % args.precision.upper(),
                                    pairs * FLOPS_PER_PAIR, msa),
-                    force_fp64=roofline("sym64_kernel (FP64, symmetric from 12288 particles: staging, block "
-                                        "diagonal, half ring, slot sum)" if n >= 12288 else "accel_kernel<FP64>",
+                    force_fp64=roofline("sym64_kernel (FP64, symmetric from 8192 particles: staging, block "
+                                        "diagonal, half ring, slot sum)" if n >= 8192 else "accel_kernel<FP64>",
                                         pairs * FLOPS_PER_PAIR, msa64, peak=FP64_PEAK_TFLOPS))
     cpu = None
     if not args.no_cpu:

@@ -85,7 +85,7 @@ typedef struct nbody_params {
 
 /* Accelerations a (3*n) of particles at x (3*n) with masses m (n).
  * Eq. (1) of Sec. 2.1 divided by m_i, softened as in App. A.
- * From 49152 particles on in FP32C and FP32, from 12288 in FP64 (or as
+ * From 49152 particles on in FP32C and FP32, from 8192 in FP64 (or as
  * nbody_config.pairs says), each unordered pair is evaluated once and applied
  * to both particles, with sums in a fixed order; this uses a workspace of up
  * to about 2 GiB (staged records and per-distance sums) and several launches
@@ -315,8 +315,8 @@ typedef struct nbody_config {
                       steps and (FP32C/FP32 only) of nbody_accel_vjp and the
                       adjoint sweep: 0 = automatic (the tuned choice for
                       (n, precision), else symmetric from 49152 particles
-                      on in FP32C/FP32 and from 12288 in FP64 for the force,
-                      from 32768 for the VJP),
+                      on in FP32C/FP32 and from 8192 in FP64 for the force,
+                      from 12288 for the VJP),
                       1 = ordered: every ordered pair evaluated for its i;
                       2 = symmetric: every unordered pair evaluated once and
                       applied to both particles (a_j gets the opposite of i's

@@ -45,10 +45,10 @@ constexpr int kFold = 64;          // j-terms summed in plain FP32/FP64 before a
 constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
 // Sizes from which the symmetric kernels are the default (measured crossovers
 // against the ordered kernels): the FP32C/FP32 force from 49152 particles, the
-// FP64 force from 12288, the FP32C/FP32 VJP from 32768.
+// FP64 force from 8192, the FP32C/FP32 VJP from 12288.
 constexpr int64_t kSymMinN = 49152;
-constexpr int64_t kSymMinN64 = 12288;
-constexpr int64_t kSymMinNVjp = 32768;
+constexpr int64_t kSymMinN64 = 8192;
+constexpr int64_t kSymMinNVjp = 12288;
 
 // Per-call configuration of the all-pairs kernels.
 struct PairConfig {

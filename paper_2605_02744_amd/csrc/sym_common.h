@@ -67,7 +67,7 @@ struct SymArgs {
   int dmax;         // largest ring distance
   int half;         // nb even: distance dmax only for g < nb / 2
   int d_lo;         // first distance of this chunk
-  int L;            // distances per workgroup
+  int T;            // tiles per workgroup (kSTiles per ring distance)
   int nparts;       // workgroups per I-block in this chunk
   double eps;
   float fx;         // repair-radius factor max(kNearX, kNearN n^-1/3)
@@ -147,7 +147,18 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
     acc += (double)v3;
   }
   for (; s < sn; ++s) acc += (double)q[s * stride];
-  for (int k = 0; k < nparts; ++k) acc += pi[((size_t)k * C + c) * npad + p];
+  const double* qi = pi + (size_t)c * npad + p;
+  const size_t pstride = (size_t)C * npad;
+  int k = 0;
+  for (; k + 4 <= nparts; k += 4) {
+    const double v0 = qi[k * pstride], v1 = qi[(k + 1) * pstride], v2 = qi[(k + 2) * pstride],
+                 v3 = qi[(k + 3) * pstride];
+    acc += v0;
+    acc += v1;
+    acc += v2;
+    acc += v3;
+  }
+  for (; k < nparts; ++k) acc += qi[k * pstride];
   if (est) {
     for (int d = 0; d < sn; ++d) ea += pw[(size_t)d * npad + p];
     for (int k = 0; k < nparts; ++k) ea += pe[(size_t)k * npad + p];
@@ -162,31 +173,40 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
 // sums (sum_bytes of them the sums themselves, the rest error estimates) per
 // particle and distance, part_bytes of i-side sums per particle and workgroup
 // of a block, and fixed_bytes per particle of staged records and
-// block-diagonal sums: distances per workgroup (L) and per launch (D), the
+// block-diagonal sums: tiles per workgroup (T: whole distances of kSTiles
+// tiles, or for small rings a part of one) and distances per launch (D), the
 // sum slots of a launch kept near 1 GiB and the whole layout within budget
 // bytes; launches > 0 asks for at least that many launches.  Returns the bytes
 // the layout needs, which exceed budget only if one distance per launch does
 // not fit.
 inline size_t sym_plan(int64_t n, int launches, int slot_bytes, int sum_bytes, int part_bytes, int fixed_bytes,
-                       size_t budget, int* nb_out, int* L_out, int* D_out) {
+                       size_t budget, int* nb_out, int* T_out, int* D_out) {
   const int nb = (int)((n + kSI - 1) / kSI);
   const int dmax = nb / 2;
   const int64_t npad = (int64_t)nb * kSI;
   int64_t dcap = std::max<int64_t>(1, (int64_t(1) << 30) / (sum_bytes * npad));
   if (launches > 0) dcap = std::min<int64_t>(dcap, std::max(1, (dmax + launches - 1) / launches));
   int d0 = (int)std::max<int64_t>(1, std::min<int64_t>(dmax, dcap));
-  int L = 1, D = 1;
+  int T = kSTiles, D = 1;
   size_t need = 0;
   for (;;) {
-    // at least ~4096 workgroups per launch (several rounds of 7 per CU), at most 16 distances each
-    L = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(16, d0), (int64_t)nb * d0 / 4096));
-    D = (d0 + L - 1) / L * L;
-    need = (size_t)npad * ((size_t)fixed_bytes + (size_t)D * slot_bytes + (size_t)(D / L) * part_bytes);
+    // at least ~4096 workgroups per launch (several rounds of 7 per CU), at most
+    // 16 distances each; where whole distances leave fewer, 2 or 4 tiles each
+    const int64_t tiles = (int64_t)nb * d0 * kSTiles / 4096;
+    if (tiles >= kSTiles) {
+      const int L = (int)std::min<int64_t>(std::min(16, d0), tiles / kSTiles);
+      T = L * kSTiles;
+      D = (d0 + L - 1) / L * L;
+    } else {
+      T = tiles >= 4 ? 4 : 2;
+      D = d0;
+    }
+    need = (size_t)npad * ((size_t)fixed_bytes + (size_t)D * slot_bytes + (size_t)(D * kSTiles / T) * part_bytes);
     if (need <= budget || d0 == 1) break;
     d0 = std::max(1, d0 - std::max(1, d0 / 8));
   }
   *nb_out = nb;
-  *L_out = L;
+  *T_out = T;
   *D_out = D;
   return need;
 }

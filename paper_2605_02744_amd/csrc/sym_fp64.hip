@@ -40,7 +40,7 @@ __device__ __forceinline__ double bpermute64(int addr, double v) {
 struct S64Args {
   const double* x;  // [3][n]
   const double* m;  // [n]
-  int n, nb, npad, dmax, half, d_lo, L, nparts;
+  int n, nb, npad, dmax, half, d_lo, T, nparts;  // T: tiles per workgroup
   double eps;
   const double4* rec;  // [npad] staged (x, y, z, m); padding far away and massless
   double* pj;          // [D][3][npad] j-side tile sums of the chunk's distances
@@ -122,9 +122,11 @@ __global__ __launch_bounds__(kSL, 6) void sym64_kernel(S64Args A) {
   const int lid = xcd_local_index(blockIdx.x, gridDim.x);
   const int g = lid % A.nb;
   const int part = lid / A.nb;
-  const int dbeg = A.d_lo + part * A.L;
-  const int dend = min(dbeg + A.L, (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1);
-  const int ntiles = dend > dbeg ? (dend - dbeg) * kSTiles : 0;
+  // this workgroup's tiles: kbeg, kbeg + 1, ... of the chunk, counted from the
+  // first tile of distance d_lo (A.T of them, fewer where g's ring ends)
+  const int kbeg = part * A.T;
+  const int rend = (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1;  // g's ring ends before this distance
+  const int ntiles = max(0, min(kbeg + A.T, (rend - A.d_lo) * kSTiles) - kbeg);
   const double e2 = A.eps * A.eps;
 
   DSet s;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kSL, 6) void sym64_kernel(S64Args A) {
   // 16-byte pieces lay the sub-block's 16 records out twice in a row
   const unsigned lane_off = (unsigned)((((t & 63) >> 1) & (kSR - 1)) * sizeof(double4) + (t & 1) * 16);
   auto stage = [&](int k, int b) {
-    const int rec0 = __builtin_amdgcn_readfirstlane(((g + dbeg + k / kSTiles) % A.nb) * kSI + (k % kSTiles) * kST);
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + A.d_lo + (kbeg + k) / kSTiles) % A.nb) * kSI + ((kbeg + k) % kSTiles) * kST);
     const char* base = reinterpret_cast<const char*>(A.rec) + (size_t)rec0 * sizeof(double4);
     unsigned o = lane_off;
     asm volatile("" : "+v"(o));
@@ -156,8 +158,8 @@ __global__ __launch_bounds__(kSL, 6) void sym64_kernel(S64Args A) {
 
   for (int k = 0; k < ntiles; ++k) {
     const int b = k & 1;
-    const int d = dbeg + k / kSTiles;
-    const int tt = k % kSTiles;
+    const int d = A.d_lo + (kbeg + k) / kSTiles;
+    const int tt = (kbeg + k) % kSTiles;
     if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
     double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0}, pz[2] = {0.0, 0.0};
 #pragma unroll 1
@@ -281,17 +283,17 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, doub
 int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps, bool excl,
                        const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
-  int nb, L, D;
+  int nb, T, D;
   // per particle: FP64 j-side slot sums per distance, FP64 i-side sums per workgroup,
   // FP64 block-diagonal sums (in pds slices) and one staged double4 record
   const int pds = diag_slices((int)((n + kSI - 1) / kSI));
   sym_plan(n, cfg.launches, 3 * sizeof(double), 3 * sizeof(double), 3 * sizeof(double),
-           pds * 3 * (int)sizeof(double) + (int)sizeof(double4), cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L,
+           pds * 3 * (int)sizeof(double) + (int)sizeof(double4), cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &T,
            &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
-  const int nparts = D / L;
+  const int nparts = D * kSTiles / T;
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(double) * 3 * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
@@ -301,7 +303,7 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
   if (!ws) return st;
   S64Args A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
-  A.L = L; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
   A.pj = reinterpret_cast<double*>(ws);
   A.pi = reinterpret_cast<double*>(ws + pj_bytes);
   double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);

@@ -229,9 +229,10 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   const int lid = xcd_local_index(blockIdx.x, gridDim.x);
   const int g = lid % A.nb;
   const int part = lid / A.nb;
-  const int dbeg = A.d_lo + part * A.L;
-  const int dend = min(dbeg + A.L, ring_end(A, g));
-  const int ntiles = dend > dbeg ? (dend - dbeg) * kSTiles : 0;
+  // this workgroup's tiles: kbeg, kbeg + 1, ... of the chunk, counted from the
+  // first tile of distance d_lo (A.T of them, fewer where g's ring ends)
+  const int kbeg = part * A.T;
+  const int ntiles = max(0, min(kbeg + A.T, (ring_end(A, g) - A.d_lo) * kSTiles) - kbeg);
   const int n = A.n;
   const float e2 = (float)(A.eps * A.eps);
 
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   auto stage = [&](int k, int b) {
     // the tile's first record, kept scalar (an address in VGPR pairs would cost
     // registers the pair loop needs)
-    const int rec0 = __builtin_amdgcn_readfirstlane(((g + dbeg + k / kSTiles) % A.nb) * kSI + (k % kSTiles) * kST);
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + A.d_lo + (kbeg + k) / kSTiles) % A.nb) * kSI + ((kbeg + k) % kSTiles) * kST);
     const size_t base = (size_t)rec0 * sizeof(float4);
     const char* hb = reinterpret_cast<const char*>(A.rhi) + base;
     const char* lb = reinterpret_cast<const char*>(A.rlo) + base;
@@ -278,8 +279,8 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
 
   for (int k = 0; k < ntiles; ++k) {
     const int b = k & 1;
-    const int d = dbeg + k / kSTiles;
-    const int tt = k % kSTiles;
+    const int d = A.d_lo + (kbeg + k) / kSTiles;
+    const int tt = (kbeg + k) % kSTiles;
     // the next tile's records travel while this one is evaluated (buffer b ^ 1
     // was last read in tile k - 1, before the barrier that ended it)
     if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
@@ -514,7 +515,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   if (n > (int64_t(1) << 30)) return set_error(NBODY_EINVAL, "symmetric pair kernel: n too large");
   const bool near = precision == kFP32C;
   const bool rescue = near && cfg.rescue;
-  int nb, L, D;
+  int nb, T, D;
   // per particle: FP32 j-side slot sums (and, for the rescue, an FP32 error estimate)
   // per distance, FP64 i-side sums (and an FP32 estimate) per workgroup, FP64
   // block-diagonal sums, two staged float4 records and, for the rescue, two FP32
@@ -528,11 +529,11 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   sym_plan(n, cfg.launches, 3 * sizeof(float) + est_slot, 3 * sizeof(float), 3 * sizeof(double) + est_part,
            pds * (3 * (int)sizeof(double) + (rescue ? (int)sizeof(float) : 0)) + 2 * sizeof(float4) + est_fixed -
                (rescue ? (int)sizeof(float) : 0),
-           cfg.scratch ? cfg.scratch_bytes - count_bytes : SIZE_MAX, &nb, &L, &D);
+           cfg.scratch ? cfg.scratch_bytes - count_bytes : SIZE_MAX, &nb, &T, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
-  const int nparts = D / L;
+  const int nparts = D * kSTiles / T;
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(float) * 3 * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
@@ -547,7 +548,7 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   if (!ws) return st;
   SymArgs A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
-  A.L = L; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
   A.fx = std::max(kNearX, kNearN / std::cbrt((float)n));
   A.pj = reinterpret_cast<float*>(ws);
   A.pi = reinterpret_cast<double*>(ws + pj_bytes);

@@ -213,9 +213,10 @@ __global__ __launch_bounds__(kSL, 6) void vsym_kernel(SymArgs A) {
   const int lid = xcd_local_index(blockIdx.x, gridDim.x);
   const int g = lid % A.nb;
   const int part = lid / A.nb;
-  const int dbeg = A.d_lo + part * A.L;
-  const int dend = min(dbeg + A.L, ring_end(A, g));
-  const int ntiles = dend > dbeg ? (dend - dbeg) * kSTiles : 0;
+  // this workgroup's tiles: kbeg, kbeg + 1, ... of the chunk, counted from the
+  // first tile of distance d_lo (A.T of them, fewer where g's ring ends)
+  const int kbeg = part * A.T;
+  const int ntiles = max(0, min(kbeg + A.T, (ring_end(A, g) - A.d_lo) * kSTiles) - kbeg);
   const float e2 = (float)(A.eps * A.eps);
 
   VSet s;
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(kSL, 6) void vsym_kernel(SymArgs A) {
   const unsigned lane_hi = (unsigned)((((t & 63) >> 5) * kSR + (t & (kSR - 1))) * sizeof(float4));
   const unsigned lane_lo = (unsigned)((t & 63) * sizeof(float4));
   auto stage = [&](int k, int b) {
-    const int rec0 = __builtin_amdgcn_readfirstlane(((g + dbeg + k / kSTiles) % A.nb) * kSI + (k % kSTiles) * kST);
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + A.d_lo + (kbeg + k) / kSTiles) % A.nb) * kSI + ((kbeg + k) % kSTiles) * kST);
     const size_t base = (size_t)rec0 * sizeof(float4);
     const char* hb = reinterpret_cast<const char*>(A.rhi) + base;
     const char* wb = reinterpret_cast<const char*>(A.rw) + base;
@@ -260,8 +261,8 @@ __global__ __launch_bounds__(kSL, 6) void vsym_kernel(SymArgs A) {
 
   for (int k = 0; k < ntiles; ++k) {
     const int b = k & 1;
-    const int d = dbeg + k / kSTiles;
-    const int tt = k % kSTiles;
+    const int d = A.d_lo + (kbeg + k) / kSTiles;
+    const int tt = (kbeg + k) % kSTiles;
     if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
     float p[2][kVC];
 #pragma unroll
@@ -316,24 +317,29 @@ __global__ __launch_bounds__(kSL, 6) void vsym_kernel(SymArgs A) {
 // The block with itself (distance 0): the k-side of all ordered pairs inside
 // I-block g, record broadcast to every lane, with the near-field correction.
 // The own pair is always left out: its term is zero (d = 0 and u = 0), which
-// the fused u would not reproduce exactly.  Writes hi + lo into pd[4][npad].
+// the fused u would not reproduce exactly.  The gridDim.y workgroups of a block
+// each take a slice of its j, and their kDiagG groups of kSL lanes each a part
+// of the slice; group 0 adds the groups' hi + lo in group order into
+// pd[slice][4][npad].
 template <bool NEAR>
-__global__ __launch_bounds__(kSL) void vsym_diag_kernel(SymArgs A, double* __restrict__ pd) {
+__global__ __launch_bounds__(kSL* kDiagG) void vsym_diag_kernel(SymArgs A, double* __restrict__ pd) {
   __shared__ float4 s_hi[kSI];
   __shared__ float4 s_w[kSI];
   __shared__ float4 s_lo[kSI];
-  const int t = threadIdx.x;
+  __shared__ double s_part[kDiagG - 1][kVC][kSI];
+  const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
   const int g = blockIdx.x;
   const float e2 = (float)(A.eps * A.eps);
+  const int span = kSI / ((int)gridDim.y * kDiagG), fl = span < kFold ? span : kFold;
+  const int f0 = ((int)blockIdx.y * kDiagG + grp) * span;
   VSet s;
   float thr[2];
   load_vset<false>(A, g, t, s, thr);
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const size_t j = (size_t)g * kSI + u * kSL + t;
-    s_hi[u * kSL + t] = A.rhi[j];
-    s_w[u * kSL + t] = A.rw[j];
-    s_lo[u * kSL + t] = A.rlo[j];
+  for (int k = threadIdx.x; k < kSI; k += kSL * kDiagG) {
+    const size_t j = (size_t)g * kSI + k;
+    s_hi[k] = A.rhi[j];
+    s_w[k] = A.rw[j];
+    s_lo[k] = A.rlo[j];
   }
   __syncthreads();
   float h[2][kVC], l[2][kVC];
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(kSL) void vsym_diag_kernel(SymArgs A, double* __res
 #pragma unroll
     for (int c = 0; c < kVC; ++c) h[u][c] = l[u][c] = 0.f;
 #pragma unroll 1
-  for (int f = 0; f < kSI; f += kFold) {
+  for (int f = f0; f < f0 + span; f += fl) {
     float p[2][kVC];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -350,7 +356,7 @@ __global__ __launch_bounds__(kSL) void vsym_diag_kernel(SymArgs A, double* __res
       for (int c = 0; c < kVC; ++c) p[u][c] = 0.f;
     float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 8
-    for (int j = f; j < f + kFold; ++j) {
+    for (int j = f; j < f + fl; ++j) {
       const float4 r = s_hi[j];
       const float4 wj = s_w[j];
 #pragma unroll
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(kSL) void vsym_diag_kernel(SymArgs A, double* __res
     }
     if constexpr (NEAR) {
       if (r2min[0] < thr[0] || r2min[1] < thr[1]) {
-        for (int j = f; j < f + kFold; ++j) {
+        for (int j = f; j < f + fl; ++j) {
           const float4 rh = s_hi[j];
           const float4 wj = s_w[j];
           const float4 lo = s_lo[j];
@@ -395,11 +401,26 @@ __global__ __launch_bounds__(kSL) void vsym_diag_kernel(SymArgs A, double* __res
 #pragma unroll
       for (int c = 0; c < kVC; ++c) fold(h[u][c], l[u][c], p[u][c]);
   }
+  if (grp > 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kVC; ++c) s_part[grp - 1][c][u * kSL + t] = (double)h[u][c] + (double)l[u][c];
+  }
+  __syncthreads();
+  if (grp > 0) return;
+  double* const pds = pd + (size_t)blockIdx.y * kVC * A.npad;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const size_t i = (size_t)g * kSI + u * kSL + t;
+    const int k = u * kSL + t;
+    const size_t i = (size_t)g * kSI + k;
 #pragma unroll
-    for (int c = 0; c < kVC; ++c) pd[(size_t)c * A.npad + i] = (double)h[u][c] + (double)l[u][c];
+    for (int c = 0; c < kVC; ++c) {
+      double v = (double)h[u][c] + (double)l[u][c];
+#pragma unroll
+      for (int q = 0; q < kDiagG - 1; ++q) v += s_part[q][c][k];
+      pds[(size_t)c * A.npad + i] = v;
+    }
   }
 }
 
@@ -410,19 +431,21 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   if (n == 0) return NBODY_OK;
   if (precision != kFP32C && precision != kFP32)
     return set_error(NBODY_EUNSUPPORTED, "symmetric VJP kernel: FP32C and FP32 only");
-  int nb, L, D;
+  int nb, T, D;
   // per particle: FP32 j-side slot sums per distance, FP64 i-side sums per workgroup,
-  // FP64 block-diagonal sums and three staged float4 records
-  sym_plan(n, cfg.launches, kVC * sizeof(float), kVC * sizeof(float), kVC * sizeof(double), kVC * sizeof(double) + 3 * sizeof(float4),
-           cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb, &L, &D);
+  // FP64 block-diagonal sums (in pds slices) and three staged float4 records
+  const int pds = diag_slices((int)((n + kSI - 1) / kSI));
+  sym_plan(n, cfg.launches, kVC * sizeof(float), kVC * sizeof(float), kVC * sizeof(double),
+           pds * kVC * (int)sizeof(double) + 3 * (int)sizeof(float4), cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb,
+           &T, &D);
   const int dmax = nb / 2;
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
-  const int nparts = D / L;
+  const int nparts = D * kSTiles / T;
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(float) * kVC * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * kVC * (size_t)npad * nparts;
-  const size_t pd_bytes = sizeof(double) * kVC * (size_t)npad;
+  const size_t pd_bytes = sizeof(double) * kVC * (size_t)npad * pds;
   const size_t rec_bytes = sizeof(float4) * (size_t)npad;
   char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + 3 * rec_bytes, &st));
   if (!ws) return st;
@@ -430,7 +453,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   A.pe = nullptr;
   A.pw = nullptr;
   A.x = x; A.m = m; A.w = w; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
-  A.L = L; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
   A.fx = std::max(kNearX, kNearN / std::cbrt((float)n));
   A.pj = reinterpret_cast<float*>(ws);
   A.pi = reinterpret_cast<double*>(ws + pj_bytes);
@@ -448,13 +471,14 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   NB_LAUNCH_CHECK("vsym_stage_kernel");
   // the own pair is always left out of the block-diagonal sums, so exclude_self needs no variant
   (void)excl;
-  if (near) vsym_diag_kernel<true><<<nb, kSL, 0, s>>>(A, pd);
-  else vsym_diag_kernel<false><<<nb, kSL, 0, s>>>(A, pd);
+  const dim3 dg((unsigned)nb, (unsigned)pds);
+  if (near) vsym_diag_kernel<true><<<dg, kSL * kDiagG, 0, s>>>(A, pd);
+  else vsym_diag_kernel<false><<<dg, kSL * kDiagG, 0, s>>>(A, pd);
   NB_LAUNCH_CHECK("vsym_diag_kernel");
   const dim3 rg((unsigned)((n + 255) / 256), kVC);
   if (dmax == 0) {
     sym_reduce_kernel<kVC, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, gx, gm, G,
-                                              1, 1);
+                                              1, 1, nullptr, nullptr, nullptr, nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
   }
@@ -466,7 +490,7 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
     else vsym_kernel<false><<<grid, kSL, 0, s>>>(A);
     NB_LAUNCH_CHECK("vsym_kernel");
     sym_reduce_kernel<kVC, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
-                                              gx, gm, G, c == 0, c == nchunks - 1);
+                                              gx, gm, G, c == 0, c == nchunks - 1, nullptr, nullptr, nullptr, nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   }
   return NBODY_OK;

@@ -145,10 +145,10 @@ def test_sym_and_ordered_agree(nb, oracle_mod):
 
 
 def test_sym_fp64_automatic_threshold(nb):
-    """The FP64 force runs the symmetric kernel from 12288 particles on (the
+    """The FP64 force runs the symmetric kernel from 8192 particles on (the
     measured crossover) and the ordered one below: the automatic result equals
     the forced form's bitwise on each side."""
-    for n, pairs in ((12288, 2), (12287, 1)):
+    for n, pairs in ((8192, 2), (8191, 1)):
         x, _, m = ics.plummer(n, seed=10)
         nb.nbody_set_config(pairs=pairs)
         try:
