@@ -762,7 +762,26 @@ def bench_jerk(args, torch, nb):
                                                      precision=args.precision, acc_valid=True), 20, 0, torch)
     e1 = nb.nbody_energy(hx, hv, hm, eps=0.005).cpu().numpy()[2]
     ms = out[args.precision]
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's acceleration + jerk on rows of the same system in a seeded order, in
+        # chunks until about --cpu-budget seconds have been spent
+        import oracle
+        order = np.random.default_rng(6).permutation(n)
+        oracle.accel_jerk_rows(x, v, m, order[:8], eps=0.001)  # thread pool start-up, untimed
+        el, done, chunk = 0.0, 0, 256
+        while done < n and el < args.cpu_budget:
+            rows = order[done:done + chunk]
+            t0 = time.perf_counter()
+            oracle.accel_jerk_rows(x, v, m, rows, eps=0.001)
+            dt = time.perf_counter() - t0
+            el += dt
+            done += rows.size
+            chunk = int(max(64, min(8192, rows.size * (0.1 * args.cpu_budget) / max(dt, 1e-3))))
+        cpu = {"value": round(done * (n - 1) / el / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "acceleration and jerk of %d sampled rows x %d j (%.1f s)" % (done, n - 1, el)}
     return {"metric": METRIC, "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
+            "cpu_baseline": cpu,
             "steps": max(2, args.steps // 3), "warmup": 1, "ms_per_step": round(ms, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "jerk1m", "n": n, "eps": 0.001, "precision": args.precision},

@@ -58,6 +58,8 @@ def _load():
         lib.oracle_accel_jerk_snap.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _D, _D, _D]
         lib.oracle_accel_jerk_snap_rows.argtypes = [_I64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, _I64,
                                                     ctypes.POINTER(ctypes.c_int64), _D, _D, _D]
+        lib.oracle_accel_jerk_rows.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, _I64,
+                                               ctypes.POINTER(ctypes.c_int64), _D, _D]
         lib.oracle_hermite6_crackle.argtypes = [_I64, ctypes.c_double, _D, _D, _D, _D, _D, _D, _D]
         lib.oracle_hermite6.argtypes = [_I64, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I64]
         lib.oracle_potential.argtypes = [_I64, _D, _D, ctypes.c_double, ctypes.c_double, _D]
@@ -237,6 +239,20 @@ def accel_jerk(x, v, m, G=1.0, eps=0.0):
     a = np.empty((3, n))
     jk = np.empty((3, n))
     _load().oracle_accel_jerk(n, _p(x), _p(v), _p(m), float(G), float(eps), _p(a), _p(jk))
+    return a, jk
+
+
+def accel_jerk_rows(x, v, m, rows, G=1.0, eps=0.0):
+    """The listed rows of ``accel_jerk``, each (3, len(rows))."""
+    m = _c(m)
+    n = m.shape[0]
+    x = _c(x, (3, n))
+    v = _c(v, (3, n))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    a = np.empty((3, rows.size))
+    jk = np.empty((3, rows.size))
+    _load().oracle_accel_jerk_rows(n, _p(x), _p(v), _p(m), float(G), float(eps), rows.size,
+                                   rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(a), _p(jk))
     return a, jk
 
 

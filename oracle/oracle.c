@@ -387,6 +387,21 @@ void oracle_accel_jerk(int64_t n, const double* x, const double* v, const double
     }
 }
 
+/* The listed rows of oracle_accel_jerk (the same per-row computation), out
+ * arrays of shape (3, nrows). */
+void oracle_accel_jerk_rows(int64_t n, const double* x, const double* v, const double* m, double G, double eps,
+                            int64_t nrows, const int64_t* rows, double* a, double* jk) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nrows; ++r) {
+        double ai[3], ji[3];
+        accel_jerk_row(n, x, v, m, G, eps, rows[r], ai, ji);
+        for (int c = 0; c < 3; ++c) {
+            a[c * nrows + r] = ai[c];
+            jk[c * nrows + r] = ji[c];
+        }
+    }
+}
+
 /* Fourth-order Hermite predictor-evaluator-corrector, shared step dt:
  *   predict  xp = x + v dt + a dt^2/2 + j dt^3/6,  vp = v + a dt + j dt^2/2
  *   evaluate a1, j1 at (xp, vp)

@@ -390,6 +390,16 @@ def test_jerk_total_is_zero_momentum_rate(oracle_mod):
     assert np.abs((jk * m).sum(axis=1)).max() <= 1e-14 * (np.abs(jk) * m).sum()
 
 
+def test_jerk_rows_equal_full_evaluation(oracle_mod):
+    """The rows variant computes each listed row exactly as the pinned full
+    evaluation does (bitwise), in any order and with repeats."""
+    x, v, m = ics.random_cloud(257, seed=43)
+    a, jk = oracle_mod.accel_jerk(x, v, m, G=0.8, eps=0.03)
+    rows = np.array([256, 0, 17, 17, 131, 5])
+    ar, jr = oracle_mod.accel_jerk_rows(x, v, m, rows, G=0.8, eps=0.03)
+    assert np.array_equal(ar, a[:, rows]) and np.array_equal(jr, jk[:, rows])
+
+
 def test_hermite4_kepler_fourth_order(oracle_mod):
     m1, m2, a_sm, e = 0.7, 0.3, 1.0, 0.5
     x0, v0, m = _kepler_ics(m1, m2, a_sm, e)
