@@ -39,22 +39,17 @@ struct ISet {
   float x[2], y[2], z[2], mneg[2];
 };
 
-// One step of a sub-block: both i of the lane against record (r + K).  EST
-// (FP32C with the rescue): the j's smallest squared distance to the lane's
-// two i also travels to its owner lane (a DPP row rotation fused into a min),
-// for the far side's share of the error estimate.
-template <int K, bool NEAR, bool EST>
+// One step of a sub-block: both i of the lane against record (r + K).
+template <int K, bool NEAR>
 __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
                                          float (&py)[2], float (&pz)[2], float (&r2min)[2], float& ajx,
-                                         float& ajy, float& ajz, float& ajm) {
+                                         float& ajy, float& ajz) {
   const float4 r = rowp[K];
   float tx = 0.f, ty = 0.f, tz = 0.f;
-  float r2u[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const float dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
-    r2u[u] = r2;
     const float ri = rsqrt32(r2);
     const float ri3 = (ri * ri) * ri;
     const float si = r.w * ri3;
@@ -70,20 +65,18 @@ __device__ __forceinline__ void sym_step(const ISet& s, const float4* __restrict
   // at step 0, is K lanes further on
   if constexpr (K == 0) {
     ajx += tx; ajy += ty; ajz += tz;
-    if constexpr (EST) ajm = fminf(ajm, fminf(r2u[0], r2u[1]));
   } else {
     ajx += row_ror<K>(tx);
     ajy += row_ror<K>(ty);
     ajz += row_ror<K>(tz);
-    if constexpr (EST) ajm = fminf(ajm, row_ror<K>(fminf(r2u[0], r2u[1])));
   }
 }
 
-template <bool NEAR, bool EST, int... K>
+template <bool NEAR, int... K>
 __device__ __forceinline__ void sym_sub(const ISet& s, const float4* __restrict__ rowp, float e2, float (&px)[2],
                                         float (&py)[2], float (&pz)[2], float (&r2min)[2], float& ajx,
-                                        float& ajy, float& ajz, float& ajm, std::integer_sequence<int, K...>) {
-  (sym_step<K, NEAR, EST>(s, rowp, e2, px, py, pz, r2min, ajx, ajy, ajz, ajm), ...);
+                                        float& ajy, float& ajz, std::integer_sequence<int, K...>) {
+  (sym_step<K, NEAR>(s, rowp, e2, px, py, pz, r2min, ajx, ajy, ajz), ...);
 }
 
 // Loads the two i of lane t of I-block g (padding i: far away and massless, so
@@ -221,7 +214,7 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
   __shared__ float s_part[3][kSW][kST];
   __shared__ float s_acc_lo[6][kSL];      // the lo halves of the i-side (hi, lo) sums
   __shared__ float s_est[2][kSL];         // the i-side error estimates (EST)
-  __shared__ float s_pmin[kSW][kST];      // the j's smallest squared distance per wave (EST)
+  __shared__ float s_pmin[kSW];           // the tile's smallest non-repaired squared distance per wave (EST)
 
   const int t = threadIdx.x;
   const int rl = t & (kSR - 1);
@@ -288,9 +281,8 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
     float r2min[2] = {3.0e38f, 3.0e38f};
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
-      float ajx = 0.f, ajy = 0.f, ajz = 0.f, ajm = 3.0e38f;
-      sym_sub<NEAR, EST>(s, &s_hi[b][q][rl], e2, px, py, pz, r2min, ajx, ajy, ajz, ajm,
-                         std::make_integer_sequence<int, kSR>{});
+      float ajx = 0.f, ajy = 0.f, ajz = 0.f;
+      sym_sub<NEAR>(s, &s_hi[b][q][rl], e2, px, py, pz, r2min, ajx, ajy, ajz, std::make_integer_sequence<int, kSR>{});
       // the four rows' sums of the same 16 j: rows (0 + 1) and (2 + 3) by a
       // swizzle, then the two halves by a permute, after which all four rows
       // hold the same totals and store the same values (no branch in the loop)
@@ -303,11 +295,6 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
       s_part[0][wave][q * kSR + rl] = ajx;
       s_part[1][wave][q * kSR + rl] = ajy;
       s_part[2][wave][q * kSR + rl] = ajz;
-      if constexpr (EST) {
-        ajm = fminf(ajm, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(ajm), 0x401F)));
-        ajm = fminf(ajm, __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(ajm))));
-        s_pmin[wave][q * kSR + rl] = ajm;
-      }
     }
     if constexpr (NEAR) {
       // rare: a pair of this tile may be closer than the larger repair radius
@@ -318,13 +305,23 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
         px[0] = r.x0; px[1] = r.x1; py[0] = r.y0; py[1] = r.y1; pz[0] = r.z0; pz[1] = r.z1;
       }
       // the error estimate of the rescue: this tile's partial sums, weighted by
-      // the distance of their closest pair left in rounded positions
+      // the distance of their closest pair left in rounded positions (r2min
+      // holds it after the repair); for the far side, the wave's smallest such
+      // distance over the whole tile, a lower bound of every j's own
       if constexpr (EST) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const float xinf = fmaxf(fabsf(s.x[u]), fmaxf(fabsf(s.y[u]), fabsf(s.z[u])));
           s_est[u][t] = est_add(s_est[u][t], px[u], py[u], pz[u], xinf, r2min[u]);
         }
+        float tm = fminf(r2min[0], r2min[1]);
+        tm = fminf(tm, row_ror<8>(tm));
+        tm = fminf(tm, row_ror<4>(tm));
+        tm = fminf(tm, row_ror<2>(tm));
+        tm = fminf(tm, row_ror<1>(tm));
+        tm = fminf(tm, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(tm), 0x401F)));
+        tm = fminf(tm, __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(tm))));
+        if ((t & 63) == 0) s_pmin[wave] = tm;
       }
     }
 #pragma unroll
@@ -352,12 +349,13 @@ __global__ __launch_bounds__(kSL, 7) void sym_accel_kernel(SymArgs A) {
         for (int c = 0; c < 3; ++c) A.pj[((size_t)(d - A.d_lo) * 3 + c) * A.npad + col] = v[c];
       } else if constexpr (EST) {
         // the far side's share of j's error estimate: this tile's sum over the
-        // workgroup's i, weighted by the distance of the closest pair left in
-        // rounded positions; a pair closer than j's own repair radius was
-        // repaired, so that radius bounds the distance from below
-        float dm = s_pmin[0][jl];
+        // workgroup's i, weighted by the smallest distance of the tile's pairs
+        // left in rounded positions (over all its j: a lower bound of j's own
+        // closest such pair); a pair closer than j's own repair radius was
+        // repaired, so that radius bounds the distance from below too
+        float dm = s_pmin[0];
 #pragma unroll
-        for (int w = 1; w < kSW; ++w) dm = fminf(dm, s_pmin[w][jl]);
+        for (int w = 1; w < kSW; ++w) dm = fminf(dm, s_pmin[w]);
         const float4 rj = s_hi[b][jl / kSR][jl % kSR];
         const float xinf = fmaxf(fabsf(rj.x), fmaxf(fabsf(rj.y), fabsf(rj.z)));
         const float wj = fmaf(kEstNear * xinf, rsqrt32(fmaxf(dm, s_lo[b][jl].w)), 1.0f);
