@@ -14,7 +14,8 @@
 // up to 512 terms) they add the square of the block's partial sum |P_b|,
 // weighted by 1 + kEstNear |x_i|_inf / d_b, d_b the smallest softened distance
 // of a pair of that block that was not repaired with float-float
-// displacements:
+// displacements (for a far-side slot, a lower bound of it: the smallest such
+// distance among all pairs of the tile of 64 j the slot belongs to):
 //   E_i = sum_b ((1 + kEstNear |x_i| / d_b) |P_b|)^2 .
 // The rounding error of a block's sum grows like the magnitude of its partial
 // sum both when one term dominates the block and when its terms have random
@@ -29,11 +30,13 @@
 // 6.25e-4) and the two-component model, the estimate exceeded the actual
 // error of FP32C (without rescue, against FP64) by 4 to 10 at the median and
 // the row left unflagged with the largest error stayed at 2.7e-6, against 4e-5
-// for the largest error without rescue; 0.4 % (2^20) to 2 % (4096 particles
-// with softening 6.25e-4) of the rows are recomputed.  The estimate misses
-// cancellation that is systematic inside one block of consecutive indices
-// (terms of a block that cancel each other more than random directions do);
-// the far side of the symmetric kernels carries no distance factor.
+// for the largest error without rescue.  With the far side's per-tile bound,
+// 610 000 rows of Plummer spheres (4096 to 262144 particles, softenings
+// 6.25e-4 to 1e-3, symmetric kernel) left 2.3e-6 as the largest unflagged
+// error with 0.86 % of the rows recomputed; 0.12 % of the rows of the 2^20
+// two-component model are.  The estimate misses cancellation that is
+// systematic inside one block of consecutive indices (terms of a block that
+// cancel each other more than random directions do).
 //
 // Here, for the force of one system: the flagged rows go to a list (an atomic
 // counter, one add per wave, orders them, which does not change any result:
