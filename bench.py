@@ -28,6 +28,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -51,16 +52,25 @@ FLOPS_JERK = 42
 FLOPS_SNAP = 80
 # sources of the headline evaluation's kernels (the symmetric FP32C path: staging,
 # block-diagonal, half-ring chunks, slot sums and the FP64 rescue); counter figures
-# taken on other sources are not reported
+# taken on other code are not reported
 KERNEL_SOURCES = ("paper_2605_02744_amd/csrc/sym_pairs.hip", "paper_2605_02744_amd/csrc/sym_common.h",
                   "paper_2605_02744_amd/csrc/pair_math.h", "paper_2605_02744_amd/csrc/rescue.hip")
+
+
+def code_text(src):
+    """C++ source without its comments and layout: edits to comments or
+    whitespace leave it (and the compiled kernels) unchanged.  The sources hold
+    no string literal with comment markers in it."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(" ".join(l.split()) for l in src.splitlines() if l.strip())
 
 
 def kernel_hash():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -31,10 +31,6 @@ __device__ __forceinline__ float row_ror(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xF, 0xF, true));
 }
 
-// Orders a wave's LDS accesses around a rewrite by other lanes (LDS
-// instructions of one wave execute in order; this keeps the compiler from
-// moving, merging or dropping reads and writes across the point, which it may
-// otherwise do because to it different lanes are different threads).
 // Workgroups go to the chip's 8 XCDs round-robin (workgroup id mod 8), and
 // each XCD has its own L2.  This logical index gives each XCD runs of
 // kXCDRun consecutive indices (the runs dealt to the XCDs in turn), so that
@@ -52,6 +48,10 @@ __device__ __forceinline__ int xcd_local_index(int bid, int grid) {
   return ((k / kXCDRun) * kXCDs + x) * kXCDRun + k % kXCDRun;
 }
 
+// Orders a wave's LDS accesses around a rewrite by other lanes (LDS
+// instructions of one wave execute in order; this keeps the compiler from
+// moving, merging or dropping reads and writes across the point, which it may
+// otherwise do because to it different lanes are different threads).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
