@@ -454,7 +454,7 @@ def bench_ensemble(args, torch, nb):
     # kernel (mode 0, the library default without tuning) is timed beside it.
     tuned = {}
     if args.bsplit is None and not args.split:
-        nb.nbody_set_config()
+        nb.nbody_set_config(rescue=args.rescue)
         tx0, tv0 = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
         for prec in (args.precision, "fp64"):
             tuned[prec] = nb.nbody_tune_batched(off, epsv, tx0, tv0, tm, w["dt"], 50, precision=prec)
@@ -462,7 +462,8 @@ def bench_ensemble(args, torch, nb):
     else:
         mode = args.bsplit if args.bsplit is not None else 1
         # bsplit 0 alone would read as "automatic": a pass width forces the resident kernel
-        nb.nbody_set_config(bsplit=mode, bpass=args.bpass or (4 if mode == 0 else 0), bitem=args.bitem)
+        nb.nbody_set_config(bsplit=mode, bpass=args.bpass or (4 if mode == 0 else 0), bitem=args.bitem,
+                            rescue=args.rescue)
     res, drift = {}, {}
 
     def energies(tx, tv):
@@ -481,8 +482,7 @@ def bench_ensemble(args, torch, nb):
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, w["dt"], 0, precision=prec)  # plan + a(x)
         steps = args.steps
         # all clusters, all steps: one persistent launch (modes 0-2), or two (mode 3) or three (mode 4)
-        # launches per step,
-        # captured in a HIP graph and replayed once
+        # launches per step and one more for the FP32C rescue, captured in a HIP graph and replayed once
         gs = torch.cuda.Stream()
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
@@ -523,9 +523,11 @@ def bench_ensemble(args, torch, nb):
                                        "value": round(pairs * naive_steps / (msn * 1e-3) / 1e9, 3),
                                        "note": "one nbody_step call per cluster, %d steps each" % naive_steps}
     ms = res[args.precision]
+    resc = args.precision == "fp32c" and mode in (3, 4) and args.rescue != 2  # the FP32C rescue (default on)
     kname = {0: "ensemble_kernel", 1: "ensemble_kernel (split)", 2: "ens_stream_kernel / ens_wave_kernel",
-             3: "ens_waveforce_kernel (one step: publish and force launches)",
-             4: "esym_force_kernel (one step: publish, force and far-side sum launches)"}[mode]
+             3: "ens_waveforce_kernel (one step: publish and force launches%s)" % (", FP64 rescue" if resc else ""),
+             4: "esym_force_kernel (one step: publish, force and far-side sum launches%s)"
+                % (", FP64 rescue" if resc else "")}[mode]
     # one step of the graph-replayed run: C20 flops of every system's ordered pairs over the step time
     roof = roofline(kname, pairs * FLOPS_PER_PAIR, ms / args.steps)
     cpu = None
@@ -553,7 +555,9 @@ def bench_ensemble(args, torch, nb):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble512", "clusters": int(w["ncl"]), "particles": int(off[-1]),
                        "interactions_per_step": pairs, "dt": w["dt"], "precision": args.precision,
-                       "launches": {3: 2 * args.steps + 1, 4: 3 * args.steps + 1}.get(mode, 1), "hip_graph": True, "kernel_mode": mode,
+                       "fp32c_rescue": resc,
+                       "launches": {3: (2 + resc) * args.steps + 1, 4: (3 + resc) * args.steps + 1}.get(mode, 1),
+                       "hip_graph": True, "kernel_mode": mode,
                        "autotuned": tuned or None, "bpass": args.bpass, "bitem": args.bitem},
             "pct_fp32_peak": round(100 * pairs * args.steps * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2),
             "energy_drift_per_cluster": drift,
@@ -924,6 +928,8 @@ def main():
     ap.add_argument("--bitem", type=int, default=0, help="streamed ensemble: most particles per item (0 = auto)")
     ap.add_argument("--pairs", type=int, default=0, choices=[0, 1, 2],
                     help="force kernel form: 1 ordered, 2 symmetric (each unordered pair once), 0 automatic")
+    ap.add_argument("--rescue", type=int, default=0, choices=[0, 1, 2],
+                    help="ensemble: the FP32C rescue, 0 automatic (on), 1 on, 2 off")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)

@@ -194,8 +194,9 @@ int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64
  * step is a few launches over items of 64 particles of all systems: two per
  * step (mode 3: kicks and records, then forces), or three for FP32C/FP32
  * layouts whose systems span several blocks of 64 (mode 4: each unordered
- * pair of a system once, then a fixed-order sum of the far-side terms); the
- * steps of a call may be captured into a HIP graph.  All systems and all
+ * pair of a system once, then a fixed-order sum of the far-side terms), and
+ * one more with the FP32C rescue (the FP64 rows); the steps of a call may be
+ * captured into a HIP graph.  All systems and all
  * steps run inside ONE persistent kernel launch in modes 0-2 (bsplit 0, 1, 2
  * or nbody_tune_batched with allow_cooperative).  off (ncl+1, int64,
  * off[0] == 0, non-decreasing) and eps (ncl) are HOST arrays; the work plan
@@ -297,8 +298,9 @@ typedef struct nbody_config {
                       (Eq. 1's antisymmetry: an item's block of 64 meets its own
                       block and half of its system's other blocks, and the terms
                       of the far side are added per particle in FP64 in a fixed
-                      order by a third launch per step); FP32C and FP32 only (FP64
-                      runs mode 3), and layouts whose per-distance sums would
+                      order by a third launch per step, and with the FP32C rescue
+                      a fourth recomputes the flagged rows); FP32C and FP32 only
+                      (FP64 runs mode 3), and layouts whose per-distance sums would
                       exceed 1 GiB (about 3 x sum of N_c^2 / 128 floats) run mode 3.
                       Modes 1 and 2 need every workgroup of the launch resident at
                       once: with another kernel occupying the GPU a bounded wait can
@@ -327,8 +329,8 @@ typedef struct nbody_config {
   int32_t rescue;  /* FP32C force of nbody_accel, nbody_accel_noalloc, the
                       KDK steps of nbody_step and of the adjoint's recompute,
                       and of nbody_step_batched with the per-step items of 64
-                      (mode 3): 0 = automatic (on where the kernels carry it),
-                      1 = on (batched modes other than 3 then return
+                      (modes 3 and 4): 0 = automatic (on where the kernels
+                      carry it), 1 = on (batched modes 0-2 then return
                       NBODY_EUNSUPPORTED), 2 = off.  On: while summing, the
                       kernels estimate each row's FP32 rounding error (per
                       block of terms summed in FP32: the magnitude of the
@@ -338,7 +340,7 @@ typedef struct nbody_config {
                       4e-6 |a_i| (rows whose terms cancel strongly) are
                       recomputed in FP64; this keeps such rows inside the 1e-5
                       FP32C bound at the cost of one FP64 row evaluation each
-                      (0.4 % of the rows of the 2^20 two-component model). */
+                      (0.12 % of the rows of the 2^20 two-component model). */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros
@@ -371,8 +373,8 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
  * split mode and the streamed kernel with items of 64, 256, 512 or 1024 particles
  * (the modes that need every workgroup of a launch resident at once). allow_cooperative = 2 keeps
  * to the single-launch modes 0, 1 and 2 (all steps in one persistent launch).
- * FP32C with the rescue on (nbody_config.rescue 0 or 1) has one candidate, the
- * per-step items of 64 (mode 3), the only batched form that carries it; the
+ * FP32C with the rescue on (nbody_config.rescue 0 or 1) has two candidates, the
+ * per-step items of 64 (modes 3 and 4), the batched forms that carry it; the
  * single-launch search (allow_cooperative = 2) then goes without the rescue,
  * or returns NBODY_EUNSUPPORTED if the rescue was asked for explicitly.  The
  * choice is recorded for this (device, precision, rescue, layout): later

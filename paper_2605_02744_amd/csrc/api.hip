@@ -301,9 +301,10 @@ BatchConfig batch_config_for(int32_t ncl, const int64_t* off, const double* eps,
         std::equal(e.off.begin(), e.off.end(), off) && std::equal(e.eps.begin(), e.eps.end(), eps) &&
         e.bc.rescue == bc.rescue)
       return e.bc;
-  // FP32C with the rescue runs the per-step wave items (mode 3, the batched
-  // form with the rescue); otherwise their symmetric form where it pays
-  const bool sym = precision == NBODY_FP32 || (precision == NBODY_FP32C && !bc.rescue);
+  // the symmetric per-step items where they pay (FP32C and FP32 layouts whose
+  // systems mostly span several blocks of 64), else the ordered ones; both
+  // carry the FP32C rescue
+  const bool sym = precision == NBODY_FP32 || precision == NBODY_FP32C;
   bc.mode = (sym && sym_ensemble_default(ncl, off)) ? 4 : 3;
   return bc;
 }
@@ -480,8 +481,9 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
   if (x == v || x == a || v == a) return set_error(NBODY_EINVAL, "x, v and a must be distinct");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const BatchConfig bc = batch_config_for(ncl, off, eps, p->precision, current_device());
-  if (p->precision == NBODY_FP32C && t_cfg.rescue == 1 && bc.mode != 3)
-    return set_error(NBODY_EUNSUPPORTED, "batched: the FP32C rescue runs with the per-step wave items (bsplit 3) only");
+  if (p->precision == NBODY_FP32C && t_cfg.rescue == 1 && bc.mode != 3 && bc.mode != 4)
+    return set_error(NBODY_EUNSUPPORTED,
+                     "batched: the FP32C rescue runs with the per-step items (bsplit 3 or 4) only");
   int st = run_batched(ncl, off, eps, x, v, a, m, dt, nsteps, p->G, p->precision,
                        (p->flags & NBODY_EXCLUDE_SELF) != 0, (p->flags & NBODY_ACC_VALID) != 0, bc, s);
   return finish(st, s, p, {{x, 3 * total}, {v, 3 * total}, {a, 3 * total}});
@@ -504,11 +506,12 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
   const int rescue = t_cfg.rescue == 2 ? 0 : 1;
   std::vector<BatchConfig> cand;
   if (p->precision == NBODY_FP32C && rescue && (allow_cooperative != 2 || t_cfg.rescue == 1)) {
-    // only the per-step wave items carry the FP32C rescue (the single-launch
+    // only the per-step items carry the FP32C rescue (the single-launch
     // search, allow_cooperative = 2, goes without it unless it was asked for)
     if (allow_cooperative == 2)
       return set_error(NBODY_EUNSUPPORTED, "tune_batched: no single-launch mode carries the FP32C rescue");
     cand.push_back(BatchConfig{3, 0, 64, 1});
+    cand.push_back(BatchConfig{4, 0, 0, 1});
   } else {
     for (int pass : {1, 2, 4}) cand.push_back(BatchConfig{0, pass, 0, rescue});
     if (allow_cooperative != 2) {

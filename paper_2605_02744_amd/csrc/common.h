@@ -128,6 +128,16 @@ int run_hermite6(int64_t n, double* x, double* v, double* a, double* jk, double*
 int launch_rescue(int64_t n, const double* x, const double* m, double eps, double G, bool excl, const float* est,
                   int nslices, size_t stride, double* a, int* list, int* count, hipStream_t s);
 
+// FP64 rescue of batched FP32C rows: the rcnt[c] rows of system c listed in
+// rlist from the system's first particle on (system-local indices, in any
+// order), each recomputed in FP64 over its own system and written to a in
+// place (x, a: [3][total], m: [total]; d_off: ncl + 1 system offsets, d_eps:
+// ncl softenings, all on the device).  Results do not depend on the lists'
+// order.
+int launch_ens_rescue(int32_t ncl, const int64_t* d_off, const double* d_eps, int64_t total, const double* x,
+                      const double* m, double G, bool excl, const int* rcnt, const int* rlist, double* a,
+                      hipStream_t s);
+
 // Elementwise KDK pieces over 3n entries.
 int launch_kick(int64_t n3, double* v, const double* a, double h, hipStream_t s);
 int launch_kick_drift(int64_t n3, double* x, double* v, const double* a, double h, double dt,
@@ -138,14 +148,14 @@ int launch_potential(int64_t n, const double* x, const double* m, double eps, do
                      int split, hipStream_t s);
 
 // Configuration of the batched (ensemble) kernels: mode 0 resident systems,
-// 1 resident with split systems, 2 streamed items; pass = i-particles per lane
-// per pass of mode 0/1 (0 = automatic); item = most particles per item of
-// mode 2 (0 = automatic).
+// 1 resident with split systems, 2 streamed items, 3 per-step wave items, 4
+// symmetric per-step items; pass = i-particles per lane per pass of mode 0/1
+// (0 = automatic); item = most particles per item of mode 2 (0 = automatic).
 struct BatchConfig {
   int mode = 0;
   int pass = 0;
   int item = 0;
-  int rescue = 1;  // FP32C, mode 3: rows flagged by the error estimate recomputed in FP64
+  int rescue = 1;  // FP32C, modes 3 and 4: rows flagged by the error estimate recomputed in FP64
 };
 
 

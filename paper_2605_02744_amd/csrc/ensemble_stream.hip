@@ -1092,15 +1092,7 @@ int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double*
       ens_waveforce_kernel<MODE, false><<<p->nwg, kSBlock, 0, s>>>(p->d_off, p->d_eps, p->d_items, p->d_wg_off,
                                                                    p->d_wg_list, rec, a, p->total, G, rcnt, rlist);
     NB_LAUNCH_CHECK("ens_waveforce_kernel");
-    if (rcnt) {
-      if (excl)
-        ens_rescue_kernel<true><<<dim3(p->ncl, kRSplit), 64 * kRWaves, 0, s>>>(p->d_off, p->d_eps, p->total, x, m, G,
-                                                                              rcnt, rlist, a);
-      else
-        ens_rescue_kernel<false><<<dim3(p->ncl, kRSplit), 64 * kRWaves, 0, s>>>(p->d_off, p->d_eps, p->total, x, m, G,
-                                                                               rcnt, rlist, a);
-      NB_LAUNCH_CHECK("ens_rescue_kernel");
-    }
+    if (rcnt) return launch_ens_rescue(p->ncl, p->d_off, p->d_eps, p->total, x, m, G, excl, rcnt, rlist, a, s);
     return NBODY_OK;
   };
   int st;
@@ -1122,6 +1114,18 @@ int launch_wsteps(const SPlan* p, double* x, double* v, double* a, const double*
 }
 
 }  // namespace
+
+int launch_ens_rescue(int32_t ncl, const int64_t* d_off, const double* d_eps, int64_t total, const double* x,
+                      const double* m, double G, bool excl, const int* rcnt, const int* rlist, double* a,
+                      hipStream_t s) {
+  if (ncl <= 0) return NBODY_OK;
+  if (excl)
+    ens_rescue_kernel<true><<<dim3(ncl, kRSplit), 64 * kRWaves, 0, s>>>(d_off, d_eps, total, x, m, G, rcnt, rlist, a);
+  else
+    ens_rescue_kernel<false><<<dim3(ncl, kRSplit), 64 * kRWaves, 0, s>>>(d_off, d_eps, total, x, m, G, rcnt, rlist, a);
+  NB_LAUNCH_CHECK("ens_rescue_kernel");
+  return NBODY_OK;
+}
 
 int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                        const double* m, double dt, int64_t nsteps, double G, int precision, bool excl,

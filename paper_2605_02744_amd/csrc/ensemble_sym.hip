@@ -29,6 +29,16 @@
 // kernels applies: in the ordered block a pair closer than particle i's repair
 // radius, in a block pair a pair closer than the larger radius of its two
 // particles, gets float-float displacements.
+// With the FP64 rescue (FP32C), each sum of 64 terms that a wave forms also
+// adds its share to the row's rounding-error estimate (rescue.hip): the i-side
+// sums of the ordered block and of every block pair, weighted by the lane's
+// closest pair left in rounded positions, into per-part estimate slots; for
+// the j-side sums of a block pair the wave records only the closest such pair
+// of the whole block pair (one wave reduction, a lower bound of each j's own),
+// and the reduction, which reads each j-side sum anyway, weights it with that
+// distance.  The reduction then lists the rows whose estimate is too large
+// against |a_i| per system, and the batched rescue recomputes those rows in
+// FP64.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -59,11 +69,16 @@ struct EItem {
 // Per-system geometry: particles [o, o + nc) of the concatenated arrays, nb
 // blocks of 64, j-side slots [dmax][3][nb * 64] floats from sbase, i-side
 // slots [parts - 1][3][nb * 64] doubles from ibase for the parts after the
-// first (a block's distances cut into parts of lp).
+// first (a block's distances cut into parts of lp); with the rescue, the
+// i-side error estimates [parts][nb * 64] floats from iebase (every part) and
+// per block pair its closest pair left in rounded positions (squared),
+// [dmax][nb] floats from wbase, indexed by distance and J-block.
 struct ESys {
   int64_t o;
   int64_t sbase;
   int64_t ibase;
+  int64_t iebase;
+  int64_t wbase;
   double eps;
   int nc, nb, dmax, half;
   float fx;  // repair-radius factor max(kNearX, kNearN nc^-1/3)
@@ -80,12 +95,15 @@ __host__ __device__ inline int esym_dend(const ESys& S, int b) {
 // rounded separately), x += dt v.  Then the pair records of the new position:
 // hi = (x, y, z, m) rounded to FP32, lo = (x - hi, y - hi, z - hi, repair
 // radius^2, or -1 without the repair).
+// With rcnt (the rescue): clears the ncl per-system counts of flagged rows.
 template <bool NEAR>
 __global__ void esym_publish_kernel(int nblocks, const EItem* __restrict__ blocks, const ESys* __restrict__ sys,
                                     int64_t total, double* __restrict__ x, double* __restrict__ v,
                                     const double* __restrict__ a, const double* __restrict__ m,
                                     float4* __restrict__ rhi, float4* __restrict__ rlo, double h, double dt,
-                                    int kicks) {
+                                    int kicks, int* __restrict__ rcnt, int ncl) {
+  if (rcnt)
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) rcnt[c] = 0;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nblocks * 64;
        g += (int64_t)gridDim.x * blockDim.x) {
     const EItem it = blocks[g >> 6];
@@ -153,11 +171,15 @@ __device__ __forceinline__ void esym_sub(const float4& ip, float mneg, const flo
   (esym_step<K, NEAR>(ip, mneg, rowp, e2, px, py, pz, r2m, ajx, ajy, ajz), ...);
 }
 
-template <bool NEAR, bool EXCL>
+// EST (FP32C with the rescue): the i-side shares of the error estimate into
+// iest, each block pair's closest pair left in rounded positions into wslots.
+template <bool NEAR, bool EXCL, bool EST>
 __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
     const ESys* __restrict__ sys, const EItem* __restrict__ items, const int* __restrict__ wg_off,
     const int* __restrict__ wg_list, const float4* __restrict__ rhi, const float4* __restrict__ rlo,
-    double* __restrict__ a, double* __restrict__ islot, float* __restrict__ slots, int64_t total) {
+    double* __restrict__ a, double* __restrict__ islot, float* __restrict__ slots, int64_t total,
+    float* __restrict__ iest, float* __restrict__ wslots) {
+  static_assert(NEAR || !EST, "the estimate belongs to FP32C");
   __shared__ float4 s_hi[kEWaves][4][2 * kSR];  // (x, y, z, m) hi parts, each sub-block twice
   __shared__ float4 s_lo[kEWaves][64];          // lo parts and the repair radius^2
   __shared__ float s_j[kEWaves][3][64];         // the block pair's j-side sums
@@ -209,6 +231,9 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
       wave_sync();
     };
     float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+    float eacc = 0.f;  // the lane's i-side share of its row's error estimate (EST)
+    // |x_i|_inf, formed where it is used (cheaper than a register held over the item)
+    auto xinf = [&]() { return fmaxf(fabsf(ip.x), fmaxf(fabsf(ip.y), fabsf(ip.z))); };
     float4 nh, nq;
     const int r0 = it.d0 > 0 ? it.d0 : 1;  // first distance of the ring in this part
     if (it.d0 == 0) {
@@ -236,7 +261,7 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
         if (r2min < iq.w) {
           // rare: redo the block with float-float displacements for the pairs
           // closer than particle i's repair radius
-          float qx = 0.f, qy = 0.f, qz = 0.f;
+          float qx = 0.f, qy = 0.f, qz = 0.f, r2nr = 3.0e38f;
           for (int jj = 0; jj < 64; ++jj) {
             const float4 r = s_hi[wv][jj >> 4][jj & (kSR - 1)];
             const float4 q = s_lo[wv][jj];
@@ -247,6 +272,8 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
               dy += q.y - iq.y;
               dz += q.z - iq.z;
               r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+            } else if (jj != lane) {
+              r2nr = fminf(r2nr, r2);
             }
             const float ri = rsqrt32(r2);
             float sc = (r.w * ri) * (ri * ri);
@@ -258,7 +285,11 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
           px = qx;
           py = qy;
           pz = qz;
+          r2min = r2nr;
         }
+        // the block's share of the estimate, weighted by its closest pair left
+        // in rounded positions
+        if constexpr (EST) eacc = est_add(eacc, px, py, pz, xinf(), r2min);
       }
       fold(hx, lx, px);
       fold(hy, ly, py);
@@ -291,7 +322,9 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
       }
       if constexpr (NEAR) {
         wave_sync();
+        float r2nr = r2m;  // a lane without a repair keeps all its pairs in rounded positions
         if (r2m < thr) {
+          r2nr = 3.0e38f;
           // rare: for every pair of the lane's i closer than the larger repair
           // radius of its two particles, the rounded-position term is replaced
           // by the float-float one on both sides.  The j are visited in the
@@ -305,6 +338,7 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
             const float dx = r.x - ip.x, dy = r.y - ip.y, dz = r.z - ip.z;
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
             float cx = 0.f, cy = 0.f, cz = 0.f;
+            if (!(r2 < fmaxf(iq.w, ql.w))) r2nr = fminf(r2nr, r2);
             if (r2 < fmaxf(iq.w, ql.w)) {
               const float ex = dx + (ql.x - iq.x), ey = dy + (ql.y - iq.y), ez = dz + (ql.z - iq.z);
               const float ri = rsqrt32(r2);
@@ -333,6 +367,19 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
             }
           }
         }
+        if constexpr (EST) {
+          eacc = est_add(eacc, px, py, pz, xinf(), r2nr);
+          // the wave's minimum: within each row of 16 by rotations, then rows
+          // (0 + 1) and (2 + 3) by a swizzle, then the two halves by a permute
+          float tm = r2nr;
+          tm = fminf(tm, row_ror<8>(tm));
+          tm = fminf(tm, row_ror<4>(tm));
+          tm = fminf(tm, row_ror<2>(tm));
+          tm = fminf(tm, row_ror<1>(tm));
+          tm = fminf(tm, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(tm), 0x401F)));
+          tm = fminf(tm, __int_as_float(__builtin_amdgcn_ds_bpermute(xor32, __float_as_int(tm))));
+          if (lane == 0) wslots[S.wbase + (size_t)(d - 1) * nb + J] = tm;
+        }
       }
       fold(hx, lx, px);
       fold(hy, ly, py);
@@ -350,6 +397,7 @@ __global__ __launch_bounds__(kEBlock, kEOcc) void esym_force_kernel(
       o[0] = (double)hx + (double)lx;
       o[st] = (double)hy + (double)ly;
       o[2 * st] = (double)hz + (double)lz;
+      if constexpr (EST) iest[S.iebase + (size_t)it.part * npad + il] = eacc;
     }
   }
 }
@@ -399,6 +447,85 @@ __global__ void esym_reduce_kernel(int nblocks, const EItem* __restrict__ blocks
   }
 }
 
+// The same sums with the rescue's estimate, one thread per particle (the three
+// components read together, each added in the order above, so the forces equal
+// those of esym_reduce_kernel bitwise).  The row's estimate adds its i-side
+// shares in part order, then per distance the far side's share: the j-side sum
+// of the slot, weighted by the closest pair of its block pair left in rounded
+// positions, or by the particle's own repair radius where that is larger
+// (pairs inside it were repaired).  A row whose estimate is too large against
+// |a_i| (see rescue.hip) is appended to its system's list for the batched
+// rescue (rlist from the system's first particle on, system-local indices,
+// rcnt[system] rows; one atomic add per wave, a wave being one block of 64 of
+// one system).
+__global__ void esym_reduce_est_kernel(int nblocks, const EItem* __restrict__ blocks, const ESys* __restrict__ sys,
+                                       int64_t total, const double* __restrict__ islot,
+                                       const float* __restrict__ slots, const float* __restrict__ iest,
+                                       const float* __restrict__ wslots, const float4* __restrict__ rhi,
+                                       const float4* __restrict__ rlo, double* __restrict__ a, double G,
+                                       int* __restrict__ rcnt, int* __restrict__ rlist) {
+  // the grid stride is a whole number of waves, so every wave stays one block
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (int64_t)nblocks * 64;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const EItem it = blocks[g >> 6];
+    const int lane = (int)(g & 63);
+    const ESys& S = sys[it.sys];
+    const int p = it.b * 64 + lane;
+    bool flag = false;
+    if (lane < it.ni) {
+      const int64_t i = S.o + p;
+      const size_t npad = (size_t)S.nb * 64;
+      int dn = S.dmax;
+      if (S.half && dn > 0) {
+        int src = it.b - S.dmax;
+        if (src < 0) src += S.nb;
+        if (src >= S.nb / 2) --dn;
+      }
+      const size_t stride = 3 * npad;
+      const int np = (esym_dend(S, it.b) + S.lp - 1) / S.lp;
+      double ax = a[i], ay = a[total + i], az = a[2 * total + i];
+      const double* iq = islot + S.ibase + p;
+      for (int k = 1; k < np; ++k) {
+        const double* o = iq + (size_t)(k - 1) * stride;
+        ax += o[0];
+        ay += o[npad];
+        az += o[2 * npad];
+      }
+      float e = 0.f;
+      for (int k = 0; k < np; ++k) e += iest[S.iebase + (size_t)k * npad + p];
+      const float4 rh = rhi[i];
+      const float rc = rlo[i].w;
+      const float xw = kEstNear * fmaxf(fabsf(rh.x), fmaxf(fabsf(rh.y), fabsf(rh.z)));
+      const float* q = slots + S.sbase + p;
+      const float* wq = wslots + S.wbase + it.b;
+#pragma unroll 4
+      for (int d = 0; d < dn; ++d) {
+        const float* qd = q + (size_t)d * stride;
+        const float fx = qd[0], fy = qd[npad], fz = qd[2 * npad];
+        const float w = fmaf(xw, rsqrt32(fmaxf(wq[(size_t)d * S.nb], rc)), 1.0f);
+        ax += (double)fx;
+        ay += (double)fy;
+        az += (double)fz;
+        e = fmaf(w * w, fmaf(fx, fx, fmaf(fy, fy, fz * fz)), e);
+      }
+      ax *= G;
+      ay *= G;
+      az *= G;
+      a[i] = ax;
+      a[total + i] = ay;
+      a[2 * total + i] = az;
+      flag = sqrt((double)e) * (kRescueScale * fabs(G)) > sqrt(ax * ax + ay * ay + az * az);
+    }
+    const unsigned long long mask = __ballot(flag);
+    if (mask) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&rcnt[it.sys], __popcll(mask));
+      base = __shfl(base, 0, 64);
+      if (flag) rlist[S.o + base + __popcll(mask & ((1ull << lane) - 1ull))] = p;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ plans
 struct EPlan {
   std::vector<int64_t> off;
@@ -414,14 +541,23 @@ struct EPlan {
   float4* d_rhi = nullptr;
   float4* d_rlo = nullptr;
   float* d_slots = nullptr;
+  // FP32C: the rescue's estimate slots, the systems' offsets and softenings
+  // on the device, and the per-system lists of flagged rows
+  float* d_iest = nullptr;
+  float* d_wslots = nullptr;
+  int64_t* d_off = nullptr;
+  double* d_eps = nullptr;
+  int* d_rcnt = nullptr;   // ncl
+  int* d_rlist = nullptr;  // total
 };
 
 std::mutex g_eplan_mu;
 std::vector<EPlan*> g_eplans;
 
 void free_eplan(EPlan* p) {
-  for (void* q : {(void*)p->d_sys, (void*)p->d_blocks, (void*)p->d_items, (void*)p->d_islot, (void*)p->d_wg_off, (void*)p->d_wg_list, (void*)p->d_rhi,
-                  (void*)p->d_rlo, (void*)p->d_slots})
+  for (void* q : {(void*)p->d_sys, (void*)p->d_blocks, (void*)p->d_items, (void*)p->d_islot, (void*)p->d_wg_off,
+                  (void*)p->d_wg_list, (void*)p->d_rhi, (void*)p->d_rlo, (void*)p->d_slots, (void*)p->d_iest,
+                  (void*)p->d_wslots, (void*)p->d_off, (void*)p->d_eps, (void*)p->d_rcnt, (void*)p->d_rlist})
     if (q) (void)hipFree(q);
   delete p;
 }
@@ -460,15 +596,19 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   p->device = device;
   p->ncl = ncl;
   p->total = off[ncl];
-  int per_cu = 0, per_cu1 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&esym_force_kernel<true, false>),
-                                                   kEBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, reinterpret_cast<const void*>(&esym_force_kernel<true, true>),
-                                                   kEBlock, 0) != hipSuccess) {
-    (void)hipGetLastError();
-    per_cu = per_cu1 = 1;
+  int per_cu = kEMaxPerCu;
+  for (const void* f : {reinterpret_cast<const void*>(&esym_force_kernel<true, false, false>),
+                        reinterpret_cast<const void*>(&esym_force_kernel<true, true, false>),
+                        reinterpret_cast<const void*>(&esym_force_kernel<true, false, true>),
+                        reinterpret_cast<const void*>(&esym_force_kernel<true, true, true>)}) {
+    int k = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, kEBlock, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      k = 1;
+    }
+    per_cu = std::min(per_cu, k);
   }
-  per_cu = std::max(1, std::min(kEMaxPerCu, std::min(per_cu, per_cu1)));
+  per_cu = std::max(1, per_cu);
   const int cap_wg = std::max(1, per_cu * cu_count(device));
   std::vector<ESys> sys(std::max(1, ncl));
   int64_t work = 0;  // block distances (the ordered block counted as one)
@@ -479,13 +619,15 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
   const int lp = (int)std::max<int64_t>(4, std::min<int64_t>(64, work / (4 * (int64_t)cap_wg * kEWaves)));
   std::vector<EItem> blocks, items;
   std::vector<double> cost;
-  int64_t sbase = 0, ibase = 0;
+  int64_t sbase = 0, ibase = 0, iebase = 0, wbase = 0;
   for (int c = 0; c < ncl; ++c) {
     const int64_t nc = off[c + 1] - off[c];
     ESys& S = sys[c];
     S.o = off[c];
     S.sbase = sbase;
     S.ibase = ibase;
+    S.iebase = iebase;
+    S.wbase = wbase;
     S.eps = eps[c];
     S.nc = (int)nc;
     S.nb = (int)((nc + 63) / 64);
@@ -495,6 +637,8 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
     S.lp = lp;
     sbase += (int64_t)S.dmax * 3 * S.nb * 64;
     ibase += (int64_t)((S.dmax + 1 + lp - 1) / lp - 1) * 3 * S.nb * 64;
+    iebase += (int64_t)((S.dmax + 1 + lp - 1) / lp) * S.nb * 64;
+    wbase += (int64_t)S.dmax * S.nb;
     for (int b = 0; b < S.nb; ++b) {
       const int ni = (int)std::min<int64_t>(64, nc - (int64_t)b * 64);
       const int dend = esym_dend(S, b);
@@ -533,6 +677,12 @@ int build_eplan(int32_t ncl, const int64_t* off, const double* eps, int precisio
             eupload(&p->d_wg_list, wg_list) && hipMalloc(&p->d_rhi, nrec * sizeof(float4)) == hipSuccess &&
             hipMalloc(&p->d_rlo, nrec * sizeof(float4)) == hipSuccess &&
             hipMalloc(&p->d_slots, sizeof(float) * (size_t)std::max<int64_t>(1, sbase)) == hipSuccess;
+  if (ok && precision == NBODY_FP32C)
+    ok = hipMalloc(&p->d_iest, sizeof(float) * (size_t)std::max<int64_t>(1, iebase)) == hipSuccess &&
+         hipMalloc(&p->d_wslots, sizeof(float) * (size_t)std::max<int64_t>(1, wbase)) == hipSuccess &&
+         eupload(&p->d_off, p->off) && eupload(&p->d_eps, p->eps) &&
+         hipMalloc(&p->d_rcnt, sizeof(int) * (size_t)std::max(1, ncl)) == hipSuccess &&
+         hipMalloc(&p->d_rlist, sizeof(int) * nrec) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     free_eplan(p);
@@ -550,24 +700,37 @@ EPlan* find_eplan(int32_t ncl, const int64_t* off, const double* eps, int precis
   return nullptr;
 }
 
-template <bool NEAR>
+// EST (FP32C with the rescue): each step's force also keeps the error
+// estimate, the reduction lists the flagged rows, and the batched rescue
+// recomputes them in FP64 before the next kick.
+template <bool NEAR, bool EST>
 int launch_esteps(const EPlan* p, double* x, double* v, double* a, const double* m, double dt, int64_t nsteps,
                   double G, bool acc_valid, bool excl, hipStream_t s) {
   if (p->total == 0 || (nsteps == 0 && acc_valid)) return NBODY_OK;
   const double h = 0.5 * dt;
   const unsigned ew = (unsigned)std::min<int64_t>(((int64_t)p->nblocks * 64 + 255) / 256, 4096);
   const unsigned kw = (unsigned)std::min<int64_t>((3 * p->total + 255) / 256, 4096);
+  int* rcnt = EST ? p->d_rcnt : nullptr;
   auto step = [&](int kicks) -> int {
     esym_publish_kernel<NEAR><<<ew, 256, 0, s>>>(p->nblocks, p->d_blocks, p->d_sys, p->total, x, v, a, m, p->d_rhi,
-                                                  p->d_rlo, h, dt, kicks);
+                                                  p->d_rlo, h, dt, kicks, rcnt, p->ncl);
     NB_LAUNCH_CHECK("esym_publish_kernel");
     if (excl)
-      esym_force_kernel<NEAR, true><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
-                                                               p->d_rhi, p->d_rlo, a, p->d_islot, p->d_slots, p->total);
+      esym_force_kernel<NEAR, true, EST><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
+                                                                    p->d_rhi, p->d_rlo, a, p->d_islot, p->d_slots,
+                                                                    p->total, p->d_iest, p->d_wslots);
     else
-      esym_force_kernel<NEAR, false><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
-                                                                p->d_rhi, p->d_rlo, a, p->d_islot, p->d_slots, p->total);
+      esym_force_kernel<NEAR, false, EST><<<p->nwg, kEBlock, 0, s>>>(p->d_sys, p->d_items, p->d_wg_off, p->d_wg_list,
+                                                                     p->d_rhi, p->d_rlo, a, p->d_islot, p->d_slots,
+                                                                     p->total, p->d_iest, p->d_wslots);
     NB_LAUNCH_CHECK("esym_force_kernel");
+    if constexpr (EST) {
+      esym_reduce_est_kernel<<<ew, 256, 0, s>>>(p->nblocks, p->d_blocks, p->d_sys, p->total, p->d_islot, p->d_slots,
+                                                p->d_iest, p->d_wslots, p->d_rhi, p->d_rlo, a, G, p->d_rcnt,
+                                                p->d_rlist);
+      NB_LAUNCH_CHECK("esym_reduce_est_kernel");
+      return launch_ens_rescue(p->ncl, p->d_off, p->d_eps, p->total, x, m, G, excl, p->d_rcnt, p->d_rlist, a, s);
+    }
     esym_reduce_kernel<<<dim3(ew, 3), 256, 0, s>>>(p->nblocks, p->d_blocks, p->d_sys, p->total, p->d_islot,
                                                    p->d_slots, a, G);
     NB_LAUNCH_CHECK("esym_reduce_kernel");
@@ -591,8 +754,8 @@ int run_batched_stream(int32_t ncl, const int64_t* off, const double* eps, doubl
                        bool acc_valid, int bitem, bool per_step, bool rescue, hipStream_t s);
 
 // Mode 4.  FP64, and layouts whose slots would exceed kESlotCap, run the
-// ordered per-step wave items (mode 3) instead, with the FP32C rescue as asked.
-// Mode 4 itself has no rescue.
+// ordered per-step wave items (mode 3) instead; FP32C takes the rescue as
+// asked in either form.
 int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* x, double* v, double* a,
                     const double* m, double dt, int64_t nsteps, double G, int precision, bool excl, bool acc_valid,
                     bool rescue, hipStream_t s) {
@@ -613,8 +776,10 @@ int run_batched_sym(int32_t ncl, const int64_t* off, const double* eps, double* 
     if (st) return st;
     g_eplans.push_back(p);
   }
-  if (precision == NBODY_FP32C) return launch_esteps<true>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
-  return launch_esteps<false>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  if (precision == NBODY_FP32C && rescue)
+    return launch_esteps<true, true>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  if (precision == NBODY_FP32C) return launch_esteps<true, false>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
+  return launch_esteps<false, false>(p, x, v, a, m, dt, nsteps, G, acc_valid, excl, s);
 }
 
 // The untuned default takes the symmetric items when the layout's block pairs

@@ -20,10 +20,12 @@ constexpr int kSW = kSL / 64;       // waves per workgroup
 constexpr int kDiagG = 4;          // lane groups of the block-diagonal kernels, each over kSI / kDiagG of the j
 // Workgroups per block of the block-diagonal kernels (each over a slice of the
 // j, the slices summed by the slot-sum kernel): several where the blocks are
-// too few to fill the chip, one where the slices' extra sums would only cost
-// memory.
-inline int diag_slices(int nb) { return nb < 256 ? 4 : 1; }
-static_assert(kSI % (4 * kDiagG * 16) == 0, "each diagonal lane group takes whole runs of 16 j");
+// too few to fill the chip (eight below 64 blocks, 32768 particles, so that
+// those sizes still launch about one workgroup per CU), one where the slices'
+// extra sums would only cost memory.
+constexpr int kDiagMaxSlices = 8;
+inline int diag_slices(int nb) { return nb < 64 ? kDiagMaxSlices : nb < 256 ? 4 : 1; }
+static_assert(kSI % (kDiagMaxSlices * kDiagG * 16) == 0, "each diagonal lane group takes whole runs of 16 j");
 
 // v rotated within each row of 16 lanes: lane r gets the value of lane (r - K) mod 16.
 template <int K>

@@ -215,13 +215,12 @@ def test_ens_sym_fp64_runs_ordered_items(nb):
 
 
 def test_ens_sym_untuned_default(nb):
-    """Without a forced or tuned choice, FP32C runs the per-step wave items
-    (mode 3), the batched form that carries the FP64 rescue of ill-conditioned
-    rows; with the rescue off it runs mode 4 on a layout whose systems span
-    several blocks of 64 and mode 3 on one of single-block systems (bitwise
-    the forced modes' states)."""
-    for rescue, sizes, mode in ((0, [4096, 3000, 700, 129], 3), (2, [4096, 3000, 700, 129], 4),
-                                (2, [64, 40, 64, 17], 3)):
+    """Without a forced or tuned choice, FP32C runs mode 4 on a layout whose
+    systems span several blocks of 64 and mode 3 on one of single-block
+    systems, with the FP64 rescue of ill-conditioned rows (the default) and
+    without it (bitwise the forced modes' states)."""
+    for rescue, sizes, mode in ((0, [4096, 3000, 700, 129], 4), (2, [4096, 3000, 700, 129], 4),
+                                (0, [64, 40, 64, 17], 3), (2, [64, 40, 64, 17], 3)):
         off, epsv, x, v, m = ics.ensemble(len(sizes), seed=47, sizes=sizes)
         tx, tv, tm = dev(x), dev(v), dev(m)
         ta = torch.empty_like(tx)

@@ -89,53 +89,73 @@ def _layout():
     return off, epsv, np.concatenate(xs, axis=1), np.concatenate(ms)
 
 
-def test_rescue_batched_wave_items(nb, oracle_mod):
-    """The batched per-step wave items (mode 3, the FP32C default) with the
-    rescue: a(x) of every system within 1e-5 of the oracle; without the
-    rescue some row exceeds it."""
+@pytest.mark.parametrize("mode", [3, 4])
+def test_rescue_batched_per_step_items(nb, oracle_mod, mode):
+    """The batched per-step items, ordered (mode 3) and symmetric (mode 4, the
+    FP32C default on this layout), with the rescue: a(x) of every system within
+    1e-5 of the oracle, and some rows recomputed in FP64 (within 1e-12 of the
+    oracle, which no FP32C row comes near); without the rescue no row is, and
+    in mode 3 some row exceeds 1e-5."""
     off, epsv, x, m = _layout()
-    worst = {}
+    worst, exact = {}, {}
     for rescue in (0, 2):
         tx, tv, tm = dev(x), dev(np.zeros_like(x)), dev(m)
         ta = torch.empty_like(tx)
-        nb.nbody_set_config(bsplit=3, rescue=rescue)
+        print("batched mode %d rescue %d" % (mode, rescue), flush=True)
+        nb.nbody_set_config(bsplit=mode, rescue=rescue)
         try:
             nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 0, precision="fp32c", check_finite=True)
         finally:
             nb.nbody_set_config()
         a = ta.cpu().numpy()
-        worst[rescue] = max(row_rel(a[:, off[c]:off[c + 1]],
-                                    oracle_mod.accel(x[:, off[c]:off[c + 1]], m[off[c]:off[c + 1]], eps=float(epsv[c]))).max()
-                            for c in range(len(epsv)))
-    print("batched mode 3: rescue %.2e, without %.2e" % (worst[0], worst[2]))
-    assert worst[0] <= 1e-5 < worst[2]
+        err = np.concatenate([row_rel(a[:, off[c]:off[c + 1]],
+                                      oracle_mod.accel(x[:, off[c]:off[c + 1]], m[off[c]:off[c + 1]],
+                                                       eps=float(epsv[c])))
+                              for c in range(len(epsv))])
+        worst[rescue], exact[rescue] = err.max(), int((err < 1e-12).sum())
+    print("batched mode %d: rescue %.2e (%d rows in FP64), without %.2e" % (mode, worst[0], exact[0], worst[2]))
+    assert worst[0] <= 1e-5
+    assert exact[0] > 0 and exact[2] == 0
+    if mode == 3:
+        assert worst[2] > 1e-5
 
 
-def test_rescue_batched_explicit_needs_wave_items(nb):
+def test_rescue_batched_explicit_needs_per_step_items(nb):
     """rescue = 1 (asked for explicitly) with a batched mode that has no rescue
-    is refused; rescue = 0 (automatic) runs such a mode without it."""
+    (the resident kernel, mode 0) is refused; rescue = 0 (automatic) runs such a
+    mode without it."""
     off, epsv, x, m = _layout()
     tx, tv, tm = dev(x), dev(np.zeros_like(x)), dev(m)
     ta = torch.empty_like(tx)
-    nb.nbody_set_config(bsplit=4, rescue=1)
+    nb.nbody_set_config(bsplit=0, bpass=4, rescue=1)  # bpass forces the resident kernel
     try:
         with pytest.raises(nb.NBodyError) as ei:
             nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 0, precision="fp32c")
         assert ei.value.status == nb.NBODY_EUNSUPPORTED
     finally:
         nb.nbody_set_config()
-    nb.nbody_set_config(bsplit=4)
+    nb.nbody_set_config(bsplit=0, bpass=4)
     try:
         nb.nbody_step_batched(off, epsv, tx, tv, ta, tm, 1.0 / 512, 0, precision="fp32c", check_finite=True)
     finally:
         nb.nbody_set_config()
 
 
-def test_rescue_batched_graph_replays(nb):
-    """Two steps of the batched wave items with the rescue captured in a HIP
-    graph and replayed three times, with eager work between the replays: every
-    replay equals the eager run from the same state (the flag count is cleared
-    by a kernel, not a memset)."""
+@pytest.mark.parametrize("mode", [3, 4])
+def test_rescue_batched_graph_replays(nb, mode):
+    """Two steps of the batched per-step items (ordered and symmetric) with the
+    rescue captured in a HIP graph and replayed three times, with eager work
+    between the replays: every replay equals the eager run from the same state
+    (the flag counts are cleared by a kernel, not a memset)."""
+    print("graph replays, batched mode %d" % mode, flush=True)
+    nb.nbody_set_config(bsplit=mode)
+    try:
+        _graph_replays(nb)
+    finally:
+        nb.nbody_set_config()
+
+
+def _graph_replays(nb):
     off, epsv, x, m = _layout()
     v = np.random.default_rng(1).standard_normal(x.shape) * 0.1
     tm = dev(m)
