@@ -51,7 +51,6 @@
 namespace nb {
 namespace {
 
-constexpr int kRB = 256;           // lanes per workgroup of the rescue kernel
 constexpr int64_t kRSmall = 131072;  // systems up to this size take one row per workgroup pass
 
 // One thread per particle: sums the nslices slices of the estimate (stride
@@ -81,15 +80,18 @@ __global__ void flag_rows_kernel(int n, const float* __restrict__ est, int nslic
 // Recomputes the listed rows of a = G sum_j m_j d / (|d|^2 + eps^2)^(3/2) in
 // FP64: each pass takes R rows of the list (8 for large systems, where each j
 // record then serves eight rows; 1 for small ones, where the few flagged rows
-// should run side by side), the lanes split the j-range (lane t takes j = t,
-// t + 256, ...), and the lane sums are added in a fixed order: a butterfly
-// inside each wave, then the four wave sums in wave order.
-template <int R>
-__global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* __restrict__ x,
-                                                          const double* __restrict__ m, double eps, double G,
-                                                          int excl, const int* __restrict__ list,
-                                                          const int* __restrict__ count, double* __restrict__ a) {
-  __shared__ double red[3][R][kRB / 64];
+// should run side by side), the B lanes split the j-range (lane t takes
+// j = t, t + B, ...), loading U records ahead of the arithmetic (the records
+// come from L2 or HBM, and few waves are resident when few rows are flagged),
+// and the lane sums are added in a fixed order: a butterfly inside each wave,
+// then the wave sums in wave order.
+template <int R, int B, int U>
+__global__ __launch_bounds__(B) void rescue_rows_kernel(int n, const double* __restrict__ x,
+                                                        const double* __restrict__ m, double eps, double G,
+                                                        int excl, const int* __restrict__ list,
+                                                        const int* __restrict__ count, double* __restrict__ a) {
+  constexpr int W = B / 64;
+  __shared__ double red[3][R][W];
   const int t = threadIdx.x;
   const int wave = t / 64, lane = t % 64;
   const int cnt = *count;
@@ -106,19 +108,33 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
       zi[k] = x[2 * n + i];
       sx[k] = sy[k] = sz[k] = 0.0;
     }
-#pragma unroll(R == 1 ? 4 : 1)
-    for (int j = t; j < n; j += kRB) {
-      const double xj = x[j], yj = x[n + j], zj = x[2 * n + j], mj = m[j];
+    for (int j0 = t; j0 < n; j0 += U * B) {
+      // U records per lane, all loaded before any is used; past n: far away
+      // and massless, so they add exact zeros
+      double xj[U], yj[U], zj[U], mj[U];
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const double dx = xj - xi[k], dy = yj - yi[k], dz = zj - zi[k];
-        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-        const double ri = rsqrt64(r2);
-        double s = (mj * ri) * (ri * ri);
-        if (excl && j == row[k]) s = 0.0;
-        sx[k] = fma(s, dx, sx[k]);
-        sy[k] = fma(s, dy, sy[k]);
-        sz[k] = fma(s, dz, sz[k]);
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * B;
+        const bool in = j < n;
+        xj[u] = in ? x[j] : 1.0e30;
+        yj[u] = in ? x[n + j] : 1.0e30;
+        zj[u] = in ? x[2 * n + j] : 1.0e30;
+        mj[u] = in ? m[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * B;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const double dx = xj[u] - xi[k], dy = yj[u] - yi[k], dz = zj[u] - zi[k];
+          const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+          const double ri = rsqrt64(r2);
+          double s = (mj[u] * ri) * (ri * ri);
+          if (excl && j == row[k]) s = 0.0;
+          sx[k] = fma(s, dx, sx[k]);
+          sy[k] = fma(s, dy, sy[k]);
+          sz[k] = fma(s, dz, sz[k]);
+        }
       }
     }
 #pragma unroll
@@ -142,7 +158,7 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
       for (int c = 0; c < 3; ++c) {
         v[c] = red[c][t][0];
 #pragma unroll
-        for (int w = 1; w < kRB / 64; ++w) v[c] += red[c][t][w];
+        for (int w = 1; w < W; ++w) v[c] += red[c][t][w];
       }
       a[i] = G * v[0];
       a[n + i] = G * v[1];
@@ -151,6 +167,11 @@ __global__ __launch_bounds__(kRB) void rescue_rows_kernel(int n, const double* _
     __syncthreads();
   }
 }
+
+// Launch shapes of the rescue, small systems (one row per pass) and large ones
+// (eight rows per pass): lanes per workgroup and records loaded ahead.
+constexpr int kRBSmall = 512, kRUSmall = 8;
+constexpr int kRBLarge = 1024, kRULarge = 4;
 
 }  // namespace
 
@@ -161,12 +182,15 @@ int launch_rescue(int64_t n, const double* x, const double* m, double eps, doubl
   flag_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((int)n, est, nslices, stride, a, scale, list, count);
   NB_LAUNCH_CHECK("flag_rows_kernel");
   const int cus = cu_count(current_device());
+  // about as many workgroups as are resident at once; each strides over the list
   if (n <= kRSmall) {
-    const unsigned grid = (unsigned)std::min<int64_t>(n, 8 * (int64_t)cus);
-    rescue_rows_kernel<1><<<grid, kRB, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list, count, a);
+    const unsigned grid = (unsigned)std::min<int64_t>(n, (2048 / kRBSmall) * (int64_t)cus);
+    rescue_rows_kernel<1, kRBSmall, kRUSmall><<<grid, kRBSmall, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list,
+                                                                        count, a);
   } else {
-    const unsigned grid = (unsigned)std::min<int64_t>((n + 7) / 8, 4 * (int64_t)cus);
-    rescue_rows_kernel<8><<<grid, kRB, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list, count, a);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 7) / 8, (2048 / kRBLarge) * (int64_t)cus);
+    rescue_rows_kernel<8, kRBLarge, kRULarge><<<grid, kRBLarge, 0, s>>>((int)n, x, m, eps, G, excl ? 1 : 0, list,
+                                                                        count, a);
   }
   NB_LAUNCH_CHECK("rescue_rows_kernel");
   return NBODY_OK;
