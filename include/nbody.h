@@ -88,8 +88,11 @@ typedef struct nbody_params {
  * From 49152 particles on in FP32C and FP32, from 8192 in FP64 (or as
  * nbody_config.pairs says), each unordered pair is evaluated once and applied
  * to both particles, with sums in a fixed order; this uses a workspace of up
- * to about 2 GiB (staged records and per-distance sums) and several launches
- * per call.
+ * to about 4 GiB (staged records and two sets of per-distance sums) and
+ * several launches per call: when the half ring takes several launches, each
+ * one's per-distance sums are added on a second stream of the library's while
+ * the next launch runs, and the caller's stream waits for that stream before
+ * the call's last kernel (a captured call records both streams' work).
  * n == 0 is a no-op.  x, m, a must not alias.  Errors: NBODY_EINVAL for null
  * pointers with n > 0, n < 0, n > 2^29, eps < 0, eps == 0 without
  * NBODY_EXCLUDE_SELF, non-finite G, unknown precision; NBODY_ENOMEM if the
@@ -324,7 +327,7 @@ typedef struct nbody_config {
                       applied to both particles (a_j gets the opposite of i's
                       term scaled by m_i / m_j), results summed in a fixed order
                       (reproducible), at the cost of a workspace of about
-                      2 GiB for large n and, in FP32C/FP32, an FP32 sum of up
+                      4 GiB for large n and, in FP32C/FP32, an FP32 sum of up
                       to 512 terms per j before the FP64 sums */
   int32_t rescue;  /* FP32C force of nbody_accel, nbody_accel_noalloc, the
                       KDK steps of nbody_step and of the adjoint's recompute,

@@ -22,6 +22,7 @@ int run_traj_grad(int64_t n, const double* ckx, const double* ckv, int64_t every
 void release_batched_plans();
 void release_stream_plans();
 void release_sym_ensemble_plans();
+void release_side_streams();
 bool sym_ensemble_default(int32_t ncl, const int64_t* off);
 
 // ------------------------------------------------------------------ errors
@@ -820,6 +821,7 @@ int nbody_finalize(void) {
     std::lock_guard<std::mutex> lk(g_tb_mu);
     g_tuned_batch.clear();
   }
+  release_side_streams();
   release_workspaces();
   return NBODY_OK;
 }

@@ -30,6 +30,8 @@
 // FP32C (positions rounded to FP32 plus the near-field repair of the ordered
 // kernel: pairs closer than the larger repair radius of their two particles get
 // float-float displacements, for both sides) and FP32 (no repair) are built.
+#include <mutex>
+
 #include "sym_common.h"
 
 namespace nb {
@@ -503,7 +505,69 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
   }
 }
 
+// A second stream per device: the slot sums of one half-ring chunk run on it
+// while the next chunk's pair kernel runs on the caller's stream (the sums
+// stream HBM, the pair kernel is bound by VALU issue), ordered by events:
+// a chunk's slot sum waits for its pair kernel, the pair kernel two chunks
+// later (which reuses the chunk's slot buffer) waits for that slot sum, and
+// the caller's stream waits for the last one.  Created on first use outside
+// stream capture (a captured call then records the fork and the join into
+// the graph), kept until nbody_finalize; the mutex keeps one call's records
+// and waits together.
+struct SideStream {
+  hipStream_t side = nullptr;
+  hipEvent_t pair[2] = {nullptr, nullptr}, red[2] = {nullptr, nullptr}, join = nullptr;
+};
+constexpr int kSideDev = 64;
+std::mutex g_side_mu;
+SideStream g_side[kSideDev];
+
+void destroy_side(SideStream& S) {
+  for (hipEvent_t* e : {&S.pair[0], &S.pair[1], &S.red[0], &S.red[1], &S.join})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+  if (S.side) (void)hipStreamDestroy(S.side);
+  S.side = nullptr;
+}
+
+// The device's side stream and events (g_side_mu held), or nullptr: then the
+// caller runs everything on its own stream.
+SideStream* side_stream(int dev, hipStream_t s) {
+  if (dev < 0 || dev >= kSideDev) return nullptr;
+  SideStream& S = g_side[dev];
+  if (S.side) return &S;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  bool ok = hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking) == hipSuccess;
+  for (hipEvent_t* e : {&S.pair[0], &S.pair[1], &S.red[0], &S.red[1], &S.join})
+    ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    destroy_side(S);
+    return nullptr;
+  }
+  return &S;
+}
+
 }  // namespace
+
+void release_side_streams() {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  for (int d = 0; d < kSideDev; ++d)
+    if (g_side[d].side) {
+      (void)hipSetDevice(d);
+      (void)hipStreamSynchronize(g_side[d].side);
+      destroy_side(g_side[d]);
+    }
+  (void)hipSetDevice(prev);
+}
 
 int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, double G, double eps, int precision,
                      bool excl, const PairConfig& cfg, hipStream_t s) {
@@ -532,6 +596,17 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
   const int nparts = D * kSTiles / T;
+  const int nchunks = dmax > 0 ? (dmax + D - 1) / D : 0;
+  // with two chunks or more and the library's own workspace, the slot sums run
+  // on the side stream, and the slots (pj, pi, pe, pw) come twice
+  std::unique_lock<std::mutex> side_lk(g_side_mu, std::defer_lock);
+  SideStream* side = nullptr;
+  if (nchunks >= 2 && !cfg.scratch) {
+    side_lk.lock();
+    side = side_stream(current_device(), s);
+    if (!side) side_lk.unlock();
+  }
+  const int nbuf = side ? 2 : 1;
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(float) * 3 * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * 3 * (size_t)npad * nparts;
@@ -541,26 +616,33 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const size_t pw_bytes = rescue ? sizeof(float) * (size_t)npad * D : 0;
   const size_t eo_bytes = rescue ? sizeof(float) * (1 + pds) * (size_t)npad : 0;  // eo [npad], ed [pds][npad]
   const size_t list_bytes = rescue ? sizeof(int) * (size_t)npad + count_bytes : 0;  // the count, then the list
-  char* ws = static_cast<char*>(pair_scratch(
-      cfg, pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes + pe_bytes + pw_bytes + eo_bytes + list_bytes, &st));
+  const size_t buf_bytes = pj_bytes + pi_bytes + pe_bytes + pw_bytes;  // one set of slots
+  char* ws = static_cast<char*>(
+      pair_scratch(cfg, nbuf * buf_bytes + pd_bytes + 2 * rec_bytes + eo_bytes + list_bytes, &st));
   if (!ws) return st;
   SymArgs A;
   A.x = x; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
   A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
   A.fx = std::max(kNearX, kNearN / std::cbrt((float)n));
-  A.pj = reinterpret_cast<float*>(ws);
-  A.pi = reinterpret_cast<double*>(ws + pj_bytes);
-  double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);
-  float4* rhi = reinterpret_cast<float4*>(ws + pj_bytes + pi_bytes + pd_bytes);
+  // slot set b: pj, pi, pe, pw
+  auto slots = [&](int b, SymArgs& Q) {
+    char* q = ws + (size_t)b * buf_bytes;
+    Q.pj = reinterpret_cast<float*>(q);
+    Q.pi = reinterpret_cast<double*>(q + pj_bytes);
+    Q.pe = rescue ? reinterpret_cast<float*>(q + pj_bytes + pi_bytes) : nullptr;
+    Q.pw = rescue ? reinterpret_cast<float*>(q + pj_bytes + pi_bytes + pe_bytes) : nullptr;
+  };
+  slots(0, A);
+  char* fixed = ws + nbuf * buf_bytes;
+  double* pd = reinterpret_cast<double*>(fixed);
+  float4* rhi = reinterpret_cast<float4*>(fixed + pd_bytes);
   float4* rlo = rhi + npad;
-  char* tail = ws + pj_bytes + pi_bytes + pd_bytes + 2 * rec_bytes;
+  char* tail = fixed + pd_bytes + 2 * rec_bytes;
   A.rhi = rhi;
   A.rlo = rlo;
-  A.pe = rescue ? reinterpret_cast<float*>(tail) : nullptr;
-  A.pw = rescue ? reinterpret_cast<float*>(tail + pe_bytes) : nullptr;
-  float* eo = rescue ? reinterpret_cast<float*>(tail + pe_bytes + pw_bytes) : nullptr;
+  float* eo = rescue ? reinterpret_cast<float*>(tail) : nullptr;
   float* ed = rescue ? eo + npad : nullptr;
-  int* list = rescue ? reinterpret_cast<int*>(tail + pe_bytes + pw_bytes + eo_bytes) : nullptr;
+  int* list = rescue ? reinterpret_cast<int*>(tail + eo_bytes) : nullptr;
   const unsigned sg = (unsigned)((npad + 255) / 256);
   if (near) sym_stage_kernel<true><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
   else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
@@ -580,18 +662,34 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
                                             1, 1, A.pe, A.pw, ed, eo, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   } else {
-    const int nchunks = (dmax + D - 1) / D;
+    auto check = [](hipError_t e, const char* what) { return e == hipSuccess ? NBODY_OK : hip_fail(e, what); };
     for (int c = 0; c < nchunks; ++c) {
-      A.d_lo = 1 + c * D;
+      const int b = c % nbuf;
+      SymArgs B = A;
+      slots(b, B);
+      B.d_lo = 1 + c * D;
+      // the pair kernel that reuses slot set b waits for the slot sum of chunk c - 2
+      if (side && c >= 2 && (st = check(hipStreamWaitEvent(s, side->red[b], 0), "hipStreamWaitEvent"))) return st;
       const unsigned grid = (unsigned)nb * (unsigned)nparts;
-      if (rescue) sym_accel_kernel<true, true><<<grid, kSL, 0, s>>>(A);
-      else if (near) sym_accel_kernel<true, false><<<grid, kSL, 0, s>>>(A);
-      else sym_accel_kernel<false, false><<<grid, kSL, 0, s>>>(A);
+      if (rescue) sym_accel_kernel<true, true><<<grid, kSL, 0, s>>>(B);
+      else if (near) sym_accel_kernel<true, false><<<grid, kSL, 0, s>>>(B);
+      else sym_accel_kernel<false, false><<<grid, kSL, 0, s>>>(B);
       NB_LAUNCH_CHECK("sym_accel_kernel");
-      sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
-                                              a, nullptr, G, c == 0, c == nchunks - 1, A.pe, A.pw, ed, eo, pds);
+      hipStream_t rs = s;
+      if (side) {
+        if ((st = check(hipEventRecord(side->pair[b], s), "hipEventRecord")) ||
+            (st = check(hipStreamWaitEvent(side->side, side->pair[b], 0), "hipStreamWaitEvent")))
+          return st;
+        rs = side->side;
+      }
+      sym_reduce_kernel<3, float><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, B.d_lo, D, nparts, B.pj, B.pi,
+                                               pd, a, nullptr, G, c == 0, c == nchunks - 1, B.pe, B.pw, ed, eo, pds);
       NB_LAUNCH_CHECK("sym_reduce_kernel");
+      if (side && (st = check(hipEventRecord(side->red[b], rs), "hipEventRecord"))) return st;
     }
+    if (side && ((st = check(hipEventRecord(side->join, side->side), "hipEventRecord")) ||
+                 (st = check(hipStreamWaitEvent(s, side->join, 0), "hipStreamWaitEvent"))))
+      return st;
   }
   if (rescue) return launch_rescue(n, x, m, eps, G, excl, eo, 1, (size_t)npad, a, list + 64, list, s);
   return NBODY_OK;
