@@ -6,6 +6,8 @@
 // its term applied to both particles; the layout is described in sym_pairs.hip.
 #pragma once
 
+#include <mutex>
+
 #include "pair_math.h"
 
 namespace nb {
@@ -170,6 +172,55 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
 }
 
 }  // namespace
+
+// A second stream per device for the symmetric evaluations: their
+// block-diagonal kernel and their slot sums run on it while the caller's
+// stream runs the half ring's pair kernels (the slot sums stream HBM, the pair
+// kernels are bound by VALU issue), ordered by events.  Created on first use
+// outside stream capture (a captured call then records the fork and the join
+// into the graph) and kept until nbody_finalize.
+struct SideStream {
+  hipStream_t side = nullptr;
+  hipEvent_t stage = nullptr, pair[2] = {nullptr, nullptr}, red[2] = {nullptr, nullptr}, join = nullptr;
+};
+
+// The current device's side stream, with lk (the side streams' mutex, which
+// keeps one call's records and waits together) locked; or nullptr, lk
+// unlocked, where there is none: the caller then runs on its own stream.
+SideStream* acquire_side_stream(hipStream_t s, std::unique_lock<std::mutex>& lk);
+
+// The launches of one symmetric evaluation after its staging kernel on s:
+// diag(stream) launches the block-diagonal kernel, pair(c, b) the pair kernel
+// of half-ring chunk c on s, writing slot set b = c % nbuf, and sum(c, b,
+// stream) that chunk's slot sum.  Without a side stream everything runs on s
+// in that order.  With one, the diagonal kernel waits for the staging and the
+// slot sums run after it on the side stream, each after its pair kernel; a
+// pair kernel that reuses a slot set waits for the slot sum that last read
+// it, and s waits for the last slot sum before it goes on.
+template <class Diag, class Pair, class Sum>
+int run_sym_chunks(SideStream* side, hipStream_t s, int nchunks, int nbuf, Diag diag, Pair pair, Sum sum) {
+  auto ok = [](hipError_t e, const char* what) { return e == hipSuccess ? NBODY_OK : hip_fail(e, what); };
+  int st = NBODY_OK;
+  const hipStream_t rs = side ? side->side : s;
+  if (side && ((st = ok(hipEventRecord(side->stage, s), "hipEventRecord")) ||
+               (st = ok(hipStreamWaitEvent(rs, side->stage, 0), "hipStreamWaitEvent"))))
+    return st;
+  if ((st = diag(rs))) return st;
+  for (int c = 0; c < nchunks; ++c) {
+    const int b = c % nbuf;
+    if (side && c >= nbuf && (st = ok(hipStreamWaitEvent(s, side->red[b], 0), "hipStreamWaitEvent"))) return st;
+    if ((st = pair(c, b))) return st;
+    if (side && ((st = ok(hipEventRecord(side->pair[b], s), "hipEventRecord")) ||
+                 (st = ok(hipStreamWaitEvent(rs, side->pair[b], 0), "hipStreamWaitEvent"))))
+      return st;
+    if ((st = sum(c, b, rs))) return st;
+    if (side && (st = ok(hipEventRecord(side->red[b], rs), "hipEventRecord"))) return st;
+  }
+  if (side && ((st = ok(hipEventRecord(side->join, rs), "hipEventRecord")) ||
+               (st = ok(hipStreamWaitEvent(s, side->join, 0), "hipStreamWaitEvent"))))
+    return st;
+  return NBODY_OK;
+}
 
 // Chunking of the half ring for n particles, with slot_bytes bytes of j-side
 // sums (sum_bytes of them the sums themselves, the rest error estimates) per

@@ -505,25 +505,12 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym_diag_kernel(SymArgs A, double
   }
 }
 
-// A second stream per device: the slot sums of one half-ring chunk run on it
-// while the next chunk's pair kernel runs on the caller's stream (the sums
-// stream HBM, the pair kernel is bound by VALU issue), ordered by events:
-// a chunk's slot sum waits for its pair kernel, the pair kernel two chunks
-// later (which reuses the chunk's slot buffer) waits for that slot sum, and
-// the caller's stream waits for the last one.  Created on first use outside
-// stream capture (a captured call then records the fork and the join into
-// the graph), kept until nbody_finalize; the mutex keeps one call's records
-// and waits together.
-struct SideStream {
-  hipStream_t side = nullptr;
-  hipEvent_t pair[2] = {nullptr, nullptr}, red[2] = {nullptr, nullptr}, join = nullptr;
-};
 constexpr int kSideDev = 64;
 std::mutex g_side_mu;
 SideStream g_side[kSideDev];
 
 void destroy_side(SideStream& S) {
-  for (hipEvent_t* e : {&S.pair[0], &S.pair[1], &S.red[0], &S.red[1], &S.join})
+  for (hipEvent_t* e : {&S.stage, &S.pair[0], &S.pair[1], &S.red[0], &S.red[1], &S.join})
     if (*e) {
       (void)hipEventDestroy(*e);
       *e = nullptr;
@@ -532,29 +519,27 @@ void destroy_side(SideStream& S) {
   S.side = nullptr;
 }
 
-// The device's side stream and events (g_side_mu held), or nullptr: then the
-// caller runs everything on its own stream.
-SideStream* side_stream(int dev, hipStream_t s) {
+}  // namespace
+
+SideStream* acquire_side_stream(hipStream_t s, std::unique_lock<std::mutex>& lk) {
+  const int dev = current_device();
   if (dev < 0 || dev >= kSideDev) return nullptr;
+  lk = std::unique_lock<std::mutex>(g_side_mu);
   SideStream& S = g_side[dev];
   if (S.side) return &S;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  bool ok = hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking) == hipSuccess;
-  for (hipEvent_t* e : {&S.pair[0], &S.pair[1], &S.red[0], &S.red[1], &S.join})
+  bool ok = hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+            hipStreamCreateWithFlags(&S.side, hipStreamNonBlocking) == hipSuccess;
+  for (hipEvent_t* e : {&S.stage, &S.pair[0], &S.pair[1], &S.red[0], &S.red[1], &S.join})
     ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     destroy_side(S);
+    lk.unlock();
     return nullptr;
   }
   return &S;
 }
-
-}  // namespace
 
 void release_side_streams() {
   std::lock_guard<std::mutex> lk(g_side_mu);
@@ -597,15 +582,13 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   const int64_t npad = (int64_t)nb * kSI;
   const int nparts = D * kSTiles / T;
   const int nchunks = dmax > 0 ? (dmax + D - 1) / D : 0;
-  // with two chunks or more and the library's own workspace, the slot sums run
-  // on the side stream, and the slots (pj, pi, pe, pw) come twice
-  std::unique_lock<std::mutex> side_lk(g_side_mu, std::defer_lock);
-  SideStream* side = nullptr;
-  if (nchunks >= 2 && !cfg.scratch) {
-    side_lk.lock();
-    side = side_stream(current_device(), s);
-    if (!side) side_lk.unlock();
-  }
+  // with two half-ring chunks or more and the library's own workspace, the
+  // block-diagonal kernel and the slot sums run on the side stream, and the
+  // slots come twice, so that a chunk's pair kernel need not wait for the
+  // previous chunk's slot sum (with one chunk the cross-stream waits cost more
+  // than the overlap gains: 15 us of a 0.15 ms evaluation at 16384)
+  std::unique_lock<std::mutex> side_lk;
+  SideStream* side = nchunks >= 2 && !cfg.scratch ? acquire_side_stream(s, side_lk) : nullptr;
   const int nbuf = side ? 2 : 1;
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(float) * 3 * (size_t)npad * D;
@@ -648,48 +631,44 @@ int launch_sym_accel(int64_t n, const double* x, const double* m, double* a, dou
   else sym_stage_kernel<false><<<sg, 256, 0, s>>>(A, rhi, rlo, list);
   NB_LAUNCH_CHECK("sym_stage_kernel");
   const dim3 dg((unsigned)nb, (unsigned)pds);
-  if (near) {
-    if (excl) sym_diag_kernel<true, true><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
-    else sym_diag_kernel<true, false><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
-  } else {
-    if (excl) sym_diag_kernel<false, true><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
-    else sym_diag_kernel<false, false><<<dg, kSL * kDiagG, 0, s>>>(A, pd, ed);
-  }
-  NB_LAUNCH_CHECK("sym_diag_kernel");
+  auto diag = [&](hipStream_t ds) -> int {
+    if (near) {
+      if (excl) sym_diag_kernel<true, true><<<dg, kSL * kDiagG, 0, ds>>>(A, pd, ed);
+      else sym_diag_kernel<true, false><<<dg, kSL * kDiagG, 0, ds>>>(A, pd, ed);
+    } else {
+      if (excl) sym_diag_kernel<false, true><<<dg, kSL * kDiagG, 0, ds>>>(A, pd, ed);
+      else sym_diag_kernel<false, false><<<dg, kSL * kDiagG, 0, ds>>>(A, pd, ed);
+    }
+    NB_LAUNCH_CHECK("sym_diag_kernel");
+    return NBODY_OK;
+  };
   const dim3 rg((unsigned)((n + 255) / 256), 3);
   if (dmax == 0) {
+    if ((st = diag(s))) return st;
     sym_reduce_kernel<3, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a, nullptr, G,
                                             1, 1, A.pe, A.pw, ed, eo, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
   } else {
-    auto check = [](hipError_t e, const char* what) { return e == hipSuccess ? NBODY_OK : hip_fail(e, what); };
-    for (int c = 0; c < nchunks; ++c) {
-      const int b = c % nbuf;
+    auto pair = [&](int c, int b) -> int {
       SymArgs B = A;
       slots(b, B);
       B.d_lo = 1 + c * D;
-      // the pair kernel that reuses slot set b waits for the slot sum of chunk c - 2
-      if (side && c >= 2 && (st = check(hipStreamWaitEvent(s, side->red[b], 0), "hipStreamWaitEvent"))) return st;
       const unsigned grid = (unsigned)nb * (unsigned)nparts;
       if (rescue) sym_accel_kernel<true, true><<<grid, kSL, 0, s>>>(B);
       else if (near) sym_accel_kernel<true, false><<<grid, kSL, 0, s>>>(B);
       else sym_accel_kernel<false, false><<<grid, kSL, 0, s>>>(B);
       NB_LAUNCH_CHECK("sym_accel_kernel");
-      hipStream_t rs = s;
-      if (side) {
-        if ((st = check(hipEventRecord(side->pair[b], s), "hipEventRecord")) ||
-            (st = check(hipStreamWaitEvent(side->side, side->pair[b], 0), "hipStreamWaitEvent")))
-          return st;
-        rs = side->side;
-      }
-      sym_reduce_kernel<3, float><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, B.d_lo, D, nparts, B.pj, B.pi,
+      return NBODY_OK;
+    };
+    auto sum = [&](int c, int b, hipStream_t rs) -> int {
+      SymArgs B = A;
+      slots(b, B);
+      sym_reduce_kernel<3, float><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, 1 + c * D, D, nparts, B.pj, B.pi,
                                                pd, a, nullptr, G, c == 0, c == nchunks - 1, B.pe, B.pw, ed, eo, pds);
       NB_LAUNCH_CHECK("sym_reduce_kernel");
-      if (side && (st = check(hipEventRecord(side->red[b], rs), "hipEventRecord"))) return st;
-    }
-    if (side && ((st = check(hipEventRecord(side->join, side->side), "hipEventRecord")) ||
-                 (st = check(hipStreamWaitEvent(s, side->join, 0), "hipStreamWaitEvent"))))
-      return st;
+      return NBODY_OK;
+    };
+    if ((st = run_sym_chunks(side, s, nchunks, nbuf, diag, pair, sum))) return st;
   }
   if (rescue) return launch_rescue(n, x, m, eps, G, excl, eo, 1, (size_t)npad, a, list + 64, list, s);
   return NBODY_OK;

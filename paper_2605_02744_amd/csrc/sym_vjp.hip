@@ -442,12 +442,22 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   const int half = (nb % 2 == 0) ? 1 : 0;
   const int64_t npad = (int64_t)nb * kSI;
   const int nparts = D * kSTiles / T;
+  const int nchunks = dmax > 0 ? (dmax + D - 1) / D : 0;
+  // with two half-ring chunks or more and the library's own workspace, the
+  // block-diagonal kernel and the slot sums run on the side stream, and the
+  // slots come twice, so that a chunk's pair kernel need not wait for the
+  // previous chunk's slot sum (with one chunk the cross-stream waits cost more
+  // than the overlap gains: 15 us of a 0.15 ms evaluation at 16384)
+  std::unique_lock<std::mutex> side_lk;
+  SideStream* side = nchunks >= 2 && !cfg.scratch ? acquire_side_stream(s, side_lk) : nullptr;
+  const int nbuf = side ? 2 : 1;
   int st = NBODY_OK;
   const size_t pj_bytes = sizeof(float) * kVC * (size_t)npad * D;
   const size_t pi_bytes = sizeof(double) * kVC * (size_t)npad * nparts;
   const size_t pd_bytes = sizeof(double) * kVC * (size_t)npad * pds;
   const size_t rec_bytes = sizeof(float4) * (size_t)npad;
-  char* ws = static_cast<char*>(pair_scratch(cfg, pj_bytes + pi_bytes + pd_bytes + 3 * rec_bytes, &st));
+  const size_t buf_bytes = pj_bytes + pi_bytes;  // one slot set
+  char* ws = static_cast<char*>(pair_scratch(cfg, nbuf * buf_bytes + pd_bytes + 3 * rec_bytes, &st));
   if (!ws) return st;
   SymArgs A;
   A.pe = nullptr;
@@ -455,10 +465,13 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   A.x = x; A.m = m; A.w = w; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
   A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
   A.fx = std::max(kNearX, kNearN / std::cbrt((float)n));
-  A.pj = reinterpret_cast<float*>(ws);
-  A.pi = reinterpret_cast<double*>(ws + pj_bytes);
-  double* pd = reinterpret_cast<double*>(ws + pj_bytes + pi_bytes);
-  float4* rhi = reinterpret_cast<float4*>(ws + pj_bytes + pi_bytes + pd_bytes);
+  auto slots = [&](int b, SymArgs& Q) {
+    Q.pj = reinterpret_cast<float*>(ws + (size_t)b * buf_bytes);
+    Q.pi = reinterpret_cast<double*>(ws + (size_t)b * buf_bytes + pj_bytes);
+  };
+  slots(0, A);
+  double* pd = reinterpret_cast<double*>(ws + nbuf * buf_bytes);
+  float4* rhi = reinterpret_cast<float4*>(ws + nbuf * buf_bytes + pd_bytes);
   float4* rw = rhi + npad;
   float4* rlo = rw + npad;
   A.rhi = rhi;
@@ -472,28 +485,40 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
   // the own pair is always left out of the block-diagonal sums, so exclude_self needs no variant
   (void)excl;
   const dim3 dg((unsigned)nb, (unsigned)pds);
-  if (near) vsym_diag_kernel<true><<<dg, kSL * kDiagG, 0, s>>>(A, pd);
-  else vsym_diag_kernel<false><<<dg, kSL * kDiagG, 0, s>>>(A, pd);
-  NB_LAUNCH_CHECK("vsym_diag_kernel");
+  auto diag = [&](hipStream_t ds) -> int {
+    if (near) vsym_diag_kernel<true><<<dg, kSL * kDiagG, 0, ds>>>(A, pd);
+    else vsym_diag_kernel<false><<<dg, kSL * kDiagG, 0, ds>>>(A, pd);
+    NB_LAUNCH_CHECK("vsym_diag_kernel");
+    return NBODY_OK;
+  };
   const dim3 rg((unsigned)((n + 255) / 256), kVC);
   if (dmax == 0) {
+    if ((st = diag(s))) return st;
     sym_reduce_kernel<kVC, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, gx, gm, G,
                                               1, 1, nullptr, nullptr, nullptr, nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
   }
-  const int nchunks = (dmax + D - 1) / D;
-  for (int c = 0; c < nchunks; ++c) {
-    A.d_lo = 1 + c * D;
+  auto pair = [&](int c, int b) -> int {
+    SymArgs B = A;
+    slots(b, B);
+    B.d_lo = 1 + c * D;
     const unsigned grid = (unsigned)nb * (unsigned)nparts;
-    if (near) vsym_kernel<true><<<grid, kSL, 0, s>>>(A);
-    else vsym_kernel<false><<<grid, kSL, 0, s>>>(A);
+    if (near) vsym_kernel<true><<<grid, kSL, 0, s>>>(B);
+    else vsym_kernel<false><<<grid, kSL, 0, s>>>(B);
     NB_LAUNCH_CHECK("vsym_kernel");
-    sym_reduce_kernel<kVC, float><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, A.d_lo, D, nparts, A.pj, A.pi, pd,
-                                              gx, gm, G, c == 0, c == nchunks - 1, nullptr, nullptr, nullptr, nullptr, pds);
+    return NBODY_OK;
+  };
+  auto sum = [&](int c, int b, hipStream_t rs) -> int {
+    SymArgs B = A;
+    slots(b, B);
+    sym_reduce_kernel<kVC, float><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, 1 + c * D, D, nparts, B.pj, B.pi,
+                                               pd, gx, gm, G, c == 0, c == nchunks - 1, nullptr, nullptr, nullptr,
+                                               nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
-  }
-  return NBODY_OK;
+    return NBODY_OK;
+  };
+  return run_sym_chunks(side, s, nchunks, nbuf, diag, pair, sum);
 }
 
 }  // namespace nb

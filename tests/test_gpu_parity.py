@@ -621,12 +621,14 @@ def test_batched_repeat_and_graph_capture(nb):
         assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
 
 
-@pytest.mark.parametrize("kind", ["kdk", "kdk_sym", "hermite6"])
+@pytest.mark.parametrize("kind", ["kdk", "kdk_sym", "kdk_sym_one", "kdk_sym64", "hermite6"])
 def test_single_system_graph_capture(nb, kind):
-    """nbody_step (ordered and symmetric force kernels) and nbody_step_hermite6
-    captured into a HIP graph (after one eager call has sized the library's
-    workspace) replay bitwise like eager calls, with eager work and
-    synchronisation between the replays."""
+    """nbody_step (ordered and symmetric force kernels: FP32C with two
+    half-ring launches, whose slot sums run on the library's second stream, or
+    with one, where only the block-diagonal kernel does; FP64 with two) and
+    nbody_step_hermite6 captured into a HIP graph (after one eager call has
+    sized the library's workspace) replay bitwise like eager calls, with eager
+    work and synchronisation between the replays."""
     x, v, m = ics.plummer(3001, seed=19)
     dt = 1.0 / 256
     tm = dev(m)
@@ -638,10 +640,12 @@ def test_single_system_graph_capture(nb, kind):
     def call(st, valid):
         if kind == "kdk":
             nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
-        elif kind == "kdk_sym":
-            nb.nbody_set_config(pairs=2, split=2)  # two half-ring launches per evaluation
+        elif kind.startswith("kdk_sym"):
+            # two half-ring launches per evaluation, or one
+            nb.nbody_set_config(pairs=2, split=1 if kind == "kdk_sym_one" else 2)
             try:
-                nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
+                nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01,
+                              precision="fp64" if kind == "kdk_sym64" else "fp32c", acc_valid=valid)
             finally:
                 nb.nbody_set_config()
         else:
@@ -665,6 +669,32 @@ def test_single_system_graph_capture(nb, kind):
         torch.cuda.synchronize()
         _ = (graph[0].sum() + 1.0).item()  # eager work between replays
         assert torch.equal(graph[0], ref[k][0]) and torch.equal(graph[1], ref[k][1]), k
+
+
+def test_sym_vjp_graph_capture(nb):
+    """The symmetric VJP with two half-ring launches (its block-diagonal kernel
+    and slot sums on the library's second stream) captured into a HIP graph
+    replays bitwise like the eager call, with eager work between replays."""
+    x, _, m = ics.plummer(3001, seed=23)
+    w = np.random.default_rng(3).standard_normal(x.shape)
+    tx, tm, tw = dev(x), dev(m), dev(w)
+    nb.nbody_set_config(pairs=2, split=2)
+    try:
+        rx, rm = nb.nbody_accel_vjp(tx, tm, tw, eps=0.01, precision="fp32c")
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+            gx, gm = nb.nbody_accel_vjp(tx, tm, tw, eps=0.01, precision="fp32c")
+    finally:
+        nb.nbody_set_config()
+    for k in range(3):
+        gx.zero_()
+        gm.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (tx.sum() + 1.0).item()  # eager work between replays
+        assert torch.equal(gx, rx) and torch.equal(gm, rm), k
 
 
 def test_abi_rejects_bad_pointers(nb):
