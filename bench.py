@@ -799,7 +799,9 @@ def bench_jerk(args, torch, nb):
             "steps": max(2, args.steps // 3), "warmup": 1, "ms_per_step": round(ms, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "jerk1m", "n": n, "eps": 0.001, "precision": args.precision},
-            "roofline": roofline("jerk_kernel<%s> (42 flops per interaction)" % args.precision.upper(),
+            "roofline": roofline(("jsym_kernel<%s> (symmetric from 12288 particles: staging, block diagonal, half "
+                                  "ring, slot sums; 42 flops per interaction)" if args.precision != "fp64" and args.pairs != 1
+                                  else "jerk_kernel<%s> (42 flops per interaction)") % args.precision.upper(),
                                  pairs * FLOPS_JERK, ms),
             "fp64_path": {"value": round(pairs / (out["fp64"] * 1e-3) / 1e9, 3), "ms_per_eval": round(out["fp64"], 4)},
             "accuracy": {"accel_max_rel_vs_fp64": float(ea.max()), "jerk_max_rel_vs_fp64": float(ej.max()),

@@ -222,9 +222,15 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
  *   a_i  = G sum_{j != i} m_j r_ij / r^3,
  *   jk_i = G sum_{j != i} m_j [ v_ij - 3 (r_ij . v_ij) r_ij / r^2 ] / r^3,
  * r_ij = x_j - x_i, v_ij = v_j - v_i, r^2 = |r_ij|^2 + eps^2 (the time
- * derivative of the softened acceleration along the motion).  FP32C keeps
- * float-float positions and FP32 velocities for every pair.  Errors: as
- * nbody_accel; a and jk must be distinct from each other and the inputs. */
+ * derivative of the softened acceleration along the motion).  FP32C rounds
+ * positions to FP32 and gives the pairs closer than the near-field radius
+ * float-float displacements (as nbody_accel), with FP32 velocities.  From
+ * 12288 particles in FP32C and FP32 (or as nbody_config.pairs says) each
+ * unordered pair is evaluated once and applied to both particles (the jerk
+ * term, like the acceleration, changes sign when i and j swap), summed in a
+ * fixed order, with a workspace of per-distance sums as nbody_accel's.
+ * Errors: as nbody_accel; a and jk must be distinct from each other and the
+ * inputs. */
 int nbody_accel_jerk(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk,
                      const nbody_params* p, void* stream);
 
@@ -316,12 +322,14 @@ typedef struct nbody_config {
                       wave against the system's whole j-range; or 256, 512, 1024:
                       most particles per item of a system above 256 particles,
                       evaluated by a whole workgroup */
-  int32_t pairs;   /* form of the force kernel of nbody_accel, of the KDK
-                      steps and (FP32C/FP32 only) of nbody_accel_vjp and the
-                      adjoint sweep: 0 = automatic (the tuned choice for
-                      (n, precision), else symmetric from 49152 particles
-                      on in FP32C/FP32 and from 8192 in FP64 for the force,
-                      from 12288 for the VJP),
+  int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
+                      steps, and (FP32C/FP32 only) of nbody_accel_vjp, the
+                      adjoint sweep, nbody_accel_jerk and the fourth-order
+                      Hermite steps:
+                      0 = automatic (the tuned choice for (n, precision),
+                      else symmetric from 49152 particles on in FP32C/FP32
+                      and from 8192 in FP64 for the force, from 12288 for
+                      the VJP and for acceleration + jerk),
                       1 = ordered: every ordered pair evaluated for its i;
                       2 = symmetric: every unordered pair evaluated once and
                       applied to both particles (a_j gets the opposite of i's

@@ -331,3 +331,79 @@ def test_sym_accel_fp64_exclude_self_eps_zero(nb, oracle_mod):
     a = sym_accel(nb, x, m, eps=0.0, precision="fp64", exclude_self=True)
     assert np.isfinite(a).all()
     assert rel_err(a, ref) <= 1e-11
+
+
+# ---- symmetric acceleration + jerk (Algorithm 3's pair term once per pair) ---
+
+def sym_jerk(nb, x, v, m, launches=2, **kw):
+    """nbody_accel_jerk through the symmetric kernel (pairs = 2), the half ring
+    in at least `launches` launches where it is that long."""
+    nb.nbody_set_config(pairs=2, split=launches)
+    try:
+        a, jk = nb.nbody_accel_jerk(dev(x), dev(v), dev(m), **kw)
+    finally:
+        nb.nbody_set_config()
+    return a.cpu().numpy(), jk.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1, 2, 511, 513, 1500, 2049, 4113])
+@pytest.mark.parametrize("prec,tola,tolj", [("fp32c", 1e-5, 1e-4), ("fp32", 1e-4, 1e-3)])
+def test_sym_jerk_matches_oracle(nb, oracle_mod, n, prec, tola, tolj):
+    """Per-row acceleration and jerk against the oracle at sizes that span one
+    block, a two-block ring seen from one side, odd and even block counts and
+    ragged last blocks, G != 1; FP32C also meets the paper's per-component
+    jerk criterion (0.2 %, Sec. 4.1)."""
+    x, v, m = ics.plummer(n, seed=70 + n)
+    ra, rj = oracle_mod.accel_jerk(x, v, m, G=1.1, eps=0.01)
+    print("sym jerk n=%d %s" % (n, prec), flush=True)
+    a, jk = sym_jerk(nb, x, v, m, G=1.1, eps=0.01, precision=prec)
+    assert rel_err(a, ra) <= tola
+    assert rel_err(jk, rj) <= tolj
+    if prec == "fp32c":
+        assert np.all(np.abs(jk - rj) <= 2e-3 * np.abs(rj) + 1e-6 * np.abs(rj).max())
+
+
+def test_sym_jerk_exclude_self_eps_zero(nb, oracle_mod):
+    """Without softening, the self pair left out (NBODY_EXCLUDE_SELF)."""
+    x, v, m = ics.plummer(3000, seed=77)
+    ra, rj = oracle_mod.accel_jerk(x, v, m, eps=0.0)
+    a, jk = sym_jerk(nb, x, v, m, eps=0.0, precision="fp32c", exclude_self=True)
+    assert np.isfinite(a).all() and np.isfinite(jk).all()
+    assert rel_err(a, ra) <= 1e-5 and rel_err(jk, rj) <= 1e-4
+
+
+def test_sym_jerk_default_and_ordered_agree(nb, oracle_mod):
+    """From 16384 particles the symmetric kernel is the FP32C default: it and
+    the ordered kernel (pairs = 1) agree, and both meet the oracle on sampled
+    rows."""
+    n = 20000
+    x, v, m = ics.plummer(n, seed=78)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    a2, j2 = [q.cpu().numpy() for q in nb.nbody_accel_jerk(tx, tv, tm, eps=0.01, precision="fp32c")]
+    nb.nbody_set_config(pairs=1)
+    try:
+        a1, j1 = [q.cpu().numpy() for q in nb.nbody_accel_jerk(tx, tv, tm, eps=0.01, precision="fp32c")]
+    finally:
+        nb.nbody_set_config()
+    rows = np.random.default_rng(5).choice(n, 256, replace=False)
+    ra, rj = oracle_mod.accel_jerk_rows(x, v, m, rows, eps=0.01)
+    for a, jk in ((a2, j2), (a1, j1)):
+        assert rel_err(a[:, rows], ra) <= 1e-5 and rel_err(jk[:, rows], rj) <= 1e-4
+    assert rel_err(a2, a1) <= 2e-5 and rel_err(j2, j1) <= 2e-4
+
+
+def test_sym_jerk_hermite_matches_oracle(nb, oracle_mod):
+    """Eight fourth-order Hermite steps with the symmetric acceleration + jerk
+    (pairs = 2, two launches per evaluation) against the oracle's Hermite run."""
+    x, v, m = ics.plummer(1024, seed=61)
+    dt, steps, eps = 1.0 / 256, 8, 0.01
+    rx, rv = oracle_mod.hermite4(x, v, m, dt, steps, eps=eps)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta, tj = torch.empty_like(tx), torch.empty_like(tx)
+    nb.nbody_set_config(pairs=2, split=2)
+    try:
+        nb.nbody_step_hermite(tx, tv, ta, tj, tm, dt, steps, eps=eps, precision="fp32c")
+    finally:
+        nb.nbody_set_config()
+    assert np.abs(tx.cpu().numpy() - rx).max() <= 1e-6
+    assert np.abs(tv.cpu().numpy() - rv).max() <= 1e-5
