@@ -859,7 +859,9 @@ def bench_hermite6(args, torch, nb):
     tx0, tv0 = torch.tensor(x, device=dev), torch.tensor(v, device=dev)
     mss, _, _ = timed(lambda: nb.nbody_accel_jerk_snap(tx0, tv0, accs, tm, eps=eps, precision=args.precision),
                       5, 1, torch)
-    roof = roofline("snap_kernel<%s> (80 flops per interaction)" % args.precision.upper(), pairs * FLOPS_SNAP, mss)
+    roof = roofline(("ssym_kernel<%s> (symmetric from 8192 particles: staging, block diagonal, half ring, slot sums; "
+                     "80 flops per interaction)" if args.precision != "fp64" and args.pairs != 1
+                     else "snap_kernel<%s> (80 flops per interaction)") % args.precision.upper(), pairs * FLOPS_SNAP, mss)
     cpu = None
     if not args.no_cpu:
         import oracle

@@ -259,8 +259,12 @@ int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, c
  * acc is an input: the snap takes the accelerations the particles move with
  * (in a Hermite step, the predicted ones).  Outputs a, jk, sn: [3][n] FP64,
  * caller-owned, distinct from each other and the inputs.  FP32C evaluates
- * pairs with float-float positions and FP32 velocity and acceleration
- * differences.  Errors: as nbody_accel_jerk. */
+ * pairs with FP32-rounded positions (float-float displacements for the pairs
+ * closer than the near-field radius, as nbody_accel) and FP32 velocity and
+ * acceleration differences.  From 8192 particles in FP32C and FP32 (or as
+ * nbody_config.pairs says) each unordered pair is evaluated once and applied
+ * to both particles (every term changes sign when i and j swap), summed in a
+ * fixed order.  Errors: as nbody_accel_jerk. */
 int nbody_accel_jerk_snap(int64_t n, const double* x, const double* v, const double* acc, const double* m,
                           double* a, double* jk, double* sn, const nbody_params* p, void* stream);
 
@@ -324,12 +328,13 @@ typedef struct nbody_config {
                       evaluated by a whole workgroup */
   int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
                       steps, and (FP32C/FP32 only) of nbody_accel_vjp, the
-                      adjoint sweep, nbody_accel_jerk and the fourth-order
-                      Hermite steps:
+                      adjoint sweep, nbody_accel_jerk, nbody_accel_jerk_snap
+                      and the Hermite steps:
                       0 = automatic (the tuned choice for (n, precision),
                       else symmetric from 49152 particles on in FP32C/FP32
                       and from 8192 in FP64 for the force, from 12288 for
-                      the VJP and for acceleration + jerk),
+                      the VJP and for acceleration + jerk, from 8192 for
+                      acceleration + jerk + snap),
                       1 = ordered: every ordered pair evaluated for its i;
                       2 = symmetric: every unordered pair evaluated once and
                       applied to both particles (a_j gets the opposite of i's

@@ -953,6 +953,8 @@ int launch_accel_jerk_snap(int64_t n, const double* x, const double* v, const do
                            double* a, double* jk, double* sn, double G, double eps, int precision, bool excl,
                            const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
+  if (cfg.sym_snap && precision != kFP64)
+    return launch_sym_snap(n, x, v, acc, m, a, jk, sn, G, eps, precision, excl, cfg, s);
   const int split = cfg.split < 1 ? 1 : cfg.split;
   switch (precision) {
     case kFP64: return snap_dispatch<kFP64, 1>(n, x, v, acc, m, a, jk, sn, G, eps, excl, split, s);

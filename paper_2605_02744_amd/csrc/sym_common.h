@@ -77,9 +77,11 @@ struct SymArgs {
   float fx;         // repair-radius factor max(kNearX, kNearN n^-1/3)
   const float4* rhi;  // [npad] staged j-records: (x, y, z, m) rounded to FP32
   const float4* rlo;  // [npad] (x, y, z) lo parts and the repair radius^2 (-1 for padding)
-  const double* w;  // [3][n] cotangent (VJP) or velocities (acceleration + jerk)
+  const double* w;  // [3][n] cotangent (VJP) or velocities (acceleration + jerk (+ snap))
   const float4* rw; // [npad] staged cotangents or velocities
-  float* pj;        // [D][C][npad] j-side tile sums of the chunk's distances (C = 3; 4 for the VJP, 6 for a + jerk)
+  const double* u;  // [3][n] accelerations the particles move with (acceleration + jerk + snap)
+  const float4* ru; // [npad] staged accelerations
+  float* pj;        // [D][C][npad] j-side tile sums of the chunk's distances (C = 3; 4 for the VJP, 6 for a + jerk, 9 with snap)
   double* pi;       // [nparts][C][npad] i-side sums of the chunk's workgroups
   float* pe;        // [nparts][npad] i-side error estimates of the chunk's workgroups (FP32C force), or null
   float* pw;        // [D][npad] j-side error estimates of the chunk's distances (FP32C force), or null
@@ -101,7 +103,7 @@ __device__ __forceinline__ float sym_rc2(double xa, double ya, double za, double
 using lds_ptr = __attribute__((address_space(3))) void*;
 
 // Adds the chunk's slots into the outputs (component c < 3 at out[c n + p],
-// c >= 3 at outm[(c - 3) n + p]): the j-side tile sums of distances d_lo .. d_lo + D - 1
+// 3 <= c < 6 at outm[(c - 3) n + p], c >= 6 at outs[(c - 6) n + p]): the j-side tile sums of distances d_lo .. d_lo + D - 1
 // that were evaluated (slots of type S: float, or double for the FP64 kernel),
 // then the i-side sums of the chunk's workgroups; the first chunk starts from
 // the distance-0 sums pd, the last applies G.  One thread per (particle,
@@ -119,11 +121,11 @@ __global__ void sym_reduce_kernel(int n, int npad, int nb, int dmax, int half, i
                                   const double* __restrict__ pd, double* __restrict__ out, double* __restrict__ outm,
                                   double G, int first, int last, const float* __restrict__ pe = nullptr,
                                   const float* __restrict__ pw = nullptr, const float* __restrict__ ed = nullptr,
-                                  float* __restrict__ eo = nullptr, int pds = 1) {
+                                  float* __restrict__ eo = nullptr, int pds = 1, double* __restrict__ outs = nullptr) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (p >= n) return;
-  double* o = c < 3 ? out + (size_t)c * n + p : outm + (size_t)(c - 3) * n + p;
+  double* o = c < 3 ? out + (size_t)c * n + p : c < 6 ? outm + (size_t)(c - 3) * n + p : outs + (size_t)(c - 6) * n + p;
   const int J = p / kSI;
   double acc = first ? 0.0 : *o;
   if (first)

@@ -152,3 +152,77 @@ def test_hermite6_rejects_zero_dt(nb):
         nb.nbody_step_hermite6(tx, tv, *st, tm, 0.0, 1, eps=0.01)
     with pytest.raises(nb.NBodyError):
         nb.nbody_step_hermite6(tx, tv, st[0], st[0], st[2], st[3], tm, 0.01, 1, eps=0.01)
+
+
+# ---- symmetric acceleration + jerk + snap (each unordered pair once) ---------
+
+def sym_snap(nb, x, v, acc, m, launches=2, **kw):
+    """nbody_accel_jerk_snap through the symmetric kernel (pairs = 2), the half
+    ring in at least `launches` launches where it is that long."""
+    nb.nbody_set_config(pairs=2, split=launches)
+    try:
+        return [q.cpu().numpy() for q in nb.nbody_accel_jerk_snap(dev(x), dev(v), dev(acc), dev(m), **kw)]
+    finally:
+        nb.nbody_set_config()
+
+
+@pytest.mark.parametrize("n", [2, 511, 513, 1537, 2049, 4113])
+def test_sym_snap_matches_oracle(nb, oracle_mod, n):
+    """FP32C acceleration, jerk and snap of the symmetric kernel against the
+    oracle at sizes that span one block, a two-block ring seen from one side,
+    odd and even block counts and ragged last blocks, G != 1; the same bars as
+    the ordered kernel (the paper's acceptance levels, Sec. 4.1)."""
+    x, v, acc, m = inputs(n, 80 + n)
+    ra, rj, rs = oracle_mod.accel_jerk_snap(x, v, acc, m, G=1.1, eps=0.01)
+    print("sym snap n=%d" % n, flush=True)
+    a, jk, sn = sym_snap(nb, x, v, acc, m, G=1.1, eps=0.01, precision="fp32c")
+    ea, ej, es = row_err(a, ra), row_err(jk, rj), row_err(sn, rs)
+    print("sym snap n=%d: a %.2e jerk %.2e snap %.2e" % (n, ea.max(), ej.max(), es.max()))
+    assert ea.max() <= 1e-5
+    assert ej.max() <= 2e-3 and es.max() <= 2e-3
+
+
+def test_sym_snap_eps0_exclude_self(nb, oracle_mod):
+    """Without softening, the self pair left out (NBODY_EXCLUDE_SELF)."""
+    x, v, acc, m = inputs(1500, 87)
+    ra, rj, rs = oracle_mod.accel_jerk_snap(x, v, acc, m, eps=0.0)
+    a, jk, sn = sym_snap(nb, x, v, acc, m, eps=0.0, precision="fp32c", exclude_self=True, check_finite=True)
+    assert row_err(a, ra).max() <= 1e-5
+    assert row_err(jk, rj).max() <= 2e-3 and row_err(sn, rs).max() <= 2e-3
+
+
+def test_sym_snap_default_and_ordered_agree(nb, oracle_mod):
+    """From 8192 particles the symmetric kernel is the FP32C default: it and
+    the ordered kernel (pairs = 1) meet the oracle on sampled rows and agree."""
+    n = 20000
+    x, v, acc, m = inputs(n, 88)
+    args = (dev(x), dev(v), dev(acc), dev(m))
+    o2 = [q.cpu().numpy() for q in nb.nbody_accel_jerk_snap(*args, eps=0.01, precision="fp32c")]
+    nb.nbody_set_config(pairs=1)
+    try:
+        o1 = [q.cpu().numpy() for q in nb.nbody_accel_jerk_snap(*args, eps=0.01, precision="fp32c")]
+    finally:
+        nb.nbody_set_config()
+    rows = np.random.default_rng(6).choice(n, 256, replace=False)
+    ref = oracle_mod.accel_jerk_snap_rows(x, v, acc, m, rows, eps=0.01)
+    for o in (o2, o1):
+        assert row_err(o[0][:, rows], ref[0]).max() <= 1e-5
+        assert row_err(o[1][:, rows], ref[1]).max() <= 2e-3 and row_err(o[2][:, rows], ref[2]).max() <= 2e-3
+    assert row_err(o2[0], o1[0]).max() <= 2e-5
+
+
+def test_sym_snap_hermite6_matches_oracle(nb, oracle_mod):
+    """Eight sixth-order Hermite steps with the symmetric evaluations (pairs =
+    2, two launches each) against the oracle's Hermite run."""
+    x, v, m = ics.plummer(1024, seed=74)
+    dt, steps, eps = 1.0 / 256, 8, 0.01
+    rx, rv = oracle_mod.hermite6(x, v, m, dt, steps, eps=eps)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    st = [torch.empty_like(tx) for _ in range(4)]
+    nb.nbody_set_config(pairs=2, split=2)
+    try:
+        nb.nbody_step_hermite6(tx, tv, *st, tm, dt, steps, eps=eps, precision="fp32c", check_finite=True)
+    finally:
+        nb.nbody_set_config()
+    assert np.abs(tx.cpu().numpy() - rx).max() <= 1e-6
+    assert np.abs(tv.cpu().numpy() - rv).max() <= 1e-5
