@@ -182,6 +182,26 @@ def test_sym_snap_matches_oracle(nb, oracle_mod, n):
     assert ej.max() <= 2e-3 and es.max() <= 2e-3
 
 
+def test_sym_snap_fp32_no_worse_than_ordered(nb, oracle_mod):
+    """FP32 (no compensation): the symmetric kernel's acceleration, jerk and
+    snap errors against the oracle stay within three times the ordered FP32
+    kernel's on the same input (both round positions to FP32; the symmetric
+    kernel sums up to 512 terms per j in FP32 before its FP64 sums)."""
+    x, v, acc, m = inputs(3000, 89)
+    ref = oracle_mod.accel_jerk_snap(x, v, acc, m, eps=0.01)
+    sym = sym_snap(nb, x, v, acc, m, eps=0.01, precision="fp32")
+    nb.nbody_set_config(pairs=1)
+    try:
+        ords = [q.cpu().numpy() for q in nb.nbody_accel_jerk_snap(dev(x), dev(v), dev(acc), dev(m), eps=0.01,
+                                                                  precision="fp32")]
+    finally:
+        nb.nbody_set_config()
+    for k in range(3):
+        es, eo = row_err(sym[k], ref[k]).max(), row_err(ords[k], ref[k]).max()
+        print("fp32 component %d: symmetric %.2e ordered %.2e" % (k, es, eo))
+        assert es <= max(3 * eo, 1e-6)
+
+
 def test_sym_snap_eps0_exclude_self(nb, oracle_mod):
     """Without softening, the self pair left out (NBODY_EXCLUDE_SELF)."""
     x, v, acc, m = inputs(1500, 87)

@@ -621,21 +621,22 @@ def test_batched_repeat_and_graph_capture(nb):
         assert torch.equal(gx, ref[k][0]) and torch.equal(gv, ref[k][1]), k
 
 
-@pytest.mark.parametrize("kind", ["kdk", "kdk_sym", "kdk_sym_one", "kdk_sym64", "hermite6"])
+@pytest.mark.parametrize("kind", ["kdk", "kdk_sym", "kdk_sym_one", "kdk_sym64", "hermite6", "hermite6_sym"])
 def test_single_system_graph_capture(nb, kind):
     """nbody_step (ordered and symmetric force kernels: FP32C with two
-    half-ring launches, whose slot sums run on the library's second stream, or
-    with one, where only the block-diagonal kernel does; FP64 with two) and
-    nbody_step_hermite6 captured into a HIP graph (after one eager call has
-    sized the library's workspace) replay bitwise like eager calls, with eager
-    work and synchronisation between the replays."""
+    half-ring launches, whose block-diagonal kernel and slot sums run on the
+    library's second stream, or with one, all on the caller's stream; FP64 with
+    two) and nbody_step_hermite6 (ordered, and symmetric acceleration + jerk +
+    snap with two launches) captured into a HIP graph (after one eager call
+    has sized the library's workspace) replay bitwise like eager calls, with
+    eager work and synchronisation between the replays."""
     x, v, m = ics.plummer(3001, seed=19)
     dt = 1.0 / 256
     tm = dev(m)
 
     def state():
         tx, tv = dev(x), dev(v)
-        return [tx, tv] + [torch.empty_like(tx) for _ in range(1 if kind != "hermite6" else 4)]
+        return [tx, tv] + [torch.empty_like(tx) for _ in range(4 if kind.startswith("hermite6") else 1)]
 
     def call(st, valid):
         if kind == "kdk":
@@ -646,6 +647,13 @@ def test_single_system_graph_capture(nb, kind):
             try:
                 nb.nbody_step(st[0], st[1], st[2], tm, dt, 2, eps=0.01,
                               precision="fp64" if kind == "kdk_sym64" else "fp32c", acc_valid=valid)
+            finally:
+                nb.nbody_set_config()
+        elif kind == "hermite6_sym":
+            # the symmetric acceleration + jerk + snap, two half-ring launches per evaluation
+            nb.nbody_set_config(pairs=2, split=2)
+            try:
+                nb.nbody_step_hermite6(st[0], st[1], *st[2:], tm, dt, 2, eps=0.01, precision="fp32c", acc_valid=valid)
             finally:
                 nb.nbody_set_config()
         else:
