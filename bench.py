@@ -147,14 +147,16 @@ def idle_power(meter, seconds=2.0):
     return (meter.joules() - ja) / seconds
 
 
-def energy_per_call(fn, reps, torch, meter, idle_before=None, settle=0.5):
+def energy_per_call(fn, reps, torch, meter, idle_before=None, settle=2.0, min_busy=4.0):
     """GPU board energy (J) of one call of fn, from the amdsmi energy counter
-    over `reps` back-to-back calls.  The counter is refreshed with some delay,
-    so every read follows a settling pause, and the idle energy of the pauses
-    is subtracted: with the idle power measured before the program's first GPU
-    work (idle_before) when given, else with that of a one-second window just
-    before the calls; the second figure is returned too, since a board that
-    has just been busy still draws more.  Returns a dict or None."""
+    over back-to-back calls: `reps` of them, repeated until they have kept the
+    GPU busy for at least min_busy seconds.  The counter is refreshed with a
+    delay (a read shortly after busy work misses the end of it), so every read
+    follows a settling pause of `settle` seconds, and the idle energy of the
+    pauses is subtracted: with the idle power measured before the program's
+    first GPU work (idle_before) when given, else with that of a one-second
+    window just before the calls; the second figure is returned too, since a
+    board that has just been busy still draws more.  Returns a dict or None."""
     if meter is None or meter.joules() is None:
         return None
     torch.cuda.synchronize()
@@ -165,9 +167,13 @@ def energy_per_call(fn, reps, torch, meter, idle_before=None, settle=0.5):
     tb = time.perf_counter()
     idle_recent = (jb - ja) / 1.0
     t0 = time.perf_counter()
-    for _ in range(reps):
-        fn()
-    torch.cuda.synchronize()
+    calls = 0
+    while calls == 0 or time.perf_counter() - t0 < min_busy:
+        for _ in range(reps):
+            fn()
+        calls += reps
+        torch.cuda.synchronize()
+    reps = calls
     busy = time.perf_counter() - t0
     time.sleep(settle)
     jc = meter.joules()
