@@ -357,6 +357,14 @@ typedef struct nbody_config {
                       recomputed in FP64; this keeps such rows inside the 1e-5
                       FP32C bound at the cost of one FP64 row evaluation each
                       (0.12 % of the rows of the 2^20 two-component model). */
+  int32_t sweep;   /* reverse sweep of nbody_traj_grad: 0 = automatic (with more
+                      than one segment, n <= 65536 and the symmetric kernels'
+                      launches left automatic, the trajectory of the next
+                      segment is recomputed on a second stream of the library,
+                      with its own workspace, while the caller's stream runs
+                      the adjoint steps of the current one: at such sizes
+                      neither fills the GPU alone), 1 = everything on the
+                      caller's stream.  Both give bitwise the same result. */
 } nbody_config;
 
 /* Force a tile configuration for subsequent calls on this thread (all zeros

@@ -48,7 +48,7 @@ class nbody_params(ctypes.Structure):
 class nbody_config(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("bsplit", ctypes.c_int32), ("bpass", ctypes.c_int32), ("bitem", ctypes.c_int32),
-                ("pairs", ctypes.c_int32), ("rescue", ctypes.c_int32)]
+                ("pairs", ctypes.c_int32), ("rescue", ctypes.c_int32), ("sweep", ctypes.c_int32)]
 
 
 _lib = None
@@ -337,7 +337,7 @@ def nbody_step_hermite6(x, v, a, jk, sn, cr, m, dt, nsteps, *, G=1.0, eps, preci
                                        _stream(x.device)))
 
 
-def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0, rescue=0):
+def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0, rescue=0, sweep=0):
     """Forces a tile configuration on this thread (all zeros = automatic).
     Ensemble (nbody_step_batched): bsplit=0 with bpass set runs one workgroup
     per system (its records resident in LDS), bsplit=1 as 0 with the largest
@@ -351,8 +351,12 @@ def nbody_set_config(ipl=0, split=0, bsplit=0, bpass=0, bitem=0, pairs=0, rescue
     one workgroup per item).  pairs: the form of the force kernels (1 ordered,
     2 symmetric: each unordered pair once; 0 automatic; the VJP follows in
     FP32C/FP32).  rescue: FP32C force rows flagged by the kernels' error
-    estimate recomputed in FP64 (0 automatic = on, 1 on, 2 off)."""
-    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem), int(pairs), int(rescue))
+    estimate recomputed in FP64 (0 automatic = on, 1 on, 2 off).  sweep: the
+    adjoint sweep of nbody_traj_grad (0 automatic: the next segment's
+    trajectory recomputed on a second stream where that helps; 1 one stream;
+    bitwise the same result)."""
+    c = nbody_config(int(ipl), int(split), int(bsplit), int(bpass), int(bitem), int(pairs), int(rescue),
+                     int(sweep))
     _check(load().nbody_set_config(ctypes.byref(c)))
 
 

@@ -23,6 +23,7 @@ void release_batched_plans();
 void release_stream_plans();
 void release_sym_ensemble_plans();
 void release_side_streams();
+void release_sweep_streams();
 bool sym_ensemble_default(int32_t ncl, const int64_t* off);
 
 // ------------------------------------------------------------------ errors
@@ -40,7 +41,7 @@ int hip_fail(hipError_t e, const char* what) {
 // --------------------------------------------------------------- workspace
 namespace {
 constexpr int kMaxDev = 64;
-constexpr int kSlots = 4;
+constexpr int kSlots = 5;
 struct Buf { void* p = nullptr; size_t bytes = 0; };
 std::mutex g_ws_mu;
 Buf g_ws[kMaxDev][kSlots];
@@ -93,7 +94,7 @@ void* workspace(int device, int slot, size_t bytes, int* status) {
 }
 
 void* pair_scratch(const PairConfig& cfg, size_t bytes, int* status) {
-  if (!cfg.scratch) return workspace(current_device(), 0, bytes, status);
+  if (!cfg.scratch) return workspace(current_device(), cfg.ws_slot, bytes, status);
   if (bytes > cfg.scratch_bytes) {
     *status = set_error(NBODY_EINVAL, "the call needs " + std::to_string(bytes) + " bytes of scratch, more than the " +
                                           std::to_string(cfg.scratch_bytes) + " it was given");
@@ -119,7 +120,7 @@ void release_workspaces() {
 
 // ------------------------------------------------------------- configuration
 namespace {
-thread_local nbody_config t_cfg = {0, 0, 0, 0, 0, 0, 0};
+thread_local nbody_config t_cfg = {0, 0, 0, 0, 0, 0, 0, 0};
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int64_t>, PairConfig> g_tuned;  // (device, precision, n)
 }  // namespace
@@ -169,6 +170,7 @@ PairConfig choose_config(int64_t n, int precision, int device) {
   if (t.split) c.split = t.split;
   if (t.pairs) c.sym = c.sym_vjp = c.sym_jerk = c.sym_snap = t.pairs == 2 ? 1 : 0;
   c.rescue = t.rescue == 2 ? 0 : 1;
+  c.sweep = t.sweep;
   // the symmetric kernels read a set split as a least number of launches (0 =
   // automatic); the ordered kernels that serve the same sizes (acceleration +
   // jerk (+ snap) below their thresholds, the FP64 VJP) keep their own j-split
@@ -702,6 +704,7 @@ int nbody_set_config(const nbody_config* cfg) {
     return set_error(NBODY_EINVAL, "bitem must be 0, 64, 256, 512 or 1024");
   if (cfg->pairs < 0 || cfg->pairs > 2) return set_error(NBODY_EINVAL, "pairs must be 0, 1 or 2");
   if (cfg->rescue < 0 || cfg->rescue > 2) return set_error(NBODY_EINVAL, "rescue must be 0, 1 or 2");
+  if (cfg->sweep < 0 || cfg->sweep > 1) return set_error(NBODY_EINVAL, "sweep must be 0 or 1");
   set_thread_config(*cfg);
   return NBODY_OK;
 }
@@ -824,6 +827,7 @@ int nbody_finalize(void) {
     g_tuned_batch.clear();
   }
   release_side_streams();
+  release_sweep_streams();
   release_workspaces();
   return NBODY_OK;
 }

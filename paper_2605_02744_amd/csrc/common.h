@@ -15,6 +15,7 @@ namespace nb {
 // Thread-local message for nbody_last_error(); set_error returns the status.
 int set_error(int status, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+inline int hip_ok(hipError_t e, const char* what) { return e == hipSuccess ? NBODY_OK : hip_fail(e, what); }
 
 #define NB_HIP(call)                                        \
   do {                                                      \
@@ -32,7 +33,10 @@ int hip_fail(hipError_t e, const char* what);
 // Growable scratch allocations, one per (device, slot), never shrunk.  Slots
 // keep nested users apart: 0 = per-launch partial sums of the all-pairs
 // kernels, 1 = per-call buffers of a driver (energy, adjoint sweep),
-// 2 = batched plans, 3 = status flags.  Growing a slot synchronises the device.
+// 2 = batched plans, 3 = status flags, 4 = the all-pairs scratch of the
+// adjoint sweep's recompute on its second stream (kSweepSlot), which runs
+// alongside slot 0's users.  Growing a slot synchronises the device.
+constexpr int kSweepSlot = 4;
 void* workspace(int device, int slot, size_t bytes, int* status);
 void release_workspaces();
 int current_device();
@@ -64,6 +68,8 @@ struct PairConfig {
   int sym_snap = 0;  // 1: the symmetric acceleration + jerk + snap (FP32C/FP32 only)
   int launches = 0;  // symmetric kernels: least number of launches of the half ring (0 = automatic)
   int rescue = 1;  // FP32C force: recompute rows flagged by the error estimate in FP64
+  int sweep = 0;   // adjoint sweep: 0 = recompute overlapped on a second stream where allowed, 1 = one stream
+  int ws_slot = 0;  // workspace slot of the all-pairs launchers' scratch (kSweepSlot on the sweep's second stream)
   // Device memory the caller lends for this call's partial sums, staged
   // records and slots.  When set, the all-pairs launchers fit their plans into
   // scratch_bytes and never touch the library workspace (no allocation).
@@ -72,7 +78,7 @@ struct PairConfig {
 };
 
 // `bytes` of scratch for one all-pairs launch: cfg.scratch when the caller lent
-// memory (NBODY_EINVAL if it is smaller), else workspace slot 0.
+// memory (NBODY_EINVAL if it is smaller), else workspace slot cfg.ws_slot.
 void* pair_scratch(const PairConfig& cfg, size_t bytes, int* status);
 
 PairConfig choose_config(int64_t n, int precision, int device);

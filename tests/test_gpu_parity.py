@@ -314,6 +314,65 @@ def test_traj_grad_recompute_matches_forward(nb):
     assert torch.equal(xT, ax) and torch.equal(vT, av)
 
 
+def _sweep_inputs(nb, n, steps, every, seed):
+    """Checkpoints of an FP64 KDK run (the states at steps 0, every, ...) and
+    random final cotangents, for nbody_traj_grad."""
+    x, v, m = ics.plummer(n, seed=seed)
+    dt, eps = 1.0 / 256, 0.01
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta = torch.empty_like(tx)
+    ckx, ckv = [], []
+    for c in range(-(-steps // every)):
+        ckx.append(tx.clone())
+        ckv.append(tv.clone())
+        nb.nbody_step(tx, tv, ta, tm, dt, min(every, steps - c * every), eps=eps, precision="fp64", acc_valid=c > 0)
+    rng = np.random.default_rng(seed + 1)
+    gxT, gvT = dev(rng.standard_normal((3, n))), dev(rng.standard_normal((3, n)))
+    return torch.stack(ckx), torch.stack(ckv), tm, gxT, gvT, dt, eps
+
+
+@pytest.mark.parametrize("prec,n,steps,every", [("fp32c", 2049, 47, 10), ("fp64", 1500, 30, 6), ("fp32", 999, 8, 3),
+                                                ("fp32c", 16384, 9, 4), ("fp32c", 700, 13, 13)])
+def test_traj_grad_two_streams_bitwise(nb, prec, n, steps, every):
+    """The adjoint sweep with the next segment's trajectory recomputed on the
+    library's second stream (sweep = 0, automatic: more than one segment and
+    n <= 65536) and with everything on the caller's stream (sweep = 1) give
+    bitwise the same cotangents, and repeated calls do too: shorter last
+    segments, an odd and an even number of segments, the symmetric VJP
+    (16384) and one segment (no second stream)."""
+    ckx, ckv, tm, gxT, gvT, dt, eps = _sweep_inputs(nb, n, steps, every, 31)
+    out = []
+    for sweep in (0, 1, 0):
+        nb.nbody_set_config(sweep=sweep)
+        try:
+            out.append(nb.nbody_traj_grad(ckx, ckv, every, steps, tm, dt, gxT, gvT, eps=eps, precision=prec))
+        finally:
+            nb.nbody_set_config()
+    for k, (a, b, c) in enumerate(zip(*out)):
+        assert torch.isfinite(a).all() and torch.equal(a, b) and torch.equal(a, c), k
+
+
+def test_traj_grad_two_streams_graph_capture(nb):
+    """The two-stream adjoint sweep captured into a HIP graph (after one eager
+    call has sized the workspaces and made the second stream) replays bitwise
+    like the eager call, with eager work and eager sweeps between replays."""
+    n, steps, every = 1024, 12, 4
+    ckx, ckv, tm, gxT, gvT, dt, eps = _sweep_inputs(nb, n, steps, every, 33)
+    call = lambda: nb.nbody_traj_grad(ckx, ckv, every, steps, tm, dt, gxT, gvT, eps=eps, precision="fp32c")
+    ref = call()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        outs = call()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (outs[0].sum() + 1.0).item()  # eager work between replays
+        assert all(torch.equal(a, b) for a, b in zip(outs, ref)), k
+        assert all(torch.equal(a, b) for a, b in zip(call(), ref)), k
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 def test_batched_matches_single_system(nb, prec):
     """Every system of a batched run against nbody_step on that system alone:
