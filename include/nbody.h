@@ -181,6 +181,13 @@ int nbody_accel_vjp(int64_t n, const double* x, const double* m, const double* w
  * p->precision: with FP64 checkpoints and an FP32C sweep, each segment's
  * FP32C recompute restarts from an FP64 state, and the result is the
  * gradient of the FP64 trajectory to FP32C accuracy.
+ * With more than one segment and n <= 65536 (nbody_config.sweep 0) the
+ * recompute of the next segment runs on a second stream that the library
+ * owns, ordered against `stream` by events and joined back into it before
+ * the call returns (a captured call records the fork and the join); it uses
+ * a second trajectory buffer and workspace of its own, so the call needs
+ * about twice the memory of a one-stream sweep.  The result is bitwise the
+ * same either way.
  * Errors: as nbody_step, plus every < 1. */
 int nbody_traj_grad(int64_t n, const double* ckpt_x, const double* ckpt_v, int64_t every,
                     int64_t nsteps, const double* m, double dt, const double* gxT,
