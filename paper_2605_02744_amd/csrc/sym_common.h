@@ -245,15 +245,25 @@ inline size_t sym_plan(int64_t n, int launches, int slot_bytes, int sum_bytes, i
   int T = kSTiles, D = 1;
   size_t need = 0;
   for (;;) {
-    // at least ~4096 workgroups per launch (several rounds of 7 per CU), at most
-    // 16 distances each; where whole distances leave fewer, 2 or 4 tiles each
-    const int64_t tiles = (int64_t)nb * d0 * kSTiles / 4096;
-    if (tiles >= kSTiles) {
-      const int L = (int)std::min<int64_t>(std::min(16, d0), tiles / kSTiles);
+    // whole distances per workgroup (at most 16), as many as still leave
+    // `want` workgroups per launch (several rounds of 6-7 per CU); one while
+    // that leaves ~4096; below that 2 or 4 tiles each.  A launch that covers
+    // the whole half ring (small rings) wants ~8192: 8192 workgroups of one or
+    // four distances beat 4096 of two or eight by 2-3 % at 65536 and 131072
+    // particles, while halving the tiles of one distance to reach 8192 lost
+    // 0.3-1.2 % at 49152, and fewer, longer workgroups lost more; the chunked
+    // launches of large rings keep ~4096 (16 distances per workgroup at 2^20)
+    const int64_t bp = (int64_t)nb * d0;  // block pairs of whole distances
+    const int64_t want = d0 == dmax ? 8192 : 4096;
+    if (bp >= want) {
+      const int L = (int)std::min<int64_t>(std::min(16, d0), bp / want);
       T = L * kSTiles;
       D = (d0 + L - 1) / L * L;
+    } else if (bp >= 4096) {
+      T = kSTiles;
+      D = d0;
     } else {
-      T = tiles >= 4 ? 4 : 2;
+      T = bp * kSTiles / 4096 >= 4 ? 4 : 2;
       D = d0;
     }
     need = (size_t)npad * ((size_t)fixed_bytes + (size_t)D * slot_bytes + (size_t)(D * kSTiles / T) * part_bytes);
