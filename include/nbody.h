@@ -424,7 +424,11 @@ int nbody_tune_batched(int32_t ncl, const int64_t* off, const double* eps, const
 /* Message describing the last non-OK status returned on this thread. */
 const char* nbody_last_error(void);
 
-/* Releases the per-device workspaces and plans. */
+/* Waits for the work of every device the library has run on, then releases
+ * its per-device workspaces, batched plans and batched tuned choices and its
+ * own second streams.  Later calls build again what they need (results are
+ * bitwise as before).  Not to be called while another thread is inside the
+ * library. */
 int nbody_finalize(void);
 
 /* Library version, major * 10000 + minor * 100 + patch. */

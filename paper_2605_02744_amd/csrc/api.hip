@@ -46,12 +46,27 @@ struct Buf { void* p = nullptr; size_t bytes = 0; };
 std::mutex g_ws_mu;
 Buf g_ws[kMaxDev][kSlots];
 std::atomic<int> g_cus[kMaxDev];  // zero-initialised (static storage)
+std::atomic<bool> g_used[kMaxDev];  // devices the library has run on (false initially)
 }  // namespace
 
 int current_device() {
   int d = 0;
   if (hipGetDevice(&d) != hipSuccess) return 0;
+  if (d >= 0 && d < kMaxDev && !g_used[d].load(std::memory_order_relaxed)) g_used[d].store(true, std::memory_order_relaxed);
   return d;
+}
+
+// Waits for all work on every device the library has run on (every path that
+// enqueues work or keeps state asks current_device() first).
+void sync_used_devices() {
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  for (int d = 0; d < kMaxDev; ++d)
+    if (g_used[d].load(std::memory_order_relaxed)) {
+      (void)hipSetDevice(d);
+      (void)hipDeviceSynchronize();
+    }
+  (void)hipSetDevice(prev);
 }
 
 int cu_count(int device) {
@@ -819,6 +834,8 @@ int nbody_tune(int64_t n, int32_t precision, const char* cache_path, nbody_confi
 const char* nbody_last_error(void) { return g_err.c_str(); }
 
 int nbody_finalize(void) {
+  // nothing enqueued may still read what is released below
+  sync_used_devices();
   release_batched_plans();
   release_stream_plans();
   release_sym_ensemble_plans();
