@@ -942,7 +942,7 @@ def main():
                     help="ensemble: the FP32C rescue, 0 automatic (on), 1 on, 2 off")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
         args.steps = {"twocomp1m_force": 10, "plummer64k_fp32c": 100, "ensemble512": 1000, "grad16k": 200,

@@ -51,7 +51,7 @@ typedef enum {
   NBODY_EHIP = -2,         /* a HIP runtime call or kernel launch failed */
   NBODY_ENOMEM = -3,       /* workspace allocation failed */
   NBODY_ENONFINITE = -4,   /* NBODY_CHECK_FINITE found NaN/Inf in an output */
-  NBODY_EUNSUPPORTED = -5  /* valid request this build cannot serve */
+  NBODY_EUNSUPPORTED = -5  /* valid request the library cannot serve */
 } nbody_status;
 
 /* Arithmetic of the pair evaluation.  The particle state, the integrator and
