@@ -55,6 +55,7 @@ constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
 constexpr int64_t kSymMinN = 49152;
 constexpr int64_t kSymMinN64 = 8192;
 constexpr int64_t kSymMinNVjp = 12288;
+constexpr int64_t kSymMinNVjp64 = 8192;  // the FP64 VJP
 constexpr int64_t kSymMinNJerk = 12288;
 constexpr int64_t kSymMinNSnap = 8192;
 
@@ -63,7 +64,8 @@ struct PairConfig {
   int ipl = 1;    // i-particles per lane
   int split = 1;  // j-range split across workgroups (the ordered kernels)
   int sym = 0;      // 1: the symmetric force kernels (each unordered pair once)
-  int sym_vjp = 0;  // 1: the symmetric VJP (FP32C/FP32 only)
+  int sym_vjp = 0;  // 1: the symmetric VJP (FP32C/FP32)
+  int sym_vjp64 = 0;  // 1: the symmetric FP64 VJP
   int sym_jerk = 0;  // 1: the symmetric acceleration + jerk (FP32C/FP32 only)
   int sym_snap = 0;  // 1: the symmetric acceleration + jerk + snap (FP32C/FP32 only)
   int launches = 0;  // symmetric kernels: least number of launches of the half ring (0 = automatic)
@@ -117,6 +119,10 @@ int launch_sym_snap(int64_t n, const double* x, const double* v, const double* a
 // The same VJP from the symmetric kernel (FP32C or FP32; launches as above).
 int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
                    double eps, int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
+
+// The same VJP in FP64 from the symmetric FP64 kernel (launches as above).
+int launch_sym_vjp64(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
+                     double eps, const PairConfig& cfg, hipStream_t s);
 
 // (da/dx)^T w into gx and (da/dm)^T w into gm.
 int launch_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx,

@@ -1012,6 +1012,7 @@ int launch_vjp(int64_t n, const double* x, const double* m, const double* w, dou
                double G, double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   if (cfg.sym_vjp && precision != kFP64) return launch_sym_vjp(n, x, m, w, gx, gm, G, eps, precision, excl, cfg, s);
+  if (cfg.sym_vjp64 && precision == kFP64) return launch_sym_vjp64(n, x, m, w, gx, gm, G, eps, cfg, s);
   const int split = cfg.split < 1 ? 1 : cfg.split;
   // The VJP keeps twice the accumulators of the force, so it runs at most 2 i per lane.
   const bool one = cfg.ipl <= 1;

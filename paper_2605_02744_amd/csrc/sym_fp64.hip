@@ -8,7 +8,9 @@
 // across rows on the LDS pipe; tile sums to per-distance FP64 slots; a half
 // ring of block pairs in chunks; FP64 slot sums in a fixed order.  All
 // arithmetic is FP64 with the refined inverse square root of the ordered FP64
-// kernel; there is no near-field repair to do.
+// kernel; there is no near-field repair to do.  The vector-Jacobian product of
+// the acceleration (the adjoint's pairwise VJP) runs on the same layout with
+// four FP64 components per particle.
 #include "sym_common.h"
 
 namespace nb {
@@ -278,6 +280,289 @@ __global__ __launch_bounds__(kSL* kDiagG) void sym64_diag_kernel(S64Args A, doub
   }
 }
 
+
+// ------------------------------------------------ symmetric FP64 VJP
+// The vector-Jacobian product of the acceleration on the same layout, in FP64:
+// with d = x_j - x_k, r^2 = |d|^2 + eps^2 and u = m_k w_j - m_j w_k, the
+// unordered pair {k, j} gives
+//   gx_k += r^-3 u - 3 r^-5 (d.u) d,   gm_k -= r^-3 (d . w_j),
+//   gx_j -= r^-3 u - 3 r^-5 (d.u) d,   gm_j += r^-3 (d . w_k)
+// (d and u both change sign when k and j swap).  Four components per particle
+// (gx, gy, gz, gm); cotangents staged as a second record per particle.
+constexpr int kV64 = 4;
+
+struct V64Args {
+  const double* x;  // [3][n]
+  const double* m;  // [n]
+  const double* w;  // [3][n] cotangent
+  int n, nb, npad, dmax, half, d_lo, T, nparts;
+  double eps;
+  const double4* rec;   // [npad] staged (x, y, z, m); padding far away and massless
+  const double4* recw;  // [npad] staged (wx, wy, wz, 0); padding zero
+  double* pj;           // [D][4][npad] j-side tile sums of the chunk's distances
+  double* pi;           // [nparts][4][npad] i-side sums of the chunk's workgroups
+};
+
+struct VDSet {
+  double x[2], y[2], z[2], m[2], wx[2], wy[2], wz[2];
+};
+
+__device__ __forceinline__ void load_vdset(const V64Args& A, int g, int t, VDSet& s) {
+  const int n = A.n;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = g * kSI + u * kSL + t;
+    if (i < n) {
+      s.x[u] = A.x[i]; s.y[u] = A.x[n + i]; s.z[u] = A.x[2 * n + i];
+      s.m[u] = A.m[i];
+      s.wx[u] = A.w[i]; s.wy[u] = A.w[n + i]; s.wz[u] = A.w[2 * n + i];
+    } else {
+      s.x[u] = s.y[u] = s.z[u] = kFarAway;
+      s.m[u] = 0.0;
+      s.wx[u] = s.wy[u] = s.wz[u] = 0.0;
+    }
+  }
+}
+
+// One pair's terms for lane particle u against record (r, wj): the k-side
+// terms added to p[u], the j-side ones to (ax, ay, az, am).
+__device__ __forceinline__ void vjp64_pair(const VDSet& s, int u, const double4& r, const double4& wj, double e2,
+                                           double (&p)[2][kV64], double& ax, double& ay, double& az, double& am) {
+  const double dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
+  const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+  const double ri = rsqrt64(r2);
+  const double ri2 = ri * ri;
+  const double r3 = ri2 * ri;
+  const double c5 = (-3.0 * ri2) * r3;
+  const double ux = fma(s.m[u], wj.x, -(r.w * s.wx[u]));
+  const double uy = fma(s.m[u], wj.y, -(r.w * s.wy[u]));
+  const double uz = fma(s.m[u], wj.z, -(r.w * s.wz[u]));
+  const double cc = c5 * fma(dz, uz, fma(dy, uy, dx * ux));
+  p[u][0] = fma(cc, dx, fma(r3, ux, p[u][0]));
+  p[u][1] = fma(cc, dy, fma(r3, uy, p[u][1]));
+  p[u][2] = fma(cc, dz, fma(r3, uz, p[u][2]));
+  ax = fma(-cc, dx, fma(-r3, ux, ax));
+  ay = fma(-cc, dy, fma(-r3, uy, ay));
+  az = fma(-cc, dz, fma(-r3, uz, az));
+  p[u][3] = fma(-r3, fma(dz, wj.z, fma(dy, wj.y, dx * wj.x)), p[u][3]);
+  am = fma(r3, fma(dz, s.wz[u], fma(dy, s.wy[u], dx * s.wx[u])), am);
+}
+
+template <int K>
+__device__ __forceinline__ void vstep64(const VDSet& s, const double4* __restrict__ rowp,
+                                        const double4* __restrict__ roww, double e2, double (&p)[2][kV64],
+                                        double (&aj)[kV64]) {
+  const double4 r = rowp[K];
+  const double4 wj = roww[K];
+  double ax = 0.0, ay = 0.0, az = 0.0, am = 0.0;
+  vjp64_pair(s, 0, r, wj, e2, p, ax, ay, az, am);
+  vjp64_pair(s, 1, r, wj, e2, p, ax, ay, az, am);
+  // the j met here sits at row position (r + K): its owner is K lanes further on
+  if constexpr (K == 0) {
+    aj[0] += ax; aj[1] += ay; aj[2] += az; aj[3] += am;
+  } else {
+    aj[0] += row_ror64<K>(ax);
+    aj[1] += row_ror64<K>(ay);
+    aj[2] += row_ror64<K>(az);
+    aj[3] += row_ror64<K>(am);
+  }
+}
+
+template <int... K>
+__device__ __forceinline__ void vsub64(const VDSet& s, const double4* __restrict__ rowp,
+                                       const double4* __restrict__ roww, double e2, double (&p)[2][kV64],
+                                       double (&aj)[kV64], std::integer_sequence<int, K...>) {
+  (vstep64<K>(s, rowp, roww, e2, p, aj), ...);
+}
+
+__global__ void vsym64_stage_kernel(V64Args A, double4* __restrict__ rec, double4* __restrict__ recw) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.npad) return;
+  const int n = A.n;
+  rec[j] = j < n ? make_double4(A.x[j], A.x[n + j], A.x[2 * n + j], A.m[j])
+                 : make_double4(kFarAway, kFarAway, kFarAway, 0.0);
+  recw[j] = j < n ? make_double4(A.w[j], A.w[n + j], A.w[2 * n + j], 0.0) : make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
+// Grid: nb * nparts workgroups; workgroup (g, part) takes tiles kbeg ..
+// kbeg + T - 1 of the chunk (fewer where g's ring ends), as sym64_kernel.
+__global__ __launch_bounds__(kSL, 3) void vsym64_kernel(V64Args A) {
+  __shared__ double4 s_rec[2][4][2 * kSR];  // each sub-block twice in a row
+  __shared__ double4 s_w[2][4][2 * kSR];    // cotangents, laid out as s_rec
+  __shared__ double s_part[kV64][kSW][kST];
+  __shared__ double s_acc_lo[2 * kV64][kSL];  // the lo halves of the i-side (hi, lo) sums
+
+  const int t = threadIdx.x;
+  const int rl = t & (kSR - 1);
+  const int wave = t / 64;
+  const int lid = xcd_local_index(blockIdx.x, gridDim.x);
+  const int g = lid % A.nb;
+  const int part = lid / A.nb;
+  const int kbeg = part * A.T;
+  const int rend = (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1;  // g's ring ends before this distance
+  const int ntiles = max(0, min(kbeg + A.T, (rend - A.d_lo) * kSTiles) - kbeg);
+  const double e2 = A.eps * A.eps;
+
+  VDSet s;
+  load_vdset(A, g, t, s);
+  double h[2][kV64];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int c = 0; c < kV64; ++c) h[u][c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2 * kV64; ++c) s_acc_lo[c][t] = 0.0;
+  const int xor32 = ((t & 63) ^ 32) * 4;
+
+  // the last wave copies tile k into LDS buffer b, one sub-block per copy: lane
+  // L brings the half (L & 1) of record (L >> 1) mod 16, so that the 64 lanes'
+  // 16-byte pieces lay the sub-block's 16 records out twice in a row
+  const unsigned lane_off = (unsigned)((((t & 63) >> 1) & (kSR - 1)) * sizeof(double4) + (t & 1) * 16);
+  auto stage = [&](int k, int b) {
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + A.d_lo + (kbeg + k) / kSTiles) % A.nb) * kSI + ((kbeg + k) % kSTiles) * kST);
+    const char* base = reinterpret_cast<const char*>(A.rec) + (size_t)rec0 * sizeof(double4);
+    const char* wbase = reinterpret_cast<const char*>(A.recw) + (size_t)rec0 * sizeof(double4);
+    unsigned o = lane_off;
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __builtin_amdgcn_global_load_lds(base + q * kSR * sizeof(double4) + o, (lds_ptr)&s_rec[b][q][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(wbase + q * kSR * sizeof(double4) + o, (lds_ptr)&s_w[b][q][0], 16, 0, 0);
+    }
+  };
+
+  if (ntiles > 0 && t >= 3 * 64) {
+    stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+
+  for (int k = 0; k < ntiles; ++k) {
+    const int b = k & 1;
+    const int d = A.d_lo + (kbeg + k) / kSTiles;
+    const int tt = (kbeg + k) % kSTiles;
+    if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
+    double p[2][kV64];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kV64; ++c) p[u][c] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      double aj[kV64] = {0.0, 0.0, 0.0, 0.0};
+      vsub64(s, &s_rec[b][q][rl], &s_w[b][q][rl], e2, p, aj, std::make_integer_sequence<int, kSR>{});
+      // the four rows' sums of the same 16 j
+#pragma unroll
+      for (int c = 0; c < kV64; ++c) {
+        aj[c] += swizzle64_xor16(aj[c]);
+        aj[c] += bpermute64(xor32, aj[c]);
+        s_part[c][wave][q * kSR + rl] = aj[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kV64; ++c) fold(h[u][c], s_acc_lo[u * kV64 + c][t], p[u][c]);
+    __syncthreads();
+    {
+      // the tile's j-side sums: the 4 wave sums of each j, in wave order
+      const int c = t / kST, jl = t % kST;
+      double v = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < kSW; ++w2) v += s_part[c][w2][jl];
+      const int J = (g + d) % A.nb;
+      A.pj[((size_t)(d - A.d_lo) * kV64 + c) * A.npad + (size_t)J * kSI + tt * kST + jl] = v;
+    }
+    if (t >= 3 * 64) __builtin_amdgcn_s_waitcnt(0);  // the next tile's copies have landed in LDS
+    __syncthreads();
+  }
+
+  double* o = A.pi + (size_t)part * kV64 * A.npad;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const size_t i = (size_t)g * kSI + u * kSL + t;
+#pragma unroll
+    for (int c = 0; c < kV64; ++c) o[(size_t)c * A.npad + i] = h[u][c] + s_acc_lo[u * kV64 + c][t];
+  }
+}
+
+// The block with itself (distance 0): the k-side of all ordered pairs inside
+// I-block g, own pair left out (its term is zero: d = 0 and u = 0).  The
+// gridDim.y workgroups of a block each take a slice of its j, and their kDiagG
+// groups of kSL lanes each a part of the slice; group 0 adds the groups' hi +
+// lo in group order into pd[slice][4][npad].
+__global__ __launch_bounds__(kSL* kDiagG) void vsym64_diag_kernel(V64Args A, double* __restrict__ pd) {
+  __shared__ double4 s_rec[kSI];
+  __shared__ double4 s_w[kSI];
+  __shared__ double s_part[kDiagG - 1][kV64][kSI];
+  const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
+  const int g = blockIdx.x;
+  const double e2 = A.eps * A.eps;
+  const int span = kSI / ((int)gridDim.y * kDiagG), fl = span < kFold ? span : kFold;
+  const int f0 = ((int)blockIdx.y * kDiagG + grp) * span;
+  VDSet s;
+  load_vdset(A, g, t, s);
+  for (int k = threadIdx.x; k < kSI; k += kSL * kDiagG) {
+    s_rec[k] = A.rec[(size_t)g * kSI + k];
+    s_w[k] = A.recw[(size_t)g * kSI + k];
+  }
+  __syncthreads();
+  double h[2][kV64], l[2][kV64];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int c = 0; c < kV64; ++c) h[u][c] = l[u][c] = 0.0;
+#pragma unroll 1
+  for (int f = f0; f < f0 + span; f += fl) {
+    double p[2][kV64];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kV64; ++c) p[u][c] = 0.0;
+#pragma unroll 4
+    for (int j = f; j < f + fl; ++j) {
+      const double4 r = s_rec[j];
+      const double4 wj = s_w[j];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        double q[2][kV64];
+#pragma unroll
+        for (int c = 0; c < kV64; ++c) q[0][c] = q[1][c] = 0.0;
+        double ax = 0.0, ay = 0.0, az = 0.0, am = 0.0;
+        vjp64_pair(s, u, r, wj, e2, q, ax, ay, az, am);
+        const bool own = j == u * kSL + t;
+#pragma unroll
+        for (int c = 0; c < kV64; ++c) p[u][c] += own ? 0.0 : q[u][c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kV64; ++c) fold(h[u][c], l[u][c], p[u][c]);
+  }
+  if (grp > 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kV64; ++c) s_part[grp - 1][c][u * kSL + t] = h[u][c] + l[u][c];
+  }
+  __syncthreads();
+  if (grp > 0) return;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int k = u * kSL + t;
+    const size_t i = (size_t)g * kSI + k;
+    double* const pds = pd + (size_t)blockIdx.y * kV64 * A.npad;
+#pragma unroll
+    for (int c = 0; c < kV64; ++c) {
+      double v = h[u][c] + l[u][c];
+#pragma unroll
+      for (int q = 0; q < kDiagG - 1; ++q) v += s_part[q][c][k];
+      pds[(size_t)c * A.npad + i] = v;
+    }
+  }
+}
+
 }  // namespace
 
 int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps, bool excl,
@@ -353,6 +638,81 @@ int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, d
     sym_reduce_kernel<3, double><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, 1 + c * D, D, nparts, B.pj, B.pi,
                                                      pd, a, nullptr, G, c == 0, c == nchunks - 1, nullptr, nullptr,
                                                      nullptr, nullptr, pds);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+    return NBODY_OK;
+  };
+  return run_sym_chunks(side, s, nchunks, nbuf, diag, pair, sum);
+}
+
+int launch_sym_vjp64(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
+                     double eps, const PairConfig& cfg, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  int nb, T, D;
+  // per particle: FP64 j-side slot sums per distance and i-side sums per
+  // workgroup (4 components), block-diagonal sums (pds slices), two records
+  const int pds = diag_slices((int)((n + kSI - 1) / kSI));
+  sym_plan(n, cfg.launches, kV64 * sizeof(double), kV64 * sizeof(double), kV64 * sizeof(double),
+           pds * kV64 * (int)sizeof(double) + 2 * (int)sizeof(double4), cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb,
+           &T, &D);
+  const int dmax = nb / 2;
+  const int half = (nb % 2 == 0) ? 1 : 0;
+  const int64_t npad = (int64_t)nb * kSI;
+  const int nparts = D * kSTiles / T;
+  const int nchunks = dmax > 0 ? (dmax + D - 1) / D : 0;
+  std::unique_lock<std::mutex> side_lk;
+  SideStream* side = nchunks >= 2 && !cfg.scratch ? acquire_side_stream(s, side_lk) : nullptr;
+  const int nbuf = side ? 2 : 1;
+  int st = NBODY_OK;
+  const size_t pj_bytes = sizeof(double) * kV64 * (size_t)npad * D;
+  const size_t pi_bytes = sizeof(double) * kV64 * (size_t)npad * nparts;
+  const size_t pd_bytes = sizeof(double) * kV64 * (size_t)npad * pds;
+  const size_t rec_bytes = sizeof(double4) * (size_t)npad;
+  const size_t buf_bytes = pj_bytes + pi_bytes;  // one slot set
+  char* ws = static_cast<char*>(pair_scratch(cfg, nbuf * buf_bytes + pd_bytes + 2 * rec_bytes, &st));
+  if (!ws) return st;
+  V64Args A;
+  A.x = x; A.m = m; A.w = w; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
+  A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  auto slots = [&](int b, V64Args& Q) {
+    Q.pj = reinterpret_cast<double*>(ws + (size_t)b * buf_bytes);
+    Q.pi = reinterpret_cast<double*>(ws + (size_t)b * buf_bytes + pj_bytes);
+  };
+  slots(0, A);
+  double* pd = reinterpret_cast<double*>(ws + nbuf * buf_bytes);
+  double4* rec = reinterpret_cast<double4*>(ws + nbuf * buf_bytes + pd_bytes);
+  double4* recw = rec + npad;
+  A.rec = rec;
+  A.recw = recw;
+  vsym64_stage_kernel<<<(unsigned)((npad + 255) / 256), 256, 0, s>>>(A, rec, recw);
+  NB_LAUNCH_CHECK("vsym64_stage_kernel");
+  const dim3 dg((unsigned)nb, (unsigned)pds);
+  auto diag = [&](hipStream_t ds) -> int {
+    vsym64_diag_kernel<<<dg, kSL * kDiagG, 0, ds>>>(A, pd);
+    NB_LAUNCH_CHECK("vsym64_diag_kernel");
+    return NBODY_OK;
+  };
+  const dim3 rg((unsigned)((n + 255) / 256), kV64);
+  if (dmax == 0) {
+    if ((st = diag(s))) return st;
+    sym_reduce_kernel<kV64, double><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, gx,
+                                                       gm, G, 1, 1, nullptr, nullptr, nullptr, nullptr, pds);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+    return NBODY_OK;
+  }
+  auto pair = [&](int c, int b) -> int {
+    V64Args B = A;
+    slots(b, B);
+    B.d_lo = 1 + c * D;
+    vsym64_kernel<<<(unsigned)nb * (unsigned)nparts, kSL, 0, s>>>(B);
+    NB_LAUNCH_CHECK("vsym64_kernel");
+    return NBODY_OK;
+  };
+  auto sum = [&](int c, int b, hipStream_t rs) -> int {
+    V64Args B = A;
+    slots(b, B);
+    sym_reduce_kernel<kV64, double><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, 1 + c * D, D, nparts, B.pj,
+                                                        B.pi, pd, gx, gm, G, c == 0, c == nchunks - 1, nullptr, nullptr,
+                                                        nullptr, nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;
   };

@@ -188,9 +188,10 @@ def test_sym_tune_candidate(nb):
 # pair serves both particles.  Gated per row on the condition-normalised error
 # |g_k - ref_k| / scale_k (scale_k: the sum of the magnitudes of row k's terms,
 # from the oracle), with the ordered VJP's bars: 2e-5 for FP32C (the rounding
-# bound of a pair just outside the near-field radius), 5e-4 for FP32.
+# bound of a pair just outside the near-field radius), 5e-4 for FP32, 1e-13
+# for FP64 (the symmetric FP64 kernel, from 8192 particles by default).
 
-CTOL = {"fp32c": 2e-5, "fp32": 5e-4}
+CTOL = {"fp32c": 2e-5, "fp32": 5e-4, "fp64": 1e-13}
 
 
 def sym_vjp(nb, x, m, w, launches=0, **kw):
@@ -210,7 +211,7 @@ def vjp_cond(oracle_mod, x, m, w, gx, gm, G=1.0, eps=0.0):
 
 
 @pytest.mark.parametrize("n", [2, 511, 513, 1025, 2048, 3001])
-@pytest.mark.parametrize("prec", ["fp32c", "fp32"])
+@pytest.mark.parametrize("prec", ["fp32c", "fp32", "fp64"])
 def test_sym_vjp_matches_oracle(nb, oracle_mod, n, prec):
     x, _, m = ics.two_component(n, seed=11)
     w = np.random.default_rng(n).standard_normal((3, n))
@@ -222,13 +223,15 @@ def test_sym_vjp_matches_oracle(nb, oracle_mod, n, prec):
 
 
 @pytest.mark.parametrize("n,launches", [(5000, 3), (9000, 9)])
-def test_sym_vjp_launch_splits(nb, oracle_mod, n, launches):
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_sym_vjp_launch_splits(nb, oracle_mod, n, launches, prec):
     x, _, m = ics.plummer(n, seed=42)
     w = np.random.default_rng(42).standard_normal((3, n))
-    print("sym vjp n=%d launches=%d" % (n, launches), flush=True)
-    gx, gm = sym_vjp(nb, x, m, w, launches=launches, eps=0.01, precision="fp32c")
+    print("sym vjp n=%d launches=%d %s" % (n, launches, prec), flush=True)
+    gx, gm = sym_vjp(nb, x, m, w, launches=launches, eps=0.01, precision=prec)
     ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.01)
-    assert ex <= CTOL["fp32c"] and em <= CTOL["fp32c"]
+    print("  cond gx %.3e gm %.3e" % (ex, em))
+    assert ex <= CTOL[prec] and em <= CTOL[prec]
 
 
 def test_sym_vjp_tight_pairs_near_field(nb, oracle_mod):
@@ -257,6 +260,45 @@ def test_sym_vjp_exclude_self_eps_zero(nb, oracle_mod):
     ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.0)
     print("sym vjp eps=0 cond gx %.3e gm %.3e" % (ex, em))
     assert ex <= 10 * CTOL["fp32c"] and em <= 10 * CTOL["fp32c"]
+
+
+def test_sym_vjp64_exclude_self_eps_zero(nb, oracle_mod):
+    """The FP64 symmetric VJP with eps = 0 (the block-diagonal kernel leaves
+    the own pair out): finite, and at the FP64 bar ten times looser for the
+    unsoftened closest pairs."""
+    x, _, m = ics.random_cloud(1500, seed=3)
+    w = np.random.default_rng(5).standard_normal(x.shape)
+    gx, gm = sym_vjp(nb, x, m, w, eps=0.0, precision="fp64", exclude_self=True)
+    assert np.isfinite(gx).all() and np.isfinite(gm).all()
+    ex, em = vjp_cond(oracle_mod, x, m, w, gx, gm, eps=0.0)
+    print("sym vjp64 eps=0 cond gx %.3e gm %.3e" % (ex, em))
+    assert ex <= 10 * CTOL["fp64"] and em <= 10 * CTOL["fp64"]
+
+
+@pytest.mark.parametrize("n", [8192, 12289])
+def test_sym_vjp64_default_matches_ordered_and_oracle(nb, oracle_mod, n):
+    """From 8192 particles the FP64 VJP is the symmetric one by default: it
+    repeats bitwise and both it and the ordered FP64 VJP meet the FP64 bar
+    against the oracle on sampled rows."""
+    x, _, m = ics.two_component(n, seed=8)
+    w = np.random.default_rng(8).standard_normal((3, n))
+    tx, tm, tw = dev(x), dev(m), dev(w)
+    runs = [nb.nbody_accel_vjp(tx, tm, tw, eps=0.01, precision="fp64") for _ in range(2)]
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    nb.nbody_set_config(pairs=1)
+    try:
+        ogx, ogm = nb.nbody_accel_vjp(tx, tm, tw, eps=0.01, precision="fp64")
+    finally:
+        nb.nbody_set_config()
+    rows = np.random.default_rng(n).choice(n, 96, replace=False)
+    rows[:2] = [0, n - 1]
+    rgx, rgm = oracle_mod.accel_vjp_rows(x, m, w, rows, eps=0.01)
+    sx, sm = oracle_mod.accel_vjp_scale_rows(x, m, w, rows, eps=0.01)
+    for gx, gm in ((runs[0][0], runs[0][1]), (ogx, ogm)):
+        gx, gm = gx.cpu().numpy()[:, rows], gm.cpu().numpy()[rows]
+        ex, em = cond_err(gx, rgx, sx).max(), cond_err(gm, rgm, sm).max()
+        print("vjp64 n=%d cond gx %.3e gm %.3e" % (n, ex, em))
+        assert ex <= CTOL["fp64"] and em <= CTOL["fp64"]
 
 
 def test_sym_vjp_repeat_bitwise_and_agrees_with_ordered(nb, oracle_mod):
