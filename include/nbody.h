@@ -160,7 +160,11 @@ int nbody_potential(int64_t n, const double* x, const double* m, double* phi, co
  *   gm_k = -G sum_{j != k} s_kj^(-3/2) (d_kj . w_j),
  *   d_kj = x_j - x_k, s = |d|^2 + eps^2, K(d) = s^(-3/2) I - 3 s^(-5/2) d d^T.
  * Outputs gx (3*n) and gm (n) are overwritten.  Pair arithmetic follows
- * p->precision (FP32C/FP32 use FP32 pairs with compensated sums).
+ * p->precision (FP32C/FP32 use FP32 pairs with compensated sums).  From 12288
+ * particles in FP32C/FP32 and from 8192 in FP64 (or as nbody_config.pairs
+ * says) each unordered pair is evaluated once and serves both particles (the
+ * pair term changes sign when k and j swap), with sums in a fixed order; the
+ * own pair is then always left out (its term is zero for eps > 0).
  * Errors: as nbody_accel. */
 int nbody_accel_vjp(int64_t n, const double* x, const double* m, const double* w,
                     double* gx, double* gm, const nbody_params* p, void* stream);
@@ -334,13 +338,14 @@ typedef struct nbody_config {
                       most particles per item of a system above 256 particles,
                       evaluated by a whole workgroup */
   int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
-                      steps, and (FP32C/FP32 only) of nbody_accel_vjp, the
-                      adjoint sweep, nbody_accel_jerk, nbody_accel_jerk_snap
-                      and the Hermite steps:
+                      steps, of nbody_accel_vjp and the adjoint sweep, and
+                      (FP32C/FP32 only) of nbody_accel_jerk,
+                      nbody_accel_jerk_snap and the Hermite steps:
                       0 = automatic (the tuned choice for (n, precision),
                       else symmetric from 49152 particles on in FP32C/FP32
-                      and from 8192 in FP64 for the force, from 12288 for
-                      the VJP and for acceleration + jerk, from 8192 for
+                      and from 8192 in FP64 for the force, from 12288 in
+                      FP32C/FP32 and 8192 in FP64 for the VJP, from 12288 for
+                      acceleration + jerk, from 8192 for
                       acceleration + jerk + snap),
                       1 = ordered: every ordered pair evaluated for its i;
                       2 = symmetric: every unordered pair evaluated once and

@@ -49,13 +49,13 @@ constexpr int kFold = 64;          // j-terms summed in plain FP32/FP64 before a
 constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
 // Sizes from which the symmetric kernels are the default (measured crossovers
 // against the ordered kernels): the FP32C/FP32 force from 49152 particles, the
-// FP64 force from 8192, the FP32C/FP32 VJP from 12288, the FP32C/FP32
-// acceleration + jerk from 12288, the FP32C/FP32 acceleration + jerk + snap
-// from 8192.
+// FP64 force from 8192, the FP32C/FP32 VJP from 12288, the FP64 VJP from 8192,
+// the FP32C/FP32 acceleration + jerk from 12288, the FP32C/FP32 acceleration +
+// jerk + snap from 8192.
 constexpr int64_t kSymMinN = 49152;
 constexpr int64_t kSymMinN64 = 8192;
 constexpr int64_t kSymMinNVjp = 12288;
-constexpr int64_t kSymMinNVjp64 = 8192;  // the FP64 VJP
+constexpr int64_t kSymMinNVjp64 = 8192;
 constexpr int64_t kSymMinNJerk = 12288;
 constexpr int64_t kSymMinNSnap = 8192;
 
