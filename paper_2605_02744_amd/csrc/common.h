@@ -50,12 +50,13 @@ constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
 // Sizes from which the symmetric kernels are the default (measured crossovers
 // against the ordered kernels): the FP32C/FP32 force from 49152 particles, the
 // FP64 force from 8192, the FP32C/FP32 VJP from 12288, the FP64 VJP from 8192,
-// the FP32C/FP32 acceleration + jerk from 12288, the FP32C/FP32 acceleration +
-// jerk + snap from 8192.
+// the FP32C/FP32 acceleration + jerk from 12288 and the FP64 one from 8192, the
+// FP32C/FP32 acceleration + jerk + snap from 8192.
 constexpr int64_t kSymMinN = 49152;
 constexpr int64_t kSymMinN64 = 8192;
 constexpr int64_t kSymMinNVjp = 12288;
 constexpr int64_t kSymMinNVjp64 = 8192;
+constexpr int64_t kSymMinNJerk64 = 8192;
 constexpr int64_t kSymMinNJerk = 12288;
 constexpr int64_t kSymMinNSnap = 8192;
 
@@ -66,7 +67,8 @@ struct PairConfig {
   int sym = 0;      // 1: the symmetric force kernels (each unordered pair once)
   int sym_vjp = 0;  // 1: the symmetric VJP (FP32C/FP32)
   int sym_vjp64 = 0;  // 1: the symmetric FP64 VJP
-  int sym_jerk = 0;  // 1: the symmetric acceleration + jerk (FP32C/FP32 only)
+  int sym_jerk = 0;  // 1: the symmetric acceleration + jerk (FP32C/FP32)
+  int sym_jerk64 = 0;  // 1: the symmetric FP64 acceleration + jerk
   int sym_snap = 0;  // 1: the symmetric acceleration + jerk + snap (FP32C/FP32 only)
   int launches = 0;  // symmetric kernels: least number of launches of the half ring (0 = automatic)
   int rescue = 1;  // FP32C force: recompute rows flagged by the error estimate in FP64
@@ -119,6 +121,10 @@ int launch_sym_snap(int64_t n, const double* x, const double* v, const double* a
 // The same VJP from the symmetric kernel (FP32C or FP32; launches as above).
 int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,
                    double eps, int precision, bool exclude_self, const PairConfig& cfg, hipStream_t s);
+
+// Acceleration and jerk in FP64 from the symmetric FP64 kernel (launches as above).
+int launch_sym_jerk64(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
+                      double eps, bool exclude_self, const PairConfig& cfg, hipStream_t s);
 
 // The same VJP in FP64 from the symmetric FP64 kernel (launches as above).
 int launch_sym_vjp64(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,

@@ -968,6 +968,7 @@ int launch_accel_jerk(int64_t n, const double* x, const double* v, const double*
                       double eps, int precision, bool excl, const PairConfig& cfg, hipStream_t s) {
   if (n == 0) return NBODY_OK;
   if (cfg.sym_jerk && precision != kFP64) return launch_sym_jerk(n, x, v, m, a, jk, G, eps, precision, excl, cfg, s);
+  if (cfg.sym_jerk64 && precision == kFP64) return launch_sym_jerk64(n, x, v, m, a, jk, G, eps, excl, cfg, s);
   const int split = cfg.split < 1 ? 1 : cfg.split;
   const bool one = cfg.ipl <= 1;
   switch (precision) {

@@ -10,7 +10,8 @@
 // arithmetic is FP64 with the refined inverse square root of the ordered FP64
 // kernel; there is no near-field repair to do.  The vector-Jacobian product of
 // the acceleration (the adjoint's pairwise VJP) runs on the same layout with
-// four FP64 components per particle.
+// four FP64 components per particle, and acceleration + jerk (Algorithm 3) with
+// six.
 #include "sym_common.h"
 
 namespace nb {
@@ -563,6 +564,279 @@ __global__ __launch_bounds__(kSL* kDiagG) void vsym64_diag_kernel(V64Args A, dou
   }
 }
 
+
+// ------------------------------------------ symmetric FP64 acceleration + jerk
+// Algorithm 3's pair term once per unordered pair, in FP64: with d = x_j - x_i,
+// w = v_j - v_i, r^2 = |d|^2 + eps^2 and q = -3 r^-2 (d . w),
+//   a_i += m_j r^-3 d,   jerk_i += m_j r^-3 (w + q d),
+//   a_j -= m_i r^-3 d,   jerk_j -= m_i r^-3 (w + q d)
+// (d and w change sign when i and j swap, q does not).  Six components per
+// particle (a, then jerk); velocities staged as a second record per particle.
+constexpr int kJ64 = 6;
+
+struct J64Args {
+  const double* x;  // [3][n]
+  const double* v;  // [3][n]
+  const double* m;  // [n]
+  int n, nb, npad, dmax, half, d_lo, T, nparts;
+  double eps;
+  const double4* rec;   // [npad] staged (x, y, z, m); padding far away and massless
+  const double4* recv;  // [npad] staged (vx, vy, vz, 0); padding at rest
+  double* pj;           // [D][6][npad] j-side tile sums of the chunk's distances
+  double* pi;           // [nparts][6][npad] i-side sums of the chunk's workgroups
+};
+
+struct JDSet {
+  double x[2], y[2], z[2], mneg[2], vx[2], vy[2], vz[2];
+};
+
+__device__ __forceinline__ void load_jdset(const J64Args& A, int g, int t, JDSet& s) {
+  const int n = A.n;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = g * kSI + u * kSL + t;
+    if (i < n) {
+      s.x[u] = A.x[i]; s.y[u] = A.x[n + i]; s.z[u] = A.x[2 * n + i];
+      s.mneg[u] = -A.m[i];
+      s.vx[u] = A.v[i]; s.vy[u] = A.v[n + i]; s.vz[u] = A.v[2 * n + i];
+    } else {
+      s.x[u] = s.y[u] = s.z[u] = kFarAway;
+      s.mneg[u] = 0.0;
+      s.vx[u] = s.vy[u] = s.vz[u] = 0.0;
+    }
+  }
+}
+
+// One pair for lane particle u against record (r, vj): the i-side terms are
+// added to p[u] (scale m_j), the j-side ones to b (scale -m_i).  The own pair
+// (masked with own) adds nothing: its r^-3 and q are replaced by zeros, since
+// without softening they are infinite and NaN.
+__device__ __forceinline__ void jerk64_pair(const JDSet& s, int u, const double4& r, const double4& vj, double e2,
+                                            bool own, double (&p)[2][kJ64], double (&b)[kJ64]) {
+  const double dx = r.x - s.x[u], dy = r.y - s.y[u], dz = r.z - s.z[u];
+  const double wx = vj.x - s.vx[u], wy = vj.y - s.vy[u], wz = vj.z - s.vz[u];
+  const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+  const double ri = rsqrt64(r2);
+  const double ri2 = ri * ri;
+  const double r3 = own ? 0.0 : ri2 * ri;
+  const double q = own ? 0.0 : (-3.0 * ri2) * fma(dz, wz, fma(dy, wy, dx * wx));
+  const double tx = fma(q, dx, wx), ty = fma(q, dy, wy), tz = fma(q, dz, wz);
+  const double si = r.w * r3;
+  const double sj = s.mneg[u] * r3;
+  p[u][0] = fma(si, dx, p[u][0]);
+  p[u][1] = fma(si, dy, p[u][1]);
+  p[u][2] = fma(si, dz, p[u][2]);
+  p[u][3] = fma(si, tx, p[u][3]);
+  p[u][4] = fma(si, ty, p[u][4]);
+  p[u][5] = fma(si, tz, p[u][5]);
+  b[0] = fma(sj, dx, b[0]); b[1] = fma(sj, dy, b[1]); b[2] = fma(sj, dz, b[2]);
+  b[3] = fma(sj, tx, b[3]); b[4] = fma(sj, ty, b[4]); b[5] = fma(sj, tz, b[5]);
+}
+
+template <int K>
+__device__ __forceinline__ void jstep64(const JDSet& s, const double4* __restrict__ rowp,
+                                        const double4* __restrict__ rowv, double e2, double (&p)[2][kJ64],
+                                        double (&aj)[kJ64]) {
+  const double4 r = rowp[K];
+  const double4 vj = rowv[K];
+  double b[kJ64] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  jerk64_pair(s, 0, r, vj, e2, false, p, b);
+  jerk64_pair(s, 1, r, vj, e2, false, p, b);
+  // the j met here sits at row position (r + K): its owner is K lanes further on
+  if constexpr (K == 0) {
+#pragma unroll
+    for (int c = 0; c < kJ64; ++c) aj[c] += b[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < kJ64; ++c) aj[c] += row_ror64<K>(b[c]);
+  }
+}
+
+template <int... K>
+__device__ __forceinline__ void jsub64(const JDSet& s, const double4* __restrict__ rowp,
+                                       const double4* __restrict__ rowv, double e2, double (&p)[2][kJ64],
+                                       double (&aj)[kJ64], std::integer_sequence<int, K...>) {
+  (jstep64<K>(s, rowp, rowv, e2, p, aj), ...);
+}
+
+__global__ void jsym64_stage_kernel(J64Args A, double4* __restrict__ rec, double4* __restrict__ recv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.npad) return;
+  const int n = A.n;
+  rec[j] = j < n ? make_double4(A.x[j], A.x[n + j], A.x[2 * n + j], A.m[j])
+                 : make_double4(kFarAway, kFarAway, kFarAway, 0.0);
+  recv[j] = j < n ? make_double4(A.v[j], A.v[n + j], A.v[2 * n + j], 0.0) : make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
+// Grid: nb * nparts workgroups; workgroup (g, part) takes tiles kbeg ..
+// kbeg + T - 1 of the chunk (fewer where g's ring ends), as sym64_kernel.
+__global__ __launch_bounds__(kSL, 2) void jsym64_kernel(J64Args A) {
+  __shared__ double4 s_rec[2][4][2 * kSR];  // each sub-block twice in a row
+  __shared__ double4 s_v[2][4][2 * kSR];    // velocities, laid out as s_rec
+  __shared__ double s_part[kJ64][kSW][kST];
+  __shared__ double s_acc_lo[2 * kJ64][kSL];  // the lo halves of the i-side (hi, lo) sums
+
+  const int t = threadIdx.x;
+  const int rl = t & (kSR - 1);
+  const int wave = t / 64;
+  const int lid = xcd_local_index(blockIdx.x, gridDim.x);
+  const int g = lid % A.nb;
+  const int part = lid / A.nb;
+  const int kbeg = part * A.T;
+  const int rend = (A.half && g >= A.nb / 2) ? A.dmax : A.dmax + 1;  // g's ring ends before this distance
+  const int ntiles = max(0, min(kbeg + A.T, (rend - A.d_lo) * kSTiles) - kbeg);
+  const double e2 = A.eps * A.eps;
+
+  JDSet s;
+  load_jdset(A, g, t, s);
+  double h[2][kJ64];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int c = 0; c < kJ64; ++c) h[u][c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2 * kJ64; ++c) s_acc_lo[c][t] = 0.0;
+  const int xor32 = ((t & 63) ^ 32) * 4;
+
+  // the last wave copies tile k into LDS buffer b, as in sym64_kernel
+  const unsigned lane_off = (unsigned)((((t & 63) >> 1) & (kSR - 1)) * sizeof(double4) + (t & 1) * 16);
+  auto stage = [&](int k, int b) {
+    const int rec0 = __builtin_amdgcn_readfirstlane(((g + A.d_lo + (kbeg + k) / kSTiles) % A.nb) * kSI + ((kbeg + k) % kSTiles) * kST);
+    const char* base = reinterpret_cast<const char*>(A.rec) + (size_t)rec0 * sizeof(double4);
+    const char* vbase = reinterpret_cast<const char*>(A.recv) + (size_t)rec0 * sizeof(double4);
+    unsigned o = lane_off;
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __builtin_amdgcn_global_load_lds(base + q * kSR * sizeof(double4) + o, (lds_ptr)&s_rec[b][q][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(vbase + q * kSR * sizeof(double4) + o, (lds_ptr)&s_v[b][q][0], 16, 0, 0);
+    }
+  };
+
+  if (ntiles > 0 && t >= 3 * 64) {
+    stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+
+  for (int k = 0; k < ntiles; ++k) {
+    const int b = k & 1;
+    const int d = A.d_lo + (kbeg + k) / kSTiles;
+    const int tt = (kbeg + k) % kSTiles;
+    if (t >= 3 * 64 && k + 1 < ntiles) stage(k + 1, b ^ 1);
+    double p[2][kJ64];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kJ64; ++c) p[u][c] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      double aj[kJ64] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      jsub64(s, &s_rec[b][q][rl], &s_v[b][q][rl], e2, p, aj, std::make_integer_sequence<int, kSR>{});
+      // the four rows' sums of the same 16 j
+#pragma unroll
+      for (int c = 0; c < kJ64; ++c) {
+        aj[c] += swizzle64_xor16(aj[c]);
+        aj[c] += bpermute64(xor32, aj[c]);
+        s_part[c][wave][q * kSR + rl] = aj[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kJ64; ++c) fold(h[u][c], s_acc_lo[u * kJ64 + c][t], p[u][c]);
+    __syncthreads();
+    // the tile's j-side sums: the 4 wave sums of each j, in wave order (6 x 64
+    // of them over 256 lanes)
+    for (int e = t; e < kJ64 * kST; e += kSL) {
+      const int c = e / kST, jl = e % kST;
+      double v = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < kSW; ++w2) v += s_part[c][w2][jl];
+      const int J = (g + d) % A.nb;
+      A.pj[((size_t)(d - A.d_lo) * kJ64 + c) * A.npad + (size_t)J * kSI + tt * kST + jl] = v;
+    }
+    if (t >= 3 * 64) __builtin_amdgcn_s_waitcnt(0);  // the next tile's copies have landed in LDS
+    __syncthreads();
+  }
+
+  double* o = A.pi + (size_t)part * kJ64 * A.npad;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const size_t i = (size_t)g * kSI + u * kSL + t;
+#pragma unroll
+    for (int c = 0; c < kJ64; ++c) o[(size_t)c * A.npad + i] = h[u][c] + s_acc_lo[u * kJ64 + c][t];
+  }
+}
+
+// The block with itself (distance 0): the i-side of all ordered pairs inside
+// I-block g, own pair masked when asked, in slices as sym64_diag_kernel; group
+// 0 adds the groups' hi + lo in group order into pd[slice][6][npad].
+template <bool EXCL>
+__global__ __launch_bounds__(kSL* kDiagG) void jsym64_diag_kernel(J64Args A, double* __restrict__ pd) {
+  __shared__ double4 s_rec[kSI];
+  __shared__ double4 s_v[kSI];
+  __shared__ double s_part[kDiagG - 1][kJ64][kSI];
+  const int t = threadIdx.x % kSL, grp = threadIdx.x / kSL;
+  const int g = blockIdx.x;
+  const double e2 = A.eps * A.eps;
+  const int span = kSI / ((int)gridDim.y * kDiagG), fl = span < kFold ? span : kFold;
+  const int f0 = ((int)blockIdx.y * kDiagG + grp) * span;
+  JDSet s;
+  load_jdset(A, g, t, s);
+  for (int k = threadIdx.x; k < kSI; k += kSL * kDiagG) {
+    s_rec[k] = A.rec[(size_t)g * kSI + k];
+    s_v[k] = A.recv[(size_t)g * kSI + k];
+  }
+  __syncthreads();
+  double h[2][kJ64], l[2][kJ64];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int c = 0; c < kJ64; ++c) h[u][c] = l[u][c] = 0.0;
+#pragma unroll 1
+  for (int f = f0; f < f0 + span; f += fl) {
+    double p[2][kJ64];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kJ64; ++c) p[u][c] = 0.0;
+#pragma unroll 2
+    for (int j = f; j < f + fl; ++j) {
+      const double4 r = s_rec[j];
+      const double4 vj = s_v[j];
+      double b[kJ64] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // the j side is not needed here
+      jerk64_pair(s, 0, r, vj, e2, EXCL && j == t, p, b);
+      jerk64_pair(s, 1, r, vj, e2, EXCL && j == kSL + t, p, b);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kJ64; ++c) fold(h[u][c], l[u][c], p[u][c]);
+  }
+  if (grp > 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < kJ64; ++c) s_part[grp - 1][c][u * kSL + t] = h[u][c] + l[u][c];
+  }
+  __syncthreads();
+  if (grp > 0) return;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int k = u * kSL + t;
+    const size_t i = (size_t)g * kSI + k;
+    double* const pds = pd + (size_t)blockIdx.y * kJ64 * A.npad;
+#pragma unroll
+    for (int c = 0; c < kJ64; ++c) {
+      double v = h[u][c] + l[u][c];
+#pragma unroll
+      for (int q = 0; q < kDiagG - 1; ++q) v += s_part[q][c][k];
+      pds[(size_t)c * A.npad + i] = v;
+    }
+  }
+}
+
 }  // namespace
 
 int launch_sym_accel64(int64_t n, const double* x, const double* m, double* a, double G, double eps, bool excl,
@@ -712,6 +986,83 @@ int launch_sym_vjp64(int64_t n, const double* x, const double* m, const double* 
     slots(b, B);
     sym_reduce_kernel<kV64, double><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, 1 + c * D, D, nparts, B.pj,
                                                         B.pi, pd, gx, gm, G, c == 0, c == nchunks - 1, nullptr, nullptr,
+                                                        nullptr, nullptr, pds);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+    return NBODY_OK;
+  };
+  return run_sym_chunks(side, s, nchunks, nbuf, diag, pair, sum);
+}
+
+
+int launch_sym_jerk64(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
+                      double eps, bool excl, const PairConfig& cfg, hipStream_t s) {
+  if (n == 0) return NBODY_OK;
+  int nb, T, D;
+  // per particle: FP64 j-side slot sums per distance and i-side sums per
+  // workgroup (6 components), block-diagonal sums (pds slices), two records
+  const int pds = diag_slices((int)((n + kSI - 1) / kSI));
+  sym_plan(n, cfg.launches, kJ64 * sizeof(double), kJ64 * sizeof(double), kJ64 * sizeof(double),
+           pds * kJ64 * (int)sizeof(double) + 2 * (int)sizeof(double4), cfg.scratch ? cfg.scratch_bytes : SIZE_MAX, &nb,
+           &T, &D);
+  const int dmax = nb / 2;
+  const int half = (nb % 2 == 0) ? 1 : 0;
+  const int64_t npad = (int64_t)nb * kSI;
+  const int nparts = D * kSTiles / T;
+  const int nchunks = dmax > 0 ? (dmax + D - 1) / D : 0;
+  std::unique_lock<std::mutex> side_lk;
+  SideStream* side = nchunks >= 2 && !cfg.scratch ? acquire_side_stream(s, side_lk) : nullptr;
+  const int nbuf = side ? 2 : 1;
+  int st = NBODY_OK;
+  const size_t pj_bytes = sizeof(double) * kJ64 * (size_t)npad * D;
+  const size_t pi_bytes = sizeof(double) * kJ64 * (size_t)npad * nparts;
+  const size_t pd_bytes = sizeof(double) * kJ64 * (size_t)npad * pds;
+  const size_t rec_bytes = sizeof(double4) * (size_t)npad;
+  const size_t buf_bytes = pj_bytes + pi_bytes;  // one slot set
+  char* ws = static_cast<char*>(pair_scratch(cfg, nbuf * buf_bytes + pd_bytes + 2 * rec_bytes, &st));
+  if (!ws) return st;
+  J64Args A;
+  A.x = x; A.v = v; A.m = m; A.n = (int)n; A.nb = nb; A.npad = (int)npad; A.dmax = dmax; A.half = half;
+  A.T = T; A.nparts = nparts; A.eps = eps; A.d_lo = 1;
+  auto slots = [&](int b, J64Args& Q) {
+    Q.pj = reinterpret_cast<double*>(ws + (size_t)b * buf_bytes);
+    Q.pi = reinterpret_cast<double*>(ws + (size_t)b * buf_bytes + pj_bytes);
+  };
+  slots(0, A);
+  double* pd = reinterpret_cast<double*>(ws + nbuf * buf_bytes);
+  double4* rec = reinterpret_cast<double4*>(ws + nbuf * buf_bytes + pd_bytes);
+  double4* recv = rec + npad;
+  A.rec = rec;
+  A.recv = recv;
+  jsym64_stage_kernel<<<(unsigned)((npad + 255) / 256), 256, 0, s>>>(A, rec, recv);
+  NB_LAUNCH_CHECK("jsym64_stage_kernel");
+  const dim3 dg((unsigned)nb, (unsigned)pds);
+  auto diag = [&](hipStream_t ds) -> int {
+    if (excl) jsym64_diag_kernel<true><<<dg, kSL * kDiagG, 0, ds>>>(A, pd);
+    else jsym64_diag_kernel<false><<<dg, kSL * kDiagG, 0, ds>>>(A, pd);
+    NB_LAUNCH_CHECK("jsym64_diag_kernel");
+    return NBODY_OK;
+  };
+  const dim3 rg((unsigned)((n + 255) / 256), kJ64);
+  if (dmax == 0) {
+    if ((st = diag(s))) return st;
+    sym_reduce_kernel<kJ64, double><<<rg, 256, 0, s>>>((int)n, (int)npad, nb, dmax, half, 1, 0, 0, A.pj, A.pi, pd, a,
+                                                       jk, G, 1, 1, nullptr, nullptr, nullptr, nullptr, pds);
+    NB_LAUNCH_CHECK("sym_reduce_kernel");
+    return NBODY_OK;
+  }
+  auto pair = [&](int c, int b) -> int {
+    J64Args B = A;
+    slots(b, B);
+    B.d_lo = 1 + c * D;
+    jsym64_kernel<<<(unsigned)nb * (unsigned)nparts, kSL, 0, s>>>(B);
+    NB_LAUNCH_CHECK("jsym64_kernel");
+    return NBODY_OK;
+  };
+  auto sum = [&](int c, int b, hipStream_t rs) -> int {
+    J64Args B = A;
+    slots(b, B);
+    sym_reduce_kernel<kJ64, double><<<rg, 256, 0, rs>>>((int)n, (int)npad, nb, dmax, half, 1 + c * D, D, nparts, B.pj,
+                                                        B.pi, pd, a, jk, G, c == 0, c == nchunks - 1, nullptr, nullptr,
                                                         nullptr, nullptr, pds);
     NB_LAUNCH_CHECK("sym_reduce_kernel");
     return NBODY_OK;

@@ -389,7 +389,7 @@ def sym_jerk(nb, x, v, m, launches=2, **kw):
 
 
 @pytest.mark.parametrize("n", [1, 2, 511, 513, 1500, 2049, 4113])
-@pytest.mark.parametrize("prec,tola,tolj", [("fp32c", 1e-5, 1e-4), ("fp32", 1e-4, 1e-3)])
+@pytest.mark.parametrize("prec,tola,tolj", [("fp32c", 1e-5, 1e-4), ("fp32", 1e-4, 1e-3), ("fp64", 1e-12, 1e-11)])
 def test_sym_jerk_matches_oracle(nb, oracle_mod, n, prec, tola, tolj):
     """Per-row acceleration and jerk against the oracle at sizes that span one
     block, a two-block ring seen from one side, odd and even block counts and
@@ -403,6 +403,57 @@ def test_sym_jerk_matches_oracle(nb, oracle_mod, n, prec, tola, tolj):
     assert rel_err(jk, rj) <= tolj
     if prec == "fp32c":
         assert np.all(np.abs(jk - rj) <= 2e-3 * np.abs(rj) + 1e-6 * np.abs(rj).max())
+
+
+def test_sym_jerk64_exclude_self_eps_zero(nb, oracle_mod):
+    """The FP64 symmetric acceleration + jerk without softening, the self pair
+    left out (NBODY_EXCLUDE_SELF), at the FP64 bars ten times looser for the
+    unsoftened closest pairs."""
+    x, v, m = ics.plummer(3000, seed=77)
+    ra, rj = oracle_mod.accel_jerk(x, v, m, eps=0.0)
+    a, jk = sym_jerk(nb, x, v, m, eps=0.0, precision="fp64", exclude_self=True)
+    assert np.isfinite(a).all() and np.isfinite(jk).all()
+    assert rel_err(a, ra) <= 1e-11 and rel_err(jk, rj) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [8192, 10001])
+def test_sym_jerk64_default_and_ordered_agree(nb, oracle_mod, n):
+    """From 8192 particles the FP64 acceleration + jerk is the symmetric one by
+    default: it repeats bitwise, and both it and the ordered FP64 kernel
+    (pairs = 1) meet the FP64 bars against the oracle on sampled rows."""
+    x, v, m = ics.plummer(n, seed=79)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    runs = [nb.nbody_accel_jerk(tx, tv, tm, eps=0.01, precision="fp64") for _ in range(2)]
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    nb.nbody_set_config(pairs=1)
+    try:
+        a1, j1 = nb.nbody_accel_jerk(tx, tv, tm, eps=0.01, precision="fp64")
+    finally:
+        nb.nbody_set_config()
+    rows = np.random.default_rng(n).choice(n, 128, replace=False)
+    rows[:2] = [0, n - 1]
+    ra, rj = oracle_mod.accel_jerk_rows(x, v, m, rows, eps=0.01)
+    for a, jk in ((runs[0][0], runs[0][1]), (a1, j1)):
+        a, jk = a.cpu().numpy(), jk.cpu().numpy()
+        assert rel_err(a[:, rows], ra) <= 1e-12 and rel_err(jk[:, rows], rj) <= 1e-11
+
+
+def test_sym_jerk64_hermite_matches_oracle(nb, oracle_mod):
+    """Eight FP64 fourth-order Hermite steps with the symmetric FP64
+    acceleration + jerk (pairs = 2, two launches per evaluation) against the
+    oracle's Hermite run, at the ordered FP64 path's bars."""
+    x, v, m = ics.plummer(1024, seed=61)
+    dt, steps, eps = 1.0 / 256, 8, 0.01
+    rx, rv = oracle_mod.hermite4(x, v, m, dt, steps, eps=eps)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    ta, tj = torch.empty_like(tx), torch.empty_like(tx)
+    nb.nbody_set_config(pairs=2, split=2)
+    try:
+        nb.nbody_step_hermite(tx, tv, ta, tj, tm, dt, steps, eps=eps, precision="fp64")
+    finally:
+        nb.nbody_set_config()
+    assert np.abs(tx.cpu().numpy() - rx).max() <= 1e-11
+    assert np.abs(tv.cpu().numpy() - rv).max() <= 1e-10
 
 
 def test_sym_jerk_exclude_self_eps_zero(nb, oracle_mod):
