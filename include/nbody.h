@@ -236,7 +236,8 @@ int nbody_step_batched(int32_t ncl, const int64_t* off, const double* eps, doubl
  * derivative of the softened acceleration along the motion).  FP32C rounds
  * positions to FP32 and gives the pairs closer than the near-field radius
  * float-float displacements (as nbody_accel), with FP32 velocities.  From
- * 12288 particles in FP32C and FP32 (or as nbody_config.pairs says) each
+ * 12288 particles in FP32C and FP32 and from 8192 in FP64 (or as
+ * nbody_config.pairs says) each
  * unordered pair is evaluated once and applied to both particles (the jerk
  * term, like the acceleration, changes sign when i and j swap), summed in a
  * fixed order, with a workspace of per-distance sums as nbody_accel's.
@@ -338,13 +339,14 @@ typedef struct nbody_config {
                       most particles per item of a system above 256 particles,
                       evaluated by a whole workgroup */
   int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
-                      steps, of nbody_accel_vjp and the adjoint sweep, and
-                      (FP32C/FP32 only) of nbody_accel_jerk,
-                      nbody_accel_jerk_snap and the Hermite steps:
+                      steps, of nbody_accel_vjp and the adjoint sweep, of
+                      nbody_accel_jerk and the fourth-order Hermite steps,
+                      and (FP32C/FP32 only) of nbody_accel_jerk_snap and the
+                      sixth-order Hermite steps:
                       0 = automatic (the tuned choice for (n, precision),
                       else symmetric from 49152 particles on in FP32C/FP32
                       and from 8192 in FP64 for the force, from 12288 in
-                      FP32C/FP32 and 8192 in FP64 for the VJP, from 12288 for
+                      FP32C/FP32 and 8192 in FP64 for the VJP and for
                       acceleration + jerk, from 8192 for
                       acceleration + jerk + snap),
                       1 = ordered: every ordered pair evaluated for its i;
