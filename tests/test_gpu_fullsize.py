@@ -5,7 +5,10 @@ benchmark uses, on outputs the oracle can compute one by one:
   against the ordered FP64 kernel (max gated), and on sampled, worst and
   central rows against the oracle; the FP32C VJP per row (condition-
   normalised) against the oracle on sampled rows and on the rows where it
-  differs most from the FP64 VJP;
+  differs most from the ordered FP64 VJP, both FP64 VJP forms on the same rows;
+* N = 2^20 Plummer acceleration + jerk (eps = 0.001): the symmetric FP32C and
+  FP64 kernels and the ordered FP64 kernel against the oracle on sampled rows
+  and on the rows where FP32C differs most from the ordered FP64 kernel;
 * N = 65536 Plummer force (eps = 0.005): every row against the ordered FP64
   kernel at t = 0 and after 100 FP32C KDK steps, with the energy drift;
 * 512-cluster ensemble, every batched mode: sampled clusters against the
@@ -92,16 +95,24 @@ def test_twocomp1m_all_rows(nb, oracle_mod):
 def test_twocomp1m_vjp(nb, oracle_mod):
     """The FP32C VJP at N = 2^20 in the benchmark's configuration (the
     symmetric kernel): per-row condition-normalised error against the oracle
-    on sampled rows and on the rows that differ most from the (ordered) FP64
-    VJP, which is itself checked against the oracle on the same rows."""
+    on sampled rows and on the rows that differ most from the ordered FP64
+    VJP (pairs = 1: no code shared with the symmetric ring), which is itself
+    checked against the oracle on the same rows, as is the symmetric FP64 VJP
+    (the FP64 default at this size)."""
     w_ = ics.WORKLOADS["twocomp1m_force"]
     n, eps = w_["n"], w_["eps"]
     x, _, m = ics.two_component(n, seed=w_["seed"])
     w = np.random.default_rng(1).standard_normal((3, n))
     tx, tm, tw = dev(x), dev(m), dev(w)
     gx, gm = nb.nbody_accel_vjp(tx, tm, tw, eps=eps, precision="fp32c")
-    gx64, gm64 = nb.nbody_accel_vjp(tx, tm, tw, eps=eps, precision="fp64")
+    sx64, sm64 = nb.nbody_accel_vjp(tx, tm, tw, eps=eps, precision="fp64")
+    nb.nbody_set_config(pairs=1)
+    try:
+        gx64, gm64 = nb.nbody_accel_vjp(tx, tm, tw, eps=eps, precision="fp64")
+    finally:
+        nb.nbody_set_config()
     gx, gm, gx64, gm64 = gx.cpu().numpy(), gm.cpu().numpy(), gx64.cpu().numpy(), gm64.cpu().numpy()
+    sx64, sm64 = sx64.cpu().numpy(), sm64.cpu().numpy()
     dx = np.linalg.norm(gx - gx64, axis=0)
     dm = np.abs(gm - gm64)
     worst = np.concatenate([np.argsort(dx)[-48:], np.argsort(dx / np.linalg.norm(gx64, axis=0))[-48:],
@@ -109,13 +120,44 @@ def test_twocomp1m_vjp(nb, oracle_mod):
     rows = np.unique(np.concatenate([np.random.default_rng(12).choice(n, 96, replace=False), worst]))
     rgx, rgm = oracle_mod.accel_vjp_rows(x, m, w, rows, eps=eps)
     sx, sm = oracle_mod.accel_vjp_scale_rows(x, m, w, rows, eps=eps)
-    for name, (a, b, tol) in {"fp32c": (gx, gm, 2e-5), "fp64": (gx64, gm64, 1e-13)}.items():
+    for name, (a, b, tol) in {"fp32c": (gx, gm, 2e-5), "fp64 ordered": (gx64, gm64, 1e-13),
+                              "fp64 symmetric": (sx64, sm64, 1e-13)}.items():
         cx = cond_err(a[:, rows], rgx, sx)
         cm = cond_err(b[rows], rgm, sm)
         print("vjp 2^20 %s vs oracle on %d rows: condition-normalised gx %.2e gm %.2e; rel gx %.2e gm %.2e"
               % (name, rows.size, cx.max(), cm.max(), row_err(a[:, rows], rgx).max(),
                  (np.abs(b[rows] - rgm) / np.abs(rgm)).max()))
         assert cx.max() <= tol and cm.max() <= tol, name
+
+
+def test_jerk1m_sampled_rows(nb, oracle_mod):
+    """Acceleration + jerk at N = 2^20 in the benchmark's configuration
+    (Plummer, eps = 0.001): the symmetric FP32C and FP64 kernels (the defaults
+    at this size) against the oracle on sampled rows and on the rows where the
+    FP32C jerk differs most from the ordered FP64 kernel's (pairs = 1).  FP32C:
+    acceleration within 1e-5 per row, jerk within the paper's 0.2 % per
+    component (Sec. 4.1); FP64: 1e-12 and 1e-11 per row."""
+    n, eps = 1 << 20, 0.001
+    x, v, m = ics.plummer(n, seed=6)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    a32, j32 = [q.cpu().numpy() for q in nb.nbody_accel_jerk(tx, tv, tm, eps=eps, precision="fp32c")]
+    a64, j64 = [q.cpu().numpy() for q in nb.nbody_accel_jerk(tx, tv, tm, eps=eps, precision="fp64")]
+    nb.nbody_set_config(pairs=1)
+    try:
+        o64, oj64 = [q.cpu().numpy() for q in nb.nbody_accel_jerk(tx, tv, tm, eps=eps, precision="fp64")]
+    finally:
+        nb.nbody_set_config()
+    dj = np.linalg.norm(j32 - oj64, axis=0) / np.linalg.norm(oj64, axis=0)
+    da = np.linalg.norm(a32 - o64, axis=0) / np.linalg.norm(o64, axis=0)
+    rows = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(6).choice(n, 96, replace=False),
+                                     np.argsort(dj)[-32:], np.argsort(da)[-32:]]))
+    ra, rj = oracle_mod.accel_jerk_rows(x, v, m, rows, eps=eps)
+    for name, (a, jk, tola, tolj) in {"fp32c": (a32, j32, 1e-5, 2e-3), "fp64 symmetric": (a64, j64, 1e-12, 1e-11),
+                                      "fp64 ordered": (o64, oj64, 1e-12, 1e-11)}.items():
+        ea, ej = row_err(a[:, rows], ra), row_err(jk[:, rows], rj)
+        print("jerk 2^20 %s vs oracle on %d rows: a %.2e jerk %.2e" % (name, rows.size, ea.max(), ej.max()))
+        assert ea.max() <= tola and ej.max() <= tolj, name
+    assert np.all(np.abs(j32[:, rows] - rj) <= 2e-3 * np.abs(rj) + 1e-6 * np.abs(rj).max())
 
 
 def test_plummer64k_force_and_drift(nb, oracle_mod):
