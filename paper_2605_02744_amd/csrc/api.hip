@@ -182,16 +182,17 @@ PairConfig choose_config(int64_t n, int precision, int device) {
   c.sym_vjp64 = n >= kSymMinNVjp64 ? 1 : 0;
   c.sym_jerk = n >= kSymMinNJerk ? 1 : 0;
   c.sym_jerk64 = n >= kSymMinNJerk64 ? 1 : 0;
+  c.sym_snap64 = n >= kSymMinNSnap64 ? 1 : 0;
   c.sym_snap = n >= kSymMinNSnap ? 1 : 0;
   if (t.ipl) c.ipl = t.ipl;
   if (t.split) c.split = t.split;
-  if (t.pairs) c.sym = c.sym_vjp = c.sym_vjp64 = c.sym_jerk = c.sym_jerk64 = c.sym_snap = t.pairs == 2 ? 1 : 0;
+  if (t.pairs) c.sym = c.sym_vjp = c.sym_vjp64 = c.sym_jerk = c.sym_jerk64 = c.sym_snap = c.sym_snap64 = t.pairs == 2 ? 1 : 0;
   c.rescue = t.rescue == 2 ? 0 : 1;
   c.sweep = t.sweep;
   // the symmetric kernels read a set split as a least number of launches (0 =
   // automatic); the ordered kernels that serve the same sizes (acceleration +
   // jerk (+ snap) below their thresholds, the FP64 VJP) keep their own j-split
-  c.launches = c.sym || c.sym_vjp || c.sym_vjp64 || c.sym_jerk || c.sym_jerk64 || c.sym_snap ? t.split : 0;
+  c.launches = c.sym || c.sym_vjp || c.sym_vjp64 || c.sym_jerk || c.sym_jerk64 || c.sym_snap || c.sym_snap64 ? t.split : 0;
   if (c.split <= 0) c.split = auto_split(n, c.ipl, device);
   return c;
 }

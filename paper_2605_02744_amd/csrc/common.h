@@ -57,6 +57,7 @@ constexpr int64_t kSymMinN64 = 8192;
 constexpr int64_t kSymMinNVjp = 12288;
 constexpr int64_t kSymMinNVjp64 = 8192;
 constexpr int64_t kSymMinNJerk64 = 8192;
+constexpr int64_t kSymMinNSnap64 = 8192;
 constexpr int64_t kSymMinNJerk = 12288;
 constexpr int64_t kSymMinNSnap = 8192;
 
@@ -69,6 +70,7 @@ struct PairConfig {
   int sym_vjp64 = 0;  // 1: the symmetric FP64 VJP
   int sym_jerk = 0;  // 1: the symmetric acceleration + jerk (FP32C/FP32)
   int sym_jerk64 = 0;  // 1: the symmetric FP64 acceleration + jerk
+  int sym_snap64 = 0;  // 1: the symmetric FP64 acceleration + jerk + snap
   int sym_snap = 0;  // 1: the symmetric acceleration + jerk + snap (FP32C/FP32 only)
   int launches = 0;  // symmetric kernels: least number of launches of the half ring (0 = automatic)
   int rescue = 1;  // FP32C force: recompute rows flagged by the error estimate in FP64
@@ -125,6 +127,11 @@ int launch_sym_vjp(int64_t n, const double* x, const double* m, const double* w,
 // Acceleration and jerk in FP64 from the symmetric FP64 kernel (launches as above).
 int launch_sym_jerk64(int64_t n, const double* x, const double* v, const double* m, double* a, double* jk, double G,
                       double eps, bool exclude_self, const PairConfig& cfg, hipStream_t s);
+
+// Acceleration, jerk and snap in FP64 from the symmetric FP64 kernel (launches as above).
+int launch_sym_snap64(int64_t n, const double* x, const double* v, const double* acc, const double* m, double* a,
+                      double* jk, double* sn, double G, double eps, bool exclude_self, const PairConfig& cfg,
+                      hipStream_t s);
 
 // The same VJP in FP64 from the symmetric FP64 kernel (launches as above).
 int launch_sym_vjp64(int64_t n, const double* x, const double* m, const double* w, double* gx, double* gm, double G,

@@ -955,6 +955,7 @@ int launch_accel_jerk_snap(int64_t n, const double* x, const double* v, const do
   if (n == 0) return NBODY_OK;
   if (cfg.sym_snap && precision != kFP64)
     return launch_sym_snap(n, x, v, acc, m, a, jk, sn, G, eps, precision, excl, cfg, s);
+  if (cfg.sym_snap64 && precision == kFP64) return launch_sym_snap64(n, x, v, acc, m, a, jk, sn, G, eps, excl, cfg, s);
   const int split = cfg.split < 1 ? 1 : cfg.split;
   switch (precision) {
     case kFP64: return snap_dispatch<kFP64, 1>(n, x, v, acc, m, a, jk, sn, G, eps, excl, split, s);

@@ -182,6 +182,69 @@ def test_sym_snap_matches_oracle(nb, oracle_mod, n):
     assert ej.max() <= 2e-3 and es.max() <= 2e-3
 
 
+@pytest.mark.parametrize("n", [2, 511, 513, 1537, 2049, 4113])
+def test_sym_snap64_matches_oracle(nb, oracle_mod, n):
+    """The symmetric FP64 acceleration, jerk and snap (two launches where the
+    half ring is that long) against the oracle at the ordered FP64 kernel's
+    bars, G != 1."""
+    x, v, acc, m = inputs(n, 90 + n)
+    ra, rj, rs = oracle_mod.accel_jerk_snap(x, v, acc, m, G=1.1, eps=0.01)
+    print("sym snap64 n=%d" % n, flush=True)
+    a, jk, sn = sym_snap(nb, x, v, acc, m, G=1.1, eps=0.01, precision="fp64")
+    ea, ej, es = row_err(a, ra), row_err(jk, rj), row_err(sn, rs)
+    print("sym snap64 n=%d: a %.2e jerk %.2e snap %.2e" % (n, ea.max(), ej.max(), es.max()))
+    assert ea.max() <= 1e-12 and ej.max() <= 1e-11 and es.max() <= 1e-10
+
+
+def test_sym_snap64_eps0_exclude_self(nb, oracle_mod):
+    """The symmetric FP64 kernel without softening, the self pair left out: its
+    block-diagonal kernel zeroes the own pair's s^-3/2, alpha and beta."""
+    x, v, acc, m = inputs(1500, 97)
+    ra, rj, rs = oracle_mod.accel_jerk_snap(x, v, acc, m, eps=0.0)
+    a, jk, sn = sym_snap(nb, x, v, acc, m, eps=0.0, precision="fp64", exclude_self=True, check_finite=True)
+    assert row_err(a, ra).max() <= 1e-11
+    assert row_err(jk, rj).max() <= 1e-10 and row_err(sn, rs).max() <= 1e-9
+
+
+def test_sym_snap64_default_and_ordered_agree(nb, oracle_mod):
+    """From 8192 particles the FP64 evaluation is the symmetric one by default:
+    it repeats bitwise, and it and the ordered FP64 kernel (pairs = 1) meet the
+    FP64 bars against the oracle on sampled rows."""
+    n = 9000
+    x, v, acc, m = inputs(n, 98)
+    args = (dev(x), dev(v), dev(acc), dev(m))
+    o2 = [[q.cpu().numpy() for q in nb.nbody_accel_jerk_snap(*args, eps=0.01, precision="fp64")] for _ in range(2)]
+    assert all(np.array_equal(p, q) for p, q in zip(o2[0], o2[1]))
+    nb.nbody_set_config(pairs=1)
+    try:
+        o1 = [q.cpu().numpy() for q in nb.nbody_accel_jerk_snap(*args, eps=0.01, precision="fp64")]
+    finally:
+        nb.nbody_set_config()
+    rows = np.random.default_rng(9).choice(n, 128, replace=False)
+    ref = oracle_mod.accel_jerk_snap_rows(x, v, acc, m, rows, eps=0.01)
+    for out in (o2[0], o1):
+        errs = [row_err(out[k][:, rows], ref[k]).max() for k in range(3)]
+        print("snap64 n=%d: a %.2e jerk %.2e snap %.2e" % ((n,) + tuple(errs)))
+        assert errs[0] <= 1e-12 and errs[1] <= 1e-11 and errs[2] <= 1e-10
+
+
+def test_sym_snap64_hermite6_matches_oracle(nb, oracle_mod):
+    """Eight FP64 sixth-order Hermite steps with the symmetric FP64 kernels
+    (pairs = 2, two launches per evaluation) against the oracle's run."""
+    x, v, m = ics.plummer(1024, seed=74)
+    dt, steps, eps = 1.0 / 256, 8, 0.01
+    rx, rv = oracle_mod.hermite6(x, v, m, dt, steps, eps=eps)
+    tx, tv, tm = dev(x), dev(v), dev(m)
+    st = [torch.empty_like(tx) for _ in range(4)]
+    nb.nbody_set_config(pairs=2, split=2)
+    try:
+        nb.nbody_step_hermite6(tx, tv, *st, tm, dt, steps, eps=eps, precision="fp64", check_finite=True)
+    finally:
+        nb.nbody_set_config()
+    assert np.abs(tx.cpu().numpy() - rx).max() <= 1e-11
+    assert np.abs(tv.cpu().numpy() - rv).max() <= 1e-10
+
+
 def test_sym_snap_fp32_no_worse_than_ordered(nb, oracle_mod):
     """FP32 (no compensation): the symmetric kernel's acceleration, jerk and
     snap errors against the oracle stay within three times the ordered FP32
