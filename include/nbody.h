@@ -273,7 +273,7 @@ int nbody_step_hermite(int64_t n, double* x, double* v, double* a, double* jk, c
  * caller-owned, distinct from each other and the inputs.  FP32C evaluates
  * pairs with FP32-rounded positions (float-float displacements for the pairs
  * closer than the near-field radius, as nbody_accel) and FP32 velocity and
- * acceleration differences.  From 8192 particles in FP32C and FP32 (or as
+ * acceleration differences.  From 8192 particles in every precision (or as
  * nbody_config.pairs says) each unordered pair is evaluated once and applied
  * to both particles (every term changes sign when i and j swap), summed in a
  * fixed order.  Errors: as nbody_accel_jerk. */
@@ -340,14 +340,13 @@ typedef struct nbody_config {
                       evaluated by a whole workgroup */
   int32_t pairs;   /* form of the force kernel of nbody_accel and of the KDK
                       steps, of nbody_accel_vjp and the adjoint sweep, of
-                      nbody_accel_jerk and the fourth-order Hermite steps,
-                      and (FP32C/FP32 only) of nbody_accel_jerk_snap and the
-                      sixth-order Hermite steps:
+                      nbody_accel_jerk, nbody_accel_jerk_snap and the Hermite
+                      steps:
                       0 = automatic (the tuned choice for (n, precision),
                       else symmetric from 49152 particles on in FP32C/FP32
                       and from 8192 in FP64 for the force, from 12288 in
                       FP32C/FP32 and 8192 in FP64 for the VJP and for
-                      acceleration + jerk, from 8192 for
+                      acceleration + jerk, from 8192 in every precision for
                       acceleration + jerk + snap),
                       1 = ordered: every ordered pair evaluated for its i;
                       2 = symmetric: every unordered pair evaluated once and
