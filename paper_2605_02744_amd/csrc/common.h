@@ -51,7 +51,7 @@ constexpr double kFarAway = 1.0e15;  // position of padding j-records (mass 0)
 // against the ordered kernels): the FP32C/FP32 force from 49152 particles, the
 // FP64 force from 8192, the FP32C/FP32 VJP from 12288, the FP64 VJP from 8192,
 // the FP32C/FP32 acceleration + jerk from 12288 and the FP64 one from 8192, the
-// FP32C/FP32 acceleration + jerk + snap from 8192.
+// acceleration + jerk + snap from 8192 in every precision.
 constexpr int64_t kSymMinN = 49152;
 constexpr int64_t kSymMinN64 = 8192;
 constexpr int64_t kSymMinNVjp = 12288;
