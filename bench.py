@@ -724,6 +724,24 @@ def bench_kdk1k(args, torch, nb):
     sx, sv, sa = tx.clone(), tv.clone(), ta.clone()
     run = lambda: nb.nbody_step(sx, sv, sa, tm, dt, steps, eps=eps, precision="fp64", acc_valid=True)
     ms, _, _ = timed(run, args.steps, max(args.warmup, 1000), torch)
+    # the same 10-step call captured once into a HIP graph and replayed (the launches of a short loop
+    # cost more than its kernels at this size); one replay is checked bitwise against an eager call
+    # from the same state
+    gxs, gvs, gas = sx.clone(), sv.clone(), sa.clone()
+    gs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs, capture_error_mode="relaxed"):
+        nb.nbody_step(gxs, gvs, gas, tm, dt, steps, eps=eps, precision="fp64", acc_valid=True)
+    s0 = (sx.clone(), sv.clone(), sa.clone())
+    for q, q0 in zip((gxs, gvs, gas), s0):
+        q.copy_(q0)
+    graph.replay()
+    ex, ev, ea = (q.clone() for q in s0)
+    nb.nbody_step(ex, ev, ea, tm, dt, steps, eps=eps, precision="fp64", acc_valid=True)
+    torch.cuda.synchronize()
+    replay_same = bool(torch.equal(gxs, ex) and torch.equal(gvs, ev) and torch.equal(gas, ea))
+    msg, _, _ = timed(graph.replay, args.steps, 200, torch)
     t0 = time.perf_counter()
     rx, rv = oracle.kdk(x, v, m, dt, steps, eps=eps)
     cpu = time.perf_counter() - t0
@@ -746,6 +764,9 @@ def bench_kdk1k(args, torch, nb):
             "config": {"workload": "plummer1k_fp64", "n": n, "eps": eps, "dt": dt, "kdk_steps_per_run": steps,
                        "precision": "fp64"},
             "roofline": roof,
+            "graph_replay": {"value": round(pairs / (msg * 1e-3) / 1e9, 3), "unit": UNIT,
+                             "ms_per_run": round(msg, 4), "bitwise_equal_to_eager": replay_same,
+                             "note": "the 10-step call captured into one HIP graph and replayed"},
             "max_abs_dx_vs_oracle": float(np.abs(gx - rx).max()),
             "max_abs_dv_vs_oracle": float(np.abs(gv - rv).max()),
             "cpu_baseline": {"value": round(pairs / cpu / 1e9, 4), "unit": UNIT, "cores": cores,
