@@ -150,7 +150,29 @@ def test_set_config_validation(lib):
         nb.nbody_set_config(bitem=300)
     with pytest.raises(nb.NBodyError):
         nb.nbody_set_config(bitem=32)
+    with pytest.raises(nb.NBodyError):
+        nb.nbody_set_config(sweep=2)
     nb.nbody_set_config(bsplit=2, bitem=64)
     nb.nbody_set_config(bsplit=4)
     nb.nbody_set_config(ipl=2, split=4)
+    nb.nbody_set_config(sweep=1)
     nb.nbody_set_config()
+
+
+def _header_struct_fields(name):
+    """(type, field) pairs of `typedef struct name { ... } name;` in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
+    return re.findall(r"\b(int32_t|uint32_t|double)\s+(\w+)\s*;", body)
+
+
+def test_binding_structs_match_header():
+    """The ctypes structures of the binding have the header's fields, in the
+    header's order and types (a drift would silently shift every later field)."""
+    import ctypes as ct
+    from paper_2605_02744_amd import _binding as B
+    ctype = {"int32_t": ct.c_int32, "uint32_t": ct.c_uint32, "double": ct.c_double}
+    for name, cls in (("nbody_config", B.nbody_config), ("nbody_params", B.nbody_params)):
+        fields = _header_struct_fields(name)
+        assert fields, name
+        assert [(f, ctype[t]) for t, f in fields] == [(f, t) for f, t in cls._fields_], name
